@@ -1,0 +1,402 @@
+"""Pins for the FP64 oracle: closed forms, invariants, brute force, autograd and
+finite differences.  CPU only; nothing here touches the HIP library."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from paper_2408_12282_amd import scene
+from oracle import brute, oracle
+
+TILE = 16
+
+
+def _single(n=1, feat=0, sh=False):
+    g = scene.make_gaussians(n, feat, sh, seed=11)
+    return g
+
+
+def _tensor_params(g, mlp=None):
+    p = {k: torch.tensor(v.astype(np.float64), requires_grad=True) for k, v in g.arrays().items()}
+    if mlp is not None:
+        p["mlp"] = torch.tensor(mlp.params.astype(np.float64), requires_grad=True)
+    return p
+
+
+# --------------------------------------------------------------------------- scene
+
+def test_scene_is_deterministic():
+    a = scene.workload(2, seed=7, n=500)
+    b = scene.workload(2, seed=7, n=500)
+    for k, v in a.gaussians.arrays().items():
+        assert v.tobytes() == b.gaussians.arrays()[k].tobytes()
+    c = scene.workload(2, seed=8, n=500)
+    assert a.gaussians.means.tobytes() != c.gaussians.means.tobytes()
+
+
+def test_look_at_default_camera():
+    cam = scene.look_at_camera((0, 0, 3), 800, 800)
+    np.testing.assert_allclose(cam.R, [[1, 0, 0], [0, -1, 0], [0, 0, -1]], atol=1e-7)
+    np.testing.assert_allclose(cam.center, [0, 0, 3], atol=1e-6)
+    assert abs(cam.fx - 800 / (2 * math.tan(math.radians(25)))) < 1e-3
+
+
+# --------------------------------------------------------------------------- projection (Eq. 1-2)
+
+@pytest.mark.parametrize("s,W,H", [(0.2, 64, 64), (0.05, 64, 48), (0.5, 40, 40)])
+def test_projection_on_axis_isotropic_closed_form(s, W, H):
+    """Isotropic Gaussian on the optical axis: Sigma' = ((f s / z)^2 + 0.3) I whatever the rotation."""
+    g = _single()
+    g.means[:] = 0.0
+    g.log_scales[:] = np.float32(math.log(s))
+    cam = scene.look_at_camera((0, 0, 3), W, H)
+    o = oracle.render(g, cam, scene.default_light())
+    z = 3.0
+    sig2 = (cam.fx * math.exp(float(np.float32(math.log(s)))) / z) ** 2 + 0.3
+    np.testing.assert_allclose(o["conic"][:, 0], [1 / sig2, 0.0, 1 / sig2], rtol=1e-12, atol=1e-15)
+    np.testing.assert_allclose(o["mean2d"][:, 0], [W / 2, H / 2], rtol=0, atol=1e-12)
+    lam = sig2 + math.sqrt(0.1)        # mid^2 - det = 0, floored at 0.1
+    assert o["radius"][0] == math.ceil(3 * math.sqrt(lam))
+    assert o["depth"][0] == pytest.approx(3.0, abs=1e-12)
+
+
+def test_projection_matches_matrix_chain():
+    """Off-axis, anisotropic: the oracle's conic equals inv(J W Sigma W^T J^T + 0.3 I) built with numpy."""
+    g = scene.make_gaussians(64, 0, False, seed=4)
+    cam = scene.look_at_camera((0.7, -0.4, 2.6), 96, 80)
+    o = oracle.render(g, cam, scene.default_light())
+    Rw = cam.R.astype(np.float64)
+    t = cam.t.astype(np.float64)
+    for i in range(g.n):
+        mu = g.means[:, i].astype(np.float64)
+        pc = Rw @ mu + t
+        if pc[2] <= 0.2:
+            continue
+        q = g.quats[:, i].astype(np.float64)
+        q /= np.linalg.norm(q)
+        w, x, y, z = q
+        # rotation from the quaternion via the axis-angle (Rodrigues) form, not the polynomial form
+        ang = 2 * math.atan2(math.sqrt(x * x + y * y + z * z), w)
+        ax = np.array([x, y, z]) / max(1e-300, math.sqrt(x * x + y * y + z * z))
+        K = np.array([[0, -ax[2], ax[1]], [ax[2], 0, -ax[0]], [-ax[1], ax[0], 0]])
+        Rq = np.eye(3) + math.sin(ang) * K + (1 - math.cos(ang)) * K @ K
+        S = np.diag(np.exp(g.log_scales[:, i].astype(np.float64)))
+        Sig = Rq @ S @ S @ Rq.T
+        limx, limy = 1.3 * 0.5 * cam.width / cam.fx, 1.3 * 0.5 * cam.height / cam.fy
+        tx = np.clip(pc[0] / pc[2], -limx, limx)
+        ty = np.clip(pc[1] / pc[2], -limy, limy)
+        J = np.array([[cam.fx / pc[2], 0, -cam.fx * tx / pc[2]], [0, cam.fy / pc[2], -cam.fy * ty / pc[2]]])
+        S2 = J @ Rw @ Sig @ Rw.T @ J.T + 0.3 * np.eye(2)
+        inv = np.linalg.inv(S2)
+        if o["radius"][i] == 0:
+            continue
+        np.testing.assert_allclose(o["conic"][:, i], [inv[0, 0], inv[0, 1], inv[1, 1]], rtol=1e-9, atol=1e-12)
+        np.testing.assert_allclose(o["mean2d"][:, i], [cam.fx * pc[0] / pc[2] + cam.cx,
+                                                       cam.fy * pc[1] / pc[2] + cam.cy], rtol=1e-12)
+
+
+# --------------------------------------------------------------------------- footprint / compositing (Eq. 3)
+
+@pytest.mark.parametrize("s,logit,W,H", [(0.2, 0.0, 64, 64), (0.1, 3.0, 64, 64), (0.3, 5.0, 50, 37)])
+def test_single_gaussian_footprint_closed_form(s, logit, W, H):
+    """One Gaussian: G_albedo(p) = min(0.99, o e^{-d^2/2 sigma^2}) * albedo inside the tile rectangle
+    where that alpha >= 1/255, else 0; alpha(p) equals the same weight."""
+    g = _single()
+    g.means[:] = 0.0
+    g.log_scales[:] = np.float32(math.log(s))
+    g.opacity_logits[:] = np.float32(logit)
+    g.albedo[:] = np.array([[0.25], [0.5], [1.0]], np.float32)
+    cam = scene.look_at_camera((0, 0, 3), W, H)
+    o = oracle.render(g, cam, scene.default_light())
+    sig2 = (cam.fx * math.exp(float(np.float32(math.log(s)))) / 3.0) ** 2 + 0.3
+    op = 1 / (1 + math.exp(-float(np.float32(logit))))
+    r = math.ceil(3 * math.sqrt(sig2 + math.sqrt(0.1)))
+    TX, TY = -(-W // TILE), -(-H // TILE)
+    x0 = min(max(math.floor((W / 2 - r) / TILE), 0), TX)
+    x1 = min(max(math.floor((W / 2 + r + TILE - 1) / TILE), 0), TX)
+    y0 = min(max(math.floor((H / 2 - r) / TILE), 0), TY)
+    y1 = min(max(math.floor((H / 2 + r + TILE - 1) / TILE), 0), TY)
+    py, px = np.mgrid[0:H, 0:W]
+    d2 = (W / 2 - (px + 0.5)) ** 2 + (H / 2 - (py + 0.5)) ** 2
+    al = np.minimum(0.99, op * np.exp(-0.5 * d2 / sig2))
+    inrect = (px // TILE >= x0) & (px // TILE < x1) & (py // TILE >= y0) & (py // TILE < y1)
+    expect = np.where(inrect & (al >= 1 / 255), al, 0.0)
+    np.testing.assert_allclose(o["alpha"], expect, rtol=1e-12, atol=1e-15)
+    for c, b in enumerate([0.25, 0.5, 1.0]):
+        np.testing.assert_allclose(o["gbuf"][c], expect * b, rtol=1e-12, atol=1e-15)
+
+
+@pytest.mark.parametrize("swap", [False, True])
+def test_two_gaussians_closed_form(swap):
+    """Two on-axis Gaussians: G = a_f c_f + (1 - a_f) a_b c_b, decided by depth, not by index."""
+    g = _single(2)
+    g.means[:] = 0.0
+    zf, zb = (0.5, -0.5)
+    g.means[2] = [zf, zb] if not swap else [zb, zf]
+    g.log_scales[:] = np.float32(math.log(0.15))
+    g.opacity_logits[:] = np.float32(1.0)
+    g.albedo[0] = [0.9, 0.1] if not swap else [0.1, 0.9]
+    cam = scene.look_at_camera((0, 0, 3), 32, 32)
+    o = oracle.render(g, cam, scene.default_light())
+    s = math.exp(float(np.float32(math.log(0.15))))
+    op = 1 / (1 + math.exp(-1.0))
+    d2 = 0.5 ** 2 + 0.5 ** 2   # pixel (15,15) centre vs (16,16)
+
+    def alpha(z):
+        sig2 = (cam.fx * s / z) ** 2 + 0.3
+        return min(0.99, op * math.exp(-0.5 * d2 / sig2))
+    af, ab = alpha(3.0 - 0.5), alpha(3.0 + 0.5)
+    c9, c1 = float(np.float32(0.9)), float(np.float32(0.1))
+    expect = af * c9 + (1 - af) * ab * c1
+    assert o["gbuf"][0, 15, 15] == pytest.approx(expect, rel=1e-12)
+    assert o["alpha"][15, 15] == pytest.approx(1 - (1 - af) * (1 - ab), rel=1e-12)
+
+
+def test_depth_ties_break_by_index():
+    """Equal float32 depths: the lower index is in front."""
+    g = _single(2)
+    g.means[:] = 0.0
+    g.log_scales[:] = np.float32(math.log(0.15))
+    g.opacity_logits[:] = np.float32(2.0)
+    g.albedo[0] = [0.8, 0.2]
+    cam = scene.look_at_camera((0, 0, 3), 32, 32)
+    o = oracle.render(g, cam, scene.default_light(), lists=True)
+    a = o["alpha"][15, 15]
+    a1 = 1 - math.sqrt(1 - a)         # equal alphas
+    c8, c2 = float(np.float32(0.8)), float(np.float32(0.2))
+    assert o["gbuf"][0, 15, 15] == pytest.approx(a1 * c8 + (1 - a1) * a1 * c2, rel=1e-12)
+    t = (15 // TILE) * 2 + 15 // TILE
+    lo, hi = o["tile_ranges"][t]
+    assert list(o["tile_list"][lo:hi]) == [0, 1]
+
+
+def test_transmittance_invariants():
+    """Sum of blend weights + T_final = 1; T_final >= 1e-4; n_contrib within the list."""
+    w = scene.workload(2, seed=3, n=3000)
+    g = w.gaussians
+    g.albedo[:] = 1.0
+    g.log_scales += 1.0
+    cam = scene.look_at_camera((0, 0, 3), 64, 64)
+    o = oracle.render(g, cam, scene.default_light(), lists=True)
+    np.testing.assert_allclose(o["gbuf"][0], o["alpha"], rtol=0, atol=1e-12)
+    T = 1 - o["alpha"]
+    assert T.min() >= 1e-4 - 1e-15
+    assert (T < 0.01).mean() > 0.5, "scene should saturate most pixels"
+    rng = o["tile_ranges"]
+    for py in range(0, 64, 7):
+        for px in range(0, 64, 5):
+            t = (py // TILE) * 4 + px // TILE
+            assert 0 <= o["n_contrib"][py, px] <= rng[t, 1] - rng[t, 0]
+
+
+# --------------------------------------------------------------------------- brute force
+
+def _brute_case(case):
+    if case == "plain":
+        g = scene.make_gaussians(48, 4, False, seed=3)
+        g.log_scales += 1.5
+        return g, scene.look_at_camera((0, 0, 3), 48, 32), None, -1
+    if case == "mlp":
+        g = scene.make_gaussians(40, 4, False, seed=8)
+        g.log_scales += 1.5
+        return g, scene.look_at_camera((0.3, 0.2, 2.9), 40, 40), scene.make_mlp(4, 32, 3, 6, seed=1), -1
+    if case == "sh":
+        g = scene.make_gaussians(40, 8, True, seed=5)
+        g.log_scales += 1.5
+        return g, scene.look_at_camera((0.5, 1, 2.8), 32, 32), scene.make_mlp(8, 32, 3, 6, seed=2), 3
+    if case == "ties":
+        g = scene.make_gaussians(40, 0, False, seed=9)
+        g.log_scales += 1.2
+        g.means[2, :20] = np.float32(0.25)     # 20 Gaussians share one float32 depth
+        g.means[2, 20:] = np.float32(-0.1)
+        return g, scene.look_at_camera((0, 0, 3), 33, 31), None, -1
+    raise ValueError(case)
+
+
+@pytest.mark.parametrize("case", ["plain", "mlp", "sh", "ties"])
+def test_oracle_equals_brute_force(case):
+    g, cam, mlp, shd = _brute_case(case)
+    light = scene.default_light()
+    o = oracle.render(g, cam, light, mlp, lists=True)
+    b = brute.render(_tensor_params(g, mlp), cam, light, mlp, sh_degree=shd)
+    for k in ("rgb", "gbuf", "alpha"):
+        np.testing.assert_allclose(o[k], b[k].detach().numpy(), rtol=0, atol=1e-12 * max(1.0, np.abs(o[k]).max()))
+    assert (o["n_contrib"] == b["n_contrib"]).all()
+    TX = -(-cam.width // TILE)
+    for t, lst in b["lists"].items():
+        lo, hi = o["tile_ranges"][t]
+        assert list(o["tile_list"][lo:hi]) == list(lst), f"tile {t}"
+    valid = b["valid"]
+    np.testing.assert_array_equal(o["radius"], b["radius"])
+    np.testing.assert_array_equal(o["rect"][:, valid], b["rect"][:, valid])
+    assert o["num_instances"] == sum(len(v) for v in b["lists"].values())
+    del TX
+
+
+@pytest.mark.parametrize("case", ["plain", "mlp", "sh"])
+def test_oracle_gradient_equals_autograd(case):
+    g, cam, mlp, shd = _brute_case(case)
+    light = scene.default_light()
+    rng = np.random.default_rng(17)
+    C = 10 + g.feat_dim
+    w_rgb = rng.normal(size=(3, cam.height, cam.width))
+    w_g = rng.normal(size=(C, cam.height, cam.width))
+    w_a = rng.normal(size=(cam.height, cam.width))
+    p = _tensor_params(g, mlp)
+    b = brute.render(p, cam, light, mlp, sh_degree=shd)
+    L = (b["rgb"] * torch.tensor(w_rgb)).sum() + (b["gbuf"] * torch.tensor(w_g)).sum() + \
+        (b["alpha"] * torch.tensor(w_a)).sum()
+    L.backward()
+    og = oracle.render(g, cam, light, mlp, drgb=w_rgb, dgbuf=w_g, dalpha=w_a)["grads"]
+    for k, t in p.items():
+        if t.grad is None:
+            continue
+        ref = t.grad.numpy()
+        if k == "albedo" and shd >= 0:
+            continue      # albedo is unused when the colour comes from SH
+        np.testing.assert_allclose(og[k], ref, rtol=0, atol=1e-9 * max(1.0, np.abs(ref).max()), err_msg=k)
+
+
+# --------------------------------------------------------------------------- finite differences
+
+@pytest.mark.parametrize("use_mlp,sh", [(False, False), (True, False), (True, True)])
+def test_oracle_gradient_equals_central_differences(use_mlp, sh):
+    g = scene.make_gaussians(60, 4, sh, seed=21)
+    g.log_scales += 1.3
+    cam = scene.look_at_camera((0.2, 0.1, 3.0), 48, 48)
+    light = scene.default_light()
+    mlp = scene.make_mlp(4, 16, 3, 6, seed=5) if use_mlp else None
+    rng = np.random.default_rng(5)
+    C = 10 + g.feat_dim
+    w_rgb = rng.normal(size=(3, 48, 48))
+    w_g = rng.normal(size=(C, 48, 48))
+    w_a = rng.normal(size=(48, 48))
+    base = {k: v.astype(np.float64) for k, v in g.arrays().items()}
+    if mlp is not None:
+        base["mlp"] = mlp.params.astype(np.float64)
+
+    def loss(pp):
+        o = oracle.render(g, cam, light, mlp, params64=pp)
+        return (o["rgb"] * w_rgb).sum() + (o["gbuf"] * w_g).sum() + (o["alpha"] * w_a).sum(), o["signature"]
+
+    an = oracle.render(g, cam, light, mlp, drgb=w_rgb, dgbuf=w_g, dalpha=w_a, params64=base)["grads"]
+    names = [k for k in base if base[k].size and not (sh and k == "albedo")]
+    checked = rejected = 0
+    for trial in range(90):
+        k = names[trial % len(names)]
+        flat = base[k].reshape(-1)
+        j = int(rng.integers(flat.size))
+        if k == "mlp" and an["mlp"].reshape(-1)[j] == 0.0:
+            continue
+        h = 1e-6 * max(1.0, abs(flat[j]))
+        pp = {kk: vv.copy() for kk, vv in base.items()}
+        pp[k].reshape(-1)[j] = flat[j] + h
+        lp, sp = loss(pp)
+        pp[k].reshape(-1)[j] = flat[j] - h
+        lm, sm = loss(pp)
+        if sp != sm:
+            rejected += 1
+            continue
+        fd = (lp - lm) / (2 * h)
+        a = an[k].reshape(-1)[j]
+        scale = np.abs(an[k]).max()
+        assert abs(fd - a) <= 1e-5 * (abs(a) + 1e-2 * scale) + 1e-7, f"{k}[{j}]: fd={fd} analytic={a}"
+        checked += 1
+    assert checked >= 60 and rejected <= 10
+
+
+# --------------------------------------------------------------------------- BRDF (Eq. 4)
+
+@pytest.mark.parametrize("rough", [0.35, 0.6, 1.0])
+def test_ggx_distribution_is_normalised(rough):
+    """The projected microfacet distribution integrates to one over the hemisphere."""
+    from scipy import integrate
+    val, _ = integrate.quad(lambda th: oracle.ggx_d(math.cos(th), rough) * math.cos(th) * math.sin(th),
+                            0, math.pi / 2, limit=400, points=[0.01, 0.05, 0.2])
+    assert 2 * math.pi * val == pytest.approx(1.0, rel=1e-6)
+
+
+def test_brdf_normal_incidence_closed_form():
+    """w_o = w_i = n: D = 1/(pi a^2), F = F0, G = 1 => f_s = F0 / (4 pi a^2); f_d = (1-m) b / pi."""
+    n = np.array([0.0, 0.0, 1.0])
+    for b, r, m in [(0.3, 0.5, 0.0), (0.8, 0.7, 1.0), (0.5, 0.9, 0.4)]:
+        fs, fd = oracle.brdf(n, n, n, b, r, m)
+        F0 = 0.04 * (1 - m) + b * m
+        assert fs == pytest.approx(F0 / (4 * math.pi * (r * r) ** 2), rel=1e-12)
+        assert fd == pytest.approx((1 - m) * b / math.pi, rel=1e-12)
+
+
+def test_brdf_reciprocity_and_lambert():
+    rng = np.random.default_rng(2)
+    n = np.array([0.0, 0.0, 1.0])
+    for _ in range(50):
+        a = rng.normal(size=3); a[2] = abs(a[2]) + 0.1; a /= np.linalg.norm(a)
+        c = rng.normal(size=3); c[2] = abs(c[2]) + 0.1; c /= np.linalg.norm(c)
+        b, r, m = rng.uniform(0, 1), rng.uniform(0.1, 1), rng.uniform(0, 1)
+        f1 = oracle.brdf(n, a, c, b, r, m)
+        f2 = oracle.brdf(n, c, a, b, r, m)
+        assert f1[0] == pytest.approx(f2[0], rel=1e-12)
+        assert oracle.brdf(n, a, c, b, r, 0.0)[1] == pytest.approx(b / math.pi, rel=1e-14)
+
+
+def test_sh_basis_orthonormal():
+    xs, ws = np.polynomial.legendre.leggauss(24)
+    nphi = 48
+    M = np.zeros((16, 16))
+    for ct, wt in zip(xs, ws):
+        st = math.sqrt(1 - ct * ct)
+        for k in range(nphi):
+            ph = 2 * math.pi * k / nphi
+            Y = oracle.sh_basis([st * math.cos(ph), st * math.sin(ph), ct])
+            M += np.outer(Y, Y) * wt * (2 * math.pi / nphi)
+    np.testing.assert_allclose(M, np.eye(16), atol=1e-12)
+
+
+# --------------------------------------------------------------------------- BF16 emulation
+
+def test_round_bf16_matches_torch_on_float32_values():
+    rng = np.random.default_rng(0)
+    x = np.concatenate([rng.normal(size=2000) * 10 ** rng.uniform(-6, 6, size=2000),
+                        [1 + 2 ** -8, 1 + 3 * 2 ** -8, -(1 + 2 ** -8), 2 ** -8 * 3, 0.0]]).astype(np.float32)
+    ref = torch.tensor(x).to(torch.bfloat16).to(torch.float64).numpy()
+    got = np.array([oracle.round_bf16(float(v)) for v in x])
+    np.testing.assert_array_equal(got, ref)
+    assert oracle.round_bf16(1 + 2 ** -8) == 1.0            # tie to even (down)
+    assert oracle.round_bf16(1 + 3 * 2 ** -8) == 1 + 2 ** -6  # tie to even (up)
+
+
+def test_bf16_emulation_forward_matches_torch_bf16_chain():
+    g, cam, mlp, shd = _brute_case("mlp")
+    light = scene.default_light()
+    o = oracle.render(g, cam, light, mlp, bf16=True)
+    b = brute.render(_tensor_params(g, mlp), cam, light, mlp, bf16=True, sh_degree=shd)
+    ref = b["rgb"].detach().numpy()
+    # the torch chain rounds through float32 first: rare double-rounding flips only
+    assert np.linalg.norm(o["rgb"] - ref) / np.linalg.norm(ref) < 1e-4
+    assert np.mean(np.abs(o["rgb"] - ref) > 1e-9) < 0.05
+
+
+# --------------------------------------------------------------------------- edge cases
+
+def test_empty_and_culled_scenes():
+    light = scene.default_light()
+    cam = scene.look_at_camera((0, 0, 3), 37, 21)
+    g0 = scene.make_gaussians(0, 0, False, seed=0)
+    o = oracle.render(g0, cam, light)
+    assert o["num_instances"] == 0 and np.all(o["rgb"] == 0) and np.all(o["alpha"] == 0)
+    g = scene.make_gaussians(20, 0, False, seed=0)
+    g.means[2] = 5.0        # all behind the camera (z_cam = 3 - 5 < 0)
+    o = oracle.render(g, cam, light, grads=True, drgb=np.ones((3, 21, 37)))
+    assert o["num_instances"] == 0 and np.all(o["rgb"] == 0)
+    assert all(np.all(v == 0) for v in o["grads"].values())
+
+
+def test_one_pixel_image():
+    g = _single()
+    g.means[:] = 0.0
+    g.log_scales[:] = np.float32(math.log(0.3))
+    cam = scene.look_at_camera((0, 0, 3), 1, 1)
+    o = oracle.render(g, cam, scene.default_light())
+    assert o["num_instances"] == 1
+    assert 0 < o["alpha"][0, 0] <= 0.99
