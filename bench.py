@@ -1,0 +1,189 @@
+"""Benchmark: forward + backward of one 800x800 view with 300k Gaussians, the
+deferred G-buffer, GGX shading and the residual network (BF16 on the matrix
+cores vs FP32), on one MI355X.
+
+One step = render_forward + render_backward of the whole hot path (projection,
+radix binning, compositing, shading, and their backward) on inputs already
+resident in HBM.  Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+WORKLOAD = 3
+MPIX = 0.64
+HBM_PEAK_GBS = 8000.0
+FP32_VALU_TFLOPS = 78.6      # non-packed FP32 FMA: 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz
+BF16_MFMA_TFLOPS = 2500.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-views", type=int, default=2, help="views in the CPU oracle sample")
+    ap.add_argument("--precision", choices=["both", "bf16", "fp32"], default="both")
+    return ap.parse_args()
+
+
+def tile_stats(view, cam):
+    """Per-tile processed-record counts from the forward state (for algorithmic bytes)."""
+    import torch
+    lay = view.layout
+    H, W = cam.height, cam.width
+    nc = view.region(lay.n_contrib, H * W, torch.int32).view(H, W).to(torch.int64)
+    TX, TY = -(-W // 16), -(-H // 16)
+    pad = torch.zeros((TY * 16, TX * 16), dtype=torch.int64, device=nc.device)
+    pad[:H, :W] = nc
+    per_tile_max = pad.view(TY, 16, TX, 16).amax(dim=(1, 3))
+    rg = view.region(lay.tile_ranges, 2 * TX * TY, torch.int32).view(-1, 2).to(torch.int64)
+    listed = (rg[:, 1] - rg[:, 0]).clamp(min=0)
+    # records a tile touches in the forward: up to the last contributor of its slowest pixel,
+    # plus the Gaussian that stopped it when the list continues
+    fwd = torch.minimum(per_tile_max.view(-1) + 1, listed)
+    return int(per_tile_max.sum()), int(fwd.sum()), int(listed.sum())
+
+
+def run_gpu(precision: str, steps: int, warmup: int):
+    import torch
+    from paper_2408_12282_amd import scene, sssgs as B
+    w = scene.workload(WORKLOAD)
+    g, cam, light, mlp = w.gaussians, w.cameras[0], w.lights[0], w.mlp
+    dev = "cuda"
+    p = {k: torch.from_numpy(np.ascontiguousarray(v)).to(dev) for k, v in g.arrays().items()}
+    mp = torch.from_numpy(mlp.params).to(dev)
+    prec = B.PREC_BF16 if precision == "bf16" else B.PREC_FP32
+    cap = 24 * g.n
+    view = B.View(g.n, cam.width, cam.height, g.feat_dim, mlp.width, cap, device=dev)
+    bc, bl = B.make_camera(cam), B.make_light(light)
+    _, _, _, M = B.render_forward(view, p, -1, bc, bl, mp, mlp.width, prec, want_count=True)
+    drgb = torch.from_numpy(scene.upstream_weights((3, cam.height, cam.width), 1)).to(dev)
+    grads = {k: torch.zeros_like(v) for k, v in p.items()}
+    dmlp = torch.zeros_like(mp)
+
+    def step():
+        rgb, gbuf, alpha, _ = B.render_forward(view, p, -1, bc, bl, mp, mlp.width, prec)
+        B.render_backward(view, p, -1, bc, bl, gbuf, drgb, None, None, mp, mlp.width, prec, grads, dmlp)
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    B.sssgs_timing_read()
+    B.sssgs_timing_enable(True)
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0.record()
+    for _ in range(steps):
+        step()
+    t1.record()
+    torch.cuda.synchronize()
+    B.sssgs_timing_enable(False)
+    stages = B.sssgs_timing_read()
+    ms = t0.elapsed_time(t1) / steps
+    flags, m_dev = B.sssgs_workspace_status(ctypes_ptr(view), g.n, cam.width, cam.height, g.feat_dim, mlp.width,
+                                            cap)
+    assert flags == 0 and m_dev == M, (flags, m_dev, M)
+    per_tile_last, fwd_records, listed = tile_stats(view, cam)
+    return {"ms": ms, "stages": {k: (v[0] / max(v[1], 1), v[1]) for k, v in stages.items()}, "M": M,
+            "bwd_records": per_tile_last, "fwd_records": fwd_records, "listed": listed, "n": g.n,
+            "C": 10 + g.feat_dim, "HW": cam.width * cam.height}
+
+
+def ctypes_ptr(view):
+    import ctypes as ct
+    return ct.c_void_p(view.workspace.data_ptr())
+
+
+def roofline(r):
+    """Algorithmic bytes of the compositing kernels per launch / their measured duration."""
+    C = r["C"]
+    RS = (6 + C + 3) // 4 * 4
+    HW = r["HW"]
+    # forward: records + index per processed instance, G-buffer + T + n_contrib written
+    fwd_bytes = r["fwd_records"] * (4 * RS + 4) + HW * 4 * (C + 2)
+    # backward: records + index per processed instance, dG + dT + T + n_contrib read, per-Gaussian grads written
+    bwd_bytes = r["bwd_records"] * (4 * RS + 4) + HW * 4 * (C + 3) + r["n"] * 4 * (6 + C)
+    out = {}
+    for name, nbytes in (("composite_fwd", fwd_bytes), ("composite_bwd", bwd_bytes)):
+        t = r["stages"].get(name, (0.0, 0))[0]
+        if t > 0:
+            gbs = nbytes / (t * 1e-3) / 1e9
+            out[name] = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None, "kernel": name,
+                         "bytes_per_launch": int(nbytes), "ms_per_launch": round(t, 4)}
+    return out
+
+
+def cpu_baseline(views: int):
+    from oracle import oracle
+    from paper_2408_12282_amd import scene
+    w = scene.workload(WORKLOAD)
+    g, cam, light, mlp = w.gaussians, w.cameras[0], w.lights[0], w.mlp
+    drgb = scene.upstream_weights((3, cam.height, cam.width), 1)
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    oracle.render(scene.make_gaussians(100, 16, False, 0), scene.look_at_camera((0, 0, 3), 32, 32), light, mlp)
+    t = time.perf_counter()
+    for _ in range(views):
+        oracle.render(g, cam, light, mlp, bf16=True, drgb=drgb, nthreads=threads)
+    dt = (time.perf_counter() - t) / views
+    return {"value": round(MPIX / dt, 4), "unit": "Mpix/s", "cores": threads, "kind": "oracle",
+            "sample": f"{views} full views (300k Gaussians, 800x800, fwd+bwd, FP64 with BF16 network emulation)",
+            "s_per_view": round(dt, 3)}
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; multi-GPU runs are not supported",
+                          "n_gpus": a.gpus}))
+        sys.exit(2)
+    res = {}
+    for prec in (["bf16", "fp32"] if a.precision == "both" else [a.precision]):
+        res[prec] = run_gpu(prec, a.steps, a.warmup)
+    head = res.get("bf16") or res.get("fp32")
+    rl = roofline(head)
+    dominant = max(rl.values(), key=lambda v: v["ms_per_launch"]) if rl else None
+    line = {
+        "metric": "fwd+bwd ms/view & Mpix/s, 300k Gaussians 800x800 (BF16 MLP vs FP32 plain)",
+        "value": round(MPIX / (head["ms"] * 1e-3), 2),
+        "unit": "Mpix/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": round(head["ms"], 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 (network bf16)" if "bf16" in res else "f32",
+        "data": "synthetic",
+        "config": {"workload": "300k-800sq-ggx-mlp-fwdbwd", "gaussians": head["n"], "width": 800, "height": 800,
+                   "features": 16, "gbuffer_channels": head["C"], "mlp": "58(64)->64x3->6",
+                   "mlp_precision": "bf16" if "bf16" in res else "fp32", "tile_instances": head["M"]},
+        "roofline": dominant,
+        "stages_ms": {k: round(v[0], 4) for k, v in head["stages"].items()},
+    }
+    if "fp32" in res and "bf16" in res:
+        f = res["fp32"]
+        line["fp32_plain"] = {"ms_per_step": round(f["ms"], 4), "mpix_s": round(MPIX / (f["ms"] * 1e-3), 2),
+                              "stages_ms": {k: round(v[0], 4) for k, v in f["stages"].items()}}
+        line["bf16_speedup_vs_fp32"] = round(f["ms"] / head["ms"], 3)
+    line["roofline_all"] = rl
+    if not a.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(a.cpu_views)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

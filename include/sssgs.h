@@ -1,0 +1,218 @@
+/*
+ * sssgs.h -- C ABI of libsssgs.so: differentiable deferred Gaussian splatting
+ * with GGX + residual-network shading on AMD Instinct MI355X (gfx950).
+ *
+ * Method: arxiv 2408.12282, "Subsurface Scattering for 3D Gaussian Splatting".
+ *   Sec. 3.1, Eq. 1-2   Gaussians with covariance R S S^T R^T projected by the
+ *                       EWA approximation Sigma' = J W Sigma W^T J^T.
+ *   Sec. 3.1, Eq. 3     front-to-back alpha compositing of per-Gaussian values.
+ *   Sec. 3.1, Eq. 4     Disney diffuse + microfacet specular BRDF.
+ *   Sec. 3.2, Eq. 6-7   residual network for incident light and SSS radiance,
+ *                       combined with the BRDF through the per-Gaussian sss.
+ *   Sec. 3.2 "Per-Pixel Deferred Shading": composite properties into buffers,
+ *                       back-project the composited depth, shade per pixel.
+ *
+ * Conventions (all the paper leaves open):
+ *   - Camera: p_cam = R p + t with x right, y down, z forward; pinhole fx, fy,
+ *     cx, cy; pixel (i, j) is sampled at (i + 0.5, j + 0.5).
+ *   - Gaussians with z <= 0.2 are culled; x/z and y/z are clamped to
+ *     +-1.3 * (W/2)/fx and +-1.3 * (H/2)/fy inside the Jacobian; Sigma' gets
+ *     +0.3 on its diagonal; radius = ceil(3 sqrt(lambda_max)) with the
+ *     eigenvalue gap floored at 0.1; 16x16 tiles; a Gaussian is evaluated at
+ *     a pixel iff the pixel's tile lies in its tile rectangle
+ *     [floor((u-r)/16), floor((u+r+15)/16)) (clamped to the grid).
+ *   - alpha = min(0.99, o exp(power)); skipped if power > 0 or alpha < 1/255;
+ *     the walk stops before a Gaussian that would bring T below 1e-4.
+ *   - Order inside a tile: ascending (float32 depth, Gaussian index).  The
+ *     depth key is the float32 rounding of a float64 evaluation of z.
+ *   - G-buffer channels, premultiplied (sum of T alpha value):
+ *       [0..2] basecolour (albedo, or SH colour when sh_degree = 3)
+ *       [3..5] normal (world; axis of the smallest scale, facing the camera)
+ *       [6] roughness [7] metallic [8] sss [9] view-space depth
+ *       [10 .. 10+F) features.                              C = 10 + F.
+ *   - Shading uses the mean values G / a with a = 1 - T_final; a pixel with
+ *     a < 1e-6 is background (rgb 0, no gradient).  rgb = a * L_out.
+ *
+ * Memory: every array pointer below is a DEVICE pointer owned by the caller.
+ * Per-Gaussian arrays are structure-of-arrays float32 planes [k][n]; images
+ * are planes [k][height][width].  The library allocates no device memory: the
+ * caller passes one workspace buffer (size from sssgs_workspace_bytes) that
+ * must stay untouched between a forward call and the backward call that uses
+ * it.  All work is enqueued on the caller's HIP stream (hipStream_t passed as
+ * void*; NULL = default stream); calls with distinct workspaces may overlap.
+ *
+ * Errors: every entry point returns an sssgs_status.  Arguments are checked
+ * on the host before anything is enqueued; an invalid argument enqueues
+ * nothing.  SSSGS_ERR_HIP reports a failed launch; sssgs_last_error() gives
+ * the HIP error text.
+ */
+#ifndef SSSGS_H
+#define SSSGS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  SSSGS_OK = 0,
+  SSSGS_ERR_INVALID_ARG = -1, /* NULL pointer, bad size, bad shape */
+  SSSGS_ERR_CAPACITY = -2,    /* more tile instances than instance_capacity */
+  SSSGS_ERR_UNSUPPORTED = -3, /* feature width / network shape without a kernel */
+  SSSGS_ERR_HIP = -4          /* a HIP call failed */
+} sssgs_status;
+
+/* Gaussian parameters (Sec. 3.1: mean, scale, rotation quaternion, opacity;
+   R3DGS material attributes; Eq. 7 subsurfaceness; features for Eq. 6).
+   opacity = sigmoid(opacity_logit), scale = exp(log_scale), the quaternion
+   (w, x, y, z) is normalised inside. */
+typedef struct {
+  int32_t n;          /* number of Gaussians, >= 0 */
+  int32_t feat_dim;   /* F in {0, 8, 16, 32} */
+  int32_t sh_degree;  /* -1: albedo colour; 3: degree-3 SH colour (48 planes) */
+  const float *means;          /* [3][n] */
+  const float *log_scales;     /* [3][n] */
+  const float *quats;          /* [4][n] */
+  const float *opacity_logits; /* [n] */
+  const float *albedo;         /* [3][n] (ignored when sh_degree = 3) */
+  const float *roughness;      /* [n] */
+  const float *metallic;       /* [n] */
+  const float *sss;            /* [n] */
+  const float *features;       /* [F][n]; may be NULL when F = 0 */
+  const float *sh;             /* [48][n], plane k*3+c; NULL unless sh_degree = 3 */
+} sssgs_gaussians;
+
+/* Gradient outputs, same shapes as sssgs_gaussians.  A NULL plane is skipped. */
+typedef struct {
+  float *means, *log_scales, *quats, *opacity_logits, *albedo, *roughness, *metallic, *sss, *features, *sh;
+} sssgs_gaussian_grads;
+
+typedef struct {
+  float R[9];   /* world -> camera rotation, row-major */
+  float t[3];   /* p_cam = R p + t */
+  float fx, fy, cx, cy;
+  int32_t width, height; /* >= 1 each */
+} sssgs_camera;
+
+/* One point light of known position (OLAT, Sec. 3.2 "Incident Light"). */
+typedef struct {
+  float pos[3];
+  float intensity[3]; /* used only without the network: L_in = I / |p_L - x|^2 */
+} sssgs_light;
+
+/* Residual network of Eq. 6, evaluated per pixel.  Input
+   [mean features (F) | Fourier encoding of the surface point: for k = 0..5,
+   sin then cos of 2^k pi x for x, y, z (36) | w_out (3) | w_in (3)], zero
+   padded to in_pad = in_dim rounded up to 32.  `hidden` ReLU layers of
+   `width`, then a linear layer to 6 outputs: ReLU of [0..2] is the incident
+   light, sigmoid of [3..5] the SSS radiance.  params packs row-major
+   W0 [width][in_pad], b0, (hidden-1) x (W [width][width], b), W_out [6][width],
+   b_out.  params == NULL (or a NULL sssgs_mlp*) renders without the network:
+   L_out = (f_s + f_d) L_in (n . w_in). */
+typedef struct {
+  int32_t in_dim;   /* must equal F + 42 */
+  int32_t width;    /* 64 or 128 */
+  int32_t hidden;   /* 3 */
+  int32_t out_dim;  /* 6 */
+  const float *params; /* device, sssgs_mlp_param_count() floats */
+} sssgs_mlp;
+
+typedef enum { SSSGS_PREC_FP32 = 0, SSSGS_PREC_BF16 = 1 } sssgs_precision;
+
+typedef struct {
+  int32_t precision;        /* network arithmetic: FP32 on the vector ALUs, or
+                               BF16 operands on the matrix cores with FP32
+                               accumulation.  Everything else is FP32. */
+  int32_t accumulate_grads; /* backward: 0 overwrite gradient outputs, 1 add */
+} sssgs_options;
+
+/* Number of floats in sssgs_mlp.params. */
+int64_t sssgs_mlp_param_count(int32_t in_dim, int32_t width, int32_t hidden, int32_t out_dim);
+
+/* Bytes of workspace for one view: n Gaussians, width x height pixels,
+   feature width F, network width (0 without network) and room for
+   instance_capacity (tile, Gaussian) instances.  Returns 0 on bad arguments. */
+size_t sssgs_workspace_bytes(int32_t n, int32_t width, int32_t height, int32_t feat_dim, int32_t mlp_width,
+                             int64_t instance_capacity);
+
+/* Forward pass: projection, binning (radix sort of (tile, depth) keys),
+   compositing into the G-buffer, deferred shading.
+   out_rgb [3][H][W], out_gbuffer [C][H][W] and out_alpha [H][W] are required.
+   out_num_instances (HOST pointer) may be NULL.  When it is non-NULL the call
+   waits for the stream once, stores the number of tile instances M and
+   returns SSSGS_ERR_CAPACITY if M > instance_capacity (outputs are then
+   undefined; retry with a larger workspace).  When it is NULL the call never
+   waits; an overflow is recorded in the workspace (sssgs_workspace_status),
+   kernels stay in bounds and the outputs are undefined. */
+sssgs_status sssgs_render_forward(const sssgs_gaussians *g, const sssgs_camera *cam, const sssgs_light *light,
+                                  const sssgs_mlp *mlp, const sssgs_options *opt, void *workspace,
+                                  size_t workspace_bytes, int64_t instance_capacity, float *out_rgb,
+                                  float *out_gbuffer, float *out_alpha, int64_t *out_num_instances,
+                                  void *stream);
+
+/* Backward pass of the forward call that filled `workspace` (same g, cam,
+   light, mlp, options; gbuffer = that call's out_gbuffer).  Upstream gradients
+   dL_drgb [3][H][W] (required), dL_dgbuffer [C][H][W] and dL_dalpha [H][W]
+   (either may be NULL).  Writes (or adds, per opt->accumulate_grads) the
+   gradient of every non-NULL plane of `grads` and, when mlp->params is
+   non-NULL and dL_dmlp is non-NULL, of the network parameters.
+   Transmittance is recomputed by reverse traversal; nothing per pixel-Gaussian
+   pair is stored by the forward. */
+sssgs_status sssgs_render_backward(const sssgs_gaussians *g, const sssgs_camera *cam, const sssgs_light *light,
+                                   const sssgs_mlp *mlp, const sssgs_options *opt, void *workspace,
+                                   size_t workspace_bytes, int64_t instance_capacity, const float *gbuffer,
+                                   const float *dL_drgb, const float *dL_dgbuffer, const float *dL_dalpha,
+                                   sssgs_gaussian_grads *grads, float *dL_dmlp, void *stream);
+
+/* Image loss of the training objective (Appendix "Losses": the L1 part),
+   over `count` values: *loss_out (device) += sum |pred - target| * scale and
+   dL_dpred = sign(pred - target) * scale (sign(0) = 0).  loss_out may be NULL. */
+sssgs_status sssgs_l1_loss(const float *pred, const float *target, int64_t count, float scale, float *loss_out,
+                           float *dL_dpred, void *stream);
+
+/* Device-side status of the last forward on this workspace (sizes as passed
+   to sssgs_workspace_bytes): flags bit 0 set = instance capacity overflowed;
+   num_instances = tiles touched by all Gaussians.  Waits for the stream. */
+sssgs_status sssgs_workspace_status(const void *workspace, int32_t n, int32_t width, int32_t height,
+                                    int32_t feat_dim, int32_t mlp_width, int64_t instance_capacity, void *stream,
+                                    int32_t *flags_out, int64_t *num_instances_out);
+
+/* Byte offsets of the regions a test may inspect (all inside the workspace). */
+typedef struct {
+  size_t records;        /* float [n][rec_stride]: u, v, conic a b c, opacity, channels */
+  int32_t rec_stride;    /* floats per record */
+  size_t depth_keys;     /* uint32 [n] float bits of the depth key */
+  size_t rects;          /* uint16x4 [n]: x0, y0, x1, y1 tiles */
+  size_t radii;          /* int32 [n] */
+  size_t tile_ranges;    /* uint32x2 [tiles]: [start, end) into sorted_gauss */
+  size_t sorted_gauss;   /* uint32 [capacity] Gaussian index per instance, tile-major */
+  size_t sorted_tiles;   /* uint32 [capacity] tile id per instance */
+  size_t t_final;        /* float [H][W] */
+  size_t n_contrib;      /* uint32 [H][W] */
+  size_t status;         /* int32[4]: flags, M low, M high, unused */
+} sssgs_layout;
+
+sssgs_status sssgs_workspace_layout(int32_t n, int32_t width, int32_t height, int32_t feat_dim, int32_t mlp_width,
+                                    int64_t instance_capacity, sssgs_layout *out);
+
+/* Optional stage timing.  While enabled, every stage of a forward or
+   backward call (projection, depth sort, expansion, tile sort, ranges,
+   compositing, shading, network-gradient reduction, compositing backward,
+   projection backward) records a pair of HIP events on the call's stream.
+   sssgs_timing_read waits for the recorded events, writes per-stage summed
+   milliseconds and call counts into arrays of sssgs_timing_stages() entries
+   and clears the record.  Process-wide; not thread-safe. */
+sssgs_status sssgs_timing_enable(int32_t on);
+sssgs_status sssgs_timing_read(int32_t max_stages, double *total_ms, int32_t *launches, int32_t *n_stages);
+int32_t sssgs_timing_stages(void);
+const char *sssgs_timing_stage_name(int32_t k);
+
+const char *sssgs_status_string(sssgs_status s);
+const char *sssgs_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -239,7 +239,13 @@ static double frac_margin(double x) { /* distance of x to the nearest integer */
   return f < 1.0 - f ? f : 1.0 - f;
 }
 
-static int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
+/* floor(v) clamped to [0, hi], clamped before the conversion to int */
+static int floor_clamped(double v, int hi) {
+  double f = floor(v);
+  if (f < 0) f = 0;
+  if (f > hi) f = hi;
+  return (int)f;
+}
 
 static void project_one(const og_gauss *g, const og_cam *cam, int i, int TX, int TY, proj_t *P) {
   const int n = g->n;
@@ -325,10 +331,10 @@ static void project_one(const og_gauss *g, const og_cam *cam, int i, int TX, int
   P->v = cam->fy * y / z + cam->cy;
   double fx0 = (P->u - P->r) / TILE, fx1 = (P->u + P->r + TILE - 1) / TILE;
   double fy0 = (P->v - P->r) / TILE, fy1 = (P->v + P->r + TILE - 1) / TILE;
-  P->rect[0] = clampi((int)floor(fx0), 0, TX);
-  P->rect[1] = clampi((int)floor(fy0), 0, TY);
-  P->rect[2] = clampi((int)floor(fx1), 0, TX);
-  P->rect[3] = clampi((int)floor(fy1), 0, TY);
+  P->rect[0] = floor_clamped(fx0, TX);
+  P->rect[1] = floor_clamped(fy0, TY);
+  P->rect[2] = floor_clamped(fx1, TX);
+  P->rect[3] = floor_clamped(fy1, TY);
   {
     double m = frac_margin(r3);
     double m2 = frac_margin(fx0), m3 = frac_margin(fx1), m4 = frac_margin(fy0), m5 = frac_margin(fy1);

@@ -1,0 +1,591 @@
+// abi.hip -- the C ABI of libsssgs.so (include/sssgs.h): argument checks,
+// workspace layout and the sequence of kernel launches on the caller's stream.
+#include <stdio.h>
+#include <string.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/sssgs.h"
+#include "launch.hpp"
+#include "shade_common.hpp"
+
+using namespace sssgs;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+// ---- optional per-stage timing with HIP events on the caller's stream
+enum Stage {
+  kStProject = 0, kStSortDepth, kStExpand, kStSortTiles, kStRanges, kStCompositeFwd, kStShadeFwd,
+  kStShadeBwd, kStMlpReduce, kStCompositeBwd, kStProjectBwd, kStCount
+};
+const char *kStageNames[kStCount] = {"project_fwd",   "sort_depth",    "expand",        "sort_tiles",
+                                     "tile_ranges",   "composite_fwd", "shade_fwd",     "shade_bwd",
+                                     "mlp_reduce",    "composite_bwd", "project_bwd"};
+struct TimerRec {
+  int stage;
+  hipEvent_t a, b;
+};
+struct Timer {
+  bool on = false;
+  std::vector<hipEvent_t> pool;
+  std::vector<TimerRec> recs;
+  hipEvent_t get() {
+    if (!pool.empty()) {
+      hipEvent_t e = pool.back();
+      pool.pop_back();
+      return e;
+    }
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+  }
+};
+Timer g_timer;
+
+struct Scope {
+  int stage;
+  hipStream_t st;
+  hipEvent_t a = nullptr;
+  Scope(int s, hipStream_t stream) : stage(s), st(stream) {
+    if (g_timer.on) {
+      a = g_timer.get();
+      if (a) hipEventRecord(a, st);
+    }
+  }
+  ~Scope() {
+    if (g_timer.on && a) {
+      hipEvent_t b = g_timer.get();
+      if (b) {
+        hipEventRecord(b, st);
+        g_timer.recs.push_back({stage, a, b});
+      }
+    }
+  }
+};
+
+sssgs_status fail(sssgs_status s, const char *msg) {
+  g_last_error = msg;
+  return s;
+}
+
+sssgs_status check_hip(const char *where) {
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) {
+    g_last_error = std::string(where) + ": " + hipGetErrorString(e);
+    return SSSGS_ERR_HIP;
+  }
+  return SSSGS_OK;
+}
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+int in_pad_of(int in_dim) { return (in_dim + 31) / 32 * 32; }
+
+struct Layout {
+  size_t records, depth_keys, vals_a, keys_b, vals_b, keys_a, rects, radii, tt, offsets, partials, hist;
+  size_t ik_a, iv_a, ik_b, iv_b, ranges, t_final, n_contrib, status, m_total;
+  size_t gacc, dG, dT, wops, tops, mlp_part;
+  size_t total;
+  int C, RS, GS, TX, TY, T;
+  uint32_t nb_g, nb_i;
+  int shade_bwd_blocks, shade_parts, nparams;
+};
+
+constexpr int kShadeBwdMaxBlocks = 512;
+
+bool make_layout(int32_t n, int32_t W, int32_t H, int32_t F, int32_t mlp_width, int64_t cap, Layout &L) {
+  if (n < 0 || W <= 0 || H <= 0 || cap < 0 || cap >= (int64_t(1) << 31)) return false;
+  if (!(F == 0 || F == 8 || F == 16 || F == 32)) return false;
+  if (!(mlp_width == 0 || mlp_width == 64 || mlp_width == 128)) return false;
+  if (W > 16 * 65535 || H > 16 * 65535) return false;
+  L.C = kChFeat + F;
+  L.RS = rec_stride(L.C);
+  L.GS = grad_stride(L.C);
+  L.TX = (W + kTile - 1) / kTile;
+  L.TY = (H + kTile - 1) / kTile;
+  L.T = L.TX * L.TY;
+  L.nb_g = radix_blocks((uint64_t)n);
+  L.nb_i = radix_blocks((uint64_t)cap);
+  const uint32_t nbmax = L.nb_g > L.nb_i ? L.nb_g : L.nb_i;
+  const size_t nn = (size_t)(n > 0 ? n : 1), HW = (size_t)W * H, cc = (size_t)(cap > 0 ? cap : 1);
+  size_t p = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = p;
+    p = align256(p + bytes);
+    return o;
+  };
+  L.records = take(nn * L.RS * 4);
+  L.depth_keys = take(nn * 4);
+  L.vals_a = take(nn * 4);
+  L.keys_a = take(nn * 4);
+  L.keys_b = take(nn * 4);
+  L.vals_b = take(nn * 4);
+  L.rects = take(nn * 8);
+  L.radii = take(nn * 4);
+  L.tt = take(nn * 4);
+  L.offsets = take(nn * 4);
+  size_t np = scan_partials_needed(nn);
+  const size_t np2 = scan_partials_needed((uint64_t)nbmax * kRadixBins);
+  if (np2 > np) np = np2;
+  L.partials = take(np * 4);
+  L.hist = take((size_t)nbmax * kRadixBins * 4);
+  L.ik_a = take(cc * 4);
+  L.iv_a = take(cc * 4);
+  L.ik_b = take(cc * 4);
+  L.iv_b = take(cc * 4);
+  L.ranges = take((size_t)L.T * 8);
+  L.t_final = take(HW * 4);
+  L.n_contrib = take(HW * 4);
+  L.status = take(16);
+  L.m_total = take(16);
+  L.gacc = take(nn * L.GS * 4);
+  L.dG = take(HW * L.C * 4);
+  L.dT = take(HW * 4);
+  const int in_pad = in_pad_of(F + kNumPE + 6);
+  L.nparams = mlp_width ? (int)sssgs_mlp_param_count(F + kNumPE + 6, mlp_width, 3, 6) : 0;
+  L.shade_bwd_blocks = kShadeBwdMaxBlocks;
+  L.shade_parts = 4 * kShadeBwdMaxBlocks;  // upper bound on grid x waves
+  L.wops = take(mlp_width ? prep_weight_bytes(mlp_width, in_pad) : 0);
+  L.tops = take(mlp_width ? prep_weight_bytes(mlp_width, in_pad) : 0);
+  L.mlp_part = take(mlp_width ? (size_t)L.shade_parts * L.nparams * 4 : 0);
+  L.total = p;
+  return true;
+}
+
+CamArgs cam_args(const sssgs_camera *c, const Layout &L) {
+  CamArgs a;
+  for (int k = 0; k < 9; k++) a.R[k] = c->R[k];
+  for (int k = 0; k < 3; k++) a.t[k] = c->t[k];
+  a.fx = c->fx; a.fy = c->fy; a.cx = c->cx; a.cy = c->cy;
+  a.W = c->width; a.H = c->height; a.TX = L.TX; a.TY = L.TY;
+  for (int k = 0; k < 3; k++)
+    a.Cw[k] = (float)(-((double)c->R[k] * c->t[0] + (double)c->R[3 + k] * c->t[1] + (double)c->R[6 + k] * c->t[2]));
+  return a;
+}
+
+template <class T>
+T *at(void *ws, size_t off) {
+  return reinterpret_cast<T *>(static_cast<char *>(ws) + off);
+}
+
+sssgs_status check_common(const sssgs_gaussians *g, const sssgs_camera *cam, const sssgs_light *light,
+                          const sssgs_mlp *mlp, const sssgs_options *opt, void *ws, int &net, int &width) {
+  if (!g || !cam || !light || !opt || !ws) return fail(SSSGS_ERR_INVALID_ARG, "null argument");
+  if (g->n < 0) return fail(SSSGS_ERR_INVALID_ARG, "n < 0");
+  if (cam->width <= 0 || cam->height <= 0) return fail(SSSGS_ERR_INVALID_ARG, "image size must be >= 1");
+  if (!(cam->fx > 0.f) || !(cam->fy > 0.f)) return fail(SSSGS_ERR_INVALID_ARG, "focal lengths must be > 0");
+  if (!(g->feat_dim == 0 || g->feat_dim == 8 || g->feat_dim == 16 || g->feat_dim == 32))
+    return fail(SSSGS_ERR_UNSUPPORTED, "feat_dim must be 0, 8, 16 or 32");
+  if (!(g->sh_degree == -1 || g->sh_degree == 3)) return fail(SSSGS_ERR_UNSUPPORTED, "sh_degree must be -1 or 3");
+  if (g->n > 0) {
+    if (!g->means || !g->log_scales || !g->quats || !g->opacity_logits || !g->roughness || !g->metallic || !g->sss)
+      return fail(SSSGS_ERR_INVALID_ARG, "null Gaussian parameter plane");
+    if (g->sh_degree < 0 && !g->albedo) return fail(SSSGS_ERR_INVALID_ARG, "null albedo");
+    if (g->sh_degree == 3 && !g->sh) return fail(SSSGS_ERR_INVALID_ARG, "null sh");
+    if (g->feat_dim > 0 && !g->features) return fail(SSSGS_ERR_INVALID_ARG, "null features");
+  }
+  if (!(opt->precision == SSSGS_PREC_FP32 || opt->precision == SSSGS_PREC_BF16))
+    return fail(SSSGS_ERR_INVALID_ARG, "precision must be FP32 or BF16");
+  net = 0;
+  width = 0;
+  if (mlp && mlp->params) {
+    if (mlp->hidden != 3 || mlp->out_dim != 6) return fail(SSSGS_ERR_UNSUPPORTED, "network must be 3 hidden layers, 6 outputs");
+    if (mlp->in_dim != g->feat_dim + kNumPE + 6) return fail(SSSGS_ERR_INVALID_ARG, "mlp in_dim must equal F + 42");
+    if (!(mlp->width == 64 || mlp->width == 128)) return fail(SSSGS_ERR_UNSUPPORTED, "network width must be 64 or 128");
+    if (opt->precision == SSSGS_PREC_FP32 && mlp->width != 64)
+      return fail(SSSGS_ERR_UNSUPPORTED, "FP32 network supports width 64 only");
+    net = opt->precision == SSSGS_PREC_BF16 ? 2 : 1;
+    width = mlp->width;
+  }
+  return SSSGS_OK;
+}
+
+ProjIn proj_in(const sssgs_gaussians *g) {
+  ProjIn p;
+  p.n = g->n;
+  p.means = g->means; p.log_scales = g->log_scales; p.quats = g->quats; p.opacity_logits = g->opacity_logits;
+  p.albedo = g->albedo; p.roughness = g->roughness; p.metallic = g->metallic; p.sss = g->sss;
+  p.features = g->features; p.sh = g->sh;
+  return p;
+}
+
+template <int F>
+void project_fwd_f(bool sh, const ProjIn &in, const CamArgs &cam, float *rec, uint32_t *k, uint32_t *v, ushort4 *r,
+                   int32_t *rad, hipStream_t st) {
+  if (sh) launch_project_fwd_t<F, true>(in, cam, rec, k, v, r, rad, st);
+  else launch_project_fwd_t<F, false>(in, cam, rec, k, v, r, rad, st);
+}
+
+void project_fwd(int F, bool sh, const ProjIn &in, const CamArgs &cam, float *rec, uint32_t *k, uint32_t *v,
+                 ushort4 *r, int32_t *rad, hipStream_t st) {
+  switch (F) {
+    case 0: project_fwd_f<0>(sh, in, cam, rec, k, v, r, rad, st); break;
+    case 8: project_fwd_f<8>(sh, in, cam, rec, k, v, r, rad, st); break;
+    case 16: project_fwd_f<16>(sh, in, cam, rec, k, v, r, rad, st); break;
+    default: project_fwd_f<32>(sh, in, cam, rec, k, v, r, rad, st); break;
+  }
+}
+
+template <int F>
+void project_bwd_f(bool sh, const ProjIn &in, const CamArgs &cam, const float *gacc, const ProjGradOut &o,
+                   hipStream_t st) {
+  if (sh) launch_project_bwd_t<F, true>(in, cam, gacc, o, st);
+  else launch_project_bwd_t<F, false>(in, cam, gacc, o, st);
+}
+
+void project_bwd(int F, bool sh, const ProjIn &in, const CamArgs &cam, const float *gacc, const ProjGradOut &o,
+                 hipStream_t st) {
+  switch (F) {
+    case 0: project_bwd_f<0>(sh, in, cam, gacc, o, st); break;
+    case 8: project_bwd_f<8>(sh, in, cam, gacc, o, st); break;
+    case 16: project_bwd_f<16>(sh, in, cam, gacc, o, st); break;
+    default: project_bwd_f<32>(sh, in, cam, gacc, o, st); break;
+  }
+}
+
+void composite_fwd(int C, const Layout &L, void *ws, int W, int H, float *gbuf, hipStream_t st) {
+  const uint2 *rg = at<uint2>(ws, L.ranges);
+  const uint32_t *sg = at<uint32_t>(ws, L.iv_a);
+  const float *rec = at<float>(ws, L.records);
+  float *tf = at<float>(ws, L.t_final);
+  uint32_t *nc = at<uint32_t>(ws, L.n_contrib);
+  switch (C) {
+    case 10: launch_composite_fwd_t<10>(rg, sg, rec, W, H, L.TX, L.TY, gbuf, tf, nc, st); break;
+    case 18: launch_composite_fwd_t<18>(rg, sg, rec, W, H, L.TX, L.TY, gbuf, tf, nc, st); break;
+    case 26: launch_composite_fwd_t<26>(rg, sg, rec, W, H, L.TX, L.TY, gbuf, tf, nc, st); break;
+    default: launch_composite_fwd_t<42>(rg, sg, rec, W, H, L.TX, L.TY, gbuf, tf, nc, st); break;
+  }
+}
+
+void composite_bwd(int C, const Layout &L, void *ws, int W, int H, hipStream_t st) {
+  const uint2 *rg = at<uint2>(ws, L.ranges);
+  const uint32_t *sg = at<uint32_t>(ws, L.iv_a);
+  const float *rec = at<float>(ws, L.records);
+  const float *tf = at<float>(ws, L.t_final);
+  const uint32_t *nc = at<uint32_t>(ws, L.n_contrib);
+  const float *dG = at<float>(ws, L.dG);
+  const float *dT = at<float>(ws, L.dT);
+  float *ga = at<float>(ws, L.gacc);
+  switch (C) {
+    case 10: launch_composite_bwd_t<10>(rg, sg, rec, W, H, L.TX, L.TY, tf, nc, dG, dT, ga, st); break;
+    case 18: launch_composite_bwd_t<18>(rg, sg, rec, W, H, L.TX, L.TY, tf, nc, dG, dT, ga, st); break;
+    case 26: launch_composite_bwd_t<26>(rg, sg, rec, W, H, L.TX, L.TY, tf, nc, dG, dT, ga, st); break;
+    default: launch_composite_bwd_t<42>(rg, sg, rec, W, H, L.TX, L.TY, tf, nc, dG, dT, ga, st); break;
+  }
+}
+
+// Dispatch over (F, NET, WIDTH, IN_PAD) for the shading kernels.
+template <bool BWD>
+bool shade_dispatch(int F, int net, int width, const ShadeArgs &a, int nblocks, hipStream_t st) {
+  const int in_pad = in_pad_of(F + kNumPE + 6);
+  const int w = net ? width : 64;
+#define SSSGS_TRY(F_, NET_, W_, P_)                                              \
+  if (F == F_ && net == NET_ && w == W_ && in_pad == P_) {                     \
+    if constexpr (BWD) launch_shade_bwd_t<F_, NET_, W_, P_>(a, nblocks, st);   \
+    else launch_shade_fwd_t<F_, NET_, W_, P_>(a, st);                          \
+    return true;                                                                \
+  }
+  SSSGS_SHADE_INSTANCES(SSSGS_TRY)
+#undef SSSGS_TRY
+  return false;
+}
+
+}  // namespace
+
+extern "C" {
+
+int64_t sssgs_mlp_param_count(int32_t in_dim, int32_t width, int32_t hidden, int32_t out_dim) {
+  if (in_dim <= 0 || width <= 0 || hidden <= 0 || out_dim <= 0) return 0;
+  const int64_t ip = in_pad_of(in_dim);
+  return (int64_t)width * ip + width + (int64_t)(hidden - 1) * ((int64_t)width * width + width) +
+         (int64_t)out_dim * width + out_dim;
+}
+
+size_t sssgs_workspace_bytes(int32_t n, int32_t width, int32_t height, int32_t feat_dim, int32_t mlp_width,
+                             int64_t instance_capacity) {
+  Layout L;
+  if (!make_layout(n, width, height, feat_dim, mlp_width, instance_capacity, L)) return 0;
+  return L.total;
+}
+
+sssgs_status sssgs_workspace_layout(int32_t n, int32_t width, int32_t height, int32_t feat_dim, int32_t mlp_width,
+                                    int64_t instance_capacity, sssgs_layout *out) {
+  Layout L;
+  if (!out) return fail(SSSGS_ERR_INVALID_ARG, "null layout");
+  if (!make_layout(n, width, height, feat_dim, mlp_width, instance_capacity, L))
+    return fail(SSSGS_ERR_INVALID_ARG, "bad layout arguments");
+  out->records = L.records;
+  out->rec_stride = L.RS;
+  out->depth_keys = L.depth_keys;
+  out->rects = L.rects;
+  out->radii = L.radii;
+  out->tile_ranges = L.ranges;
+  out->sorted_gauss = L.iv_a;
+  out->sorted_tiles = L.ik_a;
+  out->t_final = L.t_final;
+  out->n_contrib = L.n_contrib;
+  out->status = L.status;
+  return SSSGS_OK;
+}
+
+sssgs_status sssgs_render_forward(const sssgs_gaussians *g, const sssgs_camera *cam, const sssgs_light *light,
+                                  const sssgs_mlp *mlp, const sssgs_options *opt, void *ws, size_t ws_bytes,
+                                  int64_t cap, float *out_rgb, float *out_gbuffer, float *out_alpha,
+                                  int64_t *out_num_instances, void *stream) {
+  int net, width;
+  sssgs_status s = check_common(g, cam, light, mlp, opt, ws, net, width);
+  if (s != SSSGS_OK) return s;
+  if (!out_rgb || !out_gbuffer || !out_alpha) return fail(SSSGS_ERR_INVALID_ARG, "null output");
+  Layout L;
+  if (!make_layout(g->n, cam->width, cam->height, g->feat_dim, width, cap, L))
+    return fail(SSSGS_ERR_INVALID_ARG, "bad sizes");
+  if (ws_bytes < L.total) return fail(SSSGS_ERR_INVALID_ARG, "workspace too small");
+  hipStream_t st = (hipStream_t)stream;
+  const CamArgs ca = cam_args(cam, L);
+  const ProjIn in = proj_in(g);
+  const uint32_t n = (uint32_t)g->n, ucap = (uint32_t)cap;
+  const int W = cam->width, H = cam->height;
+  float *rec = at<float>(ws, L.records);
+  uint32_t *dk = at<uint32_t>(ws, L.depth_keys), *ka = at<uint32_t>(ws, L.keys_a), *kb = at<uint32_t>(ws, L.keys_b);
+  uint32_t *va = at<uint32_t>(ws, L.vals_a), *vb = at<uint32_t>(ws, L.vals_b);
+  ushort4 *rects = at<ushort4>(ws, L.rects);
+  uint32_t *hist = at<uint32_t>(ws, L.hist), *part = at<uint32_t>(ws, L.partials);
+  uint32_t *mtot = at<uint32_t>(ws, L.m_total);
+  int32_t *status = at<int32_t>(ws, L.status);
+  // 1. projection (Eq. 1-2): records, depth keys, tile rectangles
+  {
+    Scope sc(kStProject, st);
+    project_fwd(g->feat_dim, g->sh_degree == 3, in, ca, rec, dk, va, rects, at<int32_t>(ws, L.radii), st);
+  }
+  // 2. depth passes of the radix sort on the N Gaussians (stable, index order on ties)
+  const uint32_t *kin = dk;
+  const uint32_t *vin = va;
+  {
+    Scope sc(kStSortDepth, st);
+    for (int pass = 0; pass < 4; pass++) {
+      uint32_t *ko = (pass & 1) ? ka : kb;
+      uint32_t *vo = (pass & 1) ? va : vb;
+      launch_radix_pass(kin, vin, ko, vo, n, nullptr, pass * kRadixBits, hist, part, st);
+      kin = ko;
+      vin = vo;
+    }
+  }
+  // sorted Gaussian indices are now in va
+  // 3. instance offsets: exclusive scan of the tiles each Gaussian touches, in depth order
+  uint32_t *tt = at<uint32_t>(ws, L.tt), *offs = at<uint32_t>(ws, L.offsets);
+  Scope *sc_expand = new Scope(kStExpand, st);
+  launch_gather_tiles(va, rects, n, tt, st);
+  launch_scan(tt, offs, n, part, mtot, st);
+  // 4. expand into (tile, Gaussian) instances, then the tile passes of the sort
+  int tbits = 0;
+  while ((1u << tbits) < (uint32_t)L.T) tbits++;
+  const int tpasses = (tbits + kRadixBits - 1) / kRadixBits;
+  uint32_t *ik_a = at<uint32_t>(ws, L.ik_a), *iv_a = at<uint32_t>(ws, L.iv_a);
+  uint32_t *ik_b = at<uint32_t>(ws, L.ik_b), *iv_b = at<uint32_t>(ws, L.iv_b);
+  uint32_t *ek = (tpasses & 1) ? ik_b : ik_a, *ev = (tpasses & 1) ? iv_b : iv_a;
+  launch_emit(va, rects, offs, n, ucap, L.TX, ek, ev, mtot, status, st);
+  delete sc_expand;
+  {
+    Scope sc(kStSortTiles, st);
+    for (int pass = 0; pass < tpasses; pass++) {
+      const bool from_a = (ek == ik_a) == (pass % 2 == 0);
+      uint32_t *ki = from_a ? ik_a : ik_b, *vi = from_a ? iv_a : iv_b;
+      uint32_t *ko = from_a ? ik_b : ik_a, *vo = from_a ? iv_b : iv_a;
+      launch_radix_pass(ki, vi, ko, vo, ucap, mtot, pass * kRadixBits, hist, part, st);
+    }
+  }
+  // 5. per-tile [start, end) ranges of the sorted instances
+  uint2 *ranges = at<uint2>(ws, L.ranges);
+  {
+    Scope sc(kStRanges, st);
+    launch_fill_u32(reinterpret_cast<uint32_t *>(ranges), 0u, 2u * (uint32_t)L.T, st);
+    launch_tile_ranges(ik_a, mtot, ucap, ranges, st);
+  }
+  // 6. compositing into the G-buffer (Eq. 3)
+  {
+    Scope sc(kStCompositeFwd, st);
+    composite_fwd(L.C, L, ws, W, H, out_gbuffer, st);
+  }
+  // 7. deferred shading (Eq. 4, 6, 7)
+  ShadeArgs sa;
+  memset(&sa, 0, sizeof(sa));
+  sa.cam = ca;
+  for (int k = 0; k < 3; k++) {
+    sa.light.pos[k] = light->pos[k];
+    sa.light.intensity[k] = light->intensity[k];
+  }
+  sa.gbuf = out_gbuffer;
+  sa.t_final = at<float>(ws, L.t_final);
+  sa.rgb = out_rgb;
+  sa.alpha = out_alpha;
+  if (net) {
+    sa.params = mlp->params;
+    sa.wops = at<void>(ws, L.wops);
+    launch_prep_weights(net, width, in_pad_of(mlp->in_dim), mlp->params, at<void>(ws, L.wops), nullptr, st);
+  }
+  {
+    Scope sc(kStShadeFwd, st);
+    if (!shade_dispatch<false>(g->feat_dim, net, width, sa, 0, st))
+      return fail(SSSGS_ERR_UNSUPPORTED, "no shading kernel for this configuration");
+  }
+  s = check_hip("forward launch");
+  if (s != SSSGS_OK) return s;
+  if (out_num_instances) {
+    int32_t hs[4];
+    if (hipMemcpyAsync(hs, status, sizeof(hs), hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+      return check_hip("instance count readback");
+    *out_num_instances = (int64_t)(uint32_t)hs[kStatusMLo];
+    if (hs[kStatusFlags] & kFlagOverflow) return fail(SSSGS_ERR_CAPACITY, "instance capacity exceeded");
+  }
+  return SSSGS_OK;
+}
+
+sssgs_status sssgs_render_backward(const sssgs_gaussians *g, const sssgs_camera *cam, const sssgs_light *light,
+                                   const sssgs_mlp *mlp, const sssgs_options *opt, void *ws, size_t ws_bytes,
+                                   int64_t cap, const float *gbuffer, const float *dL_drgb,
+                                   const float *dL_dgbuffer, const float *dL_dalpha, sssgs_gaussian_grads *grads,
+                                   float *dL_dmlp, void *stream) {
+  int net, width;
+  sssgs_status s = check_common(g, cam, light, mlp, opt, ws, net, width);
+  if (s != SSSGS_OK) return s;
+  if (!gbuffer || !dL_drgb || !grads) return fail(SSSGS_ERR_INVALID_ARG, "null gbuffer, dL_drgb or grads");
+  if (!(opt->accumulate_grads == 0 || opt->accumulate_grads == 1))
+    return fail(SSSGS_ERR_INVALID_ARG, "accumulate_grads must be 0 or 1");
+  Layout L;
+  if (!make_layout(g->n, cam->width, cam->height, g->feat_dim, width, cap, L))
+    return fail(SSSGS_ERR_INVALID_ARG, "bad sizes");
+  if (ws_bytes < L.total) return fail(SSSGS_ERR_INVALID_ARG, "workspace too small");
+  hipStream_t st = (hipStream_t)stream;
+  const CamArgs ca = cam_args(cam, L);
+  const int W = cam->width, H = cam->height;
+  // 1. shading backward: dL/dG (premultiplied), dL/dT_final, network gradients
+  ShadeArgs sa;
+  memset(&sa, 0, sizeof(sa));
+  sa.cam = ca;
+  for (int k = 0; k < 3; k++) {
+    sa.light.pos[k] = light->pos[k];
+    sa.light.intensity[k] = light->intensity[k];
+  }
+  sa.gbuf = gbuffer;
+  sa.t_final = at<float>(ws, L.t_final);
+  sa.drgb = dL_drgb;
+  sa.dgbuf_ext = dL_dgbuffer;
+  sa.dalpha_ext = dL_dalpha;
+  sa.dG = at<float>(ws, L.dG);
+  sa.dT = at<float>(ws, L.dT);
+  if (net) {
+    sa.params = mlp->params;
+    sa.wops = at<void>(ws, L.wops);
+    sa.tops = at<void>(ws, L.tops);
+    sa.mlp_partials = at<float>(ws, L.mlp_part);
+    sa.nparams = L.nparams;
+    launch_prep_weights(net, width, in_pad_of(mlp->in_dim), mlp->params, at<void>(ws, L.wops),
+                        at<void>(ws, L.tops), st);
+  }
+  const int nblk = L.shade_bwd_blocks;
+  {
+    Scope sc(kStShadeBwd, st);
+    if (!shade_dispatch<true>(g->feat_dim, net, width, sa, nblk, st))
+      return fail(SSSGS_ERR_UNSUPPORTED, "no shading kernel for this configuration");
+  }
+  if (net && dL_dmlp) {
+    Scope sc(kStMlpReduce, st);
+    const int ip = in_pad_of(mlp->in_dim);
+    const int parts = shade_bwd_grid(net, width, ip, L.T, nblk) * shade_bwd_waves(net, width, ip);
+    launch_reduce_partials(sa.mlp_partials, parts, L.nparams, dL_dmlp, opt->accumulate_grads, st);
+  }
+  // 2. compositing backward into the per-Gaussian accumulators
+  launch_zero_f32(at<float>(ws, L.gacc), (size_t)(g->n) * L.GS, st);
+  {
+    Scope sc(kStCompositeBwd, st);
+    composite_bwd(L.C, L, ws, W, H, st);
+  }
+  // 3. projection backward
+  ProjGradOut go;
+  go.means = grads->means; go.log_scales = grads->log_scales; go.quats = grads->quats;
+  go.opacity_logits = grads->opacity_logits; go.albedo = grads->albedo; go.roughness = grads->roughness;
+  go.metallic = grads->metallic; go.sss = grads->sss; go.features = grads->features; go.sh = grads->sh;
+  go.accumulate = opt->accumulate_grads;
+  {
+    Scope sc(kStProjectBwd, st);
+    project_bwd(g->feat_dim, g->sh_degree == 3, proj_in(g), ca, at<float>(ws, L.gacc), go, st);
+  }
+  return check_hip("backward launch");
+}
+
+sssgs_status sssgs_l1_loss(const float *pred, const float *target, int64_t count, float scale, float *loss_out,
+                           float *dL_dpred, void *stream) {
+  if (count < 0) return fail(SSSGS_ERR_INVALID_ARG, "count < 0");
+  if (count > 0 && (!pred || !target)) return fail(SSSGS_ERR_INVALID_ARG, "null pred or target");
+  launch_l1_loss(pred, target, count, scale, loss_out, dL_dpred, (hipStream_t)stream);
+  return check_hip("l1 launch");
+}
+
+sssgs_status sssgs_workspace_status(const void *ws, int32_t n, int32_t width, int32_t height, int32_t feat_dim,
+                                    int32_t mlp_width, int64_t cap, void *stream, int32_t *flags_out,
+                                    int64_t *num_out) {
+  Layout L;
+  if (!ws) return fail(SSSGS_ERR_INVALID_ARG, "null workspace");
+  if (!make_layout(n, width, height, feat_dim, mlp_width, cap, L)) return fail(SSSGS_ERR_INVALID_ARG, "bad sizes");
+  int32_t hs[4];
+  hipStream_t st = (hipStream_t)stream;
+  if (hipMemcpyAsync(hs, static_cast<const char *>(ws) + L.status, sizeof(hs), hipMemcpyDeviceToHost, st) !=
+          hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess)
+    return check_hip("status readback");
+  if (flags_out) *flags_out = hs[kStatusFlags];
+  if (num_out) *num_out = (int64_t)(uint32_t)hs[kStatusMLo];
+  return SSSGS_OK;
+}
+
+const char *sssgs_status_string(sssgs_status s) {
+  switch (s) {
+    case SSSGS_OK: return "ok";
+    case SSSGS_ERR_INVALID_ARG: return "invalid argument";
+    case SSSGS_ERR_CAPACITY: return "instance capacity exceeded";
+    case SSSGS_ERR_UNSUPPORTED: return "unsupported configuration";
+    case SSSGS_ERR_HIP: return "HIP error";
+  }
+  return "unknown status";
+}
+
+const char *sssgs_last_error(void) { return g_last_error.c_str(); }
+
+sssgs_status sssgs_timing_enable(int32_t on) {
+  g_timer.on = on != 0;
+  return SSSGS_OK;
+}
+
+sssgs_status sssgs_timing_read(int32_t max_stages, double *total_ms, int32_t *launches, int32_t *n_stages) {
+  if (!total_ms || !launches || !n_stages || max_stages < (int32_t)kStCount)
+    return fail(SSSGS_ERR_INVALID_ARG, "timing_read needs arrays of sssgs_timing_stages() entries");
+  for (int k = 0; k < kStCount; k++) {
+    total_ms[k] = 0.0;
+    launches[k] = 0;
+  }
+  sssgs_status s = SSSGS_OK;
+  for (const TimerRec &r : g_timer.recs) {
+    float ms = 0.f;
+    if (hipEventSynchronize(r.b) != hipSuccess || hipEventElapsedTime(&ms, r.a, r.b) != hipSuccess) {
+      s = check_hip("timing read");
+    } else {
+      total_ms[r.stage] += ms;
+      launches[r.stage] += 1;
+    }
+    g_timer.pool.push_back(r.a);
+    g_timer.pool.push_back(r.b);
+  }
+  g_timer.recs.clear();
+  *n_stages = kStCount;
+  return s;
+}
+
+int32_t sssgs_timing_stages(void) { return kStCount; }
+
+const char *sssgs_timing_stage_name(int32_t k) { return (k >= 0 && k < kStCount) ? kStageNames[k] : ""; }
+
+}  // extern "C"

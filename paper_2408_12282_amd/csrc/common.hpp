@@ -1,0 +1,60 @@
+// common.hpp -- shared definitions of the gfx950 kernels behind libsssgs.so.
+// The CPU oracle shares nothing with this file.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace sssgs {
+
+constexpr int kTile = 16;            // 16x16 pixel tiles
+constexpr int kTilePix = kTile * kTile;
+constexpr int kChAlb = 0, kChNrm = 3, kChRough = 6, kChMetal = 7, kChSss = 8, kChDepth = 9, kChFeat = 10;
+constexpr int kNumPE = 36;           // 6 octaves x {sin, cos} x 3 axes
+constexpr int kRadixBits = 8;
+constexpr int kRadixBins = 1 << kRadixBits;
+constexpr int kSortThreads = 256;
+constexpr int kSortRounds = 8;                     // keys per thread per radix block
+constexpr int kSortItems = kSortThreads * kSortRounds;
+constexpr int kScanThreads = 256;
+constexpr int kScanItems = kScanThreads * 4;
+
+// Floats per splat record: u, v, conic (a, b, c), opacity, C channels; padded to 16 B.
+__host__ __device__ constexpr int rec_stride(int C) { return (6 + C + 3) / 4 * 4; }
+// Per-Gaussian gradient accumulator: du dv dA dB dC dopacity | dchannels, padded to 16 B.
+__host__ __device__ constexpr int grad_stride(int C) { return (6 + C + 3) / 4 * 4; }
+
+struct CamArgs {
+  float R[9], t[3], fx, fy, cx, cy;
+  int W, H, TX, TY;
+  float Cw[3];   // camera centre in world space
+};
+
+struct LightArgs {
+  float pos[3], intensity[3];
+};
+
+__device__ __forceinline__ float4 ld4(const float *p) { return *reinterpret_cast<const float4 *>(p); }
+__device__ __forceinline__ void st4(float *p, float4 v) { *reinterpret_cast<float4 *>(p) = v; }
+
+// Splat power at a pixel: -0.5 (a dx^2 + c dy^2) - b dx dy with dx = u - px.
+// The operation sequence is pinned so that forward and backward kernels take
+// bit-identical decisions.
+__device__ __forceinline__ float splat_power(float u, float v, float ca, float cb, float cc, float px, float py,
+                                             float &dx, float &dy) {
+  dx = u - px;
+  dy = v - py;
+  float q = __fmul_rn(ca, __fmul_rn(dx, dx));
+  q = __fmaf_rn(cc, __fmul_rn(dy, dy), q);
+  return __fmaf_rn(-0.5f, q, -__fmul_rn(cb, __fmul_rn(dx, dy)));
+}
+
+// exp via the hardware exp2 (v_exp_f32) with a folded log2(e).
+__device__ __forceinline__ float fast_exp(float x) { return __builtin_amdgcn_exp2f(__fmul_rn(x, 1.44269504088896341f)); }
+
+__device__ __forceinline__ float splat_alpha_raw(float opacity, float power) { return __fmul_rn(opacity, fast_exp(power)); }
+
+// Status word layout in the workspace.
+constexpr int kStatusFlags = 0, kStatusMLo = 1, kStatusMHi = 2;
+constexpr int kFlagOverflow = 1;
+
+}  // namespace sssgs

@@ -1,0 +1,61 @@
+// launch.hpp -- host-side launchers of the kernels (defined next to them).
+#pragma once
+#include "common.hpp"
+
+namespace sssgs {
+
+struct ProjIn {
+  int n;
+  const float *means, *log_scales, *quats, *opacity_logits, *albedo, *roughness, *metallic, *sss, *features, *sh;
+};
+struct ProjGradOut {
+  float *means, *log_scales, *quats, *opacity_logits, *albedo, *roughness, *metallic, *sss, *features, *sh;
+  int accumulate;
+};
+struct ShadeArgs;
+
+template <int F, bool SH>
+void launch_project_fwd_t(const ProjIn &in, const CamArgs &cam, float *records, uint32_t *keys, uint32_t *vals,
+                          ushort4 *rects, int32_t *radii, hipStream_t st);
+template <int F, bool SH>
+void launch_project_bwd_t(const ProjIn &in, const CamArgs &cam, const float *gacc, const ProjGradOut &out,
+                          hipStream_t st);
+
+void launch_scan(const uint32_t *in, uint32_t *out, uint32_t n, uint32_t *partials, uint32_t *total_dev,
+                 hipStream_t st);
+uint32_t radix_blocks(uint64_t n);
+uint32_t scan_partials_needed(uint64_t n);
+void launch_radix_pass(const uint32_t *kin, const uint32_t *vin, uint32_t *kout, uint32_t *vout, uint32_t n_host,
+                       const uint32_t *n_dev, int shift, uint32_t *hist, uint32_t *partials, hipStream_t st);
+void launch_gather_tiles(const uint32_t *sorted_g, const ushort4 *rects, uint32_t n, uint32_t *tt, hipStream_t st);
+void launch_emit(const uint32_t *sorted_g, const ushort4 *rects, const uint32_t *offsets, uint32_t n, uint32_t cap,
+                 int TX, uint32_t *ik, uint32_t *iv, const uint32_t *m_dev, int32_t *status, hipStream_t st);
+void launch_fill_u32(uint32_t *p, uint32_t v, uint32_t n, hipStream_t st);
+void launch_tile_ranges(const uint32_t *keys, const uint32_t *m_dev, uint32_t cap, uint2 *ranges, hipStream_t st);
+
+template <int C>
+void launch_composite_fwd_t(const uint2 *ranges, const uint32_t *sorted_g, const float *records, int W, int H,
+                            int TX, int TY, float *gbuf, float *t_final, uint32_t *n_contrib, hipStream_t st);
+template <int C>
+void launch_composite_bwd_t(const uint2 *ranges, const uint32_t *sorted_g, const float *records, int W, int H,
+                            int TX, int TY, const float *t_final, const uint32_t *n_contrib, const float *dG,
+                            const float *dT, float *gacc, hipStream_t st);
+
+template <int F, int NET, int WIDTH, int IN_PAD>
+void launch_shade_fwd_t(const ShadeArgs &a, hipStream_t st);
+template <int F, int NET, int WIDTH, int IN_PAD>
+void launch_shade_bwd_t(const ShadeArgs &a, int nblocks, hipStream_t st);
+int shade_bwd_waves(int net, int width, int in_pad);
+int shade_bwd_grid(int net, int width, int in_pad, int tiles, int max_blocks);
+
+// network weight preparation and gradient reduction (mlp_prep.hip)
+void launch_prep_weights(int net, int width, int in_pad, const float *params, void *wops, void *tops,
+                         hipStream_t st);
+size_t prep_weight_bytes(int width, int in_pad);
+void launch_reduce_partials(const float *partials, int nblocks, int nparams, float *out, int accumulate,
+                            hipStream_t st);
+void launch_l1_loss(const float *pred, const float *target, int64_t count, float scale, float *loss_out,
+                    float *grad, hipStream_t st);
+void launch_zero_f32(float *p, size_t n, hipStream_t st);
+
+}  // namespace sssgs

@@ -1,0 +1,569 @@
+// shade_bwd.hip -- backward of the per-pixel deferred shading (Sec. 3.2,
+// Eq. 4, 6, 7): from dL/d(rgb) to dL/d(G-buffer), dL/d(T_final) and the
+// network parameter gradients.
+//
+// Persistent grid; each wave shades 64-pixel strips (16 x 4).  The network
+// forward is recomputed (layer 3 input kept, layers 1-2 recomputed as
+// needed); input gradients use the transposed weights on the matrix cores
+// (dX^T = W^T dY^T, consuming the accumulator layout directly); weight
+// gradients dW = dY^T X (K = the strip's 64 pixels) go through an LDS
+// transpose and are added to a per-wave partial owned by that wave alone, so
+// the final reduction over partials is deterministic.
+#include "launch.hpp"
+#include "shade_common.hpp"
+
+namespace sssgs {
+
+// B-operand packing of a masked upstream gradient (D layout -> permuted K).
+template <class M, int MB>
+__device__ __forceinline__ void grad_to_ops(const f32x4 (&d)[MB][4], typename M::Op (&B)[(MB * 16) / M::KS][4]) {
+  constexpr int KSN = (MB * 16) / M::KS;
+#pragma unroll
+  for (int ks = 0; ks < KSN; ks++)
+#pragma unroll
+    for (int nb = 0; nb < 4; nb++) {
+      if constexpr (M::KPL == 8) {
+        bf16x8 o;
+#pragma unroll
+        for (int j = 0; j < 8; j++) o[j] = (__bf16)d[2 * ks + (j >> 2)][nb][j & 3];
+        B[ks][nb] = o;
+      } else {
+        B[ks][nb] = d[ks >> 2][nb][ks & 3];
+      }
+    }
+}
+
+// Activation value held in op H[ks][nb] for D-layout position (mb, j).
+template <class M, int KSN>
+__device__ __forceinline__ float act_at(const typename M::Op (&H)[KSN][4], int mb, int nb, int j) {
+  if constexpr (M::KPL == 8) return (float)H[mb >> 1][nb][4 * (mb & 1) + j];
+  else return H[4 * mb + j][nb];
+}
+
+// One forward layer from B operands H (K = WIDTH) to accumulators.
+template <class M, int MB, int KSN>
+__device__ __forceinline__ void layer_mma(const typename M::Op *__restrict__ w, const typename M::Op (&H)[KSN][4],
+                                          f32x4 (&acc)[MB][4], int lane) {
+#pragma unroll
+  for (int mb = 0; mb < MB; mb++)
+#pragma unroll
+    for (int nb = 0; nb < 4; nb++) acc[mb][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int ks = 0; ks < KSN; ks++)
+#pragma unroll
+    for (int mb = 0; mb < MB; mb++) {
+      const typename M::Op a = w[(mb * KSN + ks) * 64 + lane];
+#pragma unroll
+      for (int nb = 0; nb < 4; nb++) acc[mb][nb] = M::mma(a, H[ks][nb], acc[mb][nb]);
+    }
+}
+
+template <class M, int MB, int KS0>
+__device__ __forceinline__ void layer0_mma(const typename M::Op *__restrict__ w, const typename M::Elem *xs, int XS,
+                                           f32x4 (&acc)[MB][4], int lane) {
+  const int g = lane >> 4, col = lane & 15;
+#pragma unroll
+  for (int mb = 0; mb < MB; mb++)
+#pragma unroll
+    for (int nb = 0; nb < 4; nb++) acc[mb][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int ks = 0; ks < KS0; ks++) {
+    typename M::Op B[4];
+#pragma unroll
+    for (int nb = 0; nb < 4; nb++) B[nb] = load_op_lds<M>(xs + (16 * nb + col) * XS + ks * M::KS + g * M::KPL);
+#pragma unroll
+    for (int mb = 0; mb < MB; mb++) {
+      const typename M::Op a = w[(mb * KS0 + ks) * 64 + lane];
+#pragma unroll
+      for (int nb = 0; nb < 4; nb++) acc[mb][nb] = M::mma(a, B[nb], acc[mb][nb]);
+    }
+  }
+}
+
+// Staging of the weight-gradient operands.  For BF16 (8 pixels per lane and
+// k-step) both factors are stored feature-major [feat][px]; for FP32 (one
+// pixel per lane and k-step) pixel-major [px][feat].
+template <class M>
+struct Stage {
+  static constexpr bool FM = M::KPL == 8;  // feature-major
+  static constexpr int PXS = 64 + 8;       // feature-major row stride (elements)
+  __device__ static __forceinline__ int idx(int feat, int px, int fstride) {
+    return FM ? feat * PXS + px : px * fstride + feat;
+  }
+};
+
+// dW[o][k] += sum over the wave's 64 pixels of dY[o][px] X[k][px].
+// dy: staged upstream gradient (rows o < ROWS16), xk: staged layer input
+// (features k < KCOLS).  Adds into the wave's partial at W offset `woff`
+// (row-major [rows][cols]) for o < rows, k < cols.
+template <class M, int ROWS16, int KCOLS>
+__device__ __forceinline__ void dw_accumulate(const typename M::Elem *dy, int dys, const typename M::Elem *xk,
+                                              int xks, float *__restrict__ part, int woff, int rows, int cols,
+                                              bool first, int lane) {
+  using Op = typename M::Op;
+  using ST = Stage<M>;
+  constexpr int MBO = ROWS16 / 16, NBK = KCOLS / 16, KSP = 64 / M::KS;
+  const int g = lane >> 4, col = lane & 15;
+#pragma unroll
+  for (int mbo = 0; mbo < MBO; mbo++) {
+    f32x4 acc[NBK];
+#pragma unroll
+    for (int nbk = 0; nbk < NBK; nbk++) acc[nbk] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int ks = 0; ks < KSP; ks++) {
+      const int px0 = ks * M::KS + g * M::KPL;
+      Op a;
+      if constexpr (M::KPL == 8) a = *reinterpret_cast<const bf16x8 *>(dy + ST::idx(16 * mbo + col, px0, dys));
+      else a = dy[ST::idx(16 * mbo + col, px0, dys)];
+#pragma unroll
+      for (int nbk = 0; nbk < NBK; nbk++) {
+        Op b;
+        if constexpr (M::KPL == 8) b = *reinterpret_cast<const bf16x8 *>(xk + ST::idx(16 * nbk + col, px0, xks));
+        else b = xk[ST::idx(16 * nbk + col, px0, xks)];
+        acc[nbk] = M::mma(a, b, acc[nbk]);
+      }
+    }
+    // D layout: lane (col, g) holds dW[16 mbo + 4 g + j][16 nbk + col]
+#pragma unroll
+    for (int nbk = 0; nbk < NBK; nbk++)
+#pragma unroll
+      for (int j = 0; j < 4; j++) {
+        const int o = 16 * mbo + 4 * g + j, k = 16 * nbk + col;
+        if (o < rows && k < cols) {
+          float *p = part + woff + o * cols + k;
+          *p = first ? acc[nbk][j] : *p + acc[nbk][j];
+        }
+      }
+  }
+}
+
+// Sum of D-layout values over the wave's pixels per output feature -> bias gradient.
+template <int MB>
+__device__ __forceinline__ void db_accumulate(const f32x4 (&d)[MB][4], float *__restrict__ part, int boff, int rows,
+                                              bool first, int lane) {
+  const int g = lane >> 4, col = lane & 15;
+#pragma unroll
+  for (int mb = 0; mb < MB; mb++)
+#pragma unroll
+    for (int j = 0; j < 4; j++) {
+      float s = (d[mb][0][j] + d[mb][1][j]) + (d[mb][2][j] + d[mb][3][j]);
+      s += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(s), 0xB1, 0xF, 0xF, false));
+      s += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(s), 0x4E, 0xF, 0xF, false));
+      s += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(s), 0x141, 0xF, 0xF, false));
+      s += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(s), 0x140, 0xF, 0xF, false));
+      const int o = 16 * mb + 4 * g + j;
+      if (col == 0 && o < rows) {
+        float *p = part + boff + o;
+        *p = first ? s : *p + s;
+      }
+    }
+}
+
+// Write D-layout values (feature f = 16 mb + 4 g + j, pixel 16 nb + col) into a stage.
+template <class M, int MB>
+__device__ __forceinline__ void stage_d(const f32x4 (&d)[MB][4], typename M::Elem *st, int fstride, int lane) {
+  using ST = Stage<M>;
+  const int g = lane >> 4, col = lane & 15;
+#pragma unroll
+  for (int mb = 0; mb < MB; mb++)
+#pragma unroll
+    for (int nb = 0; nb < 4; nb++)
+#pragma unroll
+      for (int j = 0; j < 4; j++) st[ST::idx(16 * mb + 4 * g + j, 16 * nb + col, fstride)] = M::cvt(d[mb][nb][j]);
+}
+
+// Write B-operand activations (permuted features) into a stage at their true feature index.
+template <class M, int KSN>
+__device__ __forceinline__ void stage_ops(const typename M::Op (&H)[KSN][4], typename M::Elem *st, int fstride,
+                                          int lane) {
+  using ST = Stage<M>;
+  const int g = lane >> 4, col = lane & 15;
+#pragma unroll
+  for (int ks = 0; ks < KSN; ks++)
+#pragma unroll
+    for (int nb = 0; nb < 4; nb++) {
+      if constexpr (M::KPL == 8) {
+#pragma unroll
+        for (int j = 0; j < 8; j++) st[ST::idx(feat_index<M>(false, ks, g, j), 16 * nb + col, fstride)] = H[ks][nb][j];
+      } else {
+        st[ST::idx(feat_index<M>(false, ks, g, 0), 16 * nb + col, fstride)] = H[ks][nb];
+      }
+    }
+}
+
+// -------------------------------------------------------------- per pixel
+
+// Backward of everything after the network outputs (or of the light
+// fall-off without network): fills dgbar (d L / d mean values) and returns
+// d L / d a (direct part).  dnet_in: gradient w.r.t. the network input vector
+// (or null), used for features, position encoding and directions.
+template <int C, int F, bool NET>
+__device__ __forceinline__ float shade_pixel_bwd(const PixShade &S, const float *gb, const float *gL,
+                                                 const LightArgs &light, const float *dnet_in, float *dgbar) {
+#pragma unroll
+  for (int k = 0; k < C; k++) dgbar[k] = 0.f;
+  float dA = 0.f, gLo[3];
+  for (int c = 0; c < 3; c++) {
+    dA += gL[c] * S.L[c];
+    gLo[c] = S.a * gL[c];
+  }
+  float dfs[3], dfd[3], dcos = 0.f, dx[3] = {0.f, 0.f, 0.f}, dwo[3] = {0.f, 0.f, 0.f}, dwi[3] = {0.f, 0.f, 0.f};
+  float dvi[3] = {0.f, 0.f, 0.f};
+  if constexpr (!NET) {
+    float dli2 = 0.f;
+    for (int c = 0; c < 3; c++) {
+      dfs[c] = gLo[c] * S.Lin[c] * S.cosI;
+      dfd[c] = dfs[c];
+      const float dLin = gLo[c] * (S.fs[c] + S.fd[c]) * S.cosI;
+      dcos += gLo[c] * (S.fs[c] + S.fd[c]) * S.Lin[c];
+      dli2 -= dLin * light.intensity[c] / (S.li2 * S.li2);
+    }
+    if (dot3(S.vi, S.vi) >= 1e-12f)
+      for (int k = 0; k < 3; k++) dvi[k] += 2.f * dli2 * S.vi[k];
+  } else {
+    const float sss = gb[kChSss] * S.ia;
+    float dsss = 0.f;
+    for (int c = 0; c < 3; c++) {
+      const float B = S.fs[c] + S.fd[c];
+      dsss += gLo[c] * (S.Lsss[c] - B * S.Lin[c] * S.cosI);
+      dfs[c] = gLo[c] * (1.f - sss) * S.Lin[c] * S.cosI;
+      dfd[c] = dfs[c];
+      dcos += gLo[c] * (1.f - sss) * B * S.Lin[c];
+    }
+    dgbar[kChSss] += dsss;
+#pragma unroll
+    for (int f = 0; f < F; f++) dgbar[kChFeat + f] += dnet_in[f];
+    int p = F;
+#pragma unroll
+    for (int oct = 0; oct < 6; oct++) {
+      const float sc = (float)(1 << oct);
+      float cs[3], sn[3];
+#pragma unroll
+      for (int ax = 0; ax < 3; ax++) {
+        sn[ax] = sinpif(sc * S.x[ax]);
+        cs[ax] = cospif(sc * S.x[ax]);
+      }
+#pragma unroll
+      for (int ax = 0; ax < 3; ax++) dx[ax] += dnet_in[p + ax] * (sc * kPi) * cs[ax];
+#pragma unroll
+      for (int ax = 0; ax < 3; ax++) dx[ax] -= dnet_in[p + 3 + ax] * (sc * kPi) * sn[ax];
+      p += 6;
+    }
+    for (int k = 0; k < 3; k++) dwo[k] += dnet_in[p + k];
+    for (int k = 0; k < 3; k++) dwi[k] += dnet_in[p + 3 + k];
+  }
+  // BRDF
+  const float r = gb[kChRough] * S.ia, m = gb[kChMetal] * S.ia;
+  float dD = 0.f, dGv = 0.f, dQ = 0.f, dVoH = 0.f, dm = 0.f;
+  const float w = S.w, w4 = (w * w) * (w * w), w5 = w4 * w;
+  for (int c = 0; c < 3; c++) {
+    dD += dfs[c] * S.F[c] * S.Gv * S.Q;
+    const float dF = dfs[c] * S.D * S.Gv * S.Q;
+    dGv += dfs[c] * S.D * S.F[c] * S.Q;
+    dQ += dfs[c] * S.D * S.F[c] * S.Gv;
+    const float dF0 = dF * (1.f - w5);
+    dVoH -= dF * (1.f - S.F0[c]) * 5.f * w4;
+    const float b = gb[kChAlb + c] * S.ia;
+    dgbar[kChAlb + c] += dfd[c] * (1.f - m) * (1.f / kPi) + dF0 * m;
+    dm += -dfd[c] * b * (1.f / kPi) + dF0 * (b - 0.04f);
+  }
+  float dNoV = -dQ * S.Q / S.NoV, dNoL = -dQ * S.Q / S.NoL;
+  const float dg1v = dGv * S.g1l, dg1l = dGv * S.g1v;
+  dNoV += dg1v * S.k / (S.dv * S.dv);
+  dNoL += dg1l * S.k / (S.dl * S.dl);
+  const float dk = -dg1v * S.NoV * (1.f - S.NoV) / (S.dv * S.dv) - dg1l * S.NoL * (1.f - S.NoL) / (S.dl * S.dl);
+  float dr = dk * (r + 1.f) * 0.25f;
+  const float ag = S.ag, den = S.den;
+  const float dag = dD * (2.f * ag / (kPi * den * den)) * (1.f - 2.f * ag * ag * S.NoH * S.NoH / den);
+  const float dNoH = dD * (-2.f * ag * ag / (kPi * den * den * den)) * 2.f * S.NoH * (ag * ag - 1.f);
+  dr += dag * 2.f * r;
+  dgbar[kChRough] += dr;
+  dgbar[kChMetal] += dm;
+  const float dnov = S.nov > 1e-4f ? dNoV : 0.f;
+  const float dnol = (S.nol > 1e-4f ? dNoL : 0.f) + (S.nol > 0.f ? dcos : 0.f);
+  const float dnoh = S.noh > 0.f ? dNoH : 0.f;
+  const float dvoh = S.voh > 0.f ? dVoH : 0.f;
+  float dn[3], dh[3];
+  for (int k = 0; k < 3; k++) {
+    dn[k] = dnov * S.wo[k] + dnol * S.wi[k] + dnoh * S.h[k];
+    dwo[k] += dnov * S.n[k] + dvoh * S.h[k];
+    dwi[k] += dnol * S.n[k];
+    dh[k] = dnoh * S.n[k] + dvoh * S.wo[k];
+  }
+  // normalisations v / max(|v|, eps)
+  auto nbwd = [](const float *v, float l, const float *o, const float *dout, float *dv) {
+    if (l > 1e-12f) {
+      const float p = dot3(o, dout), il = 1.f / l;
+      for (int k = 0; k < 3; k++) dv[k] += (dout[k] - o[k] * p) * il;
+    } else {
+      for (int k = 0; k < 3; k++) dv[k] += dout[k] * 1e12f;
+    }
+    (void)v;
+  };
+  float dhv[3] = {0.f, 0.f, 0.f};
+  nbwd(S.hv, S.hl, S.h, dh, dhv);
+  for (int k = 0; k < 3; k++) {
+    dwo[k] += dhv[k];
+    dwi[k] += dhv[k];
+  }
+  float dvo[3] = {0.f, 0.f, 0.f};
+  nbwd(S.vo, S.lo, S.wo, dwo, dvo);
+  nbwd(S.vi, S.li, S.wi, dwi, dvi);
+  for (int k = 0; k < 3; k++) dx[k] -= dvo[k] + dvi[k];
+  dgbar[kChDepth] += dot3(dx, S.ray);
+  float dnr[3] = {0.f, 0.f, 0.f};
+  nbwd(S.nraw, S.nlen, S.n, dn, dnr);
+  for (int k = 0; k < 3; k++) dgbar[kChNrm + k] += dnr[k];
+  return dA;
+}
+
+// -------------------------------------------------------------- kernel
+
+// Waves per workgroup: bounded by the LDS each wave needs (160 KB per CU).
+template <int NET, int WIDTH, int IN_PAD> struct BwdWaves {
+  static constexpr int value = NET == 0 ? 4 : ((NET == 2 && WIDTH == 64 && IN_PAD == 64) ? 4 : 2);
+};
+
+int shade_bwd_waves(int net, int width, int in_pad) {
+  return net == 0 ? 4 : ((net == 2 && width == 64 && in_pad == 64) ? 4 : 2);
+}
+
+template <int F, int NET, int WIDTH, int IN_PAD>
+__global__ __launch_bounds__((BwdWaves<NET, WIDTH, IN_PAD>::value * 64)) void shade_bwd_kernel(ShadeArgs A, int nstrips) {
+  using M = typename NetTraits<NET>::M;
+  using E = typename M::Elem;
+  using Op = typename M::Op;
+  using NS = NetShape<M, WIDTH, IN_PAD>;
+  using PO = ParamOffsets<WIDTH, IN_PAD>;
+  using ST = Stage<M>;
+  constexpr int NW = BwdWaves<NET, WIDTH, IN_PAD>::value;
+  constexpr int C = kChFeat + F;
+  constexpr int MB = NS::MB;
+  constexpr int XS = IN_PAD + XPad<M>::value;
+  constexpr int FMAX = WIDTH > IN_PAD ? WIDTH : IN_PAD;
+  constexpr int FST = FMAX + 4;  // pixel-major stage stride (FP32)
+  // per wave: input rows, two stages, network outputs / upstream, input gradient
+  constexpr int STAGE_ELEMS = ST::FM ? FMAX * ST::PXS : 64 * FST;
+  constexpr int XS_ELEMS = 64 * XS;
+  __shared__ E xs_all[NET ? NW * XS_ELEMS : 1];
+  __shared__ E st_all[NET ? NW * 2 * STAGE_ELEMS : 1];
+  __shared__ float io_all[NET ? NW * 64 * 8 : 1];
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int g = lane >> 4, col = lane & 15;
+  E *xs = xs_all + (NET ? w * XS_ELEMS : 0);
+  E *sdy = st_all + (NET ? w * 2 * STAGE_ELEMS : 0);
+  E *sxk = sdy + (NET ? STAGE_ELEMS : 0);
+  float *io = io_all + (NET ? w * 64 * 8 : 0);
+  float *dxin = reinterpret_cast<float *>(sdy);  // [64][IN_PAD + 1] after the last weight gradient
+  float *part = A.mlp_partials ? A.mlp_partials + (size_t)(blockIdx.x * NW + w) * A.nparams : nullptr;
+  const size_t HW = (size_t)A.cam.W * A.cam.H;
+  bool first = true;
+  for (int s0 = blockIdx.x * NW; s0 < nstrips; s0 += gridDim.x * NW) {
+    const int strip = s0 + w;
+    const int tile = strip >> 2, sub = strip & 3;
+    const int tx = tile % A.cam.TX, ty = tile / A.cam.TX;
+    const int px = tx * kTile + (lane & 15), py = ty * kTile + 4 * sub + (lane >> 4);
+    const bool inside = strip < nstrips && px < A.cam.W && py < A.cam.H;
+    const size_t pix = inside ? (size_t)py * A.cam.W + px : 0;
+    float gb[C];
+    float T = 1.f, gL[3] = {0.f, 0.f, 0.f};
+    if (inside) {
+#pragma unroll
+      for (int c = 0; c < C; c++) gb[c] = A.gbuf[c * HW + pix];
+      T = A.t_final[pix];
+      for (int c = 0; c < 3; c++) gL[c] = A.drgb[c * HW + pix];
+    } else {
+#pragma unroll
+      for (int c = 0; c < C; c++) gb[c] = 0.f;
+    }
+    PixShade S;
+    shade_geometry<C>(gb, T, (float)px + 0.5f, (float)py + 0.5f, A.cam, A.light, NET != 0, S);
+    if (S.bg || !inside)
+      for (int c = 0; c < 3; c++) gL[c] = 0.f;
+    float dgbar[C];
+    float dA;
+    if constexpr (NET != 0) {
+      const Op *__restrict__ wops = reinterpret_cast<const Op *>(A.wops);
+      const Op *__restrict__ tops = reinterpret_cast<const Op *>(A.tops);
+      // ---- network forward (inputs in LDS, layer-3 input kept)
+      build_net_input<F, IN_PAD, M>(gb, S, xs + lane * XS);
+      __syncthreads();
+      f32x4 acc[MB][4];
+      Op H3[NS::KSH][4];
+      {
+        Op Ht[NS::KSH][4];
+        layer0_mma<M, MB, NS::KS0>(wops, xs, XS, acc, lane);
+        acc_to_ops<M, MB>(acc, A.params + PO::b(0), g, Ht);
+        layer_mma<M, MB, NS::KSH>(wops + NS::L0, Ht, acc, lane);
+        acc_to_ops<M, MB>(acc, A.params + PO::b(1), g, Ht);
+        layer_mma<M, MB, NS::KSH>(wops + NS::L0 + NS::LH, Ht, acc, lane);
+        acc_to_ops<M, MB>(acc, A.params + PO::b(2), g, H3);
+      }
+      f32x4 oacc[1][4];
+      layer_mma<M, 1, NS::KSH>(wops + NS::L0 + 2 * NS::LH, H3, oacc, lane);
+      if (g < 2)
+#pragma unroll
+        for (int nb = 0; nb < 4; nb++)
+#pragma unroll
+          for (int j = 0; j < 4; j++) {
+            const int o = 4 * g + j;
+            io[(16 * nb + col) * 8 + o] = oacc[0][nb][j] + (o < 6 ? A.params[PO::b(3) + o] : 0.f);
+          }
+      __syncthreads();
+      // ---- per pixel: outputs, Eq. 7, upstream gradient of the outputs
+      float o[6];
+      for (int k = 0; k < 6; k++) o[k] = io[lane * 8 + k];
+      combine_net(S, gb[kChSss], o);
+      {
+        const float sss = gb[kChSss] * S.ia;
+        float dout[8];
+        for (int c = 0; c < 3; c++) {
+          const float gLo = S.a * gL[c];
+          const float dLin = gLo * (1.f - sss) * (S.fs[c] + S.fd[c]) * S.cosI;
+          dout[c] = o[c] > 0.f ? dLin : 0.f;
+          dout[3 + c] = gLo * sss * S.Lsss[c] * (1.f - S.Lsss[c]);
+        }
+        dout[6] = dout[7] = 0.f;
+        __syncthreads();
+        for (int k = 0; k < 8; k++) io[lane * 8 + k] = dout[k];
+      }
+      __syncthreads();
+      // ---- output layer: dW3, db3, dH3 = W3^T dout
+      f32x4 dO[1][4];
+#pragma unroll
+      for (int nb = 0; nb < 4; nb++)
+#pragma unroll
+        for (int j = 0; j < 4; j++) dO[0][nb][j] = (g < 2) ? io[(16 * nb + col) * 8 + 4 * g + j] : 0.f;
+      stage_d<M, 1>(dO, sdy, FST, lane);
+      stage_ops<M, NS::KSH>(H3, sxk, FST, lane);
+      __syncthreads();
+      dw_accumulate<M, 16, WIDTH>(sdy, FST, sxk, FST, part, PO::w(3), 6, WIDTH, first, lane);
+      db_accumulate<1>(dO, part, PO::b(3), 6, first, lane);
+      f32x4 dH[MB][4];
+      {
+        Op Bo[NS::KT_O][4];
+#pragma unroll
+        for (int ks = 0; ks < NS::KT_O; ks++)
+#pragma unroll
+          for (int nb = 0; nb < 4; nb++) {
+            if constexpr (M::KPL == 8) {
+              bf16x8 v;
+#pragma unroll
+              for (int j = 0; j < 8; j++) v[j] = (__bf16)(j < 4 ? dO[0][nb][j] : 0.f);
+              Bo[ks][nb] = v;
+            } else {
+              Bo[ks][nb] = dO[0][nb][ks];
+            }
+          }
+        layer_mma<M, MB, NS::KT_O>(tops + NS::T0 + 2 * NS::TH, Bo, dH, lane);
+      }
+      // ---- hidden layers 2 and 1 (inputs recomputed), then layer 0
+      Op H1[NS::KSH][4], H2[NS::KSH][4];
+      layer0_mma<M, MB, NS::KS0>(wops, xs, XS, acc, lane);
+      acc_to_ops<M, MB>(acc, A.params + PO::b(0), g, H1);
+      layer_mma<M, MB, NS::KSH>(wops + NS::L0, H1, acc, lane);
+      acc_to_ops<M, MB>(acc, A.params + PO::b(1), g, H2);
+#pragma unroll
+      for (int l = 2; l >= 1; l--) {
+        // mask by the ReLU of this layer's output (held in H_{l+1})
+#pragma unroll
+        for (int mb = 0; mb < MB; mb++)
+#pragma unroll
+          for (int nb = 0; nb < 4; nb++)
+#pragma unroll
+            for (int j = 0; j < 4; j++) {
+              const float hv = (l == 2) ? act_at<M, NS::KSH>(H3, mb, nb, j) : act_at<M, NS::KSH>(H2, mb, nb, j);
+              if (!(hv > 0.f)) dH[mb][nb][j] = 0.f;
+            }
+        __syncthreads();
+        stage_d<M, MB>(dH, sdy, FST, lane);
+        if (l == 2) stage_ops<M, NS::KSH>(H2, sxk, FST, lane);
+        else stage_ops<M, NS::KSH>(H1, sxk, FST, lane);
+        __syncthreads();
+        dw_accumulate<M, WIDTH, WIDTH>(sdy, FST, sxk, FST, part, PO::w(l), WIDTH, WIDTH, first, lane);
+        db_accumulate<MB>(dH, part, PO::b(l), WIDTH, first, lane);
+        Op Bd[NS::KSH][4];
+        grad_to_ops<M, MB>(dH, Bd);
+        layer_mma<M, MB, NS::KT_H>(tops + NS::T0 + (l - 1) * NS::TH, Bd, dH, lane);
+      }
+      // layer 0: mask by ReLU of h1, dW0 with the input rows, dX = W0^T dpre0
+#pragma unroll
+      for (int mb = 0; mb < MB; mb++)
+#pragma unroll
+        for (int nb = 0; nb < 4; nb++)
+#pragma unroll
+          for (int j = 0; j < 4; j++)
+            if (!(act_at<M, NS::KSH>(H1, mb, nb, j) > 0.f)) dH[mb][nb][j] = 0.f;
+      __syncthreads();
+      stage_d<M, MB>(dH, sdy, FST, lane);
+      if constexpr (ST::FM) {
+        // input rows [px][k] -> feature-major stage
+        for (int k = 0; k < IN_PAD; k++) sxk[ST::idx(k, lane, FST)] = xs[lane * XS + k];
+      } else {
+        for (int k = 0; k < IN_PAD; k++) sxk[ST::idx(k, lane, FST)] = xs[lane * XS + k];
+      }
+      __syncthreads();
+      dw_accumulate<M, WIDTH, IN_PAD>(sdy, FST, sxk, FST, part, PO::w(0), WIDTH, IN_PAD, first, lane);
+      db_accumulate<MB>(dH, part, PO::b(0), WIDTH, first, lane);
+      f32x4 dX[NS::MB0][4];
+      {
+        Op Bd[NS::KSH][4];
+        grad_to_ops<M, MB>(dH, Bd);
+        layer_mma<M, NS::MB0, NS::KT_H>(tops, Bd, dX, lane);
+      }
+      __syncthreads();
+      // dX (D layout over input features) -> per-pixel rows
+#pragma unroll
+      for (int mb = 0; mb < NS::MB0; mb++)
+#pragma unroll
+        for (int nb = 0; nb < 4; nb++)
+#pragma unroll
+          for (int j = 0; j < 4; j++) dxin[(16 * nb + col) * (IN_PAD + 1) + 16 * mb + 4 * g + j] = dX[mb][nb][j];
+      __syncthreads();
+      float din[F + kNumPE + 6];
+#pragma unroll
+      for (int k = 0; k < F + kNumPE + 6; k++) din[k] = dxin[lane * (IN_PAD + 1) + k];
+      dA = shade_pixel_bwd<C, F, true>(S, gb, gL, A.light, din, dgbar);
+      first = false;
+    } else {
+      dA = shade_pixel_bwd<C, F, false>(S, gb, gL, A.light, nullptr, dgbar);
+    }
+    if (inside) {
+      float dT = 0.f;
+      if (!S.bg) {
+#pragma unroll
+        for (int k = 0; k < C; k++) dA -= dgbar[k] * gb[k] * S.ia * S.ia;
+        dT = -dA;
+      }
+      if (A.dalpha_ext) dT -= A.dalpha_ext[pix];
+      A.dT[pix] = dT;
+#pragma unroll
+      for (int k = 0; k < C; k++) {
+        float v = S.bg ? 0.f : dgbar[k] * S.ia;
+        if (A.dgbuf_ext) v += A.dgbuf_ext[k * HW + pix];
+        A.dG[k * HW + pix] = v;
+      }
+    }
+  }
+}
+
+// Workgroups of the persistent grid: every workgroup gets at least one strip.
+int shade_bwd_grid(int net, int width, int in_pad, int tiles, int max_blocks) {
+  const int nw = shade_bwd_waves(net, width, in_pad), nstrips = tiles * 4;
+  int grid = (nstrips + nw - 1) / nw;
+  if (grid > max_blocks) grid = max_blocks;
+  return grid < 1 ? 1 : grid;
+}
+
+template <int F, int NET, int WIDTH, int IN_PAD>
+void launch_shade_bwd_t(const ShadeArgs &a, int nblocks, hipStream_t st) {
+  constexpr int NW = BwdWaves<NET, WIDTH, IN_PAD>::value;
+  const int grid = shade_bwd_grid(NET, WIDTH, IN_PAD, a.cam.TX * a.cam.TY, nblocks);
+  shade_bwd_kernel<F, NET, WIDTH, IN_PAD><<<grid, NW * 64, 0, st>>>(a, a.cam.TX * a.cam.TY * 4);
+}
+
+#define SSSGS_SHADE_BWD(F, NET, WIDTH, IN_PAD) \
+  template void launch_shade_bwd_t<F, NET, WIDTH, IN_PAD>(const ShadeArgs &, int, hipStream_t);
+SSSGS_SHADE_INSTANCES(SSSGS_SHADE_BWD)
+
+}  // namespace sssgs

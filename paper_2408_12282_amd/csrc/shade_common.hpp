@@ -1,0 +1,280 @@
+// shade_common.hpp -- per-pixel shading math shared by the forward and
+// backward shading kernels, and the wave-level network forward.
+#pragma once
+#include "mlp.hpp"
+
+namespace sssgs {
+
+struct ShadeArgs {
+  CamArgs cam;
+  LightArgs light;
+  const float *gbuf;     // [C][H][W] premultiplied
+  const float *t_final;  // [H][W]
+  float *rgb;            // [3][H][W]
+  float *alpha;          // [H][W] or null
+  const void *wops;      // prepared forward weights (MmaF32::Op or MmaBF16::Op)
+  const void *tops;      // prepared transposed weights (backward)
+  const float *params;   // raw parameters (biases are read from here)
+  // backward
+  const float *drgb, *dgbuf_ext, *dalpha_ext;
+  float *dG;             // [C][H][W] out
+  float *dT;             // [H][W] out
+  float *mlp_partials;   // [gridDim.x][nparams] out
+  int nparams;
+};
+
+template <int NET> struct NetTraits { using M = MmaF32; };
+template <> struct NetTraits<2> { using M = MmaBF16; };
+
+template <class M> struct XPad { static constexpr int value = 4; };
+template <> struct XPad<MmaBF16> { static constexpr int value = 8; };
+
+constexpr float kPi = 3.14159265358979323846f;
+
+struct PixShade {
+  bool bg;
+  float a, ia;
+  float nraw[3], nlen, n[3];
+  float ray[3], x[3];
+  float vo[3], lo, wo[3], vi[3], li, wi[3], hv[3], hl, h[3];
+  float nov, nol, noh, voh, NoV, NoL, NoH, VoH, cosI;
+  float ag, den, D, k, dv, dl, g1v, g1l, Gv, Q, w;
+  float F0[3], F[3], fs[3], fd[3];
+  float li2, Lin[3], Lsss[3];
+  float L[3];
+};
+
+__device__ __forceinline__ float dot3(const float *a, const float *b) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
+
+// v / max(|v|, 1e-12); returns |v|
+__device__ __forceinline__ float norm3(const float *v, float *o) {
+  const float l = sqrtf(dot3(v, v));
+  const float inv = 1.f / fmaxf(l, 1e-12f);
+  o[0] = v[0] * inv; o[1] = v[1] * inv; o[2] = v[2] * inv;
+  return l;
+}
+
+// Geometry and BRDF of one pixel from its premultiplied G-buffer values.
+template <int C>
+__device__ __forceinline__ void shade_geometry(const float *gb, float T, float uc, float vc, const CamArgs &cam,
+                                               const LightArgs &light, bool net, PixShade &S) {
+  S.a = 1.f - T;
+  S.bg = !(S.a >= 1e-6f);
+  S.ia = S.bg ? 0.f : 1.f / S.a;
+  for (int k = 0; k < 3; k++) S.nraw[k] = gb[kChNrm + k] * S.ia;
+  S.nlen = norm3(S.nraw, S.n);
+  const float rc0 = (uc - cam.cx) / cam.fx, rc1 = (vc - cam.cy) / cam.fy;
+  const float dbar = gb[kChDepth] * S.ia;
+  for (int k = 0; k < 3; k++) {
+    S.ray[k] = cam.R[k] * rc0 + cam.R[3 + k] * rc1 + cam.R[6 + k];
+    S.x[k] = cam.Cw[k] + dbar * S.ray[k];
+    S.vo[k] = cam.Cw[k] - S.x[k];
+    S.vi[k] = light.pos[k] - S.x[k];
+  }
+  S.lo = norm3(S.vo, S.wo);
+  S.li = norm3(S.vi, S.wi);
+  for (int k = 0; k < 3; k++) S.hv[k] = S.wo[k] + S.wi[k];
+  S.hl = norm3(S.hv, S.h);
+  S.nov = dot3(S.n, S.wo);
+  S.nol = dot3(S.n, S.wi);
+  S.noh = dot3(S.n, S.h);
+  S.voh = dot3(S.wo, S.h);
+  S.NoV = fmaxf(S.nov, 1e-4f);
+  S.NoL = fmaxf(S.nol, 1e-4f);
+  S.NoH = fmaxf(S.noh, 0.f);
+  S.VoH = fmaxf(S.voh, 0.f);
+  S.cosI = fmaxf(S.nol, 0.f);
+  const float r = gb[kChRough] * S.ia, m = gb[kChMetal] * S.ia;
+  // GGX distribution, alpha = roughness^2
+  S.ag = r * r;
+  S.den = S.NoH * S.NoH * (S.ag * S.ag - 1.f) + 1.f;
+  S.D = S.ag * S.ag / (kPi * S.den * S.den);
+  // Smith / Schlick-GGX shadowing, k = (r + 1)^2 / 8
+  S.k = (r + 1.f) * (r + 1.f) * 0.125f;
+  S.dv = S.NoV * (1.f - S.k) + S.k;
+  S.dl = S.NoL * (1.f - S.k) + S.k;
+  S.g1v = S.NoV / S.dv;
+  S.g1l = S.NoL / S.dl;
+  S.Gv = S.g1v * S.g1l;
+  S.Q = 1.f / (4.f * S.NoV * S.NoL);
+  S.w = 1.f - S.VoH;
+  const float w2 = S.w * S.w, w5 = w2 * w2 * S.w;
+  for (int c = 0; c < 3; c++) {
+    const float b = gb[kChAlb + c] * S.ia;
+    S.F0[c] = 0.04f * (1.f - m) + b * m;
+    S.F[c] = S.F0[c] + (1.f - S.F0[c]) * w5;
+    S.fs[c] = S.D * S.F[c] * S.Gv * S.Q;
+    S.fd[c] = (1.f - m) * b * (1.f / kPi);
+  }
+  if (!net) {
+    S.li2 = fmaxf(dot3(S.vi, S.vi), 1e-12f);
+    for (int c = 0; c < 3; c++) {
+      S.Lin[c] = light.intensity[c] / S.li2;
+      S.L[c] = (S.fs[c] + S.fd[c]) * S.Lin[c] * S.cosI;
+    }
+  }
+}
+
+// Network input [features | sin/cos(2^k pi x) | w_o | w_i | 0 ...] into an LDS row.
+template <int F, int IN_PAD, class M>
+__device__ __forceinline__ void build_net_input(const float *gb, const PixShade &S, typename M::Elem *row) {
+  int p = 0;
+#pragma unroll
+  for (int f = 0; f < F; f++) row[p++] = M::cvt(gb[kChFeat + f] * S.ia);
+#pragma unroll
+  for (int oct = 0; oct < 6; oct++) {
+    const float sc = (float)(1 << oct);
+    float sv[3], cv[3];
+#pragma unroll
+    for (int ax = 0; ax < 3; ax++) {
+      sv[ax] = sinpif(sc * S.x[ax]);
+      cv[ax] = cospif(sc * S.x[ax]);
+    }
+#pragma unroll
+    for (int ax = 0; ax < 3; ax++) row[p++] = M::cvt(sv[ax]);
+#pragma unroll
+    for (int ax = 0; ax < 3; ax++) row[p++] = M::cvt(cv[ax]);
+  }
+#pragma unroll
+  for (int k = 0; k < 3; k++) row[p++] = M::cvt(S.wo[k]);
+#pragma unroll
+  for (int k = 0; k < 3; k++) row[p++] = M::cvt(S.wi[k]);
+#pragma unroll
+  for (; p < IN_PAD; p++) row[p] = M::cvt(0.f);
+}
+
+__device__ __forceinline__ void combine_net(PixShade &S, float sss_pre, const float *o) {
+  const float sss = sss_pre * S.ia;
+  for (int c = 0; c < 3; c++) {
+    S.Lin[c] = fmaxf(o[c], 0.f);
+    S.Lsss[c] = 1.f / (1.f + expf(-o[3 + c]));
+    S.L[c] = sss * S.Lsss[c] + (1.f - sss) * (S.fs[c] + S.fd[c]) * S.Lin[c] * S.cosI;
+  }
+}
+
+// ----------------------------------------------------------------- network
+
+// Offsets into the packed parameter vector.
+template <int WIDTH, int IN_PAD>
+struct ParamOffsets {
+  static constexpr int w(int l) {  // three hidden layers, six outputs
+    return l == 0 ? 0 : WIDTH * IN_PAD + WIDTH + (l - 1) * (WIDTH * WIDTH + WIDTH);
+  }
+  static constexpr int rows(int l) { return l == 3 ? 6 : WIDTH; }
+  static constexpr int cols(int l) { return l == 0 ? IN_PAD : WIDTH; }
+  static constexpr int b(int l) { return w(l) + rows(l) * cols(l); }
+  static constexpr int total() { return b(3) + 6; }
+};
+
+template <class M>
+__device__ __forceinline__ typename M::Op load_op_lds(const typename M::Elem *p) {
+  if constexpr (M::KPL == 8) return *reinterpret_cast<const bf16x8 *>(p);
+  else return *p;
+}
+
+// Pack the bias-added, ReLU-ed accumulators of a layer into the next layer's
+// B operands (permuted K order, see feat_index).
+template <class M, int MB>
+__device__ __forceinline__ void acc_to_ops(const f32x4 (&acc)[MB][4], const float *bias, int g,
+                                           typename M::Op (&H)[(MB * 16) / M::KS][4]) {
+  constexpr int KSN = (MB * 16) / M::KS;
+#pragma unroll
+  for (int ks = 0; ks < KSN; ks++)
+#pragma unroll
+    for (int nb = 0; nb < 4; nb++) {
+      if constexpr (M::KPL == 8) {
+        bf16x8 o;
+#pragma unroll
+        for (int j = 0; j < 8; j++) {
+          const int mb = 2 * ks + (j >> 2), jj = j & 3;
+          o[j] = (__bf16)fmaxf(acc[mb][nb][jj] + bias[16 * mb + 4 * g + jj], 0.f);
+        }
+        H[ks][nb] = o;
+      } else {
+        const int mb = ks >> 2, jj = ks & 3;
+        H[ks][nb] = fmaxf(acc[mb][nb][jj] + bias[16 * mb + 4 * g + jj], 0.f);
+      }
+    }
+}
+
+// Forward of the whole network for the wave's 64 pixels.  xs: LDS rows of
+// the inputs (row stride XS).  Writes the 6 outputs of pixel p (bias added,
+// before the output activations) to outs[p * 8 + o].
+template <class M, int WIDTH, int IN_PAD, bool SAVE>
+__device__ __forceinline__ void net_forward_wave(const void *wops_v, const float *__restrict__ params,
+                                                 const typename M::Elem *xs, int XS, float *outs, void *) {
+  using Op = typename M::Op;
+  using NS = NetShape<M, WIDTH, IN_PAD>;
+  using PO = ParamOffsets<WIDTH, IN_PAD>;
+  constexpr int MB = NS::MB, KS0 = NS::KS0, KSH = NS::KSH;
+  const Op *__restrict__ wops = reinterpret_cast<const Op *>(wops_v);
+  const int lane = threadIdx.x & 63, g = lane >> 4, col = lane & 15;
+  f32x4 acc[MB][4];
+  Op H[KSH][4];
+  // layer 0: B operands from the LDS input rows
+#pragma unroll
+  for (int mb = 0; mb < MB; mb++)
+#pragma unroll
+    for (int nb = 0; nb < 4; nb++) acc[mb][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int ks = 0; ks < KS0; ks++) {
+    Op B[4];
+#pragma unroll
+    for (int nb = 0; nb < 4; nb++) B[nb] = load_op_lds<M>(xs + (16 * nb + col) * XS + ks * M::KS + g * M::KPL);
+#pragma unroll
+    for (int mb = 0; mb < MB; mb++) {
+      const Op a = wops[(mb * KS0 + ks) * 64 + lane];
+#pragma unroll
+      for (int nb = 0; nb < 4; nb++) acc[mb][nb] = M::mma(a, B[nb], acc[mb][nb]);
+    }
+  }
+  acc_to_ops<M, MB>(acc, params + PO::b(0), g, H);
+  const Op *wl = wops + NS::L0;
+  // hidden layers 1, 2
+#pragma unroll
+  for (int l = 1; l < 3; l++) {
+#pragma unroll
+    for (int mb = 0; mb < MB; mb++)
+#pragma unroll
+      for (int nb = 0; nb < 4; nb++) acc[mb][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int ks = 0; ks < KSH; ks++)
+#pragma unroll
+      for (int mb = 0; mb < MB; mb++) {
+        const Op a = wl[(mb * KSH + ks) * 64 + lane];
+#pragma unroll
+        for (int nb = 0; nb < 4; nb++) acc[mb][nb] = M::mma(a, H[ks][nb], acc[mb][nb]);
+      }
+    acc_to_ops<M, MB>(acc, params + PO::b(l), g, H);
+    wl += NS::LH;
+  }
+  // output layer: 6 rows of one 16-row block
+  f32x4 oacc[4];
+#pragma unroll
+  for (int nb = 0; nb < 4; nb++) oacc[nb] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int ks = 0; ks < KSH; ks++) {
+    const Op a = wl[ks * 64 + lane];
+#pragma unroll
+    for (int nb = 0; nb < 4; nb++) oacc[nb] = M::mma(a, H[ks][nb], oacc[nb]);
+  }
+  if (g < 2) {
+    const float *bo = params + PO::b(3);
+#pragma unroll
+    for (int nb = 0; nb < 4; nb++)
+#pragma unroll
+      for (int j = 0; j < 4; j++) {
+        const int o = 4 * g + j;
+        outs[(16 * nb + col) * 8 + o] = oacc[nb][j] + (o < 6 ? bo[o] : 0.f);
+      }
+  }
+}
+
+// Instances: (F, NET, WIDTH, IN_PAD).  NET 0 = no network, 1 = FP32, 2 = BF16.
+#define SSSGS_SHADE_INSTANCES(X) \
+  X(0, 0, 64, 64) X(0, 1, 64, 64) X(0, 2, 64, 64) X(0, 2, 128, 64) \
+  X(8, 0, 64, 64) X(8, 1, 64, 64) X(8, 2, 64, 64) X(8, 2, 128, 64) \
+  X(16, 0, 64, 64) X(16, 1, 64, 64) X(16, 2, 64, 64) X(16, 2, 128, 64) \
+  X(32, 0, 64, 96) X(32, 1, 64, 96) X(32, 2, 64, 96) X(32, 2, 128, 96)
+
+}  // namespace sssgs

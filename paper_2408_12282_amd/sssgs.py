@@ -1,0 +1,336 @@
+"""Thin Python binding of libsssgs.so (see include/sssgs.h) plus a
+torch.autograd.Function around it.
+
+Only argument marshalling happens here: every step of projection, binning,
+compositing and shading runs in the library's HIP kernels.  PyTorch provides
+device memory and the current HIP stream.  There is no CPU fallback: when the
+library is missing, importing the binding raises.
+"""
+from __future__ import annotations
+
+import ctypes as ct
+import os
+from typing import Optional, Sequence
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libsssgs.so")
+
+OK, ERR_INVALID_ARG, ERR_CAPACITY, ERR_UNSUPPORTED, ERR_HIP = 0, -1, -2, -3, -4
+PREC_FP32, PREC_BF16 = 0, 1
+PARAM_NAMES = ("means", "log_scales", "quats", "opacity_logits", "albedo", "roughness", "metallic", "sss",
+               "features", "sh")
+
+_fp = ct.POINTER(ct.c_float)
+
+
+class Gaussians(ct.Structure):
+    _fields_ = [("n", ct.c_int32), ("feat_dim", ct.c_int32), ("sh_degree", ct.c_int32)] + \
+               [(k, ct.c_void_p) for k in PARAM_NAMES]
+
+
+class GaussianGrads(ct.Structure):
+    _fields_ = [(k, ct.c_void_p) for k in PARAM_NAMES]
+
+
+class Camera(ct.Structure):
+    _fields_ = [("R", ct.c_float * 9), ("t", ct.c_float * 3), ("fx", ct.c_float), ("fy", ct.c_float),
+                ("cx", ct.c_float), ("cy", ct.c_float), ("width", ct.c_int32), ("height", ct.c_int32)]
+
+
+class Light(ct.Structure):
+    _fields_ = [("pos", ct.c_float * 3), ("intensity", ct.c_float * 3)]
+
+
+class Mlp(ct.Structure):
+    _fields_ = [("in_dim", ct.c_int32), ("width", ct.c_int32), ("hidden", ct.c_int32), ("out_dim", ct.c_int32),
+                ("params", ct.c_void_p)]
+
+
+class Options(ct.Structure):
+    _fields_ = [("precision", ct.c_int32), ("accumulate_grads", ct.c_int32)]
+
+
+class Layout(ct.Structure):
+    _fields_ = [("records", ct.c_size_t), ("rec_stride", ct.c_int32), ("depth_keys", ct.c_size_t),
+                ("rects", ct.c_size_t), ("radii", ct.c_size_t), ("tile_ranges", ct.c_size_t),
+                ("sorted_gauss", ct.c_size_t), ("sorted_tiles", ct.c_size_t), ("t_final", ct.c_size_t),
+                ("n_contrib", ct.c_size_t), ("status", ct.c_size_t)]
+
+
+EXPORTS = ("sssgs_mlp_param_count", "sssgs_workspace_bytes", "sssgs_render_forward", "sssgs_render_backward",
+           "sssgs_l1_loss", "sssgs_workspace_status", "sssgs_workspace_layout", "sssgs_status_string",
+           "sssgs_last_error", "sssgs_timing_enable", "sssgs_timing_read", "sssgs_timing_stages",
+           "sssgs_timing_stage_name")
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libsssgs.so and declare its signatures.  Raises if the file is absent."""
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it first (python -m paper_2408_12282_amd.build)")
+    L = ct.CDLL(path)
+    L.sssgs_mlp_param_count.restype = ct.c_int64
+    L.sssgs_mlp_param_count.argtypes = [ct.c_int32] * 4
+    L.sssgs_workspace_bytes.restype = ct.c_size_t
+    L.sssgs_workspace_bytes.argtypes = [ct.c_int32] * 5 + [ct.c_int64]
+    L.sssgs_render_forward.restype = ct.c_int
+    L.sssgs_render_forward.argtypes = [ct.POINTER(Gaussians), ct.POINTER(Camera), ct.POINTER(Light),
+                                       ct.POINTER(Mlp), ct.POINTER(Options), ct.c_void_p, ct.c_size_t, ct.c_int64,
+                                       ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.POINTER(ct.c_int64), ct.c_void_p]
+    L.sssgs_render_backward.restype = ct.c_int
+    L.sssgs_render_backward.argtypes = [ct.POINTER(Gaussians), ct.POINTER(Camera), ct.POINTER(Light),
+                                        ct.POINTER(Mlp), ct.POINTER(Options), ct.c_void_p, ct.c_size_t, ct.c_int64,
+                                        ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_void_p,
+                                        ct.POINTER(GaussianGrads), ct.c_void_p, ct.c_void_p]
+    L.sssgs_l1_loss.restype = ct.c_int
+    L.sssgs_l1_loss.argtypes = [ct.c_void_p, ct.c_void_p, ct.c_int64, ct.c_float, ct.c_void_p, ct.c_void_p,
+                                ct.c_void_p]
+    L.sssgs_workspace_status.restype = ct.c_int
+    L.sssgs_workspace_status.argtypes = [ct.c_void_p] + [ct.c_int32] * 5 + [ct.c_int64, ct.c_void_p,
+                                                                           ct.POINTER(ct.c_int32),
+                                                                           ct.POINTER(ct.c_int64)]
+    L.sssgs_workspace_layout.restype = ct.c_int
+    L.sssgs_workspace_layout.argtypes = [ct.c_int32] * 5 + [ct.c_int64, ct.POINTER(Layout)]
+    L.sssgs_status_string.restype = ct.c_char_p
+    L.sssgs_status_string.argtypes = [ct.c_int]
+    L.sssgs_last_error.restype = ct.c_char_p
+    L.sssgs_last_error.argtypes = []
+    L.sssgs_timing_enable.restype = ct.c_int
+    L.sssgs_timing_enable.argtypes = [ct.c_int32]
+    L.sssgs_timing_read.restype = ct.c_int
+    L.sssgs_timing_read.argtypes = [ct.c_int32, ct.POINTER(ct.c_double), ct.POINTER(ct.c_int32),
+                                    ct.POINTER(ct.c_int32)]
+    L.sssgs_timing_stages.restype = ct.c_int32
+    L.sssgs_timing_stages.argtypes = []
+    L.sssgs_timing_stage_name.restype = ct.c_char_p
+    L.sssgs_timing_stage_name.argtypes = [ct.c_int32]
+    return L
+
+
+_LIB = None
+
+
+def lib():
+    global _LIB
+    if _LIB is None:
+        _LIB = load_library()
+    return _LIB
+
+
+class SSSGSError(RuntimeError):
+    def __init__(self, status: int):
+        L = lib()
+        super().__init__(f"{L.sssgs_status_string(status).decode()}: {L.sssgs_last_error().decode()}")
+        self.status = status
+
+
+def _check(status: int):
+    if status != OK:
+        raise SSSGSError(status)
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    if t is None:
+        return None
+    assert t.is_contiguous() and t.dtype == torch.float32, "float32 contiguous tensors expected"
+    return ct.c_void_p(t.data_ptr())
+
+
+def _stream():
+    return ct.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+# ------------------------------------------------------------------ same-name C entry points
+
+def sssgs_mlp_param_count(in_dim, width, hidden=3, out_dim=6) -> int:
+    return int(lib().sssgs_mlp_param_count(in_dim, width, hidden, out_dim))
+
+
+def sssgs_workspace_bytes(n, width, height, feat_dim, mlp_width, instance_capacity) -> int:
+    return int(lib().sssgs_workspace_bytes(n, width, height, feat_dim, mlp_width, instance_capacity))
+
+
+def sssgs_workspace_layout(n, width, height, feat_dim, mlp_width, instance_capacity) -> Layout:
+    lay = Layout()
+    _check(lib().sssgs_workspace_layout(n, width, height, feat_dim, mlp_width, instance_capacity, ct.byref(lay)))
+    return lay
+
+
+def sssgs_render_forward(g, cam, light, mlp, opt, workspace, ws_bytes, capacity, out_rgb, out_gbuffer, out_alpha,
+                         want_count=False, stream=None):
+    cnt = ct.c_int64(0)
+    st = lib().sssgs_render_forward(ct.byref(g), ct.byref(cam), ct.byref(light), ct.byref(mlp) if mlp else None,
+                                    ct.byref(opt), workspace, ws_bytes, capacity, out_rgb, out_gbuffer, out_alpha,
+                                    ct.byref(cnt) if want_count else None, stream)
+    return st, int(cnt.value)
+
+
+def sssgs_render_backward(g, cam, light, mlp, opt, workspace, ws_bytes, capacity, gbuffer, drgb, dgbuf, dalpha,
+                          grads, dmlp, stream=None):
+    return lib().sssgs_render_backward(ct.byref(g), ct.byref(cam), ct.byref(light), ct.byref(mlp) if mlp else None,
+                                       ct.byref(opt), workspace, ws_bytes, capacity, gbuffer, drgb, dgbuf, dalpha,
+                                       ct.byref(grads), dmlp, stream)
+
+
+def sssgs_l1_loss(pred, target, count, scale, loss_out, grad, stream=None):
+    return lib().sssgs_l1_loss(pred, target, count, scale, loss_out, grad, stream)
+
+
+def sssgs_workspace_status(workspace, n, width, height, feat_dim, mlp_width, capacity, stream=None):
+    flags = ct.c_int32(0)
+    num = ct.c_int64(0)
+    _check(lib().sssgs_workspace_status(workspace, n, width, height, feat_dim, mlp_width, capacity, stream,
+                                        ct.byref(flags), ct.byref(num)))
+    return int(flags.value), int(num.value)
+
+
+def sssgs_timing_enable(on: bool):
+    _check(lib().sssgs_timing_enable(int(bool(on))))
+
+
+def sssgs_timing_read() -> dict:
+    """Stage name -> (summed ms, launches) of the calls timed since the last read."""
+    L = lib()
+    k = L.sssgs_timing_stages()
+    ms = (ct.c_double * k)()
+    cnt = (ct.c_int32 * k)()
+    ns = ct.c_int32(0)
+    _check(L.sssgs_timing_read(k, ms, cnt, ct.byref(ns)))
+    return {L.sssgs_timing_stage_name(i).decode(): (ms[i], cnt[i]) for i in range(ns.value)}
+
+
+def sssgs_timing_stages() -> int:
+    return int(lib().sssgs_timing_stages())
+
+
+def sssgs_timing_stage_name(k: int) -> str:
+    return lib().sssgs_timing_stage_name(k).decode()
+
+
+# ------------------------------------------------------------------ helpers
+
+def make_camera(cam) -> Camera:
+    """From scene.Camera (numpy R, t, intrinsics)."""
+    return Camera((ct.c_float * 9)(*[float(v) for v in cam.R.reshape(-1)]),
+                  (ct.c_float * 3)(*[float(v) for v in cam.t.reshape(-1)]),
+                  float(cam.fx), float(cam.fy), float(cam.cx), float(cam.cy), int(cam.width), int(cam.height))
+
+
+def make_light(light) -> Light:
+    return Light((ct.c_float * 3)(*[float(v) for v in light.pos]),
+                 (ct.c_float * 3)(*[float(v) for v in light.intensity]))
+
+
+def gaussians_struct(params: dict, feat_dim: int, sh_degree: int) -> Gaussians:
+    n = int(params["means"].shape[1])
+    return Gaussians(n, feat_dim, sh_degree, *[_ptr(params.get(k)) if params.get(k) is not None
+                                               and params[k].numel() else None for k in PARAM_NAMES])
+
+
+def grads_struct(grads: dict) -> GaussianGrads:
+    return GaussianGrads(*[_ptr(grads.get(k)) if grads.get(k) is not None and grads[k].numel() else None
+                           for k in PARAM_NAMES])
+
+
+class View:
+    """Everything one view needs on the device: workspace and output buffers."""
+
+    def __init__(self, n: int, width: int, height: int, feat_dim: int, mlp_width: int, capacity: int,
+                 device="cuda"):
+        self.n, self.width, self.height, self.feat_dim, self.mlp_width = n, width, height, feat_dim, mlp_width
+        self.capacity = int(capacity)
+        self.C = 10 + feat_dim
+        self.ws_bytes = sssgs_workspace_bytes(n, width, height, feat_dim, mlp_width, self.capacity)
+        if self.ws_bytes == 0:
+            raise SSSGSError(ERR_INVALID_ARG)
+        self.workspace = torch.empty(self.ws_bytes, dtype=torch.uint8, device=device)
+        self.layout = sssgs_workspace_layout(n, width, height, feat_dim, mlp_width, self.capacity)
+
+    def region(self, offset: int, count: int, dtype=torch.int32) -> torch.Tensor:
+        """A typed view of `count` elements of the workspace at byte `offset`."""
+        nbytes = count * torch.empty((), dtype=dtype).element_size()
+        return self.workspace[offset:offset + nbytes].view(dtype)
+
+
+def render_forward(view: View, params: dict, sh_degree: int, cam: Camera, light: Light, mlp_params=None,
+                   mlp_width: int = 64, precision: int = PREC_BF16, want_count: bool = False):
+    """One forward call.  Returns (rgb [3,H,W], gbuf [C,H,W], alpha [H,W], M or None)."""
+    dev = params["means"].device
+    H, W = view.height, view.width
+    rgb = torch.empty((3, H, W), dtype=torch.float32, device=dev)
+    gbuf = torch.empty((view.C, H, W), dtype=torch.float32, device=dev)
+    alpha = torch.empty((H, W), dtype=torch.float32, device=dev)
+    g = gaussians_struct(params, view.feat_dim, sh_degree)
+    m = None
+    if mlp_params is not None:
+        m = Mlp(view.feat_dim + 42, mlp_width, 3, 6, _ptr(mlp_params))
+    opt = Options(precision, 0)
+    st, cnt = sssgs_render_forward(g, cam, light, m, opt, ct.c_void_p(view.workspace.data_ptr()), view.ws_bytes,
+                                   view.capacity, _ptr(rgb), _ptr(gbuf), _ptr(alpha), want_count, _stream())
+    _check(st)
+    return rgb, gbuf, alpha, (cnt if want_count else None)
+
+
+def render_backward(view: View, params: dict, sh_degree: int, cam: Camera, light: Light, gbuf, drgb, dgbuf=None,
+                    dalpha=None, mlp_params=None, mlp_width: int = 64, precision: int = PREC_BF16,
+                    grads: Optional[dict] = None, dmlp: Optional[torch.Tensor] = None, accumulate: bool = False):
+    dev = params["means"].device
+    if grads is None:
+        grads = {k: torch.zeros_like(v) for k, v in params.items() if v is not None}
+    if mlp_params is not None and dmlp is None:
+        dmlp = torch.zeros_like(mlp_params)
+    g = gaussians_struct(params, view.feat_dim, sh_degree)
+    m = Mlp(view.feat_dim + 42, mlp_width, 3, 6, _ptr(mlp_params)) if mlp_params is not None else None
+    opt = Options(precision, int(accumulate))
+    gs = grads_struct(grads)
+    st = sssgs_render_backward(g, cam, light, m, opt, ct.c_void_p(view.workspace.data_ptr()), view.ws_bytes,
+                               view.capacity, _ptr(gbuf), _ptr(drgb.contiguous()),
+                               _ptr(dgbuf.contiguous()) if dgbuf is not None else None,
+                               _ptr(dalpha.contiguous()) if dalpha is not None else None, gs,
+                               _ptr(dmlp) if dmlp is not None else None, _stream())
+    _check(st)
+    del dev
+    return grads, dmlp
+
+
+class SSSGSRender(torch.autograd.Function):
+    """(rgb, gbuffer, alpha) = render(Gaussian parameters, network parameters).
+
+    Differentiable w.r.t. every Gaussian parameter tensor and the packed
+    network parameters.  ``ctx_args`` = (view, sh_degree, Camera, Light,
+    mlp_width, precision).
+    """
+
+    @staticmethod
+    def forward(ctx, ctx_args, mlp_params, *tensors):
+        view, sh_degree, cam, light, mlp_width, precision = ctx_args
+        params = {k: (t if t is not None and t.numel() else None) for k, t in zip(PARAM_NAMES, tensors)}
+        rgb, gbuf, alpha, _ = render_forward(view, params, sh_degree, cam, light, mlp_params, mlp_width, precision)
+        ctx.ctx_args = ctx_args
+        ctx.params = params
+        ctx.save_for_backward(gbuf, mlp_params if mlp_params is not None else torch.empty(0), *[
+            t if t is not None else torch.empty(0) for t in tensors])
+        ctx.has_mlp = mlp_params is not None
+        return rgb, gbuf, alpha
+
+    @staticmethod
+    def backward(ctx, drgb, dgbuf, dalpha):
+        view, sh_degree, cam, light, mlp_width, precision = ctx.ctx_args
+        saved = ctx.saved_tensors
+        gbuf = saved[0]
+        mlp_params = saved[1] if ctx.has_mlp else None
+        params = ctx.params
+        drgb = drgb if drgb is not None else torch.zeros((3, view.height, view.width), device=gbuf.device)
+        grads, dmlp = render_backward(view, params, sh_degree, cam, light, gbuf, drgb.contiguous(),
+                                      dgbuf.contiguous() if dgbuf is not None else None,
+                                      dalpha.contiguous() if dalpha is not None else None, mlp_params, mlp_width,
+                                      precision)
+        out = [grads.get(k) if params.get(k) is not None else None for k in PARAM_NAMES]
+        return (None, dmlp, *out)
+
+
+def render(view: View, params: dict, sh_degree: int, cam: Camera, light: Light, mlp_params=None,
+           mlp_width: int = 64, precision: int = PREC_BF16):
+    tensors: Sequence = [params.get(k) for k in PARAM_NAMES]
+    return SSSGSRender.apply((view, sh_degree, cam, light, mlp_width, precision), mlp_params, *tensors)

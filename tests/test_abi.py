@@ -1,0 +1,93 @@
+"""The C-ABI library loads and exports everything include/sssgs.h declares;
+host-side sizing and argument checks (no device work)."""
+import ctypes as ct
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "sssgs.h")
+
+
+def _declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(sssgs_[a-z0-9_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def B():
+    from paper_2408_12282_amd import sssgs
+    return sssgs
+
+
+def test_header_declares_the_entry_points():
+    names = _declared_functions()
+    for required in ("sssgs_render_forward", "sssgs_render_backward", "sssgs_workspace_bytes", "sssgs_l1_loss"):
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol(B):
+    L = B.lib()
+    for name in _declared_functions():
+        assert hasattr(L, name), f"{name} not exported"
+        assert name in B.EXPORTS, f"{name} has no Python binding"
+
+
+def test_param_count_matches_generator(B):
+    from paper_2408_12282_amd import scene
+    for F, W in [(16, 64), (32, 128), (0, 64), (8, 64)]:
+        m = scene.make_mlp(F, W, 3, 6, seed=0)
+        assert B.sssgs_mlp_param_count(m.in_dim, W, 3, 6) == m.params.size
+
+
+def test_workspace_sizing(B):
+    a = B.sssgs_workspace_bytes(1000, 128, 128, 0, 0, 10000)
+    b = B.sssgs_workspace_bytes(1000, 128, 128, 0, 0, 20000)
+    assert 0 < a < b
+    assert B.sssgs_workspace_bytes(300000, 800, 800, 16, 64, 6_000_000) > 0
+    assert B.sssgs_workspace_bytes(10, 0, 10, 0, 0, 10) == 0          # bad image
+    assert B.sssgs_workspace_bytes(10, 10, 10, 5, 0, 10) == 0         # unsupported F
+    assert B.sssgs_workspace_bytes(10, 10, 10, 0, 96, 10) == 0        # unsupported width
+    lay = B.sssgs_workspace_layout(1000, 128, 128, 16, 64, 10000)
+    assert lay.rec_stride == 32
+    offs = [lay.records, lay.depth_keys, lay.rects, lay.radii, lay.tile_ranges, lay.sorted_gauss, lay.t_final,
+            lay.n_contrib, lay.status]
+    assert all(o % 256 == 0 for o in offs)
+    assert len(set(offs)) == len(offs)
+    assert max(offs) < B.sssgs_workspace_bytes(1000, 128, 128, 16, 64, 10000)
+
+
+def test_invalid_arguments_are_rejected_before_any_launch(B):
+    L = B.lib()
+    cam = B.Camera((ct.c_float * 9)(1, 0, 0, 0, -1, 0, 0, 0, -1), (ct.c_float * 3)(0, 0, 3), 100.0, 100.0, 16.0,
+                   16.0, 32, 32)
+    light = B.Light((ct.c_float * 3)(1, 1, 1), (ct.c_float * 3)(9, 9, 9))
+    opt = B.Options(0, 0)
+    g = B.Gaussians(10, 0, -1, *([None] * 10))        # null planes
+    buf = ct.c_void_p(1)
+    st = L.sssgs_render_forward(ct.byref(g), ct.byref(cam), ct.byref(light), None, ct.byref(opt), buf, 1 << 30,
+                                100, buf, buf, buf, None, None)
+    assert st == B.ERR_INVALID_ARG
+    g2 = B.Gaussians(10, 5, -1, *([buf] * 10))         # unsupported feature width
+    st = L.sssgs_render_forward(ct.byref(g2), ct.byref(cam), ct.byref(light), None, ct.byref(opt), buf, 1 << 30,
+                                100, buf, buf, buf, None, None)
+    assert st == B.ERR_UNSUPPORTED
+    g3 = B.Gaussians(10, 0, -1, *([buf] * 10))
+    st = L.sssgs_render_forward(ct.byref(g3), ct.byref(cam), ct.byref(light), None, ct.byref(opt), buf, 16,
+                                100, buf, buf, buf, None, None)
+    assert st == B.ERR_INVALID_ARG                    # workspace too small
+    m = B.Mlp(43, 64, 3, 6, buf)                       # in_dim must be F + 42
+    st = L.sssgs_render_forward(ct.byref(g3), ct.byref(cam), ct.byref(light), ct.byref(m), ct.byref(opt), buf,
+                                1 << 30, 100, buf, buf, buf, None, None)
+    assert st == B.ERR_INVALID_ARG
+    m2 = B.Mlp(42, 128, 3, 6, buf)                     # FP32 network only at width 64
+    st = L.sssgs_render_forward(ct.byref(g3), ct.byref(cam), ct.byref(light), ct.byref(m2), ct.byref(opt), buf,
+                                1 << 30, 100, buf, buf, buf, None, None)
+    assert st == B.ERR_UNSUPPORTED
+    st = L.sssgs_render_backward(ct.byref(g3), ct.byref(cam), ct.byref(light), None, ct.byref(opt), buf, 1 << 30,
+                                 100, None, buf, None, None, None, None, None)
+    assert st == B.ERR_INVALID_ARG
+    assert B.lib().sssgs_status_string(B.ERR_CAPACITY).decode() == "instance capacity exceeded"
+    assert L.sssgs_l1_loss(None, None, -1, 1.0, None, None, None) == B.ERR_INVALID_ARG
