@@ -52,7 +52,10 @@ class OgMlp(ct.Structure):
 
 
 class OgOut(ct.Structure):
-    _fields_ = [("rgb", _dp), ("gbuf", _dp), ("alpha", _dp), ("n_contrib", _ip), ("pix_flag", _up),
+    _fields_ = [("rgb", _dp), ("gbuf", _dp), ("alpha", _dp), ("gbuf_abs", _dp), ("net_margin", _dp),
+                ("rgb_sens", _dp),
+                ("n_contrib", _ip),
+                ("pix_flag", _up),
                 ("mean2d", _dp), ("conic", _dp), ("depth", _dp), ("opacity", _dp), ("channels", _dp),
                 ("radius", _ip), ("rect", _ip), ("tiles_touched", _ip), ("g_flag", _up),
                 ("tile_ranges", _lp), ("tile_list", _ip), ("list_capacity", ct.c_int64),
@@ -142,6 +145,7 @@ def render(g, cam, light, mlp=None, bf16: bool = False, crop=None, drgb=None, dg
         mp = OgMlp(mlp.in_dim, mlp.in_pad, mlp.width, mlp.hidden, mlp.out_dim, int(bf16), _p(mlp_params))
     o = {
         "rgb": np.zeros((3, H, W)), "gbuf": np.zeros((C, H, W)), "alpha": np.zeros((H, W)),
+        "gbuf_abs": np.zeros((C, H, W)), "net_margin": np.zeros((H, W)), "rgb_sens": np.zeros((3, H, W)),
         "n_contrib": np.zeros((H, W), np.int32), "pix_flag": np.zeros((H, W), np.uint8),
         "mean2d": np.zeros((2, n)), "conic": np.zeros((3, n)), "depth": np.zeros(n), "opacity": np.zeros(n),
         "channels": np.zeros((C, n)),
@@ -157,7 +161,10 @@ def render(g, cam, light, mlp=None, bf16: bool = False, crop=None, drgb=None, dg
         # a first pass over rects gives M; render twice is wasteful, so size from the projection
         cap = int(_count_instances(g, cam, arr)) + 1
         tl = np.zeros(cap, np.int32)
-    out = OgOut(_p(o["rgb"]), _p(o["gbuf"]), _p(o["alpha"]), _p(o["n_contrib"], _ip), _p(o["pix_flag"], _up),
+    out = OgOut(_p(o["rgb"]), _p(o["gbuf"]), _p(o["alpha"]), _p(o["gbuf_abs"]), _p(o["net_margin"]),
+                _p(o["rgb_sens"]),
+                _p(o["n_contrib"], _ip),
+                _p(o["pix_flag"], _up),
                 _p(o["mean2d"]), _p(o["conic"]), _p(o["depth"]), _p(o["opacity"]), _p(o["channels"]),
                 _p(o["radius"], _ip), _p(o["rect"], _ip), _p(o["tiles_touched"], _ip), _p(o["g_flag"], _up),
                 _p(o["tile_ranges"], _lp), _p(tl, _ip), cap, _p(num, _lp), _p(sig, _u64p))

@@ -78,6 +78,10 @@ typedef struct {
 typedef struct {
   /* images */
   double *rgb, *gbuf, *alpha;
+  double *gbuf_abs; /* diagnostic: sum of T alpha |value| per channel (scale of rounding errors) */
+  double *net_margin; /* diagnostic: smallest |pre-activation| of any ReLU of the network at the pixel */
+  double *rgb_sens;   /* diagnostic [3][H][W]: sum_k |d rgb_c / d G_k| (|G_k| + sum|terms_k|) + |d rgb_c / d T| T,
+                         the first-order change of rgb under unit relative perturbations of the G-buffer */
   int32_t *n_contrib;
   uint8_t *pix_flag;
   /* per Gaussian */
@@ -398,6 +402,7 @@ typedef struct {
   double act[8][MAXW];       /* layer inputs as used (after bf16 rounding in emulation) */
   double pre[8][MAXW];       /* pre-activations */
   double out[8];
+  double margin;             /* smallest |argument| of any ReLU */
   double Lsss[3];
   double L[3];
   int background;
@@ -505,6 +510,7 @@ static void shade_pixel(const og_cam *cam, const og_light *light, const og_mlp *
   for (int k = 0; k < 3; k++) S->in[p++] = S->wi[k];
   for (; p < mlp->in_pad; p++) S->in[p] = 0;
   for (int k = 0; k < mlp->in_pad; k++) S->act[0][k] = rb(mlp, S->in[k]);
+  S->margin = INFINITY;
   for (int l = 0; l <= mlp->hidden; l++) {
     int rows = 0, cols = 0;
     const double *bias = NULL;
@@ -516,6 +522,7 @@ static void shade_pixel(const og_cam *cam, const og_light *light, const og_mlp *
       S->pre[l][o] = acc;
       if (l < mlp->hidden) S->act[l + 1][o] = rb(mlp, acc > 0 ? acc : 0);
       else S->out[o] = acc;
+      if ((l < mlp->hidden || o < 3) && fabs(acc) < S->margin) S->margin = fabs(acc);
     }
   }
   for (int c = 0; c < 3; c++) {
@@ -837,6 +844,7 @@ int og_render(const og_gauss *g, const og_cam *cam, const og_light *light, const
     uint64_t sig = mix64(0x1234, (uint64_t)t);
     for (int64_t e = 0; e < len; e++) sig = mix64(sig, (uint64_t)L[e].i);
     double *Gp = (double *)malloc(sizeof(double) * MAXC);
+    double *Ga = (double *)malloc(sizeof(double) * MAXC);
     shade_t *S = (shade_t *)malloc(sizeof(shade_t));
     for (int py = ty * TILE; py < (ty + 1) * TILE && py < H; py++)
       for (int px = tx * TILE; px < (tx + 1) * TILE && px < W; px++) {
@@ -845,7 +853,7 @@ int og_render(const og_gauss *g, const og_cam *cam, const og_light *light, const
         double uc = px + 0.5, vc = py + 0.5;
         /* Eq. 3: front-to-back compositing */
         double Tr = 1.0;
-        for (int k = 0; k < C; k++) Gp[k] = 0;
+        for (int k = 0; k < C; k++) { Gp[k] = 0; Ga[k] = 0; }
         int32_t last = 0;
         uint8_t flag = 0;
         for (int64_t e = 0; e < len; e++) {
@@ -862,17 +870,32 @@ int og_render(const og_gauss *g, const og_cam *cam, const og_light *light, const
           double tn = Tr * (1.0 - al);
           if (fabs(tn - 1e-4) < 1e-5 * 1e-4) flag |= 2;
           if (tn < 1e-4) { sig = mix64(sig, (uint64_t)(e * 4 + 2)); break; }
-          for (int k = 0; k < C; k++) Gp[k] += Tr * al * q->ch[k];
+          for (int k = 0; k < C; k++) {
+            Gp[k] += Tr * al * q->ch[k];
+            Ga[k] += Tr * al * fabs(q->ch[k]);
+          }
           Tr = tn;
           last = (int32_t)(e + 1);
           sig = mix64(sig, (uint64_t)(e * 4 + 3));
         }
         if (fabs((1.0 - Tr) - 1e-6) < 1e-5 * 1e-6) flag |= 16;
         if (out->gbuf) for (int k = 0; k < C; k++) out->gbuf[(size_t)k * H * W + pix] = Gp[k];
+        if (out->gbuf_abs) for (int k = 0; k < C; k++) out->gbuf_abs[(size_t)k * H * W + pix] = Ga[k];
         if (out->alpha) out->alpha[pix] = 1.0 - Tr;
         if (out->n_contrib) out->n_contrib[pix] = last;
         if (out->pix_flag) out->pix_flag[pix] = flag;
         shade_pixel(cam, light, mlp, C, F, Gp, Tr, uc, vc, S);
+        if (out->net_margin) out->net_margin[pix] = (mlp && !S->background) ? S->margin : INFINITY;
+        if (out->rgb_sens) {
+          for (int c = 0; c < 3; c++) {
+            double e[3] = {0, 0, 0}, dGs[MAXC];
+            e[c] = 1.0;
+            double dTs = shade_pixel_bwd(cam, light, mlp, C, F, S, e, dGs, NULL);
+            double sacc = fabs(dTs) * Tr;
+            for (int k = 0; k < C; k++) sacc += fabs(dGs[k]) * (fabs(Gp[k]) + Ga[k]);
+            out->rgb_sens[(size_t)c * H * W + pix] = sacc;
+          }
+        }
         if (out->rgb) for (int c = 0; c < 3; c++) out->rgb[(size_t)c * H * W + pix] = S->a * S->L[c] * !S->background;
         if (!up) continue;
         /* ---- backward ---- */
@@ -917,6 +940,7 @@ int og_render(const og_gauss *g, const og_cam *cam, const og_light *light, const
       }
     sigs[t] = sig;
     free(Gp);
+    free(Ga);
     free(S);
   }
   if (out->signature) {

@@ -87,7 +87,7 @@ int in_pad_of(int in_dim) { return (in_dim + 31) / 32 * 32; }
 struct Layout {
   size_t records, depth_keys, vals_a, keys_b, vals_b, keys_a, rects, radii, tt, offsets, partials, hist;
   size_t ik_a, iv_a, ik_b, iv_b, ranges, t_final, n_contrib, status, m_total;
-  size_t gacc, dG, dT, wops, tops, mlp_part;
+  size_t gacc, dG, dT, wops, tops, mlp_part, mlp_mid;
   size_t total;
   int C, RS, GS, TX, TY, T;
   uint32_t nb_g, nb_i;
@@ -151,6 +151,7 @@ bool make_layout(int32_t n, int32_t W, int32_t H, int32_t F, int32_t mlp_width, 
   L.wops = take(mlp_width ? prep_weight_bytes(mlp_width, in_pad) : 0);
   L.tops = take(mlp_width ? prep_weight_bytes(mlp_width, in_pad) : 0);
   L.mlp_part = take(mlp_width ? (size_t)L.shade_parts * L.nparams * 4 : 0);
+  L.mlp_mid = take(mlp_width ? (size_t)reduce_scratch_floats(L.nparams) * 4 : 0);
   L.total = p;
   return true;
 }
@@ -496,7 +497,8 @@ sssgs_status sssgs_render_backward(const sssgs_gaussians *g, const sssgs_camera 
     Scope sc(kStMlpReduce, st);
     const int ip = in_pad_of(mlp->in_dim);
     const int parts = shade_bwd_grid(net, width, ip, L.T, nblk) * shade_bwd_waves(net, width, ip);
-    launch_reduce_partials(sa.mlp_partials, parts, L.nparams, dL_dmlp, opt->accumulate_grads, st);
+    launch_reduce_partials(sa.mlp_partials, parts, L.nparams, at<float>(ws, L.mlp_mid), dL_dmlp,
+                           opt->accumulate_grads, st);
   }
   // 2. compositing backward into the per-Gaussian accumulators
   launch_zero_f32(at<float>(ws, L.gacc), (size_t)(g->n) * L.GS, st);

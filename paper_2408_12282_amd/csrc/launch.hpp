@@ -52,8 +52,9 @@ int shade_bwd_grid(int net, int width, int in_pad, int tiles, int max_blocks);
 void launch_prep_weights(int net, int width, int in_pad, const float *params, void *wops, void *tops,
                          hipStream_t st);
 size_t prep_weight_bytes(int width, int in_pad);
-void launch_reduce_partials(const float *partials, int nblocks, int nparams, float *out, int accumulate,
-                            hipStream_t st);
+void launch_reduce_partials(const float *partials, int nparts, int nparams, float *scratch, float *out,
+                            int accumulate, hipStream_t st);
+int reduce_scratch_floats(int nparams);
 void launch_l1_loss(const float *pred, const float *target, int64_t count, float scale, float *loss_out,
                     float *grad, hipStream_t st);
 void launch_zero_f32(float *p, size_t n, hipStream_t st);

@@ -104,20 +104,39 @@ size_t prep_weight_bytes(int width, int in_pad) {
   return 4 * (elems_fwd > elems_bwd ? elems_fwd : elems_bwd);
 }
 
-// out[p] (+)= sum_b partials[b][p], in block order (deterministic).
-__global__ __launch_bounds__(256) void reduce_partials_kernel(const float *__restrict__ partials, int nblocks,
-                                                              int nparams, float *__restrict__ out, int accumulate) {
+// Two-level deterministic sum of per-wave partials: level 1 sums kSplit
+// contiguous groups of partials (grid y = group), level 2 sums the groups in order.
+constexpr int kSplit = 64;
+
+__global__ __launch_bounds__(256) void reduce_partials_l1_kernel(const float *__restrict__ partials, int nparts,
+                                                                 int nparams, float *__restrict__ mid) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= nparams) return;
+  const int per = (nparts + kSplit - 1) / kSplit;
+  const int b0 = blockIdx.y * per, b1 = min(nparts, b0 + per);
+  float s = 0.f;
+  for (int b = b0; b < b1; b++) s += partials[(size_t)b * nparams + p];
+  mid[(size_t)blockIdx.y * nparams + p] = s;
+}
+
+__global__ __launch_bounds__(256) void reduce_partials_l2_kernel(const float *__restrict__ mid, int nparams,
+                                                                 float *__restrict__ out, int accumulate) {
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= nparams) return;
   float s = 0.f;
-  for (int b = 0; b < nblocks; b++) s += partials[(size_t)b * nparams + p];
+  for (int k = 0; k < kSplit; k++) s += mid[(size_t)k * nparams + p];
   out[p] = accumulate ? out[p] + s : s;
 }
 
-void launch_reduce_partials(const float *partials, int nblocks, int nparams, float *out, int accumulate,
-                            hipStream_t st) {
-  reduce_partials_kernel<<<(nparams + 255) / 256, 256, 0, st>>>(partials, nblocks, nparams, out, accumulate);
+// `scratch` holds kSplit * nparams floats.
+void launch_reduce_partials(const float *partials, int nparts, int nparams, float *scratch, float *out,
+                            int accumulate, hipStream_t st) {
+  const dim3 g1((nparams + 255) / 256, kSplit);
+  reduce_partials_l1_kernel<<<g1, 256, 0, st>>>(partials, nparts, nparams, scratch);
+  reduce_partials_l2_kernel<<<(nparams + 255) / 256, 256, 0, st>>>(scratch, nparams, out, accumulate);
 }
+
+int reduce_scratch_floats(int nparams) { return kSplit * nparams; }
 
 __global__ __launch_bounds__(256) void l1_kernel(const float *__restrict__ pred, const float *__restrict__ target,
                                                  int64_t count, float scale, float *__restrict__ loss_out,

@@ -104,7 +104,7 @@ __device__ __forceinline__ void dw_accumulate(const typename M::Elem *dy, int dy
   using ST = Stage<M>;
   constexpr int MBO = ROWS16 / 16, NBK = KCOLS / 16, KSP = 64 / M::KS;
   const int g = lane >> 4, col = lane & 15;
-#pragma unroll
+#pragma unroll 1
   for (int mbo = 0; mbo < MBO; mbo++) {
     f32x4 acc[NBK];
 #pragma unroll
@@ -328,6 +328,74 @@ int shade_bwd_waves(int net, int width, int in_pad) {
   return net == 0 ? 4 : ((net == 2 && width == 64 && in_pad == 64) ? 4 : 2);
 }
 
+// ReLU masks of one layer's outputs in D layout, one bit per (mb, nb, j).
+template <int MB>
+struct Mask {
+  uint32_t w[(MB * 16 + 31) / 32];
+  __device__ __forceinline__ void set_from(const f32x4 (&acc)[MB][4], const float *bias, int g) {
+#pragma unroll
+    for (int k = 0; k < (MB * 16 + 31) / 32; k++) w[k] = 0u;
+#pragma unroll
+    for (int mb = 0; mb < MB; mb++)
+#pragma unroll
+      for (int nb = 0; nb < 4; nb++)
+#pragma unroll
+        for (int j = 0; j < 4; j++) {
+          const int b = mb * 16 + nb * 4 + j;
+          if (acc[mb][nb][j] + bias[16 * mb + 4 * g + j] > 0.f) w[b >> 5] |= 1u << (b & 31);
+        }
+  }
+  __device__ __forceinline__ void apply(f32x4 (&d)[MB][4]) const {
+#pragma unroll
+    for (int mb = 0; mb < MB; mb++)
+#pragma unroll
+      for (int nb = 0; nb < 4; nb++)
+#pragma unroll
+        for (int j = 0; j < 4; j++) {
+          const int b = mb * 16 + nb * 4 + j;
+          if (!((w[b >> 5] >> (b & 31)) & 1u)) d[mb][nb][j] = 0.f;
+        }
+  }
+};
+
+// Per-pixel inputs of the shading backward (reloaded in each per-pixel phase
+// instead of being kept live across the network phases).
+template <int C>
+__device__ __forceinline__ void load_pixel(const ShadeArgs &A, bool inside, size_t pix, size_t HW, float *gb,
+                                           float &T, float *gL) {
+  T = 1.f;
+  for (int c = 0; c < 3; c++) gL[c] = 0.f;
+  if (inside) {
+#pragma unroll
+    for (int c = 0; c < C; c++) gb[c] = A.gbuf[c * HW + pix];
+    T = A.t_final[pix];
+    for (int c = 0; c < 3; c++) gL[c] = A.drgb[c * HW + pix];
+  } else {
+#pragma unroll
+    for (int c = 0; c < C; c++) gb[c] = 0.f;
+  }
+}
+
+template <int C, int F>
+__device__ __forceinline__ void write_pixel_grads(const ShadeArgs &A, bool inside, size_t pix, size_t HW,
+                                                  const PixShade &S, const float *gb, float *dgbar, float dA) {
+  if (!inside) return;
+  float dT = 0.f;
+  if (!S.bg) {
+#pragma unroll
+    for (int k = 0; k < C; k++) dA -= dgbar[k] * gb[k] * S.ia * S.ia;
+    dT = -dA;
+  }
+  if (A.dalpha_ext) dT -= A.dalpha_ext[pix];
+  A.dT[pix] = dT;
+#pragma unroll
+  for (int k = 0; k < C; k++) {
+    float v = S.bg ? 0.f : dgbar[k] * S.ia;
+    if (A.dgbuf_ext) v += A.dgbuf_ext[k * HW + pix];
+    A.dG[k * HW + pix] = v;
+  }
+}
+
 template <int F, int NET, int WIDTH, int IN_PAD>
 __global__ __launch_bounds__((BwdWaves<NET, WIDTH, IN_PAD>::value * 64)) void shade_bwd_kernel(ShadeArgs A, int nstrips) {
   using M = typename NetTraits<NET>::M;
@@ -342,18 +410,18 @@ __global__ __launch_bounds__((BwdWaves<NET, WIDTH, IN_PAD>::value * 64)) void sh
   constexpr int XS = IN_PAD + XPad<M>::value;
   constexpr int FMAX = WIDTH > IN_PAD ? WIDTH : IN_PAD;
   constexpr int FST = FMAX + 4;  // pixel-major stage stride (FP32)
-  // per wave: input rows, two stages, network outputs / upstream, input gradient
   constexpr int STAGE_ELEMS = ST::FM ? FMAX * ST::PXS : 64 * FST;
   constexpr int XS_ELEMS = 64 * XS;
+  // per wave: network input rows, two weight-gradient stages, outputs + their gradients
   __shared__ E xs_all[NET ? NW * XS_ELEMS : 1];
   __shared__ E st_all[NET ? NW * 2 * STAGE_ELEMS : 1];
-  __shared__ float io_all[NET ? NW * 64 * 8 : 1];
+  __shared__ float io_all[NET ? NW * 64 * 16 : 1];
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int g = lane >> 4, col = lane & 15;
   E *xs = xs_all + (NET ? w * XS_ELEMS : 0);
   E *sdy = st_all + (NET ? w * 2 * STAGE_ELEMS : 0);
   E *sxk = sdy + (NET ? STAGE_ELEMS : 0);
-  float *io = io_all + (NET ? w * 64 * 8 : 0);
+  float *io = io_all + (NET ? w * 64 * 16 : 0);  // [px][0..7] outputs, [px][8..15] output gradients
   float *dxin = reinterpret_cast<float *>(sdy);  // [64][IN_PAD + 1] after the last weight gradient
   float *part = A.mlp_partials ? A.mlp_partials + (size_t)(blockIdx.x * NW + w) * A.nparams : nullptr;
   const size_t HW = (size_t)A.cam.W * A.cam.H;
@@ -365,82 +433,98 @@ __global__ __launch_bounds__((BwdWaves<NET, WIDTH, IN_PAD>::value * 64)) void sh
     const int px = tx * kTile + (lane & 15), py = ty * kTile + 4 * sub + (lane >> 4);
     const bool inside = strip < nstrips && px < A.cam.W && py < A.cam.H;
     const size_t pix = inside ? (size_t)py * A.cam.W + px : 0;
-    float gb[C];
-    float T = 1.f, gL[3] = {0.f, 0.f, 0.f};
-    if (inside) {
-#pragma unroll
-      for (int c = 0; c < C; c++) gb[c] = A.gbuf[c * HW + pix];
-      T = A.t_final[pix];
-      for (int c = 0; c < 3; c++) gL[c] = A.drgb[c * HW + pix];
+    const float uc = (float)px + 0.5f, vc = (float)py + 0.5f;
+    if constexpr (NET == 0) {
+      float gb[C], T, gL[3], dgbar[C];
+      load_pixel<C>(A, inside, pix, HW, gb, T, gL);
+      PixShade S;
+      shade_geometry<C>(gb, T, uc, vc, A.cam, A.light, false, S);
+      if (S.bg) gL[0] = gL[1] = gL[2] = 0.f;
+      const float dA = shade_pixel_bwd<C, F, false>(S, gb, gL, A.light, nullptr, dgbar);
+      write_pixel_grads<C, F>(A, inside, pix, HW, S, gb, dgbar, dA);
     } else {
-#pragma unroll
-      for (int c = 0; c < C; c++) gb[c] = 0.f;
-    }
-    PixShade S;
-    shade_geometry<C>(gb, T, (float)px + 0.5f, (float)py + 0.5f, A.cam, A.light, NET != 0, S);
-    if (S.bg || !inside)
-      for (int c = 0; c < 3; c++) gL[c] = 0.f;
-    float dgbar[C];
-    float dA;
-    if constexpr (NET != 0) {
       const Op *__restrict__ wops = reinterpret_cast<const Op *>(A.wops);
       const Op *__restrict__ tops = reinterpret_cast<const Op *>(A.tops);
-      // ---- network forward (inputs in LDS, layer-3 input kept)
-      build_net_input<F, IN_PAD, M>(gb, S, xs + lane * XS);
+      // ---- A: network input rows
+      {
+        float gb[C], T, gL[3];
+        load_pixel<C>(A, inside, pix, HW, gb, T, gL);
+        PixShade S;
+        shade_geometry<C>(gb, T, uc, vc, A.cam, A.light, true, S);
+        build_net_input<F, IN_PAD, M>(gb, S, xs + lane * XS);
+      }
       __syncthreads();
-      f32x4 acc[MB][4];
+      // ---- B: network forward; keep the layer-3 input and the ReLU masks
+      Mask<MB> m1, m2, m3;
       Op H3[NS::KSH][4];
       {
-        Op Ht[NS::KSH][4];
-        layer0_mma<M, MB, NS::KS0>(wops, xs, XS, acc, lane);
-        acc_to_ops<M, MB>(acc, A.params + PO::b(0), g, Ht);
-        layer_mma<M, MB, NS::KSH>(wops + NS::L0, Ht, acc, lane);
-        acc_to_ops<M, MB>(acc, A.params + PO::b(1), g, Ht);
-        layer_mma<M, MB, NS::KSH>(wops + NS::L0 + NS::LH, Ht, acc, lane);
+        f32x4 acc[MB][4];
+        Op H[NS::KSH][4];
+        __builtin_amdgcn_sched_barrier(0);
+        __builtin_amdgcn_sched_barrier(0);
+      layer0_mma<M, MB, NS::KS0>(wops, xs, XS, acc, lane);
+        m1.set_from(acc, A.params + PO::b(0), g);
+        acc_to_ops<M, MB>(acc, A.params + PO::b(0), g, H);
+        __builtin_amdgcn_sched_barrier(0);
+        __builtin_amdgcn_sched_barrier(0);
+      layer_mma<M, MB, NS::KSH>(wops + NS::L0, H, acc, lane);
+        m2.set_from(acc, A.params + PO::b(1), g);
+        acc_to_ops<M, MB>(acc, A.params + PO::b(1), g, H);
+        __builtin_amdgcn_sched_barrier(0);
+        __builtin_amdgcn_sched_barrier(0);
+      layer_mma<M, MB, NS::KSH>(wops + NS::L0 + NS::LH, H, acc, lane);
+        m3.set_from(acc, A.params + PO::b(2), g);
         acc_to_ops<M, MB>(acc, A.params + PO::b(2), g, H3);
       }
-      f32x4 oacc[1][4];
-      layer_mma<M, 1, NS::KSH>(wops + NS::L0 + 2 * NS::LH, H3, oacc, lane);
-      if (g < 2)
-#pragma unroll
-        for (int nb = 0; nb < 4; nb++)
-#pragma unroll
-          for (int j = 0; j < 4; j++) {
-            const int o = 4 * g + j;
-            io[(16 * nb + col) * 8 + o] = oacc[0][nb][j] + (o < 6 ? A.params[PO::b(3) + o] : 0.f);
-          }
-      __syncthreads();
-      // ---- per pixel: outputs, Eq. 7, upstream gradient of the outputs
-      float o[6];
-      for (int k = 0; k < 6; k++) o[k] = io[lane * 8 + k];
-      combine_net(S, gb[kChSss], o);
       {
+        f32x4 oacc[1][4];
+        layer_mma<M, 1, NS::KSH>(wops + NS::L0 + 2 * NS::LH, H3, oacc, lane);
+        if (g < 2)
+#pragma unroll
+          for (int nb = 0; nb < 4; nb++)
+#pragma unroll
+            for (int j = 0; j < 4; j++) {
+              const int o = 4 * g + j;
+              io[(16 * nb + col) * 16 + o] = oacc[0][nb][j] + (o < 6 ? A.params[PO::b(3) + o] : 0.f);
+            }
+      }
+      __syncthreads();
+      // ---- C: per pixel, Eq. 7 and the gradient of the network outputs
+      {
+        float gb[C], T, gL[3];
+        load_pixel<C>(A, inside, pix, HW, gb, T, gL);
+        PixShade S;
+        shade_geometry<C>(gb, T, uc, vc, A.cam, A.light, true, S);
+        if (S.bg) gL[0] = gL[1] = gL[2] = 0.f;
+        float o[6];
+        for (int k = 0; k < 6; k++) o[k] = io[lane * 16 + k];
+        combine_net(S, gb[kChSss], o);
         const float sss = gb[kChSss] * S.ia;
-        float dout[8];
         for (int c = 0; c < 3; c++) {
           const float gLo = S.a * gL[c];
           const float dLin = gLo * (1.f - sss) * (S.fs[c] + S.fd[c]) * S.cosI;
-          dout[c] = o[c] > 0.f ? dLin : 0.f;
-          dout[3 + c] = gLo * sss * S.Lsss[c] * (1.f - S.Lsss[c]);
+          io[lane * 16 + 8 + c] = o[c] > 0.f ? dLin : 0.f;
+          io[lane * 16 + 11 + c] = gLo * sss * S.Lsss[c] * (1.f - S.Lsss[c]);
         }
-        dout[6] = dout[7] = 0.f;
-        __syncthreads();
-        for (int k = 0; k < 8; k++) io[lane * 8 + k] = dout[k];
+        io[lane * 16 + 14] = 0.f;
+        io[lane * 16 + 15] = 0.f;
       }
       __syncthreads();
-      // ---- output layer: dW3, db3, dH3 = W3^T dout
-      f32x4 dO[1][4];
-#pragma unroll
-      for (int nb = 0; nb < 4; nb++)
-#pragma unroll
-        for (int j = 0; j < 4; j++) dO[0][nb][j] = (g < 2) ? io[(16 * nb + col) * 8 + 4 * g + j] : 0.f;
-      stage_d<M, 1>(dO, sdy, FST, lane);
-      stage_ops<M, NS::KSH>(H3, sxk, FST, lane);
-      __syncthreads();
-      dw_accumulate<M, 16, WIDTH>(sdy, FST, sxk, FST, part, PO::w(3), 6, WIDTH, first, lane);
-      db_accumulate<1>(dO, part, PO::b(3), 6, first, lane);
-      f32x4 dH[MB][4];
+      // ---- D: network backward
+      Op Bd[NS::KSH][4];
       {
+        f32x4 dO[1][4];
+#pragma unroll
+        for (int nb = 0; nb < 4; nb++)
+#pragma unroll
+          for (int j = 0; j < 4; j++) dO[0][nb][j] = (g < 2) ? io[(16 * nb + col) * 16 + 8 + 4 * g + j] : 0.f;
+        stage_d<M, 1>(dO, sdy, FST, lane);
+        stage_ops<M, NS::KSH>(H3, sxk, FST, lane);
+        __syncthreads();
+        __builtin_amdgcn_sched_barrier(0);
+        __builtin_amdgcn_sched_barrier(0);
+      dw_accumulate<M, 16, WIDTH>(sdy, FST, sxk, FST, part, PO::w(3), 6, WIDTH, first, lane);
+        db_accumulate<1>(dO, part, PO::b(3), 6, first, lane);
         Op Bo[NS::KT_O][4];
 #pragma unroll
         for (int ks = 0; ks < NS::KT_O; ks++)
@@ -455,94 +539,84 @@ __global__ __launch_bounds__((BwdWaves<NET, WIDTH, IN_PAD>::value * 64)) void sh
               Bo[ks][nb] = dO[0][nb][ks];
             }
           }
-        layer_mma<M, MB, NS::KT_O>(tops + NS::T0 + 2 * NS::TH, Bo, dH, lane);
+        f32x4 dH[MB][4];
+        __builtin_amdgcn_sched_barrier(0);
+        __builtin_amdgcn_sched_barrier(0);
+      layer_mma<M, MB, NS::KT_O>(tops + NS::T0 + 2 * NS::TH, Bo, dH, lane);
+        m3.apply(dH);                       // upstream of layer 2's pre-activation
+        __syncthreads();
+        stage_d<M, MB>(dH, sdy, FST, lane);
+        db_accumulate<MB>(dH, part, PO::b(2), WIDTH, first, lane);
+        grad_to_ops<M, MB>(dH, Bd);
       }
-      // ---- hidden layers 2 and 1 (inputs recomputed), then layer 0
-      Op H1[NS::KSH][4], H2[NS::KSH][4];
-      layer0_mma<M, MB, NS::KS0>(wops, xs, XS, acc, lane);
-      acc_to_ops<M, MB>(acc, A.params + PO::b(0), g, H1);
-      layer_mma<M, MB, NS::KSH>(wops + NS::L0, H1, acc, lane);
-      acc_to_ops<M, MB>(acc, A.params + PO::b(1), g, H2);
-#pragma unroll
+#pragma unroll 1
       for (int l = 2; l >= 1; l--) {
-        // mask by the ReLU of this layer's output (held in H_{l+1})
+        // recompute this layer's input h_l from the input rows
+        {
+          f32x4 acc[MB][4];
+          Op H[NS::KSH][4];
+          __builtin_amdgcn_sched_barrier(0);
+        __builtin_amdgcn_sched_barrier(0);
+      layer0_mma<M, MB, NS::KS0>(wops, xs, XS, acc, lane);
+          acc_to_ops<M, MB>(acc, A.params + PO::b(0), g, H);
+          if (l == 2) {
+            __builtin_amdgcn_sched_barrier(0);
+        __builtin_amdgcn_sched_barrier(0);
+      layer_mma<M, MB, NS::KSH>(wops + NS::L0, H, acc, lane);
+            acc_to_ops<M, MB>(acc, A.params + PO::b(1), g, H);
+          }
+          stage_ops<M, NS::KSH>(H, sxk, FST, lane);
+        }
+        __syncthreads();
+        __builtin_amdgcn_sched_barrier(0);
+        __builtin_amdgcn_sched_barrier(0);
+      dw_accumulate<M, WIDTH, WIDTH>(sdy, FST, sxk, FST, part, PO::w(l), WIDTH, WIDTH, first, lane);
+        f32x4 dH[MB][4];
+        __builtin_amdgcn_sched_barrier(0);
+        __builtin_amdgcn_sched_barrier(0);
+      layer_mma<M, MB, NS::KT_H>(tops + NS::T0 + (l - 1) * NS::TH, Bd, dH, lane);
+        if (l == 2) m2.apply(dH);
+        else m1.apply(dH);
+        __syncthreads();
+        stage_d<M, MB>(dH, sdy, FST, lane);
+        db_accumulate<MB>(dH, part, PO::b(l - 1), WIDTH, first, lane);
+        grad_to_ops<M, MB>(dH, Bd);
+      }
+      // layer 0: weight gradient with the input rows, input gradient W0^T dpre0
+      for (int k = 0; k < IN_PAD; k++) sxk[ST::idx(k, lane, FST)] = xs[lane * XS + k];
+      __syncthreads();
+      __builtin_amdgcn_sched_barrier(0);
+      dw_accumulate<M, WIDTH, IN_PAD>(sdy, FST, sxk, FST, part, PO::w(0), WIDTH, IN_PAD, first, lane);
+      {
+        f32x4 dX[NS::MB0][4];
+        __builtin_amdgcn_sched_barrier(0);
+        __builtin_amdgcn_sched_barrier(0);
+      layer_mma<M, NS::MB0, NS::KT_H>(tops, Bd, dX, lane);
+        __syncthreads();
 #pragma unroll
-        for (int mb = 0; mb < MB; mb++)
+        for (int mb = 0; mb < NS::MB0; mb++)
 #pragma unroll
           for (int nb = 0; nb < 4; nb++)
 #pragma unroll
-            for (int j = 0; j < 4; j++) {
-              const float hv = (l == 2) ? act_at<M, NS::KSH>(H3, mb, nb, j) : act_at<M, NS::KSH>(H2, mb, nb, j);
-              if (!(hv > 0.f)) dH[mb][nb][j] = 0.f;
-            }
-        __syncthreads();
-        stage_d<M, MB>(dH, sdy, FST, lane);
-        if (l == 2) stage_ops<M, NS::KSH>(H2, sxk, FST, lane);
-        else stage_ops<M, NS::KSH>(H1, sxk, FST, lane);
-        __syncthreads();
-        dw_accumulate<M, WIDTH, WIDTH>(sdy, FST, sxk, FST, part, PO::w(l), WIDTH, WIDTH, first, lane);
-        db_accumulate<MB>(dH, part, PO::b(l), WIDTH, first, lane);
-        Op Bd[NS::KSH][4];
-        grad_to_ops<M, MB>(dH, Bd);
-        layer_mma<M, MB, NS::KT_H>(tops + NS::T0 + (l - 1) * NS::TH, Bd, dH, lane);
-      }
-      // layer 0: mask by ReLU of h1, dW0 with the input rows, dX = W0^T dpre0
-#pragma unroll
-      for (int mb = 0; mb < MB; mb++)
-#pragma unroll
-        for (int nb = 0; nb < 4; nb++)
-#pragma unroll
-          for (int j = 0; j < 4; j++)
-            if (!(act_at<M, NS::KSH>(H1, mb, nb, j) > 0.f)) dH[mb][nb][j] = 0.f;
-      __syncthreads();
-      stage_d<M, MB>(dH, sdy, FST, lane);
-      if constexpr (ST::FM) {
-        // input rows [px][k] -> feature-major stage
-        for (int k = 0; k < IN_PAD; k++) sxk[ST::idx(k, lane, FST)] = xs[lane * XS + k];
-      } else {
-        for (int k = 0; k < IN_PAD; k++) sxk[ST::idx(k, lane, FST)] = xs[lane * XS + k];
+            for (int j = 0; j < 4; j++) dxin[(16 * nb + col) * (IN_PAD + 1) + 16 * mb + 4 * g + j] = dX[mb][nb][j];
       }
       __syncthreads();
-      dw_accumulate<M, WIDTH, IN_PAD>(sdy, FST, sxk, FST, part, PO::w(0), WIDTH, IN_PAD, first, lane);
-      db_accumulate<MB>(dH, part, PO::b(0), WIDTH, first, lane);
-      f32x4 dX[NS::MB0][4];
+      // ---- E: per pixel backward of geometry, BRDF and Eq. 7
       {
-        Op Bd[NS::KSH][4];
-        grad_to_ops<M, MB>(dH, Bd);
-        layer_mma<M, NS::MB0, NS::KT_H>(tops, Bd, dX, lane);
+        float gb[C], T, gL[3], dgbar[C];
+        load_pixel<C>(A, inside, pix, HW, gb, T, gL);
+        PixShade S;
+        shade_geometry<C>(gb, T, uc, vc, A.cam, A.light, true, S);
+        if (S.bg) gL[0] = gL[1] = gL[2] = 0.f;
+        float o[6];
+        for (int k = 0; k < 6; k++) o[k] = io[lane * 16 + k];
+        combine_net(S, gb[kChSss], o);
+        const float *din = dxin + lane * (IN_PAD + 1);
+        const float dA = shade_pixel_bwd<C, F, true>(S, gb, gL, A.light, din, dgbar);
+        write_pixel_grads<C, F>(A, inside, pix, HW, S, gb, dgbar, dA);
       }
-      __syncthreads();
-      // dX (D layout over input features) -> per-pixel rows
-#pragma unroll
-      for (int mb = 0; mb < NS::MB0; mb++)
-#pragma unroll
-        for (int nb = 0; nb < 4; nb++)
-#pragma unroll
-          for (int j = 0; j < 4; j++) dxin[(16 * nb + col) * (IN_PAD + 1) + 16 * mb + 4 * g + j] = dX[mb][nb][j];
-      __syncthreads();
-      float din[F + kNumPE + 6];
-#pragma unroll
-      for (int k = 0; k < F + kNumPE + 6; k++) din[k] = dxin[lane * (IN_PAD + 1) + k];
-      dA = shade_pixel_bwd<C, F, true>(S, gb, gL, A.light, din, dgbar);
       first = false;
-    } else {
-      dA = shade_pixel_bwd<C, F, false>(S, gb, gL, A.light, nullptr, dgbar);
-    }
-    if (inside) {
-      float dT = 0.f;
-      if (!S.bg) {
-#pragma unroll
-        for (int k = 0; k < C; k++) dA -= dgbar[k] * gb[k] * S.ia * S.ia;
-        dT = -dA;
-      }
-      if (A.dalpha_ext) dT -= A.dalpha_ext[pix];
-      A.dT[pix] = dT;
-#pragma unroll
-      for (int k = 0; k < C; k++) {
-        float v = S.bg ? 0.f : dgbar[k] * S.ia;
-        if (A.dgbuf_ext) v += A.dgbuf_ext[k * HW + pix];
-        A.dG[k * HW + pix] = v;
-      }
+      __syncthreads();
     }
   }
 }

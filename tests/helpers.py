@@ -70,12 +70,18 @@ def rel_norm(a, b):
     return float(np.linalg.norm(a - b) / (d if d > 0 else 1.0))
 
 
-def assert_close_masked(got, ref, mask_ok, rtol, name=""):
-    """Element-wise |got - ref| <= rtol * (|ref| + mean|ref|) where mask_ok."""
+def assert_close_masked(got, ref, mask_ok, rtol, name="", scale=None):
+    """Element-wise |got - ref| <= rtol * scale where mask_ok.
+
+    scale defaults to |ref| + mean|ref|; for composited values pass |ref| plus
+    the oracle's sum of |terms| (the size of the rounding error of a sum)."""
     got = np.asarray(got, np.float64)
     ref = np.asarray(ref, np.float64)
-    scale = np.abs(ref) + np.abs(ref).mean()
-    bad = (np.abs(got - ref) > rtol * scale) & mask_ok
+    if scale is None:
+        scale = np.abs(ref) + np.abs(ref).mean()
+    err = np.abs(got - ref) / np.maximum(scale, 1e-300)
+    print(f"  {name}: max element error / scale = {float(np.max(np.where(mask_ok, err, 0.0))):.2e}")
+    bad = (err > rtol) & mask_ok
     if bad.any():
         idx = np.argwhere(bad)[:5]
         raise AssertionError(f"{name}: {int(bad.sum())} elements off (rtol {rtol}); first {idx.tolist()}; "

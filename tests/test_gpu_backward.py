@@ -11,6 +11,25 @@ pytestmark = pytest.mark.gpu
 
 GRAD_REL = 1e-3   # per parameter group, relative L2
 
+# The rendered function is piecewise smooth: alpha cut-offs, the transmittance
+# stop and the network's ReLUs are decisions taken in floating point.  FP32 and
+# FP64 can take them differently within rounding distance, and one flipped
+# decision moves a gradient by O(1) of that pixel's share.  The tests therefore
+# put zero upstream gradient on pixels the oracle finds within a margin of such
+# a decision: alpha decisions within 1e-5 relative, and any ReLU argument of the
+# network below `net_tau` (FP32: 1e-3, about 50x the FP32 error of a
+# pre-activation; BF16: 5e-3, about 10x the effect of one bfloat16 rounding
+# flip of an input).
+NET_TAU = {"fp32": 1e-3, "bf16": 5e-3}
+
+
+def _keep_mask(ora, precision=None):
+    keep = ora["pix_flag"] == 0
+    if precision is not None:
+        keep &= ora["net_margin"] >= NET_TAU[precision]
+    print(f"  pixels kept for the gradient comparison: {keep.mean():.3f}")
+    return keep
+
 
 def _upstream(shape_rgb, C, H, W, seed, rgb=True, gbuf=True, alpha=True):
     rng = np.random.default_rng(seed)
@@ -45,6 +64,8 @@ def test_gbuffer_backward_no_shading(F):
     C = 10 + F
     drgb, dg, da = _upstream((3, 96, 96), C, 96, 96, seed=1, rgb=False)
     print(f"[gpu] gbuffer backward F={F}", flush=True)
+    keep = _keep_mask(O.render(g, cam, light, None))
+    dg, da = dg * keep, da * keep
     ora = O.render(g, cam, light, None, drgb=drgb, dgbuf=dg, dalpha=da)
     out = gpu_render(g, cam, light, None, "fp32", backward=(drgb, dg, da))
     _compare_grads(out, ora, GROUPS if F else GROUPS[:-1])
@@ -55,6 +76,7 @@ def test_shading_backward_no_network():
     g, cam, light = w.gaussians, w.cameras[0], w.lights[0]
     drgb, dg, da = _upstream((3, 128, 128), 10, 128, 128, seed=3, gbuf=False, alpha=False)
     print("[gpu] GGX backward 1k 128x128", flush=True)
+    drgb = drgb * _keep_mask(O.render(g, cam, light, None))
     ora = O.render(g, cam, light, None, drgb=drgb)
     out = gpu_render(g, cam, light, None, "fp32", backward=(drgb, None, None))
     _compare_grads(out, ora, GROUPS[:-1])
@@ -66,9 +88,11 @@ def test_network_backward_small(precision):
     cam, light = cams[0], lights[0]
     drgb, dg, da = _upstream((3, 96, 128), 26, 96, 128, seed=4, gbuf=False, alpha=False)
     print(f"[gpu] network backward {precision}", flush=True)
-    ora = O.render(g, cam, light, mlp, drgb=drgb, bf16=(precision == "bf16"))
+    bf = precision == "bf16"
+    drgb = drgb * _keep_mask(O.render(g, cam, light, mlp, bf16=bf), precision)
+    ora = O.render(g, cam, light, mlp, drgb=drgb, bf16=bf)
     out = gpu_render(g, cam, light, mlp, precision, backward=(drgb, None, None))
-    tol = GRAD_REL if precision == "fp32" else 2e-2
+    tol = GRAD_REL if precision == "fp32" else 1e-2
     _compare_grads(out, ora, GROUPS + ["mlp"], tol)
 
 
@@ -78,7 +102,8 @@ def test_sh_features32_width128_backward():
     cam, light = cams[0], lights[0]
     drgb, dg, da = _upstream((3, 96, 128), 42, 96, 128, seed=5, gbuf=False, alpha=False)
     print("[gpu] SH + F32 + width 128 backward", flush=True)
+    drgb = drgb * _keep_mask(O.render(g, cam, light, mlp, bf16=True), "bf16")
     ora = O.render(g, cam, light, mlp, drgb=drgb, bf16=True)
     out = gpu_render(g, cam, light, mlp, "bf16", backward=(drgb, None, None))
     groups = [k for k in GROUPS if k != "albedo"] + ["sh", "mlp"]
-    _compare_grads(out, ora, groups, 2e-2)
+    _compare_grads(out, ora, groups, 1e-2)
