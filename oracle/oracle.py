@@ -115,11 +115,13 @@ def _f64(a):
 
 
 def render(g, cam, light, mlp=None, bf16: bool = False, crop=None, drgb=None, dgbuf=None, dalpha=None,
-           grads: bool = False, nthreads: int = 0, lists: bool = False, params64: Optional[dict] = None):
+           grads: bool = False, nthreads: int = 0, lists: bool = False, params64: Optional[dict] = None,
+           sens: bool = False):
     """Render one view (and optionally its backward) in FP64.
 
     ``g`` is a ``scene.Gaussians``; ``params64`` may override any of its arrays
-    with float64 arrays (used by the finite-difference checks).  Returns a dict
+    with float64 arrays (used by the finite-difference checks).  ``sens``
+    also fills the shading-sensitivity diagnostic ``rgb_sens``.  Returns a dict
     of numpy arrays.
     """
     L = lib()
@@ -162,7 +164,7 @@ def render(g, cam, light, mlp=None, bf16: bool = False, crop=None, drgb=None, dg
         cap = int(_count_instances(g, cam, arr)) + 1
         tl = np.zeros(cap, np.int32)
     out = OgOut(_p(o["rgb"]), _p(o["gbuf"]), _p(o["alpha"]), _p(o["gbuf_abs"]), _p(o["net_margin"]),
-                _p(o["rgb_sens"]),
+                _p(o["rgb_sens"]) if sens else None,
                 _p(o["n_contrib"], _ip),
                 _p(o["pix_flag"], _up),
                 _p(o["mean2d"]), _p(o["conic"]), _p(o["depth"]), _p(o["opacity"]), _p(o["channels"]),

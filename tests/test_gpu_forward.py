@@ -72,7 +72,7 @@ def test_small_scene_no_network_1k_128():
     w = scene.workload(1)
     g, cam, light = w.gaussians, w.cameras[0], w.lights[0]
     print(f"[gpu] forward 1k 128x128 N={g.n}", flush=True)
-    ora = O.render(g, cam, light, None, lists=True)
+    ora = O.render(g, cam, light, None, lists=True, sens=True)
     out = gpu_render(g, cam, light)
     assert out["M"] == ora["num_instances"]
     _projection_checks(g, out, ora)
@@ -87,7 +87,7 @@ def test_ragged_image_sizes(W, H):
     cam = scene.look_at_camera((0.1, -0.2, 3.0), W, H)
     light = scene.default_light()
     print(f"[gpu] ragged {W}x{H}", flush=True)
-    ora = O.render(g, cam, light, None, lists=True)
+    ora = O.render(g, cam, light, None, lists=True, sens=True)
     out = gpu_render(g, cam, light)
     assert out["M"] == ora["num_instances"]
     tile_lists_equal(out, ora, ora["g_flag"])
@@ -102,7 +102,7 @@ def test_depth_ties_order_by_index():
     cam = scene.look_at_camera((0, 0, 3), 64, 48)
     light = scene.default_light()
     print("[gpu] depth ties", flush=True)
-    ora = O.render(g, cam, light, None, lists=True)
+    ora = O.render(g, cam, light, None, lists=True, sens=True)
     out = gpu_render(g, cam, light)
     tile_lists_equal(out, ora)
     _image_checks(out, ora)
