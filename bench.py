@@ -79,19 +79,24 @@ def run_gpu(precision: str, steps: int, warmup: int):
     for _ in range(warmup):
         step()
     torch.cuda.synchronize()
-    B.sssgs_timing_read()
-    B.sssgs_timing_enable(True)
+    # timed region: exactly `steps` steps, no per-stage events
     t0 = torch.cuda.Event(enable_timing=True)
     t1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
     t0.record()
     for _ in range(steps):
         step()
     t1.record()
     torch.cuda.synchronize()
+    ms = t0.elapsed_time(t1) / steps
+    # per-stage kernel durations: HIP events recorded around every stage on the
+    # stream its kernels run on, over separate steps
+    B.sssgs_timing_read()
+    B.sssgs_timing_enable(True)
+    for _ in range(max(1, min(steps, 10))):
+        step()
+    torch.cuda.synchronize()
     B.sssgs_timing_enable(False)
     stages = B.sssgs_timing_read()
-    ms = t0.elapsed_time(t1) / steps
     flags, m_dev = B.sssgs_workspace_status(ctypes_ptr(view), g.n, cam.width, cam.height, g.feat_dim, mlp.width,
                                             cap)
     assert flags == 0 and m_dev == M, (flags, m_dev, M)

@@ -192,6 +192,8 @@ typedef struct {
   size_t t_final;        /* float [H][W] */
   size_t n_contrib;      /* uint32 [H][W] */
   size_t status;         /* int32[4]: flags, M low, M high, unused */
+  size_t boxes;          /* int16x4 [n]: inclusive pixel bounds x_lo, x_hi, y_lo, y_hi
+                            outside which alpha < 1/255 (empty: x_lo > x_hi) */
 } sssgs_layout;
 
 sssgs_status sssgs_workspace_layout(int32_t n, int32_t width, int32_t height, int32_t feat_dim, int32_t mlp_width,

@@ -15,6 +15,13 @@ FLAGS = ["-O3", "--offload-arch=gfx950", "-fPIC", "-std=c++17", "-munsafe-fp-ato
          "-I", os.path.join(ROOT, "include")]
 
 
+# Per-source additions.  -amdgpu-mfma-vgpr-form keeps matrix-core results in
+# VGPRs: with AGPR accumulators this compiler produced wrong reads of the MFMA
+# results after the reduction loop of the compositing backward (the gradient
+# tests catch it); the shading kernels need the AGPRs for their working set.
+EXTRA = {"composite.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"]}
+
+
 def build(jobs: int = 8, verbose: bool = False) -> str:
     """Compile every source to an object (in parallel) and link the shared library."""
     objdir = os.path.join(HERE, "_build")
@@ -24,7 +31,7 @@ def build(jobs: int = 8, verbose: bool = False) -> str:
     for src in SOURCES:
         obj = os.path.join(objdir, src.replace(".hip", ".o"))
         objs.append(obj)
-        cmd = ["hipcc", *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+        cmd = ["hipcc", *FLAGS, *EXTRA.get(src, []), "-c", os.path.join(CSRC, src), "-o", obj]
         procs.append((src, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT)))
         while len([p for _, p in procs if p.poll() is None]) >= jobs:
             procs[0][1].wait()

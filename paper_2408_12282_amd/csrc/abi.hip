@@ -6,7 +6,7 @@
 #include <string>
 #include <vector>
 
-#include "../../include/sssgs.h"
+#include "sssgs.h"
 #include "launch.hpp"
 #include "shade_common.hpp"
 
@@ -85,7 +85,7 @@ size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 int in_pad_of(int in_dim) { return (in_dim + 31) / 32 * 32; }
 
 struct Layout {
-  size_t records, depth_keys, vals_a, keys_b, vals_b, keys_a, rects, radii, tt, offsets, partials, hist;
+  size_t records, depth_keys, vals_a, keys_b, vals_b, keys_a, rects, radii, boxes, tt, offsets, partials, hist;
   size_t ik_a, iv_a, ik_b, iv_b, ranges, t_final, n_contrib, status, m_total;
   size_t gacc, dG, dT, wops, tops, mlp_part, mlp_mid;
   size_t total;
@@ -125,6 +125,7 @@ bool make_layout(int32_t n, int32_t W, int32_t H, int32_t F, int32_t mlp_width, 
   L.vals_b = take(nn * 4);
   L.rects = take(nn * 8);
   L.radii = take(nn * 4);
+  L.boxes = take(nn * 8);
   L.tt = take(nn * 4);
   L.offsets = take(nn * 4);
   size_t np = scan_partials_needed(nn);
@@ -215,18 +216,18 @@ ProjIn proj_in(const sssgs_gaussians *g) {
 
 template <int F>
 void project_fwd_f(bool sh, const ProjIn &in, const CamArgs &cam, float *rec, uint32_t *k, uint32_t *v, ushort4 *r,
-                   int32_t *rad, hipStream_t st) {
-  if (sh) launch_project_fwd_t<F, true>(in, cam, rec, k, v, r, rad, st);
-  else launch_project_fwd_t<F, false>(in, cam, rec, k, v, r, rad, st);
+                   int32_t *rad, short4 *box, hipStream_t st) {
+  if (sh) launch_project_fwd_t<F, true>(in, cam, rec, k, v, r, rad, box, st);
+  else launch_project_fwd_t<F, false>(in, cam, rec, k, v, r, rad, box, st);
 }
 
 void project_fwd(int F, bool sh, const ProjIn &in, const CamArgs &cam, float *rec, uint32_t *k, uint32_t *v,
-                 ushort4 *r, int32_t *rad, hipStream_t st) {
+                 ushort4 *r, int32_t *rad, short4 *box, hipStream_t st) {
   switch (F) {
-    case 0: project_fwd_f<0>(sh, in, cam, rec, k, v, r, rad, st); break;
-    case 8: project_fwd_f<8>(sh, in, cam, rec, k, v, r, rad, st); break;
-    case 16: project_fwd_f<16>(sh, in, cam, rec, k, v, r, rad, st); break;
-    default: project_fwd_f<32>(sh, in, cam, rec, k, v, r, rad, st); break;
+    case 0: project_fwd_f<0>(sh, in, cam, rec, k, v, r, rad, box, st); break;
+    case 8: project_fwd_f<8>(sh, in, cam, rec, k, v, r, rad, box, st); break;
+    case 16: project_fwd_f<16>(sh, in, cam, rec, k, v, r, rad, box, st); break;
+    default: project_fwd_f<32>(sh, in, cam, rec, k, v, r, rad, box, st); break;
   }
 }
 
@@ -251,13 +252,14 @@ void composite_fwd(int C, const Layout &L, void *ws, int W, int H, float *gbuf, 
   const uint2 *rg = at<uint2>(ws, L.ranges);
   const uint32_t *sg = at<uint32_t>(ws, L.iv_a);
   const float *rec = at<float>(ws, L.records);
+  const short4 *bx = at<short4>(ws, L.boxes);
   float *tf = at<float>(ws, L.t_final);
   uint32_t *nc = at<uint32_t>(ws, L.n_contrib);
   switch (C) {
-    case 10: launch_composite_fwd_t<10>(rg, sg, rec, W, H, L.TX, L.TY, gbuf, tf, nc, st); break;
-    case 18: launch_composite_fwd_t<18>(rg, sg, rec, W, H, L.TX, L.TY, gbuf, tf, nc, st); break;
-    case 26: launch_composite_fwd_t<26>(rg, sg, rec, W, H, L.TX, L.TY, gbuf, tf, nc, st); break;
-    default: launch_composite_fwd_t<42>(rg, sg, rec, W, H, L.TX, L.TY, gbuf, tf, nc, st); break;
+    case 10: launch_composite_fwd_t<10>(rg, sg, rec, bx, W, H, L.TX, L.TY, gbuf, tf, nc, st); break;
+    case 18: launch_composite_fwd_t<18>(rg, sg, rec, bx, W, H, L.TX, L.TY, gbuf, tf, nc, st); break;
+    case 26: launch_composite_fwd_t<26>(rg, sg, rec, bx, W, H, L.TX, L.TY, gbuf, tf, nc, st); break;
+    default: launch_composite_fwd_t<42>(rg, sg, rec, bx, W, H, L.TX, L.TY, gbuf, tf, nc, st); break;
   }
 }
 
@@ -265,16 +267,17 @@ void composite_bwd(int C, const Layout &L, void *ws, int W, int H, hipStream_t s
   const uint2 *rg = at<uint2>(ws, L.ranges);
   const uint32_t *sg = at<uint32_t>(ws, L.iv_a);
   const float *rec = at<float>(ws, L.records);
+  const short4 *bx = at<short4>(ws, L.boxes);
   const float *tf = at<float>(ws, L.t_final);
   const uint32_t *nc = at<uint32_t>(ws, L.n_contrib);
   const float *dG = at<float>(ws, L.dG);
   const float *dT = at<float>(ws, L.dT);
   float *ga = at<float>(ws, L.gacc);
   switch (C) {
-    case 10: launch_composite_bwd_t<10>(rg, sg, rec, W, H, L.TX, L.TY, tf, nc, dG, dT, ga, st); break;
-    case 18: launch_composite_bwd_t<18>(rg, sg, rec, W, H, L.TX, L.TY, tf, nc, dG, dT, ga, st); break;
-    case 26: launch_composite_bwd_t<26>(rg, sg, rec, W, H, L.TX, L.TY, tf, nc, dG, dT, ga, st); break;
-    default: launch_composite_bwd_t<42>(rg, sg, rec, W, H, L.TX, L.TY, tf, nc, dG, dT, ga, st); break;
+    case 10: launch_composite_bwd_t<10>(rg, sg, rec, bx, W, H, L.TX, L.TY, tf, nc, dG, dT, ga, st); break;
+    case 18: launch_composite_bwd_t<18>(rg, sg, rec, bx, W, H, L.TX, L.TY, tf, nc, dG, dT, ga, st); break;
+    case 26: launch_composite_bwd_t<26>(rg, sg, rec, bx, W, H, L.TX, L.TY, tf, nc, dG, dT, ga, st); break;
+    default: launch_composite_bwd_t<42>(rg, sg, rec, bx, W, H, L.TX, L.TY, tf, nc, dG, dT, ga, st); break;
   }
 }
 
@@ -323,6 +326,7 @@ sssgs_status sssgs_workspace_layout(int32_t n, int32_t width, int32_t height, in
   out->depth_keys = L.depth_keys;
   out->rects = L.rects;
   out->radii = L.radii;
+  out->boxes = L.boxes;
   out->tile_ranges = L.ranges;
   out->sorted_gauss = L.iv_a;
   out->sorted_tiles = L.ik_a;
@@ -359,7 +363,8 @@ sssgs_status sssgs_render_forward(const sssgs_gaussians *g, const sssgs_camera *
   // 1. projection (Eq. 1-2): records, depth keys, tile rectangles
   {
     Scope sc(kStProject, st);
-    project_fwd(g->feat_dim, g->sh_degree == 3, in, ca, rec, dk, va, rects, at<int32_t>(ws, L.radii), st);
+    project_fwd(g->feat_dim, g->sh_degree == 3, in, ca, rec, dk, va, rects, at<int32_t>(ws, L.radii),
+                at<short4>(ws, L.boxes), st);
   }
   // 2. depth passes of the radix sort on the N Gaussians (stable, index order on ties)
   const uint32_t *kin = dk;

@@ -1,50 +1,76 @@
 // composite.hip -- per-tile front-to-back alpha compositing of the deferred
 // G-buffer (Sec. 3.1, Eq. 3) and its backward.
 //
-// One 256-lane workgroup per 16x16 tile, one pixel per lane.  Gaussian
-// records of the tile's depth-ordered list are staged through LDS in batches
-// of 256; each lane walks the batch, and the workgroup stops loading as soon
-// as every pixel has terminated.  The backward walks the same list from each
-// pixel's last contributor down, recovering transmittance by division instead
-// of storing per-pixel lists; per-Gaussian gradients are reductions over the
-// tile's pixels done on the matrix cores (see composite_bwd_kernel).
+// One 256-lane workgroup per 16x16 tile, one pixel per lane; wave w owns the
+// 16x4 strip of rows 4w..4w+3.  Records of the tile's depth-ordered list are
+// staged through LDS by the whole workgroup.  Each wave first tests the
+// staged Gaussians' alpha boxes (see alpha_box in project.hip) against its
+// strip with one ballot per 64 Gaussians and then walks only the Gaussians
+// that can reach it; the boxes are conservative, so skipping the others
+// changes no result.  The backward walks the same list from each pixel's last
+// contributor down, recovering transmittance by division instead of storing
+// per-pixel lists; per-Gaussian gradients are reductions over the tile's
+// pixels done on the matrix cores (see composite_bwd_kernel).
 #include "common.hpp"
 
 namespace sssgs {
 
+// Does the alpha box (int16 x_lo, x_hi | y_lo, y_hi packed in two dwords)
+// reach the 16x4 strip with top-left pixel (sx, sy)?
+__device__ __forceinline__ bool box_hits(uint2 bx, int sx, int sy) {
+  const int xlo = (int)(short)(bx.x & 0xffffu), xhi = (int)bx.x >> 16;
+  const int ylo = (int)(short)(bx.y & 0xffffu), yhi = (int)bx.y >> 16;
+  return !(xlo > sx + kTile - 1 || xhi < sx || ylo > sy + 3 || yhi < sy);
+}
+
 template <int C>
 __global__ __launch_bounds__(256) void composite_fwd_kernel(const uint2 *__restrict__ ranges,
                                                             const uint32_t *__restrict__ sorted_g,
-                                                            const float *__restrict__ records, int W, int H,
+                                                            const float *__restrict__ records,
+                                                            const short4 *__restrict__ boxes, int W, int H,
                                                             int TX, float *__restrict__ gbuf,
                                                             float *__restrict__ t_final,
                                                             uint32_t *__restrict__ n_contrib) {
   constexpr int RS = rec_stride(C);
-  __shared__ float4 batch[256 * RS / 4];
+  constexpr int NB = 256;  // records per batch
+  __shared__ float4 batch[NB * RS / 4];
+  __shared__ uint2 bbox[NB];
+  const int t = threadIdx.x, lane = t & 63;
+  const int w = __builtin_amdgcn_readfirstlane(t >> 6);
   const int tile = blockIdx.x;
   const int tx = tile % TX, ty = tile / TX;
-  const int px = tx * kTile + (threadIdx.x & 15), py = ty * kTile + (threadIdx.x >> 4);
+  const int sx = tx * kTile, sy = ty * kTile + 4 * w;  // the wave's strip
+  const int px = sx + (lane & 15), py = sy + (lane >> 4);
   const bool inside = px < W && py < H;
   const float pxc = (float)px + 0.5f, pyc = (float)py + 0.5f;
   const uint2 rg = ranges[tile];
+  const uint2 *bxs = reinterpret_cast<const uint2 *>(boxes);
   float T = 1.f;
   float acc[C];
 #pragma unroll
   for (int c = 0; c < C; c++) acc[c] = 0.f;
   uint32_t last = 0;
   bool done = !inside;
-  for (uint32_t b0 = rg.x; b0 < rg.y; b0 += 256) {
+  for (uint32_t b0 = rg.x; b0 < rg.y; b0 += NB) {
     if (__syncthreads_count(done) == 256) break;
-    const uint32_t e = b0 + threadIdx.x;
+    const uint32_t e = b0 + t;
     if (e < rg.y) {
-      const float *src = records + (size_t)sorted_g[e] * RS;
+      const uint32_t gi = sorted_g[e];
+      const float *src = records + (size_t)gi * RS;
 #pragma unroll
-      for (int k = 0; k < RS / 4; k++) batch[threadIdx.x * (RS / 4) + k] = ld4(src + 4 * k);
+      for (int k = 0; k < RS / 4; k++) batch[t * (RS / 4) + k] = ld4(src + 4 * k);
+      bbox[t] = bxs[gi];
     }
     __syncthreads();
-    const int cnt = (int)min(256u, rg.y - b0);
-    if (!done) {
-      for (int j = 0; j < cnt; j++) {
+    const int cnt = (int)min((uint32_t)NB, rg.y - b0);
+    for (int j0 = 0; j0 < cnt; j0 += 64) {
+      bool h = false;
+      if (j0 + lane < cnt) h = box_hits(bbox[j0 + lane], sx, sy);
+      uint64_t m = __ballot(h);
+      while (m != 0 && __ballot(!done) != 0) {
+        const int j = j0 + (int)__builtin_ctzll(m);
+        m &= m - 1;
+        if (done) continue;
         const float *r = reinterpret_cast<const float *>(&batch[j * (RS / 4)]);
         float dx, dy;
         const float pw = splat_power(r[0], r[1], r[2], r[3], r[4], pxc, pyc, dx, dy);
@@ -54,7 +80,7 @@ __global__ __launch_bounds__(256) void composite_fwd_kernel(const uint2 *__restr
         const float tn = T * (1.f - al);
         if (tn < 1e-4f) {
           done = true;
-          break;
+          continue;
         }
         const float wgt = al * T;
 #pragma unroll
@@ -79,42 +105,57 @@ typedef __attribute__((__vector_size__(4 * sizeof(float)))) float cf32x4;
 
 // Backward of the compositing, one workgroup per tile.  Each pixel walks its
 // list from the last contributor down in batches of kBJ Gaussians, recovering
-// transmittance by division, and produces three numbers per (pixel,
-// Gaussian): the blend weight w = T alpha, dL/dpower and dL/dopacity.  Every
-// per-Gaussian gradient is then a reduction over the tile's pixels of one of
-// those numbers times a per-pixel factor:
-//   dL/dchannel_c = sum_p w_p dG_p,c                      (w  x  dG)
-//   dL/d(u, v, conic) from sum_p dpower_p * (1, x, y, x^2, xy, y^2)_p
-//   dL/dopacity   = sum_p dopacity_p
-// so the reductions run on the matrix cores (v_mfma_f32_16x16x4_f32, K = the
-// tile's pixels) instead of one cross-lane reduction per value.
-constexpr int kBJ = 16;  // Gaussians per backward batch
+// transmittance with v_rcp_f32, and produces two numbers per (pixel, Gaussian):
+// the blend weight w = T alpha and g = dL/dpower.  Every per-Gaussian gradient
+// is a reduction over the tile's pixels of one of them times a per-pixel
+// factor:
+//   dL/dchannel_c = sum_p w_p dG_p,c
+//   dL/d(u, v, conic) from the moments sum_p g_p (1, x, y, x^2, xy, y^2)_p
+//   dL/dopacity   = sum_p g_p / opacity   (alpha = o e^power: dalpha/do = alpha/o)
+// so the reductions run on the matrix cores (v_mfma_f32_16x16x4_f32 with
+// K = the tile's pixels) rather than as one cross-lane reduction per value.
+// The batch's records are staged in LDS (double-buffered; the next batch is
+// fetched into registers while the current one is walked), and each wave
+// skips the Gaussians whose alpha box misses its strip.
+constexpr int kBJ = 16;       // Gaussians per backward batch
+constexpr int kMS = 256 + 4;  // row stride of the [Gaussian][pixel] matrices (conflict-free column reads)
 
 template <int C>
 __global__ __launch_bounds__(256, 2) void composite_bwd_kernel(
     const uint2 *__restrict__ ranges, const uint32_t *__restrict__ sorted_g, const float *__restrict__ records,
-    int W, int H, int TX, const float *__restrict__ t_final, const uint32_t *__restrict__ n_contrib,
-    const float *__restrict__ dG, const float *__restrict__ dT, float *__restrict__ gacc) {
+    const short4 *__restrict__ boxes, int W, int H, int TX, const float *__restrict__ t_final,
+    const uint32_t *__restrict__ n_contrib, const float *__restrict__ dG, const float *__restrict__ dT,
+    float *__restrict__ gacc) {
   constexpr int RS = rec_stride(C);
+  constexpr int R4 = RS / 4;              // float4 per record
   constexpr int GS = grad_stride(C);
   constexpr int CP = (C + 15) / 16 * 16;  // channels padded to 16-column blocks
   constexpr int NBC = CP / 16;
   constexpr int DS = CP + 4;              // LDS row stride of dG
+  constexpr int RW = CP + 16;             // columns of the per-wave partial sums: channels | moments
+  static_assert(RW <= 64, "per-wave partial sums must fit the wave's 64 columns");
+  static_assert(kBJ * R4 <= 256, "one thread per record chunk");
   __shared__ float dgs[256 * DS];         // dL/dG of the tile, [pixel][channel]
-  __shared__ float4 recs[kBJ * RS / 4];   // records of the batch
-  __shared__ uint32_t gidx[kBJ];
-  __shared__ float mat[2 * 256 * kBJ];    // [pixel][j] weights, later dpower | dopacity
-  constexpr int RED = 4 * kBJ * CP > 4 * 2 * kBJ * 16 ? 4 * kBJ * CP : 4 * 2 * kBJ * 16;
-  __shared__ float red[RED];              // per-wave partial sums of the two reductions
+  // [j][pixel]: weights (rows 0..kBJ-1) and dL/dpower (rows kBJ..2kBJ-1).  A
+  // wave only touches its own 64 pixel columns, so once its reductions are
+  // done it stores its partial sums [j][channels | moments] over its own
+  // columns of the weight rows.
+  __shared__ float mat[2 * kBJ * kMS];
+  __shared__ float4 recs[2][kBJ * R4];
+  __shared__ uint32_t gidx[2][kBJ];
+  __shared__ uint2 bbox[2][kBJ];
   __shared__ uint32_t maxlast;
-  const int t = threadIdx.x, lane = t & 63, w = t >> 6, g = lane >> 4, col = lane & 15;
+  const int t = threadIdx.x, lane = t & 63, g = lane >> 4, col = lane & 15;
+  const int w = __builtin_amdgcn_readfirstlane(t >> 6);
   const int tile = blockIdx.x;
   const int tx = tile % TX, ty = tile / TX;
-  const int px = tx * kTile + (t & 15), py = ty * kTile + (t >> 4);
+  const int sx = tx * kTile, sy = ty * kTile + 4 * w;  // the wave's 16x4 strip
+  const int px = sx + (lane & 15), py = sy + (lane >> 4);
   const bool inside = px < W && py < H;
   const float pxc = (float)px + 0.5f, pyc = (float)py + 0.5f;
   const uint2 rg = ranges[tile];
   const size_t HW = (size_t)W * H, pix = inside ? (size_t)py * W + px : 0;
+  const uint2 *bxs = reinterpret_cast<const uint2 *>(boxes);
   if (t == 0) maxlast = 0;
   __syncthreads();
   float gch[C];
@@ -135,27 +176,55 @@ __global__ __launch_bounds__(256, 2) void composite_bwd_kernel(
   for (int c = 0; c < CP; c++) dgs[t * DS + c] = c < C ? gch[c] : 0.f;
   __syncthreads();
   const int top = (int)maxlast;
-  float Tcur = Tfin, S = 0.f;
-  for (int hi = top; hi > 0; hi -= kBJ) {
-    const int lo = hi > kBJ ? hi - kBJ : 0, cnt = hi - lo;
-    for (int k = t; k < kBJ * RS / 4; k += 256) {
-      const int jj = k / (RS / 4), q4 = k % (RS / 4);
-      if (jj < cnt) {
-        const uint32_t gi = sorted_g[rg.x + lo + jj];
-        if (q4 == 0) gidx[jj] = gi;
-        recs[k] = ld4(records + (size_t)gi * RS + 4 * q4);
+  // Batch fetch into registers: thread t < kBJ * R4 holds chunk t % R4 of
+  // record t / R4 and, for chunk 0, the Gaussian's index and box.
+  const int fj = t / R4, fq = t % R4;
+  float4 f_rec = make_float4(0.f, 0.f, 0.f, 0.f);
+  uint32_t f_g = 0;
+  uint2 f_box = make_uint2(0u, 0u);
+  auto fetch = [&](int lo_, int cnt_) {
+    if (t < kBJ * R4 && fj < cnt_) {
+      f_g = sorted_g[rg.x + lo_ + fj];
+      f_rec = ld4(records + (size_t)f_g * RS + 4 * fq);
+      if (fq == 0) f_box = bxs[f_g];
+    }
+  };
+  auto stage = [&](int buf, int cnt_) {
+    if (t < kBJ * R4 && fj < cnt_) {
+      recs[buf][t] = f_rec;
+      if (fq == 0) {
+        gidx[buf][fj] = f_g;
+        bbox[buf][fj] = f_box;
       }
     }
-    __syncthreads();
+  };
+  if (top > 0) {
+    const int lo0 = top > kBJ ? top - kBJ : 0;
+    fetch(lo0, top - lo0);
+    stage(0, top - lo0);
+  }
+  __syncthreads();
+  const float dTT = dTfin * Tfin;
+  float Tcur = Tfin, S = 0.f;
+  int buf = 0;
+  for (int hi = top; hi > 0; hi -= kBJ, buf ^= 1) {
+    const int lo = hi > kBJ ? hi - kBJ : 0, cnt = hi - lo;
+    const int nlo = lo > kBJ ? lo - kBJ : 0, ncnt = lo - nlo;
+    if (ncnt > 0) fetch(nlo, ncnt);  // next batch, in flight during this one
+    // Gaussians of the batch that can reach this wave's strip
+    bool h = false;
+    if (lane < cnt) h = box_hits(bbox[buf][lane], sx, sy);
+    const uint32_t hm = (uint32_t)__ballot(h);
     // ---- per pixel, last to first
-    float wv[kBJ], pv[kBJ], qv[kBJ];
+    float wv[kBJ], pv[kBJ];
 #pragma unroll
     for (int jj = kBJ - 1; jj >= 0; jj--) {
       wv[jj] = 0.f;
       pv[jj] = 0.f;
-      qv[jj] = 0.f;
-      if (jj < cnt && (uint32_t)(lo + jj) < last) {
-        const float *r = reinterpret_cast<const float *>(&recs[jj * (RS / 4)]);
+      if (!((hm >> jj) & 1u)) continue;
+      if (__ballot((uint32_t)(lo + jj) < last) == 0) continue;
+      if ((uint32_t)(lo + jj) < last) {
+        const float *r = reinterpret_cast<const float *>(&recs[buf][jj * R4]);
         float dx, dy;
         const float pw = splat_power(r[0], r[1], r[2], r[3], r[4], pxc, pyc, dx, dy);
         if (pw <= 0.f) {
@@ -163,113 +232,84 @@ __global__ __launch_bounds__(256, 2) void composite_bwd_kernel(
           const float araw = __fmul_rn(r[5], ex);
           const float al = fminf(0.99f, araw);
           if (al >= (1.f / 255.f)) {
-            const float om = 1.f - al;
-            const float Tb = Tcur / om;
+            const float inv = __builtin_amdgcn_rcpf(1.f - al);
+            const float Tb = Tcur * inv;
             const float wgt = al * Tb;
             float eg = 0.f;
 #pragma unroll
             for (int c = 0; c < C; c++) eg = __fmaf_rn(gch[c], r[6 + c], eg);
-            const float dal = (Tb * eg - S / om) - dTfin * Tfin / om;
+            const float dal = Tb * eg - (S + dTT) * inv;
             S = __fmaf_rn(wgt, eg, S);
             Tcur = Tb;
             wv[jj] = wgt;
-            if (araw < 0.99f) {
-              pv[jj] = dal * al;
-              qv[jj] = dal * ex;
-            }
+            if (araw < 0.99f) pv[jj] = dal * al;
           }
         }
       }
-      __builtin_amdgcn_sched_barrier(0);  // keep record loads of later Gaussians from piling up in registers
     }
-    // ---- channel gradients: D1[j][c] = sum_p w[p][j] dG[p][c]
 #pragma unroll
-    for (int k = 0; k < kBJ; k += 4) *reinterpret_cast<float4 *>(&mat[t * kBJ + k]) = make_float4(wv[k], wv[k + 1], wv[k + 2], wv[k + 3]);
+    for (int jj = 0; jj < kBJ; jj++) {
+      mat[jj * kMS + t] = wv[jj];
+      mat[(kBJ + jj) * kMS + t] = pv[jj];
+    }
     __syncthreads();
+    // ---- reductions over this wave's 64 pixels (4 per MFMA step):
+    //   [j][c]  = sum_p w[j][p] dG[p][c]
+    //   [j][n]  = sum_p g[j][p] basis_n(p),  basis = (1, x, y, x^2, xy, y^2) from the tile corner
     {
-      cf32x4 acc[NBC];
+      cf32x4 acc[NBC + 1];
 #pragma unroll
-      for (int nc = 0; nc < NBC; nc++) acc[nc] = cf32x4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-      for (int ks = 0; ks < 16; ks++) {  // this wave's 64 pixels, 4 per step
+      for (int nc = 0; nc <= NBC; nc++) acc[nc] = cf32x4{0.f, 0.f, 0.f, 0.f};
+      // column col of the basis, branch-free: exactly one selector is 1
+      const float s0 = col == 0, s1 = col == 1, s2 = col == 2, s3 = col == 3, s4 = col == 4, s5 = col == 5;
+#pragma unroll 4
+      for (int ks = 0; ks < 16; ks++) {
         const int p = 64 * w + 4 * ks + g;
-        const float a = mat[p * kBJ + col];
+        const float a = mat[col * kMS + p];
 #pragma unroll
         for (int nc = 0; nc < NBC; nc++)
           acc[nc] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, dgs[p * DS + 16 * nc + col], acc[nc], 0, 0, 0);
+        const float x = (float)(p & 15) + 0.5f, y = (float)(p >> 4) + 0.5f;
+        const float b = s0 + x * (s1 + s3 * x + s4 * y) + y * (s2 + s5 * y);
+        acc[NBC] = __builtin_amdgcn_mfma_f32_16x16x4f32(mat[(kBJ + col) * kMS + p], b, acc[NBC], 0, 0, 0);
       }
-      // D layout: lane (col, g) holds rows j = 4 g + i, column c = 16 nc + col
+      // D layout: lane (col, g) holds rows j = 4 g + i of column 16 nc + col
 #pragma unroll
-      for (int nc = 0; nc < NBC; nc++)
+      for (int nc = 0; nc <= NBC; nc++)
 #pragma unroll
-        for (int i = 0; i < 4; i++) red[(w * kBJ + 4 * g + i) * CP + 16 * nc + col] = acc[nc][i];
+        for (int i = 0; i < 4; i++) mat[(4 * g + i) * kMS + 64 * w + 16 * nc + col] = acc[nc][i];
     }
+    if (ncnt > 0) stage(buf ^ 1, ncnt);
     __syncthreads();
     for (int k = t; k < kBJ * C; k += 256) {
       const int jj = k / C, c = k % C;
       if (jj < cnt) {
-        const float s = (red[(0 * kBJ + jj) * CP + c] + red[(1 * kBJ + jj) * CP + c]) +
-                        (red[(2 * kBJ + jj) * CP + c] + red[(3 * kBJ + jj) * CP + c]);
-        if (s != 0.f) atomicAdd(gacc + (size_t)gidx[jj] * GS + 6 + c, s);
+        const float s = (mat[jj * kMS + 0 * 64 + c] + mat[jj * kMS + 1 * 64 + c]) +
+                        (mat[jj * kMS + 2 * 64 + c] + mat[jj * kMS + 3 * 64 + c]);
+        if (s != 0.f) atomicAdd(gacc + (size_t)gidx[buf][jj] * GS + 6 + c, s);
       }
     }
-    // ---- geometric moments: rows 0..15 dpower, rows 16..31 dopacity, against
-    // the pixel basis (1, x, y, x^2, xy, y^2) relative to the tile corner
-    __syncthreads();
-#pragma unroll
-    for (int k = 0; k < kBJ; k += 4) {
-      *reinterpret_cast<float4 *>(&mat[t * kBJ + k]) = make_float4(pv[k], pv[k + 1], pv[k + 2], pv[k + 3]);
-      *reinterpret_cast<float4 *>(&mat[256 * kBJ + t * kBJ + k]) = make_float4(qv[k], qv[k + 1], qv[k + 2], qv[k + 3]);
-    }
-    __syncthreads();
-    {
-      cf32x4 acc[2] = {cf32x4{0.f, 0.f, 0.f, 0.f}, cf32x4{0.f, 0.f, 0.f, 0.f}};
-#pragma unroll
-      for (int ks = 0; ks < 16; ks++) {
-        const int p = 64 * w + 4 * ks + g;
-        const float x = (float)(p & 15) + 0.5f, y = (float)(p >> 4) + 0.5f;
-        float b = 0.f;
-        switch (col) {
-          case 0: b = 1.f; break;
-          case 1: b = x; break;
-          case 2: b = y; break;
-          case 3: b = x * x; break;
-          case 4: b = x * y; break;
-          case 5: b = y * y; break;
-          default: b = 0.f;
-        }
-        acc[0] = __builtin_amdgcn_mfma_f32_16x16x4f32(mat[p * kBJ + col], b, acc[0], 0, 0, 0);
-        acc[1] = __builtin_amdgcn_mfma_f32_16x16x4f32(mat[256 * kBJ + p * kBJ + col], b, acc[1], 0, 0, 0);
-      }
-#pragma unroll
-      for (int m = 0; m < 2; m++)
-#pragma unroll
-        for (int i = 0; i < 4; i++) red[(w * 2 * kBJ + 16 * m + 4 * g + i) * 16 + col] = acc[m][i];
-    }
-    __syncthreads();
     if (t < cnt) {
-      float mo[6], sq = 0.f;
+      float mo[6];
 #pragma unroll
       for (int n = 0; n < 6; n++)
-        mo[n] = (red[(0 * 2 * kBJ + t) * 16 + n] + red[(1 * 2 * kBJ + t) * 16 + n]) +
-                (red[(2 * 2 * kBJ + t) * 16 + n] + red[(3 * 2 * kBJ + t) * 16 + n]);
-      sq = (red[(0 * 2 * kBJ + 16 + t) * 16] + red[(1 * 2 * kBJ + 16 + t) * 16]) +
-           (red[(2 * 2 * kBJ + 16 + t) * 16] + red[(3 * 2 * kBJ + 16 + t) * 16]);
-      const float *r = reinterpret_cast<const float *>(&recs[t * (RS / 4)]);
-      const float up = r[0] - (float)(tx * kTile), vp = r[1] - (float)(ty * kTile);
-      // sums of dpower * dx, dy, dx^2, dx dy, dy^2 with dx = u - x, dy = v - y
-      const float sx = up * mo[0] - mo[1], sy = vp * mo[0] - mo[2];
-      const float sxx = up * up * mo[0] - 2.f * up * mo[1] + mo[3];
-      const float sxy = up * vp * mo[0] - up * mo[2] - vp * mo[1] + mo[4];
-      const float syy = vp * vp * mo[0] - 2.f * vp * mo[2] + mo[5];
-      float *ga = gacc + (size_t)gidx[t] * GS;
-      if (mo[0] != 0.f || sq != 0.f) {
-        atomicAdd(ga + 0, -(r[2] * sx + r[3] * sy));
-        atomicAdd(ga + 1, -(r[4] * sy + r[3] * sx));
-        atomicAdd(ga + 2, -0.5f * sxx);
-        atomicAdd(ga + 3, -sxy);
-        atomicAdd(ga + 4, -0.5f * syy);
-        atomicAdd(ga + 5, sq);
+        mo[n] = (mat[t * kMS + 0 * 64 + CP + n] + mat[t * kMS + 1 * 64 + CP + n]) +
+                (mat[t * kMS + 2 * 64 + CP + n] + mat[t * kMS + 3 * 64 + CP + n]);
+      if (mo[0] != 0.f || mo[1] != 0.f || mo[2] != 0.f) {
+        const float *r = reinterpret_cast<const float *>(&recs[buf][t * R4]);
+        const float up = r[0] - (float)(tx * kTile), vp = r[1] - (float)(ty * kTile);
+        // sums of g dx, g dy, g dx^2, g dx dy, g dy^2 with dx = u - x, dy = v - y
+        const float mx = up * mo[0] - mo[1], my = vp * mo[0] - mo[2];
+        const float mxx = up * up * mo[0] - 2.f * up * mo[1] + mo[3];
+        const float mxy = up * vp * mo[0] - up * mo[2] - vp * mo[1] + mo[4];
+        const float myy = vp * vp * mo[0] - 2.f * vp * mo[2] + mo[5];
+        float *ga = gacc + (size_t)gidx[buf][t] * GS;
+        atomicAdd(ga + 0, -(r[2] * mx + r[3] * my));
+        atomicAdd(ga + 1, -(r[4] * my + r[3] * mx));
+        atomicAdd(ga + 2, -0.5f * mxx);
+        atomicAdd(ga + 3, -mxy);
+        atomicAdd(ga + 4, -0.5f * myy);
+        atomicAdd(ga + 5, mo[0] / r[5]);
       }
     }
     __syncthreads();
@@ -277,25 +317,27 @@ __global__ __launch_bounds__(256, 2) void composite_bwd_kernel(
 }
 
 template <int C>
-void launch_composite_fwd_t(const uint2 *ranges, const uint32_t *sorted_g, const float *records, int W, int H,
-                            int TX, int TY, float *gbuf, float *t_final, uint32_t *n_contrib, hipStream_t st) {
-  composite_fwd_kernel<C><<<TX * TY, 256, 0, st>>>(ranges, sorted_g, records, W, H, TX, gbuf, t_final, n_contrib);
+void launch_composite_fwd_t(const uint2 *ranges, const uint32_t *sorted_g, const float *records, const short4 *boxes,
+                            int W, int H, int TX, int TY, float *gbuf, float *t_final, uint32_t *n_contrib,
+                            hipStream_t st) {
+  composite_fwd_kernel<C><<<TX * TY, 256, 0, st>>>(ranges, sorted_g, records, boxes, W, H, TX, gbuf, t_final,
+                                                   n_contrib);
 }
 
 template <int C>
-void launch_composite_bwd_t(const uint2 *ranges, const uint32_t *sorted_g, const float *records, int W, int H,
-                            int TX, int TY, const float *t_final, const uint32_t *n_contrib, const float *dG,
-                            const float *dT, float *gacc, hipStream_t st) {
-  composite_bwd_kernel<C><<<TX * TY, 256, 0, st>>>(ranges, sorted_g, records, W, H, TX, t_final, n_contrib, dG,
-                                                   dT, gacc);
+void launch_composite_bwd_t(const uint2 *ranges, const uint32_t *sorted_g, const float *records, const short4 *boxes,
+                            int W, int H, int TX, int TY, const float *t_final, const uint32_t *n_contrib,
+                            const float *dG, const float *dT, float *gacc, hipStream_t st) {
+  composite_bwd_kernel<C><<<TX * TY, 256, 0, st>>>(ranges, sorted_g, records, boxes, W, H, TX, t_final, n_contrib,
+                                                   dG, dT, gacc);
 }
 
 #define SSSGS_COMP_INST(C)                                                                                      \
-  template void launch_composite_fwd_t<C>(const uint2 *, const uint32_t *, const float *, int, int, int, int,  \
-                                          float *, float *, uint32_t *, hipStream_t);                          \
-  template void launch_composite_bwd_t<C>(const uint2 *, const uint32_t *, const float *, int, int, int, int,  \
-                                          const float *, const uint32_t *, const float *, const float *, float *, \
-                                          hipStream_t);
+  template void launch_composite_fwd_t<C>(const uint2 *, const uint32_t *, const float *, const short4 *, int,  \
+                                          int, int, int, float *, float *, uint32_t *, hipStream_t);          \
+  template void launch_composite_bwd_t<C>(const uint2 *, const uint32_t *, const float *, const short4 *, int,  \
+                                          int, int, int, const float *, const uint32_t *, const float *,      \
+                                          const float *, float *, hipStream_t);
 SSSGS_COMP_INST(10)
 SSSGS_COMP_INST(18)
 SSSGS_COMP_INST(26)

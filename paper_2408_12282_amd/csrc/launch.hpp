@@ -16,7 +16,7 @@ struct ShadeArgs;
 
 template <int F, bool SH>
 void launch_project_fwd_t(const ProjIn &in, const CamArgs &cam, float *records, uint32_t *keys, uint32_t *vals,
-                          ushort4 *rects, int32_t *radii, hipStream_t st);
+                          ushort4 *rects, int32_t *radii, short4 *boxes, hipStream_t st);
 template <int F, bool SH>
 void launch_project_bwd_t(const ProjIn &in, const CamArgs &cam, const float *gacc, const ProjGradOut &out,
                           hipStream_t st);
@@ -34,12 +34,13 @@ void launch_fill_u32(uint32_t *p, uint32_t v, uint32_t n, hipStream_t st);
 void launch_tile_ranges(const uint32_t *keys, const uint32_t *m_dev, uint32_t cap, uint2 *ranges, hipStream_t st);
 
 template <int C>
-void launch_composite_fwd_t(const uint2 *ranges, const uint32_t *sorted_g, const float *records, int W, int H,
-                            int TX, int TY, float *gbuf, float *t_final, uint32_t *n_contrib, hipStream_t st);
+void launch_composite_fwd_t(const uint2 *ranges, const uint32_t *sorted_g, const float *records, const short4 *boxes,
+                            int W, int H, int TX, int TY, float *gbuf, float *t_final, uint32_t *n_contrib,
+                            hipStream_t st);
 template <int C>
-void launch_composite_bwd_t(const uint2 *ranges, const uint32_t *sorted_g, const float *records, int W, int H,
-                            int TX, int TY, const float *t_final, const uint32_t *n_contrib, const float *dG,
-                            const float *dT, float *gacc, hipStream_t st);
+void launch_composite_bwd_t(const uint2 *ranges, const uint32_t *sorted_g, const float *records, const short4 *boxes,
+                            int W, int H, int TX, int TY, const float *t_final, const uint32_t *n_contrib,
+                            const float *dG, const float *dT, float *gacc, hipStream_t st);
 
 template <int F, int NET, int WIDTH, int IN_PAD>
 void launch_shade_fwd_t(const ShadeArgs &a, hipStream_t st);

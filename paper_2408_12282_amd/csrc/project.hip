@@ -161,6 +161,26 @@ __device__ inline void project_geometry(const ProjIn &in, const CamArgs &cam, in
   G.valid = (G.x1 > G.x0) && (G.y1 > G.y0);
 }
 
+// Inclusive pixel bounds [x_lo, x_hi] x [y_lo, y_hi] outside of which the
+// Gaussian's alpha stays below the 1/255 cut-off.  opacity e^power >= 1/255
+// needs power >= -q with q = ln(255 opacity), an ellipse d^T Sigma^-1 d <= 2q
+// whose half-extents are sqrt(2 q Sigma_xx) and sqrt(2 q Sigma_yy).  The bounds
+// are widened by 1% + 1e-6 x the condition number of Sigma (the FP32 conic the
+// compositing evaluates) and one pixel, so the FP32 decision can never fall
+// outside them; empty (x_lo > x_hi) when no pixel can pass.
+__device__ inline short4 alpha_box(const Geo &G, double opac) {
+  const short4 empty = make_short4(32767, -32768, 32767, -32768);
+  if (!G.valid || 255.0 * opac < 1.0 - 1e-6) return empty;
+  const double q = fmax(log(255.0 * opac), 0.0);
+  const double mid = 0.5 * (G.a + G.c), disc = sqrt(fmax(mid * mid - G.det, 0.0));
+  const double lmax = mid + disc, lmin = G.det / lmax;
+  const double grow = 1.01 + 1e-6 * lmax / lmin;
+  const double ex = sqrt(2.0 * q * G.a) * grow + 1.0, ey = sqrt(2.0 * q * G.c) * grow + 1.0;
+  auto clamp16 = [](double v) { return (short)fmin(fmax(v, -32768.0), 32767.0); };
+  return make_short4(clamp16(ceil(G.u - ex - 0.5)), clamp16(floor(G.u + ex - 0.5)), clamp16(ceil(G.v - ey - 0.5)),
+                     clamp16(floor(G.v + ey - 0.5)));
+}
+
 // Index of the smallest log-scale (first on ties) and the sign that turns
 // that rotation axis toward the camera.
 __device__ inline void normal_axis(const ProjIn &in, const CamArgs &cam, int i, const double *Rq, int &kmin,
@@ -181,7 +201,8 @@ __device__ inline void normal_axis(const ProjIn &in, const CamArgs &cam, int i, 
 template <int F, bool SH>
 __global__ __launch_bounds__(256) void project_fwd_kernel(ProjIn in, CamArgs cam, float *__restrict__ records,
                                                           uint32_t *__restrict__ keys, uint32_t *__restrict__ vals,
-                                                          ushort4 *__restrict__ rects, int32_t *__restrict__ radii) {
+                                                          ushort4 *__restrict__ rects, int32_t *__restrict__ radii,
+                                                          short4 *__restrict__ boxes) {
   constexpr int C = kChFeat + F;
   constexpr int RS = rec_stride(C);
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -195,6 +216,8 @@ __global__ __launch_bounds__(256) void project_fwd_kernel(ProjIn in, CamArgs cam
   rects[i] = G.valid ? make_ushort4((unsigned short)G.x0, (unsigned short)G.y0, (unsigned short)G.x1,
                                     (unsigned short)G.y1)
                      : make_ushort4(0, 0, 0, 0);
+  const double opac = 1.0 / (1.0 + exp(-(double)in.opacity_logits[i]));
+  boxes[i] = alpha_box(G, opac);
   if (!G.valid) return;
   float rec[RS];
   rec[0] = (float)G.u;
@@ -202,7 +225,7 @@ __global__ __launch_bounds__(256) void project_fwd_kernel(ProjIn in, CamArgs cam
   rec[2] = (float)(G.c / G.det);
   rec[3] = (float)(-G.b / G.det);
   rec[4] = (float)(G.a / G.det);
-  rec[5] = (float)(1.0 / (1.0 + exp(-(double)in.opacity_logits[i])));
+  rec[5] = (float)opac;
   if (SH) {
     double d0 = (double)in.means[i] - cam.Cw[0], d1 = (double)in.means[n + i] - cam.Cw[1],
            d2 = (double)in.means[2 * n + i] - cam.Cw[2];
@@ -401,9 +424,9 @@ __global__ __launch_bounds__(256) void project_bwd_kernel(ProjIn in, CamArgs cam
 // Host-side launchers (declared in launch.hpp).
 template <int F, bool SH>
 void launch_project_fwd_t(const ProjIn &in, const CamArgs &cam, float *records, uint32_t *keys, uint32_t *vals,
-                          ushort4 *rects, int32_t *radii, hipStream_t st) {
+                          ushort4 *rects, int32_t *radii, short4 *boxes, hipStream_t st) {
   if (in.n == 0) return;
-  project_fwd_kernel<F, SH><<<(in.n + 255) / 256, 256, 0, st>>>(in, cam, records, keys, vals, rects, radii);
+  project_fwd_kernel<F, SH><<<(in.n + 255) / 256, 256, 0, st>>>(in, cam, records, keys, vals, rects, radii, boxes);
 }
 
 template <int F, bool SH>
@@ -415,7 +438,7 @@ void launch_project_bwd_t(const ProjIn &in, const CamArgs &cam, const float *gac
 
 #define SSSGS_PROJ_INST(F, SH)                                                                              \
   template void launch_project_fwd_t<F, SH>(const ProjIn &, const CamArgs &, float *, uint32_t *, uint32_t *, \
-                                            ushort4 *, int32_t *, hipStream_t);                             \
+                                            ushort4 *, int32_t *, short4 *, hipStream_t);                   \
   template void launch_project_bwd_t<F, SH>(const ProjIn &, const CamArgs &, const float *,                 \
                                             const ProjGradOut &, hipStream_t);
 SSSGS_PROJ_INST(0, false)

@@ -45,6 +45,7 @@ def gpu_render(g, cam, light, mlp=None, precision="fp32", capacity=None, backwar
     rs = lay.rec_stride
     out["records"] = view.region(lay.records, rs * g.n, torch.float32).view(g.n, rs).cpu().numpy()
     out["depth_keys"] = view.region(lay.depth_keys, g.n, torch.float32).cpu().numpy()
+    out["boxes"] = view.region(lay.boxes, 4 * g.n, torch.int16).view(g.n, 4).cpu().numpy().astype(np.int64)
     if backward is not None:
         drgb, dgbuf, dalpha = backward
         t = lambda a: None if a is None else torch.from_numpy(np.ascontiguousarray(a, np.float32)).cuda()

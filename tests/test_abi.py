@@ -53,7 +53,7 @@ def test_workspace_sizing(B):
     lay = B.sssgs_workspace_layout(1000, 128, 128, 16, 64, 10000)
     assert lay.rec_stride == 32
     offs = [lay.records, lay.depth_keys, lay.rects, lay.radii, lay.tile_ranges, lay.sorted_gauss, lay.t_final,
-            lay.n_contrib, lay.status]
+            lay.n_contrib, lay.status, lay.boxes]
     assert all(o % 256 == 0 for o in offs)
     assert len(set(offs)) == len(offs)
     assert max(offs) < B.sssgs_workspace_bytes(1000, 128, 128, 16, 64, 10000)

@@ -55,20 +55,22 @@ def _compare_grads(out, ora, names, tol=GRAD_REL):
 GROUPS = ["means", "log_scales", "quats", "opacity_logits", "albedo", "roughness", "metallic", "sss", "features"]
 
 
-@pytest.mark.parametrize("F", [16, 8])
-def test_gbuffer_backward_no_shading(F):
-    """G-buffer fwd+bwd with L = sum(w * G) + sum(w_a * alpha) (the 100k/800 workload, reduced)."""
-    g = scene.make_gaussians(5000, F, False, seed=2)
+@pytest.mark.parametrize("F,sh", [(16, False), (8, False), (0, False), (32, True)])
+def test_gbuffer_backward_no_shading(F, sh):
+    """G-buffer fwd+bwd with L = sum(w * G) + sum(w_a * alpha) (the 100k/800 workload, reduced;
+    every channel count C = 10 + F the kernels are built for, SH colour with F = 32)."""
+    g = scene.make_gaussians(5000, F, sh, seed=2)
     cam = scene.look_at_camera((0, 0, 3), 96, 96)
     light = scene.default_light()
     C = 10 + F
     drgb, dg, da = _upstream((3, 96, 96), C, 96, 96, seed=1, rgb=False)
-    print(f"[gpu] gbuffer backward F={F}", flush=True)
+    print(f"[gpu] gbuffer backward F={F} sh={sh}", flush=True)
     keep = _keep_mask(O.render(g, cam, light, None))
     dg, da = dg * keep, da * keep
     ora = O.render(g, cam, light, None, drgb=drgb, dgbuf=dg, dalpha=da)
     out = gpu_render(g, cam, light, None, "fp32", backward=(drgb, dg, da))
-    _compare_grads(out, ora, GROUPS if F else GROUPS[:-1])
+    groups = [k for k in GROUPS if (F or k != "features") and not (sh and k == "albedo")] + (["sh"] if sh else [])
+    _compare_grads(out, ora, groups)
 
 
 def test_shading_backward_no_network():

@@ -157,6 +157,24 @@ def test_network_shading_small(precision):
         assert e64 < BF16_FP64_REL
 
 
+def test_sh_features32_forward_small():
+    """The large-scene form (SH colour, 32 features, C = 42, width-128 BF16 network) on a reduced scene."""
+    g, cams, lights, mlp = small_workload(5, 20000, 128, 96)
+    cam, light = cams[0], lights[0]
+    print("[gpu] SH + F32 forward 20k 128x96", flush=True)
+    ora = O.render(g, cam, light, mlp, lists=True, bf16=True)
+    out = gpu_render(g, cam, light, mlp, "bf16")
+    assert out["M"] == ora["num_instances"]
+    tile_lists_equal(out, ora, ora["g_flag"])
+    ok = ora["pix_flag"] == 0
+    assert_close_masked(out["gbuf"], ora["gbuf"], np.broadcast_to(ok, out["gbuf"].shape), ELEM_REL, "gbuf",
+                        scale=np.abs(ora["gbuf"]) + ora["gbuf_abs"])
+    assert rel_norm(out["gbuf"], ora["gbuf"]) < FWD_REL
+    e = rel_norm(out["rgb"], ora["rgb"])
+    print(f"rgb rel err vs BF16 emulation: {e:.3e}")
+    assert e < BF16_EMU_REL
+
+
 @pytest.mark.parametrize("precision", ["fp32", "bf16"])
 def test_headline_300k_800(precision):
     """The 300k-Gaussian 800x800 view: tile lists bit-exact, images to tolerance."""
