@@ -148,7 +148,7 @@ bool make_layout(int32_t n, int32_t W, int32_t H, int32_t F, int32_t mlp_width, 
   const int in_pad = in_pad_of(F + kNumPE + 6);
   L.nparams = mlp_width ? (int)sssgs_mlp_param_count(F + kNumPE + 6, mlp_width, 3, 6) : 0;
   L.shade_bwd_blocks = kShadeBwdMaxBlocks;
-  L.shade_parts = 4 * kShadeBwdMaxBlocks;  // upper bound on grid x waves
+  L.shade_parts = kShadeBwdMaxBlocks;  // one weight-gradient partial per workgroup
   L.wops = take(mlp_width ? prep_weight_bytes(mlp_width, in_pad) : 0);
   L.tops = take(mlp_width ? prep_weight_bytes(mlp_width, in_pad) : 0);
   L.mlp_part = take(mlp_width ? (size_t)L.shade_parts * L.nparams * 4 : 0);
@@ -501,7 +501,7 @@ sssgs_status sssgs_render_backward(const sssgs_gaussians *g, const sssgs_camera 
   if (net && dL_dmlp) {
     Scope sc(kStMlpReduce, st);
     const int ip = in_pad_of(mlp->in_dim);
-    const int parts = shade_bwd_grid(net, width, ip, L.T, nblk) * shade_bwd_waves(net, width, ip);
+    const int parts = shade_bwd_grid(net, width, ip, L.T, nblk);
     launch_reduce_partials(sa.mlp_partials, parts, L.nparams, at<float>(ws, L.mlp_mid), dL_dmlp,
                            opt->accumulate_grads, st);
   }

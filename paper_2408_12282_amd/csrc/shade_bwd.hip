@@ -6,9 +6,11 @@
 // forward is recomputed (layer 3 input kept, layers 1-2 recomputed as
 // needed); input gradients use the transposed weights on the matrix cores
 // (dX^T = W^T dY^T, consuming the accumulator layout directly); weight
-// gradients dW = dY^T X (K = the strip's 64 pixels) go through an LDS
-// transpose and are added to a per-wave partial owned by that wave alone, so
-// the final reduction over partials is deterministic.
+// gradients dW = dY^T X are computed per workgroup over the strips of all its
+// waves (K = 64 x waves pixels, staged through LDS) and added to a
+// per-workgroup partial; the first strips store, later ones add with
+// no-return float atomics, so no wave stalls on a read-modify-write, and
+// every address is written by one wave only, so the sums are deterministic.
 #include "launch.hpp"
 #include "shade_common.hpp"
 
@@ -92,38 +94,56 @@ struct Stage {
   }
 };
 
-// dW[o][k] += sum over the wave's 64 pixels of dY[o][px] X[k][px].
-// dy: staged upstream gradient (rows o < ROWS16), xk: staged layer input
-// (features k < KCOLS).  Adds into the wave's partial at W offset `woff`
-// (row-major [rows][cols]) for o < rows, k < cols.
-template <class M, int ROWS16, int KCOLS>
-__device__ __forceinline__ void dw_accumulate(const typename M::Elem *dy, int dys, const typename M::Elem *xk,
-                                              int xks, float *__restrict__ part, int woff, int rows, int cols,
-                                              bool first, int lane) {
+// Workgroup weight gradient of one layer over the NW strips its waves have
+// staged (K = 64 NW pixels): dW[o][k] = sum_p dY[o][p] X[k][p] and the bias
+// gradient db[o] = sum_p dY[o][p] (the product with an all-ones column).
+// Wave w computes the 16-row blocks mbo = w, w + NW, ... and stores them
+// into (first call) or adds them to (later calls, with no-return float
+// atomics) the workgroup's partial at W offset woff (row-major [rows][cols])
+// and bias offset boff.  Every address of the partial is written by one wave
+// only, so the sums are deterministic.
+template <class M, int ROWS16, int KCOLS, int NW>
+__device__ __forceinline__ void dw_block(const typename M::Elem *st_all, int stage_elems, int fst,
+                                         float *__restrict__ part, int woff, int boff, int rows, int cols,
+                                         bool first, int w, int lane) {
   using Op = typename M::Op;
+  using E = typename M::Elem;
   using ST = Stage<M>;
-  constexpr int MBO = ROWS16 / 16, NBK = KCOLS / 16, KSP = 64 / M::KS;
+  constexpr int MBO = ROWS16 / 16, NBK = KCOLS / 16, KSW = 64 / M::KS;
   const int g = lane >> 4, col = lane & 15;
+  Op ones;
+  if constexpr (M::KPL == 8) {
+#pragma unroll
+    for (int j = 0; j < 8; j++) ones[j] = (__bf16)(col == 0 ? 1.f : 0.f);
+  } else {
+    ones = col == 0 ? 1.f : 0.f;
+  }
 #pragma unroll 1
-  for (int mbo = 0; mbo < MBO; mbo++) {
-    f32x4 acc[NBK];
+  for (int mbo = w; mbo < MBO; mbo += NW) {
+    f32x4 acc[NBK + 1];
 #pragma unroll
-    for (int nbk = 0; nbk < NBK; nbk++) acc[nbk] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int nbk = 0; nbk <= NBK; nbk++) acc[nbk] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll 1
+    for (int v = 0; v < NW; v++) {
+      const E *dy = st_all + v * 2 * stage_elems;
+      const E *xk = dy + stage_elems;
 #pragma unroll
-    for (int ks = 0; ks < KSP; ks++) {
-      const int px0 = ks * M::KS + g * M::KPL;
-      Op a;
-      if constexpr (M::KPL == 8) a = *reinterpret_cast<const bf16x8 *>(dy + ST::idx(16 * mbo + col, px0, dys));
-      else a = dy[ST::idx(16 * mbo + col, px0, dys)];
+      for (int ks = 0; ks < KSW; ks++) {
+        const int px0 = ks * M::KS + g * M::KPL;
+        Op a;
+        if constexpr (M::KPL == 8) a = *reinterpret_cast<const bf16x8 *>(dy + ST::idx(16 * mbo + col, px0, fst));
+        else a = dy[ST::idx(16 * mbo + col, px0, fst)];
 #pragma unroll
-      for (int nbk = 0; nbk < NBK; nbk++) {
-        Op b;
-        if constexpr (M::KPL == 8) b = *reinterpret_cast<const bf16x8 *>(xk + ST::idx(16 * nbk + col, px0, xks));
-        else b = xk[ST::idx(16 * nbk + col, px0, xks)];
-        acc[nbk] = M::mma(a, b, acc[nbk]);
+        for (int nbk = 0; nbk < NBK; nbk++) {
+          Op b;
+          if constexpr (M::KPL == 8) b = *reinterpret_cast<const bf16x8 *>(xk + ST::idx(16 * nbk + col, px0, fst));
+          else b = xk[ST::idx(16 * nbk + col, px0, fst)];
+          acc[nbk] = M::mma(a, b, acc[nbk]);
+        }
+        acc[NBK] = M::mma(a, ones, acc[NBK]);
       }
     }
-    // D layout: lane (col, g) holds dW[16 mbo + 4 g + j][16 nbk + col]
+    // D layout: lane (col, g) holds dW[16 mbo + 4 g + j][16 nbk + col]; the bias in column 0
 #pragma unroll
     for (int nbk = 0; nbk < NBK; nbk++)
 #pragma unroll
@@ -131,32 +151,21 @@ __device__ __forceinline__ void dw_accumulate(const typename M::Elem *dy, int dy
         const int o = 16 * mbo + 4 * g + j, k = 16 * nbk + col;
         if (o < rows && k < cols) {
           float *p = part + woff + o * cols + k;
-          *p = first ? acc[nbk][j] : *p + acc[nbk][j];
+          if (first) *p = acc[nbk][j];
+          else atomicAdd(p, acc[nbk][j]);
+        }
+      }
+    if (col == 0)
+#pragma unroll
+      for (int j = 0; j < 4; j++) {
+        const int o = 16 * mbo + 4 * g + j;
+        if (o < rows) {
+          float *p = part + boff + o;
+          if (first) *p = acc[NBK][j];
+          else atomicAdd(p, acc[NBK][j]);
         }
       }
   }
-}
-
-// Sum of D-layout values over the wave's pixels per output feature -> bias gradient.
-template <int MB>
-__device__ __forceinline__ void db_accumulate(const f32x4 (&d)[MB][4], float *__restrict__ part, int boff, int rows,
-                                              bool first, int lane) {
-  const int g = lane >> 4, col = lane & 15;
-#pragma unroll
-  for (int mb = 0; mb < MB; mb++)
-#pragma unroll
-    for (int j = 0; j < 4; j++) {
-      float s = (d[mb][0][j] + d[mb][1][j]) + (d[mb][2][j] + d[mb][3][j]);
-      s += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(s), 0xB1, 0xF, 0xF, false));
-      s += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(s), 0x4E, 0xF, 0xF, false));
-      s += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(s), 0x141, 0xF, 0xF, false));
-      s += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(s), 0x140, 0xF, 0xF, false));
-      const int o = 16 * mb + 4 * g + j;
-      if (col == 0 && o < rows) {
-        float *p = part + boff + o;
-        *p = first ? s : *p + s;
-      }
-    }
 }
 
 // Write D-layout values (feature f = 16 mb + 4 g + j, pixel 16 nb + col) into a stage.
@@ -423,7 +432,7 @@ __global__ __launch_bounds__((BwdWaves<NET, WIDTH, IN_PAD>::value * 64)) void sh
   E *sxk = sdy + (NET ? STAGE_ELEMS : 0);
   float *io = io_all + (NET ? w * 64 * 16 : 0);  // [px][0..7] outputs, [px][8..15] output gradients
   float *dxin = reinterpret_cast<float *>(sdy);  // [64][IN_PAD + 1] after the last weight gradient
-  float *part = A.mlp_partials ? A.mlp_partials + (size_t)(blockIdx.x * NW + w) * A.nparams : nullptr;
+  float *part = A.mlp_partials ? A.mlp_partials + (size_t)blockIdx.x * A.nparams : nullptr;
   const size_t HW = (size_t)A.cam.W * A.cam.H;
   bool first = true;
   for (int s0 = blockIdx.x * NW; s0 < nstrips; s0 += gridDim.x * NW) {
@@ -523,8 +532,7 @@ __global__ __launch_bounds__((BwdWaves<NET, WIDTH, IN_PAD>::value * 64)) void sh
         __syncthreads();
         __builtin_amdgcn_sched_barrier(0);
         __builtin_amdgcn_sched_barrier(0);
-      dw_accumulate<M, 16, WIDTH>(sdy, FST, sxk, FST, part, PO::w(3), 6, WIDTH, first, lane);
-        db_accumulate<1>(dO, part, PO::b(3), 6, first, lane);
+      dw_block<M, 16, WIDTH, NW>(st_all, STAGE_ELEMS, FST, part, PO::w(3), PO::b(3), 6, WIDTH, first, w, lane);
         Op Bo[NS::KT_O][4];
 #pragma unroll
         for (int ks = 0; ks < NS::KT_O; ks++)
@@ -546,7 +554,6 @@ __global__ __launch_bounds__((BwdWaves<NET, WIDTH, IN_PAD>::value * 64)) void sh
         m3.apply(dH);                       // upstream of layer 2's pre-activation
         __syncthreads();
         stage_d<M, MB>(dH, sdy, FST, lane);
-        db_accumulate<MB>(dH, part, PO::b(2), WIDTH, first, lane);
         grad_to_ops<M, MB>(dH, Bd);
       }
 #pragma unroll 1
@@ -570,7 +577,8 @@ __global__ __launch_bounds__((BwdWaves<NET, WIDTH, IN_PAD>::value * 64)) void sh
         __syncthreads();
         __builtin_amdgcn_sched_barrier(0);
         __builtin_amdgcn_sched_barrier(0);
-      dw_accumulate<M, WIDTH, WIDTH>(sdy, FST, sxk, FST, part, PO::w(l), WIDTH, WIDTH, first, lane);
+      dw_block<M, WIDTH, WIDTH, NW>(st_all, STAGE_ELEMS, FST, part, PO::w(l), PO::b(l), WIDTH, WIDTH, first, w,
+                                    lane);
         f32x4 dH[MB][4];
         __builtin_amdgcn_sched_barrier(0);
         __builtin_amdgcn_sched_barrier(0);
@@ -579,14 +587,14 @@ __global__ __launch_bounds__((BwdWaves<NET, WIDTH, IN_PAD>::value * 64)) void sh
         else m1.apply(dH);
         __syncthreads();
         stage_d<M, MB>(dH, sdy, FST, lane);
-        db_accumulate<MB>(dH, part, PO::b(l - 1), WIDTH, first, lane);
         grad_to_ops<M, MB>(dH, Bd);
       }
       // layer 0: weight gradient with the input rows, input gradient W0^T dpre0
       for (int k = 0; k < IN_PAD; k++) sxk[ST::idx(k, lane, FST)] = xs[lane * XS + k];
       __syncthreads();
       __builtin_amdgcn_sched_barrier(0);
-      dw_accumulate<M, WIDTH, IN_PAD>(sdy, FST, sxk, FST, part, PO::w(0), WIDTH, IN_PAD, first, lane);
+      dw_block<M, WIDTH, IN_PAD, NW>(st_all, STAGE_ELEMS, FST, part, PO::w(0), PO::b(0), WIDTH, IN_PAD, first, w,
+                                     lane);
       {
         f32x4 dX[NS::MB0][4];
         __builtin_amdgcn_sched_barrier(0);
