@@ -34,6 +34,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-views", type=int, default=2, help="views in the CPU oracle sample")
     ap.add_argument("--precision", choices=["both", "bf16", "fp32"], default="both")
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="after the run, copy this many MiB device-to-device (a plain copy of known size, "
+                         "to scale the HBM byte counters of a profiled run)")
     return ap.parse_args()
 
 
@@ -111,6 +114,27 @@ def ctypes_ptr(view):
     return ct.c_void_p(view.workspace.data_ptr())
 
 
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "hbm_traffic_300k_800sq_fwdbwd_bf16.md")
+
+
+def measured_traffic():
+    """HBM bytes per launch from the committed counter profile (FETCH_SIZE + WRITE_SIZE,
+    scaled by a copy of known size), only for kernels whose source is unchanged since."""
+    import hashlib
+    out = {}
+    if not os.path.exists(TRAFFIC_PROFILE):
+        return out
+    for line in open(TRAFFIC_PROFILE):
+        parts = line.split()
+        if len(parts) != 4 or parts[0] != "traffic":
+            continue
+        src, sha = parts[3].split(":")
+        path = os.path.join(ROOT, "paper_2408_12282_amd", "csrc", src)
+        if os.path.exists(path) and hashlib.sha256(open(path, "rb").read()).hexdigest() == sha:
+            out[parts[1]] = int(parts[2])
+    return out
+
+
 def roofline(r):
     """Algorithmic bytes of the compositing kernels per launch / their measured duration."""
     C = r["C"]
@@ -121,12 +145,13 @@ def roofline(r):
     # backward: records + index per processed instance, dG + dT + T + n_contrib read, per-Gaussian grads written
     bwd_bytes = r["bwd_records"] * (4 * RS + 4) + HW * 4 * (C + 3) + r["n"] * 4 * (6 + C)
     out = {}
+    traffic = measured_traffic()
     for name, nbytes in (("composite_fwd", fwd_bytes), ("composite_bwd", bwd_bytes)):
         t = r["stages"].get(name, (0.0, 0))[0]
         if t > 0:
             gbs = nbytes / (t * 1e-3) / 1e9
             out[name] = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                         "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None, "kernel": name,
+                         "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": traffic.get(name), "kernel": name,
                          "bytes_per_launch": int(nbytes), "ms_per_launch": round(t, 4)}
     return out
 
@@ -185,6 +210,13 @@ def main():
                               "stages_ms": {k: round(v[0], 4) for k, v in f["stages"].items()}}
         line["bf16_speedup_vs_fp32"] = round(f["ms"] / head["ms"], 3)
     line["roofline_all"] = rl
+    if a.calib_copy_mib > 0:
+        import torch
+        src = torch.ones(a.calib_copy_mib << 18, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
     if not a.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(a.cpu_views)
     print(json.dumps(line), flush=True)
