@@ -856,6 +856,7 @@ int og_render(const og_gauss *g, const og_cam *cam, const og_light *light, const
         for (int k = 0; k < C; k++) { Gp[k] = 0; Ga[k] = 0; }
         int32_t last = 0;
         uint8_t flag = 0;
+        double tr_unc = 0.0; /* relative uncertainty of Tr under a float32 evaluation */
         for (int64_t e = 0; e < len; e++) {
           const proj_t *q = &P[L[e].i];
           double dx = q->u - uc, dy = q->v - vc;
@@ -864,11 +865,19 @@ int og_render(const og_gauss *g, const og_cam *cam, const og_light *light, const
           if (pw > 0) { sig = mix64(sig, (uint64_t)(e * 4 + 1)); continue; }
           double araw = q->o * exp(pw);
           double al = araw < 0.99 ? araw : 0.99;
-          if (fabs(araw - 0.99) < 1e-5) flag |= 8;
-          if (fabs(al - 1.0 / 255.0) < 1e-5 * (1.0 / 255.0)) flag |= 1;
+          /* relative change of alpha = change of the power when the mean and
+             the conic are rounded to float32 (half an ulp, 2^-24 relative) */
+          const double hu = 0x1p-24;
+          double a_unc = 1e-5 + 2.0 * (fabs(q->conic[0] * dx + q->conic[1] * dy) * fabs(q->u) * hu +
+                                       fabs(q->conic[2] * dy + q->conic[1] * dx) * fabs(q->v) * hu +
+                                       (0.5 * fabs(q->conic[0]) * dx * dx + 0.5 * fabs(q->conic[2]) * dy * dy +
+                                        fabs(q->conic[1] * dx * dy)) * hu);
+          if (fabs(araw - 0.99) < a_unc * 0.99) flag |= 8;
+          if (fabs(al - 1.0 / 255.0) < a_unc * (1.0 / 255.0)) flag |= 1;
           if (al < 1.0 / 255.0) { sig = mix64(sig, (uint64_t)(e * 4 + 1)); continue; }
           double tn = Tr * (1.0 - al);
-          if (fabs(tn - 1e-4) < 1e-5 * 1e-4) flag |= 2;
+          tr_unc += al / (1.0 - al) * (a_unc - 1e-5);
+          if (fabs(tn - 1e-4) < (1e-5 + tr_unc) * 1e-4) flag |= 2;
           if (tn < 1e-4) { sig = mix64(sig, (uint64_t)(e * 4 + 2)); break; }
           for (int k = 0; k < C; k++) {
             Gp[k] += Tr * al * q->ch[k];

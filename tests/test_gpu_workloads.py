@@ -123,18 +123,21 @@ def test_olat_training_step_8_views_500k():
         f = O.render(g, cam, light, mlp, bf16=True)
         rgb_np = rgb.cpu().numpy()
         assert rel_norm(rgb_np, f["rgb"]) < 1e-3
-        # the loss gradient's sign is a decision: compare the backward on the
-        # oracle's upstream with zero weight where the sign or a decision is marginal
-        up = (np.sign(f["rgb"] - target) * scale).astype(np.float32)
-        margin = (np.abs(f["rgb"] - target) > 1e-3) & (f["pix_flag"] == 0)[None] & \
-                 (f["net_margin"] >= 5e-3)[None]
-        up *= margin
-        # the GPU's own loss gradient agrees with the oracle's wherever the margin holds
-        agree = (dl.cpu().numpy() == np.sign(rgb_np - target).astype(np.float32) * np.float32(scale))
-        assert agree.all()
-        assert np.mean((np.sign(rgb_np - target) == np.sign(f["rgb"] - target))[margin]) == 1.0
+        # the GPU's loss gradient is exactly sign(rgb - target) / (3HW)
+        dl_np = dl.cpu().numpy()
+        np.testing.assert_array_equal(dl_np, np.sign(rgb_np - target).astype(np.float32) * np.float32(scale))
+        # the sign is itself a decision: away from ties it agrees with the oracle's
+        # except where a bfloat16 rounding flip moves the pixel across the target
+        far = np.abs(f["rgb"] - target) > 1e-3
+        mismatch = np.mean((np.sign(rgb_np - target) != np.sign(f["rgb"] - target))[far])
+        print(f"  L1 sign mismatches away from ties: {mismatch:.2e}")
+        assert mismatch < 2e-5
         ref_loss = np.abs(f["rgb"] - target).sum() * scale
         assert abs(loss.item() - ref_loss) < 2e-3 * ref_loss
+        # backward of the renderer on the GPU's own loss gradient, zero where the
+        # renderer's alpha, transmittance or ReLU decisions are marginal
+        keep = (f["pix_flag"] == 0) & (f["net_margin"] >= 5e-3)
+        up = (dl_np * keep[None]).astype(np.float32)
         B.render_backward(view, p, -1, bc, bl, gbuf, torch.from_numpy(up).cuda(), None, None, mp, mlp.width,
                           B.PREC_BF16, grads, dmlp, accumulate=(v > 0))
         og = O.render(g, cam, light, mlp, bf16=True, drgb=up)["grads"]
