@@ -24,7 +24,7 @@ __device__ __forceinline__ bool box_hits(uint2 bx, int sx, int sy) {
 }
 
 template <int C>
-__global__ __launch_bounds__(256) void composite_fwd_kernel(const uint2 *__restrict__ ranges,
+__global__ __launch_bounds__(256, 6) void composite_fwd_kernel(const uint2 *__restrict__ ranges,
                                                             const uint32_t *__restrict__ sorted_g,
                                                             const float *__restrict__ records,
                                                             const short4 *__restrict__ boxes, int W, int H,
@@ -32,7 +32,7 @@ __global__ __launch_bounds__(256) void composite_fwd_kernel(const uint2 *__restr
                                                             float *__restrict__ t_final,
                                                             uint32_t *__restrict__ n_contrib) {
   constexpr int RS = rec_stride(C);
-  constexpr int NB = 256;  // records per batch
+  constexpr int NB = 128;  // records per batch (small LDS footprint: 6 waves per SIMD)
   __shared__ float4 batch[NB * RS / 4];
   __shared__ uint2 bbox[NB];
   const int t = threadIdx.x, lane = t & 63;
@@ -54,7 +54,7 @@ __global__ __launch_bounds__(256) void composite_fwd_kernel(const uint2 *__restr
   for (uint32_t b0 = rg.x; b0 < rg.y; b0 += NB) {
     if (__syncthreads_count(done) == 256) break;
     const uint32_t e = b0 + t;
-    if (e < rg.y) {
+    if (t < NB && e < rg.y) {
       const uint32_t gi = sorted_g[e];
       const float *src = records + (size_t)gi * RS;
 #pragma unroll
