@@ -112,28 +112,53 @@ __global__ __launch_bounds__(kSortThreads) void radix_hist_kernel(const uint32_t
   hist[t * nblocks + blockIdx.x] = h[t];
 }
 
+// Stable scatter of one 8-bit digit.  The block ranks its keys with wave
+// ballots into block-local digit runs in LDS, then streams the runs out, so
+// that consecutive lanes write consecutive global addresses.
 __global__ __launch_bounds__(kSortThreads) void radix_scatter_kernel(
     const uint32_t *__restrict__ keys_in, const uint32_t *__restrict__ vals_in, uint32_t *__restrict__ keys_out,
     uint32_t *__restrict__ vals_out, uint32_t n_host, const uint32_t *__restrict__ n_dev, int shift,
     const uint32_t *__restrict__ hist_scan, int nblocks) {
-  __shared__ uint32_t run[kRadixBins];
+  __shared__ uint32_t run[kRadixBins];   // running block-local position per digit
+  __shared__ uint32_t loff[kRadixBins];  // block-local start of each digit's run
+  __shared__ uint32_t gbase[kRadixBins]; // global start of this block's run of each digit
   __shared__ uint32_t wcnt[4][kRadixBins];
   __shared__ uint32_t wbase[4][kRadixBins];
+  __shared__ uint32_t sk[kSortItems], sv[kSortItems];
+  __shared__ uint32_t lds4[4];
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const uint32_t n = load_count(n_host, n_dev);
   const uint32_t base = blockIdx.x * kSortItems;
   if (base >= n) return;  // uniform per block
-  run[t] = hist_scan[t * nblocks + blockIdx.x];
+  const uint32_t cnt = min((uint32_t)kSortItems, n - base);
+  uint32_t key[kSortRounds], val[kSortRounds];
+#pragma unroll
+  for (int r = 0; r < kSortRounds; r++) {
+    const uint32_t idx = base + r * kSortThreads + t;
+    key[r] = idx < n ? keys_in[idx] : 0u;
+    val[r] = idx < n ? vals_in[idx] : 0u;
+  }
+  run[t] = 0;
+  gbase[t] = hist_scan[t * nblocks + blockIdx.x];
 #pragma unroll
   for (int k = 0; k < 4; k++) wcnt[k][t] = 0;
   __syncthreads();
+#pragma unroll
+  for (int r = 0; r < kSortRounds; r++)
+    if (r * kSortThreads + t < (int)cnt) atomicAdd(&run[(key[r] >> shift) & (kRadixBins - 1)], 1u);
+  __syncthreads();
+  {
+    uint32_t total;
+    const uint32_t ex = block_exclusive_scan(run[t], lds4, total);
+    loff[t] = ex;
+    run[t] = ex;
+  }
+  __syncthreads();
   const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+#pragma unroll
   for (int r = 0; r < kSortRounds; r++) {
-    const uint32_t idx = base + r * kSortThreads + t;
-    const bool active = idx < n;
-    const uint32_t key = active ? keys_in[idx] : 0u;
-    const uint32_t val = active ? vals_in[idx] : 0u;
-    const uint32_t d = (key >> shift) & (kRadixBins - 1);
+    const bool active = r * kSortThreads + t < (int)cnt;
+    const uint32_t d = (key[r] >> shift) & (kRadixBins - 1);
     uint64_t match = __ballot(active);
 #pragma unroll
     for (int b = 0; b < kRadixBits; b++) {
@@ -158,9 +183,16 @@ __global__ __launch_bounds__(kSortThreads) void radix_scatter_kernel(
     __syncthreads();
     if (active) {
       const uint32_t pos = wbase[w][d] + rank;
-      keys_out[pos] = key;
-      vals_out[pos] = val;
+      sk[pos] = key[r];
+      sv[pos] = val[r];
     }
+  }
+  __syncthreads();
+  for (uint32_t i = t; i < cnt; i += kSortThreads) {
+    const uint32_t k = sk[i], d = (k >> shift) & (kRadixBins - 1);
+    const uint32_t pos = gbase[d] + (i - loff[d]);
+    keys_out[pos] = k;
+    vals_out[pos] = sv[i];
   }
 }
 
@@ -176,31 +208,51 @@ __global__ __launch_bounds__(256) void gather_tiles_kernel(const uint32_t *__res
   tt[p] = (uint32_t)(r.z - r.x) * (uint32_t)(r.w - r.y);
 }
 
-// Writes each Gaussian's (tile, index) instances at its scanned offset.
+// Writes each Gaussian's (tile, index) instances at its scanned offset.  The
+// instances of a block's 256 consecutive (depth-ordered) Gaussians form one
+// contiguous range of the output, which the block writes cooperatively: each
+// output slot finds its Gaussian by a binary search over the block's offsets.
 __global__ __launch_bounds__(256) void emit_kernel(const uint32_t *__restrict__ sorted_g,
                                                    const ushort4 *__restrict__ rects,
                                                    const uint32_t *__restrict__ offsets, uint32_t n, uint32_t cap,
                                                    int TX, uint32_t *__restrict__ inst_keys,
                                                    uint32_t *__restrict__ inst_vals, const uint32_t *__restrict__ m_dev,
                                                    int32_t *__restrict__ status) {
-  const uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
+  __shared__ uint32_t soff[257];
+  __shared__ uint32_t sg[256];
+  __shared__ ushort4 srect[256];
+  const int t = threadIdx.x;
+  const uint32_t p0 = blockIdx.x * 256u, p = p0 + t;
+  const uint32_t mtot = m_dev[0];
   if (p == 0) {
-    status[kStatusMLo] = (int32_t)m_dev[0];
+    status[kStatusMLo] = (int32_t)mtot;
     status[kStatusMHi] = 0;
-    status[kStatusFlags] = m_dev[0] > cap ? kFlagOverflow : 0;
+    status[kStatusFlags] = mtot > cap ? kFlagOverflow : 0;
   }
-  if (p >= n) return;
-  const uint32_t g = sorted_g[p];
-  const ushort4 r = rects[g];
-  uint32_t off = offsets[p];
-  for (int ty = r.y; ty < r.w; ty++)
-    for (int tx = r.x; tx < r.z; tx++) {
-      if (off < cap) {
-        inst_keys[off] = (uint32_t)(ty * TX + tx);
-        inst_vals[off] = g;
-      }
-      off++;
-    }
+  if (p0 >= n) return;  // only with n == 0 (one block is launched for the status word)
+  const uint32_t nb = min(256u, n - p0);
+  if ((uint32_t)t < nb) {
+    const uint32_t g = sorted_g[p];
+    const ushort4 r = rects[g];
+    sg[t] = g;
+    srect[t] = r;
+    soff[t] = offsets[p];
+    if ((uint32_t)t == nb - 1) soff[nb] = offsets[p] + (uint32_t)(r.z - r.x) * (uint32_t)(r.w - r.y);
+  }
+  __syncthreads();
+  const uint32_t lo = soff[0], hi = min(soff[nb], cap);
+  for (uint32_t o = lo + t; o < hi; o += 256u) {
+    // the Gaussian k with soff[k] <= o < soff[k + 1] (empty ranges skipped by the search)
+    int k = 0;
+#pragma unroll
+    for (int step = 128; step > 0; step >>= 1)
+      if (k + step < (int)nb && soff[k + step] <= o) k += step;
+    const ushort4 r = srect[k];
+    const uint32_t wx = (uint32_t)(r.z - r.x), q = o - soff[k];
+    const uint32_t ty = r.y + q / wx, tx = r.x + q % wx;
+    inst_keys[o] = ty * (uint32_t)TX + tx;
+    inst_vals[o] = sg[k];
+  }
 }
 
 __global__ __launch_bounds__(256) void fill_u32_kernel(uint32_t *__restrict__ p, uint32_t v, uint32_t n) {
