@@ -257,27 +257,39 @@ __global__ __launch_bounds__(256, 2) void composite_bwd_kernel(
     //   [j][c]  = sum_p w[j][p] dG[p][c]
     //   [j][n]  = sum_p g[j][p] basis_n(p),  basis = (1, x, y, x^2, xy, y^2) from the tile corner
     {
-      cf32x4 acc[NBC + 1];
+      // operands of all 16 k-steps are loaded first; even and odd k-steps go
+      // to separate accumulators, which halves the dependent MFMA chains
+      float av[16], gv[16], bv[16][NBC];
 #pragma unroll
-      for (int nc = 0; nc <= NBC; nc++) acc[nc] = cf32x4{0.f, 0.f, 0.f, 0.f};
-      // column col of the basis, branch-free: exactly one selector is 1
-      const float s0 = col == 0, s1 = col == 1, s2 = col == 2, s3 = col == 3, s4 = col == 4, s5 = col == 5;
-#pragma unroll 4
       for (int ks = 0; ks < 16; ks++) {
         const int p = 64 * w + 4 * ks + g;
-        const float a = mat[col * kMS + p];
+        av[ks] = mat[col * kMS + p];
+        gv[ks] = mat[(kBJ + col) * kMS + p];
+#pragma unroll
+        for (int nc = 0; nc < NBC; nc++) bv[ks][nc] = dgs[p * DS + 16 * nc + col];
+      }
+      cf32x4 acc[2][NBC + 1];
+#pragma unroll
+      for (int h = 0; h < 2; h++)
+#pragma unroll
+        for (int nc = 0; nc <= NBC; nc++) acc[h][nc] = cf32x4{0.f, 0.f, 0.f, 0.f};
+      // column col of the basis, branch-free: exactly one selector is 1
+      const float s0 = col == 0, s1 = col == 1, s2 = col == 2, s3 = col == 3, s4 = col == 4, s5 = col == 5;
+#pragma unroll
+      for (int ks = 0; ks < 16; ks++) {
+        const int h = ks & 1, p = 64 * w + 4 * ks + g;
 #pragma unroll
         for (int nc = 0; nc < NBC; nc++)
-          acc[nc] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, dgs[p * DS + 16 * nc + col], acc[nc], 0, 0, 0);
+          acc[h][nc] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[ks], bv[ks][nc], acc[h][nc], 0, 0, 0);
         const float x = (float)(p & 15) + 0.5f, y = (float)(p >> 4) + 0.5f;
         const float b = s0 + x * (s1 + s3 * x + s4 * y) + y * (s2 + s5 * y);
-        acc[NBC] = __builtin_amdgcn_mfma_f32_16x16x4f32(mat[(kBJ + col) * kMS + p], b, acc[NBC], 0, 0, 0);
+        acc[h][NBC] = __builtin_amdgcn_mfma_f32_16x16x4f32(gv[ks], b, acc[h][NBC], 0, 0, 0);
       }
       // D layout: lane (col, g) holds rows j = 4 g + i of column 16 nc + col
 #pragma unroll
       for (int nc = 0; nc <= NBC; nc++)
 #pragma unroll
-        for (int i = 0; i < 4; i++) mat[(4 * g + i) * kMS + 64 * w + 16 * nc + col] = acc[nc][i];
+        for (int i = 0; i < 4; i++) mat[(4 * g + i) * kMS + 64 * w + 16 * nc + col] = acc[0][nc][i] + acc[1][nc][i];
     }
     if (ncnt > 0) stage(buf ^ 1, ncnt);
     __syncthreads();
