@@ -121,7 +121,7 @@ constexpr int kBJ = 16;       // Gaussians per backward batch
 constexpr int kMS = 256 + 4;  // row stride of the [Gaussian][pixel] matrices (conflict-free column reads)
 
 template <int C>
-__global__ __launch_bounds__(256, 2) void composite_bwd_kernel(
+__global__ __launch_bounds__(256, C > 26 ? 2 : 3) void composite_bwd_kernel(
     const uint2 *__restrict__ ranges, const uint32_t *__restrict__ sorted_g, const float *__restrict__ records,
     const short4 *__restrict__ boxes, int W, int H, int TX, const float *__restrict__ t_final,
     const uint32_t *__restrict__ n_contrib, const float *__restrict__ dG, const float *__restrict__ dT,
@@ -131,11 +131,9 @@ __global__ __launch_bounds__(256, 2) void composite_bwd_kernel(
   constexpr int GS = grad_stride(C);
   constexpr int CP = (C + 15) / 16 * 16;  // channels padded to 16-column blocks
   constexpr int NBC = CP / 16;
-  constexpr int DS = CP + 4;              // LDS row stride of dG
   constexpr int RW = CP + 16;             // columns of the per-wave partial sums: channels | moments
   static_assert(RW <= 64, "per-wave partial sums must fit the wave's 64 columns");
   static_assert(kBJ * R4 <= 256, "one thread per record chunk");
-  __shared__ float dgs[256 * DS];         // dL/dG of the tile, [pixel][channel]
   // [j][pixel]: weights (rows 0..kBJ-1) and dL/dpower (rows kBJ..2kBJ-1).  A
   // wave only touches its own 64 pixel columns, so once its reductions are
   // done it stores its partial sums [j][channels | moments] over its own
@@ -172,9 +170,20 @@ __global__ __launch_bounds__(256, 2) void composite_bwd_kernel(
 #pragma unroll
     for (int c = 0; c < C; c++) gch[c] = 0.f;
   }
+  // The tile's dL/dG is the B operand of every channel reduction below: lane
+  // (col, g) of wave w needs dG[pixel 64 w + 4 ks + g][channel 16 nc + col].
+  // It is transposed once through LDS (the weight matrix is not in use yet)
+  // and kept in registers for the whole tile.
+  float bv[16][NBC];
 #pragma unroll
-  for (int c = 0; c < CP; c++) dgs[t * DS + c] = c < C ? gch[c] : 0.f;
-  __syncthreads();
+  for (int nc = 0; nc < NBC; nc++) {
+#pragma unroll
+    for (int c = 0; c < 16; c++) mat[t * 17 + c] = 16 * nc + c < C ? gch[16 * nc + c] : 0.f;
+    __syncthreads();
+#pragma unroll
+    for (int ks = 0; ks < 16; ks++) bv[ks][nc] = mat[(64 * w + 4 * ks + g) * 17 + col];
+    __syncthreads();
+  }
   const int top = (int)maxlast;
   // Batch fetch into registers: thread t < kBJ * R4 holds chunk t % R4 of
   // record t / R4 and, for chunk 0, the Gaussian's index and box.
@@ -259,14 +268,12 @@ __global__ __launch_bounds__(256, 2) void composite_bwd_kernel(
     {
       // operands of all 16 k-steps are loaded first; even and odd k-steps go
       // to separate accumulators, which halves the dependent MFMA chains
-      float av[16], gv[16], bv[16][NBC];
+      float av[16], gv[16];
 #pragma unroll
       for (int ks = 0; ks < 16; ks++) {
         const int p = 64 * w + 4 * ks + g;
         av[ks] = mat[col * kMS + p];
         gv[ks] = mat[(kBJ + col) * kMS + p];
-#pragma unroll
-        for (int nc = 0; nc < NBC; nc++) bv[ks][nc] = dgs[p * DS + 16 * nc + col];
       }
       cf32x4 acc[2][NBC + 1];
 #pragma unroll
