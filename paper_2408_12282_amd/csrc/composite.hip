@@ -224,15 +224,11 @@ __global__ __launch_bounds__(256, C > 26 ? 2 : 3) void composite_bwd_kernel(
     bool h = false;
     if (lane < cnt) h = box_hits(bbox[buf][lane], sx, sy);
     const uint32_t hm = (uint32_t)__ballot(h);
-    // ---- per pixel, last to first
-    float wv[kBJ], pv[kBJ];
+    // ---- per pixel, last to first; each result goes straight to LDS
 #pragma unroll
     for (int jj = kBJ - 1; jj >= 0; jj--) {
-      wv[jj] = 0.f;
-      pv[jj] = 0.f;
-      if (!((hm >> jj) & 1u)) continue;
-      if (__ballot((uint32_t)(lo + jj) < last) == 0) continue;
-      if ((uint32_t)(lo + jj) < last) {
+      float wvj = 0.f, pvj = 0.f;
+      if (((hm >> jj) & 1u) && __ballot((uint32_t)(lo + jj) < last) != 0 && (uint32_t)(lo + jj) < last) {
         const float *r = reinterpret_cast<const float *>(&recs[buf][jj * R4]);
         float dx, dy;
         const float pw = splat_power(r[0], r[1], r[2], r[3], r[4], pxc, pyc, dx, dy);
@@ -250,16 +246,13 @@ __global__ __launch_bounds__(256, C > 26 ? 2 : 3) void composite_bwd_kernel(
             const float dal = Tb * eg - (S + dTT) * inv;
             S = __fmaf_rn(wgt, eg, S);
             Tcur = Tb;
-            wv[jj] = wgt;
-            if (araw < 0.99f) pv[jj] = dal * al;
+            wvj = wgt;
+            if (araw < 0.99f) pvj = dal * al;
           }
         }
       }
-    }
-#pragma unroll
-    for (int jj = 0; jj < kBJ; jj++) {
-      mat[jj * kMS + t] = wv[jj];
-      mat[(kBJ + jj) * kMS + t] = pv[jj];
+      mat[jj * kMS + t] = wvj;
+      mat[(kBJ + jj) * kMS + t] = pvj;
     }
     __syncthreads();
     // ---- reductions over this wave's 64 pixels (4 per MFMA step):
