@@ -24,6 +24,7 @@ MPIX = 0.64
 HBM_PEAK_GBS = 8000.0
 FP32_VALU_TFLOPS = 78.6      # non-packed FP32 FMA: 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz
 BF16_MFMA_TFLOPS = 2500.0
+FP32_MFMA_TFLOPS = 157.3      # dense FP32 matrix-core peak
 
 
 def parse():
@@ -106,7 +107,7 @@ def run_gpu(precision: str, steps: int, warmup: int):
     per_tile_last, fwd_records, listed = tile_stats(view, cam)
     return {"ms": ms, "stages": {k: (v[0] / max(v[1], 1), v[1]) for k, v in stages.items()}, "M": M,
             "bwd_records": per_tile_last, "fwd_records": fwd_records, "listed": listed, "n": g.n,
-            "C": 10 + g.feat_dim, "HW": cam.width * cam.height}
+            "C": 10 + g.feat_dim, "HW": cam.width * cam.height, "precision": precision}
 
 
 def ctypes_ptr(view):
@@ -128,15 +129,20 @@ def measured_traffic():
         parts = line.split()
         if len(parts) != 4 or parts[0] != "traffic":
             continue
-        src, sha = parts[3].split(":")
-        path = os.path.join(ROOT, "paper_2408_12282_amd", "csrc", src)
-        if os.path.exists(path) and hashlib.sha256(open(path, "rb").read()).hexdigest() == sha:
+        unchanged = True
+        for item in parts[3].split(","):
+            src, sha = item.split(":")
+            path = os.path.join(ROOT, "paper_2408_12282_amd", "csrc", src)
+            if not os.path.exists(path) or hashlib.sha256(open(path, "rb").read()).hexdigest() != sha:
+                unchanged = False
+        if unchanged:
             out[parts[1]] = int(parts[2])
     return out
 
 
 def roofline(r):
-    """Algorithmic bytes of the compositing kernels per launch / their measured duration."""
+    """Algorithmic bytes (compositing, HBM-bound model) or flops (shading network,
+    matrix-core model) per launch, divided by the kernels' measured durations."""
     C = r["C"]
     RS = (6 + C + 3) // 4 * 4
     HW = r["HW"]
@@ -144,6 +150,9 @@ def roofline(r):
     fwd_bytes = r["fwd_records"] * (4 * RS + 4) + HW * 4 * (C + 2)
     # backward: records + index per processed instance, dG + dT + T + n_contrib read, per-Gaussian grads written
     bwd_bytes = r["bwd_records"] * (4 * RS + 4) + HW * 4 * (C + 3) + r["n"] * 4 * (6 + C)
+    # network multiply-adds per pixel (58 inputs, three hidden layers of 64, 6 outputs): forward once;
+    # backward = input gradients + weight gradients + the forward recomputed (3x)
+    net_flop = 2 * (58 * 64 + 2 * 64 * 64 + 64 * 6)
     out = {}
     traffic = measured_traffic()
     for name, nbytes in (("composite_fwd", fwd_bytes), ("composite_bwd", bwd_bytes)):
@@ -153,6 +162,14 @@ def roofline(r):
             out[name] = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                          "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": traffic.get(name), "kernel": name,
                          "bytes_per_launch": int(nbytes), "ms_per_launch": round(t, 4)}
+    peak = BF16_MFMA_TFLOPS if r["precision"] == "bf16" else FP32_MFMA_TFLOPS
+    for name, flop in (("shade_fwd", HW * net_flop), ("shade_bwd", 3 * HW * net_flop)):
+        t = r["stages"].get(name, (0.0, 0))[0]
+        if t > 0:
+            tf = flop / (t * 1e-3) / 1e12
+            out[name] = {"bound": "mfma", "achieved": round(tf, 2), "peak": peak, "unit": "TFLOP/s",
+                         "frac": round(tf / peak, 4), "traffic": traffic.get(name), "kernel": name,
+                         "flop_per_launch": int(flop), "ms_per_launch": round(t, 4)}
     return out
 
 
