@@ -101,13 +101,53 @@ def run_gpu(precision: str, steps: int, warmup: int):
     torch.cuda.synchronize()
     B.sssgs_timing_enable(False)
     stages = B.sssgs_timing_read()
+    extras = time_training_kernels(rgb_ref=drgb, params=p, mlp_params=mp, grads=grads, dmlp=dmlp)
     flags, m_dev = B.sssgs_workspace_status(ctypes_ptr(view), g.n, cam.width, cam.height, g.feat_dim, mlp.width,
                                             cap)
     assert flags == 0 and m_dev == M, (flags, m_dev, M)
     per_tile_last, fwd_records, listed = tile_stats(view, cam)
     return {"ms": ms, "stages": {k: (v[0] / max(v[1], 1), v[1]) for k, v in stages.items()}, "M": M,
             "bwd_records": per_tile_last, "fwd_records": fwd_records, "listed": listed, "n": g.n,
-            "C": 10 + g.feat_dim, "HW": cam.width * cam.height, "precision": precision}
+            "C": 10 + g.feat_dim, "HW": cam.width * cam.height, "precision": precision, "training": extras}
+
+
+def time_training_kernels(rgb_ref, params, mlp_params, grads, dmlp, reps: int = 10):
+    """The rest of a training step, outside the headline: the image loss
+    (L1 + D-SSIM, value and gradient) of an 800x800 view and one Adam update of
+    every Gaussian and network parameter, timed with events on the stream."""
+    import torch
+    from paper_2408_12282_amd import sssgs as B
+    C, H, W = rgb_ref.shape
+    pred = (rgb_ref * 0.1).abs().contiguous()
+    target = torch.rand_like(pred)
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    B.image_loss(pred, target)
+    torch.cuda.synchronize()
+    t0.record()
+    for _ in range(reps):
+        B.image_loss(pred, target)
+    t1.record()
+    torch.cuda.synchronize()
+    loss_ms = t0.elapsed_time(t1) / reps
+    loss_bytes = 11 * C * H * W * 4
+    tensors = [(v, grads[k]) for k, v in params.items()] + [(mlp_params, dmlp)]
+    moments = [(torch.zeros_like(v), torch.zeros_like(v)) for v, _ in tensors]
+    nparam = sum(v.numel() for v, _ in tensors)
+    # Adam on copies: the benchmark's parameters stay as they are
+    work = [(v.clone(), gr) for v, gr in tensors]
+    torch.cuda.synchronize()
+    t0.record()
+    for step in range(1, reps + 1):
+        for (v, gr), (m, s2) in zip(work, moments):
+            B.adam_step(v, gr, m, s2, step, B.lr_schedule(step))
+    t1.record()
+    torch.cuda.synchronize()
+    adam_ms = t0.elapsed_time(t1) / reps
+    return {"image_loss": {"ms": round(loss_ms, 4), "shape": [C, H, W],
+                           "gbs": round(loss_bytes / (loss_ms * 1e-3) / 1e9, 1)},
+            "adam": {"ms": round(adam_ms, 4), "params": int(nparam), "launches": len(work),
+                     "gbs": round(28 * nparam / (adam_ms * 1e-3) / 1e9, 1)}}
 
 
 def ctypes_ptr(view):
@@ -227,6 +267,7 @@ def main():
                               "stages_ms": {k: round(v[0], 4) for k, v in f["stages"].items()}}
         line["bf16_speedup_vs_fp32"] = round(f["ms"] / head["ms"], 3)
     line["roofline_all"] = rl
+    line["training_kernels"] = head["training"]
     if a.calib_copy_mib > 0:
         import torch
         src = torch.ones(a.calib_copy_mib << 18, device="cuda")

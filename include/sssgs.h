@@ -172,6 +172,33 @@ sssgs_status sssgs_render_backward(const sssgs_gaussians *g, const sssgs_camera 
 sssgs_status sssgs_l1_loss(const float *pred, const float *target, int64_t count, float scale, float *loss_out,
                            float *dL_dpred, void *stream);
 
+/* Image loss of the training objective (Appendix "Losses"):
+     L = (1 - lambda) mean|pred - target| + lambda (1 - mean SSIM(pred, target))
+   over `channels` planes of height x width floats ([C][H][W], device), with the
+   paper's lambda = 0.2 passed as lambda_dssim.  SSIM: local statistics under an
+   11x11 Gaussian window (sigma 1.5, normalised), images extended with zeros
+   outside their border, C1 = 0.01^2, C2 = 0.03^2 (data range 1).  Writes
+   *loss_out (device, overwritten) and, when dL_dpred is not NULL,
+   dL/dpred ([C][H][W], device, overwritten; sign(0) = 0 in the L1 part).
+   `workspace` (device, caller-owned) holds at least
+   sssgs_image_loss_workspace_bytes(channels, height, width) bytes.
+   Deterministic: fixed summation order.  Errors: INVALID_ARG for
+   non-positive sizes, null pointers or a short workspace. */
+size_t sssgs_image_loss_workspace_bytes(int32_t channels, int32_t height, int32_t width);
+sssgs_status sssgs_image_loss(const float *pred, const float *target, int32_t channels, int32_t height,
+                              int32_t width, float lambda_dssim, void *workspace, size_t workspace_bytes,
+                              float *loss_out, float *dL_dpred, void *stream);
+
+/* One Adam update (Appendix "Training": Adam with its default parameters) of
+   `count` float parameters in place, all device arrays:
+     m = beta1 m + (1 - beta1) g;  v = beta2 v + (1 - beta2) g^2;
+     param -= lr (m / (1 - beta1^step)) / (sqrt(v / (1 - beta2^step)) + eps)
+   with step >= 1 the index of this update.  The learning-rate schedule is the
+   caller's (lr is passed per call).  Errors: INVALID_ARG for count < 0, step < 1
+   or null pointers. */
+sssgs_status sssgs_adam_step(float *param, const float *grad, float *m, float *v, int64_t count, float lr,
+                             float beta1, float beta2, float eps, int32_t step, void *stream);
+
 /* Device-side status of the last forward on this workspace (sizes as passed
    to sssgs_workspace_bytes): flags bit 0 set = instance capacity overflowed;
    num_instances = tiles touched by all Gaussians.  Waits for the stream. */

@@ -532,6 +532,31 @@ sssgs_status sssgs_l1_loss(const float *pred, const float *target, int64_t count
   return check_hip("l1 launch");
 }
 
+size_t sssgs_image_loss_workspace_bytes(int32_t channels, int32_t height, int32_t width) {
+  if (channels <= 0 || height <= 0 || width <= 0) return 0;
+  return image_loss_workspace_bytes(channels, height, width);
+}
+
+sssgs_status sssgs_image_loss(const float *pred, const float *target, int32_t channels, int32_t height,
+                              int32_t width, float lambda_dssim, void *ws, size_t ws_bytes, float *loss_out,
+                              float *dL_dpred, void *stream) {
+  if (channels <= 0 || height <= 0 || width <= 0) return fail(SSSGS_ERR_INVALID_ARG, "bad image size");
+  if (!pred || !target || !loss_out || !ws) return fail(SSSGS_ERR_INVALID_ARG, "null pointer");
+  if (ws_bytes < image_loss_workspace_bytes(channels, height, width))
+    return fail(SSSGS_ERR_INVALID_ARG, "workspace too small");
+  launch_image_loss(pred, target, channels, height, width, lambda_dssim, ws, loss_out, dL_dpred,
+                    (hipStream_t)stream);
+  return check_hip("image loss launch");
+}
+
+sssgs_status sssgs_adam_step(float *param, const float *grad, float *m, float *v, int64_t count, float lr,
+                             float beta1, float beta2, float eps, int32_t step, void *stream) {
+  if (count < 0 || step < 1) return fail(SSSGS_ERR_INVALID_ARG, "count < 0 or step < 1");
+  if (count > 0 && (!param || !grad || !m || !v)) return fail(SSSGS_ERR_INVALID_ARG, "null pointer");
+  launch_adam(param, grad, m, v, count, lr, beta1, beta2, eps, step, (hipStream_t)stream);
+  return check_hip("adam launch");
+}
+
 sssgs_status sssgs_workspace_status(const void *ws, int32_t n, int32_t width, int32_t height, int32_t feat_dim,
                                     int32_t mlp_width, int64_t cap, void *stream, int32_t *flags_out,
                                     int64_t *num_out) {

@@ -56,6 +56,11 @@ size_t prep_weight_bytes(int width, int in_pad);
 void launch_reduce_partials(const float *partials, int nparts, int nparams, float *scratch, float *out,
                             int accumulate, hipStream_t st);
 int reduce_scratch_floats(int nparams);
+size_t image_loss_workspace_bytes(int C, int H, int W);
+void launch_image_loss(const float *x, const float *y, int C, int H, int W, float lam, void *ws, float *loss,
+                       float *grad, hipStream_t st);
+void launch_adam(float *p, const float *g, float *m, float *v, int64_t n, float lr, float b1, float b2, float eps,
+                 int step, hipStream_t st);
 void launch_l1_loss(const float *pred, const float *target, int64_t count, float scale, float *loss_out,
                     float *grad, hipStream_t st);
 void launch_zero_f32(float *p, size_t n, hipStream_t st);

@@ -62,7 +62,7 @@ class Layout(ct.Structure):
 EXPORTS = ("sssgs_mlp_param_count", "sssgs_workspace_bytes", "sssgs_render_forward", "sssgs_render_backward",
            "sssgs_l1_loss", "sssgs_workspace_status", "sssgs_workspace_layout", "sssgs_status_string",
            "sssgs_last_error", "sssgs_timing_enable", "sssgs_timing_read", "sssgs_timing_stages",
-           "sssgs_timing_stage_name")
+           "sssgs_timing_stage_name", "sssgs_image_loss_workspace_bytes", "sssgs_image_loss", "sssgs_adam_step")
 
 
 def load_library(path: str = LIB_PATH):
@@ -86,6 +86,14 @@ def load_library(path: str = LIB_PATH):
     L.sssgs_l1_loss.restype = ct.c_int
     L.sssgs_l1_loss.argtypes = [ct.c_void_p, ct.c_void_p, ct.c_int64, ct.c_float, ct.c_void_p, ct.c_void_p,
                                 ct.c_void_p]
+    L.sssgs_image_loss_workspace_bytes.restype = ct.c_size_t
+    L.sssgs_image_loss_workspace_bytes.argtypes = [ct.c_int32] * 3
+    L.sssgs_image_loss.restype = ct.c_int
+    L.sssgs_image_loss.argtypes = [ct.c_void_p, ct.c_void_p, ct.c_int32, ct.c_int32, ct.c_int32, ct.c_float,
+                                   ct.c_void_p, ct.c_size_t, ct.c_void_p, ct.c_void_p, ct.c_void_p]
+    L.sssgs_adam_step.restype = ct.c_int
+    L.sssgs_adam_step.argtypes = [ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_int64, ct.c_float,
+                                  ct.c_float, ct.c_float, ct.c_float, ct.c_int32, ct.c_void_p]
     L.sssgs_workspace_status.restype = ct.c_int
     L.sssgs_workspace_status.argtypes = [ct.c_void_p] + [ct.c_int32] * 5 + [ct.c_int64, ct.c_void_p,
                                                                            ct.POINTER(ct.c_int32),
@@ -175,6 +183,45 @@ def sssgs_render_backward(g, cam, light, mlp, opt, workspace, ws_bytes, capacity
 
 def sssgs_l1_loss(pred, target, count, scale, loss_out, grad, stream=None):
     return lib().sssgs_l1_loss(pred, target, count, scale, loss_out, grad, stream)
+
+
+def sssgs_image_loss_workspace_bytes(channels, height, width) -> int:
+    return int(lib().sssgs_image_loss_workspace_bytes(channels, height, width))
+
+
+def sssgs_image_loss(pred, target, channels, height, width, lambda_dssim, workspace, ws_bytes, loss_out, grad,
+                     stream=None):
+    return lib().sssgs_image_loss(pred, target, channels, height, width, lambda_dssim, workspace, ws_bytes,
+                                  loss_out, grad, stream)
+
+
+def sssgs_adam_step(param, grad, m, v, count, lr, beta1, beta2, eps, step, stream=None):
+    return lib().sssgs_adam_step(param, grad, m, v, count, lr, beta1, beta2, eps, step, stream)
+
+
+def image_loss(pred: torch.Tensor, target: torch.Tensor, lambda_dssim: float = 0.2, want_grad: bool = True):
+    """(1 - lambda) L1 + lambda (1 - SSIM) of [C][H][W] float32 device images; returns (loss[1], dL/dpred)."""
+    C, H, W = pred.shape
+    nb = sssgs_image_loss_workspace_bytes(C, H, W)
+    ws = torch.empty(nb, dtype=torch.uint8, device=pred.device)
+    loss = torch.empty(1, dtype=torch.float32, device=pred.device)
+    grad = torch.empty_like(pred) if want_grad else None
+    _check(sssgs_image_loss(_ptr(pred), _ptr(target), C, H, W, lambda_dssim, ct.c_void_p(ws.data_ptr()), nb,
+                            _ptr(loss), _ptr(grad), _stream()))
+    return loss, grad
+
+
+def adam_step(param: torch.Tensor, grad: torch.Tensor, m: torch.Tensor, v: torch.Tensor, step: int, lr: float,
+              beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-8):
+    """In-place Adam update of a float32 device tensor (moments m, v of the same shape)."""
+    _check(sssgs_adam_step(_ptr(param), _ptr(grad), _ptr(m), _ptr(v), param.numel(), lr, beta1, beta2, eps, step,
+                           _stream()))
+
+
+def lr_schedule(step: int, base: float = 1e-3, gamma: float = 0.99, every: int = 1000) -> float:
+    """Learning rate of the network at a step: base lr 0.001 decayed by 0.99 every 1000 steps
+    (Appendix "Training")."""
+    return base * gamma ** (step // every)
 
 
 def sssgs_workspace_status(workspace, n, width, height, feat_dim, mlp_width, capacity, stream=None):

@@ -91,3 +91,15 @@ def test_invalid_arguments_are_rejected_before_any_launch(B):
     assert st == B.ERR_INVALID_ARG
     assert B.lib().sssgs_status_string(B.ERR_CAPACITY).decode() == "instance capacity exceeded"
     assert L.sssgs_l1_loss(None, None, -1, 1.0, None, None, None) == B.ERR_INVALID_ARG
+
+
+def test_image_loss_and_adam_argument_checks(B):
+    L = B.lib()
+    assert B.sssgs_image_loss_workspace_bytes(3, 16, 16) > 0
+    assert B.sssgs_image_loss_workspace_bytes(0, 16, 16) == 0
+    buf = ct.c_void_p(1)
+    st = L.sssgs_image_loss(buf, buf, 3, 16, 16, 0.2, buf, 8, buf, None, None)      # workspace too small
+    assert st == B.ERR_INVALID_ARG
+    st = L.sssgs_image_loss(buf, buf, 3, 0, 16, 0.2, buf, 1 << 20, buf, None, None)  # bad size
+    assert st == B.ERR_INVALID_ARG
+    assert L.sssgs_adam_step(buf, buf, buf, buf, 10, 1e-3, 0.9, 0.999, 1e-8, 0, None) == B.ERR_INVALID_ARG
