@@ -191,8 +191,11 @@ def roofline(r):
     # backward: records + index per processed instance, dG + dT + T + n_contrib read, per-Gaussian grads written
     bwd_bytes = r["bwd_records"] * (4 * RS + 4) + HW * 4 * (C + 3) + r["n"] * 4 * (6 + C)
     # network multiply-adds per pixel (58 inputs, three hidden layers of 64, 6 outputs): forward once;
-    # backward = input gradients + weight gradients + the forward recomputed (3x)
+    # backward = the forward recomputed + input gradients + weight gradients (3x).  With the BF16
+    # width-64 network the backward is two kernels: shading backward (recompute + input
+    # gradients, 2x) and the weight-gradient kernel (1x; it recomputes what it needs on top).
     net_flop = 2 * (58 * 64 + 2 * 64 * 64 + 64 * 6)
+    split = r["stages"].get("mlp_wgrad", (0.0, 0))[0] > 0
     out = {}
     traffic = measured_traffic()
     for name, nbytes in (("composite_fwd", fwd_bytes), ("composite_bwd", bwd_bytes)):
@@ -203,7 +206,10 @@ def roofline(r):
                          "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": traffic.get(name), "kernel": name,
                          "bytes_per_launch": int(nbytes), "ms_per_launch": round(t, 4)}
     peak = BF16_MFMA_TFLOPS if r["precision"] == "bf16" else FP32_MFMA_TFLOPS
-    for name, flop in (("shade_fwd", HW * net_flop), ("shade_bwd", 3 * HW * net_flop)):
+    flops = [("shade_fwd", HW * net_flop), ("shade_bwd", (2 if split else 3) * HW * net_flop)]
+    if split:
+        flops.append(("mlp_wgrad", HW * net_flop))
+    for name, flop in flops:
         t = r["stages"].get(name, (0.0, 0))[0]
         if t > 0:
             tf = flop / (t * 1e-3) / 1e12

@@ -19,11 +19,11 @@ thread_local std::string g_last_error;
 // ---- optional per-stage timing with HIP events on the caller's stream
 enum Stage {
   kStProject = 0, kStSortDepth, kStExpand, kStSortTiles, kStRanges, kStCompositeFwd, kStShadeFwd,
-  kStShadeBwd, kStMlpReduce, kStCompositeBwd, kStProjectBwd, kStCount
+  kStShadeBwd, kStMlpWgrad, kStMlpReduce, kStCompositeBwd, kStProjectBwd, kStCount
 };
 const char *kStageNames[kStCount] = {"project_fwd",   "sort_depth",    "expand",        "sort_tiles",
                                      "tile_ranges",   "composite_fwd", "shade_fwd",     "shade_bwd",
-                                     "mlp_reduce",    "composite_bwd", "project_bwd"};
+                                     "mlp_wgrad",     "mlp_reduce",    "composite_bwd", "project_bwd"};
 struct TimerRec {
   int stage;
   hipEvent_t a, b;
@@ -87,7 +87,7 @@ int in_pad_of(int in_dim) { return (in_dim + 31) / 32 * 32; }
 struct Layout {
   size_t records, depth_keys, vals_a, keys_b, vals_b, keys_a, rects, radii, boxes, tt, offsets, partials, hist;
   size_t ik_a, iv_a, ik_b, iv_b, ranges, t_final, n_contrib, status, m_total;
-  size_t gacc, dG, dT, wops, tops, mlp_part, mlp_mid;
+  size_t gacc, dG, dT, wops, tops, mlp_part, mlp_mid, rec_x, rec_o;
   size_t total;
   int C, RS, GS, TX, TY, T;
   uint32_t nb_g, nb_i;
@@ -153,6 +153,11 @@ bool make_layout(int32_t n, int32_t W, int32_t H, int32_t F, int32_t mlp_width, 
   L.tops = take(mlp_width ? prep_weight_bytes(mlp_width, in_pad) : 0);
   L.mlp_part = take(mlp_width ? (size_t)L.shade_parts * L.nparams * 4 : 0);
   L.mlp_mid = take(mlp_width ? (size_t)reduce_scratch_floats(L.nparams) * 4 : 0);
+  // strip records of the split shading backward (BF16 network, width 64, input width 64)
+  const bool split = mlp_width == 64 && in_pad == 64;
+  const size_t nstrips = (size_t)L.T * 4;
+  L.rec_x = take(split ? nstrips * 64 * 64 * 2 : 0);
+  L.rec_o = take(split ? nstrips * 64 * 8 * 2 : 0);
   L.total = p;
   return true;
 }
@@ -493,15 +498,33 @@ sssgs_status sssgs_render_backward(const sssgs_gaussians *g, const sssgs_camera 
                         at<void>(ws, L.tops), st);
   }
   const int nblk = L.shade_bwd_blocks;
-  {
+  const int ip = net ? in_pad_of(mlp->in_dim) : 0;
+  // BF16 width-64 network: shading backward and weight gradients as two kernels
+  const bool split = net == 2 && width == 64 && ip == 64;
+  int parts = 0;
+  if (split) {
+    __bf16 *rx = at<__bf16>(ws, L.rec_x), *ro = at<__bf16>(ws, L.rec_o);
+    {
+      Scope sc(kStShadeBwd, st);
+      switch (g->feat_dim) {
+        case 0: launch_shade_bwd_split_t<0, 64>(sa, rx, ro, st); break;
+        case 8: launch_shade_bwd_split_t<8, 64>(sa, rx, ro, st); break;
+        default: launch_shade_bwd_split_t<16, 64>(sa, rx, ro, st); break;
+      }
+    }
+    if (dL_dmlp) {
+      Scope sc(kStMlpWgrad, st);
+      launch_mlp_wgrad(sa.wops, sa.tops, sa.params, rx, ro, L.T * 4, sa.mlp_partials, st);
+      parts = mlp_wgrad_grid(L.T * 4);
+    }
+  } else {
     Scope sc(kStShadeBwd, st);
     if (!shade_dispatch<true>(g->feat_dim, net, width, sa, nblk, st))
       return fail(SSSGS_ERR_UNSUPPORTED, "no shading kernel for this configuration");
+    if (net) parts = shade_bwd_grid(net, width, ip, L.T, nblk);
   }
   if (net && dL_dmlp) {
     Scope sc(kStMlpReduce, st);
-    const int ip = in_pad_of(mlp->in_dim);
-    const int parts = shade_bwd_grid(net, width, ip, L.T, nblk);
     launch_reduce_partials(sa.mlp_partials, parts, L.nparams, at<float>(ws, L.mlp_mid), dL_dmlp,
                            opt->accumulate_grads, st);
   }

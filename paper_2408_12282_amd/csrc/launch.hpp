@@ -48,6 +48,14 @@ template <int F, int NET, int WIDTH, int IN_PAD>
 void launch_shade_bwd_t(const ShadeArgs &a, int nblocks, hipStream_t st);
 int shade_bwd_waves(int net, int width, int in_pad);
 int shade_bwd_grid(int net, int width, int in_pad, int tiles, int max_blocks);
+// split form for the BF16 width-64 network: shading backward writing per-strip
+// records (one 64-thread workgroup per strip), then the weight-gradient kernel
+template <int F, int IN_PAD>
+void launch_shade_bwd_split_t(const ShadeArgs &a, __bf16 *rec_x, __bf16 *rec_o, hipStream_t st);
+constexpr int kWgradMaxBlocks = 256;
+int mlp_wgrad_grid(int nstrips);
+void launch_mlp_wgrad(const void *wops, const void *tops, const float *params, const __bf16 *rec_x,
+                      const __bf16 *rec_o, int nstrips, float *partials, hipStream_t st);
 
 // network weight preparation and gradient reduction (mlp_prep.hip)
 void launch_prep_weights(int net, int width, int in_pad, const float *params, void *wops, void *tops,

@@ -1,0 +1,99 @@
+// net_bwd.hpp -- wave-level pieces of the network backward (Sec. 3.2,
+// Eq. 6) shared by the shading backward and the weight-gradient kernel:
+// layer products on the matrix cores, ReLU masks, and the packing of a
+// masked gradient into the next product's B operands.
+#pragma once
+#include "shade_common.hpp"
+
+namespace sssgs {
+
+// B-operand packing of a masked upstream gradient (D layout -> permuted K).
+template <class M, int MB>
+__device__ __forceinline__ void grad_to_ops(const f32x4 (&d)[MB][4], typename M::Op (&B)[(MB * 16) / M::KS][4]) {
+  constexpr int KSN = (MB * 16) / M::KS;
+#pragma unroll
+  for (int ks = 0; ks < KSN; ks++)
+#pragma unroll
+    for (int nb = 0; nb < 4; nb++) {
+      if constexpr (M::KPL == 8) {
+        bf16x8 o;
+#pragma unroll
+        for (int j = 0; j < 8; j++) o[j] = (__bf16)d[2 * ks + (j >> 2)][nb][j & 3];
+        B[ks][nb] = o;
+      } else {
+        B[ks][nb] = d[ks >> 2][nb][ks & 3];
+      }
+    }
+}
+
+// One forward layer from B operands H (K = WIDTH) to accumulators.
+template <class M, int MB, int KSN>
+__device__ __forceinline__ void layer_mma(const typename M::Op *__restrict__ w, const typename M::Op (&H)[KSN][4],
+                                          f32x4 (&acc)[MB][4], int lane) {
+#pragma unroll
+  for (int mb = 0; mb < MB; mb++)
+#pragma unroll
+    for (int nb = 0; nb < 4; nb++) acc[mb][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int ks = 0; ks < KSN; ks++)
+#pragma unroll
+    for (int mb = 0; mb < MB; mb++) {
+      const typename M::Op a = w[(mb * KSN + ks) * 64 + lane];
+#pragma unroll
+      for (int nb = 0; nb < 4; nb++) acc[mb][nb] = M::mma(a, H[ks][nb], acc[mb][nb]);
+    }
+}
+
+template <class M, int MB, int KS0>
+__device__ __forceinline__ void layer0_mma(const typename M::Op *__restrict__ w, const typename M::Elem *xs, int XS,
+                                           f32x4 (&acc)[MB][4], int lane) {
+  const int g = lane >> 4, col = lane & 15;
+#pragma unroll
+  for (int mb = 0; mb < MB; mb++)
+#pragma unroll
+    for (int nb = 0; nb < 4; nb++) acc[mb][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int ks = 0; ks < KS0; ks++) {
+    typename M::Op B[4];
+#pragma unroll
+    for (int nb = 0; nb < 4; nb++) B[nb] = load_op_lds<M>(xs + (16 * nb + col) * XS + ks * M::KS + g * M::KPL);
+#pragma unroll
+    for (int mb = 0; mb < MB; mb++) {
+      const typename M::Op a = w[(mb * KS0 + ks) * 64 + lane];
+#pragma unroll
+      for (int nb = 0; nb < 4; nb++) acc[mb][nb] = M::mma(a, B[nb], acc[mb][nb]);
+    }
+  }
+}
+
+// ReLU masks of one layer's outputs in D layout, one bit per (mb, nb, j).
+template <int MB>
+struct Mask {
+  uint32_t w[(MB * 16 + 31) / 32];
+  __device__ __forceinline__ void set_from(const f32x4 (&acc)[MB][4], const float *bias, int g) {
+#pragma unroll
+    for (int k = 0; k < (MB * 16 + 31) / 32; k++) w[k] = 0u;
+#pragma unroll
+    for (int mb = 0; mb < MB; mb++)
+#pragma unroll
+      for (int nb = 0; nb < 4; nb++)
+#pragma unroll
+        for (int j = 0; j < 4; j++) {
+          const int b = mb * 16 + nb * 4 + j;
+          if (acc[mb][nb][j] + bias[16 * mb + 4 * g + j] > 0.f) w[b >> 5] |= 1u << (b & 31);
+        }
+  }
+  __device__ __forceinline__ void apply(f32x4 (&d)[MB][4]) const {
+#pragma unroll
+    for (int mb = 0; mb < MB; mb++)
+#pragma unroll
+      for (int nb = 0; nb < 4; nb++)
+#pragma unroll
+        for (int j = 0; j < 4; j++) {
+          const int b = mb * 16 + nb * 4 + j;
+          if (!((w[b >> 5] >> (b & 31)) & 1u)) d[mb][nb][j] = 0.f;
+        }
+  }
+};
+
+}  // namespace sssgs

@@ -12,75 +12,9 @@
 // no-return float atomics, so no wave stalls on a read-modify-write, and
 // every address is written by one wave only, so the sums are deterministic.
 #include "launch.hpp"
-#include "shade_common.hpp"
+#include "net_bwd.hpp"
 
 namespace sssgs {
-
-// B-operand packing of a masked upstream gradient (D layout -> permuted K).
-template <class M, int MB>
-__device__ __forceinline__ void grad_to_ops(const f32x4 (&d)[MB][4], typename M::Op (&B)[(MB * 16) / M::KS][4]) {
-  constexpr int KSN = (MB * 16) / M::KS;
-#pragma unroll
-  for (int ks = 0; ks < KSN; ks++)
-#pragma unroll
-    for (int nb = 0; nb < 4; nb++) {
-      if constexpr (M::KPL == 8) {
-        bf16x8 o;
-#pragma unroll
-        for (int j = 0; j < 8; j++) o[j] = (__bf16)d[2 * ks + (j >> 2)][nb][j & 3];
-        B[ks][nb] = o;
-      } else {
-        B[ks][nb] = d[ks >> 2][nb][ks & 3];
-      }
-    }
-}
-
-// Activation value held in op H[ks][nb] for D-layout position (mb, j).
-template <class M, int KSN>
-__device__ __forceinline__ float act_at(const typename M::Op (&H)[KSN][4], int mb, int nb, int j) {
-  if constexpr (M::KPL == 8) return (float)H[mb >> 1][nb][4 * (mb & 1) + j];
-  else return H[4 * mb + j][nb];
-}
-
-// One forward layer from B operands H (K = WIDTH) to accumulators.
-template <class M, int MB, int KSN>
-__device__ __forceinline__ void layer_mma(const typename M::Op *__restrict__ w, const typename M::Op (&H)[KSN][4],
-                                          f32x4 (&acc)[MB][4], int lane) {
-#pragma unroll
-  for (int mb = 0; mb < MB; mb++)
-#pragma unroll
-    for (int nb = 0; nb < 4; nb++) acc[mb][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-  for (int ks = 0; ks < KSN; ks++)
-#pragma unroll
-    for (int mb = 0; mb < MB; mb++) {
-      const typename M::Op a = w[(mb * KSN + ks) * 64 + lane];
-#pragma unroll
-      for (int nb = 0; nb < 4; nb++) acc[mb][nb] = M::mma(a, H[ks][nb], acc[mb][nb]);
-    }
-}
-
-template <class M, int MB, int KS0>
-__device__ __forceinline__ void layer0_mma(const typename M::Op *__restrict__ w, const typename M::Elem *xs, int XS,
-                                           f32x4 (&acc)[MB][4], int lane) {
-  const int g = lane >> 4, col = lane & 15;
-#pragma unroll
-  for (int mb = 0; mb < MB; mb++)
-#pragma unroll
-    for (int nb = 0; nb < 4; nb++) acc[mb][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-  for (int ks = 0; ks < KS0; ks++) {
-    typename M::Op B[4];
-#pragma unroll
-    for (int nb = 0; nb < 4; nb++) B[nb] = load_op_lds<M>(xs + (16 * nb + col) * XS + ks * M::KS + g * M::KPL);
-#pragma unroll
-    for (int mb = 0; mb < MB; mb++) {
-      const typename M::Op a = w[(mb * KS0 + ks) * 64 + lane];
-#pragma unroll
-      for (int nb = 0; nb < 4; nb++) acc[mb][nb] = M::mma(a, B[nb], acc[mb][nb]);
-    }
-  }
-}
 
 // Staging of the weight-gradient operands.  For BF16 (8 pixels per lane and
 // k-step) both factors are stored feature-major [feat][px]; for FP32 (one
@@ -336,36 +270,6 @@ template <int NET, int WIDTH, int IN_PAD> struct BwdWaves {
 int shade_bwd_waves(int net, int width, int in_pad) {
   return net == 0 ? 4 : ((net == 2 && width == 64 && in_pad == 64) ? 4 : 2);
 }
-
-// ReLU masks of one layer's outputs in D layout, one bit per (mb, nb, j).
-template <int MB>
-struct Mask {
-  uint32_t w[(MB * 16 + 31) / 32];
-  __device__ __forceinline__ void set_from(const f32x4 (&acc)[MB][4], const float *bias, int g) {
-#pragma unroll
-    for (int k = 0; k < (MB * 16 + 31) / 32; k++) w[k] = 0u;
-#pragma unroll
-    for (int mb = 0; mb < MB; mb++)
-#pragma unroll
-      for (int nb = 0; nb < 4; nb++)
-#pragma unroll
-        for (int j = 0; j < 4; j++) {
-          const int b = mb * 16 + nb * 4 + j;
-          if (acc[mb][nb][j] + bias[16 * mb + 4 * g + j] > 0.f) w[b >> 5] |= 1u << (b & 31);
-        }
-  }
-  __device__ __forceinline__ void apply(f32x4 (&d)[MB][4]) const {
-#pragma unroll
-    for (int mb = 0; mb < MB; mb++)
-#pragma unroll
-      for (int nb = 0; nb < 4; nb++)
-#pragma unroll
-        for (int j = 0; j < 4; j++) {
-          const int b = mb * 16 + nb * 4 + j;
-          if (!((w[b >> 5] >> (b & 31)) & 1u)) d[mb][nb][j] = 0.f;
-        }
-  }
-};
 
 // Per-pixel inputs of the shading backward (reloaded in each per-pixel phase
 // instead of being kept live across the network phases).
@@ -628,6 +532,180 @@ __global__ __launch_bounds__((BwdWaves<NET, WIDTH, IN_PAD>::value * 64)) void sh
     }
   }
 }
+
+// ---------------------------------------------------------------- split form
+//
+// For the BF16 width-64 network the weight gradients are left to a kernel of
+// their own (mlp_wgrad.hip).  This kernel then only needs, per wave, the input
+// rows until layer 0 has consumed them, dL/d(input) afterwards (same LDS),
+// and the network outputs with their gradients: about 20 KB, and no
+// workgroup-wide exchange, so each wave shades one strip on its own and two
+// waves fit per SIMD.  For the weight-gradient kernel it leaves a record per
+// strip: the BF16 network input rows as layer 0 reads them ([64][IN_PAD]) and
+// the BF16 gradients of the six network outputs as the transposed output
+// layer reads them ([64][8], two zero pads).
+template <int IN_PAD>
+struct SplitLds {
+  static constexpr int XS = IN_PAD + XPad<MmaBF16>::value;  // bf16 input row stride
+  static constexpr int DS = IN_PAD + 1;                     // fp32 input-gradient row stride
+  static constexpr int IO = 13;  // floats per pixel: 6 outputs, 6 output gradients, pad
+  static constexpr int RB = (64 * XS * 2 > 64 * DS * 4) ? 64 * XS * 2 : 64 * DS * 4;
+  static constexpr int BYTES = RB + 64 * IO * 4;
+};
+
+template <int F, int IN_PAD>
+__global__ __launch_bounds__(64, 2) void shade_bwd_split_kernel(ShadeArgs A, __bf16 *__restrict__ rec_x,
+                                                                __bf16 *__restrict__ rec_o) {
+  using M = MmaBF16;
+  using Op = bf16x8;
+  using NS = NetShape<M, 64, IN_PAD>;
+  using PO = ParamOffsets<64, IN_PAD>;
+  using SL = SplitLds<IN_PAD>;
+  constexpr int C = kChFeat + F;
+  constexpr int MB = NS::MB;
+  __shared__ __attribute__((aligned(16))) char lds[SL::BYTES];
+  __bf16 *xs = reinterpret_cast<__bf16 *>(lds);
+  float *dxin = reinterpret_cast<float *>(lds);  // after layer 0 of the forward has read xs
+  float *io = reinterpret_cast<float *>(lds + SL::RB);
+  const int lane = threadIdx.x;
+  const int g = lane >> 4, col = lane & 15;
+  const int strip = blockIdx.x;
+  const int tile = strip >> 2, sub = strip & 3;
+  const int tx = tile % A.cam.TX, ty = tile / A.cam.TX;
+  const int px = tx * kTile + col, py = ty * kTile + 4 * sub + g;
+  const bool inside = px < A.cam.W && py < A.cam.H;
+  const size_t HW = (size_t)A.cam.W * A.cam.H;
+  const size_t pix = inside ? (size_t)py * A.cam.W + px : 0;
+  const float uc = (float)px + 0.5f, vc = (float)py + 0.5f;
+  const Op *__restrict__ wops = reinterpret_cast<const Op *>(A.wops);
+  const Op *__restrict__ tops = reinterpret_cast<const Op *>(A.tops);
+  const size_t rrow = (size_t)strip * 64 + lane;
+  // ---- A: network input row (LDS and record)
+  {
+    float gb[C], T, gL[3];
+    load_pixel<C>(A, inside, pix, HW, gb, T, gL);
+    PixShade S;
+    shade_geometry<C>(gb, T, uc, vc, A.cam, A.light, true, S);
+    build_net_input<F, IN_PAD, M>(gb, S, xs + lane * SL::XS);
+    const uint4 *src = reinterpret_cast<const uint4 *>(xs + lane * SL::XS);
+    uint4 *dst = reinterpret_cast<uint4 *>(rec_x + rrow * IN_PAD);
+#pragma unroll
+    for (int k = 0; k < IN_PAD / 8; k++) dst[k] = src[k];
+  }
+  __syncthreads();
+  // ---- B: network forward: ReLU masks and outputs
+  Mask<MB> m1, m2, m3;
+  {
+    f32x4 acc[MB][4];
+    Op H[NS::KSH][4];
+    layer0_mma<M, MB, NS::KS0>(wops, xs, SL::XS, acc, lane);
+    m1.set_from(acc, A.params + PO::b(0), g);
+    acc_to_ops<M, MB>(acc, A.params + PO::b(0), g, H);
+    layer_mma<M, MB, NS::KSH>(wops + NS::L0, H, acc, lane);
+    m2.set_from(acc, A.params + PO::b(1), g);
+    acc_to_ops<M, MB>(acc, A.params + PO::b(1), g, H);
+    layer_mma<M, MB, NS::KSH>(wops + NS::L0 + NS::LH, H, acc, lane);
+    m3.set_from(acc, A.params + PO::b(2), g);
+    acc_to_ops<M, MB>(acc, A.params + PO::b(2), g, H);
+    f32x4 oacc[1][4];
+    layer_mma<M, 1, NS::KSH>(wops + NS::L0 + 2 * NS::LH, H, oacc, lane);
+    if (g < 2)
+#pragma unroll
+      for (int nb = 0; nb < 4; nb++)
+#pragma unroll
+        for (int j = 0; j < 4; j++) {
+          const int o = 4 * g + j;
+          if (o < 6) io[(16 * nb + col) * SL::IO + o] = oacc[0][nb][j] + A.params[PO::b(3) + o];
+        }
+  }
+  __syncthreads();
+  // ---- C: Eq. 7 and the gradients of the network outputs
+  {
+    float gb[C], T, gL[3];
+    load_pixel<C>(A, inside, pix, HW, gb, T, gL);
+    PixShade S;
+    shade_geometry<C>(gb, T, uc, vc, A.cam, A.light, true, S);
+    if (S.bg) gL[0] = gL[1] = gL[2] = 0.f;
+    float o[6];
+    for (int k = 0; k < 6; k++) o[k] = io[lane * SL::IO + k];
+    combine_net(S, gb[kChSss], o);
+    const float sss = gb[kChSss] * S.ia;
+    float d[8];
+    for (int c = 0; c < 3; c++) {
+      const float gLo = S.a * gL[c];
+      const float dLin = gLo * (1.f - sss) * (S.fs[c] + S.fd[c]) * S.cosI;
+      d[c] = o[c] > 0.f ? dLin : 0.f;
+      d[3 + c] = gLo * sss * S.Lsss[c] * (1.f - S.Lsss[c]);
+    }
+    d[6] = d[7] = 0.f;
+    bf16x8 r;
+#pragma unroll
+    for (int k = 0; k < 8; k++) {
+      if (k < 6) io[lane * SL::IO + 6 + k] = d[k];
+      r[k] = (__bf16)d[k];
+    }
+    *reinterpret_cast<bf16x8 *>(rec_o + rrow * 8) = r;
+  }
+  __syncthreads();
+  // ---- D: backward through the network to its inputs
+  {
+    Op Bo[NS::KT_O][4];
+#pragma unroll
+    for (int nb = 0; nb < 4; nb++) {
+      bf16x8 v;
+#pragma unroll
+      for (int j = 0; j < 8; j++) {
+        const int o = 4 * g + j;
+        v[j] = (__bf16)((j < 4 && o < 6) ? io[(16 * nb + col) * SL::IO + 6 + o] : 0.f);
+      }
+      Bo[0][nb] = v;
+    }
+    f32x4 dH[MB][4];
+    Op Bd[NS::KSH][4];
+    layer_mma<M, MB, NS::KT_O>(tops + NS::T0 + 2 * NS::TH, Bo, dH, lane);
+    m3.apply(dH);
+    grad_to_ops<M, MB>(dH, Bd);
+    layer_mma<M, MB, NS::KT_H>(tops + NS::T0 + NS::TH, Bd, dH, lane);
+    m2.apply(dH);
+    grad_to_ops<M, MB>(dH, Bd);
+    layer_mma<M, MB, NS::KT_H>(tops + NS::T0, Bd, dH, lane);
+    m1.apply(dH);
+    grad_to_ops<M, MB>(dH, Bd);
+    f32x4 dX[NS::MB0][4];
+    layer_mma<M, NS::MB0, NS::KT_H>(tops, Bd, dX, lane);
+#pragma unroll
+    for (int mb = 0; mb < NS::MB0; mb++)
+#pragma unroll
+      for (int nb = 0; nb < 4; nb++)
+#pragma unroll
+        for (int j = 0; j < 4; j++) dxin[(16 * nb + col) * SL::DS + 16 * mb + 4 * g + j] = dX[mb][nb][j];
+  }
+  __syncthreads();
+  // ---- E: per pixel backward of geometry, BRDF and Eq. 7
+  {
+    float gb[C], T, gL[3], dgbar[C];
+    load_pixel<C>(A, inside, pix, HW, gb, T, gL);
+    PixShade S;
+    shade_geometry<C>(gb, T, uc, vc, A.cam, A.light, true, S);
+    if (S.bg) gL[0] = gL[1] = gL[2] = 0.f;
+    float o[6];
+    for (int k = 0; k < 6; k++) o[k] = io[lane * SL::IO + k];
+    combine_net(S, gb[kChSss], o);
+    const float dA = shade_pixel_bwd<C, F, true>(S, gb, gL, A.light, dxin + lane * SL::DS, dgbar);
+    write_pixel_grads<C, F>(A, inside, pix, HW, S, gb, dgbar, dA);
+  }
+}
+
+template <int F, int IN_PAD>
+void launch_shade_bwd_split_t(const ShadeArgs &a, __bf16 *rec_x, __bf16 *rec_o, hipStream_t st) {
+  const int nstrips = a.cam.TX * a.cam.TY * 4;
+  shade_bwd_split_kernel<F, IN_PAD><<<nstrips, 64, 0, st>>>(a, rec_x, rec_o);
+}
+
+template void launch_shade_bwd_split_t<0, 64>(const ShadeArgs &, __bf16 *, __bf16 *, hipStream_t);
+template void launch_shade_bwd_split_t<8, 64>(const ShadeArgs &, __bf16 *, __bf16 *, hipStream_t);
+template void launch_shade_bwd_split_t<16, 64>(const ShadeArgs &, __bf16 *, __bf16 *, hipStream_t);
+template void launch_shade_bwd_split_t<32, 96>(const ShadeArgs &, __bf16 *, __bf16 *, hipStream_t);
 
 // Workgroups of the persistent grid: every workgroup gets at least one strip.
 int shade_bwd_grid(int net, int width, int in_pad, int tiles, int max_blocks) {
