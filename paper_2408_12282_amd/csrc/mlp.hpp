@@ -17,6 +17,21 @@ namespace sssgs {
 
 typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
 typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4;
+typedef float f32x2v __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2v __attribute__((ext_vector_type(2)));
+
+// Eight floats to an eight-element BF16 operand, rounded to nearest even in
+// pairs (one v_cvt_pk_bf16_f32 per pair, no repacking of halves).
+__device__ __forceinline__ bf16x8 pack_bf16x8(float v0, float v1, float v2, float v3, float v4, float v5, float v6,
+                                              float v7) {
+  const bf16x2v p0 = __builtin_convertvector((f32x2v){v0, v1}, bf16x2v);
+  const bf16x2v p1 = __builtin_convertvector((f32x2v){v2, v3}, bf16x2v);
+  const bf16x2v p2 = __builtin_convertvector((f32x2v){v4, v5}, bf16x2v);
+  const bf16x2v p3 = __builtin_convertvector((f32x2v){v6, v7}, bf16x2v);
+  const uint4 u = make_uint4(__builtin_bit_cast(uint32_t, p0), __builtin_bit_cast(uint32_t, p1),
+                             __builtin_bit_cast(uint32_t, p2), __builtin_bit_cast(uint32_t, p3));
+  return __builtin_bit_cast(bf16x8, u);
+}
 
 struct MmaF32 {
   static constexpr int KS = 4;   // K per instruction

@@ -51,13 +51,7 @@ __device__ __forceinline__ f32x4 turn(s16x4 a, s16x4 eye) {
 // Operand with pixels along K from two pixel-row blocks: slot j of lane
 // (f, g) is pixel 4g + (j & 3) of block 2kk + (j >> 2).
 __device__ __forceinline__ bf16x8 pack_px(const f32x4 &lo, const f32x4 &hi) {
-  bf16x8 o;
-#pragma unroll
-  for (int j = 0; j < 4; j++) {
-    o[j] = (__bf16)lo[j];
-    o[4 + j] = (__bf16)hi[j];
-  }
-  return o;
+  return pack_bf16x8(lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]);
 }
 
 // The 16-feature block fb (= 2 ks + h) of features-along-K operands H[ks][nb]
@@ -94,6 +88,28 @@ __device__ __forceinline__ void layer_wgrad(const bf16x8 (&dY)[(NOB + 1) / 2][4]
 #pragma unroll
       for (int kk = 0; kk < 2; kk++) dW[ob][ib] = MmaBF16::mma(PY[ob][kk], PX[kk], dW[ob][ib]);
   }
+}
+
+// ReLU derivative from the layer's BF16 activations: zero d where the
+// activation is not positive.  The activation operands H[ks][nb] hold, in
+// slot 4 (mb & 1) + j, the feature that D-layout element (mb, nb, j) holds
+// (both use the permuted K order), so the test needs no data movement.  A
+// BF16 half is positive iff, read as the top half of a signed 32-bit word,
+// it is above zero.  (This equals the pre-activation test except for
+// pre-activations below the smallest BF16 subnormal.)
+template <int MB>
+__device__ __forceinline__ void relu_mask_from_ops(const bf16x8 (&H)[MB / 2][4], f32x4 (&d)[MB][4]) {
+#pragma unroll
+  for (int mb = 0; mb < MB; mb++)
+#pragma unroll
+    for (int nb = 0; nb < 4; nb++) {
+      const uint4 u = __builtin_bit_cast(uint4, H[mb >> 1][nb]);
+      const uint32_t w0 = (mb & 1) ? u.z : u.x, w1 = (mb & 1) ? u.w : u.y;
+      if (!((int)(w0 << 16) > 0)) d[mb][nb][0] = 0.f;
+      if (!((int)w0 > 0xFFFF)) d[mb][nb][1] = 0.f;
+      if (!((int)(w1 << 16) > 0)) d[mb][nb][2] = 0.f;
+      if (!((int)w1 > 0xFFFF)) d[mb][nb][3] = 0.f;
+    }
 }
 
 // Layer-0 B operands of a strip from its record rows ([64][stride] BF16).
@@ -229,8 +245,7 @@ __global__ __launch_bounds__(kWgradWaves * 64, 1) void mlp_wgrad_kernel(const vo
     asm volatile("v_mov_b32 %0, 0" : "=v"(z));
     const Op *wl = wl_base + z;
     const Op *tops = tops_base + z;
-    // forward: activations (H1, H2 to LDS) and ReLU masks
-    Mask<MB> m1, m2, m3;
+    // forward: activations (H1, H2 to LDS)
     Op H3[KSH][4];
     {
       Op X0[KS0][4];
@@ -238,26 +253,20 @@ __global__ __launch_bounds__(kWgradWaves * 64, 1) void mlp_wgrad_kernel(const vo
       f32x4 acc[MB][4];
       Op H[KSH][4];
 #pragma unroll
-      for (int mb = 0; mb < MB; mb++)
-#pragma unroll
-        for (int nb = 0; nb < 4; nb++) acc[mb][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
       for (int ks = 0; ks < KS0; ks++)
 #pragma unroll
         for (int mb = 0; mb < MB; mb++) {
           const Op a = wl[(mb * KS0 + ks) * 64 + lane];
 #pragma unroll
-          for (int nb = 0; nb < 4; nb++) acc[mb][nb] = M::mma(a, X0[ks][nb], acc[mb][nb]);
+          for (int nb = 0; nb < 4; nb++)
+            acc[mb][nb] = M::mma(a, X0[ks][nb], ks == 0 ? f32x4{0.f, 0.f, 0.f, 0.f} : acc[mb][nb]);
         }
-      m1.set_from(acc, bl, g);
       acc_to_ops<M, MB>(acc, bl, g, H);
       store_ops(hs, H, lane);
       layer_mma<M, MB, KSH>(wl + NS::L0, H, acc, lane);
-      m2.set_from(acc, bl + 64, g);
       acc_to_ops<M, MB>(acc, bl + 64, g, H);
       store_ops(hs + KSH * 4 * 64, H, lane);
       layer_mma<M, MB, KSH>(wl + NS::L0 + NS::LH, H, acc, lane);
-      m3.set_from(acc, bl + 128, g);
       acc_to_ops<M, MB>(acc, bl + 128, g, H3);
     }
     // output layer: dY = output gradients, X = H3 (one 16-row block, rows 0..5)
@@ -272,23 +281,23 @@ __global__ __launch_bounds__(kWgradWaves * 64, 1) void mlp_wgrad_kernel(const vo
     f32x4 dH[MB][4];
     Op Bd[KSH][4];
     layer_mma<M, MB, NS::KT_O>(tops + NS::T0 + 2 * NS::TH, Bo, dH, lane);
-    m3.apply(dH);
+    relu_mask_from_ops<MB>(H3, dH);
     grad_to_ops<M, MB>(dH, Bd);
     {
       Op X[KSH][4];
-      load_ops(hs + KSH * 4 * 64, X, lane);
+      load_ops(hs + KSH * 4 * 64, X, lane);  // H2
       layer_wgrad<MB, MB>(Bd, X, eye, dW2, db2);
+      layer_mma<M, MB, NS::KT_H>(tops + NS::T0 + NS::TH, Bd, dH, lane);
+      relu_mask_from_ops<MB>(X, dH);
     }
-    layer_mma<M, MB, NS::KT_H>(tops + NS::T0 + NS::TH, Bd, dH, lane);
-    m2.apply(dH);
     grad_to_ops<M, MB>(dH, Bd);
     {
       Op X[KSH][4];
-      load_ops(hs, X, lane);
+      load_ops(hs, X, lane);  // H1
       layer1_wgrad_lds(Bd, X, eye, d1, db1, lane);
+      layer_mma<M, MB, NS::KT_H>(tops + NS::T0, Bd, dH, lane);
+      relu_mask_from_ops<MB>(X, dH);
     }
-    layer_mma<M, MB, NS::KT_H>(tops + NS::T0, Bd, dH, lane);
-    m1.apply(dH);
     grad_to_ops<M, MB>(dH, Bd);
     {
       // the input rows again (cache-resident) rather than held across the strip

@@ -16,10 +16,8 @@ __device__ __forceinline__ void grad_to_ops(const f32x4 (&d)[MB][4], typename M:
 #pragma unroll
     for (int nb = 0; nb < 4; nb++) {
       if constexpr (M::KPL == 8) {
-        bf16x8 o;
-#pragma unroll
-        for (int j = 0; j < 8; j++) o[j] = (__bf16)d[2 * ks + (j >> 2)][nb][j & 3];
-        B[ks][nb] = o;
+        const f32x4 &lo = d[2 * ks][nb], &hi = d[2 * ks + 1][nb];
+        B[ks][nb] = pack_bf16x8(lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]);
       } else {
         B[ks][nb] = d[ks >> 2][nb][ks & 3];
       }
@@ -30,17 +28,15 @@ __device__ __forceinline__ void grad_to_ops(const f32x4 (&d)[MB][4], typename M:
 template <class M, int MB, int KSN>
 __device__ __forceinline__ void layer_mma(const typename M::Op *__restrict__ w, const typename M::Op (&H)[KSN][4],
                                           f32x4 (&acc)[MB][4], int lane) {
-#pragma unroll
-  for (int mb = 0; mb < MB; mb++)
-#pragma unroll
-    for (int nb = 0; nb < 4; nb++) acc[mb][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
+  // the first k-step takes a literal zero accumulator (an inline constant, no register clears)
 #pragma unroll
   for (int ks = 0; ks < KSN; ks++)
 #pragma unroll
     for (int mb = 0; mb < MB; mb++) {
       const typename M::Op a = w[(mb * KSN + ks) * 64 + lane];
 #pragma unroll
-      for (int nb = 0; nb < 4; nb++) acc[mb][nb] = M::mma(a, H[ks][nb], acc[mb][nb]);
+      for (int nb = 0; nb < 4; nb++)
+        acc[mb][nb] = M::mma(a, H[ks][nb], ks == 0 ? f32x4{0.f, 0.f, 0.f, 0.f} : acc[mb][nb]);
     }
 }
 
@@ -48,10 +44,6 @@ template <class M, int MB, int KS0>
 __device__ __forceinline__ void layer0_mma(const typename M::Op *__restrict__ w, const typename M::Elem *xs, int XS,
                                            f32x4 (&acc)[MB][4], int lane) {
   const int g = lane >> 4, col = lane & 15;
-#pragma unroll
-  for (int mb = 0; mb < MB; mb++)
-#pragma unroll
-    for (int nb = 0; nb < 4; nb++) acc[mb][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
   for (int ks = 0; ks < KS0; ks++) {
     typename M::Op B[4];
@@ -61,7 +53,7 @@ __device__ __forceinline__ void layer0_mma(const typename M::Op *__restrict__ w,
     for (int mb = 0; mb < MB; mb++) {
       const typename M::Op a = w[(mb * KS0 + ks) * 64 + lane];
 #pragma unroll
-      for (int nb = 0; nb < 4; nb++) acc[mb][nb] = M::mma(a, B[nb], acc[mb][nb]);
+      for (int nb = 0; nb < 4; nb++) acc[mb][nb] = M::mma(a, B[nb], ks == 0 ? f32x4{0.f, 0.f, 0.f, 0.f} : acc[mb][nb]);
     }
   }
 }

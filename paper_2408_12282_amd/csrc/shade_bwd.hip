@@ -356,8 +356,13 @@ __global__ __launch_bounds__((BwdWaves<NET, WIDTH, IN_PAD>::value * 64)) void sh
       const float dA = shade_pixel_bwd<C, F, false>(S, gb, gL, A.light, nullptr, dgbar);
       write_pixel_grads<C, F>(A, inside, pix, HW, S, gb, dgbar, dA);
     } else {
-      const Op *__restrict__ wops = reinterpret_cast<const Op *>(A.wops);
-      const Op *__restrict__ tops = reinterpret_cast<const Op *>(A.tops);
+      // Weight operands are re-read for every strip (cache hits): an opaque
+      // zero offset keeps the compiler from hoisting these loop-invariant
+      // loads out of the persistent loop, which would pin them in registers.
+      int z;
+      asm volatile("v_mov_b32 %0, 0" : "=v"(z));
+      const Op *wops = reinterpret_cast<const Op *>(A.wops) + z;
+      const Op *tops = reinterpret_cast<const Op *>(A.tops) + z;
       // ---- A: network input rows
       {
         float gb[C], T, gL[3];

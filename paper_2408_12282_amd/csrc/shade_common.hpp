@@ -183,13 +183,13 @@ __device__ __forceinline__ void acc_to_ops(const f32x4 (&acc)[MB][4], const floa
 #pragma unroll
     for (int nb = 0; nb < 4; nb++) {
       if constexpr (M::KPL == 8) {
-        bf16x8 o;
+        float v[8];
 #pragma unroll
         for (int j = 0; j < 8; j++) {
           const int mb = 2 * ks + (j >> 2), jj = j & 3;
-          o[j] = (__bf16)fmaxf(acc[mb][nb][jj] + bias[16 * mb + 4 * g + jj], 0.f);
+          v[j] = fmaxf(acc[mb][nb][jj] + bias[16 * mb + 4 * g + jj], 0.f);
         }
-        H[ks][nb] = o;
+        H[ks][nb] = pack_bf16x8(v[0], v[1], v[2], v[3], v[4], v[5], v[6], v[7]);
       } else {
         const int mb = ks >> 2, jj = ks & 3;
         H[ks][nb] = fmaxf(acc[mb][nb][jj] + bias[16 * mb + 4 * g + jj], 0.f);
@@ -212,10 +212,7 @@ __device__ __forceinline__ void net_forward_wave(const void *wops_v, const float
   f32x4 acc[MB][4];
   Op H[KSH][4];
   // layer 0: B operands from the LDS input rows
-#pragma unroll
-  for (int mb = 0; mb < MB; mb++)
-#pragma unroll
-    for (int nb = 0; nb < 4; nb++) acc[mb][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
+  // first k-steps take a literal zero accumulator (inline constant)
 #pragma unroll
   for (int ks = 0; ks < KS0; ks++) {
     Op B[4];
@@ -225,7 +222,7 @@ __device__ __forceinline__ void net_forward_wave(const void *wops_v, const float
     for (int mb = 0; mb < MB; mb++) {
       const Op a = wops[(mb * KS0 + ks) * 64 + lane];
 #pragma unroll
-      for (int nb = 0; nb < 4; nb++) acc[mb][nb] = M::mma(a, B[nb], acc[mb][nb]);
+      for (int nb = 0; nb < 4; nb++) acc[mb][nb] = M::mma(a, B[nb], ks == 0 ? f32x4{0.f, 0.f, 0.f, 0.f} : acc[mb][nb]);
     }
   }
   acc_to_ops<M, MB>(acc, params + PO::b(0), g, H);
@@ -234,16 +231,13 @@ __device__ __forceinline__ void net_forward_wave(const void *wops_v, const float
 #pragma unroll
   for (int l = 1; l < 3; l++) {
 #pragma unroll
-    for (int mb = 0; mb < MB; mb++)
-#pragma unroll
-      for (int nb = 0; nb < 4; nb++) acc[mb][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
     for (int ks = 0; ks < KSH; ks++)
 #pragma unroll
       for (int mb = 0; mb < MB; mb++) {
         const Op a = wl[(mb * KSH + ks) * 64 + lane];
 #pragma unroll
-        for (int nb = 0; nb < 4; nb++) acc[mb][nb] = M::mma(a, H[ks][nb], acc[mb][nb]);
+        for (int nb = 0; nb < 4; nb++)
+          acc[mb][nb] = M::mma(a, H[ks][nb], ks == 0 ? f32x4{0.f, 0.f, 0.f, 0.f} : acc[mb][nb]);
       }
     acc_to_ops<M, MB>(acc, params + PO::b(l), g, H);
     wl += NS::LH;
@@ -251,12 +245,10 @@ __device__ __forceinline__ void net_forward_wave(const void *wops_v, const float
   // output layer: 6 rows of one 16-row block
   f32x4 oacc[4];
 #pragma unroll
-  for (int nb = 0; nb < 4; nb++) oacc[nb] = f32x4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
   for (int ks = 0; ks < KSH; ks++) {
     const Op a = wl[ks * 64 + lane];
 #pragma unroll
-    for (int nb = 0; nb < 4; nb++) oacc[nb] = M::mma(a, H[ks][nb], oacc[nb]);
+    for (int nb = 0; nb < 4; nb++) oacc[nb] = M::mma(a, H[ks][nb], ks == 0 ? f32x4{0.f, 0.f, 0.f, 0.f} : oacc[nb]);
   }
   if (g < 2) {
     const float *bo = params + PO::b(3);
