@@ -133,11 +133,14 @@ int64_t sssgs_mlp_param_count(int32_t in_dim, int32_t width, int32_t hidden, int
 
 /* Bytes of workspace for one view: n Gaussians, width x height pixels,
    feature width F, network width (0 without network) and room for
-   instance_capacity (tile, Gaussian) instances.  Returns 0 on bad arguments. */
+   instance_capacity (tile, Gaussian) instances.  Returns 0 on bad arguments,
+   including images whose 16x16 tile grid cannot be covered by 256 super-bins
+   of at most 64x64 tiles (both sides up to 16384 pixels are always accepted). */
 size_t sssgs_workspace_bytes(int32_t n, int32_t width, int32_t height, int32_t feat_dim, int32_t mlp_width,
                              int64_t instance_capacity);
 
-/* Forward pass: projection, binning (radix sort of (tile, depth) keys),
+/* Forward pass: projection, binning (order (tile, depth, index): radix sort of
+   the depth keys, stable super-bin pass, per-tile filtering),
    compositing into the G-buffer, deferred shading.
    out_rgb [3][H][W], out_gbuffer [C][H][W] and out_alpha [H][W] are required.
    out_num_instances (HOST pointer) may be NULL.  When it is non-NULL the call

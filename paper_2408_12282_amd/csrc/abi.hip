@@ -18,12 +18,12 @@ thread_local std::string g_last_error;
 
 // ---- optional per-stage timing with HIP events on the caller's stream
 enum Stage {
-  kStProject = 0, kStSortDepth, kStExpand, kStSortTiles, kStRanges, kStCompositeFwd, kStShadeFwd,
+  kStProject = 0, kStSortDepth, kStExpand, kStSortTiles, kStCompositeFwd, kStShadeFwd,
   kStShadeBwd, kStMlpWgrad, kStMlpReduce, kStCompositeBwd, kStProjectBwd, kStCount
 };
-const char *kStageNames[kStCount] = {"project_fwd",   "sort_depth",    "expand",        "sort_tiles",
-                                     "tile_ranges",   "composite_fwd", "shade_fwd",     "shade_bwd",
-                                     "mlp_wgrad",     "mlp_reduce",    "composite_bwd", "project_bwd"};
+const char *kStageNames[kStCount] = {"project_fwd", "sort_depth", "expand",        "sort_tiles",
+                                     "composite_fwd", "shade_fwd", "shade_bwd",     "mlp_wgrad",
+                                     "mlp_reduce",  "composite_bwd", "project_bwd"};
 struct TimerRec {
   int stage;
   hipEvent_t a, b;
@@ -86,7 +86,7 @@ int in_pad_of(int in_dim) { return (in_dim + 31) / 32 * 32; }
 
 struct Layout {
   size_t records, depth_keys, vals_a, keys_b, vals_b, keys_a, rects, radii, boxes, tt, offsets, partials, hist;
-  size_t ik_a, iv_a, ik_b, iv_b, ranges, t_final, n_contrib, status, m_total;
+  size_t ik_a, iv_a, ik_b, iv_b, ranges, tcount, t_final, n_contrib, status, m_total;
   size_t gacc, dG, dT, wops, tops, mlp_part, mlp_mid, rec_x, rec_o;
   size_t total;
   int C, RS, GS, TX, TY, T;
@@ -107,6 +107,7 @@ bool make_layout(int32_t n, int32_t W, int32_t H, int32_t F, int32_t mlp_width, 
   L.TX = (W + kTile - 1) / kTile;
   L.TY = (H + kTile - 1) / kTile;
   L.T = L.TX * L.TY;
+  if (!superbin_supported(L.TX, L.TY)) return false;
   L.nb_g = radix_blocks((uint64_t)n);
   L.nb_i = radix_blocks((uint64_t)cap);
   const uint32_t nbmax = L.nb_g > L.nb_i ? L.nb_g : L.nb_i;
@@ -133,6 +134,7 @@ bool make_layout(int32_t n, int32_t W, int32_t H, int32_t F, int32_t mlp_width, 
   if (np2 > np) np = np2;
   L.partials = take(np * 4);
   L.hist = take((size_t)nbmax * kRadixBins * 4);
+  L.tcount = take((size_t)L.T * 4);
   L.ik_a = take(cc * 4);
   L.iv_a = take(cc * 4);
   L.ik_b = take(cc * 4);
@@ -385,35 +387,21 @@ sssgs_status sssgs_render_forward(const sssgs_gaussians *g, const sssgs_camera *
     }
   }
   // sorted Gaussian indices are now in va
-  // 3. instance offsets: exclusive scan of the tiles each Gaussian touches, in depth order
+  // 3. expansion of the depth-sorted Gaussians into (super-bin, Gaussian)
+  // instances; m_total holds [M, super-bin instances, tiles touched]
   uint32_t *tt = at<uint32_t>(ws, L.tt), *offs = at<uint32_t>(ws, L.offsets);
-  Scope *sc_expand = new Scope(kStExpand, st);
-  launch_gather_tiles(va, rects, n, tt, st);
-  launch_scan(tt, offs, n, part, mtot, st);
-  // 4. expand into (tile, Gaussian) instances, then the tile passes of the sort
-  int tbits = 0;
-  while ((1u << tbits) < (uint32_t)L.T) tbits++;
-  const int tpasses = (tbits + kRadixBits - 1) / kRadixBits;
   uint32_t *ik_a = at<uint32_t>(ws, L.ik_a), *iv_a = at<uint32_t>(ws, L.iv_a);
   uint32_t *ik_b = at<uint32_t>(ws, L.ik_b), *iv_b = at<uint32_t>(ws, L.iv_b);
-  uint32_t *ek = (tpasses & 1) ? ik_b : ik_a, *ev = (tpasses & 1) ? iv_b : iv_a;
-  launch_emit(va, rects, offs, n, ucap, L.TX, ek, ev, mtot, status, st);
-  delete sc_expand;
-  {
-    Scope sc(kStSortTiles, st);
-    for (int pass = 0; pass < tpasses; pass++) {
-      const bool from_a = (ek == ik_a) == (pass % 2 == 0);
-      uint32_t *ki = from_a ? ik_a : ik_b, *vi = from_a ? iv_a : iv_b;
-      uint32_t *ko = from_a ? ik_b : ik_a, *vo = from_a ? iv_b : iv_a;
-      launch_radix_pass(ki, vi, ko, vo, ucap, mtot, pass * kRadixBits, hist, part, st);
-    }
-  }
-  // 5. per-tile [start, end) ranges of the sorted instances
   uint2 *ranges = at<uint2>(ws, L.ranges);
   {
-    Scope sc(kStRanges, st);
-    launch_fill_u32(reinterpret_cast<uint32_t *>(ranges), 0u, 2u * (uint32_t)L.T, st);
-    launch_tile_ranges(ik_a, mtot, ucap, ranges, st);
+    Scope sc(kStExpand, st);
+    launch_superbin_expand(va, rects, n, ucap, L.TX, L.TY, tt, offs, ik_a, iv_a, part, mtot + 1, mtot + 2, st);
+  }
+  // 4-5. tile-major lists (Gaussian index, tile id), ranges, instance count and status
+  {
+    Scope sc(kStSortTiles, st);
+    launch_tile_lists(rects, ucap, L.TX, L.TY, ik_a, iv_a, ik_b, iv_b, at<uint32_t>(ws, L.tcount), hist, part,
+                      mtot + 1, mtot + 2, mtot, status, ranges, st);
   }
   // 6. compositing into the G-buffer (Eq. 3)
   {

@@ -198,44 +198,54 @@ __global__ __launch_bounds__(kSortThreads) void radix_scatter_kernel(
 
 // ------------------------------------------------------------------ expansion
 
-// tiles touched by the Gaussian at each depth-sorted position
-__global__ __launch_bounds__(256) void gather_tiles_kernel(const uint32_t *__restrict__ sorted_g,
-                                                           const ushort4 *__restrict__ rects, uint32_t n,
-                                                           uint32_t *__restrict__ tt) {
-  const uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= n) return;
-  const ushort4 r = rects[sorted_g[p]];
-  tt[p] = (uint32_t)(r.z - r.x) * (uint32_t)(r.w - r.y);
+// Rectangle of super-bins (squares of 2^log2s tiles) covering a tile rectangle.
+__device__ __forceinline__ ushort4 super_rect(ushort4 r, int log2s) {
+  if (r.z <= r.x || r.w <= r.y) return make_ushort4(0, 0, 0, 0);
+  return make_ushort4(r.x >> log2s, r.y >> log2s, ((r.z - 1) >> log2s) + 1, ((r.w - 1) >> log2s) + 1);
 }
 
-// Writes each Gaussian's (tile, index) instances at its scanned offset.  The
+// Super-bins touched by the Gaussian at each depth-sorted position; the
+// total number of tiles touched is added to *m_tiles (zeroed beforehand).
+__global__ __launch_bounds__(256) void gather_tiles_kernel(const uint32_t *__restrict__ sorted_g,
+                                                           const ushort4 *__restrict__ rects, uint32_t n, int log2s,
+                                                           uint32_t *__restrict__ tt, uint32_t *__restrict__ m_tiles) {
+  __shared__ uint32_t lds4[4];
+  const uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
+  uint32_t area = 0;
+  if (p < n) {
+    const ushort4 r = rects[sorted_g[p]];
+    const ushort4 q = super_rect(r, log2s);
+    tt[p] = (uint32_t)(q.z - q.x) * (uint32_t)(q.w - q.y);
+    area = (uint32_t)(r.z - r.x) * (uint32_t)(r.w - r.y);
+  }
+  uint32_t total;
+  block_exclusive_scan(area, lds4, total);
+  if (threadIdx.x == 0 && total) atomicAdd(m_tiles, total);
+}
+
+// Writes each Gaussian's (super-bin, index) instances at its scanned offset.  The
 // instances of a block's 256 consecutive (depth-ordered) Gaussians form one
 // contiguous range of the output, which the block writes cooperatively: each
 // output slot finds its Gaussian by a binary search over the block's offsets.
 __global__ __launch_bounds__(256) void emit_kernel(const uint32_t *__restrict__ sorted_g,
                                                    const ushort4 *__restrict__ rects,
                                                    const uint32_t *__restrict__ offsets, uint32_t n, uint32_t cap,
-                                                   int TX, uint32_t *__restrict__ inst_keys,
-                                                   uint32_t *__restrict__ inst_vals, const uint32_t *__restrict__ m_dev,
-                                                   int32_t *__restrict__ status) {
+                                                   int TX, int log2s, uint32_t *__restrict__ inst_keys,
+                                                   uint32_t *__restrict__ inst_vals) {
   __shared__ uint32_t soff[257];
   __shared__ uint32_t sg[256];
-  __shared__ ushort4 srect[256];
+  __shared__ ushort4 srect[256], trect[256];
   const int t = threadIdx.x;
   const uint32_t p0 = blockIdx.x * 256u, p = p0 + t;
-  const uint32_t mtot = m_dev[0];
-  if (p == 0) {
-    status[kStatusMLo] = (int32_t)mtot;
-    status[kStatusMHi] = 0;
-    status[kStatusFlags] = mtot > cap ? kFlagOverflow : 0;
-  }
-  if (p0 >= n) return;  // only with n == 0 (one block is launched for the status word)
+  if (p0 >= n) return;
   const uint32_t nb = min(256u, n - p0);
   if ((uint32_t)t < nb) {
     const uint32_t g = sorted_g[p];
-    const ushort4 r = rects[g];
+    const ushort4 tr = rects[g];
+    const ushort4 r = super_rect(tr, log2s);
     sg[t] = g;
     srect[t] = r;
+    trect[t] = tr;
     soff[t] = offsets[p];
     if ((uint32_t)t == nb - 1) soff[nb] = offsets[p] + (uint32_t)(r.z - r.x) * (uint32_t)(r.w - r.y);
   }
@@ -250,26 +260,150 @@ __global__ __launch_bounds__(256) void emit_kernel(const uint32_t *__restrict__ 
     const ushort4 r = srect[k];
     const uint32_t wx = (uint32_t)(r.z - r.x), q = o - soff[k];
     const uint32_t ty = r.y + q / wx, tx = r.x + q % wx;
-    inst_keys[o] = ty * (uint32_t)TX + tx;
+    // key: super-bin (8 bits), then the Gaussian's tile rectangle clipped to
+    // the super-bin, in super-bin-local tile coordinates (log2s bits each)
+    const ushort4 t4 = trect[k];
+    const uint32_t s = 1u << log2s, bx = tx << log2s, by = ty << log2s;
+    const uint32_t x0 = max((uint32_t)t4.x, bx) - bx, x1 = min((uint32_t)t4.z, bx + s) - bx - 1;
+    const uint32_t y0 = max((uint32_t)t4.y, by) - by, y1 = min((uint32_t)t4.w, by + s) - by - 1;
+    inst_keys[o] = (ty * (uint32_t)TX + tx) | (x0 << 8) | (x1 << (8 + log2s)) | (y0 << (8 + 2 * log2s)) |
+                   (y1 << (8 + 3 * log2s));  // TX: super-bins per row
     inst_vals[o] = sg[k];
   }
 }
 
+__global__ void zero_u32_kernel(uint32_t *__restrict__ p) { *p = 0u; }
+
+// ------------------------------------------------------------------ tile lists
+//
+// Tile lists from super-bin lists.  The depth-sorted Gaussians are expanded
+// into (super-bin, Gaussian) instances -- a super-bin is a square of 2^log2s
+// tiles, sized so that there are at most 256 -- and one stable 8-bit radix
+// pass makes them super-bin-major, depth order kept within each super-bin.
+// Each tile then filters its super-bin's list by its own rectangle test,
+// which keeps the depth order: the tile's list is written as one contiguous,
+// coalesced run.  One workgroup per tile counts its instances, one block scans
+// the counts into tile offsets, and one workgroup per tile writes its run.
+// The result is the order (tile, depth, index) of a stable sort of all
+// (tile, depth) keys.
+
+// [start, end) of super-bin sb in the radix pass output (digit-major scanned
+// histogram; digits >= the number of super-bins are empty).
+__device__ __forceinline__ uint2 superbin_range(const uint32_t *__restrict__ hist_scan, int nblocks, int sb,
+                                                uint32_t ms) {
+  const uint32_t a = hist_scan[(size_t)sb * nblocks];
+  const uint32_t b = sb + 1 < kRadixBins ? hist_scan[(size_t)(sb + 1) * nblocks] : ms;
+  return make_uint2(a, b);
+}
+
+// Does the clipped rectangle packed in a super-bin key cover the tile at
+// super-bin-local coordinates (lx, ly)?
+__device__ __forceinline__ bool key_covers(uint32_t key, int log2s, uint32_t lx, uint32_t ly) {
+  const uint32_t m = (1u << log2s) - 1u;
+  const uint32_t x0 = (key >> 8) & m, x1 = (key >> (8 + log2s)) & m;
+  const uint32_t y0 = (key >> (8 + 2 * log2s)) & m, y1 = (key >> (8 + 3 * log2s)) & m;
+  return lx >= x0 && lx <= x1 && ly >= y0 && ly <= y1;
+}
+
+constexpr int kTileItems = 4;  // list items per thread and step
+static_assert(8 + 4 * kMaxSuperbinLog2 <= 32, "super-bin key layout");
+
+__global__ __launch_bounds__(256) void tile_count_kernel(const uint32_t *__restrict__ sb_keys,
+                                                         const uint32_t *__restrict__ hist_scan, int nblocks,
+                                                         const uint32_t *__restrict__ ms_dev, uint32_t cap, int TX,
+                                                         int SX, int log2s, uint32_t *__restrict__ counts) {
+  __shared__ uint32_t lds4[4];
+  const int t = blockIdx.x;
+  const uint32_t tx = t % TX, ty = t / TX;
+  const uint32_t lx = tx & ((1u << log2s) - 1u), ly = ty & ((1u << log2s) - 1u);
+  const uint32_t ms = min(ms_dev[0], cap);
+  const uint2 rg = superbin_range(hist_scan, nblocks, (int)(ty >> log2s) * SX + (int)(tx >> log2s), ms);
+  uint32_t c = 0;
+  for (uint32_t i0 = rg.x + threadIdx.x * kTileItems; i0 < rg.y; i0 += 256u * kTileItems) {
+#pragma unroll
+    for (int j = 0; j < kTileItems; j++)
+      if (i0 + j < rg.y && key_covers(sb_keys[i0 + j], log2s, lx, ly)) c++;
+  }
+  uint32_t total;
+  block_exclusive_scan(c, lds4, total);
+  if (threadIdx.x == 0) counts[t] = total;
+}
+
+// One block: tile offsets (exclusive scan of the counts), the instance count
+// and the status word.  m_tiles is the true number of instances (the counts
+// are incomplete when the super-bin instances overflowed the capacity).
+__global__ __launch_bounds__(256) void tile_scan_kernel(uint32_t *__restrict__ counts, int T,
+                                                        const uint32_t *__restrict__ m_tiles, uint32_t cap,
+                                                        uint32_t *__restrict__ m_out, int32_t *__restrict__ status) {
+  __shared__ uint32_t lds4[4];
+  uint32_t carry = 0;
+  for (int base = 0; base < T; base += 256) {
+    const int i = base + threadIdx.x;
+    const uint32_t v = i < T ? counts[i] : 0u;
+    uint32_t total;
+    const uint32_t ex = block_exclusive_scan(v, lds4, total);
+    if (i < T) counts[i] = carry + ex;
+    carry += total;
+  }
+  if (threadIdx.x == 0) {
+    const uint32_t m = m_tiles[0];
+    m_out[0] = m;
+    status[kStatusMLo] = (int32_t)m;
+    status[kStatusMHi] = 0;
+    status[kStatusFlags] = m > cap ? kFlagOverflow : 0;
+  }
+}
+
+__global__ __launch_bounds__(256) void tile_write_kernel(const uint32_t *__restrict__ sb_keys,
+                                                         const uint32_t *__restrict__ sb_list,
+                                                         const uint32_t *__restrict__ hist_scan, int nblocks,
+                                                         const uint32_t *__restrict__ ms_dev, int TX, int T, int SX,
+                                                         int log2s, const uint32_t *__restrict__ tile_off,
+                                                         const uint32_t *__restrict__ m_tiles, uint32_t cap,
+                                                         uint32_t *__restrict__ out_tiles,
+                                                         uint32_t *__restrict__ out_gauss, uint2 *__restrict__ ranges) {
+  __shared__ uint32_t lds4[4];
+  const int t = blockIdx.x;
+  const uint32_t m = m_tiles[0];
+  if (m > cap) {  // overflow: empty tiles, nothing written
+    if (threadIdx.x == 0) ranges[t] = make_uint2(0u, 0u);
+    return;
+  }
+  const uint32_t tx = t % TX, ty = t / TX;
+  const uint32_t lx = tx & ((1u << log2s) - 1u), ly = ty & ((1u << log2s) - 1u);
+  const uint2 rg =
+      superbin_range(hist_scan, nblocks, (int)(ty >> log2s) * SX + (int)(tx >> log2s), min(ms_dev[0], cap));
+  const uint32_t start = tile_off[t];
+  uint32_t run = start;
+  for (uint32_t c0 = rg.x; c0 < rg.y; c0 += 256u * kTileItems) {
+    // thread k takes the contiguous items c0 + kTileItems k + j, so the
+    // block-wide prefix of per-thread hit counts keeps the list order
+    const uint32_t i0 = c0 + threadIdx.x * kTileItems;
+    bool hit[kTileItems];
+    uint32_t c = 0;
+#pragma unroll
+    for (int j = 0; j < kTileItems; j++) {
+      hit[j] = i0 + j < rg.y && key_covers(sb_keys[i0 + j], log2s, lx, ly);
+      c += hit[j];
+    }
+    uint32_t total;
+    uint32_t pos = run + block_exclusive_scan(c, lds4, total);
+#pragma unroll
+    for (int j = 0; j < kTileItems; j++)
+      if (hit[j]) {
+        out_tiles[pos] = (uint32_t)t;
+        out_gauss[pos] = sb_list[i0 + j];
+        pos++;
+      }
+    run += total;
+  }
+  if (threadIdx.x == 0) ranges[t] = make_uint2(start, run);
+}
 __global__ __launch_bounds__(256) void fill_u32_kernel(uint32_t *__restrict__ p, uint32_t v, uint32_t n) {
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = v;
 }
 
-__global__ __launch_bounds__(256) void tile_ranges_kernel(const uint32_t *__restrict__ keys,
-                                                          const uint32_t *__restrict__ m_dev, uint32_t cap,
-                                                          uint2 *__restrict__ ranges) {
-  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-  const uint32_t m = load_count(cap, m_dev);
-  if (i >= m) return;
-  const uint32_t k = keys[i];
-  if (i == 0 || keys[i - 1] != k) ranges[k].x = i;
-  if (i + 1 == m || keys[i + 1] != k) ranges[k].y = i + 1;
-}
 
 // ------------------------------------------------------------------ host side
 
@@ -296,21 +430,46 @@ void launch_radix_pass(const uint32_t *kin, const uint32_t *vin, uint32_t *kout,
   radix_scatter_kernel<<<nb, kSortThreads, 0, st>>>(kin, vin, kout, vout, n_host, n_dev, shift, hist, (int)nb);
 }
 
-void launch_gather_tiles(const uint32_t *sorted_g, const ushort4 *rects, uint32_t n, uint32_t *tt, hipStream_t st) {
-  if (n) gather_tiles_kernel<<<cdiv(n, 256), 256, 0, st>>>(sorted_g, rects, n, tt);
+
+
+int superbin_log2(int TX, int TY) {
+  int l = 0;
+  while ((uint64_t)cdiv(TX, 1u << l) * cdiv(TY, 1u << l) > (uint64_t)kRadixBins) l++;
+  return l;
 }
 
-void launch_emit(const uint32_t *sorted_g, const ushort4 *rects, const uint32_t *offsets, uint32_t n, uint32_t cap,
-                 int TX, uint32_t *ik, uint32_t *iv, const uint32_t *m_dev, int32_t *status, hipStream_t st) {
-  emit_kernel<<<n ? cdiv(n, 256) : 1, 256, 0, st>>>(sorted_g, rects, offsets, n, cap, TX, ik, iv, m_dev, status);
+// The super-bin key packs 8 bits of super-bin and four log2s-bit coordinates.
+bool superbin_supported(int TX, int TY) { return superbin_log2(TX, TY) <= kMaxSuperbinLog2; }
+
+void launch_superbin_expand(const uint32_t *sorted_g, const ushort4 *rects, uint32_t n, uint32_t cap, int TX, int TY,
+                            uint32_t *tt, uint32_t *offs, uint32_t *ka, uint32_t *va, uint32_t *partials,
+                            uint32_t *ms_dev, uint32_t *m_tiles, hipStream_t st) {
+  const int log2s = superbin_log2(TX, TY);
+  const int SX = (int)cdiv(TX, 1u << log2s);
+  zero_u32_kernel<<<1, 1, 0, st>>>(m_tiles);
+  if (n) gather_tiles_kernel<<<cdiv(n, 256), 256, 0, st>>>(sorted_g, rects, n, log2s, tt, m_tiles);
+  launch_scan(tt, offs, n, partials, ms_dev, st);
+  if (n) emit_kernel<<<cdiv(n, 256), 256, 0, st>>>(sorted_g, rects, offs, n, cap, SX, log2s, ka, va);
+}
+
+void launch_tile_lists(const ushort4 *rects, uint32_t cap, int TX, int TY, uint32_t *ka, uint32_t *va, uint32_t *kb,
+                       uint32_t *vb, uint32_t *counts, uint32_t *hist, uint32_t *partials, const uint32_t *ms_dev,
+                       const uint32_t *m_tiles, uint32_t *m_out, int32_t *status, uint2 *ranges, hipStream_t st) {
+  const int log2s = superbin_log2(TX, TY);
+  const int SX = (int)cdiv(TX, 1u << log2s);
+  const int T = TX * TY;
+  // one stable 8-bit pass: super-bin-major, depth order within each super-bin
+  launch_radix_pass(ka, va, kb, vb, cap, ms_dev, 0, hist, partials, st);
+  const int nb = (int)radix_blocks(cap);
+  tile_count_kernel<<<T, 256, 0, st>>>(kb, hist, nb, ms_dev, cap, TX, SX, log2s, counts);
+  tile_scan_kernel<<<1, 256, 0, st>>>(counts, T, m_tiles, cap, m_out, status);
+  tile_write_kernel<<<T, 256, 0, st>>>(kb, vb, hist, nb, ms_dev, TX, T, SX, log2s, counts, m_tiles, cap, ka, va,
+                                       ranges);
 }
 
 void launch_fill_u32(uint32_t *p, uint32_t v, uint32_t n, hipStream_t st) {
   if (n) fill_u32_kernel<<<cdiv(n, 256), 256, 0, st>>>(p, v, n);
 }
 
-void launch_tile_ranges(const uint32_t *keys, const uint32_t *m_dev, uint32_t cap, uint2 *ranges, hipStream_t st) {
-  if (cap) tile_ranges_kernel<<<cdiv(cap, 256), 256, 0, st>>>(keys, m_dev, cap, ranges);
-}
 
 }  // namespace sssgs

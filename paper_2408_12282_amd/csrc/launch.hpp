@@ -27,11 +27,18 @@ uint32_t radix_blocks(uint64_t n);
 uint32_t scan_partials_needed(uint64_t n);
 void launch_radix_pass(const uint32_t *kin, const uint32_t *vin, uint32_t *kout, uint32_t *vout, uint32_t n_host,
                        const uint32_t *n_dev, int shift, uint32_t *hist, uint32_t *partials, hipStream_t st);
-void launch_gather_tiles(const uint32_t *sorted_g, const ushort4 *rects, uint32_t n, uint32_t *tt, hipStream_t st);
-void launch_emit(const uint32_t *sorted_g, const ushort4 *rects, const uint32_t *offsets, uint32_t n, uint32_t cap,
-                 int TX, uint32_t *ik, uint32_t *iv, const uint32_t *m_dev, int32_t *status, hipStream_t st);
 void launch_fill_u32(uint32_t *p, uint32_t v, uint32_t n, hipStream_t st);
-void launch_tile_ranges(const uint32_t *keys, const uint32_t *m_dev, uint32_t cap, uint2 *ranges, hipStream_t st);
+// Tile lists (Sec. 3.1 binning): super-bin expansion of the depth-sorted
+// Gaussians, then the stable super-bin pass and the per-tile filtering into
+// tile-major (Gaussian index, tile id) lists with their ranges and the status word.
+int superbin_log2(int TX, int TY);
+bool superbin_supported(int TX, int TY);
+void launch_superbin_expand(const uint32_t *sorted_g, const ushort4 *rects, uint32_t n, uint32_t cap, int TX, int TY,
+                            uint32_t *tt, uint32_t *offs, uint32_t *ka, uint32_t *va, uint32_t *partials,
+                            uint32_t *ms_dev, uint32_t *m_tiles, hipStream_t st);
+void launch_tile_lists(const ushort4 *rects, uint32_t cap, int TX, int TY, uint32_t *ka, uint32_t *va, uint32_t *kb,
+                       uint32_t *vb, uint32_t *counts, uint32_t *hist, uint32_t *partials, const uint32_t *ms_dev,
+                       const uint32_t *m_tiles, uint32_t *m_out, int32_t *status, uint2 *ranges, hipStream_t st);
 
 template <int C>
 void launch_composite_fwd_t(const uint2 *ranges, const uint32_t *sorted_g, const float *records, const short4 *boxes,
