@@ -86,7 +86,7 @@ int in_pad_of(int in_dim) { return (in_dim + 31) / 32 * 32; }
 
 struct Layout {
   size_t records, depth_keys, vals_a, keys_b, vals_b, keys_a, rects, radii, boxes, tt, offsets, partials, hist;
-  size_t ik_a, iv_a, ik_b, iv_b, ranges, tcount, t_final, n_contrib, status, m_total;
+  size_t ik_a, iv_a, ik_b, iv_b, ranges, tcount, apart, t_final, n_contrib, status, m_total;
   size_t gacc, dG, dT, wops, tops, mlp_part, mlp_mid, rec_x, rec_o;
   size_t total;
   int C, RS, GS, TX, TY, T;
@@ -135,6 +135,7 @@ bool make_layout(int32_t n, int32_t W, int32_t H, int32_t F, int32_t mlp_width, 
   L.partials = take(np * 4);
   L.hist = take((size_t)nbmax * kRadixBins * 4);
   L.tcount = take((size_t)L.T * 4);
+  L.apart = take((size_t)area_parts((uint32_t)nn) * 4);
   L.ik_a = take(cc * 4);
   L.iv_a = take(cc * 4);
   L.ik_b = take(cc * 4);
@@ -388,20 +389,21 @@ sssgs_status sssgs_render_forward(const sssgs_gaussians *g, const sssgs_camera *
   }
   // sorted Gaussian indices are now in va
   // 3. expansion of the depth-sorted Gaussians into (super-bin, Gaussian)
-  // instances; m_total holds [M, super-bin instances, tiles touched]
+  // instances; m_total holds [M, super-bin instances]
   uint32_t *tt = at<uint32_t>(ws, L.tt), *offs = at<uint32_t>(ws, L.offsets);
   uint32_t *ik_a = at<uint32_t>(ws, L.ik_a), *iv_a = at<uint32_t>(ws, L.iv_a);
   uint32_t *ik_b = at<uint32_t>(ws, L.ik_b), *iv_b = at<uint32_t>(ws, L.iv_b);
   uint2 *ranges = at<uint2>(ws, L.ranges);
   {
     Scope sc(kStExpand, st);
-    launch_superbin_expand(va, rects, n, ucap, L.TX, L.TY, tt, offs, ik_a, iv_a, part, mtot + 1, mtot + 2, st);
+    launch_superbin_expand(va, rects, n, ucap, L.TX, L.TY, tt, offs, ik_a, iv_a, part, mtot + 1,
+                           at<uint32_t>(ws, L.apart), st);
   }
   // 4-5. tile-major lists (Gaussian index, tile id), ranges, instance count and status
   {
     Scope sc(kStSortTiles, st);
-    launch_tile_lists(rects, ucap, L.TX, L.TY, ik_a, iv_a, ik_b, iv_b, at<uint32_t>(ws, L.tcount), hist, part,
-                      mtot + 1, mtot + 2, mtot, status, ranges, st);
+    launch_tile_lists(n, ucap, L.TX, L.TY, ik_a, iv_a, ik_b, iv_b, at<uint32_t>(ws, L.tcount), hist, part,
+                      mtot + 1, at<uint32_t>(ws, L.apart), mtot, status, ranges, st);
   }
   // 6. compositing into the G-buffer (Eq. 3)
   {

@@ -205,10 +205,10 @@ __device__ __forceinline__ ushort4 super_rect(ushort4 r, int log2s) {
 }
 
 // Super-bins touched by the Gaussian at each depth-sorted position; the
-// total number of tiles touched is added to *m_tiles (zeroed beforehand).
+// block's number of tiles touched goes to area_part[block].
 __global__ __launch_bounds__(256) void gather_tiles_kernel(const uint32_t *__restrict__ sorted_g,
                                                            const ushort4 *__restrict__ rects, uint32_t n, int log2s,
-                                                           uint32_t *__restrict__ tt, uint32_t *__restrict__ m_tiles) {
+                                                           uint32_t *__restrict__ tt, uint32_t *__restrict__ area_part) {
   __shared__ uint32_t lds4[4];
   const uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
   uint32_t area = 0;
@@ -220,7 +220,7 @@ __global__ __launch_bounds__(256) void gather_tiles_kernel(const uint32_t *__res
   }
   uint32_t total;
   block_exclusive_scan(area, lds4, total);
-  if (threadIdx.x == 0 && total) atomicAdd(m_tiles, total);
+  if (threadIdx.x == 0) area_part[blockIdx.x] = total;
 }
 
 // Writes each Gaussian's (super-bin, index) instances at its scanned offset.  The
@@ -330,12 +330,18 @@ __global__ __launch_bounds__(256) void tile_count_kernel(const uint32_t *__restr
 }
 
 // One block: tile offsets (exclusive scan of the counts), the instance count
-// and the status word.  m_tiles is the true number of instances (the counts
-// are incomplete when the super-bin instances overflowed the capacity).
+// (the sum of the per-block tiles-touched totals: exact also when the
+// super-bin instances overflowed the capacity and the counts are incomplete)
+// and the status word.
 __global__ __launch_bounds__(256) void tile_scan_kernel(uint32_t *__restrict__ counts, int T,
-                                                        const uint32_t *__restrict__ m_tiles, uint32_t cap,
-                                                        uint32_t *__restrict__ m_out, int32_t *__restrict__ status) {
+                                                        const uint32_t *__restrict__ area_part, int nparts,
+                                                        uint32_t cap, uint32_t *__restrict__ m_out,
+                                                        int32_t *__restrict__ status) {
   __shared__ uint32_t lds4[4];
+  uint32_t msum = 0;
+  for (int i = threadIdx.x; i < nparts; i += 256) msum += area_part[i];
+  uint32_t mtot;
+  block_exclusive_scan(msum, lds4, mtot);
   uint32_t carry = 0;
   for (int base = 0; base < T; base += 256) {
     const int i = base + threadIdx.x;
@@ -346,7 +352,7 @@ __global__ __launch_bounds__(256) void tile_scan_kernel(uint32_t *__restrict__ c
     carry += total;
   }
   if (threadIdx.x == 0) {
-    const uint32_t m = m_tiles[0];
+    const uint32_t m = mtot;
     m_out[0] = m;
     status[kStatusMLo] = (int32_t)m;
     status[kStatusMHi] = 0;
@@ -359,12 +365,12 @@ __global__ __launch_bounds__(256) void tile_write_kernel(const uint32_t *__restr
                                                          const uint32_t *__restrict__ hist_scan, int nblocks,
                                                          const uint32_t *__restrict__ ms_dev, int TX, int T, int SX,
                                                          int log2s, const uint32_t *__restrict__ tile_off,
-                                                         const uint32_t *__restrict__ m_tiles, uint32_t cap,
+                                                         const uint32_t *__restrict__ m_dev, uint32_t cap,
                                                          uint32_t *__restrict__ out_tiles,
                                                          uint32_t *__restrict__ out_gauss, uint2 *__restrict__ ranges) {
   __shared__ uint32_t lds4[4];
   const int t = blockIdx.x;
-  const uint32_t m = m_tiles[0];
+  const uint32_t m = m_dev[0];
   if (m > cap) {  // overflow: empty tiles, nothing written
     if (threadIdx.x == 0) ranges[t] = make_uint2(0u, 0u);
     return;
@@ -441,20 +447,22 @@ int superbin_log2(int TX, int TY) {
 // The super-bin key packs 8 bits of super-bin and four log2s-bit coordinates.
 bool superbin_supported(int TX, int TY) { return superbin_log2(TX, TY) <= kMaxSuperbinLog2; }
 
+uint32_t area_parts(uint32_t n) { return n ? cdiv(n, 256) : 1; }
+
 void launch_superbin_expand(const uint32_t *sorted_g, const ushort4 *rects, uint32_t n, uint32_t cap, int TX, int TY,
                             uint32_t *tt, uint32_t *offs, uint32_t *ka, uint32_t *va, uint32_t *partials,
-                            uint32_t *ms_dev, uint32_t *m_tiles, hipStream_t st) {
+                            uint32_t *ms_dev, uint32_t *area_part, hipStream_t st) {
   const int log2s = superbin_log2(TX, TY);
   const int SX = (int)cdiv(TX, 1u << log2s);
-  zero_u32_kernel<<<1, 1, 0, st>>>(m_tiles);
-  if (n) gather_tiles_kernel<<<cdiv(n, 256), 256, 0, st>>>(sorted_g, rects, n, log2s, tt, m_tiles);
+  if (n) gather_tiles_kernel<<<cdiv(n, 256), 256, 0, st>>>(sorted_g, rects, n, log2s, tt, area_part);
+  else zero_u32_kernel<<<1, 1, 0, st>>>(area_part);
   launch_scan(tt, offs, n, partials, ms_dev, st);
   if (n) emit_kernel<<<cdiv(n, 256), 256, 0, st>>>(sorted_g, rects, offs, n, cap, SX, log2s, ka, va);
 }
 
-void launch_tile_lists(const ushort4 *rects, uint32_t cap, int TX, int TY, uint32_t *ka, uint32_t *va, uint32_t *kb,
+void launch_tile_lists(uint32_t n, uint32_t cap, int TX, int TY, uint32_t *ka, uint32_t *va, uint32_t *kb,
                        uint32_t *vb, uint32_t *counts, uint32_t *hist, uint32_t *partials, const uint32_t *ms_dev,
-                       const uint32_t *m_tiles, uint32_t *m_out, int32_t *status, uint2 *ranges, hipStream_t st) {
+                       const uint32_t *area_part, uint32_t *m_out, int32_t *status, uint2 *ranges, hipStream_t st) {
   const int log2s = superbin_log2(TX, TY);
   const int SX = (int)cdiv(TX, 1u << log2s);
   const int T = TX * TY;
@@ -462,8 +470,8 @@ void launch_tile_lists(const ushort4 *rects, uint32_t cap, int TX, int TY, uint3
   launch_radix_pass(ka, va, kb, vb, cap, ms_dev, 0, hist, partials, st);
   const int nb = (int)radix_blocks(cap);
   tile_count_kernel<<<T, 256, 0, st>>>(kb, hist, nb, ms_dev, cap, TX, SX, log2s, counts);
-  tile_scan_kernel<<<1, 256, 0, st>>>(counts, T, m_tiles, cap, m_out, status);
-  tile_write_kernel<<<T, 256, 0, st>>>(kb, vb, hist, nb, ms_dev, TX, T, SX, log2s, counts, m_tiles, cap, ka, va,
+  tile_scan_kernel<<<1, 256, 0, st>>>(counts, T, area_part, (int)area_parts(n), cap, m_out, status);
+  tile_write_kernel<<<T, 256, 0, st>>>(kb, vb, hist, nb, ms_dev, TX, T, SX, log2s, counts, m_out, cap, ka, va,
                                        ranges);
 }
 

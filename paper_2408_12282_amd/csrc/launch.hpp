@@ -33,12 +33,13 @@ void launch_fill_u32(uint32_t *p, uint32_t v, uint32_t n, hipStream_t st);
 // tile-major (Gaussian index, tile id) lists with their ranges and the status word.
 int superbin_log2(int TX, int TY);
 bool superbin_supported(int TX, int TY);
+uint32_t area_parts(uint32_t n);
 void launch_superbin_expand(const uint32_t *sorted_g, const ushort4 *rects, uint32_t n, uint32_t cap, int TX, int TY,
                             uint32_t *tt, uint32_t *offs, uint32_t *ka, uint32_t *va, uint32_t *partials,
-                            uint32_t *ms_dev, uint32_t *m_tiles, hipStream_t st);
-void launch_tile_lists(const ushort4 *rects, uint32_t cap, int TX, int TY, uint32_t *ka, uint32_t *va, uint32_t *kb,
+                            uint32_t *ms_dev, uint32_t *area_part, hipStream_t st);
+void launch_tile_lists(uint32_t n, uint32_t cap, int TX, int TY, uint32_t *ka, uint32_t *va, uint32_t *kb,
                        uint32_t *vb, uint32_t *counts, uint32_t *hist, uint32_t *partials, const uint32_t *ms_dev,
-                       const uint32_t *m_tiles, uint32_t *m_out, int32_t *status, uint2 *ranges, hipStream_t st);
+                       const uint32_t *area_part, uint32_t *m_out, int32_t *status, uint2 *ranges, hipStream_t st);
 
 template <int C>
 void launch_composite_fwd_t(const uint2 *ranges, const uint32_t *sorted_g, const float *records, const short4 *boxes,
