@@ -112,11 +112,44 @@ typedef __attribute__((__vector_size__(4 * sizeof(float)))) float cf32x4;
 //   dL/dchannel_c = sum_p w_p dG_p,c
 //   dL/d(u, v, conic) from the moments sum_p g_p (1, x, y, x^2, xy, y^2)_p
 //   dL/dopacity   = sum_p g_p / opacity   (alpha = o e^power: dalpha/do = alpha/o)
-// so the reductions run on the matrix cores (v_mfma_f32_16x16x4_f32 with
-// K = the tile's pixels) rather than as one cross-lane reduction per value.
+// so the reductions run on the matrix cores with K = the wave's 64 pixels
+// rather than as one cross-lane reduction per value.  The channel sums use
+// BF16 operands in three terms, a_hi b_hi + a_hi b_lo + a_lo b_hi with
+// x_hi = x truncated to BF16 and x_lo = x - x_hi rounded to BF16 (relative
+// error about 2^-16 per product, accumulated in FP32), on
+// v_mfma_f32_16x16x32_bf16: a sixth of the matrix-core time of FP32 operands.
+// The moment sums stay in FP32 (v_mfma_f32_16x16x4_f32): the geometry
+// gradients recombine them as u^2 sum g - 2 u sum g x + sum g x^2, which
+// cancels and would magnify a 2^-16 error.
 // The batch's records are staged in LDS (double-buffered; the next batch is
 // fetched into registers while the current one is walked), and each wave
 // skips the Gaussians whose alpha box misses its strip.
+typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 cbf16x8;
+
+// Eight floats as BF16 high parts (truncation) and low parts (RNE of the remainder).
+__device__ __forceinline__ void split_bf16x8(const float (&v)[8], cbf16x8 &hi, cbf16x8 &lo) {
+  uint32_t h[4], l[4];
+#pragma unroll
+  for (int k = 0; k < 4; k++) {
+    const uint32_t a = __float_as_uint(v[2 * k]), b = __float_as_uint(v[2 * k + 1]);
+    h[k] = __builtin_amdgcn_perm(b, a, 0x07060302u);  // upper halves: a in the low, b in the high half
+    const float ra = v[2 * k] - __uint_as_float(a & 0xffff0000u);
+    const float rb = v[2 * k + 1] - __uint_as_float(b & 0xffff0000u);
+    typedef float f2 __attribute__((ext_vector_type(2)));
+    typedef __bf16 b2 __attribute__((ext_vector_type(2)));
+    l[k] = __builtin_bit_cast(uint32_t, __builtin_convertvector((f2){ra, rb}, b2));
+  }
+  hi = __builtin_bit_cast(cbf16x8, make_uint4(h[0], h[1], h[2], h[3]));
+  lo = __builtin_bit_cast(cbf16x8, make_uint4(l[0], l[1], l[2], l[3]));
+}
+
+__device__ __forceinline__ cf32x4 mma3(const cbf16x8 &ah, const cbf16x8 &al, const cbf16x8 &bh, const cbf16x8 &bl,
+                                       cf32x4 c) {
+  c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, c, 0, 0, 0);
+  c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl, c, 0, 0, 0);
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh, c, 0, 0, 0);
+}
+
 constexpr int kBJ = 16;       // Gaussians per backward batch
 constexpr int kMS = 256 + 4;  // row stride of the [Gaussian][pixel] matrices (conflict-free column reads)
 
@@ -171,18 +204,33 @@ __global__ __launch_bounds__(256, C > 26 ? 2 : 3) void composite_bwd_kernel(
     for (int c = 0; c < C; c++) gch[c] = 0.f;
   }
   // The tile's dL/dG is the B operand of every channel reduction below: lane
-  // (col, g) of wave w needs dG[pixel 64 w + 4 ks + g][channel 16 nc + col].
-  // It is transposed once through LDS (the weight matrix is not in use yet)
-  // and kept in registers for the whole tile.
-  float bv[16][NBC];
+  // (col, g) of wave w needs dG[pixel 64 w + 32 kk + 8 g + i][channel 16 nc + col],
+  // i = 0..7.  It is transposed once through LDS (the weight matrix is not in
+  // use yet), split into BF16 high and low parts and kept in registers for
+  // the whole tile, as are the moment basis values (1, x, y, x^2, xy, y^2)
+  // of the same pixels, from the tile corner.
+  cbf16x8 bh[2][NBC], bl[2][NBC];
 #pragma unroll
   for (int nc = 0; nc < NBC; nc++) {
 #pragma unroll
     for (int c = 0; c < 16; c++) mat[t * 17 + c] = 16 * nc + c < C ? gch[16 * nc + c] : 0.f;
     __syncthreads();
 #pragma unroll
-    for (int ks = 0; ks < 16; ks++) bv[ks][nc] = mat[(64 * w + 4 * ks + g) * 17 + col];
+    for (int kk = 0; kk < 2; kk++) {
+      float v[8];
+#pragma unroll
+      for (int i = 0; i < 8; i++) v[i] = mat[(64 * w + 32 * kk + 8 * g + i) * 17 + col];
+      split_bf16x8(v, bh[kk][nc], bl[kk][nc]);
+    }
     __syncthreads();
+  }
+  // moment basis of pixel 64 w + 4 ks + g (FP32 B operand, K = 4 pixels per step)
+  float bm[16];
+#pragma unroll
+  for (int ks = 0; ks < 16; ks++) {
+    const int p = 64 * w + 4 * ks + g;
+    const float x = (float)(p & 15) + 0.5f, y = (float)(p >> 4) + 0.5f;
+    bm[ks] = col == 0 ? 1.f : col == 1 ? x : col == 2 ? y : col == 3 ? x * x : col == 4 ? x * y : col == 5 ? y * y : 0.f;
   }
   const int top = (int)maxlast;
   // Batch fetch into registers: thread t < kBJ * R4 holds chunk t % R4 of
@@ -255,41 +303,39 @@ __global__ __launch_bounds__(256, C > 26 ? 2 : 3) void composite_bwd_kernel(
       mat[(kBJ + jj) * kMS + t] = pvj;
     }
     __syncthreads();
-    // ---- reductions over this wave's 64 pixels (4 per MFMA step):
+    // ---- reductions over this wave's 64 pixels (two steps of 32):
     //   [j][c]  = sum_p w[j][p] dG[p][c]
     //   [j][n]  = sum_p g[j][p] basis_n(p),  basis = (1, x, y, x^2, xy, y^2) from the tile corner
     {
-      // operands of all 16 k-steps are loaded first; even and odd k-steps go
-      // to separate accumulators, which halves the dependent MFMA chains
-      float av[16], gv[16];
+      cf32x4 acc[NBC + 1];
 #pragma unroll
-      for (int ks = 0; ks < 16; ks++) {
-        const int p = 64 * w + 4 * ks + g;
-        av[ks] = mat[col * kMS + p];
-        gv[ks] = mat[(kBJ + col) * kMS + p];
+      for (int nc = 0; nc <= NBC; nc++) acc[nc] = cf32x4{0.f, 0.f, 0.f, 0.f};
+      float gv[16];
+#pragma unroll
+      for (int ks = 0; ks < 16; ks++) gv[ks] = mat[(kBJ + col) * kMS + 64 * w + 4 * ks + g];
+#pragma unroll
+      for (int kk = 0; kk < 2; kk++) {
+        const float4 *wr = reinterpret_cast<const float4 *>(&mat[col * kMS + 64 * w + 32 * kk + 8 * g]);
+        const float4 w0 = wr[0], w1 = wr[1];
+        const float wv[8] = {w0.x, w0.y, w0.z, w0.w, w1.x, w1.y, w1.z, w1.w};
+        cbf16x8 wh, wl;
+        split_bf16x8(wv, wh, wl);
+#pragma unroll
+        for (int nc = 0; nc < NBC; nc++) acc[nc] = mma3(wh, wl, bh[kk][nc], bl[kk][nc], acc[nc]);
       }
-      cf32x4 acc[2][NBC + 1];
+      // moments: even and odd k-steps in separate accumulators (shorter dependent chains)
+      cf32x4 am = cf32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-      for (int h = 0; h < 2; h++)
-#pragma unroll
-        for (int nc = 0; nc <= NBC; nc++) acc[h][nc] = cf32x4{0.f, 0.f, 0.f, 0.f};
-      // column col of the basis, branch-free: exactly one selector is 1
-      const float s0 = col == 0, s1 = col == 1, s2 = col == 2, s3 = col == 3, s4 = col == 4, s5 = col == 5;
-#pragma unroll
-      for (int ks = 0; ks < 16; ks++) {
-        const int h = ks & 1, p = 64 * w + 4 * ks + g;
-#pragma unroll
-        for (int nc = 0; nc < NBC; nc++)
-          acc[h][nc] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[ks], bv[ks][nc], acc[h][nc], 0, 0, 0);
-        const float x = (float)(p & 15) + 0.5f, y = (float)(p >> 4) + 0.5f;
-        const float b = s0 + x * (s1 + s3 * x + s4 * y) + y * (s2 + s5 * y);
-        acc[h][NBC] = __builtin_amdgcn_mfma_f32_16x16x4f32(gv[ks], b, acc[h][NBC], 0, 0, 0);
+      for (int ks = 0; ks < 16; ks += 2) {
+        acc[NBC] = __builtin_amdgcn_mfma_f32_16x16x4f32(gv[ks], bm[ks], acc[NBC], 0, 0, 0);
+        am = __builtin_amdgcn_mfma_f32_16x16x4f32(gv[ks + 1], bm[ks + 1], am, 0, 0, 0);
       }
+      acc[NBC] += am;
       // D layout: lane (col, g) holds rows j = 4 g + i of column 16 nc + col
 #pragma unroll
       for (int nc = 0; nc <= NBC; nc++)
 #pragma unroll
-        for (int i = 0; i < 4; i++) mat[(4 * g + i) * kMS + 64 * w + 16 * nc + col] = acc[0][nc][i] + acc[1][nc][i];
+        for (int i = 0; i < 4; i++) mat[(4 * g + i) * kMS + 64 * w + 16 * nc + col] = acc[nc][i];
     }
     if (ncnt > 0) stage(buf ^ 1, ncnt);
     __syncthreads();
