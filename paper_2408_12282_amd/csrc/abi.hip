@@ -382,7 +382,7 @@ sssgs_status sssgs_render_forward(const sssgs_gaussians *g, const sssgs_camera *
     for (int pass = 0; pass < 4; pass++) {
       uint32_t *ko = (pass & 1) ? ka : kb;
       uint32_t *vo = (pass & 1) ? va : vb;
-      launch_radix_pass(kin, vin, ko, vo, n, nullptr, pass * kRadixBits, hist, part, st);
+      launch_radix_pass(kin, vin, ko, vo, n, nullptr, pass * kRadixBits, hist, part, st, false);
       kin = ko;
       vin = vo;
     }

@@ -94,6 +94,10 @@ __device__ __forceinline__ uint32_t load_count(uint32_t n_host, const uint32_t *
   return m < n_host ? m : n_host;
 }
 
+// Per-block digit histograms: digit-major hist[digit][block] for the scan
+// across blocks, or block-major hist[block][digit] (LOCAL) when the scatter
+// derives its own offsets.
+template <bool LOCAL>
 __global__ __launch_bounds__(kSortThreads) void radix_hist_kernel(const uint32_t *__restrict__ keys, uint32_t n_host,
                                                                   const uint32_t *__restrict__ n_dev, int shift,
                                                                   uint32_t *__restrict__ hist, int nblocks) {
@@ -109,12 +113,17 @@ __global__ __launch_bounds__(kSortThreads) void radix_hist_kernel(const uint32_t
     if (idx < n) atomicAdd(&h[(keys[idx] >> shift) & (kRadixBins - 1)], 1u);
   }
   __syncthreads();
-  hist[t * nblocks + blockIdx.x] = h[t];
+  if (LOCAL) hist[blockIdx.x * kRadixBins + t] = h[t];
+  else hist[t * nblocks + blockIdx.x] = h[t];
 }
 
 // Stable scatter of one 8-bit digit.  The block ranks its keys with wave
 // ballots into block-local digit runs in LDS, then streams the runs out, so
-// that consecutive lanes write consecutive global addresses.
+// that consecutive lanes write consecutive global addresses.  The global
+// start of each of the block's runs comes from the scanned digit-major
+// histogram, or (LOCAL, few blocks) from the block-major counts directly:
+// all blocks' counts of the thread's digit, and those of earlier blocks.
+template <bool LOCAL>
 __global__ __launch_bounds__(kSortThreads) void radix_scatter_kernel(
     const uint32_t *__restrict__ keys_in, const uint32_t *__restrict__ vals_in, uint32_t *__restrict__ keys_out,
     uint32_t *__restrict__ vals_out, uint32_t n_host, const uint32_t *__restrict__ n_dev, int shift,
@@ -139,7 +148,24 @@ __global__ __launch_bounds__(kSortThreads) void radix_scatter_kernel(
     val[r] = idx < n ? vals_in[idx] : 0u;
   }
   run[t] = 0;
-  gbase[t] = hist_scan[t * nblocks + blockIdx.x];
+  if (LOCAL) {
+    // 16 independent loads in flight per step
+    uint32_t tot = 0, below = 0;
+    for (int b0 = 0; b0 < nblocks; b0 += 16) {
+      uint32_t c[16];
+#pragma unroll
+      for (int k = 0; k < 16; k++) c[k] = b0 + k < nblocks ? hist_scan[(b0 + k) * kRadixBins + t] : 0u;
+#pragma unroll
+      for (int k = 0; k < 16; k++) {
+        tot += c[k];
+        below += b0 + k < (int)blockIdx.x ? c[k] : 0u;
+      }
+    }
+    uint32_t total;
+    gbase[t] = block_exclusive_scan(tot, lds4, total) + below;
+  } else {
+    gbase[t] = hist_scan[t * nblocks + blockIdx.x];
+  }
 #pragma unroll
   for (int k = 0; k < 4; k++) wcnt[k][t] = 0;
   __syncthreads();
@@ -429,11 +455,18 @@ uint32_t scan_partials_needed(uint64_t n) { return n ? cdiv(n, kScanItems) : 1; 
 
 // One stable 8-bit pass (keys/vals in -> out) over min(n_host, *n_dev) items.
 void launch_radix_pass(const uint32_t *kin, const uint32_t *vin, uint32_t *kout, uint32_t *vout, uint32_t n_host,
-                       const uint32_t *n_dev, int shift, uint32_t *hist, uint32_t *partials, hipStream_t st) {
+                       const uint32_t *n_dev, int shift, uint32_t *hist, uint32_t *partials, hipStream_t st,
+                       bool digit_major) {
   const uint32_t nb = radix_blocks(n_host);
-  radix_hist_kernel<<<nb, kSortThreads, 0, st>>>(kin, n_host, n_dev, shift, hist, (int)nb);
+  if (!digit_major && nb <= kRadixLocalBlocks) {
+    // two launches: each scatter block sums the (few) block histograms itself
+    radix_hist_kernel<true><<<nb, kSortThreads, 0, st>>>(kin, n_host, n_dev, shift, hist, (int)nb);
+    radix_scatter_kernel<true><<<nb, kSortThreads, 0, st>>>(kin, vin, kout, vout, n_host, n_dev, shift, hist, (int)nb);
+    return;
+  }
+  radix_hist_kernel<false><<<nb, kSortThreads, 0, st>>>(kin, n_host, n_dev, shift, hist, (int)nb);
   launch_scan(hist, hist, nb * kRadixBins, partials, nullptr, st);
-  radix_scatter_kernel<<<nb, kSortThreads, 0, st>>>(kin, vin, kout, vout, n_host, n_dev, shift, hist, (int)nb);
+  radix_scatter_kernel<false><<<nb, kSortThreads, 0, st>>>(kin, vin, kout, vout, n_host, n_dev, shift, hist, (int)nb);
 }
 
 
@@ -467,7 +500,7 @@ void launch_tile_lists(uint32_t n, uint32_t cap, int TX, int TY, uint32_t *ka, u
   const int SX = (int)cdiv(TX, 1u << log2s);
   const int T = TX * TY;
   // one stable 8-bit pass: super-bin-major, depth order within each super-bin
-  launch_radix_pass(ka, va, kb, vb, cap, ms_dev, 0, hist, partials, st);
+  launch_radix_pass(ka, va, kb, vb, cap, ms_dev, 0, hist, partials, st, true);  // ranges read the scanned histogram
   const int nb = (int)radix_blocks(cap);
   tile_count_kernel<<<T, 256, 0, st>>>(kb, hist, nb, ms_dev, cap, TX, SX, log2s, counts);
   tile_scan_kernel<<<1, 256, 0, st>>>(counts, T, area_part, (int)area_parts(n), cap, m_out, status);

@@ -25,8 +25,12 @@ void launch_scan(const uint32_t *in, uint32_t *out, uint32_t n, uint32_t *partia
                  hipStream_t st);
 uint32_t radix_blocks(uint64_t n);
 uint32_t scan_partials_needed(uint64_t n);
+// One stable 8-bit pass.  digit_major: leave the scanned digit-major histogram
+// in hist (starts of every digit's output run); otherwise small inputs take a
+// two-launch form that does not.
 void launch_radix_pass(const uint32_t *kin, const uint32_t *vin, uint32_t *kout, uint32_t *vout, uint32_t n_host,
-                       const uint32_t *n_dev, int shift, uint32_t *hist, uint32_t *partials, hipStream_t st);
+                       const uint32_t *n_dev, int shift, uint32_t *hist, uint32_t *partials, hipStream_t st,
+                       bool digit_major);
 void launch_fill_u32(uint32_t *p, uint32_t v, uint32_t n, hipStream_t st);
 // Tile lists (Sec. 3.1 binning): super-bin expansion of the depth-sorted
 // Gaussians, then the stable super-bin pass and the per-tile filtering into
