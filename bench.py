@@ -102,13 +102,15 @@ def run_gpu(precision: str, steps: int, warmup: int):
     B.sssgs_timing_enable(False)
     stages = B.sssgs_timing_read()
     extras = time_training_kernels(rgb_ref=drgb, params=p, mlp_params=mp, grads=grads, dmlp=dmlp)
+    ibl = time_ibl(view, p, bc, mp, mlp.width, prec)
     flags, m_dev = B.sssgs_workspace_status(ctypes_ptr(view), g.n, cam.width, cam.height, g.feat_dim, mlp.width,
                                             cap)
     assert flags == 0 and m_dev == M, (flags, m_dev, M)
     per_tile_last, fwd_records, listed = tile_stats(view, cam)
     return {"ms": ms, "stages": {k: (v[0] / max(v[1], 1), v[1]) for k, v in stages.items()}, "M": M,
             "bwd_records": per_tile_last, "fwd_records": fwd_records, "listed": listed, "n": g.n,
-            "C": 10 + g.feat_dim, "HW": cam.width * cam.height, "precision": precision, "training": extras}
+            "C": 10 + g.feat_dim, "HW": cam.width * cam.height, "precision": precision, "training": extras,
+            "ibl": ibl}
 
 
 def time_training_kernels(rgb_ref, params, mlp_params, grads, dmlp, reps: int = 10):
@@ -148,6 +150,34 @@ def time_training_kernels(rgb_ref, params, mlp_params, grads, dmlp, reps: int = 
                            "gbs": round(loss_bytes / (loss_ms * 1e-3) / 1e9, 1)},
             "adam": {"ms": round(adam_ms, 4), "params": int(nparam), "launches": len(work),
                      "gbs": round(28 * nparam / (adam_ms * 1e-3) / 1e9, 1)}}
+
+
+def time_ibl(view, params, cam_struct, mlp_params, mlp_width, prec, k: int = 16, reps: int = 5):
+    """Image-based lighting outside the headline: the forward of the same view under
+    k environment light samples (one G-buffer, k shading evaluations summed)
+    against the single-light forward, timed with events on the stream."""
+    import torch
+    from paper_2408_12282_amd import scene, sssgs as B
+    lights, weights = scene.environment_lights(k)
+    bl = [B.make_light(l) for l in lights]
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    res = {}
+    for name, fn in (("single", lambda: B.render_forward(view, params, -1, cam_struct, bl[0], mlp_params, mlp_width,
+                                                          prec)),
+                     ("multi", lambda: B.render_forward_lights(view, params, -1, cam_struct, bl, weights, mlp_params,
+                                                               mlp_width, prec))):
+        fn()
+        torch.cuda.synchronize()
+        t0.record()
+        for _ in range(reps):
+            fn()
+        t1.record()
+        torch.cuda.synchronize()
+        res[name] = t0.elapsed_time(t1) / reps
+    return {"lights": k, "forward_ms": round(res["multi"], 4), "single_light_forward_ms": round(res["single"], 4),
+            "ms_per_added_light": round((res["multi"] - res["single"]) / (k - 1), 4),
+            "workload": "300k Gaussians 800x800, environment light samples on a Fibonacci sphere"}
 
 
 def ctypes_ptr(view):
@@ -274,6 +304,7 @@ def main():
         line["bf16_speedup_vs_fp32"] = round(f["ms"] / head["ms"], 3)
     line["roofline_all"] = rl
     line["training_kernels"] = head["training"]
+    line["image_based_lighting"] = head["ibl"]
     if a.calib_copy_mib > 0:
         import torch
         src = torch.ones(a.calib_copy_mib << 18, device="cuda")

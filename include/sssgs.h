@@ -155,6 +155,26 @@ sssgs_status sssgs_render_forward(const sssgs_gaussians *g, const sssgs_camera *
                                   float *out_gbuffer, float *out_alpha, int64_t *out_num_instances,
                                   void *stream);
 
+/* Forward pass under several point lights at once: image-based lighting as a
+   sum over light samples of an environment map (Appendix "Image Based
+   Lighting": the relit image is the sum of the single-light images scaled by
+   the environment's illumination).  Projection, binning and compositing run
+   once; the deferred shading is evaluated for every light on the same
+   G-buffer and summed:
+     out_rgb = sum_k weights[k] (per channel) * rgb(lights[k]),
+   where rgb(light) is what sssgs_render_forward writes for that light.
+   lights: HOST array of num_lights >= 1; weights: HOST array [num_lights][3]
+   of finite values (neither may be NULL).  The network input differs between
+   lights only in the incident direction.  Other arguments, outputs, the
+   workspace and errors as for sssgs_render_forward; out_gbuffer and
+   out_alpha do not depend on the lights.  Forward only. */
+sssgs_status sssgs_render_forward_lights(const sssgs_gaussians *g, const sssgs_camera *cam,
+                                         const sssgs_light *lights, const float *weights, int32_t num_lights,
+                                         const sssgs_mlp *mlp, const sssgs_options *opt, void *workspace,
+                                         size_t workspace_bytes, int64_t instance_capacity, float *out_rgb,
+                                         float *out_gbuffer, float *out_alpha, int64_t *out_num_instances,
+                                         void *stream);
+
 /* Backward pass of the forward call that filled `workspace` (same g, cam,
    light, mlp, options; gbuffer = that call's out_gbuffer).  Upstream gradients
    dL_drgb [3][H][W] (required), dL_dgbuffer [C][H][W] and dL_dalpha [H][W]

@@ -7,6 +7,7 @@
 #include <vector>
 
 #include "sssgs.h"
+#include <cmath>
 #include "launch.hpp"
 #include "shade_common.hpp"
 
@@ -291,13 +292,14 @@ void composite_bwd(int C, const Layout &L, void *ws, int W, int H, hipStream_t s
 
 // Dispatch over (F, NET, WIDTH, IN_PAD) for the shading kernels.
 template <bool BWD>
-bool shade_dispatch(int F, int net, int width, const ShadeArgs &a, int nblocks, hipStream_t st) {
+bool shade_dispatch(int F, int net, int width, const ShadeArgs &a, int nblocks, hipStream_t st,
+                    const MultiLight *ml = nullptr) {
   const int in_pad = in_pad_of(F + kNumPE + 6);
   const int w = net ? width : 64;
 #define SSSGS_TRY(F_, NET_, W_, P_)                                              \
   if (F == F_ && net == NET_ && w == W_ && in_pad == P_) {                     \
     if constexpr (BWD) launch_shade_bwd_t<F_, NET_, W_, P_>(a, nblocks, st);   \
-    else launch_shade_fwd_t<F_, NET_, W_, P_>(a, st);                          \
+    else launch_shade_fwd_t<F_, NET_, W_, P_>(a, *ml, st);                     \
     return true;                                                                \
   }
   SSSGS_SHADE_INSTANCES(SSSGS_TRY)
@@ -344,13 +346,23 @@ sssgs_status sssgs_workspace_layout(int32_t n, int32_t width, int32_t height, in
   return SSSGS_OK;
 }
 
-sssgs_status sssgs_render_forward(const sssgs_gaussians *g, const sssgs_camera *cam, const sssgs_light *light,
-                                  const sssgs_mlp *mlp, const sssgs_options *opt, void *ws, size_t ws_bytes,
-                                  int64_t cap, float *out_rgb, float *out_gbuffer, float *out_alpha,
-                                  int64_t *out_num_instances, void *stream) {
+}  // extern "C"
+
+namespace {
+
+// Forward of one view with nl >= 1 point lights: geometry, binning and
+// compositing once, then the shading summed over the lights in passes of up
+// to kMaxLights (weights: host [nl][3], null = all ones).
+sssgs_status forward_impl(const sssgs_gaussians *g, const sssgs_camera *cam, const sssgs_light *lights,
+                          const float *weights, int nl, const sssgs_mlp *mlp, const sssgs_options *opt, void *ws,
+                          size_t ws_bytes, int64_t cap, float *out_rgb, float *out_gbuffer, float *out_alpha,
+                          int64_t *out_num_instances, void *stream) {
   int net, width;
-  sssgs_status s = check_common(g, cam, light, mlp, opt, ws, net, width);
+  sssgs_status s = check_common(g, cam, lights, mlp, opt, ws, net, width);
   if (s != SSSGS_OK) return s;
+  if (nl < 1) return fail(SSSGS_ERR_INVALID_ARG, "at least one light");
+  for (int k = 0; k < nl * 3 && weights; k++)
+    if (!std::isfinite(weights[k])) return fail(SSSGS_ERR_INVALID_ARG, "light weights must be finite");
   if (!out_rgb || !out_gbuffer || !out_alpha) return fail(SSSGS_ERR_INVALID_ARG, "null output");
   Layout L;
   if (!make_layout(g->n, cam->width, cam->height, g->feat_dim, width, cap, L))
@@ -410,14 +422,10 @@ sssgs_status sssgs_render_forward(const sssgs_gaussians *g, const sssgs_camera *
     Scope sc(kStCompositeFwd, st);
     composite_fwd(L.C, L, ws, W, H, out_gbuffer, st);
   }
-  // 7. deferred shading (Eq. 4, 6, 7)
+  // 7. deferred shading (Eq. 4, 6, 7), summed over the lights
   ShadeArgs sa;
   memset(&sa, 0, sizeof(sa));
   sa.cam = ca;
-  for (int k = 0; k < 3; k++) {
-    sa.light.pos[k] = light->pos[k];
-    sa.light.intensity[k] = light->intensity[k];
-  }
   sa.gbuf = out_gbuffer;
   sa.t_final = at<float>(ws, L.t_final);
   sa.rgb = out_rgb;
@@ -429,8 +437,20 @@ sssgs_status sssgs_render_forward(const sssgs_gaussians *g, const sssgs_camera *
   }
   {
     Scope sc(kStShadeFwd, st);
-    if (!shade_dispatch<false>(g->feat_dim, net, width, sa, 0, st))
-      return fail(SSSGS_ERR_UNSUPPORTED, "no shading kernel for this configuration");
+    for (int k0 = 0; k0 < nl; k0 += kMaxLights) {
+      MultiLight ml;
+      memset(&ml, 0, sizeof(ml));
+      ml.K = nl - k0 < kMaxLights ? nl - k0 : kMaxLights;
+      ml.accumulate = k0 > 0;
+      for (int k = 0; k < ml.K; k++)
+        for (int c = 0; c < 3; c++) {
+          ml.pos[k][c] = lights[k0 + k].pos[c];
+          ml.intensity[k][c] = lights[k0 + k].intensity[c];
+          ml.weight[k][c] = weights ? weights[(k0 + k) * 3 + c] : 1.f;
+        }
+      if (!shade_dispatch<false>(g->feat_dim, net, width, sa, 0, st, &ml))
+        return fail(SSSGS_ERR_UNSUPPORTED, "no shading kernel for this configuration");
+    }
   }
   s = check_hip("forward launch");
   if (s != SSSGS_OK) return s;
@@ -443,6 +463,28 @@ sssgs_status sssgs_render_forward(const sssgs_gaussians *g, const sssgs_camera *
     if (hs[kStatusFlags] & kFlagOverflow) return fail(SSSGS_ERR_CAPACITY, "instance capacity exceeded");
   }
   return SSSGS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+sssgs_status sssgs_render_forward(const sssgs_gaussians *g, const sssgs_camera *cam, const sssgs_light *light,
+                                  const sssgs_mlp *mlp, const sssgs_options *opt, void *ws, size_t ws_bytes,
+                                  int64_t cap, float *out_rgb, float *out_gbuffer, float *out_alpha,
+                                  int64_t *out_num_instances, void *stream) {
+  return forward_impl(g, cam, light, nullptr, 1, mlp, opt, ws, ws_bytes, cap, out_rgb, out_gbuffer, out_alpha,
+                      out_num_instances, stream);
+}
+
+sssgs_status sssgs_render_forward_lights(const sssgs_gaussians *g, const sssgs_camera *cam,
+                                         const sssgs_light *lights, const float *weights, int32_t num_lights,
+                                         const sssgs_mlp *mlp, const sssgs_options *opt, void *ws, size_t ws_bytes,
+                                         int64_t cap, float *out_rgb, float *out_gbuffer, float *out_alpha,
+                                         int64_t *out_num_instances, void *stream) {
+  if (!lights || !weights) return fail(SSSGS_ERR_INVALID_ARG, "null lights or weights");
+  return forward_impl(g, cam, lights, weights, num_lights, mlp, opt, ws, ws_bytes, cap, out_rgb, out_gbuffer,
+                      out_alpha, out_num_instances, stream);
 }
 
 sssgs_status sssgs_render_backward(const sssgs_gaussians *g, const sssgs_camera *cam, const sssgs_light *light,

@@ -13,6 +13,7 @@ struct ProjGradOut {
   int accumulate;
 };
 struct ShadeArgs;
+struct MultiLight;
 
 template <int F, bool SH>
 void launch_project_fwd_t(const ProjIn &in, const CamArgs &cam, float *records, uint32_t *keys, uint32_t *vals,
@@ -55,7 +56,7 @@ void launch_composite_bwd_t(const uint2 *ranges, const uint32_t *sorted_g, const
                             const float *dG, const float *dT, float *gacc, hipStream_t st);
 
 template <int F, int NET, int WIDTH, int IN_PAD>
-void launch_shade_fwd_t(const ShadeArgs &a, hipStream_t st);
+void launch_shade_fwd_t(const ShadeArgs &a, const MultiLight &ml, hipStream_t st);
 template <int F, int NET, int WIDTH, int IN_PAD>
 void launch_shade_bwd_t(const ShadeArgs &a, int nblocks, hipStream_t st);
 int shade_bwd_waves(int net, int width, int in_pad);

@@ -1,6 +1,8 @@
 // shade.hip -- per-pixel deferred shading (Sec. 3.2 "Per-Pixel Deferred
 // Shading"): GGX BRDF (Eq. 4), residual network (Eq. 6) and the SSS/BRDF
-// combination (Eq. 7), forward.  The backward lives in shade_bwd.hip.
+// combination (Eq. 7), forward, for one or several point lights over the same
+// G-buffer (image-based lighting as a weighted sum of light samples, paper
+// appendix "Image Based Lighting").  The backward lives in shade_bwd.hip.
 //
 // One 256-lane workgroup per 16x16 tile; wave w owns rows 4w..4w+3.  Each lane
 // shades its pixel; the network runs per wave on the matrix cores with the
@@ -9,8 +11,10 @@
 
 namespace sssgs {
 
-template <int F, int NET, int WIDTH, int IN_PAD>
-__global__ __launch_bounds__(256) void shade_fwd_kernel(ShadeArgs A) {
+// MULTI = false: one light of weight 1 written (not added) -- the plain
+// forward, compiled without the light loop.
+template <int F, int NET, int WIDTH, int IN_PAD, bool MULTI>
+__global__ __launch_bounds__(256) void shade_fwd_kernel(ShadeArgs A, MultiLight ML) {
   using M = typename NetTraits<NET>::M;
   using E = typename M::Elem;
   constexpr int C = kChFeat + F;
@@ -33,31 +37,51 @@ __global__ __launch_bounds__(256) void shade_fwd_kernel(ShadeArgs A) {
 #pragma unroll
     for (int c = 0; c < C; c++) gb[c] = 0.f;
   }
-  PixShade S;
-  shade_geometry<C>(gb, T, (float)px + 0.5f, (float)py + 0.5f, A.cam, A.light, NET != 0, S);
-  if constexpr (NET != 0) {
-    E *xrow = xs + (w * 64 + lane) * XS;
-    build_net_input<F, IN_PAD, M>(gb, S, xrow);
-    __syncthreads();
-    net_forward_wave<M, WIDTH, IN_PAD, false>(A.wops, A.params, xs + w * 64 * XS, XS, outs + w * 64 * 8, nullptr);
-    __syncthreads();
-    const float *o = outs + (w * 64 + lane) * 8;
-    combine_net(S, gb[kChSss], o);
+  E *xrow = xs + (w * 64 + lane) * XS;
+  float acc[3] = {0.f, 0.f, 0.f};
+  const int K = MULTI ? ML.K : 1;
+  for (int k = 0; k < K; k++) {
+    LightArgs L;
+#pragma unroll
+    for (int c = 0; c < 3; c++) {
+      L.pos[c] = ML.pos[k][c];
+      L.intensity[c] = ML.intensity[k][c];
+    }
+    PixShade S;
+    shade_geometry<C>(gb, T, (float)px + 0.5f, (float)py + 0.5f, A.cam, L, NET != 0, S);
+    if constexpr (NET != 0) {
+      // the network input row differs between lights only in w_i
+      if (k == 0) build_net_input<F, IN_PAD, M>(gb, S, xrow);
+      else set_net_light<F, M>(S, xrow);
+      __syncthreads();
+      net_forward_wave<M, WIDTH, IN_PAD, false>(A.wops, A.params, xs + w * 64 * XS, XS, outs + w * 64 * 8, nullptr);
+      __syncthreads();
+      combine_net(S, gb[kChSss], outs + (w * 64 + lane) * 8);
+    }
+#pragma unroll
+    for (int c = 0; c < 3; c++) {
+      const float v = S.bg ? 0.f : S.a * S.L[c];
+      acc[c] = MULTI ? __fmaf_rn(ML.weight[k][c], v, acc[c]) : v;
+    }
   }
   if (inside) {
 #pragma unroll
-    for (int c = 0; c < 3; c++) A.rgb[c * HW + pix] = S.bg ? 0.f : S.a * S.L[c];
+    for (int c = 0; c < 3; c++)
+      A.rgb[c * HW + pix] = (MULTI && ML.accumulate) ? A.rgb[c * HW + pix] + acc[c] : acc[c];
     if (A.alpha) A.alpha[pix] = 1.f - T;
   }
 }
 
 template <int F, int NET, int WIDTH, int IN_PAD>
-void launch_shade_fwd_t(const ShadeArgs &a, hipStream_t st) {
-  shade_fwd_kernel<F, NET, WIDTH, IN_PAD><<<a.cam.TX * a.cam.TY, 256, 0, st>>>(a);
+void launch_shade_fwd_t(const ShadeArgs &a, const MultiLight &ml, hipStream_t st) {
+  bool multi = ml.K != 1 || ml.accumulate;
+  for (int c = 0; c < 3; c++) multi = multi || ml.weight[0][c] != 1.f;
+  if (multi) shade_fwd_kernel<F, NET, WIDTH, IN_PAD, true><<<a.cam.TX * a.cam.TY, 256, 0, st>>>(a, ml);
+  else shade_fwd_kernel<F, NET, WIDTH, IN_PAD, false><<<a.cam.TX * a.cam.TY, 256, 0, st>>>(a, ml);
 }
 
 #define SSSGS_SHADE_FWD(F, NET, WIDTH, IN_PAD) \
-  template void launch_shade_fwd_t<F, NET, WIDTH, IN_PAD>(const ShadeArgs &, hipStream_t);
+  template void launch_shade_fwd_t<F, NET, WIDTH, IN_PAD>(const ShadeArgs &, const MultiLight &, hipStream_t);
 SSSGS_SHADE_INSTANCES(SSSGS_SHADE_FWD)
 
 }  // namespace sssgs

@@ -23,6 +23,15 @@ struct ShadeArgs {
   int nparams;
 };
 
+// Point lights of one shading pass (image-based lighting by a sum over light
+// samples): rgb = sum_k weight_k * (the single-light image of light k),
+// added to the existing rgb when `accumulate` is set.
+constexpr int kMaxLights = 32;
+struct MultiLight {
+  int K, accumulate;
+  float pos[kMaxLights][3], intensity[kMaxLights][3], weight[kMaxLights][3];
+};
+
 template <int NET> struct NetTraits { using M = MmaF32; };
 template <> struct NetTraits<2> { using M = MmaBF16; };
 
@@ -141,6 +150,14 @@ __device__ __forceinline__ void build_net_input(const float *gb, const PixShade 
   for (int k = 0; k < 3; k++) row[p++] = M::cvt(S.wi[k]);
 #pragma unroll
   for (; p < IN_PAD; p++) row[p] = M::cvt(0.f);
+}
+
+// Only the incident-direction entries of a network input row (after the
+// features, the position encoding and w_o).
+template <int F, class M>
+__device__ __forceinline__ void set_net_light(const PixShade &S, typename M::Elem *row) {
+#pragma unroll
+  for (int k = 0; k < 3; k++) row[F + kNumPE + 3 + k] = M::cvt(S.wi[k]);
 }
 
 __device__ __forceinline__ void combine_net(PixShade &S, float sss_pre, const float *o) {

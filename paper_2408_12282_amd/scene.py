@@ -203,6 +203,28 @@ def fibonacci_cameras(k: int, radius: float, width: int, height: int, fov_deg: f
     return cams
 
 
+def environment_lights(k: int, radius: float = 30.0):
+    """Light samples of a synthetic HDR environment for image-based lighting:
+    k directions on a Fibonacci sphere, each a point light at `radius` whose
+    intensity radius^2 gives unit irradiance at the origin (white light), and a
+    per-channel weight = environment radiance x the sample's solid angle 4 pi / k.
+    The environment (no captured maps are available) is a blue sky above the
+    horizon, a brown ground below and a small warm sun.  Returns (lights, weights [k][3])."""
+    golden = math.pi * (3.0 - math.sqrt(5.0))
+    sun = np.array([1.0, 2.0, 0.5]) / math.sqrt(5.25)
+    lights, weights = [], []
+    for i in range(k):
+        y = 1.0 - (2.0 * i + 1.0) / k
+        rr = math.sqrt(max(0.0, 1.0 - y * y))
+        phi = i * golden
+        d = np.array([rr * math.cos(phi), y, rr * math.sin(phi)])
+        rad = (np.array([0.3, 0.5, 0.9]) * math.sqrt(max(y, 0.0)) + np.array([0.2, 0.15, 0.1]) * max(-y, 0.0)
+               + np.array([8.0, 7.0, 5.0]) * max(float(d @ sun), 0.0) ** 64)
+        lights.append(Light((radius * d).astype(np.float32), np.full(3, radius * radius, np.float32)))
+        weights.append((rad * 4.0 * math.pi / k).astype(np.float32))
+    return lights, np.stack(weights)
+
+
 @dataclasses.dataclass
 class Workload:
     name: str

@@ -62,7 +62,8 @@ class Layout(ct.Structure):
 EXPORTS = ("sssgs_mlp_param_count", "sssgs_workspace_bytes", "sssgs_render_forward", "sssgs_render_backward",
            "sssgs_l1_loss", "sssgs_workspace_status", "sssgs_workspace_layout", "sssgs_status_string",
            "sssgs_last_error", "sssgs_timing_enable", "sssgs_timing_read", "sssgs_timing_stages",
-           "sssgs_timing_stage_name", "sssgs_image_loss_workspace_bytes", "sssgs_image_loss", "sssgs_adam_step")
+           "sssgs_timing_stage_name", "sssgs_image_loss_workspace_bytes", "sssgs_image_loss", "sssgs_adam_step",
+           "sssgs_render_forward_lights")
 
 
 def load_library(path: str = LIB_PATH):
@@ -78,6 +79,12 @@ def load_library(path: str = LIB_PATH):
     L.sssgs_render_forward.argtypes = [ct.POINTER(Gaussians), ct.POINTER(Camera), ct.POINTER(Light),
                                        ct.POINTER(Mlp), ct.POINTER(Options), ct.c_void_p, ct.c_size_t, ct.c_int64,
                                        ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.POINTER(ct.c_int64), ct.c_void_p]
+    L.sssgs_render_forward_lights.restype = ct.c_int
+    L.sssgs_render_forward_lights.argtypes = [ct.POINTER(Gaussians), ct.POINTER(Camera), ct.POINTER(Light),
+                                              ct.POINTER(ct.c_float), ct.c_int32, ct.POINTER(Mlp),
+                                              ct.POINTER(Options), ct.c_void_p, ct.c_size_t, ct.c_int64,
+                                              ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.POINTER(ct.c_int64),
+                                              ct.c_void_p]
     L.sssgs_render_backward.restype = ct.c_int
     L.sssgs_render_backward.argtypes = [ct.POINTER(Gaussians), ct.POINTER(Camera), ct.POINTER(Light),
                                         ct.POINTER(Mlp), ct.POINTER(Options), ct.c_void_p, ct.c_size_t, ct.c_int64,
@@ -171,6 +178,19 @@ def sssgs_render_forward(g, cam, light, mlp, opt, workspace, ws_bytes, capacity,
     st = lib().sssgs_render_forward(ct.byref(g), ct.byref(cam), ct.byref(light), ct.byref(mlp) if mlp else None,
                                     ct.byref(opt), workspace, ws_bytes, capacity, out_rgb, out_gbuffer, out_alpha,
                                     ct.byref(cnt) if want_count else None, stream)
+    return st, int(cnt.value)
+
+
+def sssgs_render_forward_lights(g, cam, lights, weights, mlp, opt, workspace, ws_bytes, capacity, out_rgb,
+                                out_gbuffer, out_alpha, want_count=False, stream=None):
+    """lights: sequence of Light structures; weights: [len(lights)][3] floats (host)."""
+    k = len(lights)
+    arr = (Light * k)(*lights)
+    w = (ct.c_float * (3 * k))(*[float(v) for row in weights for v in row])
+    cnt = ct.c_int64(0)
+    st = lib().sssgs_render_forward_lights(ct.byref(g), ct.byref(cam), arr, w, k, ct.byref(mlp) if mlp else None,
+                                           ct.byref(opt), workspace, ws_bytes, capacity, out_rgb, out_gbuffer,
+                                           out_alpha, ct.byref(cnt) if want_count else None, stream)
     return st, int(cnt.value)
 
 
@@ -315,6 +335,25 @@ def render_forward(view: View, params: dict, sh_degree: int, cam: Camera, light:
     opt = Options(precision, 0)
     st, cnt = sssgs_render_forward(g, cam, light, m, opt, ct.c_void_p(view.workspace.data_ptr()), view.ws_bytes,
                                    view.capacity, _ptr(rgb), _ptr(gbuf), _ptr(alpha), want_count, _stream())
+    _check(st)
+    return rgb, gbuf, alpha, (cnt if want_count else None)
+
+
+def render_forward_lights(view: View, params: dict, sh_degree: int, cam: Camera, lights, weights, mlp_params=None,
+                          mlp_width: int = 64, precision: int = PREC_BF16, want_count: bool = False):
+    """Forward under several point lights: rgb = sum_k weights[k] * rgb(lights[k]) over one G-buffer.
+    Returns (rgb [3,H,W], gbuf [C,H,W], alpha [H,W], M or None)."""
+    dev = params["means"].device
+    H, W = view.height, view.width
+    rgb = torch.empty((3, H, W), dtype=torch.float32, device=dev)
+    gbuf = torch.empty((view.C, H, W), dtype=torch.float32, device=dev)
+    alpha = torch.empty((H, W), dtype=torch.float32, device=dev)
+    g = gaussians_struct(params, view.feat_dim, sh_degree)
+    m = Mlp(view.feat_dim + 42, mlp_width, 3, 6, _ptr(mlp_params)) if mlp_params is not None else None
+    opt = Options(precision, 0)
+    st, cnt = sssgs_render_forward_lights(g, cam, list(lights), weights, m, opt,
+                                          ct.c_void_p(view.workspace.data_ptr()), view.ws_bytes, view.capacity,
+                                          _ptr(rgb), _ptr(gbuf), _ptr(alpha), want_count, _stream())
     _check(st)
     return rgb, gbuf, alpha, (cnt if want_count else None)
 
