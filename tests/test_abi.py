@@ -89,6 +89,14 @@ def test_invalid_arguments_are_rejected_before_any_launch(B):
     st = L.sssgs_render_backward(ct.byref(g3), ct.byref(cam), ct.byref(light), None, ct.byref(opt), buf, 1 << 30,
                                  100, None, buf, None, None, None, None, None)
     assert st == B.ERR_INVALID_ARG
+    # several lights: null arrays, no light, non-finite weights
+    lights = (B.Light * 2)(light, light)
+    w_ok = (ct.c_float * 6)(*([1.0] * 6))
+    w_nan = (ct.c_float * 6)(1.0, float("nan"), 1.0, 1.0, 1.0, 1.0)
+    for arr, w, k in ((None, w_ok, 2), (lights, None, 2), (lights, w_ok, 0), (lights, w_nan, 2)):
+        st = L.sssgs_render_forward_lights(ct.byref(g3), ct.byref(cam), arr, w, k, None, ct.byref(opt), buf, 1 << 30,
+                                           100, buf, buf, buf, None, None)
+        assert st == B.ERR_INVALID_ARG, (arr, w, k, st)
     assert B.lib().sssgs_status_string(B.ERR_CAPACITY).decode() == "instance capacity exceeded"
     assert L.sssgs_l1_loss(None, None, -1, 1.0, None, None, None) == B.ERR_INVALID_ARG
 
