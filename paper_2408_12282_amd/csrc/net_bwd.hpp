@@ -75,6 +75,27 @@ struct Mask {
           if (acc[mb][nb][j] + bias[16 * mb + 4 * g + j] > 0.f) w[b >> 5] |= 1u << (b & 31);
         }
   }
+  // From a layer's BF16 activation operands (permuted K order: operand slot
+  // 4 (mb & 1) + j holds D-layout element (mb, nb, j)): the bit is set where
+  // the activation is positive.  A BF16 half is positive iff, as the top half
+  // of a signed 32-bit word, it is above zero.  This equals the pre-activation
+  // test except below the smallest BF16 subnormal, and it lets the
+  // pre-activations die as soon as the activations are packed.
+  __device__ __forceinline__ void set_from_ops(const bf16x8 (&H)[(MB + 1) / 2][4]) {
+#pragma unroll
+    for (int k = 0; k < (MB * 16 + 31) / 32; k++) w[k] = 0u;
+#pragma unroll
+    for (int mb = 0; mb < MB; mb++)
+#pragma unroll
+      for (int nb = 0; nb < 4; nb++) {
+        const uint4 u = __builtin_bit_cast(uint4, H[mb >> 1][nb]);
+        const uint32_t w0 = (mb & 1) ? u.z : u.x, w1 = (mb & 1) ? u.w : u.y;
+        const uint32_t bits = (uint32_t)((int)(w0 << 16) > 0) | ((uint32_t)((int)w0 > 0xFFFF) << 1) |
+                              ((uint32_t)((int)(w1 << 16) > 0) << 2) | ((uint32_t)((int)w1 > 0xFFFF) << 3);
+        const int b = mb * 16 + nb * 4;
+        w[b >> 5] |= bits << (b & 31);
+      }
+  }
   __device__ __forceinline__ void apply(f32x4 (&d)[MB][4]) const {
 #pragma unroll
     for (int mb = 0; mb < MB; mb++)

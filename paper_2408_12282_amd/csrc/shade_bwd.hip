@@ -604,14 +604,14 @@ __global__ __launch_bounds__(64, 2) void shade_bwd_split_kernel(ShadeArgs A, __b
     f32x4 acc[MB][4];
     Op H[NS::KSH][4];
     layer0_mma<M, MB, NS::KS0>(wops, xs, SL::XS, acc, lane);
-    m1.set_from(acc, A.params + PO::b(0), g);
     acc_to_ops<M, MB>(acc, A.params + PO::b(0), g, H);
+    m1.set_from_ops(H);
     layer_mma<M, MB, NS::KSH>(wops + NS::L0, H, acc, lane);
-    m2.set_from(acc, A.params + PO::b(1), g);
     acc_to_ops<M, MB>(acc, A.params + PO::b(1), g, H);
+    m2.set_from_ops(H);
     layer_mma<M, MB, NS::KSH>(wops + NS::L0 + NS::LH, H, acc, lane);
-    m3.set_from(acc, A.params + PO::b(2), g);
     acc_to_ops<M, MB>(acc, A.params + PO::b(2), g, H);
+    m3.set_from_ops(H);
     f32x4 oacc[1][4];
     layer_mma<M, 1, NS::KSH>(wops + NS::L0 + 2 * NS::LH, H, oacc, lane);
     if (g < 2)
