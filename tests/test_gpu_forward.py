@@ -193,3 +193,32 @@ def test_headline_300k_800(precision):
     e = rel_norm(out["rgb"], ora["rgb"])
     print(f"rgb rel err ({precision}): {e:.3e}")
     assert e < (FWD_REL if precision == "fp32" else BF16_EMU_REL)
+
+
+@pytest.mark.parametrize("W,H", [(4096, 4096), (2500, 300)])
+def test_tile_lists_large_grids(W, H):
+    """Tile lists on large tile grids (256 x 256 tiles: super-bins of 16 x 16
+    tiles; a wide 157 x 19 grid), checked for every tile against the order
+    (float32 depth key, index) over the Gaussians whose tile rectangle holds
+    the tile, built on the CPU from the GPU's own rectangles and depth keys
+    (those two are checked against the oracle by the tests above)."""
+    g = scene.make_gaussians(3000, 0, False, seed=7)
+    g.log_scales = (g.log_scales + 0.5).astype(np.float32)  # large footprints: hundreds of tiles each
+    cam = scene.look_at_camera((0, 0, 3), W, H)
+    print(f"[gpu] tile lists {W}x{H}", flush=True)
+    out = gpu_render(g, cam, scene.default_light(), capacity=12_000_000)
+    rects, keys = out["rects"], out["depth_keys"]
+    TX = -(-W // 16)
+    T = TX * (-(-H // 16))
+    lists = [[] for _ in range(T)]
+    for i in np.lexsort((np.arange(g.n), keys)):  # depth key, then index
+        x0, y0, x1, y1 = rects[i]
+        for ty in range(y0, y1):
+            for tx in range(x0, x1):
+                lists[ty * TX + tx].append(i)
+    total = sum(len(l) for l in lists)
+    assert out["M"] == total and total > 20 * g.n
+    gr = out["tile_ranges"]
+    for t in range(T):
+        got = out["sorted_gauss"][gr[t, 0]:gr[t, 1]]
+        assert np.array_equal(got, np.asarray(lists[t], got.dtype)), f"tile {t}"
