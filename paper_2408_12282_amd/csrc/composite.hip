@@ -224,11 +224,12 @@ __global__ __launch_bounds__(256, C > 26 ? 2 : 3) void composite_bwd_kernel(
     }
     __syncthreads();
   }
-  // moment basis of pixel 64 w + 4 ks + g (FP32 B operand, K = 4 pixels per step)
+  // moment basis of pixel 64 w + 16 g + ks (FP32 B operand; K step ks takes
+  // one pixel from each lane group, so a lane's 16 pixels are contiguous)
   float bm[16];
 #pragma unroll
   for (int ks = 0; ks < 16; ks++) {
-    const int p = 64 * w + 4 * ks + g;
+    const int p = 64 * w + 16 * g + ks;
     const float x = (float)(p & 15) + 0.5f, y = (float)(p >> 4) + 0.5f;
     bm[ks] = col == 0 ? 1.f : col == 1 ? x : col == 2 ? y : col == 3 ? x * x : col == 4 ? x * y : col == 5 ? y * y : 0.f;
   }
@@ -311,8 +312,17 @@ __global__ __launch_bounds__(256, C > 26 ? 2 : 3) void composite_bwd_kernel(
 #pragma unroll
       for (int nc = 0; nc <= NBC; nc++) acc[nc] = cf32x4{0.f, 0.f, 0.f, 0.f};
       float gv[16];
+      {
+        const float4 *gr = reinterpret_cast<const float4 *>(&mat[(kBJ + col) * kMS + 64 * w + 16 * g]);
 #pragma unroll
-      for (int ks = 0; ks < 16; ks++) gv[ks] = mat[(kBJ + col) * kMS + 64 * w + 4 * ks + g];
+        for (int q = 0; q < 4; q++) {
+          const float4 v = gr[q];
+          gv[4 * q] = v.x;
+          gv[4 * q + 1] = v.y;
+          gv[4 * q + 2] = v.z;
+          gv[4 * q + 3] = v.w;
+        }
+      }
 #pragma unroll
       for (int kk = 0; kk < 2; kk++) {
         const float4 *wr = reinterpret_cast<const float4 *>(&mat[col * kMS + 64 * w + 32 * kk + 8 * g]);
