@@ -225,14 +225,13 @@ __global__ __launch_bounds__(256, C > 26 ? 2 : 3) void composite_bwd_kernel(
     __syncthreads();
   }
   // moment basis of pixel 64 w + 16 g + ks (FP32 B operand; K step ks takes
-  // one pixel from each lane group, so a lane's 16 pixels are contiguous)
-  float bm[16];
-#pragma unroll
-  for (int ks = 0; ks < 16; ks++) {
-    const int p = 64 * w + 16 * g + ks;
-    const float x = (float)(p & 15) + 0.5f, y = (float)(p >> 4) + 0.5f;
-    bm[ks] = col == 0 ? 1.f : col == 1 ? x : col == 2 ? y : col == 3 ? x * x : col == 4 ? x * y : col == 5 ? y * y : 0.f;
-  }
+  // one pixel from each lane group, so a lane's 16 pixels are contiguous):
+  // x = ks + 1/2 and y = 4 w + g + 1/2, so column col of the basis
+  // (1, x, y, x^2, xy, y^2) is mb0 + mb1 x + mb2 x^2 with per-lane constants
+  const float yb = (float)(4 * w + g) + 0.5f;
+  const float mb0 = col == 0 ? 1.f : col == 2 ? yb : col == 5 ? yb * yb : 0.f;
+  const float mb1 = col == 1 ? 1.f : col == 4 ? yb : 0.f;
+  const float mb2 = col == 3 ? 1.f : 0.f;
   const int top = (int)maxlast;
   // Batch fetch into registers: thread t < kBJ * R4 holds chunk t % R4 of
   // record t / R4 and, for chunk 0, the Gaussian's index and box.
@@ -337,8 +336,9 @@ __global__ __launch_bounds__(256, C > 26 ? 2 : 3) void composite_bwd_kernel(
       cf32x4 am = cf32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
       for (int ks = 0; ks < 16; ks += 2) {
-        acc[NBC] = __builtin_amdgcn_mfma_f32_16x16x4f32(gv[ks], bm[ks], acc[NBC], 0, 0, 0);
-        am = __builtin_amdgcn_mfma_f32_16x16x4f32(gv[ks + 1], bm[ks + 1], am, 0, 0, 0);
+        const float x0 = (float)ks + 0.5f, x1 = x0 + 1.f;
+        acc[NBC] = __builtin_amdgcn_mfma_f32_16x16x4f32(gv[ks], mb0 + x0 * (mb1 + x0 * mb2), acc[NBC], 0, 0, 0);
+        am = __builtin_amdgcn_mfma_f32_16x16x4f32(gv[ks + 1], mb0 + x1 * (mb1 + x1 * mb2), am, 0, 0, 0);
       }
       acc[NBC] += am;
       // D layout: lane (col, g) holds rows j = 4 g + i of column 16 nc + col
