@@ -195,10 +195,11 @@ def test_headline_300k_800(precision):
     assert e < (FWD_REL if precision == "fp32" else BF16_EMU_REL)
 
 
-@pytest.mark.parametrize("W,H", [(4096, 4096), (2500, 300)])
+@pytest.mark.parametrize("W,H", [(4096, 4096), (2500, 300), (500, 450)])
 def test_tile_lists_large_grids(W, H):
     """Tile lists on large tile grids (256 x 256 tiles: super-bins of 16 x 16
-    tiles; a wide 157 x 19 grid), checked for every tile against the order
+    tiles; a wide 157 x 19 grid: super-bins of 4 x 4; 32 x 29 tiles: 2 x 2),
+    checked for every tile against the order
     (float32 depth key, index) over the Gaussians whose tile rectangle holds
     the tile, built on the CPU from the GPU's own rectangles and depth keys
     (those two are checked against the oracle by the tests above)."""
@@ -217,7 +218,7 @@ def test_tile_lists_large_grids(W, H):
             for tx in range(x0, x1):
                 lists[ty * TX + tx].append(i)
     total = sum(len(l) for l in lists)
-    assert out["M"] == total and total > 20 * g.n
+    assert out["M"] == total and total > 10 * g.n
     gr = out["tile_ranges"]
     for t in range(T):
         got = out["sorted_gauss"][gr[t, 0]:gr[t, 1]]
