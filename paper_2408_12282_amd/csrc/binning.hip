@@ -431,10 +431,6 @@ __global__ __launch_bounds__(256) void tile_write_kernel(const uint32_t *__restr
   }
   if (threadIdx.x == 0) ranges[t] = make_uint2(start, run);
 }
-__global__ __launch_bounds__(256) void fill_u32_kernel(uint32_t *__restrict__ p, uint32_t v, uint32_t n) {
-  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) p[i] = v;
-}
 
 
 // ------------------------------------------------------------------ host side
@@ -508,9 +504,6 @@ void launch_tile_lists(uint32_t n, uint32_t cap, int TX, int TY, uint32_t *ka, u
                                        ranges);
 }
 
-void launch_fill_u32(uint32_t *p, uint32_t v, uint32_t n, hipStream_t st) {
-  if (n) fill_u32_kernel<<<cdiv(n, 256), 256, 0, st>>>(p, v, n);
-}
 
 
 }  // namespace sssgs

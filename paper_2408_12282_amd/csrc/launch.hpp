@@ -32,7 +32,6 @@ uint32_t scan_partials_needed(uint64_t n);
 void launch_radix_pass(const uint32_t *kin, const uint32_t *vin, uint32_t *kout, uint32_t *vout, uint32_t n_host,
                        const uint32_t *n_dev, int shift, uint32_t *hist, uint32_t *partials, hipStream_t st,
                        bool digit_major);
-void launch_fill_u32(uint32_t *p, uint32_t v, uint32_t n, hipStream_t st);
 // Tile lists (Sec. 3.1 binning): super-bin expansion of the depth-sorted
 // Gaussians, then the stable super-bin pass and the per-tile filtering into
 // tile-major (Gaussian index, tile id) lists with their ranges and the status word.
