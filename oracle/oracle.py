@@ -48,7 +48,7 @@ class OgLight(ct.Structure):
 
 class OgMlp(ct.Structure):
     _fields_ = [("in_dim", ct.c_int), ("in_pad", ct.c_int), ("width", ct.c_int), ("hidden", ct.c_int),
-                ("out_dim", ct.c_int), ("bf16", ct.c_int), ("params", _dp)]
+                ("out_dim", ct.c_int), ("bf16", ct.c_int), ("params", _dp), ("radiance_features", ct.c_int)]
 
 
 class OgOut(ct.Structure):
@@ -116,13 +116,16 @@ def _f64(a):
 
 def render(g, cam, light, mlp=None, bf16: bool = False, crop=None, drgb=None, dgbuf=None, dalpha=None,
            grads: bool = False, nthreads: int = 0, lists: bool = False, params64: Optional[dict] = None,
-           sens: bool = False):
+           sens: bool = False, radiance_features: bool = False):
     """Render one view (and optionally its backward) in FP64.
 
     ``g`` is a ``scene.Gaussians``; ``params64`` may override any of its arrays
     with float64 arrays (used by the finite-difference checks).  ``sens``
-    also fills the shading-sensitivity diagnostic ``rgb_sens``.  Returns a dict
-    of numpy arrays.
+    also fills the shading-sensitivity diagnostic ``rgb_sens``.
+    ``radiance_features`` (no per-pixel network): feature planes 0-2 are the
+    incident light and 3-5 the SSS radiance of a per-Gaussian network, and
+    Eq. 7 takes them from the composited buffers.  Returns a dict of numpy
+    arrays.
     """
     L = lib()
     n, F = g.n, g.feat_dim
@@ -144,7 +147,9 @@ def render(g, cam, light, mlp=None, bf16: bool = False, crop=None, drgb=None, dg
     mlp_params = None
     if mlp is not None:
         mlp_params = _f64(params64["mlp"]) if (params64 and "mlp" in params64) else _f64(mlp.params)
-        mp = OgMlp(mlp.in_dim, mlp.in_pad, mlp.width, mlp.hidden, mlp.out_dim, int(bf16), _p(mlp_params))
+        mp = OgMlp(mlp.in_dim, mlp.in_pad, mlp.width, mlp.hidden, mlp.out_dim, int(bf16), _p(mlp_params), 0)
+    elif radiance_features:
+        mp = OgMlp(0, 0, 0, 0, 0, 0, None, 1)
     o = {
         "rgb": np.zeros((3, H, W)), "gbuf": np.zeros((C, H, W)), "alpha": np.zeros((H, W)),
         "gbuf_abs": np.zeros((C, H, W)), "net_margin": np.zeros((H, W)), "rgb_sens": np.zeros((3, H, W)),

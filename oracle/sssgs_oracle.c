@@ -17,6 +17,11 @@
  *   - Sec. 3.2, Eq. 6: the residual network returning incident light and SSS
  *     radiance from a Fourier-encoded position plus directions.
  *   - Sec. 3.2, Eq. 7: L_out = sss L_sss + (1-sss)(f_s+f_d) L_in (n.w_i).
+ *   - Pipeline figure and appendix "Network": with the network evaluated per
+ *     Gaussian instead (the per-Gaussian network itself is in
+ *     gaussian_mlp.py), its incident light and SSS radiance are blended like
+ *     any other channel and Eq. 7 takes them from the composited buffers
+ *     (og_mlp.radiance_features).
  *   - Sec. 3.2, "Per-Pixel Deferred Shading": properties are composited into
  *     image buffers first; the BRDF is evaluated per pixel at the surface point
  *     obtained by back-projecting the composited depth.
@@ -73,6 +78,9 @@ typedef struct {
 typedef struct {
   int in_dim, in_pad, width, hidden, out_dim, bf16; /* params NULL: no network */
   const double *params;
+  /* 1: no per-pixel network; feature channels 0-2 hold the blended incident
+     light and 3-5 the blended SSS radiance of the per-Gaussian network */
+  int radiance_features;
 } og_mlp;
 
 typedef struct {
@@ -436,7 +444,7 @@ static size_t mlp_layer_offset(const og_mlp *m, int layer) {
 
 static double rb(const og_mlp *m, double v) { return m->bf16 ? og_round_bf16(v) : v; }
 
-static void shade_pixel(const og_cam *cam, const og_light *light, const og_mlp *mlp, int C, int F,
+static void shade_pixel(const og_cam *cam, const og_light *light, const og_mlp *mlp, int blend, int C, int F,
                         const double *G, double T, double uc, double vc, shade_t *S) {
   memset(S, 0, sizeof(*S));
   S->a = 1.0 - T;
@@ -488,6 +496,16 @@ static void shade_pixel(const og_cam *cam, const og_light *light, const og_mlp *
     S->fs[c] = S->D * S->F[c] * S->Gv * S->Q;
     S->fd[c] = (1.0 - m) * b / M_PI;
   }
+  if (blend) {
+    /* Eq. 7 with the composited radiances of the per-Gaussian network */
+    double sss = S->gbar[CH_SSS];
+    for (int c = 0; c < 3; c++) {
+      S->Lin[c] = S->gbar[CH_FEAT + c];
+      S->Lsss[c] = S->gbar[CH_FEAT + 3 + c];
+      S->L[c] = sss * S->Lsss[c] + (1.0 - sss) * (S->fs[c] + S->fd[c]) * S->Lin[c] * S->cosI;
+    }
+    return;
+  }
   if (!mlp) {
     S->li2 = dot3(S->vi, S->vi);
     if (S->li2 < 1e-12) S->li2 = 1e-12;
@@ -536,8 +554,8 @@ static void shade_pixel(const og_cam *cam, const og_light *light, const og_mlp *
 
 /* Backward of one pixel's shading.  gL = dLoss/d(rgb) (3).  Writes dG (C) and
    returns dLoss/dT_final; accumulates network-parameter gradients into dmlp. */
-static double shade_pixel_bwd(const og_cam *cam, const og_light *light, const og_mlp *mlp, int C, int F,
-                              const shade_t *S, const double *gL, double *dG, double *dmlp) {
+static double shade_pixel_bwd(const og_cam *cam, const og_light *light, const og_mlp *mlp, int blend, int C,
+                              int F, const shade_t *S, const double *gL, double *dG, double *dmlp) {
   for (int k = 0; k < C; k++) dG[k] = 0;
   if (S->background) return 0.0;
   double a = S->a;
@@ -548,7 +566,19 @@ static double shade_pixel_bwd(const og_cam *cam, const og_light *light, const og
   for (int c = 0; c < 3; c++) { dA += gL[c] * S->L[c]; gLo[c] = a * gL[c]; }
   double dfs[3], dfd[3], dLin[3] = {0, 0, 0}, dcos = 0, dx[3] = {0, 0, 0}, dwo[3] = {0, 0, 0}, dwi[3] = {0, 0, 0};
   double dvi[3] = {0, 0, 0};
-  if (!mlp) {
+  if (blend) {
+    double sss = S->gbar[CH_SSS], dsss = 0;
+    for (int c = 0; c < 3; c++) {
+      double B = S->fs[c] + S->fd[c];
+      dsss += gLo[c] * (S->Lsss[c] - B * S->Lin[c] * S->cosI);
+      dfs[c] = gLo[c] * (1.0 - sss) * S->Lin[c] * S->cosI;
+      dfd[c] = dfs[c];
+      dcos += gLo[c] * (1.0 - sss) * B * S->Lin[c];
+      dgbar[CH_FEAT + c] += gLo[c] * (1.0 - sss) * B * S->cosI;
+      dgbar[CH_FEAT + 3 + c] += gLo[c] * sss;
+    }
+    dgbar[CH_SSS] += dsss;
+  } else if (!mlp) {
     for (int c = 0; c < 3; c++) {
       dfs[c] = gLo[c] * S->Lin[c] * S->cosI;
       dfd[c] = dfs[c];
@@ -734,8 +764,10 @@ int og_render(const og_gauss *g, const og_cam *cam, const og_light *light, const
   const int n = g->n, W = cam->width, H = cam->height;
   const int TX = (W + TILE - 1) / TILE, TY = (H + TILE - 1) / TILE, T = TX * TY;
   const int F = g->feat_dim, C = og_channels(F);
-  const og_mlp *mlp = (mlp_in && mlp_in->params) ? mlp_in : NULL;
+  const int blend = mlp_in && mlp_in->radiance_features;
+  const og_mlp *mlp = (!blend && mlp_in && mlp_in->params) ? mlp_in : NULL;
   if (C > MAXC) return -3;
+  if (blend && F < 6) return -3;
   if (mlp && (mlp->width > MAXW || mlp->in_pad > MAXIN || mlp->out_dim != 6 || mlp->hidden + 1 > 8 ||
               mlp->in_dim != F + NPE + 6))
     return -3;
@@ -893,13 +925,13 @@ int og_render(const og_gauss *g, const og_cam *cam, const og_light *light, const
         if (out->alpha) out->alpha[pix] = 1.0 - Tr;
         if (out->n_contrib) out->n_contrib[pix] = last;
         if (out->pix_flag) out->pix_flag[pix] = flag;
-        shade_pixel(cam, light, mlp, C, F, Gp, Tr, uc, vc, S);
+        shade_pixel(cam, light, mlp, blend, C, F, Gp, Tr, uc, vc, S);
         if (out->net_margin) out->net_margin[pix] = (mlp && !S->background) ? S->margin : INFINITY;
         if (out->rgb_sens) {
           for (int c = 0; c < 3; c++) {
             double e[3] = {0, 0, 0}, dGs[MAXC];
             e[c] = 1.0;
-            double dTs = shade_pixel_bwd(cam, light, mlp, C, F, S, e, dGs, NULL);
+            double dTs = shade_pixel_bwd(cam, light, mlp, blend, C, F, S, e, dGs, NULL);
             double sacc = fabs(dTs) * Tr;
             for (int k = 0; k < C; k++) sacc += fabs(dGs[k]) * (fabs(Gp[k]) + Ga[k]);
             out->rgb_sens[(size_t)c * H * W + pix] = sacc;
@@ -910,7 +942,7 @@ int og_render(const og_gauss *g, const og_cam *cam, const og_light *light, const
         /* ---- backward ---- */
         double gL[3], dG[MAXC];
         for (int c = 0; c < 3; c++) gL[c] = up->drgb ? up->drgb[(size_t)c * H * W + pix] : 0;
-        double dT = shade_pixel_bwd(cam, light, mlp, C, F, S, gL,
+        double dT = shade_pixel_bwd(cam, light, mlp, blend, C, F, S, gL,
                                     dG, macc ? macc + (size_t)tid * np : NULL);
         if (up->dgbuf) for (int k = 0; k < C; k++) dG[k] += up->dgbuf[(size_t)k * H * W + pix];
         if (up->dalpha) dT -= up->dalpha[pix];

@@ -190,6 +190,32 @@ def make_mlp(feat_dim: int, width: int = 64, hidden: int = 3, out_dim: int = 6, 
     return MLP(in_dim, width, hidden, out_dim, params)
 
 
+# Per-Gaussian network of the pipeline figure / appendix "Network": layer
+# shapes (rows, columns) of the packed parameter vector, in order: three trunk
+# layers, the incident-light head's hidden and output layers, the SSS head.
+GMLP_IN = 42
+GMLP_LAYERS = ((64, GMLP_IN), (32, 64), (32, 32), (32, 32), (3, 32), (3, 32))
+
+
+def gmlp_param_count() -> int:
+    return sum(r * c + r for r, c in GMLP_LAYERS)
+
+
+def make_gaussian_mlp(seed: int = 0) -> np.ndarray:
+    """Packed float32 parameters W [rows, cols] then b [rows] per layer of
+    GMLP_LAYERS: He-normal weights N(0, 2/fan_in), biases N(0, 0.1)."""
+    rng = np.random.default_rng(np.random.SeedSequence([seed, 0x474D4C50]))
+    chunks: List[np.ndarray] = []
+    for r, c in GMLP_LAYERS:
+        chunks += [rng.normal(0.0, math.sqrt(2.0 / c), size=(r, c)).ravel(), rng.normal(0.0, 0.1, size=r)]
+    return np.concatenate(chunks).astype(np.float32)
+
+
+def make_visibility(n: int, seed: int = 0) -> np.ndarray:
+    """Per-Gaussian light visibility v, U[0, 1] float32."""
+    return np.random.default_rng(np.random.SeedSequence([seed, 0x564953])).uniform(0.0, 1.0, n).astype(np.float32)
+
+
 def fibonacci_cameras(k: int, radius: float, width: int, height: int, fov_deg: float = 50.0):
     """k cameras on a Fibonacci sphere of the given radius, all looking at the origin."""
     cams = []
