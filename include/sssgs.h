@@ -126,6 +126,16 @@ typedef struct {
                                BF16 operands on the matrix cores with FP32
                                accumulation.  Everything else is FP32. */
   int32_t accumulate_grads; /* backward: 0 overwrite gradient outputs, 1 add */
+  int32_t radiance_features; /* 1: the radiances of Eq. 7 come from a per-Gaussian
+                               network (sssgs_gaussian_mlp_forward) passed as the
+                               Gaussians' eight feature planes: the deferred
+                               shading takes the incident light from composited
+                               feature planes 0-2 and the SSS radiance from planes
+                               3-5 (each divided by alpha like every channel).
+                               Requires feat_dim = 8 (the 18-plane G-buffer) and
+                               no per-pixel network (SSSGS_ERR_UNSUPPORTED /
+                               SSSGS_ERR_INVALID_ARG otherwise).  0: per-pixel
+                               network or point-light fall-off. */
 } sssgs_options;
 
 /* Number of floats in sssgs_mlp.params. */
@@ -192,6 +202,41 @@ sssgs_status sssgs_render_backward(const sssgs_gaussians *g, const sssgs_camera 
 /* Image loss of the training objective (Appendix "Losses": the L1 part),
    over `count` values: *loss_out (device) += sum |pred - target| * scale and
    dL_dpred = sign(pred - target) * scale (sign(0) = 0).  loss_out may be NULL. */
+/* Per-Gaussian network (pipeline figure: Eq. 6 evaluated for each Gaussian
+   before rasterisation, Sec. 3.2; layer sizes from the appendix "Network").
+   Input per Gaussian (42 values): normal (the shortest rotation axis turned
+   toward the camera, Sec. 3.1) | unit quaternion | scale exp(log_scale) |
+   direction to the light | direction to the camera | distance to the light |
+   visibility | sin, cos(2^k pi mu) for k = 0..3.  Trunk of 64, 32, 32 units with
+   Leaky-ReLU (slope 0.01); incident-light head: 32 units (Leaky-ReLU) then 3
+   outputs through a ReLU; SSS head: 3 outputs through a sigmoid.  params packs
+   per layer W [rows][cols] row-major then b [rows], layers in the order trunk
+   64x42, 32x64, 32x32, incident 32x32, 3x32, SSS 3x32
+   (sssgs_gaussian_mlp_param_count() floats, device).
+   Output out_features [8][n] (device): incident light (3) | SSS radiance (3) |
+   visibility | 1 -- the feature planes of a render with feat_dim = 8 and
+   options.radiance_features = 1, whose composited constant plane is alpha.
+   Only n, means, log_scales and quats of `g` are read; visibility [n] (device).
+   The light's position is used, not its intensity.  `workspace` (device,
+   caller-owned) holds sssgs_gaussian_mlp_workspace_bytes(n) bytes.  FP32. */
+int64_t sssgs_gaussian_mlp_param_count(void);
+size_t sssgs_gaussian_mlp_workspace_bytes(int32_t n);
+sssgs_status sssgs_gaussian_mlp_forward(const sssgs_gaussians *g, const sssgs_camera *cam, const sssgs_light *light,
+                                        const float *visibility, const float *params, void *workspace,
+                                        size_t workspace_bytes, float *out_features, void *stream);
+/* Backward of sssgs_gaussian_mlp_forward (recomputes the forward; nothing is
+   kept between the calls).  dL_dfeatures [8][n]: gradient of the feature
+   planes, e.g. the `features` gradient of sssgs_render_backward.  ADDS the
+   network's contribution to dL_dmeans [3][n], dL_dlog_scales [3][n] and
+   dL_dquats [4][n] (the render backward writes them first); writes (accumulate
+   = 0) or adds (1) dL_dvisibility [n] and dL_dparams.  The weight gradient is
+   summed in a fixed order (deterministic).  All device arrays. */
+sssgs_status sssgs_gaussian_mlp_backward(const sssgs_gaussians *g, const sssgs_camera *cam, const sssgs_light *light,
+                                         const float *visibility, const float *params, const float *dL_dfeatures,
+                                         void *workspace, size_t workspace_bytes, float *dL_dmeans,
+                                         float *dL_dlog_scales, float *dL_dquats, float *dL_dvisibility,
+                                         float *dL_dparams, int32_t accumulate, void *stream);
+
 sssgs_status sssgs_l1_loss(const float *pred, const float *target, int64_t count, float scale, float *loss_out,
                            float *dL_dpred, void *stream);
 

@@ -164,6 +164,18 @@ def forward(x, params):
     return feats, acts
 
 
+def forward_bound(x, params):
+    """Magnitude of the terms of each output's last sum [6, N]: |W| |a| + |b|
+    of the output layer (the sigmoid planes times the sigmoid's slope), the
+    scale of that sum's rounding error.  A diagnostic for the tolerance of an
+    FP32 evaluation, not part of the method."""
+    L = unpack(params)
+    _, a = forward(x, params)
+    bl = np.abs(a["e"]) @ np.abs(L[4][0]).T + np.abs(L[4][1])
+    bs = (np.abs(a["h3"]) @ np.abs(L[5][0]).T + np.abs(L[5][1])) * a["lsss"] * (1.0 - a["lsss"])
+    return np.concatenate([bl, bs], axis=1).T
+
+
 def backward(dfeat, params, acts, cache, cam_center, light_pos):
     """Gradients given dL/d(features) [8, N]: dict with 'params' (packed),
     'means' [3, N], 'log_scales' [3, N], 'quats' [4, N], 'visibility' [N]."""

@@ -10,7 +10,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libsssgs.so")
 SOURCES = ["abi.hip", "project.hip", "binning.hip", "composite.hip", "shade.hip", "shade_bwd.hip", "mlp_prep.hip",
-           "mlp_wgrad.hip", "losses.hip"]
+           "mlp_wgrad.hip", "losses.hip", "gmlp.hip"]
 FLAGS = ["-O3", "--offload-arch=gfx950", "-fPIC", "-std=c++17", "-munsafe-fp-atomics",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-I", os.path.join(ROOT, "include")]
@@ -24,7 +24,7 @@ FLAGS = ["-O3", "--offload-arch=gfx950", "-fPIC", "-std=c++17", "-munsafe-fp-ato
 # accumulators across loops (the accumulator-register form gave wrong sums after
 # such loops in these kernels).
 VGPR_FORM = ["-mllvm", "-amdgpu-mfma-vgpr-form"]
-EXTRA = {"composite.hip": VGPR_FORM, "mlp_wgrad.hip": VGPR_FORM, "shade_bwd.hip": VGPR_FORM}
+EXTRA = {"composite.hip": VGPR_FORM, "mlp_wgrad.hip": VGPR_FORM, "shade_bwd.hip": VGPR_FORM, "gmlp.hip": VGPR_FORM}
 
 
 def build(jobs: int = 8, verbose: bool = False) -> str:

@@ -20,11 +20,11 @@ thread_local std::string g_last_error;
 // ---- optional per-stage timing with HIP events on the caller's stream
 enum Stage {
   kStProject = 0, kStSortDepth, kStExpand, kStSortTiles, kStCompositeFwd, kStShadeFwd,
-  kStShadeBwd, kStMlpWgrad, kStMlpReduce, kStCompositeBwd, kStProjectBwd, kStCount
+  kStShadeBwd, kStMlpWgrad, kStMlpReduce, kStCompositeBwd, kStProjectBwd, kStGmlpFwd, kStGmlpBwd, kStCount
 };
 const char *kStageNames[kStCount] = {"project_fwd", "sort_depth", "expand",        "sort_tiles",
                                      "composite_fwd", "shade_fwd", "shade_bwd",     "mlp_wgrad",
-                                     "mlp_reduce",  "composite_bwd", "project_bwd"};
+                                     "mlp_reduce",  "composite_bwd", "project_bwd", "gmlp_fwd", "gmlp_bwd"};
 struct TimerRec {
   int stage;
   hipEvent_t a, b;
@@ -211,6 +211,12 @@ sssgs_status check_common(const sssgs_gaussians *g, const sssgs_camera *cam, con
     net = opt->precision == SSSGS_PREC_BF16 ? 2 : 1;
     width = mlp->width;
   }
+  if (!(opt->radiance_features == 0 || opt->radiance_features == 1))
+    return fail(SSSGS_ERR_INVALID_ARG, "radiance_features must be 0 or 1");
+  if (opt->radiance_features) {
+    if (net) return fail(SSSGS_ERR_INVALID_ARG, "radiance_features excludes the per-pixel network");
+    if (g->feat_dim != 8) return fail(SSSGS_ERR_UNSUPPORTED, "radiance_features needs feat_dim 8");
+  }
   return SSSGS_OK;
 }
 
@@ -295,7 +301,7 @@ template <bool BWD>
 bool shade_dispatch(int F, int net, int width, const ShadeArgs &a, int nblocks, hipStream_t st,
                     const MultiLight *ml = nullptr) {
   const int in_pad = in_pad_of(F + kNumPE + 6);
-  const int w = net ? width : 64;
+  const int w = (net == 1 || net == 2) ? width : 64;
 #define SSSGS_TRY(F_, NET_, W_, P_)                                              \
   if (F == F_ && net == NET_ && w == W_ && in_pad == P_) {                     \
     if constexpr (BWD) launch_shade_bwd_t<F_, NET_, W_, P_>(a, nblocks, st);   \
@@ -448,7 +454,7 @@ sssgs_status forward_impl(const sssgs_gaussians *g, const sssgs_camera *cam, con
           ml.intensity[k][c] = lights[k0 + k].intensity[c];
           ml.weight[k][c] = weights ? weights[(k0 + k) * 3 + c] : 1.f;
         }
-      if (!shade_dispatch<false>(g->feat_dim, net, width, sa, 0, st, &ml))
+      if (!shade_dispatch<false>(g->feat_dim, opt->radiance_features ? 3 : net, width, sa, 0, st, &ml))
         return fail(SSSGS_ERR_UNSUPPORTED, "no shading kernel for this configuration");
     }
   }
@@ -551,7 +557,7 @@ sssgs_status sssgs_render_backward(const sssgs_gaussians *g, const sssgs_camera 
     }
   } else {
     Scope sc(kStShadeBwd, st);
-    if (!shade_dispatch<true>(g->feat_dim, net, width, sa, nblk, st))
+    if (!shade_dispatch<true>(g->feat_dim, opt->radiance_features ? 3 : net, width, sa, nblk, st))
       return fail(SSSGS_ERR_UNSUPPORTED, "no shading kernel for this configuration");
     if (net) parts = shade_bwd_grid(net, width, ip, L.T, nblk);
   }
@@ -577,6 +583,100 @@ sssgs_status sssgs_render_backward(const sssgs_gaussians *g, const sssgs_camera 
     project_bwd(g->feat_dim, g->sh_degree == 3, proj_in(g), ca, at<float>(ws, L.gacc), go, st);
   }
   return check_hip("backward launch");
+}
+
+// ---- per-Gaussian network
+
+int64_t sssgs_gaussian_mlp_param_count(void) { return gmlp_param_count(); }
+
+namespace {
+struct GmlpLayout {
+  size_t wt, part, mid, total;
+};
+GmlpLayout gmlp_layout(int32_t n) {
+  GmlpLayout L;
+  const size_t np = (size_t)gmlp_param_count();
+  size_t p = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at_ = p;
+    p += (bytes + 255) / 256 * 256;
+    return at_;
+  };
+  L.wt = take(np * 4);
+  L.part = take((size_t)gmlp_bwd_grid(n) * np * 4);
+  L.mid = take((size_t)reduce_scratch_floats((int)np) * 4);
+  L.total = p;
+  return L;
+}
+
+sssgs_status gmlp_check(const sssgs_gaussians *g, const sssgs_camera *cam, const sssgs_light *light,
+                        const float *visibility, const float *params, void *ws, size_t ws_bytes) {
+  if (!g || !cam || !light || !params || !ws) return fail(SSSGS_ERR_INVALID_ARG, "null argument");
+  if (g->n < 0) return fail(SSSGS_ERR_INVALID_ARG, "n < 0");
+  if (g->n > 0 && (!g->means || !g->log_scales || !g->quats || !visibility))
+    return fail(SSSGS_ERR_INVALID_ARG, "null Gaussian plane or visibility");
+  if (ws_bytes < gmlp_layout(g->n).total) return fail(SSSGS_ERR_INVALID_ARG, "workspace too small");
+  return SSSGS_OK;
+}
+
+GmlpArgs gmlp_args(const sssgs_gaussians *g, const sssgs_camera *cam, const sssgs_light *light,
+                   const float *visibility, const float *params, void *ws) {
+  GmlpArgs a;
+  memset(&a, 0, sizeof(a));
+  a.n = g->n;
+  a.means = g->means; a.log_scales = g->log_scales; a.quats = g->quats; a.vis = visibility;
+  for (int k = 0; k < 3; k++) {
+    a.cam[k] = (float)(-((double)cam->R[k] * cam->t[0] + (double)cam->R[3 + k] * cam->t[1] +
+                         (double)cam->R[6 + k] * cam->t[2]));
+    a.light[k] = light->pos[k];
+  }
+  a.params = params;
+  a.wt = at<float>(ws, gmlp_layout(g->n).wt);
+  return a;
+}
+}  // namespace
+
+size_t sssgs_gaussian_mlp_workspace_bytes(int32_t n) { return n < 0 ? 0 : gmlp_layout(n).total; }
+
+sssgs_status sssgs_gaussian_mlp_forward(const sssgs_gaussians *g, const sssgs_camera *cam, const sssgs_light *light,
+                                        const float *visibility, const float *params, void *ws, size_t ws_bytes,
+                                        float *out_features, void *stream) {
+  sssgs_status s = gmlp_check(g, cam, light, visibility, params, ws, ws_bytes);
+  if (s != SSSGS_OK) return s;
+  if (g->n > 0 && !out_features) return fail(SSSGS_ERR_INVALID_ARG, "null out_features");
+  hipStream_t st = (hipStream_t)stream;
+  GmlpArgs a = gmlp_args(g, cam, light, visibility, params, ws);
+  a.feat = out_features;
+  Scope sc(kStGmlpFwd, st);
+  launch_gmlp_prep(params, at<float>(ws, gmlp_layout(g->n).wt), st);
+  launch_gmlp_fwd(a, st);
+  return check_hip("gaussian network forward launch");
+}
+
+sssgs_status sssgs_gaussian_mlp_backward(const sssgs_gaussians *g, const sssgs_camera *cam, const sssgs_light *light,
+                                         const float *visibility, const float *params, const float *dL_dfeatures,
+                                         void *ws, size_t ws_bytes, float *dL_dmeans, float *dL_dlog_scales,
+                                         float *dL_dquats, float *dL_dvisibility, float *dL_dparams,
+                                         int32_t accumulate, void *stream) {
+  sssgs_status s = gmlp_check(g, cam, light, visibility, params, ws, ws_bytes);
+  if (s != SSSGS_OK) return s;
+  if (!(accumulate == 0 || accumulate == 1)) return fail(SSSGS_ERR_INVALID_ARG, "accumulate must be 0 or 1");
+  if (!dL_dparams) return fail(SSSGS_ERR_INVALID_ARG, "null dL_dparams");
+  if (g->n > 0 && (!dL_dfeatures || !dL_dmeans || !dL_dlog_scales || !dL_dquats || !dL_dvisibility))
+    return fail(SSSGS_ERR_INVALID_ARG, "null gradient array");
+  hipStream_t st = (hipStream_t)stream;
+  const GmlpLayout L = gmlp_layout(g->n);
+  GmlpArgs a = gmlp_args(g, cam, light, visibility, params, ws);
+  a.dfeat = dL_dfeatures;
+  a.d_means = dL_dmeans; a.d_log_scales = dL_dlog_scales; a.d_quats = dL_dquats; a.d_vis = dL_dvisibility;
+  a.partials = at<float>(ws, L.part);
+  a.accumulate = accumulate;
+  Scope sc(kStGmlpBwd, st);
+  launch_gmlp_prep(params, at<float>(ws, L.wt), st);
+  launch_gmlp_bwd(a, st);
+  launch_reduce_partials(a.partials, gmlp_bwd_grid(g->n), gmlp_param_count(), at<float>(ws, L.mid), dL_dparams,
+                         accumulate, st);
+  return check_hip("gaussian network backward launch");
 }
 
 sssgs_status sssgs_l1_loss(const float *pred, const float *target, int64_t count, float scale, float *loss_out,

@@ -1,0 +1,524 @@
+// gmlp.hip -- the per-Gaussian network of the pipeline figure (Eq. 6
+// evaluated for each Gaussian, Sec. 3.2; layer sizes from the appendix
+// "Network"), forward and backward, FP32.
+//
+// Input, 42 values per Gaussian: normal (shortest rotation axis turned toward
+// the camera) 3 | unit quaternion 4 | scale 3 | direction to the light 3 |
+// direction to the camera 3 | light distance 1 | visibility 1 | sin, cos of
+// 2^k pi mu for k = 0..3 (24).  Trunk 64-32-32 with Leaky-ReLU (slope 0.01);
+// incident-light head 32 (Leaky-ReLU) -> 3 (ReLU); SSS head -> 3 (sigmoid).
+// Output: eight feature planes [8][n] = L_in (3) | L_sss (3) | v | 1, which
+// the projection and compositing blend like any other channel.
+//
+// One lane per Gaussian, one wave per workgroup.  Weights are wave-uniform and
+// come through scalar loads: the forward walks the layer input (rolled loop
+// over the input index, the input read from the lane's own LDS column) and
+// keeps all outputs of the layer in registers, which needs the weights
+// transposed ([cols][rows], prepared once per call); the backward walks the
+// output gradient the same way with the weights as stored ([rows][cols]).
+// The weight gradient sum_g dz[o][g] act[i][g] over a wave's 64 Gaussians is
+// a 16x16x4 FP32 matrix-core product with K = Gaussians, read from the LDS
+// columns; every wave keeps its sums in registers over its chunks and writes
+// one partial row, reduced in fixed order afterwards.
+#include "launch.hpp"
+
+namespace sssgs {
+
+namespace {
+
+typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4;
+
+constexpr int kGIn = 42;
+constexpr float kSlope = 0.01f;
+constexpr int kLS = 66;  // LDS row stride (floats): conflict-free for own-column and MFMA operand reads
+
+// Packed parameter layout: per layer W [rows][cols] then b [rows].
+struct GL { int rows, cols, w, b; };
+constexpr GL mk(int rows, int cols, int off) { return GL{rows, cols, off, off + rows * cols}; }
+constexpr GL kL0 = mk(64, kGIn, 0);
+constexpr GL kL1 = mk(32, 64, kL0.b + 64);
+constexpr GL kL2 = mk(32, 32, kL1.b + 32);
+constexpr GL kLi = mk(32, 32, kL2.b + 32);
+constexpr GL kLl = mk(3, 32, kLi.b + 32);
+constexpr GL kLs = mk(3, 32, kLl.b + 3);
+constexpr int kGParams = kLs.b + 3;
+static_assert(kGParams == 7142, "per-Gaussian network parameter count");
+
+// Weights and biases are read through the constant address space: with a
+// wave-uniform index the compiler issues scalar loads (SGPR operands of the
+// FMAs) instead of per-lane vector loads.
+typedef const __attribute__((address_space(4))) float *cptr;
+__device__ __forceinline__ cptr as_const(const float *p) { return (cptr)p; }
+
+__device__ __forceinline__ float lrelu(float z) { return z > 0.f ? z : kSlope * z; }
+__device__ __forceinline__ float lrelu_d(float h) { return h > 0.f ? 1.f : kSlope; }
+
+// acc[r] = b[r] + sum_i W[r][i] in[i]; wt = W transposed ([COLS][ROWS]),
+// in = the lane's LDS column (row stride kLS).
+template <int ROWS, int COLS>
+__device__ __forceinline__ void layer_fwd(cptr wt, cptr b, const float *in, float (&acc)[ROWS]) {
+#pragma unroll
+  for (int r = 0; r < ROWS; r++) acc[r] = b[r];
+#pragma unroll 2
+  for (int i = 0; i < COLS; i++) {
+    const float xi = in[i * kLS];
+#pragma unroll
+    for (int r = 0; r < ROWS; r++) acc[r] = __fmaf_rn(wt[i * ROWS + r], xi, acc[r]);
+  }
+}
+
+// d[c] = sum_r W[r][c] dz[r]; W as stored ([ROWS][COLS]), dz = the lane's LDS column.
+template <int ROWS, int COLS>
+__device__ __forceinline__ void layer_bwd(cptr w, const float *dz, float (&d)[COLS]) {
+#pragma unroll
+  for (int c = 0; c < COLS; c++) d[c] = 0.f;
+#pragma unroll 2
+  for (int r = 0; r < ROWS; r++) {
+    const float g = dz[r * kLS];
+#pragma unroll
+    for (int c = 0; c < COLS; c++) d[c] = __fmaf_rn(w[r * COLS + c], g, d[c]);
+  }
+}
+
+template <int N>
+__device__ __forceinline__ void put_col(float *col, int row0, const float (&v)[N]) {
+#pragma unroll
+  for (int k = 0; k < N; k++) col[(row0 + k) * kLS] = v[k];
+}
+
+// The per-Gaussian quantities the input vector and its backward are built from.
+struct GIn {
+  float mu[3], qn[4], qlen, s[3], wi[3], dl, wo[3], dc, v, sign, nrm[3];
+  int kmin;
+};
+
+__device__ __forceinline__ void gaussian_input(const GmlpArgs &A, int i, GIn &G) {
+  const int n = A.n;
+  for (int k = 0; k < 3; k++) G.mu[k] = A.means[k * n + i];
+  float q[4];
+  for (int k = 0; k < 4; k++) q[k] = A.quats[k * n + i];
+  G.qlen = sqrtf(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
+  for (int k = 0; k < 4; k++) G.qn[k] = q[k] / G.qlen;
+  const float w = G.qn[0], x = G.qn[1], y = G.qn[2], z = G.qn[3];
+  float R[9];
+  R[0] = 1.f - 2.f * (y * y + z * z); R[1] = 2.f * (x * y - w * z); R[2] = 2.f * (x * z + w * y);
+  R[3] = 2.f * (x * y + w * z); R[4] = 1.f - 2.f * (x * x + z * z); R[5] = 2.f * (y * z - w * x);
+  R[6] = 2.f * (x * z - w * y); R[7] = 2.f * (y * z + w * x); R[8] = 1.f - 2.f * (x * x + y * y);
+  float ls[3];
+  for (int k = 0; k < 3; k++) ls[k] = A.log_scales[k * n + i];
+  // shortest axis: first minimum of the log-scales
+  G.kmin = 0;
+  float best = ls[0];
+  if (ls[1] < best) { G.kmin = 1; best = ls[1]; }
+  if (ls[2] < best) G.kmin = 2;
+  for (int k = 0; k < 3; k++) G.s[k] = expf(ls[k]);
+  // side of the camera in FP64 (the sign is a decision; keep its margin small)
+  {
+    double qd[4], ql = 0.0;
+    for (int k = 0; k < 4; k++) { qd[k] = q[k]; ql += qd[k] * qd[k]; }
+    ql = sqrt(ql);
+    for (int k = 0; k < 4; k++) qd[k] /= ql;
+    const double W_ = qd[0], X = qd[1], Y = qd[2], Z = qd[3];
+    double col[3];
+    if (G.kmin == 0) { col[0] = 1.0 - 2.0 * (Y * Y + Z * Z); col[1] = 2.0 * (X * Y + W_ * Z); col[2] = 2.0 * (X * Z - W_ * Y); }
+    else if (G.kmin == 1) { col[0] = 2.0 * (X * Y - W_ * Z); col[1] = 1.0 - 2.0 * (X * X + Z * Z); col[2] = 2.0 * (Y * Z + W_ * X); }
+    else { col[0] = 2.0 * (X * Z + W_ * Y); col[1] = 2.0 * (Y * Z - W_ * X); col[2] = 1.0 - 2.0 * (X * X + Y * Y); }
+    double d = 0.0;
+    for (int k = 0; k < 3; k++) d += col[k] * ((double)A.cam[k] - (double)G.mu[k]);
+    G.sign = d < 0.0 ? -1.f : 1.f;
+  }
+  // column kmin of R by 0/1 weights (exact; no indexing by kmin)
+  const float m0 = G.kmin == 0 ? 1.f : 0.f, m1 = G.kmin == 1 ? 1.f : 0.f, m2 = G.kmin == 2 ? 1.f : 0.f;
+  for (int k = 0; k < 3; k++) G.nrm[k] = G.sign * (m0 * R[3 * k] + m1 * R[3 * k + 1] + m2 * R[3 * k + 2]);
+  float u[3], uo[3];
+  for (int k = 0; k < 3; k++) {
+    u[k] = A.light[k] - G.mu[k];
+    uo[k] = A.cam[k] - G.mu[k];
+  }
+  G.dl = sqrtf(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+  G.dc = sqrtf(uo[0] * uo[0] + uo[1] * uo[1] + uo[2] * uo[2]);
+  const float il = 1.f / fmaxf(G.dl, 1e-12f), ic = 1.f / fmaxf(G.dc, 1e-12f);
+  for (int k = 0; k < 3; k++) {
+    G.wi[k] = u[k] * il;
+    G.wo[k] = uo[k] * ic;
+  }
+  G.v = A.vis[i];
+}
+
+// The 42 input values into the lane's LDS column (rows row0 ..).
+__device__ __forceinline__ void write_input(const GIn &G, float *col, int row0) {
+  float *c = col + row0 * kLS;
+  for (int k = 0; k < 3; k++) c[k * kLS] = G.nrm[k];
+  for (int k = 0; k < 4; k++) c[(3 + k) * kLS] = G.qn[k];
+  for (int k = 0; k < 3; k++) c[(7 + k) * kLS] = G.s[k];
+  for (int k = 0; k < 3; k++) c[(10 + k) * kLS] = G.wi[k];
+  for (int k = 0; k < 3; k++) c[(13 + k) * kLS] = G.wo[k];
+  c[16 * kLS] = G.dl;
+  c[17 * kLS] = G.v;
+#pragma unroll
+  for (int oct = 0; oct < 4; oct++) {
+    const float sc = (float)(1 << oct);
+#pragma unroll
+    for (int ax = 0; ax < 3; ax++) {
+      c[(18 + 6 * oct + ax) * kLS] = sinpif(sc * G.mu[ax]);
+      c[(21 + 6 * oct + ax) * kLS] = cospif(sc * G.mu[ax]);
+    }
+  }
+}
+
+// ------------------------------------------------------------------ forward
+
+// Rows of the forward's LDS column: the layer input (up to 64 rows) and, for
+// the heads, the trunk output at 0..31 and the incident hidden layer at 32..63.
+__global__ __launch_bounds__(64) void gmlp_fwd_kernel(GmlpArgs A) {
+  __shared__ float lds[64 * kLS];
+  const int lane = threadIdx.x;
+  const int i = blockIdx.x * 64 + lane;
+  const bool live = i < A.n;
+  const int gi = live ? i : 0;
+  float *col = lds + lane;
+  const cptr wt = as_const(A.wt), P = as_const(A.params);
+  GIn G;
+  gaussian_input(A, gi, G);
+  write_input(G, col, 0);
+  {
+    float h[64];
+    layer_fwd<64, kGIn>(wt + kL0.w, P + kL0.b, col, h);
+#pragma unroll
+    for (int k = 0; k < 64; k++) h[k] = lrelu(h[k]);
+    put_col(col, 0, h);
+  }
+  {
+    float h[32];
+    layer_fwd<32, 64>(wt + kL1.w, P + kL1.b, col, h);
+#pragma unroll
+    for (int k = 0; k < 32; k++) h[k] = lrelu(h[k]);
+    put_col(col, 0, h);
+    layer_fwd<32, 32>(wt + kL2.w, P + kL2.b, col, h);
+#pragma unroll
+    for (int k = 0; k < 32; k++) h[k] = lrelu(h[k]);
+    put_col(col, 0, h);   // trunk output
+    layer_fwd<32, 32>(wt + kLi.w, P + kLi.b, col, h);
+#pragma unroll
+    for (int k = 0; k < 32; k++) h[k] = lrelu(h[k]);
+    put_col(col, 32, h);  // incident head, hidden
+  }
+  float zl[3], zs[3];
+  layer_fwd<3, 32>(wt + kLl.w, P + kLl.b, col + 32 * kLS, zl);
+  layer_fwd<3, 32>(wt + kLs.w, P + kLs.b, col, zs);
+  if (live) {
+    const size_t n = A.n;
+    for (int c = 0; c < 3; c++) {
+      A.feat[c * n + i] = fmaxf(zl[c], 0.f);
+      A.feat[(3 + c) * n + i] = 1.f / (1.f + expf(-zs[c]));
+    }
+    A.feat[6 * n + i] = G.v;
+    A.feat[7 * n + i] = 1.f;
+  }
+}
+
+// Transposed copy of every weight matrix (same offsets), biases copied.
+__global__ __launch_bounds__(256) void gmlp_prep_kernel(const float *__restrict__ params, float *__restrict__ wt) {
+  const int p = blockIdx.x * 256 + threadIdx.x;
+  if (p >= kGParams) return;
+  const GL Ls[6] = {kL0, kL1, kL2, kLi, kLl, kLs};
+  for (int l = 0; l < 6; l++) {
+    const GL L = Ls[l];
+    if (p >= L.w && p < L.b) {
+      const int r = (p - L.w) / L.cols, c = (p - L.w) % L.cols;
+      wt[L.w + c * L.rows + r] = params[p];
+      return;
+    }
+  }
+  wt[p] = params[p];
+}
+
+// ----------------------------------------------------------------- backward
+
+// LDS rows of one wave (row stride kLS, lane = column):
+constexpr int kRH1 = 0;     // h1 (64); later dz0
+constexpr int kRH2 = 64;    // h2 (32); x during the forward and before the layer-0 gradient (48 rows incl. zero pad)
+constexpr int kRH3 = 96;    // trunk output h3 (32)
+constexpr int kRE = 128;    // incident hidden e (32)
+constexpr int kRDZ = 160;   // output gradients of the current layer (32)
+constexpr int kRows = 192;
+
+// Weight-gradient tile: acc[o][i] += sum_g lds[arow + o][g] lds[brow + i][g]
+// over the wave's 64 Gaussians (16 steps of K = 4).
+__device__ __forceinline__ void wtile(f32x4 &acc, const float *lds, int arow, int brow) {
+  const int lane = threadIdx.x & 63, r = lane & 15, g = lane >> 4;
+  const float *a = lds + (arow + r) * kLS + g, *b = lds + (brow + r) * kLS + g;
+#pragma unroll
+  for (int k = 0; k < 16; k++) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[4 * k], b[4 * k], acc, 0, 0, 0);
+}
+
+// Bias-gradient tile: every column holds sum_g lds[arow + o][g].
+__device__ __forceinline__ void btile(f32x4 &acc, const float *lds, int arow) {
+  const int lane = threadIdx.x & 63, r = lane & 15, g = lane >> 4;
+  const float *a = lds + (arow + r) * kLS + g;
+#pragma unroll
+  for (int k = 0; k < 16; k++) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[4 * k], 1.f, acc, 0, 0, 0);
+}
+
+// Write a weight tile (rows o0.., cols i0..) of layer L into the partial row.
+__device__ __forceinline__ void put_wtile(float *part, const GL &L, int o0, int i0, const f32x4 &acc) {
+  const int lane = threadIdx.x & 63, c = i0 + (lane & 15);
+#pragma unroll
+  for (int j = 0; j < 4; j++) {
+    const int o = o0 + 4 * (lane >> 4) + j;
+    if (o < L.rows && c < L.cols) part[L.w + o * L.cols + c] = acc[j];
+  }
+}
+
+__device__ __forceinline__ void put_btile(float *part, const GL &L, int o0, int row_off, const f32x4 &acc) {
+  const int lane = threadIdx.x & 63;
+  if ((lane & 15) != 0) return;
+#pragma unroll
+  for (int j = 0; j < 4; j++) {
+    const int o = 4 * (lane >> 4) + j - row_off;
+    if (o >= 0 && o < L.rows) part[L.b + o0 + o] = acc[j];
+  }
+}
+
+__global__ __launch_bounds__(64) void gmlp_bwd_kernel(GmlpArgs A) {
+  __shared__ float lds[kRows * kLS];
+  const int lane = threadIdx.x;
+  float *col = lds + lane;
+  const cptr wt = as_const(A.wt), P = as_const(A.params);
+  // weight-gradient sums: heads (incident output over e, SSS over h3, bias of
+  // both), incident hidden, trunk 2, 1, 0 (bias of layer 0 through a ones row)
+  f32x4 gHl[2], gHs[2], gHb, gI[4], gIb[2], g2[4], g2b[2], g1[8], g1b[2], g0[12];
+  const f32x4 z4 = {0.f, 0.f, 0.f, 0.f};
+  for (int k = 0; k < 2; k++) gHl[k] = gHs[k] = gIb[k] = g2b[k] = g1b[k] = z4;
+  gHb = z4;
+  for (int k = 0; k < 4; k++) gI[k] = g2[k] = z4;
+  for (int k = 0; k < 8; k++) g1[k] = z4;
+  for (int k = 0; k < 12; k++) g0[k] = z4;
+  const size_t n = A.n;
+  for (int base = blockIdx.x * 64; base < A.n; base += gridDim.x * 64) {
+    const int i = base + lane;
+    const bool live = i < A.n;
+    const int gi = live ? i : 0;
+    GIn G;
+    gaussian_input(A, gi, G);
+    // ---- forward, keeping every layer's activations in LDS
+    write_input(G, col, kRH2);
+    {
+      float h[64];
+      layer_fwd<64, kGIn>(wt + kL0.w, P + kL0.b, col + kRH2 * kLS, h);
+#pragma unroll
+      for (int k = 0; k < 64; k++) h[k] = lrelu(h[k]);
+      put_col(col, kRH1, h);
+    }
+    float lsss[3], zl[3];
+    {
+      float h[32];
+      layer_fwd<32, 64>(wt + kL1.w, P + kL1.b, col + kRH1 * kLS, h);
+#pragma unroll
+      for (int k = 0; k < 32; k++) h[k] = lrelu(h[k]);
+      put_col(col, kRH2, h);
+      layer_fwd<32, 32>(wt + kL2.w, P + kL2.b, col + kRH2 * kLS, h);
+#pragma unroll
+      for (int k = 0; k < 32; k++) h[k] = lrelu(h[k]);
+      put_col(col, kRH3, h);
+      layer_fwd<32, 32>(wt + kLi.w, P + kLi.b, col + kRH3 * kLS, h);
+#pragma unroll
+      for (int k = 0; k < 32; k++) h[k] = lrelu(h[k]);
+      put_col(col, kRE, h);
+      float zs[3];
+      layer_fwd<3, 32>(wt + kLl.w, P + kLl.b, col + kRE * kLS, zl);
+      layer_fwd<3, 32>(wt + kLs.w, P + kLs.b, col + kRH3 * kLS, zs);
+      for (int c = 0; c < 3; c++) lsss[c] = 1.f / (1.f + expf(-zs[c]));
+    }
+    // ---- heads: output gradients (dead lanes contribute zero)
+    float df[8];
+    for (int c = 0; c < 8; c++) df[c] = live ? A.dfeat[c * n + i] : 0.f;
+    float dzl[3], dzs[3];
+    for (int c = 0; c < 3; c++) {
+      dzl[c] = zl[c] > 0.f ? df[c] : 0.f;
+      dzs[c] = df[3 + c] * lsss[c] * (1.f - lsss[c]);
+    }
+    {
+      float hd[16];
+      for (int c = 0; c < 3; c++) {
+        hd[c] = dzl[c];
+        hd[3 + c] = dzs[c];
+      }
+      for (int c = 6; c < 16; c++) hd[c] = 0.f;
+      put_col(col, kRDZ, hd);
+    }
+    __syncthreads();
+    for (int t = 0; t < 2; t++) {
+      wtile(gHl[t], lds, kRDZ, kRE + 16 * t);
+      wtile(gHs[t], lds, kRDZ, kRH3 + 16 * t);
+    }
+    btile(gHb, lds, kRDZ);
+    // incident hidden: dz_i = lrelu'(e) (Wl^T dzl); trunk output gets Ws^T dzs
+    float dh3[32];
+    {
+      float dzi[32];
+#pragma unroll
+      for (int c = 0; c < 32; c++) {
+        float d = 0.f, e = 0.f;
+#pragma unroll
+        for (int o = 0; o < 3; o++) {
+          d = __fmaf_rn(P[kLl.w + o * 32 + c], dzl[o], d);
+          e = __fmaf_rn(P[kLs.w + o * 32 + c], dzs[o], e);
+        }
+        dzi[c] = d * lrelu_d(col[(kRE + c) * kLS]);
+        dh3[c] = e;
+      }
+      __syncthreads();
+      put_col(col, kRDZ, dzi);
+    }
+    __syncthreads();
+    for (int ot = 0; ot < 2; ot++) {
+      for (int it = 0; it < 2; it++) wtile(gI[2 * ot + it], lds, kRDZ + 16 * ot, kRH3 + 16 * it);
+      btile(gIb[ot], lds, kRDZ + 16 * ot);
+    }
+    {
+      float d[32];
+      layer_bwd<32, 32>(P + kLi.w, col + kRDZ * kLS, d);
+#pragma unroll
+      for (int c = 0; c < 32; c++) dh3[c] = (dh3[c] + d[c]) * lrelu_d(col[(kRH3 + c) * kLS]);
+      __syncthreads();
+      put_col(col, kRDZ, dh3);  // dz2
+    }
+    __syncthreads();
+    for (int ot = 0; ot < 2; ot++) {
+      for (int it = 0; it < 2; it++) wtile(g2[2 * ot + it], lds, kRDZ + 16 * ot, kRH2 + 16 * it);
+      btile(g2b[ot], lds, kRDZ + 16 * ot);
+    }
+    {
+      float d[32];
+      layer_bwd<32, 32>(P + kL2.w, col + kRDZ * kLS, d);
+#pragma unroll
+      for (int c = 0; c < 32; c++) d[c] *= lrelu_d(col[(kRH2 + c) * kLS]);
+      __syncthreads();
+      put_col(col, kRDZ, d);  // dz1
+    }
+    __syncthreads();
+    for (int ot = 0; ot < 2; ot++) {
+      for (int it = 0; it < 4; it++) wtile(g1[4 * ot + it], lds, kRDZ + 16 * ot, kRH1 + 16 * it);
+      btile(g1b[ot], lds, kRDZ + 16 * ot);
+    }
+    {
+      float d[64];
+      layer_bwd<32, 64>(P + kL1.w, col + kRDZ * kLS, d);
+#pragma unroll
+      for (int c = 0; c < 64; c++) d[c] *= lrelu_d(col[(kRH1 + c) * kLS]);
+      __syncthreads();
+      put_col(col, kRH1, d);  // dz0 over h1
+      // layer-0 input again, a ones row for the bias and zero padding
+      write_input(G, col, kRH2);
+      col[(kRH2 + kGIn) * kLS] = 1.f;
+      for (int r = kGIn + 1; r < 48; r++) col[(kRH2 + r) * kLS] = 0.f;
+    }
+    __syncthreads();
+    for (int ot = 0; ot < 4; ot++)
+      for (int it = 0; it < 3; it++) wtile(g0[3 * ot + it], lds, kRH1 + 16 * ot, kRH2 + 16 * it);
+    // ---- input gradient and the chain to the Gaussian parameters
+    float dx[kGIn];
+    layer_bwd<64, kGIn>(P + kL0.w, col + kRH1 * kLS, dx);
+    if (live) {
+      float dmu[3] = {0.f, 0.f, 0.f};
+      // w_in = u / |u| and d = |u| with u = light - mu
+      {
+        const float p = G.wi[0] * dx[10] + G.wi[1] * dx[11] + G.wi[2] * dx[12];
+        const float il = 1.f / G.dl;
+        for (int k = 0; k < 3; k++) dmu[k] -= (dx[10 + k] - G.wi[k] * p) * il + dx[16] * G.wi[k];
+      }
+      {
+        const float p = G.wo[0] * dx[13] + G.wo[1] * dx[14] + G.wo[2] * dx[15];
+        const float ic = 1.f / G.dc;
+        for (int k = 0; k < 3; k++) dmu[k] -= (dx[13 + k] - G.wo[k] * p) * ic;
+      }
+#pragma unroll
+      for (int oct = 0; oct < 4; oct++) {
+        const float sc = (float)(1 << oct), fr = sc * 3.14159265358979323846f;
+#pragma unroll
+        for (int ax = 0; ax < 3; ax++)
+          dmu[ax] += fr * (dx[18 + 6 * oct + ax] * cospif(sc * G.mu[ax]) - dx[21 + 6 * oct + ax] * sinpif(sc * G.mu[ax]));
+      }
+      // normal = sign * column kmin of R(q^)
+      float dR[9];
+      for (int r = 0; r < 3; r++)
+        for (int k = 0; k < 3; k++) dR[3 * r + k] = G.kmin == k ? G.sign * dx[r] : 0.f;
+      const float w = G.qn[0], qx = G.qn[1], qy = G.qn[2], qz = G.qn[3];
+      float dqn[4];
+      dqn[0] = dx[3] + 2.f * (-qz * dR[1] + qy * dR[2] + qz * dR[3] - qx * dR[5] - qy * dR[6] + qx * dR[7]);
+      dqn[1] = dx[4] + 2.f * (qy * dR[1] + qz * dR[2] + qy * dR[3] - 2.f * qx * dR[4] - w * dR[5] + qz * dR[6] +
+                              w * dR[7] - 2.f * qx * dR[8]);
+      dqn[2] = dx[5] + 2.f * (-2.f * qy * dR[0] + qx * dR[1] + w * dR[2] + qx * dR[3] + qz * dR[5] - w * dR[6] +
+                              qz * dR[7] - 2.f * qy * dR[8]);
+      dqn[3] = dx[6] + 2.f * (-2.f * qz * dR[0] - w * dR[1] + qx * dR[2] + w * dR[3] - 2.f * qz * dR[4] +
+                              qy * dR[5] + qx * dR[6] + qy * dR[7]);
+      const float pq = w * dqn[0] + qx * dqn[1] + qy * dqn[2] + qz * dqn[3];
+      for (int k = 0; k < 3; k++) A.d_means[k * n + i] += dmu[k];
+      for (int k = 0; k < 3; k++) A.d_log_scales[k * n + i] += dx[7 + k] * G.s[k];
+      for (int k = 0; k < 4; k++) A.d_quats[k * n + i] += (dqn[k] - G.qn[k] * pq) / G.qlen;
+      const float dv = dx[17] + df[6];
+      A.d_vis[i] = A.accumulate ? A.d_vis[i] + dv : dv;
+    }
+    __syncthreads();
+  }
+  // ---- this wave's partial sums of the weight gradient
+  float *part = A.partials + (size_t)blockIdx.x * kGParams;
+  for (int t = 0; t < 2; t++) {
+    put_wtile(part, kLl, 0, 16 * t, gHl[t]);
+    // SSS rows sit at 3..5 of the head tile
+    const int lane_ = threadIdx.x & 63, c = 16 * t + (lane_ & 15);
+    for (int j = 0; j < 4; j++) {
+      const int o = 4 * (lane_ >> 4) + j - 3;
+      if (o >= 0 && o < 3) part[kLs.w + o * 32 + c] = gHs[t][j];
+    }
+  }
+  put_btile(part, kLl, 0, 0, gHb);
+  put_btile(part, kLs, 0, 3, gHb);
+  for (int ot = 0; ot < 2; ot++) {
+    for (int it = 0; it < 2; it++) {
+      put_wtile(part, kLi, 16 * ot, 16 * it, gI[2 * ot + it]);
+      put_wtile(part, kL2, 16 * ot, 16 * it, g2[2 * ot + it]);
+    }
+    for (int it = 0; it < 4; it++) put_wtile(part, kL1, 16 * ot, 16 * it, g1[4 * ot + it]);
+    put_btile(part, kLi, 16 * ot, 0, gIb[ot]);
+    put_btile(part, kL2, 16 * ot, 0, g2b[ot]);
+    put_btile(part, kL1, 16 * ot, 0, g1b[ot]);
+  }
+  // layer 0: columns 0..41 weights, column 42 (the ones row) the bias
+  {
+    const int lane_ = threadIdx.x & 63;
+    for (int ot = 0; ot < 4; ot++)
+      for (int it = 0; it < 3; it++) {
+        const int c = 16 * it + (lane_ & 15);
+        for (int j = 0; j < 4; j++) {
+          const int o = 16 * ot + 4 * (lane_ >> 4) + j;
+          if (c < kGIn) part[kL0.w + o * kGIn + c] = g0[3 * ot + it][j];
+          else if (c == kGIn) part[kL0.b + o] = g0[3 * ot + it][j];
+        }
+      }
+  }
+}
+
+}  // namespace
+
+int gmlp_param_count() { return kGParams; }
+
+int gmlp_bwd_grid(int n) {
+  const int waves = (n + 63) / 64;
+  return waves < 1 ? 1 : (waves > kGmlpMaxWaves ? kGmlpMaxWaves : waves);
+}
+
+void launch_gmlp_prep(const float *params, float *wt, hipStream_t st) {
+  gmlp_prep_kernel<<<(kGParams + 255) / 256, 256, 0, st>>>(params, wt);
+}
+
+void launch_gmlp_fwd(const GmlpArgs &a, hipStream_t st) {
+  if (a.n > 0) gmlp_fwd_kernel<<<(a.n + 63) / 64, 64, 0, st>>>(a);
+}
+
+void launch_gmlp_bwd(const GmlpArgs &a, hipStream_t st) {
+  gmlp_bwd_kernel<<<gmlp_bwd_grid(a.n), 64, 0, st>>>(a);
+}
+
+}  // namespace sssgs

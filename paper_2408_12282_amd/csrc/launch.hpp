@@ -85,4 +85,25 @@ void launch_l1_loss(const float *pred, const float *target, int64_t count, float
                     float *grad, hipStream_t st);
 void launch_zero_f32(float *p, size_t n, hipStream_t st);
 
+// Per-Gaussian network (gmlp.hip).
+struct GmlpArgs {
+  int n;
+  const float *means, *log_scales, *quats, *vis;
+  float cam[3], light[3];  // camera centre and light position (world)
+  const float *params;     // packed weights and biases
+  const float *wt;         // weights transposed per layer (launch_gmlp_prep)
+  float *feat;             // forward: [8][n]
+  const float *dfeat;      // backward: dL/d(features) [8][n]
+  float *d_means, *d_log_scales, *d_quats;  // added to
+  float *d_vis;            // written, or added when accumulate
+  float *partials;         // [gmlp_bwd_grid(n)][gmlp_param_count()]
+  int accumulate;
+};
+constexpr int kGmlpMaxWaves = 768;
+int gmlp_param_count();
+int gmlp_bwd_grid(int n);
+void launch_gmlp_prep(const float *params, float *wt, hipStream_t st);
+void launch_gmlp_fwd(const GmlpArgs &a, hipStream_t st);
+void launch_gmlp_bwd(const GmlpArgs &a, hipStream_t st);
+
 }  // namespace sssgs

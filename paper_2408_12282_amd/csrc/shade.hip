@@ -1,5 +1,6 @@
 // shade.hip -- per-pixel deferred shading (Sec. 3.2 "Per-Pixel Deferred
-// Shading"): GGX BRDF (Eq. 4), residual network (Eq. 6) and the SSS/BRDF
+// Shading"): GGX BRDF (Eq. 4), residual network (Eq. 6, per pixel, or its
+// per-Gaussian outputs composited into the G-buffer) and the SSS/BRDF
 // combination (Eq. 7), forward, for one or several point lights over the same
 // G-buffer (image-based lighting as a weighted sum of light samples, paper
 // appendix "Image Based Lighting").  The backward lives in shade_bwd.hip.
@@ -19,8 +20,8 @@ __global__ __launch_bounds__(256) void shade_fwd_kernel(ShadeArgs A, MultiLight 
   using E = typename M::Elem;
   constexpr int C = kChFeat + F;
   constexpr int XS = IN_PAD + XPad<M>::value;  // LDS row stride (elements)
-  __shared__ E xs[NET ? 4 * 64 * XS : 1];
-  __shared__ float outs[NET ? 4 * 64 * 8 : 1];
+  __shared__ E xs[kIsNet<NET> ? 4 * 64 * XS : 1];
+  __shared__ float outs[kIsNet<NET> ? 4 * 64 * 8 : 1];
   const int tile = blockIdx.x;
   const int tx = tile % A.cam.TX, ty = tile / A.cam.TX;
   const int px = tx * kTile + (threadIdx.x & 15), py = ty * kTile + (threadIdx.x >> 4);
@@ -49,7 +50,9 @@ __global__ __launch_bounds__(256) void shade_fwd_kernel(ShadeArgs A, MultiLight 
     }
     PixShade S;
     shade_geometry<C>(gb, T, (float)px + 0.5f, (float)py + 0.5f, A.cam, L, NET != 0, S);
-    if constexpr (NET != 0) {
+    if constexpr (NET == 3) {
+      combine_features(S, gb);
+    } else if constexpr (NET != 0) {
       // the network input row differs between lights only in w_i
       if (k == 0) build_net_input<F, IN_PAD, M>(gb, S, xrow);
       else set_net_light<F, M>(S, xrow);

@@ -140,7 +140,7 @@ __device__ __forceinline__ void stage_ops(const typename M::Op (&H)[KSN][4], typ
 // fall-off without network): fills dgbar (d L / d mean values) and returns
 // d L / d a (direct part).  dnet_in: gradient w.r.t. the network input vector
 // (or null), used for features, position encoding and directions.
-template <int C, int F, bool NET>
+template <int C, int F, int MODE>
 __device__ __forceinline__ float shade_pixel_bwd(const PixShade &S, const float *gb, const float *gL,
                                                  const LightArgs &light, const float *dnet_in, float *dgbar) {
 #pragma unroll
@@ -152,7 +152,20 @@ __device__ __forceinline__ float shade_pixel_bwd(const PixShade &S, const float 
   }
   float dfs[3], dfd[3], dcos = 0.f, dx[3] = {0.f, 0.f, 0.f}, dwo[3] = {0.f, 0.f, 0.f}, dwi[3] = {0.f, 0.f, 0.f};
   float dvi[3] = {0.f, 0.f, 0.f};
-  if constexpr (!NET) {
+  if constexpr (MODE == 2) {
+    const float sss = gb[kChSss] * S.ia;
+    float dsss = 0.f;
+    for (int c = 0; c < 3; c++) {
+      const float B = S.fs[c] + S.fd[c];
+      dsss += gLo[c] * (S.Lsss[c] - B * S.Lin[c] * S.cosI);
+      dfs[c] = gLo[c] * (1.f - sss) * S.Lin[c] * S.cosI;
+      dfd[c] = dfs[c];
+      dcos += gLo[c] * (1.f - sss) * B * S.Lin[c];
+      dgbar[kChFeat + c] += gLo[c] * (1.f - sss) * B * S.cosI;
+      dgbar[kChFeat + 3 + c] += gLo[c] * sss;
+    }
+    dgbar[kChSss] += dsss;
+  } else if constexpr (MODE == 0) {
     float dli2 = 0.f;
     for (int c = 0; c < 3; c++) {
       dfs[c] = gLo[c] * S.Lin[c] * S.cosI;
@@ -264,11 +277,11 @@ __device__ __forceinline__ float shade_pixel_bwd(const PixShade &S, const float 
 
 // Waves per workgroup: bounded by the LDS each wave needs (160 KB per CU).
 template <int NET, int WIDTH, int IN_PAD> struct BwdWaves {
-  static constexpr int value = NET == 0 ? 4 : ((NET == 2 && WIDTH == 64 && IN_PAD == 64) ? 4 : 2);
+  static constexpr int value = !kIsNet<NET> ? 4 : ((NET == 2 && WIDTH == 64 && IN_PAD == 64) ? 4 : 2);
 };
 
 int shade_bwd_waves(int net, int width, int in_pad) {
-  return net == 0 ? 4 : ((net == 2 && width == 64 && in_pad == 64) ? 4 : 2);
+  return (net == 0 || net == 3) ? 4 : ((net == 2 && width == 64 && in_pad == 64) ? 4 : 2);
 }
 
 // Per-pixel inputs of the shading backward (reloaded in each per-pixel phase
@@ -326,15 +339,16 @@ __global__ __launch_bounds__((BwdWaves<NET, WIDTH, IN_PAD>::value * 64)) void sh
   constexpr int STAGE_ELEMS = ST::FM ? FMAX * ST::PXS : 64 * FST;
   constexpr int XS_ELEMS = 64 * XS;
   // per wave: network input rows, two weight-gradient stages, outputs + their gradients
-  __shared__ E xs_all[NET ? NW * XS_ELEMS : 1];
-  __shared__ E st_all[NET ? NW * 2 * STAGE_ELEMS : 1];
-  __shared__ float io_all[NET ? NW * 64 * 16 : 1];
+  constexpr bool NETW = kIsNet<NET>;
+  __shared__ E xs_all[NETW ? NW * XS_ELEMS : 1];
+  __shared__ E st_all[NETW ? NW * 2 * STAGE_ELEMS : 1];
+  __shared__ float io_all[NETW ? NW * 64 * 16 : 1];
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int g = lane >> 4, col = lane & 15;
-  E *xs = xs_all + (NET ? w * XS_ELEMS : 0);
-  E *sdy = st_all + (NET ? w * 2 * STAGE_ELEMS : 0);
-  E *sxk = sdy + (NET ? STAGE_ELEMS : 0);
-  float *io = io_all + (NET ? w * 64 * 16 : 0);  // [px][0..7] outputs, [px][8..15] output gradients
+  E *xs = xs_all + (NETW ? w * XS_ELEMS : 0);
+  E *sdy = st_all + (NETW ? w * 2 * STAGE_ELEMS : 0);
+  E *sxk = sdy + (NETW ? STAGE_ELEMS : 0);
+  float *io = io_all + (NETW ? w * 64 * 16 : 0);  // [px][0..7] outputs, [px][8..15] output gradients
   float *dxin = reinterpret_cast<float *>(sdy);  // [64][IN_PAD + 1] after the last weight gradient
   float *part = A.mlp_partials ? A.mlp_partials + (size_t)blockIdx.x * A.nparams : nullptr;
   const size_t HW = (size_t)A.cam.W * A.cam.H;
@@ -347,13 +361,14 @@ __global__ __launch_bounds__((BwdWaves<NET, WIDTH, IN_PAD>::value * 64)) void sh
     const bool inside = strip < nstrips && px < A.cam.W && py < A.cam.H;
     const size_t pix = inside ? (size_t)py * A.cam.W + px : 0;
     const float uc = (float)px + 0.5f, vc = (float)py + 0.5f;
-    if constexpr (NET == 0) {
+    if constexpr (!NETW) {
       float gb[C], T, gL[3], dgbar[C];
       load_pixel<C>(A, inside, pix, HW, gb, T, gL);
       PixShade S;
-      shade_geometry<C>(gb, T, uc, vc, A.cam, A.light, false, S);
+      shade_geometry<C>(gb, T, uc, vc, A.cam, A.light, NET == 3, S);
+      if constexpr (NET == 3) combine_features(S, gb);
       if (S.bg) gL[0] = gL[1] = gL[2] = 0.f;
-      const float dA = shade_pixel_bwd<C, F, false>(S, gb, gL, A.light, nullptr, dgbar);
+      const float dA = shade_pixel_bwd<C, F, NET == 3 ? 2 : 0>(S, gb, gL, A.light, nullptr, dgbar);
       write_pixel_grads<C, F>(A, inside, pix, HW, S, gb, dgbar, dA);
     } else {
       // Weight operands are re-read for every strip (cache hits): an opaque
@@ -529,7 +544,7 @@ __global__ __launch_bounds__((BwdWaves<NET, WIDTH, IN_PAD>::value * 64)) void sh
         for (int k = 0; k < 6; k++) o[k] = io[lane * 16 + k];
         combine_net(S, gb[kChSss], o);
         const float *din = dxin + lane * (IN_PAD + 1);
-        const float dA = shade_pixel_bwd<C, F, true>(S, gb, gL, A.light, din, dgbar);
+        const float dA = shade_pixel_bwd<C, F, 1>(S, gb, gL, A.light, din, dgbar);
         write_pixel_grads<C, F>(A, inside, pix, HW, S, gb, dgbar, dA);
       }
       first = false;
@@ -696,7 +711,7 @@ __global__ __launch_bounds__(64, 2) void shade_bwd_split_kernel(ShadeArgs A, __b
     float o[6];
     for (int k = 0; k < 6; k++) o[k] = io[lane * SL::IO + k];
     combine_net(S, gb[kChSss], o);
-    const float dA = shade_pixel_bwd<C, F, true>(S, gb, gL, A.light, dxin + lane * SL::DS, dgbar);
+    const float dA = shade_pixel_bwd<C, F, 1>(S, gb, gL, A.light, dxin + lane * SL::DS, dgbar);
     write_pixel_grads<C, F>(A, inside, pix, HW, S, gb, dgbar, dA);
   }
 }

@@ -32,6 +32,11 @@ struct MultiLight {
   float pos[kMaxLights][3], intensity[kMaxLights][3], weight[kMaxLights][3];
 };
 
+// Shading modes NET: 0 point-light fall-off without network, 1 per-pixel
+// network in FP32, 2 per-pixel network in BF16, 3 radiances composited from
+// a per-Gaussian network (feature planes 0-2 incident light, 3-5 SSS).
+template <int NET> constexpr bool kIsNet = NET == 1 || NET == 2;
+
 template <int NET> struct NetTraits { using M = MmaF32; };
 template <> struct NetTraits<2> { using M = MmaBF16; };
 
@@ -169,6 +174,18 @@ __device__ __forceinline__ void combine_net(PixShade &S, float sss_pre, const fl
   }
 }
 
+// Eq. 7 with the composited radiances of a per-Gaussian network (pipeline
+// figure): the incident light and SSS radiance are blended like the other
+// channels, so their pixel values are the feature planes over alpha.
+__device__ __forceinline__ void combine_features(PixShade &S, const float *gb) {
+  const float sss = gb[kChSss] * S.ia;
+  for (int c = 0; c < 3; c++) {
+    S.Lin[c] = gb[kChFeat + c] * S.ia;
+    S.Lsss[c] = gb[kChFeat + 3 + c] * S.ia;
+    S.L[c] = sss * S.Lsss[c] + (1.f - sss) * (S.fs[c] + S.fd[c]) * S.Lin[c] * S.cosI;
+  }
+}
+
 // ----------------------------------------------------------------- network
 
 // Offsets into the packed parameter vector.
@@ -279,10 +296,10 @@ __device__ __forceinline__ void net_forward_wave(const void *wops_v, const float
   }
 }
 
-// Instances: (F, NET, WIDTH, IN_PAD).  NET 0 = no network, 1 = FP32, 2 = BF16.
+// Instances: (F, NET, WIDTH, IN_PAD), NET as for kIsNet.
 #define SSSGS_SHADE_INSTANCES(X) \
   X(0, 0, 64, 64) X(0, 1, 64, 64) X(0, 2, 64, 64) X(0, 2, 128, 64) \
-  X(8, 0, 64, 64) X(8, 1, 64, 64) X(8, 2, 64, 64) X(8, 2, 128, 64) \
+  X(8, 0, 64, 64) X(8, 1, 64, 64) X(8, 2, 64, 64) X(8, 2, 128, 64) X(8, 3, 64, 64) \
   X(16, 0, 64, 64) X(16, 1, 64, 64) X(16, 2, 64, 64) X(16, 2, 128, 64) \
   X(32, 0, 64, 96) X(32, 1, 64, 96) X(32, 2, 64, 96) X(32, 2, 128, 96)
 

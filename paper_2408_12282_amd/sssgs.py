@@ -49,7 +49,7 @@ class Mlp(ct.Structure):
 
 
 class Options(ct.Structure):
-    _fields_ = [("precision", ct.c_int32), ("accumulate_grads", ct.c_int32)]
+    _fields_ = [("precision", ct.c_int32), ("accumulate_grads", ct.c_int32), ("radiance_features", ct.c_int32)]
 
 
 class Layout(ct.Structure):
@@ -63,7 +63,8 @@ EXPORTS = ("sssgs_mlp_param_count", "sssgs_workspace_bytes", "sssgs_render_forwa
            "sssgs_l1_loss", "sssgs_workspace_status", "sssgs_workspace_layout", "sssgs_status_string",
            "sssgs_last_error", "sssgs_timing_enable", "sssgs_timing_read", "sssgs_timing_stages",
            "sssgs_timing_stage_name", "sssgs_image_loss_workspace_bytes", "sssgs_image_loss", "sssgs_adam_step",
-           "sssgs_render_forward_lights")
+           "sssgs_render_forward_lights", "sssgs_gaussian_mlp_param_count", "sssgs_gaussian_mlp_workspace_bytes",
+           "sssgs_gaussian_mlp_forward", "sssgs_gaussian_mlp_backward")
 
 
 def load_library(path: str = LIB_PATH):
@@ -90,6 +91,19 @@ def load_library(path: str = LIB_PATH):
                                         ct.POINTER(Mlp), ct.POINTER(Options), ct.c_void_p, ct.c_size_t, ct.c_int64,
                                         ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_void_p,
                                         ct.POINTER(GaussianGrads), ct.c_void_p, ct.c_void_p]
+    L.sssgs_gaussian_mlp_param_count.restype = ct.c_int64
+    L.sssgs_gaussian_mlp_param_count.argtypes = []
+    L.sssgs_gaussian_mlp_workspace_bytes.restype = ct.c_size_t
+    L.sssgs_gaussian_mlp_workspace_bytes.argtypes = [ct.c_int32]
+    L.sssgs_gaussian_mlp_forward.restype = ct.c_int
+    L.sssgs_gaussian_mlp_forward.argtypes = [ct.POINTER(Gaussians), ct.POINTER(Camera), ct.POINTER(Light),
+                                             ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_size_t, ct.c_void_p,
+                                             ct.c_void_p]
+    L.sssgs_gaussian_mlp_backward.restype = ct.c_int
+    L.sssgs_gaussian_mlp_backward.argtypes = [ct.POINTER(Gaussians), ct.POINTER(Camera), ct.POINTER(Light),
+                                              ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_size_t,
+                                              ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_void_p,
+                                              ct.c_int32, ct.c_void_p]
     L.sssgs_l1_loss.restype = ct.c_int
     L.sssgs_l1_loss.argtypes = [ct.c_void_p, ct.c_void_p, ct.c_int64, ct.c_float, ct.c_void_p, ct.c_void_p,
                                 ct.c_void_p]
@@ -321,8 +335,11 @@ class View:
 
 
 def render_forward(view: View, params: dict, sh_degree: int, cam: Camera, light: Light, mlp_params=None,
-                   mlp_width: int = 64, precision: int = PREC_BF16, want_count: bool = False):
-    """One forward call.  Returns (rgb [3,H,W], gbuf [C,H,W], alpha [H,W], M or None)."""
+                   mlp_width: int = 64, precision: int = PREC_BF16, want_count: bool = False,
+                   radiance_features: bool = False):
+    """One forward call.  Returns (rgb [3,H,W], gbuf [C,H,W], alpha [H,W], M or None).
+    ``radiance_features``: Eq. 7 takes its radiances from feature planes 0-5
+    (the outputs of the per-Gaussian network)."""
     dev = params["means"].device
     H, W = view.height, view.width
     rgb = torch.empty((3, H, W), dtype=torch.float32, device=dev)
@@ -332,7 +349,7 @@ def render_forward(view: View, params: dict, sh_degree: int, cam: Camera, light:
     m = None
     if mlp_params is not None:
         m = Mlp(view.feat_dim + 42, mlp_width, 3, 6, _ptr(mlp_params))
-    opt = Options(precision, 0)
+    opt = Options(precision, 0, int(radiance_features))
     st, cnt = sssgs_render_forward(g, cam, light, m, opt, ct.c_void_p(view.workspace.data_ptr()), view.ws_bytes,
                                    view.capacity, _ptr(rgb), _ptr(gbuf), _ptr(alpha), want_count, _stream())
     _check(st)
@@ -360,7 +377,8 @@ def render_forward_lights(view: View, params: dict, sh_degree: int, cam: Camera,
 
 def render_backward(view: View, params: dict, sh_degree: int, cam: Camera, light: Light, gbuf, drgb, dgbuf=None,
                     dalpha=None, mlp_params=None, mlp_width: int = 64, precision: int = PREC_BF16,
-                    grads: Optional[dict] = None, dmlp: Optional[torch.Tensor] = None, accumulate: bool = False):
+                    grads: Optional[dict] = None, dmlp: Optional[torch.Tensor] = None, accumulate: bool = False,
+                    radiance_features: bool = False):
     dev = params["means"].device
     if grads is None:
         grads = {k: torch.zeros_like(v) for k, v in params.items() if v is not None}
@@ -368,7 +386,7 @@ def render_backward(view: View, params: dict, sh_degree: int, cam: Camera, light
         dmlp = torch.zeros_like(mlp_params)
     g = gaussians_struct(params, view.feat_dim, sh_degree)
     m = Mlp(view.feat_dim + 42, mlp_width, 3, 6, _ptr(mlp_params)) if mlp_params is not None else None
-    opt = Options(precision, int(accumulate))
+    opt = Options(precision, int(accumulate), int(radiance_features))
     gs = grads_struct(grads)
     st = sssgs_render_backward(g, cam, light, m, opt, ct.c_void_p(view.workspace.data_ptr()), view.ws_bytes,
                                view.capacity, _ptr(gbuf), _ptr(drgb.contiguous()),
@@ -420,3 +438,75 @@ def render(view: View, params: dict, sh_degree: int, cam: Camera, light: Light, 
            mlp_width: int = 64, precision: int = PREC_BF16):
     tensors: Sequence = [params.get(k) for k in PARAM_NAMES]
     return SSSGSRender.apply((view, sh_degree, cam, light, mlp_width, precision), mlp_params, *tensors)
+
+
+# ----------------------------------------------------------------- per-Gaussian network
+
+def gaussian_mlp_param_count() -> int:
+    return int(lib().sssgs_gaussian_mlp_param_count())
+
+
+def gaussian_mlp_workspace(n: int, device="cuda") -> torch.Tensor:
+    nb = int(lib().sssgs_gaussian_mlp_workspace_bytes(int(n)))
+    return torch.empty(nb, dtype=torch.uint8, device=device)
+
+
+def gaussian_mlp_forward(params: dict, cam: Camera, light: Light, visibility: torch.Tensor, gmlp: torch.Tensor,
+                         workspace: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """Feature planes [8, N] = incident light | SSS radiance | visibility | 1 of
+    the per-Gaussian network (see include/sssgs.h)."""
+    n = int(params["means"].shape[1])
+    if workspace is None:
+        workspace = gaussian_mlp_workspace(n, params["means"].device)
+    feats = torch.empty((8, n), dtype=torch.float32, device=params["means"].device)
+    g = gaussians_struct(params, 0, -1)
+    _check(lib().sssgs_gaussian_mlp_forward(ct.byref(g), ct.byref(cam), ct.byref(light), _ptr(visibility),
+                                            _ptr(gmlp), ct.c_void_p(workspace.data_ptr()), workspace.numel(),
+                                            _ptr(feats), _stream()))
+    return feats
+
+
+def gaussian_mlp_backward(params: dict, cam: Camera, light: Light, visibility: torch.Tensor, gmlp: torch.Tensor,
+                          dfeat: torch.Tensor, grads: dict, dvis: torch.Tensor, dgmlp: torch.Tensor,
+                          accumulate: bool = False, workspace: Optional[torch.Tensor] = None):
+    """Adds the network's share to grads['means'|'log_scales'|'quats'];
+    writes (or adds) dvis and dgmlp."""
+    n = int(params["means"].shape[1])
+    if workspace is None:
+        workspace = gaussian_mlp_workspace(n, params["means"].device)
+    g = gaussians_struct(params, 0, -1)
+    _check(lib().sssgs_gaussian_mlp_backward(ct.byref(g), ct.byref(cam), ct.byref(light), _ptr(visibility),
+                                             _ptr(gmlp), _ptr(dfeat.contiguous()), ct.c_void_p(workspace.data_ptr()),
+                                             workspace.numel(), _ptr(grads["means"]), _ptr(grads["log_scales"]),
+                                             _ptr(grads["quats"]), _ptr(dvis), _ptr(dgmlp), int(accumulate),
+                                             _stream()))
+
+
+def render_gaussian_mlp_forward(view: View, params: dict, cam: Camera, light: Light, visibility: torch.Tensor,
+                                gmlp: torch.Tensor, workspace: Optional[torch.Tensor] = None,
+                                want_count: bool = False):
+    """Per-Gaussian network -> projection and compositing of the 18-plane
+    G-buffer -> Eq. 7 from the composited radiances.  ``view`` has feat_dim 8
+    and no per-pixel network.  Returns (rgb, gbuf, alpha, features, M or None)."""
+    feats = gaussian_mlp_forward(params, cam, light, visibility, gmlp, workspace)
+    p = dict(params, features=feats)
+    rgb, gbuf, alpha, cnt = render_forward(view, p, -1, cam, light, None, 64, PREC_FP32, want_count,
+                                           radiance_features=True)
+    return rgb, gbuf, alpha, feats, cnt
+
+
+def render_gaussian_mlp_backward(view: View, params: dict, cam: Camera, light: Light, visibility: torch.Tensor,
+                                 gmlp: torch.Tensor, feats: torch.Tensor, gbuf, drgb, dgbuf=None, dalpha=None,
+                                 workspace: Optional[torch.Tensor] = None):
+    """Gradients of every Gaussian parameter (dict), of the visibility and of
+    the network parameters."""
+    p = dict(params, features=feats)
+    grads = {k: torch.zeros_like(v) for k, v in p.items() if v is not None}
+    render_backward(view, p, -1, cam, light, gbuf, drgb, dgbuf, dalpha, None, 64, PREC_FP32, grads=grads,
+                    radiance_features=True)
+    dvis = torch.empty_like(visibility)
+    dgmlp = torch.empty_like(gmlp)
+    gaussian_mlp_backward(params, cam, light, visibility, gmlp, grads["features"], grads, dvis, dgmlp,
+                          workspace=workspace)
+    dfeat = grads.pop("features")
+    return grads, dvis, dgmlp, dfeat

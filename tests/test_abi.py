@@ -111,3 +111,37 @@ def test_image_loss_and_adam_argument_checks(B):
     st = L.sssgs_image_loss(buf, buf, 3, 0, 16, 0.2, buf, 1 << 20, buf, None, None)  # bad size
     assert st == B.ERR_INVALID_ARG
     assert L.sssgs_adam_step(buf, buf, buf, buf, 10, 1e-3, 0.9, 0.999, 1e-8, 0, None) == B.ERR_INVALID_ARG
+
+
+def test_gaussian_network_sizes_and_argument_checks(B):
+    from paper_2408_12282_amd import scene
+    L = B.lib()
+    assert B.gaussian_mlp_param_count() == scene.gmlp_param_count()
+    a, b = L.sssgs_gaussian_mlp_workspace_bytes(0), L.sssgs_gaussian_mlp_workspace_bytes(300000)
+    assert 0 < a <= b and L.sssgs_gaussian_mlp_workspace_bytes(-1) == 0
+    cam = B.Camera((ct.c_float * 9)(1, 0, 0, 0, -1, 0, 0, 0, -1), (ct.c_float * 3)(0, 0, 3), 100.0, 100.0, 16.0,
+                   16.0, 32, 32)
+    light = B.Light((ct.c_float * 3)(1, 1, 1), (ct.c_float * 3)(9, 9, 9))
+    buf = ct.c_void_p(1)
+    g = B.Gaussians(10, 0, -1, *([buf] * 10))
+    ws = L.sssgs_gaussian_mlp_workspace_bytes(10)
+    f = L.sssgs_gaussian_mlp_forward
+    assert f(ct.byref(g), ct.byref(cam), ct.byref(light), buf, None, buf, ws, buf, None) == B.ERR_INVALID_ARG
+    assert f(ct.byref(g), ct.byref(cam), ct.byref(light), None, buf, buf, ws, buf, None) == B.ERR_INVALID_ARG
+    assert f(ct.byref(g), ct.byref(cam), ct.byref(light), buf, buf, buf, ws - 1, buf, None) == B.ERR_INVALID_ARG
+    bw = L.sssgs_gaussian_mlp_backward
+    args = [ct.byref(g), ct.byref(cam), ct.byref(light), buf, buf, buf, buf, ws, buf, buf, buf, buf, buf]
+    assert bw(*args, 2, None) == B.ERR_INVALID_ARG                       # accumulate must be 0 or 1
+    args[12] = None
+    assert bw(*args, 0, None) == B.ERR_INVALID_ARG                       # null dL_dparams
+    # the shading mode that takes the radiances from the feature planes
+    g8 = B.Gaussians(10, 8, -1, *([buf] * 10))
+    g16 = B.Gaussians(10, 16, -1, *([buf] * 10))
+    m = B.Mlp(50, 64, 3, 6, buf)
+    rf = L.sssgs_render_forward
+    for gg, mm, mode, want in ((g16, None, 1, B.ERR_UNSUPPORTED), (g8, ct.byref(m), 1, B.ERR_INVALID_ARG),
+                               (g8, None, 2, B.ERR_INVALID_ARG)):
+        opt = B.Options(0, 0, mode)
+        st = rf(ct.byref(gg), ct.byref(cam), ct.byref(light), mm, ct.byref(opt), buf, 1 << 30, 100, buf, buf, buf,
+                None, None)
+        assert st == want, (mode, st)

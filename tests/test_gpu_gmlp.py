@@ -1,0 +1,152 @@
+"""Parity of the per-Gaussian network path (pipeline figure: Eq. 6 evaluated
+per Gaussian, its radiances composited into the 18-plane G-buffer, Eq. 7 from
+the composited values) against the FP64 oracle."""
+import numpy as np
+import pytest
+
+from oracle import gaussian_mlp as GM
+from oracle import oracle as O
+from paper_2408_12282_amd import scene
+
+from helpers import assert_close_masked, estimate_instances, rel_norm
+
+pytestmark = pytest.mark.gpu
+
+ELEM_REL = 1e-5
+GRAD_REL = 1e-3
+
+
+def _dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a, np.float32)).cuda()
+
+
+def _setup(n, seed, width=88, height=72):
+    from paper_2408_12282_amd import sssgs as B
+    g = scene.make_gaussians(n, 8, seed=seed)
+    vis = scene.make_visibility(n, seed=seed)
+    gm = scene.make_gaussian_mlp(seed=seed)
+    cam = scene.look_at_camera((0.3, -0.2, 3.0), width, height)
+    light = scene.default_light()
+    params = {k: _dev(v) for k, v in g.arrays().items() if v is not None}
+    return B, g, vis, gm, cam, light, params
+
+
+def _side_ok(g, vis, cam, light):
+    """Gaussians whose normal is not within 1e-6 of edge-on (the sign of the
+    normal is a decision taken from float inputs)."""
+    x, _ = GM.inputs(g.means, g.log_scales, g.quats, vis, cam.center, light.pos)
+    return np.abs(np.einsum("ij,ij->i", x[:, 0:3], x[:, 13:16])) > 1e-6
+
+
+@pytest.mark.parametrize("n", [1, 63, 3017])
+def test_gaussian_network_forward(n):
+    import torch
+    print(f"[gpu] per-Gaussian network forward n={n}", flush=True)
+    B, g, vis, gm, cam, light, params = _setup(n, seed=n)
+    feats = B.gaussian_mlp_forward(params, B.make_camera(cam), B.make_light(light), _dev(vis), _dev(gm))
+    torch.cuda.synchronize()
+    got = feats.cpu().numpy()
+    x, _ = GM.inputs(g.means, g.log_scales, g.quats, vis, cam.center, light.pos)
+    ref = GM.forward(x, gm)[0]
+    bound = GM.forward_bound(x, gm)   # magnitude of the terms each FP32 sum combines
+    ok = _side_ok(g, vis, cam, light)
+    for c in range(6):
+        assert_close_masked(got[c], ref[c], ok, ELEM_REL, f"plane {c}", scale=np.abs(ref[c]) + bound[c])
+    np.testing.assert_array_equal(got[6], vis)
+    np.testing.assert_array_equal(got[7], np.ones(n, np.float32))
+
+
+def test_gaussian_network_backward_and_accumulation():
+    import torch
+    n = 3017
+    print(f"[gpu] per-Gaussian network backward n={n}", flush=True)
+    B, g, vis, gm, cam, light, params = _setup(n, seed=5)
+    rng = np.random.default_rng(6)
+    dfeat = rng.normal(size=(8, n)).astype(np.float32)
+    base = {k: rng.normal(size=params[k].shape).astype(np.float32) for k in ("means", "log_scales", "quats")}
+    grads = {k: _dev(v) for k, v in base.items()}
+    dvis, dgm = _dev(np.zeros(n)), _dev(np.zeros(gm.size))
+    bc, bl = B.make_camera(cam), B.make_light(light)
+    B.gaussian_mlp_backward(params, bc, bl, _dev(vis), _dev(gm), _dev(dfeat), grads, dvis, dgm)
+    torch.cuda.synchronize()
+    ref = GM.feature_grads(g.means, g.log_scales, g.quats, vis, gm, cam.center, light.pos, dfeat)
+    ok = _side_ok(g, vis, cam, light)
+    errs = {}
+    for k in ("means", "log_scales", "quats"):
+        errs[k] = rel_norm((grads[k].cpu().numpy() - base[k])[:, ok], ref[k][:, ok])
+    errs["visibility"] = rel_norm(dvis.cpu().numpy()[ok], ref["visibility"][ok])
+    errs["params"] = rel_norm(dgm.cpu().numpy(), ref["params"])
+    print("grad rel errors:", {k: f"{v:.2e}" for k, v in errs.items()})
+    assert max(errs.values()) <= GRAD_REL, errs
+    # accumulate = 1 adds; a second identical call reproduces the sum bit for bit
+    first_p, first_v = dgm.clone(), dvis.clone()
+    B.gaussian_mlp_backward(params, bc, bl, _dev(vis), _dev(gm), _dev(dfeat), grads, dvis, dgm, accumulate=True)
+    torch.cuda.synchronize()
+    assert torch.equal(dgm, first_p + first_p) and torch.equal(dvis, first_v + first_v)
+    again_p = _dev(np.zeros(gm.size))
+    B.gaussian_mlp_backward(params, bc, bl, _dev(vis), _dev(gm), _dev(dfeat), grads, _dev(np.zeros(n)), again_p)
+    torch.cuda.synchronize()
+    assert torch.equal(again_p, first_p)
+
+
+def test_gaussian_network_empty():
+    import torch
+    B, g, vis, gm, cam, light, params = _setup(0, seed=1)
+    bc, bl = B.make_camera(cam), B.make_light(light)
+    feats = B.gaussian_mlp_forward(params, bc, bl, _dev(vis), _dev(gm))
+    dgm = _dev(np.full(gm.size, 7.0))
+    grads = {k: params[k].clone() for k in ("means", "log_scales", "quats")}
+    B.gaussian_mlp_backward(params, bc, bl, _dev(vis), _dev(gm), feats, grads, _dev(vis), dgm)
+    torch.cuda.synchronize()
+    assert feats.shape == (8, 0) and not torch.any(dgm)
+
+
+def test_render_with_per_gaussian_network():
+    """Whole path: per-Gaussian network -> projection -> binning -> 18-plane
+    compositing -> Eq. 7 from the composited radiances, forward and backward
+    through every stage back to the Gaussian parameters, the visibility and
+    the network weights (88x72 image: ragged tiles)."""
+    import torch
+    n, W, H = 4000, 88, 72
+    print(f"[gpu] per-Gaussian network render n={n} {W}x{H}", flush=True)
+    B, g, vis, gm, cam, light, params = _setup(n, seed=12, width=W, height=H)
+    feats64 = GM.features(g.means, g.log_scales, g.quats, vis, gm, cam.center, light.pos)
+    p64 = {k: v.astype(np.float64) for k, v in g.arrays().items() if v is not None and v.size}
+    p64["features"] = feats64
+    cap = max(1024, int(estimate_instances(g, cam) * 1.25) + 1024)
+    view = B.View(n, W, H, 8, 0, cap)
+    bc, bl = B.make_camera(cam), B.make_light(light)
+    rgb, gbuf, alpha, feats, _ = B.render_gaussian_mlp_forward(view, params, bc, bl, _dev(vis), _dev(gm))
+    torch.cuda.synchronize()
+    # the rendering stages on the features the network stage produced (that
+    # stage is compared on its own above), the gradient end to end below
+    ora_f = O.render(g, cam, light, radiance_features=True, params64=dict(p64, features=feats.cpu().numpy()),
+                     sens=True)
+    ok = ora_f["pix_flag"] == 0
+    assert_close_masked(gbuf.cpu().numpy(), ora_f["gbuf"], np.broadcast_to(ok, (18, H, W)), ELEM_REL, "gbuf",
+                        scale=np.abs(ora_f["gbuf"]) + ora_f["gbuf_abs"])
+    assert_close_masked(rgb.cpu().numpy(), ora_f["rgb"], np.broadcast_to(ok, (3, H, W)), ELEM_REL, "rgb",
+                        scale=np.abs(ora_f["rgb"]) + ora_f["rgb_sens"])
+    np.testing.assert_allclose(alpha.cpu().numpy(), gbuf.cpu().numpy()[17], rtol=1e-6, atol=1e-5)
+    # backward with upstream gradient on pixels away from alpha / stop decisions
+    rng = np.random.default_rng(13)
+    drgb = (rng.normal(size=(3, H, W)) * ok).astype(np.float32)
+    ora_b = O.render(g, cam, light, radiance_features=True, params64=p64, drgb=drgb)
+    x, cache = GM.inputs(g.means, g.log_scales, g.quats, vis, cam.center, light.pos)
+    _, acts = GM.forward(x, gm)
+    dnet = GM.backward(ora_b["grads"]["features"], gm, acts, cache, cam.center, light.pos)
+    ref = {k: v for k, v in ora_b["grads"].items() if k not in ("features", "sh", "mlp")}
+    for k in ("means", "log_scales", "quats"):
+        ref[k] = ref[k] + dnet[k]
+    ref["visibility"] = dnet["visibility"]
+    ref["gmlp"] = dnet["params"]
+    grads, dvis, dgm, _ = B.render_gaussian_mlp_backward(view, params, bc, bl, _dev(vis), _dev(gm), feats, gbuf,
+                                                         _dev(drgb))
+    torch.cuda.synchronize()
+    got = {k: v.cpu().numpy() for k, v in grads.items()}
+    got["visibility"] = dvis.cpu().numpy()
+    got["gmlp"] = dgm.cpu().numpy()
+    errs = {k: rel_norm(got[k], ref[k]) for k in ref if ref[k].size and np.any(ref[k])}
+    print("grad rel errors:", {k: f"{v:.2e}" for k, v in errs.items()})
+    assert max(errs.values()) <= GRAD_REL, errs
