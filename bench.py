@@ -25,6 +25,7 @@ HBM_PEAK_GBS = 8000.0
 FP32_VALU_TFLOPS = 78.6      # non-packed FP32 FMA: 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz
 BF16_MFMA_TFLOPS = 2500.0
 FP32_MFMA_TFLOPS = 157.3      # dense FP32 matrix-core peak
+FP32_VALU_TFLOPS = 157.3      # FP32 vector peak: 256 CUs x 2.4 GHz x 128 lanes (packed) x 2 flop per FMA
 
 
 def parse():
@@ -103,6 +104,7 @@ def run_gpu(precision: str, steps: int, warmup: int):
     stages = B.sssgs_timing_read()
     extras = time_training_kernels(rgb_ref=drgb, params=p, mlp_params=mp, grads=grads, dmlp=dmlp)
     ibl = time_ibl(view, p, bc, mp, mlp.width, prec)
+    gnet = time_gaussian_network(g, cam, light, drgb, steps)
     flags, m_dev = B.sssgs_workspace_status(ctypes_ptr(view), g.n, cam.width, cam.height, g.feat_dim, mlp.width,
                                             cap)
     assert flags == 0 and m_dev == M, (flags, m_dev, M)
@@ -110,7 +112,7 @@ def run_gpu(precision: str, steps: int, warmup: int):
     return {"ms": ms, "stages": {k: (v[0] / max(v[1], 1), v[1]) for k, v in stages.items()}, "M": M,
             "bwd_records": per_tile_last, "fwd_records": fwd_records, "listed": listed, "n": g.n,
             "C": 10 + g.feat_dim, "HW": cam.width * cam.height, "precision": precision, "training": extras,
-            "ibl": ibl}
+            "ibl": ibl, "gnet": gnet}
 
 
 def time_training_kernels(rgb_ref, params, mlp_params, grads, dmlp, reps: int = 10):
@@ -178,6 +180,66 @@ def time_ibl(view, params, cam_struct, mlp_params, mlp_width, prec, k: int = 16,
     return {"lights": k, "forward_ms": round(res["multi"], 4), "single_light_forward_ms": round(res["single"], 4),
             "ms_per_added_light": round((res["multi"] - res["single"]) / (k - 1), 4),
             "workload": "300k Gaussians 800x800, environment light samples on a Fibonacci sphere"}
+
+
+def time_gaussian_network(g, cam, light, drgb, steps: int):
+    """The paper's per-Gaussian network (pipeline figure) outside the headline:
+    the same 300k Gaussians and view, the network evaluated per Gaussian before
+    rasterisation (FP32), its radiances composited into the 18-plane G-buffer
+    and Eq. 7 evaluated from them; forward + backward per step, timed with
+    events on the stream, then per stage."""
+    import torch
+    from paper_2408_12282_amd import scene, sssgs as B
+    dev = "cuda"
+    n = g.n
+    p = {k: torch.from_numpy(np.ascontiguousarray(v)).to(dev) for k, v in g.arrays().items() if v is not None}
+    p["features"] = torch.empty((8, n), device=dev)
+    vis = torch.from_numpy(scene.make_visibility(n, seed=0)).to(dev)
+    gm = torch.from_numpy(scene.make_gaussian_mlp(seed=0)).to(dev)
+    view = B.View(n, cam.width, cam.height, 8, 0, 24 * n, device=dev)
+    bc, bl = B.make_camera(cam), B.make_light(light)
+    ws = B.gaussian_mlp_workspace(n)
+    grads = {k: torch.empty_like(v) for k, v in p.items()}
+    dvis, dgm = torch.empty_like(vis), torch.empty_like(gm)
+
+    def step():
+        rgb, gbuf, alpha, feats, _ = B.render_gaussian_mlp_forward(view, p, bc, bl, vis, gm, ws)
+        B.render_gaussian_mlp_backward(view, p, bc, bl, vis, gm, feats, gbuf, drgb, workspace=ws, grads=grads,
+                                       dvis=dvis, dgmlp=dgm)
+
+    for _ in range(3):
+        step()
+    torch.cuda.synchronize()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    reps = max(1, steps)
+    t0.record()
+    for _ in range(reps):
+        step()
+    t1.record()
+    torch.cuda.synchronize()
+    ms = t0.elapsed_time(t1) / reps
+    B.sssgs_timing_read()
+    B.sssgs_timing_enable(True)
+    for _ in range(max(1, min(reps, 10))):
+        step()
+    torch.cuda.synchronize()
+    B.sssgs_timing_enable(False)
+    st = {k: v[0] / v[1] for k, v in B.sssgs_timing_read().items() if v[1] > 0}
+    # multiply-adds of the network per Gaussian (42x64, 64x32, 32x32, 32x32, 32x3, 32x3); the backward
+    # recomputes the forward, propagates the input gradient and forms the weight gradient (3x)
+    flop = 2 * (42 * 64 + 64 * 32 + 32 * 32 + 32 * 32 + 32 * 3 + 32 * 3)
+    roof = {}
+    for name, f in (("gmlp_fwd", n * flop), ("gmlp_bwd", 3 * n * flop)):
+        if st.get(name, 0) > 0:
+            tf = f / (st[name] * 1e-3) / 1e12
+            roof[name] = {"bound": "alu", "achieved": round(tf, 2), "peak": FP32_VALU_TFLOPS, "unit": "TFLOP/s",
+                          "frac": round(tf / FP32_VALU_TFLOPS, 4), "flop_per_launch": int(f),
+                          "ms_per_launch": round(st[name], 4)}
+    return {"workload": "300k Gaussians 800x800, per-Gaussian network 42->64->32->32->(32->3 | 3), FP32, "
+                        "18-plane G-buffer, fwd+bwd",
+            "ms_per_step": round(ms, 4), "mpix_s": round(MPIX / (ms * 1e-3), 2),
+            "stages_ms": {k: round(v, 4) for k, v in st.items()}, "roofline": roof}
 
 
 def ctypes_ptr(view):
@@ -295,16 +357,17 @@ def main():
                    "features": 16, "gbuffer_channels": head["C"], "mlp": "58(64)->64x3->6",
                    "mlp_precision": "bf16" if "bf16" in res else "fp32", "tile_instances": head["M"]},
         "roofline": dominant,
-        "stages_ms": {k: round(v[0], 4) for k, v in head["stages"].items()},
+        "stages_ms": {k: round(v[0], 4) for k, v in head["stages"].items() if v[1] > 0},
     }
     if "fp32" in res and "bf16" in res:
         f = res["fp32"]
         line["fp32_plain"] = {"ms_per_step": round(f["ms"], 4), "mpix_s": round(MPIX / (f["ms"] * 1e-3), 2),
-                              "stages_ms": {k: round(v[0], 4) for k, v in f["stages"].items()}}
+                              "stages_ms": {k: round(v[0], 4) for k, v in f["stages"].items() if v[1] > 0}}
         line["bf16_speedup_vs_fp32"] = round(f["ms"] / head["ms"], 3)
     line["roofline_all"] = rl
     line["training_kernels"] = head["training"]
     line["image_based_lighting"] = head["ibl"]
+    line["per_gaussian_network"] = head["gnet"]
     if a.calib_copy_mib > 0:
         import torch
         src = torch.ones(a.calib_copy_mib << 18, device="cuda")

@@ -497,15 +497,20 @@ def render_gaussian_mlp_forward(view: View, params: dict, cam: Camera, light: Li
 
 def render_gaussian_mlp_backward(view: View, params: dict, cam: Camera, light: Light, visibility: torch.Tensor,
                                  gmlp: torch.Tensor, feats: torch.Tensor, gbuf, drgb, dgbuf=None, dalpha=None,
-                                 workspace: Optional[torch.Tensor] = None):
+                                 workspace: Optional[torch.Tensor] = None, grads: Optional[dict] = None,
+                                 dvis: Optional[torch.Tensor] = None, dgmlp: Optional[torch.Tensor] = None):
     """Gradients of every Gaussian parameter (dict), of the visibility and of
-    the network parameters."""
+    the network parameters (all overwritten; pass buffers to reuse them)."""
     p = dict(params, features=feats)
-    grads = {k: torch.zeros_like(v) for k, v in p.items() if v is not None}
+    if grads is None:
+        grads = {k: torch.empty_like(v) for k, v in p.items() if v is not None}
+    else:
+        grads = dict(grads)
+        grads.setdefault("features", torch.empty_like(feats))
     render_backward(view, p, -1, cam, light, gbuf, drgb, dgbuf, dalpha, None, 64, PREC_FP32, grads=grads,
                     radiance_features=True)
-    dvis = torch.empty_like(visibility)
-    dgmlp = torch.empty_like(gmlp)
+    dvis = torch.empty_like(visibility) if dvis is None else dvis
+    dgmlp = torch.empty_like(gmlp) if dgmlp is None else dgmlp
     gaussian_mlp_backward(params, cam, light, visibility, gmlp, grads["features"], grads, dvis, dgmlp,
                           workspace=workspace)
     dfeat = grads.pop("features")
