@@ -591,7 +591,7 @@ int64_t sssgs_gaussian_mlp_param_count(void) { return gmlp_param_count(); }
 
 namespace {
 struct GmlpLayout {
-  size_t wt, part, mid, total;
+  size_t wt, part, mid, act, dz, total;
 };
 GmlpLayout gmlp_layout(int32_t n) {
   GmlpLayout L;
@@ -603,8 +603,10 @@ GmlpLayout gmlp_layout(int32_t n) {
     return at_;
   };
   L.wt = take(np * 4);
-  L.part = take((size_t)gmlp_bwd_grid(n) * np * 4);
+  L.part = take((size_t)gmlp_wgrad_grid(n) * np * 4);
   L.mid = take((size_t)reduce_scratch_floats((int)np) * 4);
+  L.act = take(gmlp_act_floats(n) * 4);
+  L.dz = take(gmlp_dz_floats(n) * 4);
   L.total = p;
   return L;
 }
@@ -670,11 +672,14 @@ sssgs_status sssgs_gaussian_mlp_backward(const sssgs_gaussians *g, const sssgs_c
   a.dfeat = dL_dfeatures;
   a.d_means = dL_dmeans; a.d_log_scales = dL_dlog_scales; a.d_quats = dL_dquats; a.d_vis = dL_dvisibility;
   a.partials = at<float>(ws, L.part);
+  a.act = at<float>(ws, L.act);
+  a.dz = at<float>(ws, L.dz);
+  a.ldn = gmlp_ldn(g->n);
   a.accumulate = accumulate;
   Scope sc(kStGmlpBwd, st);
   launch_gmlp_prep(params, at<float>(ws, L.wt), st);
   launch_gmlp_bwd(a, st);
-  launch_reduce_partials(a.partials, gmlp_bwd_grid(g->n), gmlp_param_count(), at<float>(ws, L.mid), dL_dparams,
+  launch_reduce_partials(a.partials, gmlp_wgrad_grid(g->n), gmlp_param_count(), at<float>(ws, L.mid), dL_dparams,
                          accumulate, st);
   return check_hip("gaussian network backward launch");
 }

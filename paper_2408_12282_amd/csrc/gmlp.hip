@@ -234,269 +234,319 @@ __global__ __launch_bounds__(256) void gmlp_prep_kernel(const float *__restrict_
 }
 
 // ----------------------------------------------------------------- backward
+//
+// Two kernels.  gmlp_bwd_kernel: one lane per Gaussian (high occupancy: one
+// 64-row LDS column per lane); it recomputes the forward keeping only the
+// Leaky-ReLU signs (bit masks in registers), runs the backward through the
+// layers and the chain to the Gaussian parameters, and stores every layer's
+// input activations and output gradients unit-major ([unit][ldn], ldn = n
+// rounded up to 64; lanes past n store zero gradients).  gmlp_wgrad_kernel:
+// the weight gradients sum_g dz[o][g] a[i][g] on the matrix cores, streaming
+// those records; one layer group per grid row.
 
-// LDS rows of one wave (row stride kLS, lane = column):
-constexpr int kRH1 = 0;     // h1 (64); later dz0
-constexpr int kRH2 = 64;    // h2 (32); x during the forward and before the layer-0 gradient (48 rows incl. zero pad)
-constexpr int kRH3 = 96;    // trunk output h3 (32)
-constexpr int kRE = 128;    // incident hidden e (32)
-constexpr int kRDZ = 160;   // output gradients of the current layer (32)
-constexpr int kRows = 192;
+// Activation rows (layer inputs) and output-gradient rows of the records.
+constexpr int kAX = 0, kAH1 = 42, kAH2 = 106, kAH3 = 138, kAE = 170, kARows = 202;
+constexpr int kD0 = 0, kD1 = 64, kD2 = 96, kDI = 128, kDH = 160, kDRows = 166;
 
-// Weight-gradient tile: acc[o][i] += sum_g lds[arow + o][g] lds[brow + i][g]
-// over the wave's 64 Gaussians (16 steps of K = 4).
-__device__ __forceinline__ void wtile(f32x4 &acc, const float *lds, int arow, int brow) {
-  const int lane = threadIdx.x & 63, r = lane & 15, g = lane >> 4;
-  const float *a = lds + (arow + r) * kLS + g, *b = lds + (brow + r) * kLS + g;
+template <int N>
+__device__ __forceinline__ void put_rows(float *rec, int row0, size_t ldn, size_t g, const float (&v)[N]) {
 #pragma unroll
-  for (int k = 0; k < 16; k++) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[4 * k], b[4 * k], acc, 0, 0, 0);
+  for (int k = 0; k < N; k++) rec[(row0 + k) * ldn + g] = v[k];
 }
 
-// Bias-gradient tile: every column holds sum_g lds[arow + o][g].
-__device__ __forceinline__ void btile(f32x4 &acc, const float *lds, int arow) {
-  const int lane = threadIdx.x & 63, r = lane & 15, g = lane >> 4;
-  const float *a = lds + (arow + r) * kLS + g;
+template <int N>
+__device__ __forceinline__ uint64_t sign_mask(const float (&z)[N]) {
+  uint64_t m = 0;
 #pragma unroll
-  for (int k = 0; k < 16; k++) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[4 * k], 1.f, acc, 0, 0, 0);
+  for (int k = 0; k < N; k++) m |= (z[k] > 0.f ? 1ull : 0ull) << k;
+  return m;
 }
 
-// Write a weight tile (rows o0.., cols i0..) of layer L into the partial row.
-__device__ __forceinline__ void put_wtile(float *part, const GL &L, int o0, int i0, const f32x4 &acc) {
-  const int lane = threadIdx.x & 63, c = i0 + (lane & 15);
-#pragma unroll
-  for (int j = 0; j < 4; j++) {
-    const int o = o0 + 4 * (lane >> 4) + j;
-    if (o < L.rows && c < L.cols) part[L.w + o * L.cols + c] = acc[j];
-  }
-}
-
-__device__ __forceinline__ void put_btile(float *part, const GL &L, int o0, int row_off, const f32x4 &acc) {
-  const int lane = threadIdx.x & 63;
-  if ((lane & 15) != 0) return;
-#pragma unroll
-  for (int j = 0; j < 4; j++) {
-    const int o = 4 * (lane >> 4) + j - row_off;
-    if (o >= 0 && o < L.rows) part[L.b + o0 + o] = acc[j];
-  }
-}
+__device__ __forceinline__ float slope(uint64_t m, int k) { return (m >> k) & 1ull ? 1.f : kSlope; }
 
 __global__ __launch_bounds__(64) void gmlp_bwd_kernel(GmlpArgs A) {
-  __shared__ float lds[kRows * kLS];
+  __shared__ float lds[64 * kLS];
   const int lane = threadIdx.x;
+  const int i = blockIdx.x * 64 + lane;  // < ldn: the grid covers ldn / 64 blocks
+  const bool live = i < A.n;
+  const int gi = live ? i : 0;
   float *col = lds + lane;
   const cptr wt = as_const(A.wt), P = as_const(A.params);
-  // weight-gradient sums: heads (incident output over e, SSS over h3, bias of
-  // both), incident hidden, trunk 2, 1, 0 (bias of layer 0 through a ones row)
-  f32x4 gHl[2], gHs[2], gHb, gI[4], gIb[2], g2[4], g2b[2], g1[8], g1b[2], g0[12];
-  const f32x4 z4 = {0.f, 0.f, 0.f, 0.f};
-  for (int k = 0; k < 2; k++) gHl[k] = gHs[k] = gIb[k] = g2b[k] = g1b[k] = z4;
-  gHb = z4;
-  for (int k = 0; k < 4; k++) gI[k] = g2[k] = z4;
-  for (int k = 0; k < 8; k++) g1[k] = z4;
-  for (int k = 0; k < 12; k++) g0[k] = z4;
-  const size_t n = A.n;
-  for (int base = blockIdx.x * 64; base < A.n; base += gridDim.x * 64) {
-    const int i = base + lane;
-    const bool live = i < A.n;
-    const int gi = live ? i : 0;
-    GIn G;
-    gaussian_input(A, gi, G);
-    // ---- forward, keeping every layer's activations in LDS
-    write_input(G, col, kRH2);
-    {
-      float h[64];
-      layer_fwd<64, kGIn>(wt + kL0.w, P + kL0.b, col + kRH2 * kLS, h);
+  const size_t n = A.n, ldn = A.ldn;
+  float *act = A.act, *dzr = A.dz;
+  GIn G;
+  gaussian_input(A, gi, G);
+  write_input(G, col, 0);
 #pragma unroll
-      for (int k = 0; k < 64; k++) h[k] = lrelu(h[k]);
-      put_col(col, kRH1, h);
-    }
-    float lsss[3], zl[3];
-    {
-      float h[32];
-      layer_fwd<32, 64>(wt + kL1.w, P + kL1.b, col + kRH1 * kLS, h);
-#pragma unroll
-      for (int k = 0; k < 32; k++) h[k] = lrelu(h[k]);
-      put_col(col, kRH2, h);
-      layer_fwd<32, 32>(wt + kL2.w, P + kL2.b, col + kRH2 * kLS, h);
-#pragma unroll
-      for (int k = 0; k < 32; k++) h[k] = lrelu(h[k]);
-      put_col(col, kRH3, h);
-      layer_fwd<32, 32>(wt + kLi.w, P + kLi.b, col + kRH3 * kLS, h);
-#pragma unroll
-      for (int k = 0; k < 32; k++) h[k] = lrelu(h[k]);
-      put_col(col, kRE, h);
-      float zs[3];
-      layer_fwd<3, 32>(wt + kLl.w, P + kLl.b, col + kRE * kLS, zl);
-      layer_fwd<3, 32>(wt + kLs.w, P + kLs.b, col + kRH3 * kLS, zs);
-      for (int c = 0; c < 3; c++) lsss[c] = 1.f / (1.f + expf(-zs[c]));
-    }
-    // ---- heads: output gradients (dead lanes contribute zero)
-    float df[8];
-    for (int c = 0; c < 8; c++) df[c] = live ? A.dfeat[c * n + i] : 0.f;
-    float dzl[3], dzs[3];
-    for (int c = 0; c < 3; c++) {
-      dzl[c] = zl[c] > 0.f ? df[c] : 0.f;
-      dzs[c] = df[3 + c] * lsss[c] * (1.f - lsss[c]);
-    }
-    {
-      float hd[16];
-      for (int c = 0; c < 3; c++) {
-        hd[c] = dzl[c];
-        hd[3 + c] = dzs[c];
-      }
-      for (int c = 6; c < 16; c++) hd[c] = 0.f;
-      put_col(col, kRDZ, hd);
-    }
-    __syncthreads();
-    for (int t = 0; t < 2; t++) {
-      wtile(gHl[t], lds, kRDZ, kRE + 16 * t);
-      wtile(gHs[t], lds, kRDZ, kRH3 + 16 * t);
-    }
-    btile(gHb, lds, kRDZ);
-    // incident hidden: dz_i = lrelu'(e) (Wl^T dzl); trunk output gets Ws^T dzs
-    float dh3[32];
-    {
-      float dzi[32];
-#pragma unroll
-      for (int c = 0; c < 32; c++) {
-        float d = 0.f, e = 0.f;
-#pragma unroll
-        for (int o = 0; o < 3; o++) {
-          d = __fmaf_rn(P[kLl.w + o * 32 + c], dzl[o], d);
-          e = __fmaf_rn(P[kLs.w + o * 32 + c], dzs[o], e);
-        }
-        dzi[c] = d * lrelu_d(col[(kRE + c) * kLS]);
-        dh3[c] = e;
-      }
-      __syncthreads();
-      put_col(col, kRDZ, dzi);
-    }
-    __syncthreads();
-    for (int ot = 0; ot < 2; ot++) {
-      for (int it = 0; it < 2; it++) wtile(gI[2 * ot + it], lds, kRDZ + 16 * ot, kRH3 + 16 * it);
-      btile(gIb[ot], lds, kRDZ + 16 * ot);
-    }
-    {
-      float d[32];
-      layer_bwd<32, 32>(P + kLi.w, col + kRDZ * kLS, d);
-#pragma unroll
-      for (int c = 0; c < 32; c++) dh3[c] = (dh3[c] + d[c]) * lrelu_d(col[(kRH3 + c) * kLS]);
-      __syncthreads();
-      put_col(col, kRDZ, dh3);  // dz2
-    }
-    __syncthreads();
-    for (int ot = 0; ot < 2; ot++) {
-      for (int it = 0; it < 2; it++) wtile(g2[2 * ot + it], lds, kRDZ + 16 * ot, kRH2 + 16 * it);
-      btile(g2b[ot], lds, kRDZ + 16 * ot);
-    }
-    {
-      float d[32];
-      layer_bwd<32, 32>(P + kL2.w, col + kRDZ * kLS, d);
-#pragma unroll
-      for (int c = 0; c < 32; c++) d[c] *= lrelu_d(col[(kRH2 + c) * kLS]);
-      __syncthreads();
-      put_col(col, kRDZ, d);  // dz1
-    }
-    __syncthreads();
-    for (int ot = 0; ot < 2; ot++) {
-      for (int it = 0; it < 4; it++) wtile(g1[4 * ot + it], lds, kRDZ + 16 * ot, kRH1 + 16 * it);
-      btile(g1b[ot], lds, kRDZ + 16 * ot);
-    }
-    {
-      float d[64];
-      layer_bwd<32, 64>(P + kL1.w, col + kRDZ * kLS, d);
-#pragma unroll
-      for (int c = 0; c < 64; c++) d[c] *= lrelu_d(col[(kRH1 + c) * kLS]);
-      __syncthreads();
-      put_col(col, kRH1, d);  // dz0 over h1
-      // layer-0 input again, a ones row for the bias and zero padding
-      write_input(G, col, kRH2);
-      col[(kRH2 + kGIn) * kLS] = 1.f;
-      for (int r = kGIn + 1; r < 48; r++) col[(kRH2 + r) * kLS] = 0.f;
-    }
-    __syncthreads();
-    for (int ot = 0; ot < 4; ot++)
-      for (int it = 0; it < 3; it++) wtile(g0[3 * ot + it], lds, kRH1 + 16 * ot, kRH2 + 16 * it);
-    // ---- input gradient and the chain to the Gaussian parameters
-    float dx[kGIn];
-    layer_bwd<64, kGIn>(P + kL0.w, col + kRH1 * kLS, dx);
-    if (live) {
-      float dmu[3] = {0.f, 0.f, 0.f};
-      // w_in = u / |u| and d = |u| with u = light - mu
-      {
-        const float p = G.wi[0] * dx[10] + G.wi[1] * dx[11] + G.wi[2] * dx[12];
-        const float il = 1.f / G.dl;
-        for (int k = 0; k < 3; k++) dmu[k] -= (dx[10 + k] - G.wi[k] * p) * il + dx[16] * G.wi[k];
-      }
-      {
-        const float p = G.wo[0] * dx[13] + G.wo[1] * dx[14] + G.wo[2] * dx[15];
-        const float ic = 1.f / G.dc;
-        for (int k = 0; k < 3; k++) dmu[k] -= (dx[13 + k] - G.wo[k] * p) * ic;
-      }
-#pragma unroll
-      for (int oct = 0; oct < 4; oct++) {
-        const float sc = (float)(1 << oct), fr = sc * 3.14159265358979323846f;
-#pragma unroll
-        for (int ax = 0; ax < 3; ax++)
-          dmu[ax] += fr * (dx[18 + 6 * oct + ax] * cospif(sc * G.mu[ax]) - dx[21 + 6 * oct + ax] * sinpif(sc * G.mu[ax]));
-      }
-      // normal = sign * column kmin of R(q^)
-      float dR[9];
-      for (int r = 0; r < 3; r++)
-        for (int k = 0; k < 3; k++) dR[3 * r + k] = G.kmin == k ? G.sign * dx[r] : 0.f;
-      const float w = G.qn[0], qx = G.qn[1], qy = G.qn[2], qz = G.qn[3];
-      float dqn[4];
-      dqn[0] = dx[3] + 2.f * (-qz * dR[1] + qy * dR[2] + qz * dR[3] - qx * dR[5] - qy * dR[6] + qx * dR[7]);
-      dqn[1] = dx[4] + 2.f * (qy * dR[1] + qz * dR[2] + qy * dR[3] - 2.f * qx * dR[4] - w * dR[5] + qz * dR[6] +
-                              w * dR[7] - 2.f * qx * dR[8]);
-      dqn[2] = dx[5] + 2.f * (-2.f * qy * dR[0] + qx * dR[1] + w * dR[2] + qx * dR[3] + qz * dR[5] - w * dR[6] +
-                              qz * dR[7] - 2.f * qy * dR[8]);
-      dqn[3] = dx[6] + 2.f * (-2.f * qz * dR[0] - w * dR[1] + qx * dR[2] + w * dR[3] - 2.f * qz * dR[4] +
-                              qy * dR[5] + qx * dR[6] + qy * dR[7]);
-      const float pq = w * dqn[0] + qx * dqn[1] + qy * dqn[2] + qz * dqn[3];
-      for (int k = 0; k < 3; k++) A.d_means[k * n + i] += dmu[k];
-      for (int k = 0; k < 3; k++) A.d_log_scales[k * n + i] += dx[7 + k] * G.s[k];
-      for (int k = 0; k < 4; k++) A.d_quats[k * n + i] += (dqn[k] - G.qn[k] * pq) / G.qlen;
-      const float dv = dx[17] + df[6];
-      A.d_vis[i] = A.accumulate ? A.d_vis[i] + dv : dv;
-    }
-    __syncthreads();
-  }
-  // ---- this wave's partial sums of the weight gradient
-  float *part = A.partials + (size_t)blockIdx.x * kGParams;
-  for (int t = 0; t < 2; t++) {
-    put_wtile(part, kLl, 0, 16 * t, gHl[t]);
-    // SSS rows sit at 3..5 of the head tile
-    const int lane_ = threadIdx.x & 63, c = 16 * t + (lane_ & 15);
-    for (int j = 0; j < 4; j++) {
-      const int o = 4 * (lane_ >> 4) + j - 3;
-      if (o >= 0 && o < 3) part[kLs.w + o * 32 + c] = gHs[t][j];
-    }
-  }
-  put_btile(part, kLl, 0, 0, gHb);
-  put_btile(part, kLs, 0, 3, gHb);
-  for (int ot = 0; ot < 2; ot++) {
-    for (int it = 0; it < 2; it++) {
-      put_wtile(part, kLi, 16 * ot, 16 * it, gI[2 * ot + it]);
-      put_wtile(part, kL2, 16 * ot, 16 * it, g2[2 * ot + it]);
-    }
-    for (int it = 0; it < 4; it++) put_wtile(part, kL1, 16 * ot, 16 * it, g1[4 * ot + it]);
-    put_btile(part, kLi, 16 * ot, 0, gIb[ot]);
-    put_btile(part, kL2, 16 * ot, 0, g2b[ot]);
-    put_btile(part, kL1, 16 * ot, 0, g1b[ot]);
-  }
-  // layer 0: columns 0..41 weights, column 42 (the ones row) the bias
+  for (int k = 0; k < kGIn; k++) act[(kAX + k) * ldn + i] = col[k * kLS];
+  // ---- forward: activations to the records, Leaky-ReLU signs kept as masks
+  uint64_t m1, m2, m3, me;
+  float zl[3], lsss[3];
   {
-    const int lane_ = threadIdx.x & 63;
-    for (int ot = 0; ot < 4; ot++)
-      for (int it = 0; it < 3; it++) {
-        const int c = 16 * it + (lane_ & 15);
-        for (int j = 0; j < 4; j++) {
-          const int o = 16 * ot + 4 * (lane_ >> 4) + j;
-          if (c < kGIn) part[kL0.w + o * kGIn + c] = g0[3 * ot + it][j];
-          else if (c == kGIn) part[kL0.b + o] = g0[3 * ot + it][j];
+    float h[64];
+    layer_fwd<64, kGIn>(wt + kL0.w, P + kL0.b, col, h);
+    m1 = sign_mask(h);
+#pragma unroll
+    for (int k = 0; k < 64; k++) h[k] = lrelu(h[k]);
+    put_col(col, 0, h);
+    put_rows(act, kAH1, ldn, i, h);
+  }
+  {
+    float h[32];
+    layer_fwd<32, 64>(wt + kL1.w, P + kL1.b, col, h);
+    m2 = sign_mask(h);
+#pragma unroll
+    for (int k = 0; k < 32; k++) h[k] = lrelu(h[k]);
+    put_col(col, 0, h);
+    put_rows(act, kAH2, ldn, i, h);
+    layer_fwd<32, 32>(wt + kL2.w, P + kL2.b, col, h);
+    m3 = sign_mask(h);
+#pragma unroll
+    for (int k = 0; k < 32; k++) h[k] = lrelu(h[k]);
+    put_col(col, 0, h);   // trunk output
+    put_rows(act, kAH3, ldn, i, h);
+    layer_fwd<32, 32>(wt + kLi.w, P + kLi.b, col, h);
+    me = sign_mask(h);
+#pragma unroll
+    for (int k = 0; k < 32; k++) h[k] = lrelu(h[k]);
+    put_col(col, 32, h);  // incident head, hidden
+    put_rows(act, kAE, ldn, i, h);
+    float zs[3];
+    layer_fwd<3, 32>(wt + kLl.w, P + kLl.b, col + 32 * kLS, zl);
+    layer_fwd<3, 32>(wt + kLs.w, P + kLs.b, col, zs);
+    for (int c = 0; c < 3; c++) lsss[c] = 1.f / (1.f + expf(-zs[c]));
+  }
+  // ---- backward
+  float df[8];
+  for (int c = 0; c < 8; c++) df[c] = live ? A.dfeat[c * n + i] : 0.f;
+  float dzl[3], dzs[3];
+  for (int c = 0; c < 3; c++) {
+    dzl[c] = zl[c] > 0.f ? df[c] : 0.f;
+    dzs[c] = df[3 + c] * lsss[c] * (1.f - lsss[c]);
+  }
+  {
+    float hd[6] = {dzl[0], dzl[1], dzl[2], dzs[0], dzs[1], dzs[2]};
+    put_rows(dzr, kDH, ldn, i, hd);
+  }
+  float dh3[32];
+  {
+    float dzi[32];
+#pragma unroll
+    for (int c = 0; c < 32; c++) {
+      float d = 0.f, e = 0.f;
+#pragma unroll
+      for (int o = 0; o < 3; o++) {
+        d = __fmaf_rn(P[kLl.w + o * 32 + c], dzl[o], d);
+        e = __fmaf_rn(P[kLs.w + o * 32 + c], dzs[o], e);
+      }
+      dzi[c] = d * slope(me, c);
+      dh3[c] = e;
+    }
+    put_col(col, 0, dzi);
+    put_rows(dzr, kDI, ldn, i, dzi);
+  }
+  {
+    float d[32];
+    layer_bwd<32, 32>(P + kLi.w, col, d);
+#pragma unroll
+    for (int c = 0; c < 32; c++) d[c] = (dh3[c] + d[c]) * slope(m3, c);
+    put_col(col, 0, d);  // dz2
+    put_rows(dzr, kD2, ldn, i, d);
+  }
+  {
+    float d[32];
+    layer_bwd<32, 32>(P + kL2.w, col, d);
+#pragma unroll
+    for (int c = 0; c < 32; c++) d[c] *= slope(m2, c);
+    put_col(col, 0, d);  // dz1
+    put_rows(dzr, kD1, ldn, i, d);
+  }
+  {
+    float d[64];
+    layer_bwd<32, 64>(P + kL1.w, col, d);
+#pragma unroll
+    for (int c = 0; c < 64; c++) d[c] *= slope(m1, c);
+    put_col(col, 0, d);  // dz0
+    put_rows(dzr, kD0, ldn, i, d);
+  }
+  // ---- input gradient and the chain to the Gaussian parameters
+  float dx[kGIn];
+  layer_bwd<64, kGIn>(P + kL0.w, col, dx);
+  if (!live) return;
+  float dmu[3] = {0.f, 0.f, 0.f};
+  // w_in = u / |u| and d = |u| with u = light - mu
+  {
+    const float p = G.wi[0] * dx[10] + G.wi[1] * dx[11] + G.wi[2] * dx[12];
+    const float il = 1.f / G.dl;
+    for (int k = 0; k < 3; k++) dmu[k] -= (dx[10 + k] - G.wi[k] * p) * il + dx[16] * G.wi[k];
+  }
+  {
+    const float p = G.wo[0] * dx[13] + G.wo[1] * dx[14] + G.wo[2] * dx[15];
+    const float ic = 1.f / G.dc;
+    for (int k = 0; k < 3; k++) dmu[k] -= (dx[13 + k] - G.wo[k] * p) * ic;
+  }
+#pragma unroll
+  for (int oct = 0; oct < 4; oct++) {
+    const float sc = (float)(1 << oct), fr = sc * 3.14159265358979323846f;
+#pragma unroll
+    for (int ax = 0; ax < 3; ax++)
+      dmu[ax] += fr * (dx[18 + 6 * oct + ax] * cospif(sc * G.mu[ax]) - dx[21 + 6 * oct + ax] * sinpif(sc * G.mu[ax]));
+  }
+  // normal = sign * column kmin of R(q^)
+  float dR[9];
+  for (int r = 0; r < 3; r++)
+    for (int k = 0; k < 3; k++) dR[3 * r + k] = G.kmin == k ? G.sign * dx[r] : 0.f;
+  const float w = G.qn[0], qx = G.qn[1], qy = G.qn[2], qz = G.qn[3];
+  float dqn[4];
+  dqn[0] = dx[3] + 2.f * (-qz * dR[1] + qy * dR[2] + qz * dR[3] - qx * dR[5] - qy * dR[6] + qx * dR[7]);
+  dqn[1] = dx[4] + 2.f * (qy * dR[1] + qz * dR[2] + qy * dR[3] - 2.f * qx * dR[4] - w * dR[5] + qz * dR[6] +
+                          w * dR[7] - 2.f * qx * dR[8]);
+  dqn[2] = dx[5] + 2.f * (-2.f * qy * dR[0] + qx * dR[1] + w * dR[2] + qx * dR[3] + qz * dR[5] - w * dR[6] +
+                          qz * dR[7] - 2.f * qy * dR[8]);
+  dqn[3] = dx[6] + 2.f * (-2.f * qz * dR[0] - w * dR[1] + qx * dR[2] + w * dR[3] - 2.f * qz * dR[4] +
+                          qy * dR[5] + qx * dR[6] + qy * dR[7]);
+  const float pq = w * dqn[0] + qx * dqn[1] + qy * dqn[2] + qz * dqn[3];
+  for (int k = 0; k < 3; k++) A.d_means[k * n + i] += dmu[k];
+  for (int k = 0; k < 3; k++) A.d_log_scales[k * n + i] += dx[7 + k] * G.s[k];
+  for (int k = 0; k < 4; k++) A.d_quats[k * n + i] += (dqn[k] - G.qn[k] * pq) / G.qlen;
+  const float dv = dx[17] + df[6];
+  A.d_vis[i] = A.accumulate ? A.d_vis[i] + dv : dv;
+}
+
+// 16 consecutive record values of row `row` for the lane's Gaussians
+// base + 16 q + 0..15 (q = lane / 16): the lane's K operands of 16 matrix-core
+// steps (K runs over Gaussians; A and B take the same order).
+__device__ __forceinline__ void load16(const float *__restrict__ rec, int row, size_t ldn, size_t g0, float (&v)[16]) {
+  const float4 *p = reinterpret_cast<const float4 *>(rec + row * ldn + g0);
+#pragma unroll
+  for (int k = 0; k < 4; k++) {
+    const float4 t = p[k];
+    v[4 * k] = t.x; v[4 * k + 1] = t.y; v[4 * k + 2] = t.z; v[4 * k + 3] = t.w;
+  }
+}
+
+__device__ __forceinline__ void mma16(f32x4 &acc, const float (&a)[16], const float (&b)[16]) {
+#pragma unroll
+  for (int k = 0; k < 16; k++) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[k], b[k], acc, 0, 0, 0);
+}
+
+__device__ __forceinline__ void mma16_ones(f32x4 &acc, const float (&a)[16]) {
+#pragma unroll
+  for (int k = 0; k < 16; k++) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[k], 1.f, acc, 0, 0, 0);
+}
+
+// Weight and bias gradient of one dense layer: dz rows D0.. (OT tiles of 16
+// output units), input rows A0.. (IT tiles of 16 input units).
+template <int OT, int IT>
+__device__ void layer_wgrad(const GmlpArgs &A, int D0, int A0, const GL &L, float *part) {
+  const int lane = threadIdx.x & 63, r = lane & 15, q = lane >> 4;
+  const size_t ldn = A.ldn;
+  f32x4 acc[OT][IT], bacc[OT];
+  const f32x4 z4 = {0.f, 0.f, 0.f, 0.f};
+  for (int o = 0; o < OT; o++) {
+    bacc[o] = z4;
+    for (int t = 0; t < IT; t++) acc[o][t] = z4;
+  }
+  for (size_t base = (size_t)blockIdx.x * 64; base < ldn; base += (size_t)gridDim.x * 64) {
+    const size_t g0 = base + 16 * q;
+    float b[IT][16];
+#pragma unroll
+    for (int t = 0; t < IT; t++) load16(A.act, A0 + 16 * t + r, ldn, g0, b[t]);
+#pragma unroll
+    for (int o = 0; o < OT; o++) {
+      float a[16];
+      load16(A.dz, D0 + 16 * o + r, ldn, g0, a);
+#pragma unroll
+      for (int t = 0; t < IT; t++) mma16(acc[o][t], a, b[t]);
+      mma16_ones(bacc[o], a);
+    }
+  }
+  // D layout: lane holds rows 4 q + j, column r
+#pragma unroll
+  for (int o = 0; o < OT; o++) {
+#pragma unroll
+    for (int j = 0; j < 4; j++) {
+      const int ou = 16 * o + 4 * q + j;
+#pragma unroll
+      for (int t = 0; t < IT; t++) part[L.w + ou * L.cols + 16 * t + r] = acc[o][t][j];
+      if (r == 0) part[L.b + ou] = bacc[o][j];
+    }
+  }
+}
+
+__global__ __launch_bounds__(64) void gmlp_wgrad_kernel(GmlpArgs A) {
+  const int lane = threadIdx.x & 63, r = lane & 15, q = lane >> 4;
+  const size_t ldn = A.ldn;
+  float *part = A.partials + (size_t)blockIdx.x * kGParams;
+  const f32x4 z4 = {0.f, 0.f, 0.f, 0.f};
+  switch (blockIdx.y) {
+    case 0: {  // layer 0: 42 inputs as tiles of 16 (rows 42..47 zero)
+      f32x4 acc[4][3], bacc[4];
+      for (int o = 0; o < 4; o++) {
+        bacc[o] = z4;
+        for (int t = 0; t < 3; t++) acc[o][t] = z4;
+      }
+      for (size_t base = (size_t)blockIdx.x * 64; base < ldn; base += (size_t)gridDim.x * 64) {
+        const size_t g0 = base + 16 * q;
+        float b[3][16];
+        load16(A.act, kAX + r, ldn, g0, b[0]);
+        load16(A.act, kAX + 16 + r, ldn, g0, b[1]);
+        if (32 + r < kGIn) load16(A.act, kAX + 32 + r, ldn, g0, b[2]);
+        else
+          for (int k = 0; k < 16; k++) b[2][k] = 0.f;
+#pragma unroll
+        for (int o = 0; o < 4; o++) {
+          float a[16];
+          load16(A.dz, kD0 + 16 * o + r, ldn, g0, a);
+#pragma unroll
+          for (int t = 0; t < 3; t++) mma16(acc[o][t], a, b[t]);
+          mma16_ones(bacc[o], a);
         }
       }
+      for (int o = 0; o < 4; o++)
+        for (int j = 0; j < 4; j++) {
+          const int ou = 16 * o + 4 * q + j;
+          for (int t = 0; t < 3; t++)
+            if (16 * t + r < kGIn) part[kL0.w + ou * kGIn + 16 * t + r] = acc[o][t][j];
+          if (r == 0) part[kL0.b + ou] = bacc[o][j];
+        }
+      break;
+    }
+    case 1: layer_wgrad<2, 4>(A, kD1, kAH1, kL1, part); break;
+    case 2: layer_wgrad<2, 2>(A, kD2, kAH2, kL2, part); break;
+    case 3: layer_wgrad<2, 2>(A, kDI, kAH3, kLi, part); break;
+    default: {  // heads: rows 0..2 incident output (inputs e), 3..5 SSS (inputs h3)
+      f32x4 ae[2], ah[2], ab;
+      ab = z4;
+      for (int t = 0; t < 2; t++) ae[t] = ah[t] = z4;
+      for (size_t base = (size_t)blockIdx.x * 64; base < ldn; base += (size_t)gridDim.x * 64) {
+        const size_t g0 = base + 16 * q;
+        float a[16];
+        if (r < 6) load16(A.dz, kDH + r, ldn, g0, a);
+        else
+          for (int k = 0; k < 16; k++) a[k] = 0.f;
+        for (int t = 0; t < 2; t++) {
+          float b[16];
+          load16(A.act, kAE + 16 * t + r, ldn, g0, b);
+          mma16(ae[t], a, b);
+          load16(A.act, kAH3 + 16 * t + r, ldn, g0, b);
+          mma16(ah[t], a, b);
+        }
+        mma16_ones(ab, a);
+      }
+      for (int j = 0; j < 4; j++) {
+        const int ou = 4 * q + j;
+        for (int t = 0; t < 2; t++) {
+          if (ou < 3) part[kLl.w + ou * 32 + 16 * t + r] = ae[t][j];
+          else if (ou < 6) part[kLs.w + (ou - 3) * 32 + 16 * t + r] = ah[t][j];
+        }
+        if (r == 0) {
+          if (ou < 3) part[kLl.b + ou] = ab[j];
+          else if (ou < 6) part[kLs.b + ou - 3] = ab[j];
+        }
+      }
+      break;
+    }
   }
 }
 
@@ -504,10 +554,14 @@ __global__ __launch_bounds__(64) void gmlp_bwd_kernel(GmlpArgs A) {
 
 int gmlp_param_count() { return kGParams; }
 
-int gmlp_bwd_grid(int n) {
-  const int waves = (n + 63) / 64;
-  return waves < 1 ? 1 : (waves > kGmlpMaxWaves ? kGmlpMaxWaves : waves);
+int gmlp_wgrad_grid(int n) {
+  const int chunks = (n + 63) / 64;
+  return chunks < 1 ? 1 : (chunks > kGmlpMaxWaves ? kGmlpMaxWaves : chunks);
 }
+
+size_t gmlp_ldn(int n) { return (size_t)((n + 63) / 64) * 64; }
+size_t gmlp_act_floats(int n) { return (size_t)kARows * gmlp_ldn(n); }
+size_t gmlp_dz_floats(int n) { return (size_t)kDRows * gmlp_ldn(n); }
 
 void launch_gmlp_prep(const float *params, float *wt, hipStream_t st) {
   gmlp_prep_kernel<<<(kGParams + 255) / 256, 256, 0, st>>>(params, wt);
@@ -518,7 +572,8 @@ void launch_gmlp_fwd(const GmlpArgs &a, hipStream_t st) {
 }
 
 void launch_gmlp_bwd(const GmlpArgs &a, hipStream_t st) {
-  gmlp_bwd_kernel<<<gmlp_bwd_grid(a.n), 64, 0, st>>>(a);
+  if (a.n > 0) gmlp_bwd_kernel<<<(int)(a.ldn / 64), 64, 0, st>>>(a);
+  gmlp_wgrad_kernel<<<dim3(gmlp_wgrad_grid(a.n), 5), 64, 0, st>>>(a);
 }
 
 }  // namespace sssgs

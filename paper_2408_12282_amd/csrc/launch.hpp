@@ -96,12 +96,17 @@ struct GmlpArgs {
   const float *dfeat;      // backward: dL/d(features) [8][n]
   float *d_means, *d_log_scales, *d_quats;  // added to
   float *d_vis;            // written, or added when accumulate
-  float *partials;         // [gmlp_bwd_grid(n)][gmlp_param_count()]
+  float *partials;         // [gmlp_wgrad_grid(n)][gmlp_param_count()]
+  float *act, *dz;         // backward records [rows][ldn] (gmlp_act_floats, gmlp_dz_floats)
+  size_t ldn;              // n rounded up to 64
   int accumulate;
 };
-constexpr int kGmlpMaxWaves = 768;
+constexpr int kGmlpMaxWaves = 512;
 int gmlp_param_count();
-int gmlp_bwd_grid(int n);
+int gmlp_wgrad_grid(int n);
+size_t gmlp_ldn(int n);
+size_t gmlp_act_floats(int n);
+size_t gmlp_dz_floats(int n);
 void launch_gmlp_prep(const float *params, float *wt, hipStream_t st);
 void launch_gmlp_fwd(const GmlpArgs &a, hipStream_t st);
 void launch_gmlp_bwd(const GmlpArgs &a, hipStream_t st);
