@@ -16,10 +16,10 @@
 // keeps all outputs of the layer in registers, which needs the weights
 // transposed ([cols][rows], prepared once per call); the backward walks the
 // output gradient the same way with the weights as stored ([rows][cols]).
-// The weight gradient sum_g dz[o][g] act[i][g] over a wave's 64 Gaussians is
-// a 16x16x4 FP32 matrix-core product with K = Gaussians, read from the LDS
-// columns; every wave keeps its sums in registers over its chunks and writes
-// one partial row, reduced in fixed order afterwards.
+// The weight gradient sum_g dz[o][g] act[i][g] is a 16x16x4 FP32
+// matrix-core product with K = Gaussians over records the backward stores
+// (see the backward section); every wave keeps its sums in registers over
+// its chunks and writes one partial row, reduced in fixed order afterwards.
 #include "launch.hpp"
 
 namespace sssgs {
@@ -30,7 +30,7 @@ typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4;
 
 constexpr int kGIn = 42;
 constexpr float kSlope = 0.01f;
-constexpr int kLS = 66;  // LDS row stride (floats): conflict-free for own-column and MFMA operand reads
+constexpr int kLS = 64;  // LDS row stride (floats) of the per-lane columns (lane l: word row * kLS + l)
 
 // Packed parameter layout: per layer W [rows][cols] then b [rows].
 struct GL { int rows, cols, w, b; };
@@ -274,9 +274,11 @@ __global__ __launch_bounds__(64) void gmlp_bwd_kernel(GmlpArgs A) {
   const cptr wt = as_const(A.wt), P = as_const(A.params);
   const size_t n = A.n, ldn = A.ldn;
   float *act = A.act, *dzr = A.dz;
-  GIn G;
-  gaussian_input(A, gi, G);
-  write_input(G, col, 0);
+  {
+    GIn G0;
+    gaussian_input(A, gi, G0);
+    write_input(G0, col, 0);
+  }
 #pragma unroll
   for (int k = 0; k < kGIn; k++) act[(kAX + k) * ldn + i] = col[k * kLS];
   // ---- forward: activations to the records, Leaky-ReLU signs kept as masks
@@ -373,6 +375,9 @@ __global__ __launch_bounds__(64) void gmlp_bwd_kernel(GmlpArgs A) {
   float dx[kGIn];
   layer_bwd<64, kGIn>(P + kL0.w, col, dx);
   if (!live) return;
+  // the input's building blocks again (cheaper than keeping them live)
+  GIn G;
+  gaussian_input(A, gi, G);
   float dmu[3] = {0.f, 0.f, 0.f};
   // w_in = u / |u| and d = |u| with u = light - mu
   {
