@@ -105,6 +105,7 @@ def run_gpu(precision: str, steps: int, warmup: int):
     extras = time_training_kernels(rgb_ref=drgb, params=p, mlp_params=mp, grads=grads, dmlp=dmlp)
     ibl = time_ibl(view, p, bc, mp, mlp.width, prec)
     gnet = time_gaussian_network(g, cam, light, drgb, steps)
+    vis = time_visibility(p, bl, g.n)
     flags, m_dev = B.sssgs_workspace_status(ctypes_ptr(view), g.n, cam.width, cam.height, g.feat_dim, mlp.width,
                                             cap)
     assert flags == 0 and m_dev == M, (flags, m_dev, M)
@@ -112,7 +113,7 @@ def run_gpu(precision: str, steps: int, warmup: int):
     return {"ms": ms, "stages": {k: (v[0] / max(v[1], 1), v[1]) for k, v in stages.items()}, "M": M,
             "bwd_records": per_tile_last, "fwd_records": fwd_records, "listed": listed, "n": g.n,
             "C": 10 + g.feat_dim, "HW": cam.width * cam.height, "precision": precision, "training": extras,
-            "ibl": ibl, "gnet": gnet}
+            "ibl": ibl, "gnet": gnet, "vis": vis}
 
 
 def time_training_kernels(rgb_ref, params, mlp_params, grads, dmlp, reps: int = 10):
@@ -242,6 +243,35 @@ def time_gaussian_network(g, cam, light, drgb, steps: int):
             "stages_ms": {k: round(v, 4) for k, v in st.items()}, "roofline": roof}
 
 
+def time_visibility(params, light_struct, n: int, reps: int = 5):
+    """Ray-traced light visibility of every Gaussian (BVH build + one shadow
+    ray per Gaussian) on the same 300k Gaussians, timed with events on the
+    stream."""
+    import torch
+    from paper_2408_12282_amd import sssgs as B
+    ws = B.visibility_workspace(n)
+    v = B.trace_visibility(params, light_struct, ws)
+    torch.cuda.synchronize()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    t0.record()
+    for _ in range(reps):
+        B.trace_visibility(params, light_struct, ws)
+    t1.record()
+    torch.cuda.synchronize()
+    ms = t0.elapsed_time(t1) / reps
+    B.sssgs_timing_read()
+    B.sssgs_timing_enable(True)
+    B.trace_visibility(params, light_struct, ws)
+    torch.cuda.synchronize()
+    B.sssgs_timing_enable(False)
+    B.sssgs_timing_read()
+    return {"workload": "300k Gaussians, one shadow ray per Gaussian to the point light, BVH built per call",
+            "ms": round(ms, 4), "rays_per_s": round(n / (ms * 1e-3), 1),
+            "occluded_to_zero": round(float((v == 0).float().mean()), 4),
+            "mean_visibility": round(float(v.mean()), 4)}
+
+
 def ctypes_ptr(view):
     import ctypes as ct
     return ct.c_void_p(view.workspace.data_ptr())
@@ -368,6 +398,7 @@ def main():
     line["training_kernels"] = head["training"]
     line["image_based_lighting"] = head["ibl"]
     line["per_gaussian_network"] = head["gnet"]
+    line["ray_traced_visibility"] = head["vis"]
     if a.calib_copy_mib > 0:
         import torch
         src = torch.ones(a.calib_copy_mib << 18, device="cuda")

@@ -237,6 +237,26 @@ sssgs_status sssgs_gaussian_mlp_backward(const sssgs_gaussians *g, const sssgs_c
                                          float *dL_dlog_scales, float *dL_dquats, float *dL_dvisibility,
                                          float *dL_dparams, int32_t accumulate, void *stream);
 
+/* Each Gaussian's visibility of the point light, by tracing a shadow ray
+   through the other Gaussians with a bounding-volume hierarchy (Sec. 3.2,
+   "Incident Light"; the visibility input of the per-Gaussian network).
+   For Gaussian i the ray runs from its centre to light->pos.  Gaussian j
+   (j != i) occludes it at the point of the ray's line where j is densest
+   (in j's whitened frame S^-1 R^T (x - mu_j): t* = -(u.w)/(w.w), squared
+   distance D2 = |u x w|^2/|w|^2) when that point lies on the segment and
+   alpha = min(0.99, sigmoid(logit_j) exp(-D2/2)) >= 1/255; the visibility is
+   the product of (1 - alpha) over the occluders, reported as 0 below 1e-4.
+   Reads n, means, log_scales, quats and opacity_logits of `g`; writes
+   out_visibility [n] (device).  The hierarchy (Morton-ordered radix tree over
+   the ellipsoids where alpha can reach 1/255) is built in `workspace`
+   (device, caller-owned, sssgs_visibility_workspace_bytes(n) bytes) on every
+   call.  Deterministic.  A NaN output marks a ray whose traversal stack
+   overflowed (it cannot with at most 2^31 Gaussians: the tree is at most 62
+   levels deep). */
+size_t sssgs_visibility_workspace_bytes(int32_t n);
+sssgs_status sssgs_trace_visibility(const sssgs_gaussians *g, const sssgs_light *light, void *workspace,
+                                    size_t workspace_bytes, float *out_visibility, void *stream);
+
 sssgs_status sssgs_l1_loss(const float *pred, const float *target, int64_t count, float scale, float *loss_out,
                            float *dL_dpred, void *stream);
 

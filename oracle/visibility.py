@@ -55,11 +55,12 @@ def whitening(log_scales, quats):
     return np.transpose(R, (0, 2, 1)) / s[:, :, None]
 
 
-def visibility(means, log_scales, quats, opacity_logits, light_pos, margins: bool = False):
+def visibility(means, log_scales, quats, opacity_logits, light_pos, margins: bool = False, receivers=None):
     """v [N] (and, with ``margins``, a per-Gaussian flag set when one of its
     decisions lies within rounding reach of a threshold: t* within 1e-6 of 0
     or of the light, alpha within 1e-6 relative of 1/255 or 0.99, the product
-    within 1e-9 of the 1e-4 floor)."""
+    within 1e-9 of the 1e-4 floor).  ``receivers``: only these Gaussians'
+    rays (the others are returned as 1, unflagged)."""
     mu = np.asarray(means, np.float64).T
     n = mu.shape[0]
     Wm = whitening(log_scales, quats)
@@ -67,7 +68,7 @@ def visibility(means, log_scales, quats, opacity_logits, light_pos, margins: boo
     P = np.asarray(light_pos, np.float64)
     v = np.ones(n)
     flag = np.zeros(n, bool)
-    for i in range(n):
+    for i in (range(n) if receivers is None else receivers):
         dvec = P - mu[i]
         tmax = np.linalg.norm(dvec)
         d = dvec / tmax

@@ -20,11 +20,12 @@ thread_local std::string g_last_error;
 // ---- optional per-stage timing with HIP events on the caller's stream
 enum Stage {
   kStProject = 0, kStSortDepth, kStExpand, kStSortTiles, kStCompositeFwd, kStShadeFwd,
-  kStShadeBwd, kStMlpWgrad, kStMlpReduce, kStCompositeBwd, kStProjectBwd, kStGmlpFwd, kStGmlpBwd, kStCount
+  kStShadeBwd, kStMlpWgrad, kStMlpReduce, kStCompositeBwd, kStProjectBwd, kStGmlpFwd, kStGmlpBwd, kStVisibility, kStCount
 };
 const char *kStageNames[kStCount] = {"project_fwd", "sort_depth", "expand",        "sort_tiles",
                                      "composite_fwd", "shade_fwd", "shade_bwd",     "mlp_wgrad",
-                                     "mlp_reduce",  "composite_bwd", "project_bwd", "gmlp_fwd", "gmlp_bwd"};
+                                     "mlp_reduce",  "composite_bwd", "project_bwd", "gmlp_fwd", "gmlp_bwd",
+                                     "visibility"};
 struct TimerRec {
   int stage;
   hipEvent_t a, b;
@@ -682,6 +683,77 @@ sssgs_status sssgs_gaussian_mlp_backward(const sssgs_gaussians *g, const sssgs_c
   launch_reduce_partials(a.partials, gmlp_wgrad_grid(g->n), gmlp_param_count(), at<float>(ws, L.mid), dL_dparams,
                          accumulate, st);
   return check_hip("gaussian network backward launch");
+}
+
+// ---- ray-traced visibility
+
+namespace {
+struct VisLayout {
+  size_t rec, gbox, scene, ka, va, kb, vb, hist, part, left, right, pint, pleaf, nbox, flags, status, total;
+};
+VisLayout vis_layout(int32_t n) {
+  VisLayout L;
+  const size_t nn = (size_t)(n > 1 ? n : 2);
+  size_t p = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = p;
+    p = align256(p + bytes);
+    return o;
+  };
+  L.rec = take(nn * 16 * 8);
+  L.gbox = take(nn * 6 * 4);
+  L.scene = take(6 * 4);
+  L.ka = take(nn * 4);
+  L.va = take(nn * 4);
+  L.kb = take(nn * 4);
+  L.vb = take(nn * 4);
+  const uint32_t nb = radix_blocks((uint64_t)nn);
+  size_t np = scan_partials_needed(nn);
+  const size_t np2 = scan_partials_needed((uint64_t)nb * kRadixBins);
+  if (np2 > np) np = np2;
+  L.hist = take((size_t)nb * kRadixBins * 4);
+  L.part = take(np * 4);
+  L.left = take(nn * 4);
+  L.right = take(nn * 4);
+  L.pint = take(nn * 4);
+  L.pleaf = take(nn * 4);
+  L.nbox = take(nn * 6 * 4);
+  L.flags = take(nn * 4);
+  L.status = take(4);
+  L.total = p;
+  return L;
+}
+}  // namespace
+
+size_t sssgs_visibility_workspace_bytes(int32_t n) { return n < 0 ? 0 : vis_layout(n).total; }
+
+sssgs_status sssgs_trace_visibility(const sssgs_gaussians *g, const sssgs_light *light, void *ws, size_t ws_bytes,
+                                    float *out_visibility, void *stream) {
+  if (!g || !light || !ws) return fail(SSSGS_ERR_INVALID_ARG, "null argument");
+  if (g->n < 0) return fail(SSSGS_ERR_INVALID_ARG, "n < 0");
+  if (g->n > 0 && (!g->means || !g->log_scales || !g->quats || !g->opacity_logits || !out_visibility))
+    return fail(SSSGS_ERR_INVALID_ARG, "null Gaussian plane or output");
+  const VisLayout L = vis_layout(g->n);
+  if (ws_bytes < L.total) return fail(SSSGS_ERR_INVALID_ARG, "workspace too small");
+  hipStream_t st = (hipStream_t)stream;
+  VisArgs a;
+  memset(&a, 0, sizeof(a));
+  a.n = g->n;
+  a.means = g->means; a.log_scales = g->log_scales; a.quats = g->quats; a.logits = g->opacity_logits;
+  for (int k = 0; k < 3; k++) a.light[k] = light->pos[k];
+  a.rec = at<double>(ws, L.rec);
+  a.gbox = at<float>(ws, L.gbox);
+  a.scene = at<uint32_t>(ws, L.scene);
+  a.left = at<int>(ws, L.left); a.right = at<int>(ws, L.right);
+  a.parent_int = at<int>(ws, L.pint); a.parent_leaf = at<int>(ws, L.pleaf);
+  a.nbox = at<float>(ws, L.nbox);
+  a.flags = at<uint32_t>(ws, L.flags);
+  a.status = at<uint32_t>(ws, L.status);
+  a.vis = out_visibility;
+  Scope sc(kStVisibility, st);
+  launch_visibility(a, at<uint32_t>(ws, L.ka), at<uint32_t>(ws, L.va), at<uint32_t>(ws, L.kb),
+                    at<uint32_t>(ws, L.vb), at<uint32_t>(ws, L.hist), at<uint32_t>(ws, L.part), st);
+  return check_hip("visibility launch");
 }
 
 sssgs_status sssgs_l1_loss(const float *pred, const float *target, int64_t count, float scale, float *loss_out,

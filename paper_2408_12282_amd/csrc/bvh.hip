@@ -1,0 +1,325 @@
+// bvh.hip -- each Gaussian's visibility of the point light, by tracing a
+// shadow ray through the other Gaussians with a bounding-volume hierarchy
+// (Sec. 3.2, "Incident Light").
+//
+// What is computed: for Gaussian i the ray from its centre towards the light,
+// 0 < t <= |p - mu_i|.  Another Gaussian j occludes it where the ray's line
+// passes densest through j: in j's whitened frame (S^-1 R^T (x - mu_j)) the
+// line is u + t w, the densest point t* = -(u.w)/(w.w) at squared distance
+// D2 = |u x w|^2 / |w|^2; if t* is on the segment and
+// alpha = min(0.99, opacity exp(-D2/2)) >= 1/255, the ray keeps a factor
+// (1 - alpha).  v_i is the product, 0 once below 1e-4.  The product does not
+// depend on the order of the occluders and only decreases, so the traversal
+// needs no depth order and a ray stops when it crosses the floor.
+//
+// The hierarchy is a linear BVH built on the GPU each call:
+//   vis_prep    per Gaussian an FP64 record (whitening matrix, opacity,
+//               centre) and the box of the ellipsoid D2 <= 2 ln(255 opacity)
+//               outside of which alpha < 1/255 (so the box test is exact,
+//               not a 3-sigma heuristic); the box of all centres.
+//   vis_morton  30-bit Morton code of each centre in that box.
+//   radix sort  of the codes (stable: index order among equal codes).
+//   vis_tree    binary radix tree over the sorted codes, one thread per
+//               internal node (prefix lengths of equal codes continue with
+//               the bits of the sorted positions, so every split is unique).
+//   vis_refit   boxes bottom-up, one thread per leaf; the second child to
+//               arrive at a node forms its box.
+//   vis_trace   one thread per Gaussian in Morton order (coherent rays), a
+//               per-lane stack in LDS, children tested at their parent.
+// The leaf test is FP64 (the densest point is a small difference of large
+// terms for a distant, thin Gaussian); boxes and the slab test are FP32 with
+// the boxes widened outward.
+#include "launch.hpp"
+
+namespace sssgs {
+
+namespace {
+
+constexpr int kVisStack = 64;  // tree depth <= 30 code bits + 32 position bits
+constexpr double kFloor = 1e-4;
+
+__device__ __forceinline__ uint32_t ordered(float f) {
+  const uint32_t b = __float_as_uint(f);
+  return (b & 0x80000000u) ? ~b : (b | 0x80000000u);
+}
+__device__ __forceinline__ float unordered(uint32_t k) {
+  return __uint_as_float((k & 0x80000000u) ? (k & 0x7FFFFFFFu) : ~k);
+}
+
+__global__ void vis_init_kernel(uint32_t *scene, uint32_t *status) {
+  if (threadIdx.x < 3) scene[threadIdx.x] = 0xFFFFFFFFu;      // min keys
+  else if (threadIdx.x < 6) scene[threadIdx.x] = 0u;          // max keys
+  else if (threadIdx.x == 6) status[0] = 0u;
+}
+
+__global__ __launch_bounds__(256) void vis_prep_kernel(VisArgs A) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= A.n) return;
+  const int n = A.n;
+  double q[4], ql = 0.0;
+  for (int k = 0; k < 4; k++) {
+    q[k] = A.quats[k * n + i];
+    ql += q[k] * q[k];
+  }
+  ql = sqrt(ql);
+  for (int k = 0; k < 4; k++) q[k] /= ql;
+  const double w = q[0], x = q[1], y = q[2], z = q[3];
+  const double R[9] = {1.0 - 2.0 * (y * y + z * z), 2.0 * (x * y - w * z), 2.0 * (x * z + w * y),
+                       2.0 * (x * y + w * z), 1.0 - 2.0 * (x * x + z * z), 2.0 * (y * z - w * x),
+                       2.0 * (x * z - w * y), 2.0 * (y * z + w * x), 1.0 - 2.0 * (x * x + y * y)};
+  double s[3], mu[3];
+  for (int k = 0; k < 3; k++) {
+    s[k] = exp((double)A.log_scales[k * n + i]);
+    mu[k] = A.means[k * n + i];
+  }
+  const double op = 1.0 / (1.0 + exp(-(double)A.logits[i]));
+  double *rec = A.rec + (size_t)i * 16;
+  // whitening S^-1 R^T: row k = column k of R over s_k
+  for (int k = 0; k < 3; k++)
+    for (int m = 0; m < 3; m++) rec[3 * k + m] = R[3 * m + k] / s[k];
+  rec[9] = op;
+  for (int k = 0; k < 3; k++) rec[10 + k] = mu[k];
+  float *box = A.gbox + (size_t)i * 6;
+  if (255.0 * op > 1.0) {
+    const double r = sqrt(2.0 * log(255.0 * op));
+    for (int m = 0; m < 3; m++) {
+      double e2 = 0.0;
+      for (int k = 0; k < 3; k++) e2 += R[3 * m + k] * R[3 * m + k] * s[k] * s[k];
+      const double e = r * sqrt(e2), pad = 1e-6 * (1.0 + fabs(mu[m]) + e);
+      box[m] = (float)(mu[m] - e - pad);
+      box[3 + m] = (float)(mu[m] + e + pad);
+    }
+  } else {  // alpha can never reach 1/255: an empty box
+    for (int m = 0; m < 3; m++) {
+      box[m] = __int_as_float(0x7F800000);
+      box[3 + m] = -__int_as_float(0x7F800000);
+    }
+  }
+  for (int m = 0; m < 3; m++) {
+    const float c = A.means[m * n + i];
+    atomicMin(A.scene + m, ordered(c));
+    atomicMax(A.scene + 3 + m, ordered(c));
+  }
+}
+
+__device__ __forceinline__ uint32_t spread10(uint32_t v) {  // 10 bits -> every third bit
+  v &= 0x3FFu;
+  v = (v | (v << 16)) & 0x030000FFu;
+  v = (v | (v << 8)) & 0x0300F00Fu;
+  v = (v | (v << 4)) & 0x030C30C3u;
+  v = (v | (v << 2)) & 0x09249249u;
+  return v;
+}
+
+__global__ __launch_bounds__(256) void vis_morton_kernel(VisArgs A, uint32_t *codes, uint32_t *idx) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= A.n) return;
+  uint32_t c[3];
+  for (int m = 0; m < 3; m++) {
+    const float lo = unordered(A.scene[m]), hi = unordered(A.scene[3 + m]);
+    const float ext = hi - lo;
+    float f = ext > 0.f ? (A.means[m * A.n + i] - lo) / ext : 0.f;
+    f = fminf(fmaxf(f, 0.f), 1.f);
+    c[m] = (uint32_t)fminf(f * 1024.f, 1023.f);
+  }
+  codes[i] = (spread10(c[0]) << 2) | (spread10(c[1]) << 1) | spread10(c[2]);
+  idx[i] = (uint32_t)i;
+}
+
+// Length of the common prefix of sorted entries a and b (codes, then
+// positions); -1 outside [0, n).
+__device__ __forceinline__ int prefix(const uint32_t *code, int n, int a, int b) {
+  if (b < 0 || b >= n) return -1;
+  const uint32_t ca = code[a], cb = code[b];
+  if (ca != cb) return __clz(ca ^ cb);
+  return 32 + __clz((uint32_t)a ^ (uint32_t)b);
+}
+
+// Internal node i covers a range of sorted leaves that starts or ends at i;
+// its children split the range where the prefix shortens.  Children >= 0 are
+// internal nodes, < 0 leaves (~position).
+__global__ __launch_bounds__(256) void vis_tree_kernel(VisArgs A) {
+  const int n = A.n;
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= n - 1) return;
+  const uint32_t *code = A.codes;
+  const int d = prefix(code, n, i, i + 1) - prefix(code, n, i, i - 1) >= 0 ? 1 : -1;
+  const int dmin = prefix(code, n, i, i - d);
+  int lmax = 2;
+  while (prefix(code, n, i, i + lmax * d) > dmin) lmax <<= 1;
+  int l = 0;
+  for (int t = lmax >> 1; t >= 1; t >>= 1)
+    if (prefix(code, n, i, i + (l + t) * d) > dmin) l += t;
+  const int j = i + l * d;
+  const int dnode = prefix(code, n, i, j);
+  int s = 0, t = l;
+  do {
+    t = (t + 1) >> 1;
+    if (prefix(code, n, i, i + (s + t) * d) > dnode) s += t;
+  } while (t > 1);
+  const int split = i + s * d + (d < 0 ? -1 : 0);
+  const int lo = i < j ? i : j, hi = i < j ? j : i;
+  const int left = lo == split ? ~split : split;
+  const int right = hi == split + 1 ? ~(split + 1) : split + 1;
+  A.left[i] = left;
+  A.right[i] = right;
+  if (left < 0) A.parent_leaf[split] = i;
+  else A.parent_int[left] = i;
+  if (right < 0) A.parent_leaf[split + 1] = i;
+  else A.parent_int[right] = i;
+  if (i == 0) A.parent_int[0] = -1;
+}
+
+__device__ __forceinline__ float coherent_load(const float *p) {
+  return __uint_as_float(__hip_atomic_load(reinterpret_cast<const uint32_t *>(p), __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_AGENT));
+}
+
+__device__ __forceinline__ void child_box(const VisArgs &A, int c, float *b) {
+  if (c < 0) {
+    const float *g = A.gbox + (size_t)A.order[~c] * 6;
+    for (int k = 0; k < 6; k++) b[k] = g[k];
+  } else {
+    const float *g = A.nbox + (size_t)c * 6;
+    for (int k = 0; k < 6; k++) b[k] = coherent_load(g + k);
+  }
+}
+
+__global__ __launch_bounds__(256) void vis_refit_kernel(VisArgs A) {
+  const int k = blockIdx.x * 256 + threadIdx.x;
+  if (k >= A.n) return;
+  int p = A.parent_leaf[k];
+  while (p >= 0) {
+    __threadfence();
+    const uint32_t old = __hip_atomic_fetch_add(A.flags + p, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    if (old == 0) return;  // the other child is not ready: it finishes this node
+    float a[6], b[6];
+    child_box(A, A.left[p], a);
+    child_box(A, A.right[p], b);
+    float *o = A.nbox + (size_t)p * 6;
+    for (int m = 0; m < 3; m++) {
+      o[m] = fminf(a[m], b[m]);
+      o[3 + m] = fmaxf(a[3 + m], b[3 + m]);
+    }
+    p = A.parent_int[p];
+  }
+}
+
+// Does the segment o + t d, 0 <= t <= tmax, meet the box (lo, hi)?
+__device__ __forceinline__ bool slab(const float *box, const float *o, const float *inv, float tmax) {
+  float t0 = 0.f, t1 = tmax;
+#pragma unroll
+  for (int m = 0; m < 3; m++) {
+    const float a = (box[m] - o[m]) * inv[m], b = (box[3 + m] - o[m]) * inv[m];
+    t0 = fmaxf(t0, fminf(a, b));
+    t1 = fminf(t1, fmaxf(a, b));
+  }
+  return t0 <= t1;
+}
+
+__device__ __forceinline__ bool slab_at(const float *box_g, const float *o, const float *inv, float tmax) {
+  float b[6];
+  for (int k = 0; k < 6; k++) b[k] = box_g[k];
+  return slab(b, o, inv, tmax);
+}
+
+// Factor (1 - alpha_j) of occluder j on the ray (o, d, tmax), or 1.
+__device__ __forceinline__ double occlusion(const double *rec, const double *o, const double *d, double tmax) {
+  double u[3], w[3];
+  for (int k = 0; k < 3; k++) {
+    const double *Wk = rec + 3 * k;
+    u[k] = Wk[0] * (o[0] - rec[10]) + Wk[1] * (o[1] - rec[11]) + Wk[2] * (o[2] - rec[12]);
+    w[k] = Wk[0] * d[0] + Wk[1] * d[1] + Wk[2] * d[2];
+  }
+  const double ww = w[0] * w[0] + w[1] * w[1] + w[2] * w[2];
+  const double ts = -(u[0] * w[0] + u[1] * w[1] + u[2] * w[2]) / ww;
+  if (!(ts > 0.0 && ts <= tmax)) return 1.0;
+  const double c0 = u[1] * w[2] - u[2] * w[1], c1 = u[2] * w[0] - u[0] * w[2], c2 = u[0] * w[1] - u[1] * w[0];
+  const double D2 = (c0 * c0 + c1 * c1 + c2 * c2) / ww;
+  const double alpha = fmin(0.99, rec[9] * exp(-0.5 * D2));
+  return alpha >= 1.0 / 255.0 ? 1.0 - alpha : 1.0;
+}
+
+__global__ __launch_bounds__(64) void vis_trace_kernel(VisArgs A) {
+  __shared__ int stack[kVisStack][64];
+  const int lane = threadIdx.x;
+  const int k = blockIdx.x * 64 + lane;
+  if (k >= A.n) return;
+  const int n = A.n;
+  const int i = (int)A.order[k];
+  double o[3], d[3], len = 0.0;
+  for (int m = 0; m < 3; m++) {
+    o[m] = A.means[m * n + i];
+    d[m] = (double)A.light[m] - o[m];
+    len += d[m] * d[m];
+  }
+  len = sqrt(len);
+  float of[3], inv[3];
+  for (int m = 0; m < 3; m++) {
+    d[m] /= len;
+    of[m] = (float)o[m];
+    const float dm = (float)d[m];
+    inv[m] = dm != 0.f ? 1.f / dm : 1e30f;
+  }
+  const float tmaxf = (float)len * (1.f + 1e-6f) + 1e-6f;
+  double T = 1.0;
+  int sp = 0;
+  if (n >= 2) {
+    float rb[6];
+    for (int m = 0; m < 6; m++) rb[m] = A.nbox[m];
+    if (slab(rb, of, inv, tmaxf)) stack[sp++][lane] = 0;
+  }
+  bool overflow = false;
+  while (sp > 0 && T >= kFloor) {
+    const int node = stack[--sp][lane];
+    const int ch[2] = {A.left[node], A.right[node]};
+    for (int c = 0; c < 2; c++) {
+      const int cn = ch[c];
+      if (cn < 0) {
+        const int j = (int)A.order[~cn];
+        if (j != i && slab_at(A.gbox + (size_t)j * 6, of, inv, tmaxf))
+          T *= occlusion(A.rec + (size_t)j * 16, o, d, len);
+      } else if (slab_at(A.nbox + (size_t)cn * 6, of, inv, tmaxf)) {
+        if (sp < kVisStack) stack[sp++][lane] = cn;
+        else overflow = true;
+      }
+    }
+  }
+  float v = T < kFloor ? 0.f : (float)T;
+  if (overflow) {
+    v = __int_as_float(0x7FC00000);  // NaN: the stack bound was exceeded
+    atomicOr(A.status, 1u);
+  }
+  A.vis[i] = v;
+}
+
+}  // namespace
+
+void launch_visibility(const VisArgs &a0, uint32_t *keys_a, uint32_t *vals_a, uint32_t *keys_b, uint32_t *vals_b,
+                       uint32_t *hist, uint32_t *partials, hipStream_t st) {
+  VisArgs a = a0;
+  const int n = a.n;
+  if (n <= 0) return;
+  const int g256 = (n + 255) / 256;
+  vis_init_kernel<<<1, 64, 0, st>>>(a.scene, a.status);
+  vis_prep_kernel<<<g256, 256, 0, st>>>(a);
+  vis_morton_kernel<<<g256, 256, 0, st>>>(a, keys_a, vals_a);
+  const uint32_t *kin = keys_a, *vin = vals_a;
+  for (int pass = 0; pass < 4; pass++) {
+    uint32_t *ko = (pass & 1) ? keys_a : keys_b;
+    uint32_t *vo = (pass & 1) ? vals_a : vals_b;
+    launch_radix_pass(kin, vin, ko, vo, (uint32_t)n, nullptr, pass * kRadixBits, hist, partials, st, false);
+    kin = ko;
+    vin = vo;
+  }
+  a.codes = kin;
+  a.order = vin;
+  if (n >= 2) {
+    vis_tree_kernel<<<(n - 1 + 255) / 256, 256, 0, st>>>(a);
+    launch_zero_f32(reinterpret_cast<float *>(a.flags), (size_t)(n - 1), st);
+    vis_refit_kernel<<<g256, 256, 0, st>>>(a);
+  }
+  vis_trace_kernel<<<(n + 63) / 64, 64, 0, st>>>(a);
+}
+
+}  // namespace sssgs

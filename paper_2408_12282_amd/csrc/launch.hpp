@@ -111,4 +111,23 @@ void launch_gmlp_prep(const float *params, float *wt, hipStream_t st);
 void launch_gmlp_fwd(const GmlpArgs &a, hipStream_t st);
 void launch_gmlp_bwd(const GmlpArgs &a, hipStream_t st);
 
+// Ray-traced light visibility of every Gaussian (bvh.hip).
+struct VisArgs {
+  int n;
+  const float *means, *log_scales, *quats, *logits;
+  float light[3];
+  double *rec;                    // [n][16]: whitening matrix (9), opacity, centre (3)
+  float *gbox;                    // [n][6]: box lo xyz, hi xyz of the alpha >= 1/255 ellipsoid
+  uint32_t *scene;                // [6]: ordered-integer min / max of the centres
+  const uint32_t *codes, *order;  // sorted Morton codes and Gaussian indices (set by the launcher)
+  int *left, *right, *parent_int; // [n - 1] internal nodes
+  int *parent_leaf;               // [n]
+  float *nbox;                    // [n - 1][6]
+  uint32_t *flags;                // [n - 1] refit arrivals
+  uint32_t *status;               // [1]: bit 0 = a traversal stack overflowed
+  float *vis;                     // [n] out
+};
+void launch_visibility(const VisArgs &a, uint32_t *keys_a, uint32_t *vals_a, uint32_t *keys_b, uint32_t *vals_b,
+                       uint32_t *hist, uint32_t *partials, hipStream_t st);
+
 }  // namespace sssgs

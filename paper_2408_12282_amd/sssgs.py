@@ -64,7 +64,8 @@ EXPORTS = ("sssgs_mlp_param_count", "sssgs_workspace_bytes", "sssgs_render_forwa
            "sssgs_last_error", "sssgs_timing_enable", "sssgs_timing_read", "sssgs_timing_stages",
            "sssgs_timing_stage_name", "sssgs_image_loss_workspace_bytes", "sssgs_image_loss", "sssgs_adam_step",
            "sssgs_render_forward_lights", "sssgs_gaussian_mlp_param_count", "sssgs_gaussian_mlp_workspace_bytes",
-           "sssgs_gaussian_mlp_forward", "sssgs_gaussian_mlp_backward")
+           "sssgs_gaussian_mlp_forward", "sssgs_gaussian_mlp_backward", "sssgs_visibility_workspace_bytes",
+           "sssgs_trace_visibility")
 
 
 def load_library(path: str = LIB_PATH):
@@ -104,6 +105,11 @@ def load_library(path: str = LIB_PATH):
                                               ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_size_t,
                                               ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_void_p,
                                               ct.c_int32, ct.c_void_p]
+    L.sssgs_visibility_workspace_bytes.restype = ct.c_size_t
+    L.sssgs_visibility_workspace_bytes.argtypes = [ct.c_int32]
+    L.sssgs_trace_visibility.restype = ct.c_int
+    L.sssgs_trace_visibility.argtypes = [ct.POINTER(Gaussians), ct.POINTER(Light), ct.c_void_p, ct.c_size_t,
+                                         ct.c_void_p, ct.c_void_p]
     L.sssgs_l1_loss.restype = ct.c_int
     L.sssgs_l1_loss.argtypes = [ct.c_void_p, ct.c_void_p, ct.c_int64, ct.c_float, ct.c_void_p, ct.c_void_p,
                                 ct.c_void_p]
@@ -515,3 +521,24 @@ def render_gaussian_mlp_backward(view: View, params: dict, cam: Camera, light: L
                           workspace=workspace)
     dfeat = grads.pop("features")
     return grads, dvis, dgmlp, dfeat
+
+
+# ----------------------------------------------------------------- ray-traced visibility
+
+def visibility_workspace(n: int, device="cuda") -> torch.Tensor:
+    nb = int(lib().sssgs_visibility_workspace_bytes(int(n)))
+    return torch.empty(nb, dtype=torch.uint8, device=device)
+
+
+def trace_visibility(params: dict, light: Light, workspace: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """Each Gaussian's visibility of the light [N] by ray tracing through the
+    other Gaussians (see include/sssgs.h); usable as the per-Gaussian
+    network's visibility input."""
+    n = int(params["means"].shape[1])
+    if workspace is None:
+        workspace = visibility_workspace(n, params["means"].device)
+    vis = torch.empty(n, dtype=torch.float32, device=params["means"].device)
+    g = gaussians_struct(params, 0, -1)
+    _check(lib().sssgs_trace_visibility(ct.byref(g), ct.byref(light), ct.c_void_p(workspace.data_ptr()),
+                                        workspace.numel(), _ptr(vis), _stream()))
+    return vis

@@ -145,3 +145,17 @@ def test_gaussian_network_sizes_and_argument_checks(B):
         st = rf(ct.byref(gg), ct.byref(cam), ct.byref(light), mm, ct.byref(opt), buf, 1 << 30, 100, buf, buf, buf,
                 None, None)
         assert st == want, (mode, st)
+
+
+def test_visibility_argument_checks(B):
+    L = B.lib()
+    a, b = L.sssgs_visibility_workspace_bytes(0), L.sssgs_visibility_workspace_bytes(300000)
+    assert 0 < a < b and L.sssgs_visibility_workspace_bytes(-1) == 0
+    light = B.Light((ct.c_float * 3)(1, 1, 1), (ct.c_float * 3)(9, 9, 9))
+    buf = ct.c_void_p(1)
+    ws = L.sssgs_visibility_workspace_bytes(10)
+    g = B.Gaussians(10, 0, -1, *([None] * 10))
+    assert L.sssgs_trace_visibility(ct.byref(g), ct.byref(light), buf, ws, buf, None) == B.ERR_INVALID_ARG
+    g = B.Gaussians(10, 0, -1, *([buf] * 10))
+    assert L.sssgs_trace_visibility(ct.byref(g), ct.byref(light), buf, ws - 1, buf, None) == B.ERR_INVALID_ARG
+    assert L.sssgs_trace_visibility(ct.byref(g), ct.byref(light), buf, ws, None, None) == B.ERR_INVALID_ARG
