@@ -689,7 +689,7 @@ sssgs_status sssgs_gaussian_mlp_backward(const sssgs_gaussians *g, const sssgs_c
 
 namespace {
 struct VisLayout {
-  size_t rec, gbox, scene, ka, va, kb, vb, hist, part, left, right, pint, pleaf, nbox, flags, status, total;
+  size_t rec, gbox, scene, ka, va, kb, vb, hist, part, left, right, rlo, rhi, bbox, nbox, nrec, status, total;
 };
 VisLayout vis_layout(int32_t n) {
   VisLayout L;
@@ -715,10 +715,11 @@ VisLayout vis_layout(int32_t n) {
   L.part = take(np * 4);
   L.left = take(nn * 4);
   L.right = take(nn * 4);
-  L.pint = take(nn * 4);
-  L.pleaf = take(nn * 4);
+  L.rlo = take(nn * 4);
+  L.rhi = take(nn * 4);
+  L.bbox = take((nn + 255) / 256 * 6 * 4);
   L.nbox = take(nn * 6 * 4);
-  L.flags = take(nn * 4);
+  L.nrec = take(nn * 16 * 4);
   L.status = take(4);
   L.total = p;
   return L;
@@ -745,9 +746,10 @@ sssgs_status sssgs_trace_visibility(const sssgs_gaussians *g, const sssgs_light 
   a.gbox = at<float>(ws, L.gbox);
   a.scene = at<uint32_t>(ws, L.scene);
   a.left = at<int>(ws, L.left); a.right = at<int>(ws, L.right);
-  a.parent_int = at<int>(ws, L.pint); a.parent_leaf = at<int>(ws, L.pleaf);
+  a.range_lo = at<int>(ws, L.rlo); a.range_hi = at<int>(ws, L.rhi);
+  a.bbox = at<float>(ws, L.bbox);
   a.nbox = at<float>(ws, L.nbox);
-  a.flags = at<uint32_t>(ws, L.flags);
+  a.nrec = at<float>(ws, L.nrec);
   a.status = at<uint32_t>(ws, L.status);
   a.vis = out_visibility;
   Scope sc(kStVisibility, st);

@@ -22,8 +22,13 @@
 //   vis_tree    binary radix tree over the sorted codes, one thread per
 //               internal node (prefix lengths of equal codes continue with
 //               the bits of the sorted positions, so every split is unique).
-//   vis_refit   boxes bottom-up, one thread per leaf; the second child to
-//               arrive at a node forms its box.
+//   vis_block_box, vis_node_box
+//               boxes without inter-thread synchronisation: every internal
+//               node covers a contiguous range of sorted leaves, so its box
+//               is the union over that range (short ranges leaf by leaf,
+//               long ones through unions of 256-leaf blocks).
+//   vis_pack    per internal node one 64-byte record: both children and
+//               both child boxes (one cache line per visited node).
 //   vis_trace   one thread per Gaussian in Morton order (coherent rays), a
 //               per-lane stack in LDS, children tested at their parent.
 // The leaf test is FP64 (the densest point is a small difference of large
@@ -163,45 +168,76 @@ __global__ __launch_bounds__(256) void vis_tree_kernel(VisArgs A) {
   const int right = hi == split + 1 ? ~(split + 1) : split + 1;
   A.left[i] = left;
   A.right[i] = right;
-  if (left < 0) A.parent_leaf[split] = i;
-  else A.parent_int[left] = i;
-  if (right < 0) A.parent_leaf[split + 1] = i;
-  else A.parent_int[right] = i;
-  if (i == 0) A.parent_int[0] = -1;
+  A.range_lo[i] = lo;
+  A.range_hi[i] = hi;
 }
 
-__device__ __forceinline__ float coherent_load(const float *p) {
-  return __uint_as_float(__hip_atomic_load(reinterpret_cast<const uint32_t *>(p), __ATOMIC_RELAXED,
-                                           __HIP_MEMORY_SCOPE_AGENT));
-}
-
-__device__ __forceinline__ void child_box(const VisArgs &A, int c, float *b) {
-  if (c < 0) {
-    const float *g = A.gbox + (size_t)A.order[~c] * 6;
-    for (int k = 0; k < 6; k++) b[k] = g[k];
-  } else {
-    const float *g = A.nbox + (size_t)c * 6;
-    for (int k = 0; k < 6; k++) b[k] = coherent_load(g + k);
+__device__ __forceinline__ void box_empty(float *b) {
+  for (int m = 0; m < 3; m++) {
+    b[m] = __int_as_float(0x7F800000);
+    b[3 + m] = -__int_as_float(0x7F800000);
   }
 }
 
-__global__ __launch_bounds__(256) void vis_refit_kernel(VisArgs A) {
-  const int k = blockIdx.x * 256 + threadIdx.x;
-  if (k >= A.n) return;
-  int p = A.parent_leaf[k];
-  while (p >= 0) {
-    __threadfence();
-    const uint32_t old = __hip_atomic_fetch_add(A.flags + p, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-    if (old == 0) return;  // the other child is not ready: it finishes this node
-    float a[6], b[6];
-    child_box(A, A.left[p], a);
-    child_box(A, A.right[p], b);
-    float *o = A.nbox + (size_t)p * 6;
-    for (int m = 0; m < 3; m++) {
-      o[m] = fminf(a[m], b[m]);
-      o[3 + m] = fmaxf(a[3 + m], b[3 + m]);
-    }
-    p = A.parent_int[p];
+__device__ __forceinline__ void box_add(float *b, const float *g) {
+  for (int m = 0; m < 3; m++) {
+    b[m] = fminf(b[m], g[m]);
+    b[3 + m] = fmaxf(b[3 + m], g[3 + m]);
+  }
+}
+
+constexpr int kBoxBlock = 256;
+
+// Union of the boxes of each block of 256 consecutive sorted leaves.
+__global__ __launch_bounds__(kBoxBlock) void vis_block_box_kernel(VisArgs A) {
+  __shared__ float red[6][kBoxBlock];
+  const int t = threadIdx.x, k = blockIdx.x * kBoxBlock + t;
+  float b[6];
+  box_empty(b);
+  if (k < A.n) box_add(b, A.gbox + (size_t)A.order[k] * 6);
+  for (int m = 0; m < 6; m++) red[m][t] = b[m];
+  __syncthreads();
+  for (int w = kBoxBlock / 2; w > 0; w >>= 1) {
+    if (t < w)
+      for (int m = 0; m < 3; m++) {
+        red[m][t] = fminf(red[m][t], red[m][t + w]);
+        red[3 + m][t] = fmaxf(red[3 + m][t], red[3 + m][t + w]);
+      }
+    __syncthreads();
+  }
+  if (t < 6) A.bbox[(size_t)blockIdx.x * 6 + t] = red[t][0];
+}
+
+// Box of internal node i: the union over its leaf range.
+__global__ __launch_bounds__(256) void vis_node_box_kernel(VisArgs A) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= A.n - 1) return;
+  const int lo = A.range_lo[i], hi = A.range_hi[i];
+  float b[6];
+  box_empty(b);
+  if (hi - lo < 2 * kBoxBlock) {
+    for (int k = lo; k <= hi; k++) box_add(b, A.gbox + (size_t)A.order[k] * 6);
+  } else {
+    const int b0 = lo / kBoxBlock, b1 = hi / kBoxBlock;
+    for (int k = lo; k < (b0 + 1) * kBoxBlock; k++) box_add(b, A.gbox + (size_t)A.order[k] * 6);
+    for (int bb = b0 + 1; bb < b1; bb++) box_add(b, A.bbox + (size_t)bb * 6);
+    for (int k = b1 * kBoxBlock; k <= hi; k++) box_add(b, A.gbox + (size_t)A.order[k] * 6);
+  }
+  for (int m = 0; m < 6; m++) A.nbox[(size_t)i * 6 + m] = b[m];
+}
+
+// Node record: children (int bits) in floats 0, 1; left box 4..9; right box 10..15.
+__global__ __launch_bounds__(256) void vis_pack_kernel(VisArgs A) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= A.n - 1) return;
+  float *r = A.nrec + (size_t)i * 16;
+  const int ch[2] = {A.left[i], A.right[i]};
+  r[0] = __int_as_float(ch[0]);
+  r[1] = __int_as_float(ch[1]);
+  r[2] = r[3] = 0.f;
+  for (int c = 0; c < 2; c++) {
+    const float *g = ch[c] < 0 ? A.gbox + (size_t)A.order[~ch[c]] * 6 : A.nbox + (size_t)ch[c] * 6;
+    for (int m = 0; m < 6; m++) r[4 + 6 * c + m] = g[m];
   }
 }
 
@@ -217,11 +253,6 @@ __device__ __forceinline__ bool slab(const float *box, const float *o, const flo
   return t0 <= t1;
 }
 
-__device__ __forceinline__ bool slab_at(const float *box_g, const float *o, const float *inv, float tmax) {
-  float b[6];
-  for (int k = 0; k < 6; k++) b[k] = box_g[k];
-  return slab(b, o, inv, tmax);
-}
 
 // Factor (1 - alpha_j) of occluder j on the ray (o, d, tmax), or 1.
 __device__ __forceinline__ double occlusion(const double *rec, const double *o, const double *d, double tmax) {
@@ -272,16 +303,21 @@ __global__ __launch_bounds__(64) void vis_trace_kernel(VisArgs A) {
   bool overflow = false;
   while (sp > 0 && T >= kFloor) {
     const int node = stack[--sp][lane];
-    const int ch[2] = {A.left[node], A.right[node]};
+    const float4 *nr = reinterpret_cast<const float4 *>(A.nrec + (size_t)node * 16);
+    const float4 q0 = nr[0], q1 = nr[1], q2 = nr[2], q3 = nr[3];
+    const int ch[2] = {__float_as_int(q0.x), __float_as_int(q0.y)};
+    const float bx[2][6] = {{q1.x, q1.y, q1.z, q1.w, q2.x, q2.y}, {q2.z, q2.w, q3.x, q3.y, q3.z, q3.w}};
+#pragma unroll
     for (int c = 0; c < 2; c++) {
+      if (!slab(bx[c], of, inv, tmaxf)) continue;
       const int cn = ch[c];
       if (cn < 0) {
         const int j = (int)A.order[~cn];
-        if (j != i && slab_at(A.gbox + (size_t)j * 6, of, inv, tmaxf))
-          T *= occlusion(A.rec + (size_t)j * 16, o, d, len);
-      } else if (slab_at(A.nbox + (size_t)cn * 6, of, inv, tmaxf)) {
-        if (sp < kVisStack) stack[sp++][lane] = cn;
-        else overflow = true;
+        if (j != i) T *= occlusion(A.rec + (size_t)j * 16, o, d, len);
+      } else if (sp < kVisStack) {
+        stack[sp++][lane] = cn;
+      } else {
+        overflow = true;
       }
     }
   }
@@ -315,9 +351,11 @@ void launch_visibility(const VisArgs &a0, uint32_t *keys_a, uint32_t *vals_a, ui
   a.codes = kin;
   a.order = vin;
   if (n >= 2) {
-    vis_tree_kernel<<<(n - 1 + 255) / 256, 256, 0, st>>>(a);
-    launch_zero_f32(reinterpret_cast<float *>(a.flags), (size_t)(n - 1), st);
-    vis_refit_kernel<<<g256, 256, 0, st>>>(a);
+    const int gi = (n - 1 + 255) / 256;
+    vis_tree_kernel<<<gi, 256, 0, st>>>(a);
+    vis_block_box_kernel<<<(n + kBoxBlock - 1) / kBoxBlock, kBoxBlock, 0, st>>>(a);
+    vis_node_box_kernel<<<gi, 256, 0, st>>>(a);
+    vis_pack_kernel<<<gi, 256, 0, st>>>(a);
   }
   vis_trace_kernel<<<(n + 63) / 64, 64, 0, st>>>(a);
 }

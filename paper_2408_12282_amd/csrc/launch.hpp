@@ -120,10 +120,11 @@ struct VisArgs {
   float *gbox;                    // [n][6]: box lo xyz, hi xyz of the alpha >= 1/255 ellipsoid
   uint32_t *scene;                // [6]: ordered-integer min / max of the centres
   const uint32_t *codes, *order;  // sorted Morton codes and Gaussian indices (set by the launcher)
-  int *left, *right, *parent_int; // [n - 1] internal nodes
-  int *parent_leaf;               // [n]
-  float *nbox;                    // [n - 1][6]
-  uint32_t *flags;                // [n - 1] refit arrivals
+  int *left, *right;              // [n - 1] children (>= 0 internal node, < 0 leaf ~position)
+  int *range_lo, *range_hi;       // [n - 1] sorted-leaf range of each internal node
+  float *bbox;                    // [ceil(n / 256)][6] unions of 256-leaf blocks
+  float *nbox;                    // [n - 1][6] internal node boxes
+  float *nrec;                    // [n - 1][16] node records: children, both child boxes
   uint32_t *status;               // [1]: bit 0 = a traversal stack overflowed
   float *vis;                     // [n] out
 };
