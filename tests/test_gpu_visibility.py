@@ -97,3 +97,35 @@ def test_full_size_sampled():
     ref, flag = V.visibility(*_f32(g), light, margins=True, receivers=recv)
     _compare(got[recv], ref[recv], flag[recv], "300k sampled")
     assert np.all((got >= 0) & (got <= 1))
+
+
+def test_traced_visibility_feeds_the_per_gaussian_network():
+    """The paper's chain: traced visibility as the network's visibility input
+    (features of the per-Gaussian network against the oracle fed the oracle's
+    traced visibility)."""
+    import torch
+    from oracle import gaussian_mlp as GM
+    from paper_2408_12282_amd import sssgs as B
+    n = 1500
+    g = scene.make_gaussians(n, 8, seed=21)
+    g.log_scales += 1.5
+    light = scene.default_light()
+    cam = scene.look_at_camera((0.3, -0.2, 3.0), 64, 64)
+    gm = scene.make_gaussian_mlp(seed=21)
+    print("[gpu] traced visibility -> per-Gaussian network", flush=True)
+    p = {k: torch.from_numpy(np.ascontiguousarray(v)).cuda() for k, v in g.arrays().items() if v is not None}
+    bl = B.make_light(light)
+    vis = B.trace_visibility(p, bl)
+    feats = B.gaussian_mlp_forward(p, B.make_camera(cam), bl, vis, torch.from_numpy(gm).cuda())
+    torch.cuda.synchronize()
+    vref, flag = V.visibility(*_f32(g), light.pos, margins=True)
+    _compare(vis.cpu().numpy(), vref, flag, "chain visibility")
+    x, _ = GM.inputs(g.means, g.log_scales, g.quats, vref, cam.center, light.pos)
+    ref = GM.forward(x, gm)[0]
+    bound = GM.forward_bound(x, gm)
+    got = feats.cpu().numpy()
+    ok = ~flag
+    err = np.abs(got[:6] - ref[:6]) / (np.abs(ref[:6]) + bound)
+    print(f"  chain features max err {float(err[:, ok].max()):.2e}", flush=True)
+    assert float(err[:, ok].max()) < 1e-5
+    np.testing.assert_array_equal(got[6], vis.cpu().numpy())
