@@ -11,6 +11,10 @@
  *                       combined with the BRDF through the per-Gaussian sss.
  *   Sec. 3.2 "Per-Pixel Deferred Shading": composite properties into buffers,
  *                       back-project the composited depth, shade per pixel.
+ *   Pipeline figure, appendix "Network": the network evaluated per Gaussian,
+ *                       its radiances composited (sssgs_gaussian_mlp_*).
+ *   Sec. 3.2 "Incident Light": per-Gaussian light visibility by ray tracing
+ *                       through the Gaussians with a BVH (sssgs_trace_visibility).
  *
  * Conventions (all the paper leaves open):
  *   - Camera: p_cam = R p + t with x right, y down, z forward; pinhole fx, fy,
