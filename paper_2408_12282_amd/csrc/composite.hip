@@ -165,6 +165,7 @@ __global__ __launch_bounds__(256, C > 26 ? 2 : 3) void composite_bwd_kernel(
   constexpr int CP = (C + 15) / 16 * 16;  // channels padded to 16-column blocks
   constexpr int NBC = CP / 16;
   constexpr int RW = CP + 16;             // columns of the per-wave partial sums: channels | moments
+  constexpr int KC = (C + 31) / 32;       // 32-channel k-steps of the per-pair dot products
   static_assert(RW <= 64, "per-wave partial sums must fit the wave's 64 columns");
   static_assert(kBJ * R4 <= 256, "one thread per record chunk");
   // [j][pixel]: weights (rows 0..kBJ-1) and dL/dpower (rows kBJ..2kBJ-1).  A
@@ -209,7 +210,11 @@ __global__ __launch_bounds__(256, C > 26 ? 2 : 3) void composite_bwd_kernel(
   // use yet), split into BF16 high and low parts and kept in registers for
   // the whole tile, as are the moment basis values (1, x, y, x^2, xy, y^2)
   // of the same pixels, from the tile corner.
-  cbf16x8 bh[2][NBC], bl[2][NBC];
+  // The same dL/dG is also the B operand of the per-batch products
+  // eg[j][p] = sum_c channel_j,c dG[p][c] (K = channels): lane (col, g)
+  // holds channels 32 ks + 8 g + i of pixel 16 nb + col of the wave's strip.
+  cbf16x8 bh[2][NBC], bl[2][NBC], eh[KC][4], el[KC][4];
+  float ev[KC][4][8];
 #pragma unroll
   for (int nc = 0; nc < NBC; nc++) {
 #pragma unroll
@@ -222,8 +227,24 @@ __global__ __launch_bounds__(256, C > 26 ? 2 : 3) void composite_bwd_kernel(
       for (int i = 0; i < 8; i++) v[i] = mat[(64 * w + 32 * kk + 8 * g + i) * 17 + col];
       split_bf16x8(v, bh[kk][nc], bl[kk][nc]);
     }
+    // channel block nc holds k-step nc / 2 for the lanes with g / 2 == nc % 2
+    if ((g >> 1) == (nc & 1)) {
+#pragma unroll
+      for (int nb = 0; nb < 4; nb++)
+#pragma unroll
+        for (int i = 0; i < 8; i++) ev[nc >> 1][nb][i] = mat[(64 * w + 16 * nb + col) * 17 + 8 * (g & 1) + i];
+    }
     __syncthreads();
   }
+#pragma unroll
+  for (int ks = 0; ks < KC; ks++)
+#pragma unroll
+    for (int nb = 0; nb < 4; nb++) {
+      // channels of a k-step beyond the last 16-column block were never loaded
+      if (2 * ks + (g >> 1) >= NBC)
+        for (int i = 0; i < 8; i++) ev[ks][nb][i] = 0.f;
+      split_bf16x8(ev[ks][nb], eh[ks][nb], el[ks][nb]);
+    }
   // moment basis of pixel 64 w + 16 g + ks (FP32 B operand; K step ks takes
   // one pixel from each lane group, so a lane's 16 pixels are contiguous):
   // x = ks + 1/2 and y = 4 w + g + 1/2, so column col of the basis
@@ -272,6 +293,33 @@ __global__ __launch_bounds__(256, C > 26 ? 2 : 3) void composite_bwd_kernel(
     bool h = false;
     if (lane < cnt) h = box_hits(bbox[buf][lane], sx, sy);
     const uint32_t hm = (uint32_t)__ballot(h);
+    // ---- eg[j][p] = channels_j . dG_p for the batch on the matrix cores
+    // (three-term BF16 split), into this wave's columns of rows kBJ.. (each
+    // lane reads its own eg[j] there before the walk overwrites it with g)
+    {
+      const float *rc = reinterpret_cast<const float *>(&recs[buf][col * R4]);
+      cbf16x8 ah[KC], al[KC];
+#pragma unroll
+      for (int ks = 0; ks < KC; ks++) {
+        float a[8];
+#pragma unroll
+        for (int i = 0; i < 8; i++) {
+          const int c = 32 * ks + 8 * g + i;
+          a[i] = (c < C && col < cnt) ? rc[6 + (c < C ? c : 0)] : 0.f;
+        }
+        split_bf16x8(a, ah[ks], al[ks]);
+      }
+#pragma unroll
+      for (int nb = 0; nb < 4; nb++) {
+        cf32x4 d = cf32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int ks = 0; ks < KC; ks++) d = mma3(ah[ks], al[ks], eh[ks][nb], el[ks][nb], d);
+#pragma unroll
+        for (int i = 0; i < 4; i++) mat[(kBJ + 4 * g + i) * kMS + 64 * w + 16 * nb + col] = d[i];
+      }
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+    }
     // ---- per pixel, last to first; each result goes straight to LDS
 #pragma unroll
     for (int jj = kBJ - 1; jj >= 0; jj--) {
@@ -288,9 +336,7 @@ __global__ __launch_bounds__(256, C > 26 ? 2 : 3) void composite_bwd_kernel(
             const float inv = __builtin_amdgcn_rcpf(1.f - al);
             const float Tb = Tcur * inv;
             const float wgt = al * Tb;
-            float eg = 0.f;
-#pragma unroll
-            for (int c = 0; c < C; c++) eg = __fmaf_rn(gch[c], r[6 + c], eg);
+            const float eg = mat[(kBJ + jj) * kMS + t];
             const float dal = Tb * eg - (S + dTT) * inv;
             S = __fmaf_rn(wgt, eg, S);
             Tcur = Tb;
