@@ -348,7 +348,11 @@ __global__ __launch_bounds__(256, C > 26 ? 2 : 3) void composite_bwd_kernel(
       mat[jj * kMS + t] = wvj;
       mat[(kBJ + jj) * kMS + t] = pvj;
     }
-    __syncthreads();
+    // the reductions read only this wave's own columns: a wave-level fence
+    // suffices, and a wave whose strip had few hits goes on to the matrix
+    // cores while the others still walk
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
     // ---- reductions over this wave's 64 pixels (two steps of 32):
     //   [j][c]  = sum_p w[j][p] dG[p][c]
     //   [j][n]  = sum_p g[j][p] basis_n(p),  basis = (1, x, y, x^2, xy, y^2) from the tile corner
