@@ -150,3 +150,39 @@ def test_render_with_per_gaussian_network():
     errs = {k: rel_norm(got[k], ref[k]) for k in ref if ref[k].size and np.any(ref[k])}
     print("grad rel errors:", {k: f"{v:.2e}" for k, v in errs.items()})
     assert max(errs.values()) <= GRAD_REL, errs
+
+
+def test_gaussian_network_full_size():
+    """The 300k-Gaussian scene of the benchmark: every Gaussian's feature
+    planes, and the gradients for a random dL/d(features), against the
+    oracle (vectorised over all 300k Gaussians)."""
+    import torch
+    w = scene.workload(3)
+    g = w.gaussians
+    n = g.n
+    vis = scene.make_visibility(n, seed=0)
+    gm = scene.make_gaussian_mlp(seed=0)
+    cam, light = w.cameras[0], w.lights[0]
+    from paper_2408_12282_amd import sssgs as B
+    print(f"[gpu] per-Gaussian network full size n={n}", flush=True)
+    params = {k: _dev(v) for k, v in g.arrays().items() if v is not None}
+    bc, bl = B.make_camera(cam), B.make_light(light)
+    feats = B.gaussian_mlp_forward(params, bc, bl, _dev(vis), _dev(gm))
+    dfeat = np.random.default_rng(3).normal(size=(8, n)).astype(np.float32)
+    grads = {k: torch.zeros_like(params[k]) for k in ("means", "log_scales", "quats")}
+    dvis, dgm = _dev(np.zeros(n)), _dev(np.zeros(gm.size))
+    B.gaussian_mlp_backward(params, bc, bl, _dev(vis), _dev(gm), _dev(dfeat), grads, dvis, dgm)
+    torch.cuda.synchronize()
+    x, cache = GM.inputs(g.means, g.log_scales, g.quats, vis, cam.center, light.pos)
+    ref, acts = GM.forward(x, gm)
+    bound = GM.forward_bound(x, gm)
+    ok = _side_ok(g, vis, cam, light)
+    got = feats.cpu().numpy()
+    for c in range(6):
+        assert_close_masked(got[c], ref[c], ok, ELEM_REL, f"plane {c}", scale=np.abs(ref[c]) + bound[c])
+    d = GM.backward(dfeat, gm, acts, cache, cam.center, light.pos)
+    errs = {k: rel_norm(grads[k].cpu().numpy()[:, ok], d[k][:, ok]) for k in ("means", "log_scales", "quats")}
+    errs["visibility"] = rel_norm(dvis.cpu().numpy()[ok], d["visibility"][ok])
+    errs["params"] = rel_norm(dgm.cpu().numpy(), d["params"])
+    print("grad rel errors:", {k: f"{v:.2e}" for k, v in errs.items()})
+    assert max(errs.values()) <= GRAD_REL, errs
