@@ -206,8 +206,8 @@ def time_gaussian_network(g, cam, light, drgb, steps: int):
 
     def step():
         rgb, gbuf, alpha, feats, _ = B.render_gaussian_mlp_forward(view, p, bc, bl, vis, gm, ws)
-        B.render_gaussian_mlp_backward(view, p, bc, bl, vis, gm, feats, gbuf, drgb, workspace=ws, grads=grads,
-                                       dvis=dvis, dgmlp=dgm)
+        B.render_gaussian_mlp_backward(view, p, bc, bl, vis, gm, feats, gbuf, drgb, ws, grads=grads, dvis=dvis,
+                                       dgmlp=dgm)
 
     for _ in range(3):
         step()

@@ -228,8 +228,12 @@ size_t sssgs_gaussian_mlp_workspace_bytes(int32_t n);
 sssgs_status sssgs_gaussian_mlp_forward(const sssgs_gaussians *g, const sssgs_camera *cam, const sssgs_light *light,
                                         const float *visibility, const float *params, void *workspace,
                                         size_t workspace_bytes, float *out_features, void *stream);
-/* Backward of sssgs_gaussian_mlp_forward (recomputes the forward; nothing is
-   kept between the calls).  dL_dfeatures [8][n]: gradient of the feature
+/* Backward of sssgs_gaussian_mlp_forward.  It reads the per-Gaussian records
+   (layer activations and Leaky-ReLU signs) that the last forward call left
+   in the same workspace: call it after a forward with the same n, Gaussians,
+   camera, light, visibility and params, with the workspace untouched in
+   between (the backward itself does not modify the records, so it may be
+   called repeatedly).  dL_dfeatures [8][n]: gradient of the feature
    planes, e.g. the `features` gradient of sssgs_render_backward.  ADDS the
    network's contribution to dL_dmeans [3][n], dL_dlog_scales [3][n] and
    dL_dquats [4][n] (the render backward writes them first); writes (accumulate

@@ -592,7 +592,7 @@ int64_t sssgs_gaussian_mlp_param_count(void) { return gmlp_param_count(); }
 
 namespace {
 struct GmlpLayout {
-  size_t wt, part, mid, act, dz, total;
+  size_t wt, part, mid, act, dz, masks, total;
 };
 GmlpLayout gmlp_layout(int32_t n) {
   GmlpLayout L;
@@ -608,6 +608,7 @@ GmlpLayout gmlp_layout(int32_t n) {
   L.mid = take((size_t)reduce_scratch_floats((int)np) * 4);
   L.act = take(gmlp_act_floats(n) * 4);
   L.dz = take(gmlp_dz_floats(n) * 4);
+  L.masks = take(gmlp_mask_words(n) * 4);
   L.total = p;
   return L;
 }
@@ -650,6 +651,10 @@ sssgs_status sssgs_gaussian_mlp_forward(const sssgs_gaussians *g, const sssgs_ca
   hipStream_t st = (hipStream_t)stream;
   GmlpArgs a = gmlp_args(g, cam, light, visibility, params, ws);
   a.feat = out_features;
+  const GmlpLayout L = gmlp_layout(g->n);
+  a.act = at<float>(ws, L.act);
+  a.masks = at<uint32_t>(ws, L.masks);
+  a.ldn = gmlp_ldn(g->n);
   Scope sc(kStGmlpFwd, st);
   launch_gmlp_prep(params, at<float>(ws, gmlp_layout(g->n).wt), st);
   launch_gmlp_fwd(a, st);
@@ -675,6 +680,7 @@ sssgs_status sssgs_gaussian_mlp_backward(const sssgs_gaussians *g, const sssgs_c
   a.partials = at<float>(ws, L.part);
   a.act = at<float>(ws, L.act);
   a.dz = at<float>(ws, L.dz);
+  a.masks = at<uint32_t>(ws, L.masks);
   a.ldn = gmlp_ldn(g->n);
   a.accumulate = accumulate;
   Scope sc(kStGmlpBwd, st);

@@ -166,6 +166,35 @@ __device__ __forceinline__ void write_input(const GIn &G, float *col, int row0) 
   }
 }
 
+// ------------------------------------------------------------------ records
+//
+// The forward stores, unit-major ([row][ldn], ldn = n rounded up to 64), every
+// layer's input activations, the heads' pre-activations and the Leaky-ReLU
+// signs as bit masks; the backward reads them instead of recomputing the
+// network, and the weight-gradient kernel streams them.
+
+// Activation rows (layer inputs) and output-gradient rows of the records.
+// Rows kAZ.. hold the heads' pre-activations (incident 3, SSS 3).
+constexpr int kAX = 0, kAH1 = 42, kAH2 = 106, kAH3 = 138, kAE = 170, kAZ = 202, kARows = 208;
+constexpr int kMaskRows = 5;  // Leaky-ReLU signs: h1 (two words), h2, h3, e
+constexpr int kD0 = 0, kD1 = 64, kD2 = 96, kDI = 128, kDH = 160, kDRows = 166;
+
+template <int N>
+__device__ __forceinline__ void put_rows(float *rec, int row0, size_t ldn, size_t g, const float (&v)[N]) {
+#pragma unroll
+  for (int k = 0; k < N; k++) rec[(row0 + k) * ldn + g] = v[k];
+}
+
+template <int N>
+__device__ __forceinline__ uint64_t sign_mask(const float (&z)[N]) {
+  uint64_t m = 0;
+#pragma unroll
+  for (int k = 0; k < N; k++) m |= (z[k] > 0.f ? 1ull : 0ull) << k;
+  return m;
+}
+
+__device__ __forceinline__ float slope(uint64_t m, int k) { return (m >> k) & 1ull ? 1.f : kSlope; }
+
 // ------------------------------------------------------------------ forward
 
 // Rows of the forward's LDS column: the layer input (up to 64 rows) and, for
@@ -178,34 +207,55 @@ __global__ __launch_bounds__(64) void gmlp_fwd_kernel(GmlpArgs A) {
   const int gi = live ? i : 0;
   float *col = lds + lane;
   const cptr wt = as_const(A.wt), P = as_const(A.params);
+  const bool rec = A.act != nullptr;  // keep the backward's records
+  const size_t ldn = A.ldn;
+  float *act = A.act;
   GIn G;
   gaussian_input(A, gi, G);
   write_input(G, col, 0);
+  if (rec)
+#pragma unroll
+    for (int k = 0; k < kGIn; k++) act[(kAX + k) * ldn + i] = col[k * kLS];
+  uint64_t m1, m2, m3, me;
   {
     float h[64];
     layer_fwd<64, kGIn>(wt + kL0.w, P + kL0.b, col, h);
+    m1 = sign_mask(h);
 #pragma unroll
     for (int k = 0; k < 64; k++) h[k] = lrelu(h[k]);
     put_col(col, 0, h);
+    if (rec) put_rows(act, kAH1, ldn, i, h);
   }
   {
     float h[32];
     layer_fwd<32, 64>(wt + kL1.w, P + kL1.b, col, h);
+    m2 = sign_mask(h);
 #pragma unroll
     for (int k = 0; k < 32; k++) h[k] = lrelu(h[k]);
     put_col(col, 0, h);
+    if (rec) put_rows(act, kAH2, ldn, i, h);
     layer_fwd<32, 32>(wt + kL2.w, P + kL2.b, col, h);
+    m3 = sign_mask(h);
 #pragma unroll
     for (int k = 0; k < 32; k++) h[k] = lrelu(h[k]);
     put_col(col, 0, h);   // trunk output
+    if (rec) put_rows(act, kAH3, ldn, i, h);
     layer_fwd<32, 32>(wt + kLi.w, P + kLi.b, col, h);
+    me = sign_mask(h);
 #pragma unroll
     for (int k = 0; k < 32; k++) h[k] = lrelu(h[k]);
     put_col(col, 32, h);  // incident head, hidden
+    if (rec) put_rows(act, kAE, ldn, i, h);
   }
   float zl[3], zs[3];
   layer_fwd<3, 32>(wt + kLl.w, P + kLl.b, col + 32 * kLS, zl);
   layer_fwd<3, 32>(wt + kLs.w, P + kLs.b, col, zs);
+  if (rec) {
+    const float z[6] = {zl[0], zl[1], zl[2], zs[0], zs[1], zs[2]};
+    put_rows(act, kAZ, ldn, i, z);
+    const uint32_t mw[kMaskRows] = {(uint32_t)m1, (uint32_t)(m1 >> 32), (uint32_t)m2, (uint32_t)m3, (uint32_t)me};
+    for (int k = 0; k < kMaskRows; k++) A.masks[k * ldn + i] = mw[k];
+  }
   if (live) {
     const size_t n = A.n;
     for (int c = 0; c < 3; c++) {
@@ -236,33 +286,14 @@ __global__ __launch_bounds__(256) void gmlp_prep_kernel(const float *__restrict_
 // ----------------------------------------------------------------- backward
 //
 // Two kernels.  gmlp_bwd_kernel: one lane per Gaussian (high occupancy: one
-// 64-row LDS column per lane); it recomputes the forward keeping only the
-// Leaky-ReLU signs (bit masks in registers), runs the backward through the
-// layers and the chain to the Gaussian parameters, and stores every layer's
-// input activations and output gradients unit-major ([unit][ldn], ldn = n
-// rounded up to 64; lanes past n store zero gradients).  gmlp_wgrad_kernel:
+// 64-row LDS column per lane); from the forward's records (signs and head
+// pre-activations) it runs the backward through the layers and the chain to
+// the Gaussian parameters, and stores every layer's output gradients
+// unit-major ([unit][ldn]; lanes past n store zeros).  gmlp_wgrad_kernel:
 // the weight gradients sum_g dz[o][g] a[i][g] on the matrix cores, streaming
 // those records; one layer group per grid row.
 
-// Activation rows (layer inputs) and output-gradient rows of the records.
-constexpr int kAX = 0, kAH1 = 42, kAH2 = 106, kAH3 = 138, kAE = 170, kARows = 202;
-constexpr int kD0 = 0, kD1 = 64, kD2 = 96, kDI = 128, kDH = 160, kDRows = 166;
 
-template <int N>
-__device__ __forceinline__ void put_rows(float *rec, int row0, size_t ldn, size_t g, const float (&v)[N]) {
-#pragma unroll
-  for (int k = 0; k < N; k++) rec[(row0 + k) * ldn + g] = v[k];
-}
-
-template <int N>
-__device__ __forceinline__ uint64_t sign_mask(const float (&z)[N]) {
-  uint64_t m = 0;
-#pragma unroll
-  for (int k = 0; k < N; k++) m |= (z[k] > 0.f ? 1ull : 0ull) << k;
-  return m;
-}
-
-__device__ __forceinline__ float slope(uint64_t m, int k) { return (m >> k) & 1ull ? 1.f : kSlope; }
 
 __global__ __launch_bounds__(64) void gmlp_bwd_kernel(GmlpArgs A) {
   __shared__ float lds[64 * kLS];
@@ -271,52 +302,17 @@ __global__ __launch_bounds__(64) void gmlp_bwd_kernel(GmlpArgs A) {
   const bool live = i < A.n;
   const int gi = live ? i : 0;
   float *col = lds + lane;
-  const cptr wt = as_const(A.wt), P = as_const(A.params);
+  const cptr P = as_const(A.params);
   const size_t n = A.n, ldn = A.ldn;
-  float *act = A.act, *dzr = A.dz;
-  {
-    GIn G0;
-    gaussian_input(A, gi, G0);
-    write_input(G0, col, 0);
-  }
-#pragma unroll
-  for (int k = 0; k < kGIn; k++) act[(kAX + k) * ldn + i] = col[k * kLS];
-  // ---- forward: activations to the records, Leaky-ReLU signs kept as masks
-  uint64_t m1, m2, m3, me;
+  const float *act = A.act;
+  float *dzr = A.dz;
+  // ---- the forward's records: Leaky-ReLU signs and the heads' pre-activations
+  const uint64_t m1 = (uint64_t)A.masks[i] | ((uint64_t)A.masks[ldn + i] << 32);
+  const uint64_t m2 = A.masks[2 * ldn + i], m3 = A.masks[3 * ldn + i], me = A.masks[4 * ldn + i];
   float zl[3], lsss[3];
-  {
-    float h[64];
-    layer_fwd<64, kGIn>(wt + kL0.w, P + kL0.b, col, h);
-    m1 = sign_mask(h);
-#pragma unroll
-    for (int k = 0; k < 64; k++) h[k] = lrelu(h[k]);
-    put_col(col, 0, h);
-    put_rows(act, kAH1, ldn, i, h);
-  }
-  {
-    float h[32];
-    layer_fwd<32, 64>(wt + kL1.w, P + kL1.b, col, h);
-    m2 = sign_mask(h);
-#pragma unroll
-    for (int k = 0; k < 32; k++) h[k] = lrelu(h[k]);
-    put_col(col, 0, h);
-    put_rows(act, kAH2, ldn, i, h);
-    layer_fwd<32, 32>(wt + kL2.w, P + kL2.b, col, h);
-    m3 = sign_mask(h);
-#pragma unroll
-    for (int k = 0; k < 32; k++) h[k] = lrelu(h[k]);
-    put_col(col, 0, h);   // trunk output
-    put_rows(act, kAH3, ldn, i, h);
-    layer_fwd<32, 32>(wt + kLi.w, P + kLi.b, col, h);
-    me = sign_mask(h);
-#pragma unroll
-    for (int k = 0; k < 32; k++) h[k] = lrelu(h[k]);
-    put_col(col, 32, h);  // incident head, hidden
-    put_rows(act, kAE, ldn, i, h);
-    float zs[3];
-    layer_fwd<3, 32>(wt + kLl.w, P + kLl.b, col + 32 * kLS, zl);
-    layer_fwd<3, 32>(wt + kLs.w, P + kLs.b, col, zs);
-    for (int c = 0; c < 3; c++) lsss[c] = 1.f / (1.f + expf(-zs[c]));
+  for (int c = 0; c < 3; c++) {
+    zl[c] = act[(kAZ + c) * ldn + i];
+    lsss[c] = 1.f / (1.f + expf(-act[(kAZ + 3 + c) * ldn + i]));
   }
   // ---- backward
   float df[8];
@@ -567,6 +563,7 @@ int gmlp_wgrad_grid(int n) {
 size_t gmlp_ldn(int n) { return (size_t)((n + 63) / 64) * 64; }
 size_t gmlp_act_floats(int n) { return (size_t)kARows * gmlp_ldn(n); }
 size_t gmlp_dz_floats(int n) { return (size_t)kDRows * gmlp_ldn(n); }
+size_t gmlp_mask_words(int n) { return (size_t)kMaskRows * gmlp_ldn(n); }
 
 void launch_gmlp_prep(const float *params, float *wt, hipStream_t st) {
   gmlp_prep_kernel<<<(kGParams + 255) / 256, 256, 0, st>>>(params, wt);

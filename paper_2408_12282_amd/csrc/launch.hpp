@@ -97,7 +97,8 @@ struct GmlpArgs {
   float *d_means, *d_log_scales, *d_quats;  // added to
   float *d_vis;            // written, or added when accumulate
   float *partials;         // [gmlp_wgrad_grid(n)][gmlp_param_count()]
-  float *act, *dz;         // backward records [rows][ldn] (gmlp_act_floats, gmlp_dz_floats)
+  float *act, *dz;         // records [rows][ldn] (gmlp_act_floats, gmlp_dz_floats); act written by the forward
+  uint32_t *masks;         // [5][ldn] Leaky-ReLU signs written by the forward
   size_t ldn;              // n rounded up to 64
   int accumulate;
 };
@@ -107,6 +108,7 @@ int gmlp_wgrad_grid(int n);
 size_t gmlp_ldn(int n);
 size_t gmlp_act_floats(int n);
 size_t gmlp_dz_floats(int n);
+size_t gmlp_mask_words(int n);
 void launch_gmlp_prep(const float *params, float *wt, hipStream_t st);
 void launch_gmlp_fwd(const GmlpArgs &a, hipStream_t st);
 void launch_gmlp_bwd(const GmlpArgs &a, hipStream_t st);

@@ -460,7 +460,9 @@ def gaussian_mlp_workspace(n: int, device="cuda") -> torch.Tensor:
 def gaussian_mlp_forward(params: dict, cam: Camera, light: Light, visibility: torch.Tensor, gmlp: torch.Tensor,
                          workspace: Optional[torch.Tensor] = None) -> torch.Tensor:
     """Feature planes [8, N] = incident light | SSS radiance | visibility | 1 of
-    the per-Gaussian network (see include/sssgs.h)."""
+    the per-Gaussian network (see include/sssgs.h).  A backward needs the
+    records this call leaves in ``workspace``: pass the same workspace to
+    both."""
     n = int(params["means"].shape[1])
     if workspace is None:
         workspace = gaussian_mlp_workspace(n, params["means"].device)
@@ -474,12 +476,10 @@ def gaussian_mlp_forward(params: dict, cam: Camera, light: Light, visibility: to
 
 def gaussian_mlp_backward(params: dict, cam: Camera, light: Light, visibility: torch.Tensor, gmlp: torch.Tensor,
                           dfeat: torch.Tensor, grads: dict, dvis: torch.Tensor, dgmlp: torch.Tensor,
-                          accumulate: bool = False, workspace: Optional[torch.Tensor] = None):
+                          workspace: torch.Tensor, accumulate: bool = False):
     """Adds the network's share to grads['means'|'log_scales'|'quats'];
-    writes (or adds) dvis and dgmlp."""
-    n = int(params["means"].shape[1])
-    if workspace is None:
-        workspace = gaussian_mlp_workspace(n, params["means"].device)
+    writes (or adds) dvis and dgmlp.  ``workspace`` is the one the forward
+    of the same inputs used."""
     g = gaussians_struct(params, 0, -1)
     _check(lib().sssgs_gaussian_mlp_backward(ct.byref(g), ct.byref(cam), ct.byref(light), _ptr(visibility),
                                              _ptr(gmlp), _ptr(dfeat.contiguous()), ct.c_void_p(workspace.data_ptr()),
@@ -489,11 +489,12 @@ def gaussian_mlp_backward(params: dict, cam: Camera, light: Light, visibility: t
 
 
 def render_gaussian_mlp_forward(view: View, params: dict, cam: Camera, light: Light, visibility: torch.Tensor,
-                                gmlp: torch.Tensor, workspace: Optional[torch.Tensor] = None,
-                                want_count: bool = False):
+                                gmlp: torch.Tensor, workspace: torch.Tensor, want_count: bool = False):
     """Per-Gaussian network -> projection and compositing of the 18-plane
     G-buffer -> Eq. 7 from the composited radiances.  ``view`` has feat_dim 8
-    and no per-pixel network.  Returns (rgb, gbuf, alpha, features, M or None)."""
+    and no per-pixel network; ``workspace`` (gaussian_mlp_workspace) keeps the
+    network's records for the backward.  Returns (rgb, gbuf, alpha, features,
+    M or None)."""
     feats = gaussian_mlp_forward(params, cam, light, visibility, gmlp, workspace)
     p = dict(params, features=feats)
     rgb, gbuf, alpha, cnt = render_forward(view, p, -1, cam, light, None, 64, PREC_FP32, want_count,
@@ -502,8 +503,8 @@ def render_gaussian_mlp_forward(view: View, params: dict, cam: Camera, light: Li
 
 
 def render_gaussian_mlp_backward(view: View, params: dict, cam: Camera, light: Light, visibility: torch.Tensor,
-                                 gmlp: torch.Tensor, feats: torch.Tensor, gbuf, drgb, dgbuf=None, dalpha=None,
-                                 workspace: Optional[torch.Tensor] = None, grads: Optional[dict] = None,
+                                 gmlp: torch.Tensor, feats: torch.Tensor, gbuf, drgb, workspace: torch.Tensor,
+                                 dgbuf=None, dalpha=None, grads: Optional[dict] = None,
                                  dvis: Optional[torch.Tensor] = None, dgmlp: Optional[torch.Tensor] = None):
     """Gradients of every Gaussian parameter (dict), of the visibility and of
     the network parameters (all overwritten; pass buffers to reuse them)."""
@@ -517,8 +518,7 @@ def render_gaussian_mlp_backward(view: View, params: dict, cam: Camera, light: L
                     radiance_features=True)
     dvis = torch.empty_like(visibility) if dvis is None else dvis
     dgmlp = torch.empty_like(gmlp) if dgmlp is None else dgmlp
-    gaussian_mlp_backward(params, cam, light, visibility, gmlp, grads["features"], grads, dvis, dgmlp,
-                          workspace=workspace)
+    gaussian_mlp_backward(params, cam, light, visibility, gmlp, grads["features"], grads, dvis, dgmlp, workspace)
     dfeat = grads.pop("features")
     return grads, dvis, dgmlp, dfeat
 

@@ -68,7 +68,9 @@ def test_gaussian_network_backward_and_accumulation():
     grads = {k: _dev(v) for k, v in base.items()}
     dvis, dgm = _dev(np.zeros(n)), _dev(np.zeros(gm.size))
     bc, bl = B.make_camera(cam), B.make_light(light)
-    B.gaussian_mlp_backward(params, bc, bl, _dev(vis), _dev(gm), _dev(dfeat), grads, dvis, dgm)
+    ws = B.gaussian_mlp_workspace(n)
+    B.gaussian_mlp_forward(params, bc, bl, _dev(vis), _dev(gm), ws)
+    B.gaussian_mlp_backward(params, bc, bl, _dev(vis), _dev(gm), _dev(dfeat), grads, dvis, dgm, ws)
     torch.cuda.synchronize()
     ref = GM.feature_grads(g.means, g.log_scales, g.quats, vis, gm, cam.center, light.pos, dfeat)
     ok = _side_ok(g, vis, cam, light)
@@ -81,11 +83,11 @@ def test_gaussian_network_backward_and_accumulation():
     assert max(errs.values()) <= GRAD_REL, errs
     # accumulate = 1 adds; a second identical call reproduces the sum bit for bit
     first_p, first_v = dgm.clone(), dvis.clone()
-    B.gaussian_mlp_backward(params, bc, bl, _dev(vis), _dev(gm), _dev(dfeat), grads, dvis, dgm, accumulate=True)
+    B.gaussian_mlp_backward(params, bc, bl, _dev(vis), _dev(gm), _dev(dfeat), grads, dvis, dgm, ws, accumulate=True)
     torch.cuda.synchronize()
     assert torch.equal(dgm, first_p + first_p) and torch.equal(dvis, first_v + first_v)
     again_p = _dev(np.zeros(gm.size))
-    B.gaussian_mlp_backward(params, bc, bl, _dev(vis), _dev(gm), _dev(dfeat), grads, _dev(np.zeros(n)), again_p)
+    B.gaussian_mlp_backward(params, bc, bl, _dev(vis), _dev(gm), _dev(dfeat), grads, _dev(np.zeros(n)), again_p, ws)
     torch.cuda.synchronize()
     assert torch.equal(again_p, first_p)
 
@@ -94,10 +96,11 @@ def test_gaussian_network_empty():
     import torch
     B, g, vis, gm, cam, light, params = _setup(0, seed=1)
     bc, bl = B.make_camera(cam), B.make_light(light)
-    feats = B.gaussian_mlp_forward(params, bc, bl, _dev(vis), _dev(gm))
+    ws = B.gaussian_mlp_workspace(0)
+    feats = B.gaussian_mlp_forward(params, bc, bl, _dev(vis), _dev(gm), ws)
     dgm = _dev(np.full(gm.size, 7.0))
     grads = {k: params[k].clone() for k in ("means", "log_scales", "quats")}
-    B.gaussian_mlp_backward(params, bc, bl, _dev(vis), _dev(gm), feats, grads, _dev(vis), dgm)
+    B.gaussian_mlp_backward(params, bc, bl, _dev(vis), _dev(gm), feats, grads, _dev(vis), dgm, ws)
     torch.cuda.synchronize()
     assert feats.shape == (8, 0) and not torch.any(dgm)
 
@@ -117,7 +120,8 @@ def test_render_with_per_gaussian_network():
     cap = max(1024, int(estimate_instances(g, cam) * 1.25) + 1024)
     view = B.View(n, W, H, 8, 0, cap)
     bc, bl = B.make_camera(cam), B.make_light(light)
-    rgb, gbuf, alpha, feats, _ = B.render_gaussian_mlp_forward(view, params, bc, bl, _dev(vis), _dev(gm))
+    ws = B.gaussian_mlp_workspace(n)
+    rgb, gbuf, alpha, feats, _ = B.render_gaussian_mlp_forward(view, params, bc, bl, _dev(vis), _dev(gm), ws)
     torch.cuda.synchronize()
     # the rendering stages on the features the network stage produced (that
     # stage is compared on its own above), the gradient end to end below
@@ -142,7 +146,7 @@ def test_render_with_per_gaussian_network():
     ref["visibility"] = dnet["visibility"]
     ref["gmlp"] = dnet["params"]
     grads, dvis, dgm, _ = B.render_gaussian_mlp_backward(view, params, bc, bl, _dev(vis), _dev(gm), feats, gbuf,
-                                                         _dev(drgb))
+                                                         _dev(drgb), ws)
     torch.cuda.synchronize()
     got = {k: v.cpu().numpy() for k, v in grads.items()}
     got["visibility"] = dvis.cpu().numpy()
@@ -167,11 +171,12 @@ def test_gaussian_network_full_size():
     print(f"[gpu] per-Gaussian network full size n={n}", flush=True)
     params = {k: _dev(v) for k, v in g.arrays().items() if v is not None}
     bc, bl = B.make_camera(cam), B.make_light(light)
-    feats = B.gaussian_mlp_forward(params, bc, bl, _dev(vis), _dev(gm))
+    ws = B.gaussian_mlp_workspace(n)
+    feats = B.gaussian_mlp_forward(params, bc, bl, _dev(vis), _dev(gm), ws)
     dfeat = np.random.default_rng(3).normal(size=(8, n)).astype(np.float32)
     grads = {k: torch.zeros_like(params[k]) for k in ("means", "log_scales", "quats")}
     dvis, dgm = _dev(np.zeros(n)), _dev(np.zeros(gm.size))
-    B.gaussian_mlp_backward(params, bc, bl, _dev(vis), _dev(gm), _dev(dfeat), grads, dvis, dgm)
+    B.gaussian_mlp_backward(params, bc, bl, _dev(vis), _dev(gm), _dev(dfeat), grads, dvis, dgm, ws)
     torch.cuda.synchronize()
     x, cache = GM.inputs(g.means, g.log_scales, g.quats, vis, cam.center, light.pos)
     ref, acts = GM.forward(x, gm)
