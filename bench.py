@@ -229,10 +229,10 @@ def time_gaussian_network(g, cam, light, drgb, steps: int):
     B.sssgs_timing_enable(False)
     st = {k: v[0] / v[1] for k, v in B.sssgs_timing_read().items() if v[1] > 0}
     # multiply-adds of the network per Gaussian (42x64, 64x32, 32x32, 32x32, 32x3, 32x3); the backward
-    # recomputes the forward, propagates the input gradient and forms the weight gradient (3x)
+    # propagates the input gradient and forms the weight gradient (2x; it reads the forward's activations)
     flop = 2 * (42 * 64 + 64 * 32 + 32 * 32 + 32 * 32 + 32 * 3 + 32 * 3)
     roof = {}
-    for name, f in (("gmlp_fwd", n * flop), ("gmlp_bwd", 3 * n * flop)):
+    for name, f in (("gmlp_fwd", n * flop), ("gmlp_bwd", 2 * n * flop)):
         if st.get(name, 0) > 0:
             tf = f / (st[name] * 1e-3) / 1e12
             roof[name] = {"bound": "alu", "achieved": round(tf, 2), "peak": FP32_VALU_TFLOPS, "unit": "TFLOP/s",
