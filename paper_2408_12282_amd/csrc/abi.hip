@@ -54,16 +54,13 @@ struct Scope {
   Scope(int s, hipStream_t stream) : stage(s), st(stream) {
     if (g_timer.on) {
       a = g_timer.get();
-      if (a) hipEventRecord(a, st);
+      if (a && hipEventRecord(a, st) != hipSuccess) a = nullptr;  // timing is best effort
     }
   }
   ~Scope() {
     if (g_timer.on && a) {
       hipEvent_t b = g_timer.get();
-      if (b) {
-        hipEventRecord(b, st);
-        g_timer.recs.push_back({stage, a, b});
-      }
+      if (b && hipEventRecord(b, st) == hipSuccess) g_timer.recs.push_back({stage, a, b});
     }
   }
 };

@@ -51,7 +51,6 @@ typedef const __attribute__((address_space(4))) float *cptr;
 __device__ __forceinline__ cptr as_const(const float *p) { return (cptr)p; }
 
 __device__ __forceinline__ float lrelu(float z) { return z > 0.f ? z : kSlope * z; }
-__device__ __forceinline__ float lrelu_d(float h) { return h > 0.f ? 1.f : kSlope; }
 
 // acc[r] = b[r] + sum_i W[r][i] in[i]; wt = W transposed ([COLS][ROWS]),
 // in = the lane's LDS column (row stride kLS).
