@@ -241,14 +241,18 @@ __global__ __launch_bounds__(256) void vis_pack_kernel(VisArgs A) {
   }
 }
 
-// Does the segment o + t d, 0 <= t <= tmax, meet the box (lo, hi)?
+// Does the segment o + t d, 0 <= t <= tmax, meet the box (lo, hi)?  The
+// entry and exit planes are chosen by the direction's sign (not by min/max
+// of the two distances), so an empty box (lo = +inf, hi = -inf) enters at
+// +inf and leaves at -inf: never a hit.
 __device__ __forceinline__ bool slab(const float *box, const float *o, const float *inv, float tmax) {
   float t0 = 0.f, t1 = tmax;
 #pragma unroll
   for (int m = 0; m < 3; m++) {
-    const float a = (box[m] - o[m]) * inv[m], b = (box[3 + m] - o[m]) * inv[m];
-    t0 = fmaxf(t0, fminf(a, b));
-    t1 = fminf(t1, fmaxf(a, b));
+    const bool pos = inv[m] >= 0.f;
+    const float near = pos ? box[m] : box[3 + m], far = pos ? box[3 + m] : box[m];
+    t0 = fmaxf(t0, (near - o[m]) * inv[m]);
+    t1 = fminf(t1, (far - o[m]) * inv[m]);
   }
   return t0 <= t1;
 }

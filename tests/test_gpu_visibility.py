@@ -129,3 +129,20 @@ def test_traced_visibility_feeds_the_per_gaussian_network():
     print(f"  chain features max err {float(err[:, ok].max()):.2e}", flush=True)
     assert float(err[:, ok].max()) < 1e-5
     np.testing.assert_array_equal(got[6], vis.cpu().numpy())
+
+
+def test_gaussians_that_cannot_occlude():
+    """Opacities below 1/255 (empty culling boxes) change nothing: the
+    visibility equals that of the scene without them."""
+    g = scene.make_gaussians(400, 0, seed=31)
+    g.log_scales += 1.5
+    g.opacity_logits[::3] = -8.0          # sigmoid < 1/255
+    light = scene.default_light().pos
+    print("[gpu] visibility with faint Gaussians", flush=True)
+    got = _gpu(*_f32(g), light)
+    ref, flag = V.visibility(*_f32(g), light, margins=True)
+    _compare(got, ref, flag, "faint")
+    keep = np.ones(400, bool)
+    keep[::3] = False
+    sub = _gpu(g.means[:, keep], g.log_scales[:, keep], g.quats[:, keep], g.opacity_logits[keep], light)
+    np.testing.assert_allclose(got[keep], sub, rtol=2e-7, atol=0)   # other tree, other product order
