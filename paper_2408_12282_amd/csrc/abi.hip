@@ -538,6 +538,14 @@ sssgs_status sssgs_render_backward(const sssgs_gaussians *g, const sssgs_camera 
   // BF16 width-64 network: shading backward and weight gradients as two kernels
   const bool split = net == 2 && width == 64 && ip == 64;
   int parts = 0;
+  // the split shading backward clears the compositing accumulators as side
+  // work when that is at most 16 float4 stores per thread
+  const size_t gacc4 = (size_t)g->n * L.GS / 4;
+  const bool fused_zero = split && gacc4 <= (size_t)L.T * 4 * 64 * 16;
+  if (fused_zero) {
+    sa.zero_buf = at<float4>(ws, L.gacc);
+    sa.zero_count4 = gacc4;
+  }
   if (split) {
     __bf16 *rx = at<__bf16>(ws, L.rec_x), *ro = at<__bf16>(ws, L.rec_o);
     {
@@ -565,7 +573,7 @@ sssgs_status sssgs_render_backward(const sssgs_gaussians *g, const sssgs_camera 
                            opt->accumulate_grads, st);
   }
   // 2. compositing backward into the per-Gaussian accumulators
-  launch_zero_f32(at<float>(ws, L.gacc), (size_t)(g->n) * L.GS, st);
+  if (!fused_zero) launch_zero_f32(at<float>(ws, L.gacc), (size_t)(g->n) * L.GS, st);
   {
     Scope sc(kStCompositeBwd, st);
     composite_bwd(L.C, L, ws, W, H, st);

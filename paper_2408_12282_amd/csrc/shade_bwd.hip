@@ -600,6 +600,12 @@ __global__ __launch_bounds__(64, 2) void shade_bwd_split_kernel(ShadeArgs A, __b
   const Op *__restrict__ wops = reinterpret_cast<const Op *>(A.wops);
   const Op *__restrict__ tops = reinterpret_cast<const Op *>(A.tops);
   const size_t rrow = (size_t)strip * 64 + lane;
+  // clear the compositing backward's per-Gaussian accumulators on the side
+  // (stores only; they overlap with this kernel's arithmetic)
+  if (A.zero_buf) {
+    const size_t nth = (size_t)gridDim.x * 64;
+    for (size_t k = rrow; k < A.zero_count4; k += nth) A.zero_buf[k] = make_float4(0.f, 0.f, 0.f, 0.f);
+  }
   // ---- A: network input row (LDS and record)
   {
     float gb[C], T, gL[3];

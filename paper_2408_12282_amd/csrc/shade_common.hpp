@@ -21,6 +21,8 @@ struct ShadeArgs {
   float *dT;             // [H][W] out
   float *mlp_partials;   // [gridDim.x][nparams] out
   int nparams;
+  float4 *zero_buf;      // or null: cleared by the split shading backward (the
+  size_t zero_count4;    // compositing backward's accumulators, in float4)
 };
 
 // Point lights of one shading pass (image-based lighting by a sum over light
