@@ -700,7 +700,7 @@ sssgs_status sssgs_gaussian_mlp_backward(const sssgs_gaussians *g, const sssgs_c
 
 namespace {
 struct VisLayout {
-  size_t rec, gbox, scene, ka, va, kb, vb, hist, part, left, right, rlo, rhi, bbox, nbox, nrec, status, total;
+  size_t rec, gbox, scene, ka, va, kb, vb, hist, part, left, right, rlo, rhi, sbox, bbox, nbox, nrec, status, total;
 };
 VisLayout vis_layout(int32_t n) {
   VisLayout L;
@@ -728,6 +728,7 @@ VisLayout vis_layout(int32_t n) {
   L.right = take(nn * 4);
   L.rlo = take(nn * 4);
   L.rhi = take(nn * 4);
+  L.sbox = take(nn * 6 * 4);
   L.bbox = take((nn + 255) / 256 * 6 * 4);
   L.nbox = take(nn * 6 * 4);
   L.nrec = take(nn * 16 * 4);
@@ -758,6 +759,7 @@ sssgs_status sssgs_trace_visibility(const sssgs_gaussians *g, const sssgs_light 
   a.scene = at<uint32_t>(ws, L.scene);
   a.left = at<int>(ws, L.left); a.right = at<int>(ws, L.right);
   a.range_lo = at<int>(ws, L.rlo); a.range_hi = at<int>(ws, L.rhi);
+  a.sbox = at<float>(ws, L.sbox);
   a.bbox = at<float>(ws, L.bbox);
   a.nbox = at<float>(ws, L.nbox);
   a.nrec = at<float>(ws, L.nrec);

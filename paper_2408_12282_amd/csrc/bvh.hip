@@ -30,7 +30,8 @@
 //   vis_pack    per internal node one 64-byte record: both children and
 //               both child boxes (one cache line per visited node).
 //   vis_trace   one thread per Gaussian in Morton order (coherent rays), a
-//               per-lane stack in LDS, children tested at their parent.
+//               per-lane stack in LDS, children tested at their parent; a
+//               short stack first, the rare deeper rays again with a deep one.
 // The leaf test is FP64 (the densest point is a small difference of large
 // terms for a distant, thin Gaussian); boxes and the slab test are FP32 with
 // the boxes widened outward.
@@ -40,7 +41,8 @@ namespace sssgs {
 
 namespace {
 
-constexpr int kVisStack = 64;  // tree depth <= 30 code bits + 32 position bits
+constexpr int kVisStack = 64;       // tree depth <= 30 code bits + 32 position bits
+constexpr int kVisShortStack = 32;  // first pass; deeper rays are traced again
 constexpr double kFloor = 1e-4;
 
 __device__ __forceinline__ uint32_t ordered(float f) {
@@ -57,9 +59,7 @@ __global__ void vis_init_kernel(uint32_t *scene, uint32_t *status) {
   else if (threadIdx.x == 6) status[0] = 0u;
 }
 
-__global__ __launch_bounds__(256) void vis_prep_kernel(VisArgs A) {
-  const int i = blockIdx.x * 256 + threadIdx.x;
-  if (i >= A.n) return;
+__device__ __forceinline__ void prep_one(const VisArgs &A, int i) {
   const int n = A.n;
   double q[4], ql = 0.0;
   for (int k = 0; k < 4; k++) {
@@ -100,11 +100,31 @@ __global__ __launch_bounds__(256) void vis_prep_kernel(VisArgs A) {
       box[3 + m] = -__int_as_float(0x7F800000);
     }
   }
+}
+
+// Per-Gaussian records and boxes; the box of all centres as a min / max over
+// each wave first and then one atomic per wave and bound (atomics of every
+// thread on the same six words serialise in the L2).
+__global__ __launch_bounds__(256) void vis_prep_kernel(VisArgs A) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  const bool live = i < A.n;
+  if (live) prep_one(A, i);
+  uint32_t lo[3], hi[3];
   for (int m = 0; m < 3; m++) {
-    const float c = A.means[m * n + i];
-    atomicMin(A.scene + m, ordered(c));
-    atomicMax(A.scene + 3 + m, ordered(c));
+    const uint32_t key = live ? ordered(A.means[m * A.n + i]) : 0u;
+    lo[m] = live ? key : 0xFFFFFFFFu;
+    hi[m] = key;
   }
+  for (int off = 32; off >= 1; off >>= 1)
+    for (int m = 0; m < 3; m++) {
+      lo[m] = min(lo[m], (uint32_t)__shfl_xor((int)lo[m], off));
+      hi[m] = max(hi[m], (uint32_t)__shfl_xor((int)hi[m], off));
+    }
+  if ((threadIdx.x & 63) == 0 && blockIdx.x * 256 + (int)(threadIdx.x & ~63) < A.n)
+    for (int m = 0; m < 3; m++) {
+      atomicMin(A.scene + m, lo[m]);
+      atomicMax(A.scene + 3 + m, hi[m]);
+    }
 }
 
 __device__ __forceinline__ uint32_t spread10(uint32_t v) {  // 10 bits -> every third bit
@@ -188,13 +208,17 @@ __device__ __forceinline__ void box_add(float *b, const float *g) {
 
 constexpr int kBoxBlock = 256;
 
-// Union of the boxes of each block of 256 consecutive sorted leaves.
+// The leaf boxes gathered into sorted order, and the union of the boxes of
+// each block of 256 consecutive sorted leaves.
 __global__ __launch_bounds__(kBoxBlock) void vis_block_box_kernel(VisArgs A) {
   __shared__ float red[6][kBoxBlock];
   const int t = threadIdx.x, k = blockIdx.x * kBoxBlock + t;
   float b[6];
   box_empty(b);
-  if (k < A.n) box_add(b, A.gbox + (size_t)A.order[k] * 6);
+  if (k < A.n) {
+    box_add(b, A.gbox + (size_t)A.order[k] * 6);
+    for (int m = 0; m < 6; m++) A.sbox[(size_t)k * 6 + m] = b[m];
+  }
   for (int m = 0; m < 6; m++) red[m][t] = b[m];
   __syncthreads();
   for (int w = kBoxBlock / 2; w > 0; w >>= 1) {
@@ -215,13 +239,18 @@ __global__ __launch_bounds__(256) void vis_node_box_kernel(VisArgs A) {
   const int lo = A.range_lo[i], hi = A.range_hi[i];
   float b[6];
   box_empty(b);
+  const float *S = A.sbox;  // contiguous in the leaf range
   if (hi - lo < 2 * kBoxBlock) {
-    for (int k = lo; k <= hi; k++) box_add(b, A.gbox + (size_t)A.order[k] * 6);
+#pragma unroll 4
+    for (int k = lo; k <= hi; k++) box_add(b, S + (size_t)k * 6);
   } else {
     const int b0 = lo / kBoxBlock, b1 = hi / kBoxBlock;
-    for (int k = lo; k < (b0 + 1) * kBoxBlock; k++) box_add(b, A.gbox + (size_t)A.order[k] * 6);
+#pragma unroll 4
+    for (int k = lo; k < (b0 + 1) * kBoxBlock; k++) box_add(b, S + (size_t)k * 6);
+#pragma unroll 4
     for (int bb = b0 + 1; bb < b1; bb++) box_add(b, A.bbox + (size_t)bb * 6);
-    for (int k = b1 * kBoxBlock; k <= hi; k++) box_add(b, A.gbox + (size_t)A.order[k] * 6);
+#pragma unroll 4
+    for (int k = b1 * kBoxBlock; k <= hi; k++) box_add(b, S + (size_t)k * 6);
   }
   for (int m = 0; m < 6; m++) A.nbox[(size_t)i * 6 + m] = b[m];
 }
@@ -236,7 +265,7 @@ __global__ __launch_bounds__(256) void vis_pack_kernel(VisArgs A) {
   r[1] = __int_as_float(ch[1]);
   r[2] = r[3] = 0.f;
   for (int c = 0; c < 2; c++) {
-    const float *g = ch[c] < 0 ? A.gbox + (size_t)A.order[~ch[c]] * 6 : A.nbox + (size_t)ch[c] * 6;
+    const float *g = ch[c] < 0 ? A.sbox + (size_t)(~ch[c]) * 6 : A.nbox + (size_t)ch[c] * 6;
     for (int m = 0; m < 6; m++) r[4 + 6 * c + m] = g[m];
   }
 }
@@ -275,13 +304,21 @@ __device__ __forceinline__ double occlusion(const double *rec, const double *o, 
   return alpha >= 1.0 / 255.0 ? 1.0 - alpha : 1.0;
 }
 
+// One ray per thread with an LDS stack of S entries per lane.  The first pass
+// (S = kVisShortStack, half the LDS, so the registers and not the LDS bound
+// the occupancy) marks a ray whose stack would overflow with a NaN and drops
+// it; the second (RETRY, S = kVisStack) traces only the rays so marked.  The
+// visiting order does not depend on S, so every ray's product is the one a
+// single deep-stack pass computes, bit for bit.
+template <int S, bool RETRY>
 __global__ __launch_bounds__(64) void vis_trace_kernel(VisArgs A) {
-  __shared__ int stack[kVisStack][64];
+  __shared__ int stack[S][64];
   const int lane = threadIdx.x;
   const int k = blockIdx.x * 64 + lane;
   if (k >= A.n) return;
   const int n = A.n;
   const int i = (int)A.order[k];
+  if (RETRY && !__builtin_isnan(A.vis[i])) return;
   double o[3], d[3], len = 0.0;
   for (int m = 0; m < 3; m++) {
     o[m] = A.means[m * n + i];
@@ -305,7 +342,7 @@ __global__ __launch_bounds__(64) void vis_trace_kernel(VisArgs A) {
     if (slab(rb, of, inv, tmaxf)) stack[sp++][lane] = 0;
   }
   bool overflow = false;
-  while (sp > 0 && T >= kFloor) {
+  while (sp > 0 && T >= kFloor && !overflow) {
     const int node = stack[--sp][lane];
     const float4 *nr = reinterpret_cast<const float4 *>(A.nrec + (size_t)node * 16);
     const float4 q0 = nr[0], q1 = nr[1], q2 = nr[2], q3 = nr[3];
@@ -318,7 +355,7 @@ __global__ __launch_bounds__(64) void vis_trace_kernel(VisArgs A) {
       if (cn < 0) {
         const int j = (int)A.order[~cn];
         if (j != i) T *= occlusion(A.rec + (size_t)j * 16, o, d, len);
-      } else if (sp < kVisStack) {
+      } else if (sp < S) {
         stack[sp++][lane] = cn;
       } else {
         overflow = true;
@@ -328,7 +365,7 @@ __global__ __launch_bounds__(64) void vis_trace_kernel(VisArgs A) {
   float v = T < kFloor ? 0.f : (float)T;
   if (overflow) {
     v = __int_as_float(0x7FC00000);  // NaN: the stack bound was exceeded
-    atomicOr(A.status, 1u);
+    if (RETRY) atomicOr(A.status, 1u);
   }
   A.vis[i] = v;
 }
@@ -361,7 +398,8 @@ void launch_visibility(const VisArgs &a0, uint32_t *keys_a, uint32_t *vals_a, ui
     vis_node_box_kernel<<<gi, 256, 0, st>>>(a);
     vis_pack_kernel<<<gi, 256, 0, st>>>(a);
   }
-  vis_trace_kernel<<<(n + 63) / 64, 64, 0, st>>>(a);
+  vis_trace_kernel<kVisShortStack, false><<<(n + 63) / 64, 64, 0, st>>>(a);
+  vis_trace_kernel<kVisStack, true><<<(n + 63) / 64, 64, 0, st>>>(a);
 }
 
 }  // namespace sssgs

@@ -124,6 +124,7 @@ struct VisArgs {
   const uint32_t *codes, *order;  // sorted Morton codes and Gaussian indices (set by the launcher)
   int *left, *right;              // [n - 1] children (>= 0 internal node, < 0 leaf ~position)
   int *range_lo, *range_hi;       // [n - 1] sorted-leaf range of each internal node
+  float *sbox;                    // [n][6] leaf boxes in sorted (Morton) order
   float *bbox;                    // [ceil(n / 256)][6] unions of 256-leaf blocks
   float *nbox;                    // [n - 1][6] internal node boxes
   float *nrec;                    // [n - 1][16] node records: children, both child boxes

@@ -25,6 +25,32 @@ def _gpu(means, log_scales, quats, logits, light_pos):
     return v.cpu().numpy()
 
 
+def deep_tree_means(m=64, seed=41):
+    """[3, 60 + m] centres whose 30-bit Morton codes give a comb-shaped tree:
+    pair k (k = 0..29) has the top k code bits set and the next one clear, so
+    every level splits one two-leaf subtree off the rest; the last m centres
+    share the all-ones code (a balanced subtree over their positions).  With
+    every box hit, a ray's stack holds one deferred subtree per comb level
+    plus the levels of the balanced part: 36 entries for m = 64."""
+    rng = np.random.default_rng(seed)
+    unit = 1.0 / 256.0
+
+    def cell(code):
+        g = [0, 0, 0]
+        for j in range(10):
+            for a in range(3):
+                if code >> (29 - 3 * j - a) & 1:
+                    g[a] |= 1 << (9 - j)
+        return g
+
+    pts = []
+    for k in range(30):
+        g = cell(((1 << k) - 1) << (30 - k))
+        pts += [[(g[a] + rng.uniform(0.45, 0.55)) * unit for a in range(3)] for _ in range(2)]
+    pts += [[(1023 + rng.uniform(0.1, 0.9)) * unit for a in range(3)] for _ in range(m)]
+    return np.array(pts, np.float64).T
+
+
 def _f32(g):
     return (g.means.astype(np.float32), g.log_scales.astype(np.float32), g.quats.astype(np.float32),
             g.opacity_logits.astype(np.float32))
@@ -129,6 +155,26 @@ def test_traced_visibility_feeds_the_per_gaussian_network():
     print(f"  chain features max err {float(err[:, ok].max()):.2e}", flush=True)
     assert float(err[:, ok].max()) < 1e-5
     np.testing.assert_array_equal(got[6], vis.cpu().numpy())
+
+
+def test_deep_tree_stack_retry():
+    """A tree whose rays need more than the first pass's 32 stack entries
+    (deep_tree_means; every Gaussian large and faint, so every box is hit and
+    no ray reaches the transmittance floor): every ray is traced again with
+    the deep stack, and the result still matches the oracle."""
+    means = deep_tree_means()
+    n = means.shape[1]
+    rng = np.random.default_rng(43)
+    log_scales = np.full((3, n), 3.0)                     # s = 20: each box covers the whole scene
+    quats = rng.normal(size=(4, n))
+    logits = np.full(n, math.log(0.0045 / 0.9955))        # alpha ~ 0.0043 > 1/255 at every occluder
+    light = [2.0, 2.0, 2.0]                               # inside the scene: short rays, few flagged
+    args = [a.astype(np.float32) for a in (means, log_scales, quats, logits)]
+    print(f"[gpu] visibility deep tree n={n}", flush=True)
+    got = _gpu(*args, light)
+    ref, flag = V.visibility(*args, light, margins=True)
+    assert (ref < 0.99).mean() > 0.5 and ref.min() > 1e-3   # occluded rays, none at the floor
+    _compare(got, ref, flag, "deep tree")
 
 
 def test_gaussians_that_cannot_occlude():
