@@ -700,7 +700,7 @@ sssgs_status sssgs_gaussian_mlp_backward(const sssgs_gaussians *g, const sssgs_c
 
 namespace {
 struct VisLayout {
-  size_t rec, gbox, scene, ka, va, kb, vb, hist, part, left, right, rlo, rhi, sbox, bbox, nbox, nrec, status, total;
+  size_t rec, gbox, scene, bpart, ka, va, kb, vb, hist, part, left, right, rlo, rhi, sbox, bbox, nbox, nrec, status, total;
 };
 VisLayout vis_layout(int32_t n) {
   VisLayout L;
@@ -714,6 +714,7 @@ VisLayout vis_layout(int32_t n) {
   L.rec = take(nn * 16 * 8);
   L.gbox = take(nn * 6 * 4);
   L.scene = take(6 * 4);
+  L.bpart = take((nn + 255) / 256 * 6 * 4);
   L.ka = take(nn * 4);
   L.va = take(nn * 4);
   L.kb = take(nn * 4);
@@ -757,6 +758,7 @@ sssgs_status sssgs_trace_visibility(const sssgs_gaussians *g, const sssgs_light 
   a.rec = at<double>(ws, L.rec);
   a.gbox = at<float>(ws, L.gbox);
   a.scene = at<uint32_t>(ws, L.scene);
+  a.bpart = at<uint32_t>(ws, L.bpart);
   a.left = at<int>(ws, L.left); a.right = at<int>(ws, L.right);
   a.range_lo = at<int>(ws, L.rlo); a.range_hi = at<int>(ws, L.rhi);
   a.sbox = at<float>(ws, L.sbox);

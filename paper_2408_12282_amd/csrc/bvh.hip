@@ -16,7 +16,8 @@
 //   vis_prep    per Gaussian an FP64 record (whitening matrix, opacity,
 //               centre) and the box of the ellipsoid D2 <= 2 ln(255 opacity)
 //               outside of which alpha < 1/255 (so the box test is exact,
-//               not a 3-sigma heuristic); the box of all centres.
+//               not a 3-sigma heuristic); per block the box of its
+//               centres, then (vis_scene) the box of all centres.
 //   vis_morton  30-bit Morton code of each centre in that box.
 //   radix sort  of the codes (stable: index order among equal codes).
 //   vis_tree    binary radix tree over the sorted codes, one thread per
@@ -53,11 +54,6 @@ __device__ __forceinline__ float unordered(uint32_t k) {
   return __uint_as_float((k & 0x80000000u) ? (k & 0x7FFFFFFFu) : ~k);
 }
 
-__global__ void vis_init_kernel(uint32_t *scene, uint32_t *status) {
-  if (threadIdx.x < 3) scene[threadIdx.x] = 0xFFFFFFFFu;      // min keys
-  else if (threadIdx.x < 6) scene[threadIdx.x] = 0u;          // max keys
-  else if (threadIdx.x == 6) status[0] = 0u;
-}
 
 __device__ __forceinline__ void prep_one(const VisArgs &A, int i) {
   const int n = A.n;
@@ -102,29 +98,64 @@ __device__ __forceinline__ void prep_one(const VisArgs &A, int i) {
   }
 }
 
-// Per-Gaussian records and boxes; the box of all centres as a min / max over
-// each wave first and then one atomic per wave and bound (atomics of every
-// thread on the same six words serialise in the L2).
+// Min (k < 3) or max (k >= 3) of six ordered keys over the 256 threads of a
+// block; the result in red[4] after the call.
+__device__ __forceinline__ void block_minmax6(uint32_t key[6], uint32_t (*red)[6]) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1)
+#pragma unroll
+    for (int k = 0; k < 6; k++) {
+      const uint32_t o = (uint32_t)__shfl_xor((int)key[k], off);
+      key[k] = k < 3 ? min(key[k], o) : max(key[k], o);
+    }
+  const int wave = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0)
+#pragma unroll
+    for (int k = 0; k < 6; k++) red[wave][k] = key[k];
+  __syncthreads();
+  if (threadIdx.x < 6) {
+    const int k = threadIdx.x;
+    uint32_t r = red[0][k];
+    for (int w = 1; w < 4; w++) r = k < 3 ? min(r, red[w][k]) : max(r, red[w][k]);
+    red[4][k] = r;
+  }
+  __syncthreads();
+}
+
+// Per-Gaussian records and boxes, and each block's min / max of the centres
+// (ordered keys; reduced over the blocks by vis_scene_kernel, not by global
+// atomics: on this chip atomics of all blocks on the same six words serialise
+// outside the per-XCD L2s).
 __global__ __launch_bounds__(256) void vis_prep_kernel(VisArgs A) {
+  __shared__ uint32_t red[5][6];
   const int i = blockIdx.x * 256 + threadIdx.x;
   const bool live = i < A.n;
   if (live) prep_one(A, i);
-  uint32_t lo[3], hi[3];
+  uint32_t key[6];
+#pragma unroll
   for (int m = 0; m < 3; m++) {
-    const uint32_t key = live ? ordered(A.means[m * A.n + i]) : 0u;
-    lo[m] = live ? key : 0xFFFFFFFFu;
-    hi[m] = key;
+    const uint32_t k = live ? ordered(A.means[m * A.n + i]) : 0u;
+    key[m] = live ? k : 0xFFFFFFFFu;
+    key[3 + m] = k;
   }
-  for (int off = 32; off >= 1; off >>= 1)
-    for (int m = 0; m < 3; m++) {
-      lo[m] = min(lo[m], (uint32_t)__shfl_xor((int)lo[m], off));
-      hi[m] = max(hi[m], (uint32_t)__shfl_xor((int)hi[m], off));
+  block_minmax6(key, red);
+  if (threadIdx.x < 6) A.bpart[(size_t)blockIdx.x * 6 + threadIdx.x] = red[4][threadIdx.x];
+}
+
+// The box of all centres from the per-block keys (one block); clears the
+// status word of this call.
+__global__ __launch_bounds__(256) void vis_scene_kernel(VisArgs A, int nblocks) {
+  __shared__ uint32_t red[5][6];
+  uint32_t key[6] = {0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu, 0u, 0u, 0u};
+  for (int b = threadIdx.x; b < nblocks; b += 256)
+#pragma unroll
+    for (int k = 0; k < 6; k++) {
+      const uint32_t v = A.bpart[(size_t)b * 6 + k];
+      key[k] = k < 3 ? min(key[k], v) : max(key[k], v);
     }
-  if ((threadIdx.x & 63) == 0 && blockIdx.x * 256 + (int)(threadIdx.x & ~63) < A.n)
-    for (int m = 0; m < 3; m++) {
-      atomicMin(A.scene + m, lo[m]);
-      atomicMax(A.scene + 3 + m, hi[m]);
-    }
+  block_minmax6(key, red);
+  if (threadIdx.x < 6) A.scene[threadIdx.x] = red[4][threadIdx.x];
+  if (threadIdx.x == 6) A.status[0] = 0u;
 }
 
 __device__ __forceinline__ uint32_t spread10(uint32_t v) {  // 10 bits -> every third bit
@@ -378,8 +409,8 @@ void launch_visibility(const VisArgs &a0, uint32_t *keys_a, uint32_t *vals_a, ui
   const int n = a.n;
   if (n <= 0) return;
   const int g256 = (n + 255) / 256;
-  vis_init_kernel<<<1, 64, 0, st>>>(a.scene, a.status);
   vis_prep_kernel<<<g256, 256, 0, st>>>(a);
+  vis_scene_kernel<<<1, 256, 0, st>>>(a, g256);
   vis_morton_kernel<<<g256, 256, 0, st>>>(a, keys_a, vals_a);
   const uint32_t *kin = keys_a, *vin = vals_a;
   for (int pass = 0; pass < 4; pass++) {

@@ -121,6 +121,7 @@ struct VisArgs {
   double *rec;                    // [n][16]: whitening matrix (9), opacity, centre (3)
   float *gbox;                    // [n][6]: box lo xyz, hi xyz of the alpha >= 1/255 ellipsoid
   uint32_t *scene;                // [6]: ordered-integer min / max of the centres
+  uint32_t *bpart;                // [ceil(n / 256)][6]: the same per block of 256 Gaussians
   const uint32_t *codes, *order;  // sorted Morton codes and Gaussian indices (set by the launcher)
   int *left, *right;              // [n - 1] children (>= 0 internal node, < 0 leaf ~position)
   int *range_lo, *range_hi;       // [n - 1] sorted-leaf range of each internal node
