@@ -700,7 +700,7 @@ sssgs_status sssgs_gaussian_mlp_backward(const sssgs_gaussians *g, const sssgs_c
 
 namespace {
 struct VisLayout {
-  size_t rec, gbox, scene, bpart, ka, va, kb, vb, hist, part, left, right, rlo, rhi, sbox, bbox, nbox, nrec, status, total;
+  size_t rec, scene, bpart, ka, va, kb, vb, hist, part, left, right, rlo, rhi, sbox, bbox, nbox, nrec, status, total;
 };
 VisLayout vis_layout(int32_t n) {
   VisLayout L;
@@ -712,7 +712,6 @@ VisLayout vis_layout(int32_t n) {
     return o;
   };
   L.rec = take(nn * 16 * 8);
-  L.gbox = take(nn * 6 * 4);
   L.scene = take(6 * 4);
   L.bpart = take((nn + 255) / 256 * 6 * 4);
   L.ka = take(nn * 4);
@@ -756,7 +755,6 @@ sssgs_status sssgs_trace_visibility(const sssgs_gaussians *g, const sssgs_light 
   a.means = g->means; a.log_scales = g->log_scales; a.quats = g->quats; a.logits = g->opacity_logits;
   for (int k = 0; k < 3; k++) a.light[k] = light->pos[k];
   a.rec = at<double>(ws, L.rec);
-  a.gbox = at<float>(ws, L.gbox);
   a.scene = at<uint32_t>(ws, L.scene);
   a.bpart = at<uint32_t>(ws, L.bpart);
   a.left = at<int>(ws, L.left); a.right = at<int>(ws, L.right);

@@ -13,17 +13,19 @@
 // needs no depth order and a ray stops when it crosses the floor.
 //
 // The hierarchy is a linear BVH built on the GPU each call:
-//   vis_prep    per Gaussian an FP64 record (whitening matrix, opacity,
-//               centre) and the box of the ellipsoid D2 <= 2 ln(255 opacity)
-//               outside of which alpha < 1/255 (so the box test is exact,
-//               not a 3-sigma heuristic); per block the box of its
-//               centres, then (vis_scene) the box of all centres.
+//   vis_prep    per block the box of its centres, then (vis_scene) the
+//               box of all centres.
 //   vis_morton  30-bit Morton code of each centre in that box.
 //   radix sort  of the codes (stable: index order among equal codes).
 //   vis_tree    binary radix tree over the sorted codes, one thread per
 //               internal node (prefix lengths of equal codes continue with
 //               the bits of the sorted positions, so every split is unique).
-//   vis_block_box, vis_node_box
+//   vis_block_box
+//               per sorted leaf an FP64 record (whitening matrix, opacity,
+//               centre) and the box of the ellipsoid D2 <= 2 ln(255 opacity)
+//               outside of which alpha < 1/255 (so the box test is exact,
+//               not a 3-sigma heuristic); unions of 256-leaf blocks.
+//   vis_node_box
 //               boxes without inter-thread synchronisation: every internal
 //               node covers a contiguous range of sorted leaves, so its box
 //               is the union over that range (short ranges leaf by leaf,
@@ -55,37 +57,45 @@ __device__ __forceinline__ float unordered(uint32_t k) {
 }
 
 
-__device__ __forceinline__ void prep_one(const VisArgs &A, int i) {
+// Record and box of Gaussian i, stored at its sorted leaf position k.
+__device__ __forceinline__ void leaf_record(const VisArgs &A, int i, int k, float *box) {
   const int n = A.n;
   double q[4], ql = 0.0;
-  for (int k = 0; k < 4; k++) {
-    q[k] = A.quats[k * n + i];
-    ql += q[k] * q[k];
+  for (int a = 0; a < 4; a++) {
+    q[a] = A.quats[a * n + i];
+    ql += q[a] * q[a];
   }
   ql = sqrt(ql);
-  for (int k = 0; k < 4; k++) q[k] /= ql;
+  for (int a = 0; a < 4; a++) q[a] /= ql;
   const double w = q[0], x = q[1], y = q[2], z = q[3];
   const double R[9] = {1.0 - 2.0 * (y * y + z * z), 2.0 * (x * y - w * z), 2.0 * (x * z + w * y),
                        2.0 * (x * y + w * z), 1.0 - 2.0 * (x * x + z * z), 2.0 * (y * z - w * x),
                        2.0 * (x * z - w * y), 2.0 * (y * z + w * x), 1.0 - 2.0 * (x * x + y * y)};
   double s[3], mu[3];
-  for (int k = 0; k < 3; k++) {
-    s[k] = exp((double)A.log_scales[k * n + i]);
-    mu[k] = A.means[k * n + i];
+  for (int a = 0; a < 3; a++) {
+    s[a] = exp((double)A.log_scales[a * n + i]);
+    mu[a] = A.means[a * n + i];
   }
   const double op = 1.0 / (1.0 + exp(-(double)A.logits[i]));
-  double *rec = A.rec + (size_t)i * 16;
-  // whitening S^-1 R^T: row k = column k of R over s_k
-  for (int k = 0; k < 3; k++)
-    for (int m = 0; m < 3; m++) rec[3 * k + m] = R[3 * m + k] / s[k];
+  double rec[16];
+  // whitening S^-1 R^T: row a = column a of R over s_a
+#pragma unroll
+  for (int a = 0; a < 3; a++)
+#pragma unroll
+    for (int m = 0; m < 3; m++) rec[3 * a + m] = R[3 * m + a] / s[a];
   rec[9] = op;
-  for (int k = 0; k < 3; k++) rec[10 + k] = mu[k];
-  float *box = A.gbox + (size_t)i * 6;
+#pragma unroll
+  for (int a = 0; a < 3; a++) rec[10 + a] = mu[a];
+  rec[13] = rec[14] = rec[15] = 0.0;
+  // the whole 128-byte record in eight 16-byte stores
+  double2 *out = reinterpret_cast<double2 *>(A.rec + (size_t)k * 16);
+#pragma unroll
+  for (int q = 0; q < 8; q++) out[q] = make_double2(rec[2 * q], rec[2 * q + 1]);
   if (255.0 * op > 1.0) {
     const double r = sqrt(2.0 * log(255.0 * op));
     for (int m = 0; m < 3; m++) {
       double e2 = 0.0;
-      for (int k = 0; k < 3; k++) e2 += R[3 * m + k] * R[3 * m + k] * s[k] * s[k];
+      for (int a = 0; a < 3; a++) e2 += R[3 * m + a] * R[3 * m + a] * s[a] * s[a];
       const double e = r * sqrt(e2), pad = 1e-6 * (1.0 + fabs(mu[m]) + e);
       box[m] = (float)(mu[m] - e - pad);
       box[3 + m] = (float)(mu[m] + e + pad);
@@ -122,15 +132,13 @@ __device__ __forceinline__ void block_minmax6(uint32_t key[6], uint32_t (*red)[6
   __syncthreads();
 }
 
-// Per-Gaussian records and boxes, and each block's min / max of the centres
-// (ordered keys; reduced over the blocks by vis_scene_kernel, not by global
+// Each block's min / max of the centres (ordered keys; reduced over the blocks by vis_scene_kernel, not by global
 // atomics: on this chip atomics of all blocks on the same six words serialise
 // outside the per-XCD L2s).
 __global__ __launch_bounds__(256) void vis_prep_kernel(VisArgs A) {
   __shared__ uint32_t red[5][6];
   const int i = blockIdx.x * 256 + threadIdx.x;
   const bool live = i < A.n;
-  if (live) prep_one(A, i);
   uint32_t key[6];
 #pragma unroll
   for (int m = 0; m < 3; m++) {
@@ -239,16 +247,19 @@ __device__ __forceinline__ void box_add(float *b, const float *g) {
 
 constexpr int kBoxBlock = 256;
 
-// The leaf boxes gathered into sorted order, and the union of the boxes of
-// each block of 256 consecutive sorted leaves.
+// The leaves' records and boxes in sorted order (a leaf is then found by its
+// position, with no gather through the permutation), and the union of the
+// boxes of each block of 256 consecutive sorted leaves.
 __global__ __launch_bounds__(kBoxBlock) void vis_block_box_kernel(VisArgs A) {
   __shared__ float red[6][kBoxBlock];
   const int t = threadIdx.x, k = blockIdx.x * kBoxBlock + t;
   float b[6];
   box_empty(b);
   if (k < A.n) {
-    box_add(b, A.gbox + (size_t)A.order[k] * 6);
-    for (int m = 0; m < 6; m++) A.sbox[(size_t)k * 6 + m] = b[m];
+    float g[6];
+    leaf_record(A, (int)A.order[k], k, g);
+    box_add(b, g);
+    for (int m = 0; m < 6; m++) A.sbox[(size_t)k * 6 + m] = g[m];
   }
   for (int m = 0; m < 6; m++) red[m][t] = b[m];
   __syncthreads();
@@ -290,15 +301,21 @@ __global__ __launch_bounds__(256) void vis_node_box_kernel(VisArgs A) {
 __global__ __launch_bounds__(256) void vis_pack_kernel(VisArgs A) {
   const int i = blockIdx.x * 256 + threadIdx.x;
   if (i >= A.n - 1) return;
-  float *r = A.nrec + (size_t)i * 16;
   const int ch[2] = {A.left[i], A.right[i]};
+  float r[16];
   r[0] = __int_as_float(ch[0]);
   r[1] = __int_as_float(ch[1]);
   r[2] = r[3] = 0.f;
+#pragma unroll
   for (int c = 0; c < 2; c++) {
     const float *g = ch[c] < 0 ? A.sbox + (size_t)(~ch[c]) * 6 : A.nbox + (size_t)ch[c] * 6;
+#pragma unroll
     for (int m = 0; m < 6; m++) r[4 + 6 * c + m] = g[m];
   }
+  // the whole 64-byte record in four 16-byte stores
+  float4 *out = reinterpret_cast<float4 *>(A.nrec + (size_t)i * 16);
+#pragma unroll
+  for (int q = 0; q < 4; q++) out[q] = make_float4(r[4 * q], r[4 * q + 1], r[4 * q + 2], r[4 * q + 3]);
 }
 
 // Does the segment o + t d, 0 <= t <= tmax, meet the box (lo, hi)?  The
@@ -342,7 +359,7 @@ __device__ __forceinline__ double occlusion(const double *rec, const double *o, 
 // visiting order does not depend on S, so every ray's product is the one a
 // single deep-stack pass computes, bit for bit.
 template <int S, bool RETRY>
-__global__ __launch_bounds__(64) void vis_trace_kernel(VisArgs A) {
+__global__ __launch_bounds__(64, 5) void vis_trace_kernel(VisArgs A) {
   __shared__ int stack[S][64];
   const int lane = threadIdx.x;
   const int k = blockIdx.x * 64 + lane;
@@ -384,8 +401,7 @@ __global__ __launch_bounds__(64) void vis_trace_kernel(VisArgs A) {
       if (!slab(bx[c], of, inv, tmaxf)) continue;
       const int cn = ch[c];
       if (cn < 0) {
-        const int j = (int)A.order[~cn];
-        if (j != i) T *= occlusion(A.rec + (size_t)j * 16, o, d, len);
+        if (~cn != k) T *= occlusion(A.rec + (size_t)(~cn) * 16, o, d, len);
       } else if (sp < S) {
         stack[sp++][lane] = cn;
       } else {

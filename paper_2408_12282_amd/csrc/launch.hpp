@@ -118,14 +118,13 @@ struct VisArgs {
   int n;
   const float *means, *log_scales, *quats, *logits;
   float light[3];
-  double *rec;                    // [n][16]: whitening matrix (9), opacity, centre (3)
-  float *gbox;                    // [n][6]: box lo xyz, hi xyz of the alpha >= 1/255 ellipsoid
+  double *rec;                    // [n][16] per sorted leaf: whitening matrix (9), opacity, centre (3)
   uint32_t *scene;                // [6]: ordered-integer min / max of the centres
   uint32_t *bpart;                // [ceil(n / 256)][6]: the same per block of 256 Gaussians
   const uint32_t *codes, *order;  // sorted Morton codes and Gaussian indices (set by the launcher)
   int *left, *right;              // [n - 1] children (>= 0 internal node, < 0 leaf ~position)
   int *range_lo, *range_hi;       // [n - 1] sorted-leaf range of each internal node
-  float *sbox;                    // [n][6] leaf boxes in sorted (Morton) order
+  float *sbox;                    // [n][6] per sorted leaf: lo xyz, hi xyz of the alpha >= 1/255 ellipsoid
   float *bbox;                    // [ceil(n / 256)][6] unions of 256-leaf blocks
   float *nbox;                    // [n - 1][6] internal node boxes
   float *nrec;                    // [n - 1][16] node records: children, both child boxes
