@@ -1,4 +1,4 @@
-"""Python driver for the FP64 CPU oracle (``sssgs_oracle.c``).
+"""Python front end of the FP64 CPU oracle (``sssgs_oracle.c``).
 
 TEST INFRASTRUCTURE ONLY: used by the tests, the smoke check and the CPU
 baseline of the benchmark.  The product path never imports this module.
