@@ -700,7 +700,7 @@ sssgs_status sssgs_gaussian_mlp_backward(const sssgs_gaussians *g, const sssgs_c
 
 namespace {
 struct VisLayout {
-  size_t rec, scene, bpart, ka, va, kb, vb, hist, part, left, right, rlo, rhi, sbox, bbox, nbox, nrec, status, total;
+  size_t rec, scene, bpart, ka, va, kb, vb, hist, part, left, right, rlo, rhi, sbox, b16, bbox, b4k, nbox, nrec, status, total;
 };
 VisLayout vis_layout(int32_t n) {
   VisLayout L;
@@ -729,7 +729,9 @@ VisLayout vis_layout(int32_t n) {
   L.rlo = take(nn * 4);
   L.rhi = take(nn * 4);
   L.sbox = take(nn * 6 * 4);
+  L.b16 = take((nn + 15) / 16 * 6 * 4);
   L.bbox = take((nn + 255) / 256 * 6 * 4);
+  L.b4k = take((nn + 4095) / 4096 * 6 * 4);
   L.nbox = take(nn * 6 * 4);
   L.nrec = take(nn * 16 * 4);
   L.status = take(4);
@@ -760,7 +762,9 @@ sssgs_status sssgs_trace_visibility(const sssgs_gaussians *g, const sssgs_light 
   a.left = at<int>(ws, L.left); a.right = at<int>(ws, L.right);
   a.range_lo = at<int>(ws, L.rlo); a.range_hi = at<int>(ws, L.rhi);
   a.sbox = at<float>(ws, L.sbox);
+  a.b16 = at<float>(ws, L.b16);
   a.bbox = at<float>(ws, L.bbox);
+  a.b4k = at<float>(ws, L.b4k);
   a.nbox = at<float>(ws, L.nbox);
   a.nrec = at<float>(ws, L.nrec);
   a.status = at<uint32_t>(ws, L.status);

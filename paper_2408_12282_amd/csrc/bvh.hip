@@ -24,12 +24,13 @@
 //               per sorted leaf an FP64 record (whitening matrix, opacity,
 //               centre) and the box of the ellipsoid D2 <= 2 ln(255 opacity)
 //               outside of which alpha < 1/255 (so the box test is exact,
-//               not a 3-sigma heuristic); unions of 256-leaf blocks.
+//               not a 3-sigma heuristic); unions of 16- and 256-leaf
+//               blocks (vis_super_box: of 4096-leaf blocks).
 //   vis_node_box
 //               boxes without inter-thread synchronisation: every internal
 //               node covers a contiguous range of sorted leaves, so its box
-//               is the union over that range (short ranges leaf by leaf,
-//               long ones through unions of 256-leaf blocks).
+//               is the union over that range, taken from unions of aligned
+//               units of 1, 16, 256 and 4096 leaves.
 //   vis_pack    per internal node one 64-byte record: both children and
 //               both child boxes (one cache line per visited node).
 //   vis_trace   one thread per Gaussian in Morton order (coherent rays), a
@@ -261,6 +262,22 @@ __global__ __launch_bounds__(kBoxBlock) void vis_block_box_kernel(VisArgs A) {
     box_add(b, g);
     for (int m = 0; m < 6; m++) A.sbox[(size_t)k * 6 + m] = g[m];
   }
+  // unions of 16 consecutive leaves (aligned groups of 16 lanes)
+  {
+    float u[6];
+#pragma unroll
+    for (int m = 0; m < 6; m++) u[m] = b[m];
+#pragma unroll
+    for (int off = 8; off >= 1; off >>= 1)
+#pragma unroll
+      for (int m = 0; m < 6; m++) {
+        const float o = __shfl_xor(u[m], off);
+        u[m] = m < 3 ? fminf(u[m], o) : fmaxf(u[m], o);
+      }
+    if ((t & 15) == 0 && k < A.n)
+#pragma unroll
+      for (int m = 0; m < 6; m++) A.b16[(size_t)(k >> 4) * 6 + m] = u[m];
+  }
   for (int m = 0; m < 6; m++) red[m][t] = b[m];
   __syncthreads();
   for (int w = kBoxBlock / 2; w > 0; w >>= 1) {
@@ -274,25 +291,43 @@ __global__ __launch_bounds__(kBoxBlock) void vis_block_box_kernel(VisArgs A) {
   if (t < 6) A.bbox[(size_t)blockIdx.x * 6 + t] = red[t][0];
 }
 
-// Box of internal node i: the union over its leaf range.
+// Unions of 4096 consecutive leaves from 16 unions of 256.
+__global__ __launch_bounds__(256) void vis_super_box_kernel(VisArgs A, int nblocks) {
+  const int s = blockIdx.x * 256 + threadIdx.x;
+  if (s * 16 >= nblocks) return;
+  float b[6];
+  box_empty(b);
+  const int e = min(nblocks, (s + 1) * 16);
+  for (int bb = s * 16; bb < e; bb++) box_add(b, A.bbox + (size_t)bb * 6);
+  for (int m = 0; m < 6; m++) A.b4k[(size_t)s * 6 + m] = b[m];
+}
+
+// Box of internal node i: the union over its leaf range [lo, hi], taken
+// greedily as the largest aligned whole unit of 4096, 256, 16 or 1 leaves
+// that starts at the next leaf and ends inside the range (at most 15 units
+// of each size on the way up and on the way down, plus the 4096-leaf units).
 __global__ __launch_bounds__(256) void vis_node_box_kernel(VisArgs A) {
   const int i = blockIdx.x * 256 + threadIdx.x;
   if (i >= A.n - 1) return;
-  const int lo = A.range_lo[i], hi = A.range_hi[i];
+  const int lo = A.range_lo[i], end = A.range_hi[i] + 1;
   float b[6];
   box_empty(b);
-  const float *S = A.sbox;  // contiguous in the leaf range
-  if (hi - lo < 2 * kBoxBlock) {
-#pragma unroll 4
-    for (int k = lo; k <= hi; k++) box_add(b, S + (size_t)k * 6);
-  } else {
-    const int b0 = lo / kBoxBlock, b1 = hi / kBoxBlock;
-#pragma unroll 4
-    for (int k = lo; k < (b0 + 1) * kBoxBlock; k++) box_add(b, S + (size_t)k * 6);
-#pragma unroll 4
-    for (int bb = b0 + 1; bb < b1; bb++) box_add(b, A.bbox + (size_t)bb * 6);
-#pragma unroll 4
-    for (int k = b1 * kBoxBlock; k <= hi; k++) box_add(b, S + (size_t)k * 6);
+  for (int k = lo; k < end;) {
+    const float *u;
+    if ((k & 4095) == 0 && k + 4096 <= end) {
+      u = A.b4k + (size_t)(k >> 12) * 6;
+      k += 4096;
+    } else if ((k & 255) == 0 && k + 256 <= end) {
+      u = A.bbox + (size_t)(k >> 8) * 6;
+      k += 256;
+    } else if ((k & 15) == 0 && k + 16 <= end) {
+      u = A.b16 + (size_t)(k >> 4) * 6;
+      k += 16;
+    } else {
+      u = A.sbox + (size_t)k * 6;
+      k += 1;
+    }
+    box_add(b, u);
   }
   for (int m = 0; m < 6; m++) A.nbox[(size_t)i * 6 + m] = b[m];
 }
@@ -441,7 +476,9 @@ void launch_visibility(const VisArgs &a0, uint32_t *keys_a, uint32_t *vals_a, ui
   if (n >= 2) {
     const int gi = (n - 1 + 255) / 256;
     vis_tree_kernel<<<gi, 256, 0, st>>>(a);
-    vis_block_box_kernel<<<(n + kBoxBlock - 1) / kBoxBlock, kBoxBlock, 0, st>>>(a);
+    const int nblocks = (n + kBoxBlock - 1) / kBoxBlock;
+    vis_block_box_kernel<<<nblocks, kBoxBlock, 0, st>>>(a);
+    vis_super_box_kernel<<<(nblocks + 16 * 256 - 1) / (16 * 256), 256, 0, st>>>(a, nblocks);
     vis_node_box_kernel<<<gi, 256, 0, st>>>(a);
     vis_pack_kernel<<<gi, 256, 0, st>>>(a);
   }

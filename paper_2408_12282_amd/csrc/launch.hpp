@@ -125,7 +125,9 @@ struct VisArgs {
   int *left, *right;              // [n - 1] children (>= 0 internal node, < 0 leaf ~position)
   int *range_lo, *range_hi;       // [n - 1] sorted-leaf range of each internal node
   float *sbox;                    // [n][6] per sorted leaf: lo xyz, hi xyz of the alpha >= 1/255 ellipsoid
+  float *b16;                     // [ceil(n / 16)][6] unions of 16-leaf blocks
   float *bbox;                    // [ceil(n / 256)][6] unions of 256-leaf blocks
+  float *b4k;                     // [ceil(n / 4096)][6] unions of 4096-leaf blocks
   float *nbox;                    // [n - 1][6] internal node boxes
   float *nrec;                    // [n - 1][16] node records: children, both child boxes
   uint32_t *status;               // [1]: bit 0 = a traversal stack overflowed
