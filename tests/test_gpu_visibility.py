@@ -92,6 +92,13 @@ def test_random_scenes(n, grow, seed):
     _compare(got, ref, flag, f"random n={n}")
 
 
+def test_empty_scene():
+    print("[gpu] visibility n=0", flush=True)
+    z = np.zeros((3, 0))
+    got = _gpu(z, z, np.zeros((4, 0)), np.zeros(0), [1.0, 2.0, 3.0])
+    assert got.shape == (0,)
+
+
 def test_coincident_centres_and_determinism():
     """Many Gaussians on a few shared centres (equal Morton codes) and a line
     of them toward the light; two calls agree bit for bit."""
