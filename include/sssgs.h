@@ -126,9 +126,12 @@ typedef struct {
 typedef enum { SSSGS_PREC_FP32 = 0, SSSGS_PREC_BF16 = 1 } sssgs_precision;
 
 typedef struct {
-  int32_t precision;        /* network arithmetic: FP32 on the vector ALUs, or
-                               BF16 operands on the matrix cores with FP32
-                               accumulation.  Everything else is FP32. */
+  int32_t precision;        /* network arithmetic, on the matrix cores with FP32
+                               accumulation either way: FP32 operands, or BF16
+                               weights with each activation entering a forward
+                               product as two BF16 numbers (the value rounded,
+                               then the rounded remainder) and single BF16
+                               upstream gradients.  Everything else is FP32. */
   int32_t accumulate_grads; /* backward: 0 overwrite gradient outputs, 1 add */
   int32_t radiance_features; /* 1: the radiances of Eq. 7 come from a per-Gaussian
                                network (sssgs_gaussian_mlp_forward) passed as the
@@ -140,6 +143,18 @@ typedef struct {
                                no per-pixel network (SSSGS_ERR_UNSUPPORTED /
                                SSSGS_ERR_INVALID_ARG otherwise).  0: per-pixel
                                network or point-light fall-off. */
+  int32_t deterministic;    /* backward: 1 sums each Gaussian's per-tile partial
+                               gradients in a fixed order (one slot per tile of
+                               its rectangle, then a row-major pass), so two
+                               backward calls give bit-identical gradients; 0
+                               adds them with atomics (order-dependent FP32
+                               rounding).  Network weight gradients are summed
+                               in a fixed order either way. */
+  float background[3];      /* colour behind the Gaussians: rgb = a L_out +
+                               T_final background (3DGS composites over a
+                               constant background; black reproduces a plain
+                               a L_out).  Its gradient reaches the Gaussians
+                               through T_final.  Finite values. */
 } sssgs_options;
 
 /* Number of floats in sssgs_mlp.params. */
@@ -196,16 +211,14 @@ sssgs_status sssgs_render_forward_lights(const sssgs_gaussians *g, const sssgs_c
    gradient of every non-NULL plane of `grads` and, when mlp->params is
    non-NULL and dL_dmlp is non-NULL, of the network parameters.
    Transmittance is recomputed by reverse traversal; nothing per pixel-Gaussian
-   pair is stored by the forward. */
+   pair is stored by the forward.  With opt->deterministic the per-Gaussian
+   sums are bit-reproducible (see sssgs_options). */
 sssgs_status sssgs_render_backward(const sssgs_gaussians *g, const sssgs_camera *cam, const sssgs_light *light,
                                    const sssgs_mlp *mlp, const sssgs_options *opt, void *workspace,
                                    size_t workspace_bytes, int64_t instance_capacity, const float *gbuffer,
                                    const float *dL_drgb, const float *dL_dgbuffer, const float *dL_dalpha,
                                    sssgs_gaussian_grads *grads, float *dL_dmlp, void *stream);
 
-/* Image loss of the training objective (Appendix "Losses": the L1 part),
-   over `count` values: *loss_out (device) += sum |pred - target| * scale and
-   dL_dpred = sign(pred - target) * scale (sign(0) = 0).  loss_out may be NULL. */
 /* Per-Gaussian network (pipeline figure: Eq. 6 evaluated for each Gaussian
    before rasterisation, Sec. 3.2; layer sizes from the appendix "Network").
    Input per Gaussian (42 values): normal (the shortest rotation axis turned
@@ -265,6 +278,9 @@ size_t sssgs_visibility_workspace_bytes(int32_t n);
 sssgs_status sssgs_trace_visibility(const sssgs_gaussians *g, const sssgs_light *light, void *workspace,
                                     size_t workspace_bytes, float *out_visibility, void *stream);
 
+/* Image loss of the training objective (Appendix "Losses": the L1 part),
+   over `count` values: *loss_out (device) += sum |pred - target| * scale and
+   dL_dpred = sign(pred - target) * scale (sign(0) = 0).  loss_out may be NULL. */
 sssgs_status sssgs_l1_loss(const float *pred, const float *target, int64_t count, float scale, float *loss_out,
                            float *dL_dpred, void *stream);
 

@@ -65,7 +65,13 @@ def _bf16(x):
     return x.to(torch.float32).to(torch.bfloat16).to(DT)
 
 
-def render(params: dict, cam, light, mlp=None, bf16=False, sh_degree=-1):
+def _bf16_pair(x):
+    """An activation as it enters a BF16 forward product: hi + lo, two bfloat16 numbers."""
+    hi = _bf16(x)
+    return hi + _bf16(x - hi)
+
+
+def render(params: dict, cam, light, mlp=None, bf16=False, sh_degree=-1, background=None):
     """params: name -> float64 tensor (may require grad), SoA [k,N] layout.
 
     Returns dict(rgb [3,H,W], gbuf [C,H,W], alpha [H,W], n_contrib [H,W] (numpy),
@@ -232,7 +238,7 @@ def render(params: dict, cam, light, mlp=None, bf16=False, sh_degree=-1):
         pad = mlp.in_pad - inp.shape[1]
         inp = torch.cat([inp, torch.zeros((inp.shape[0], pad), dtype=DT)], -1)
         off = 0
-        act = _bf16(inp) if bf16 else inp
+        act = _bf16_pair(inp) if bf16 else inp
         dims = [mlp.in_pad] + [mlp.width] * mlp.hidden + [mlp.out_dim]
         for l in range(mlp.hidden + 1):
             rows, cols = dims[l + 1], dims[l]
@@ -246,7 +252,7 @@ def render(params: dict, cam, light, mlp=None, bf16=False, sh_degree=-1):
             if l < mlp.hidden:
                 act = torch.relu(pre)
                 if bf16:
-                    act = _bf16(act)
+                    act = _bf16_pair(act)
             else:
                 out = pre
         Lin = torch.relu(out[:, 0:3])
@@ -254,6 +260,8 @@ def render(params: dict, cam, light, mlp=None, bf16=False, sh_degree=-1):
         sss = gb[8][:, None]
         L = sss * Lsss + (1 - sss) * (fs + fd) * Lin * cosI[:, None]
     rgb = torch.where(bg[:, None], torch.zeros_like(L), a[:, None] * L).T
+    if background is not None:  # composited over a constant colour behind the Gaussians
+        rgb = rgb + _t(background)[:, None] * Tfin[None, :]
     return {
         "rgb": rgb.reshape(3, H, W), "gbuf": gbuf.reshape(C, H, W), "alpha": a.reshape(H, W),
         "n_contrib": ncontrib.reshape(H, W), "lists": lists,

@@ -90,7 +90,7 @@ def lib():
         _lib.og_render.restype = ct.c_int
         _lib.og_render.argtypes = [ct.POINTER(OgGauss), ct.POINTER(OgCam), ct.POINTER(OgLight),
                                    ct.POINTER(OgMlp), ct.POINTER(ct.c_int), ct.POINTER(OgOut),
-                                   ct.POINTER(OgUpstream), ct.POINTER(OgGrads), ct.c_int]
+                                   ct.POINTER(OgUpstream), ct.POINTER(OgGrads), ct.c_int, _dp]
         _lib.og_round_bf16.restype = ct.c_double
         _lib.og_round_bf16.argtypes = [ct.c_double]
         _lib.og_brdf.restype = None
@@ -116,7 +116,7 @@ def _f64(a):
 
 def render(g, cam, light, mlp=None, bf16: bool = False, crop=None, drgb=None, dgbuf=None, dalpha=None,
            grads: bool = False, nthreads: int = 0, lists: bool = False, params64: Optional[dict] = None,
-           sens: bool = False, radiance_features: bool = False):
+           sens: bool = False, radiance_features: bool = False, background=None):
     """Render one view (and optionally its backward) in FP64.
 
     ``g`` is a ``scene.Gaussians``; ``params64`` may override any of its arrays
@@ -124,8 +124,9 @@ def render(g, cam, light, mlp=None, bf16: bool = False, crop=None, drgb=None, dg
     also fills the shading-sensitivity diagnostic ``rgb_sens``.
     ``radiance_features`` (no per-pixel network): feature planes 0-2 are the
     incident light and 3-5 the SSS radiance of a per-Gaussian network, and
-    Eq. 7 takes them from the composited buffers.  Returns a dict of numpy
-    arrays.
+    Eq. 7 takes them from the composited buffers.  ``background`` (3 values,
+    default black) is the colour behind the Gaussians: rgb = a L_out +
+    T_final background.  Returns a dict of numpy arrays.
     """
     L = lib()
     n, F = g.n, g.feat_dim
@@ -190,9 +191,10 @@ def render(g, cam, light, mlp=None, bf16: bool = False, crop=None, drgb=None, dg
                        for k in ("means", "log_scales", "quats", "opacity_logits", "albedo", "roughness",
                                  "metallic", "sss", "features", "sh", "mlp")])
     crop_arr = (ct.c_int * 4)(*crop) if crop is not None else None
+    bg = None if background is None else np.ascontiguousarray(background, np.float64).reshape(3)
     rc = L.og_render(ct.byref(gs), ct.byref(cs), ct.byref(ls), ct.byref(mp) if mp is not None else None,
                      crop_arr, ct.byref(out), ct.byref(upp) if upp is not None else None,
-                     ct.byref(gp) if gp is not None else None, int(nthreads))
+                     ct.byref(gp) if gp is not None else None, int(nthreads), _p(bg))
     if rc != 0:
         raise RuntimeError(f"oracle og_render failed: {rc}")
     o["num_instances"] = int(num[0])
@@ -245,7 +247,7 @@ def _count_instances(g, cam, arr) -> int:
     out = OgOut()
     out.tiles_touched = _p(tt, _ip)
     crop = (ct.c_int * 4)(0, 0, 0, 0)
-    rc = L.og_render(ct.byref(gs), ct.byref(cs), ct.byref(ls), None, crop, ct.byref(out), None, None, 0)
+    rc = L.og_render(ct.byref(gs), ct.byref(cs), ct.byref(ls), None, crop, ct.byref(out), None, None, 0, None)
     if rc != 0:
         raise RuntimeError("oracle projection failed")
     return int(tt.astype(np.int64).sum())

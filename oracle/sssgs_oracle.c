@@ -87,7 +87,8 @@ typedef struct {
   /* images */
   double *rgb, *gbuf, *alpha;
   double *gbuf_abs; /* diagnostic: sum of T alpha |value| per channel (scale of rounding errors) */
-  double *net_margin; /* diagnostic: smallest |pre-activation| of any ReLU of the network at the pixel */
+  double *net_margin; /* diagnostic: smallest |argument| of any ReLU of the network at the pixel, relative to
+                         the sum of the magnitudes of its terms (|bias| + sum |w x|) */
   double *rgb_sens;   /* diagnostic [3][H][W]: sum_k |d rgb_c / d G_k| (|G_k| + sum|terms_k|) + |d rgb_c / d T| T,
                          the first-order change of rgb under unit relative perturbations of the G-buffer */
   int32_t *n_contrib;
@@ -407,10 +408,11 @@ typedef struct {
   double F0[3], F[3], fs[3], fd[3];
   double li2, Lin[3];
   double in[MAXIN];          /* network input (padded) */
-  double act[8][MAXW];       /* layer inputs as used (after bf16 rounding in emulation) */
+  double act[8][MAXW];       /* layer inputs as the forward products use them (emulation: hi + lo) */
+  double act_w[8][MAXW];     /* layer inputs as the weight gradient uses them (emulation: hi) */
   double pre[8][MAXW];       /* pre-activations */
   double out[8];
-  double margin;             /* smallest |argument| of any ReLU */
+  double margin;             /* smallest |argument| / (sum of |terms|) of any ReLU */
   double Lsss[3];
   double L[3];
   int background;
@@ -443,6 +445,16 @@ static size_t mlp_layer_offset(const og_mlp *m, int layer) {
 }
 
 static double rb(const og_mlp *m, double v) { return m->bf16 ? og_round_bf16(v) : v; }
+
+/* BF16 emulation of an activation entering a forward product: the value is
+   carried as two bfloat16 numbers, hi = RNE(v) and lo = RNE(v - hi), so the
+   product sees hi + lo (16 significant bits); the weight gradient takes hi. */
+static void rb_act(const og_mlp *m, double v, double *prod, double *wgrad) {
+  if (!m->bf16) { *prod = v; *wgrad = v; return; }
+  double hi = og_round_bf16(v);
+  *prod = hi + og_round_bf16(v - hi);
+  *wgrad = hi;
+}
 
 static void shade_pixel(const og_cam *cam, const og_light *light, const og_mlp *mlp, int blend, int C, int F,
                         const double *G, double T, double uc, double vc, shade_t *S) {
@@ -527,20 +539,25 @@ static void shade_pixel(const og_cam *cam, const og_light *light, const og_mlp *
   for (int k = 0; k < 3; k++) S->in[p++] = S->wo[k];
   for (int k = 0; k < 3; k++) S->in[p++] = S->wi[k];
   for (; p < mlp->in_pad; p++) S->in[p] = 0;
-  for (int k = 0; k < mlp->in_pad; k++) S->act[0][k] = rb(mlp, S->in[k]);
+  for (int k = 0; k < mlp->in_pad; k++) rb_act(mlp, S->in[k], &S->act[0][k], &S->act_w[0][k]);
   S->margin = INFINITY;
   for (int l = 0; l <= mlp->hidden; l++) {
     int rows = 0, cols = 0;
     const double *bias = NULL;
     const double *W = mlp_layer_w(mlp, l, &rows, &cols, &bias);
     for (int o = 0; o < rows; o++) {
-      double acc = 0;
-      for (int c = 0; c < cols; c++) acc += W[(size_t)o * cols + c] * S->act[l][c];
+      double acc = 0, mag = fabs(bias[o]);
+      for (int c = 0; c < cols; c++) {
+        acc += W[(size_t)o * cols + c] * S->act[l][c];
+        mag += fabs(W[(size_t)o * cols + c] * S->act[l][c]);
+      }
       acc += bias[o];
       S->pre[l][o] = acc;
-      if (l < mlp->hidden) S->act[l + 1][o] = rb(mlp, acc > 0 ? acc : 0);
+      if (l < mlp->hidden) rb_act(mlp, acc > 0 ? acc : 0, &S->act[l + 1][o], &S->act_w[l + 1][o]);
       else S->out[o] = acc;
-      if ((l < mlp->hidden || o < 3) && fabs(acc) < S->margin) S->margin = fabs(acc);
+      /* decision margin of the ReLU: |argument| relative to the size of its terms */
+      double rel = mag > 0 ? fabs(acc) / mag : INFINITY;
+      if ((l < mlp->hidden || o < 3) && rel < S->margin) S->margin = rel;
     }
   }
   for (int c = 0; c < 3; c++) {
@@ -624,8 +641,9 @@ static double shade_pixel_bwd(const og_cam *cam, const og_light *light, const og
         if (d == 0.0) continue;
         double dr = rb(mlp, d);
         if (dmlp) {
-          dmlp[off + (size_t)rows * cols + o] += d; /* bias */
-          for (int c = 0; c < cols; c++) dmlp[off + (size_t)o * cols + c] += dr * S->act[l][c];
+          /* bias: the sum of the upstream gradient as it enters the products */
+          dmlp[off + (size_t)rows * cols + o] += dr;
+          for (int c = 0; c < cols; c++) dmlp[off + (size_t)o * cols + c] += dr * S->act_w[l][c];
         }
         for (int c = 0; c < cols; c++) dprev[c] += W[(size_t)o * cols + c] * dr;
       }
@@ -759,8 +777,14 @@ static uint64_t mix64(uint64_t h, uint64_t v) {
 
 /* ------------------------------------------------------------------------- */
 
+/* background: colour behind the Gaussians (NULL: black).  The image is
+   composited over it like one more, fully opaque layer at the back:
+   rgb = a L_out + T_final background. */
 int og_render(const og_gauss *g, const og_cam *cam, const og_light *light, const og_mlp *mlp_in,
-              const int *crop, og_out *out, const og_upstream *up, og_grads *gr, int nthreads) {
+              const int *crop, og_out *out, const og_upstream *up, og_grads *gr, int nthreads,
+              const double *background) {
+  const double bgc[3] = {background ? background[0] : 0.0, background ? background[1] : 0.0,
+                         background ? background[2] : 0.0};
   const int n = g->n, W = cam->width, H = cam->height;
   const int TX = (W + TILE - 1) / TILE, TY = (H + TILE - 1) / TILE, T = TX * TY;
   const int F = g->feat_dim, C = og_channels(F);
@@ -772,8 +796,10 @@ int og_render(const og_gauss *g, const og_cam *cam, const og_light *light, const
               mlp->in_dim != F + NPE + 6))
     return -3;
   /* Emulation of the bfloat16 tensor-core path: the weight matrices (not the
-     biases) are rounded once; activations and upstream gradients are rounded
-     where they enter a product (shade_pixel / shade_pixel_bwd). */
+     biases) are rounded once; activations enter the forward products as a
+     pair of bfloat16 numbers (hi + lo) and the weight gradient as hi alone;
+     upstream gradients are rounded once where they enter a product
+     (shade_pixel / shade_pixel_bwd). */
   og_mlp mlp_round;
   double *wround = NULL;
   if (mlp && mlp->bf16) {
@@ -931,13 +957,14 @@ int og_render(const og_gauss *g, const og_cam *cam, const og_light *light, const
           for (int c = 0; c < 3; c++) {
             double e[3] = {0, 0, 0}, dGs[MAXC];
             e[c] = 1.0;
-            double dTs = shade_pixel_bwd(cam, light, mlp, blend, C, F, S, e, dGs, NULL);
+            double dTs = shade_pixel_bwd(cam, light, mlp, blend, C, F, S, e, dGs, NULL) + bgc[c];
             double sacc = fabs(dTs) * Tr;
             for (int k = 0; k < C; k++) sacc += fabs(dGs[k]) * (fabs(Gp[k]) + Ga[k]);
             out->rgb_sens[(size_t)c * H * W + pix] = sacc;
           }
         }
-        if (out->rgb) for (int c = 0; c < 3; c++) out->rgb[(size_t)c * H * W + pix] = S->a * S->L[c] * !S->background;
+        if (out->rgb)
+          for (int c = 0; c < 3; c++) out->rgb[(size_t)c * H * W + pix] = S->a * S->L[c] * !S->background + Tr * bgc[c];
         if (!up) continue;
         /* ---- backward ---- */
         double gL[3], dG[MAXC];
@@ -946,6 +973,7 @@ int og_render(const og_gauss *g, const og_cam *cam, const og_light *light, const
                                     dG, macc ? macc + (size_t)tid * np : NULL);
         if (up->dgbuf) for (int k = 0; k < C; k++) dG[k] += up->dgbuf[(size_t)k * H * W + pix];
         if (up->dalpha) dT -= up->dalpha[pix];
+        for (int c = 0; c < 3; c++) dT += gL[c] * bgc[c]; /* rgb = ... + T_final background */
         /* reverse traversal: T before each contributor recovered by division */
         double Tcur = Tr, Sfx = 0; /* Sfx = sum over later contributors of w_j (dG . ch_j) */
         double *ga = gacc + ((size_t)tid * n) * GS;

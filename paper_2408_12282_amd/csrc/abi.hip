@@ -7,6 +7,7 @@
 #include <vector>
 
 #include "sssgs.h"
+#include <algorithm>
 #include <cmath>
 #include "launch.hpp"
 #include "shade_common.hpp"
@@ -86,14 +87,12 @@ int in_pad_of(int in_dim) { return (in_dim + 31) / 32 * 32; }
 struct Layout {
   size_t records, depth_keys, vals_a, keys_b, vals_b, keys_a, rects, radii, boxes, tt, offsets, partials, hist;
   size_t ik_a, iv_a, ik_b, iv_b, ranges, tcount, apart, t_final, n_contrib, status, m_total;
-  size_t gacc, dG, dT, wops, tops, mlp_part, mlp_mid, rec_x, rec_o;
+  size_t gacc, slots, sflags, dG, dT, wops, tops, nops, mlp_part, mlp_mid, rec_x, rec_o, gx, gdy;
   size_t total;
   int C, RS, GS, TX, TY, T;
   uint32_t nb_g, nb_i;
-  int shade_bwd_blocks, shade_parts, nparams;
+  int parts, nparams;
 };
-
-constexpr int kShadeBwdMaxBlocks = 512;
 
 bool make_layout(int32_t n, int32_t W, int32_t H, int32_t F, int32_t mlp_width, int64_t cap, Layout &L) {
   if (n < 0 || W <= 0 || H <= 0 || cap < 0 || cap >= (int64_t(1) << 31)) return false;
@@ -145,21 +144,31 @@ bool make_layout(int32_t n, int32_t W, int32_t H, int32_t F, int32_t mlp_width, 
   L.status = take(16);
   L.m_total = take(16);
   L.gacc = take(nn * L.GS * 4);
+  // deterministic per-Gaussian sums: one slot per tile instance, and its flag
+  L.slots = take(cc * L.GS * 4);
+  L.sflags = take((cc + 3) / 4 * 4);
   L.dG = take(HW * L.C * 4);
   L.dT = take(HW * 4);
   const int in_pad = in_pad_of(F + kNumPE + 6);
   L.nparams = mlp_width ? (int)sssgs_mlp_param_count(F + kNumPE + 6, mlp_width, 3, 6) : 0;
-  L.shade_bwd_blocks = kShadeBwdMaxBlocks;
-  L.shade_parts = kShadeBwdMaxBlocks;  // one weight-gradient partial per workgroup
+  const size_t nstrips = (size_t)L.T * 4, P = nstrips * 64;
+  // one weight-gradient partial row per workgroup of the weight kernels
+  L.parts = mlp_width ? std::max(mlp_wgrad_grid((int)nstrips), wgrad_gemm_splits(P)) : 0;
   L.wops = take(mlp_width ? prep_weight_bytes(mlp_width, in_pad) : 0);
   L.tops = take(mlp_width ? prep_weight_bytes(mlp_width, in_pad) : 0);
-  L.mlp_part = take(mlp_width ? (size_t)L.shade_parts * L.nparams * 4 : 0);
+  L.nops = take(mlp_width ? prep_weight_bytes(mlp_width, in_pad) : 0);
+  L.mlp_part = take(mlp_width ? (size_t)L.parts * L.nparams * 4 : 0);
   L.mlp_mid = take(mlp_width ? (size_t)reduce_scratch_floats(L.nparams) * 4 : 0);
   // strip records of the split shading backward (BF16 network, width 64, input width 64)
   const bool split = mlp_width == 64 && in_pad == 64;
-  const size_t nstrips = (size_t)L.T * 4;
-  L.rec_x = take(split ? nstrips * 64 * 64 * 2 : 0);
+  L.rec_x = take(split ? nstrips * 64 * 2 * 64 * 2 : 0);  // BF16 values and remainders
   L.rec_o = take(split ? nstrips * 64 * 8 * 2 : 0);
+  // weight-gradient operands of the generic network backward (X_l, dY_l per
+  // pixel; FP32 where an FP32 network of this width exists, else BF16)
+  const size_t esz = mlp_width == 64 ? 4 : 2;
+  const size_t xe = (size_t)in_pad + 3 * (size_t)mlp_width, ye = 3 * (size_t)mlp_width + 8;
+  L.gx = take(mlp_width ? P * xe * esz : 0);
+  L.gdy = take(mlp_width ? P * ye * esz : 0);
   L.total = p;
   return true;
 }
@@ -215,6 +224,10 @@ sssgs_status check_common(const sssgs_gaussians *g, const sssgs_camera *cam, con
     if (net) return fail(SSSGS_ERR_INVALID_ARG, "radiance_features excludes the per-pixel network");
     if (g->feat_dim != 8) return fail(SSSGS_ERR_UNSUPPORTED, "radiance_features needs feat_dim 8");
   }
+  if (!(opt->deterministic == 0 || opt->deterministic == 1))
+    return fail(SSSGS_ERR_INVALID_ARG, "deterministic must be 0 or 1");
+  for (int c = 0; c < 3; c++)
+    if (!std::isfinite(opt->background[c])) return fail(SSSGS_ERR_INVALID_ARG, "background must be finite");
   return SSSGS_OK;
 }
 
@@ -276,7 +289,7 @@ void composite_fwd(int C, const Layout &L, void *ws, int W, int H, float *gbuf, 
   }
 }
 
-void composite_bwd(int C, const Layout &L, void *ws, int W, int H, hipStream_t st) {
+void composite_bwd(int C, const Layout &L, void *ws, int W, int H, const DetSlots &det, hipStream_t st) {
   const uint2 *rg = at<uint2>(ws, L.ranges);
   const uint32_t *sg = at<uint32_t>(ws, L.iv_a);
   const float *rec = at<float>(ws, L.records);
@@ -287,22 +300,21 @@ void composite_bwd(int C, const Layout &L, void *ws, int W, int H, hipStream_t s
   const float *dT = at<float>(ws, L.dT);
   float *ga = at<float>(ws, L.gacc);
   switch (C) {
-    case 10: launch_composite_bwd_t<10>(rg, sg, rec, bx, W, H, L.TX, L.TY, tf, nc, dG, dT, ga, st); break;
-    case 18: launch_composite_bwd_t<18>(rg, sg, rec, bx, W, H, L.TX, L.TY, tf, nc, dG, dT, ga, st); break;
-    case 26: launch_composite_bwd_t<26>(rg, sg, rec, bx, W, H, L.TX, L.TY, tf, nc, dG, dT, ga, st); break;
-    default: launch_composite_bwd_t<42>(rg, sg, rec, bx, W, H, L.TX, L.TY, tf, nc, dG, dT, ga, st); break;
+    case 10: launch_composite_bwd_t<10>(rg, sg, rec, bx, W, H, L.TX, L.TY, tf, nc, dG, dT, ga, det, st); break;
+    case 18: launch_composite_bwd_t<18>(rg, sg, rec, bx, W, H, L.TX, L.TY, tf, nc, dG, dT, ga, det, st); break;
+    case 26: launch_composite_bwd_t<26>(rg, sg, rec, bx, W, H, L.TX, L.TY, tf, nc, dG, dT, ga, det, st); break;
+    default: launch_composite_bwd_t<42>(rg, sg, rec, bx, W, H, L.TX, L.TY, tf, nc, dG, dT, ga, det, st); break;
   }
 }
 
 // Dispatch over (F, NET, WIDTH, IN_PAD) for the shading kernels.
 template <bool BWD>
-bool shade_dispatch(int F, int net, int width, const ShadeArgs &a, int nblocks, hipStream_t st,
-                    const MultiLight *ml = nullptr) {
+bool shade_dispatch(int F, int net, int width, const ShadeArgs &a, hipStream_t st, const MultiLight *ml = nullptr) {
   const int in_pad = in_pad_of(F + kNumPE + 6);
   const int w = (net == 1 || net == 2) ? width : 64;
 #define SSSGS_TRY(F_, NET_, W_, P_)                                              \
   if (F == F_ && net == NET_ && w == W_ && in_pad == P_) {                     \
-    if constexpr (BWD) launch_shade_bwd_t<F_, NET_, W_, P_>(a, nblocks, st);   \
+    if constexpr (BWD) launch_shade_bwd_t<F_, NET_, W_, P_>(a, st);            \
     else launch_shade_fwd_t<F_, NET_, W_, P_>(a, *ml, st);                     \
     return true;                                                                \
   }
@@ -433,11 +445,13 @@ sssgs_status forward_impl(const sssgs_gaussians *g, const sssgs_camera *cam, con
   sa.gbuf = out_gbuffer;
   sa.t_final = at<float>(ws, L.t_final);
   sa.rgb = out_rgb;
+  for (int c = 0; c < 3; c++) sa.bgc[c] = opt->background[c];
   sa.alpha = out_alpha;
   if (net) {
     sa.params = mlp->params;
     sa.wops = at<void>(ws, L.wops);
-    launch_prep_weights(net, width, in_pad_of(mlp->in_dim), mlp->params, at<void>(ws, L.wops), nullptr, st);
+    launch_prep_weights(net, width, in_pad_of(mlp->in_dim), mlp->params, at<void>(ws, L.wops), nullptr, nullptr,
+                        st);
   }
   {
     Scope sc(kStShadeFwd, st);
@@ -452,7 +466,7 @@ sssgs_status forward_impl(const sssgs_gaussians *g, const sssgs_camera *cam, con
           ml.intensity[k][c] = lights[k0 + k].intensity[c];
           ml.weight[k][c] = weights ? weights[(k0 + k) * 3 + c] : 1.f;
         }
-      if (!shade_dispatch<false>(g->feat_dim, opt->radiance_features ? 3 : net, width, sa, 0, st, &ml))
+      if (!shade_dispatch<false>(g->feat_dim, opt->radiance_features ? 3 : net, width, sa, st, &ml))
         return fail(SSSGS_ERR_UNSUPPORTED, "no shading kernel for this configuration");
     }
   }
@@ -524,19 +538,25 @@ sssgs_status sssgs_render_backward(const sssgs_gaussians *g, const sssgs_camera 
   sa.dalpha_ext = dL_dalpha;
   sa.dG = at<float>(ws, L.dG);
   sa.dT = at<float>(ws, L.dT);
+  for (int c = 0; c < 3; c++) sa.bgc[c] = opt->background[c];
+  const int ip = net ? in_pad_of(mlp->in_dim) : 0;
+  // BF16 width-64 network with input width 64: the split shading backward and
+  // the weight-gradient kernel that recomputes from its strip records; other
+  // network forms: the generic backward and the split-K weight contraction
+  const bool split = net == 2 && width == 64 && ip == 64;
   if (net) {
     sa.params = mlp->params;
     sa.wops = at<void>(ws, L.wops);
     sa.tops = at<void>(ws, L.tops);
+    sa.nops = split ? nullptr : at<void>(ws, L.nops);
     sa.mlp_partials = at<float>(ws, L.mlp_part);
     sa.nparams = L.nparams;
-    launch_prep_weights(net, width, in_pad_of(mlp->in_dim), mlp->params, at<void>(ws, L.wops),
-                        at<void>(ws, L.tops), st);
+    sa.gx = at<void>(ws, L.gx);
+    sa.gdy = at<void>(ws, L.gdy);
+    sa.gP = (size_t)L.T * 4 * 64;
+    launch_prep_weights(net, width, ip, mlp->params, at<void>(ws, L.wops), at<void>(ws, L.tops),
+                        split ? nullptr : at<void>(ws, L.nops), st);
   }
-  const int nblk = L.shade_bwd_blocks;
-  const int ip = net ? in_pad_of(mlp->in_dim) : 0;
-  // BF16 width-64 network: shading backward and weight gradients as two kernels
-  const bool split = net == 2 && width == 64 && ip == 64;
   int parts = 0;
   // the split shading backward clears the compositing accumulators as side
   // work when that is at most 16 float4 stores per thread
@@ -562,10 +582,16 @@ sssgs_status sssgs_render_backward(const sssgs_gaussians *g, const sssgs_camera 
       parts = mlp_wgrad_grid(L.T * 4);
     }
   } else {
-    Scope sc(kStShadeBwd, st);
-    if (!shade_dispatch<true>(g->feat_dim, opt->radiance_features ? 3 : net, width, sa, nblk, st))
-      return fail(SSSGS_ERR_UNSUPPORTED, "no shading kernel for this configuration");
-    if (net) parts = shade_bwd_grid(net, width, ip, L.T, nblk);
+    {
+      Scope sc(kStShadeBwd, st);
+      if (!shade_dispatch<true>(g->feat_dim, opt->radiance_features ? 3 : net, width, sa, st))
+        return fail(SSSGS_ERR_UNSUPPORTED, "no shading kernel for this configuration");
+    }
+    if (net && dL_dmlp) {
+      Scope sc(kStMlpWgrad, st);
+      launch_wgrad_gemm(net, width, ip, sa.gx, sa.gdy, sa.gP, sa.mlp_partials, st);
+      parts = wgrad_gemm_splits(sa.gP);
+    }
   }
   if (net && dL_dmlp) {
     Scope sc(kStMlpReduce, st);
@@ -573,10 +599,26 @@ sssgs_status sssgs_render_backward(const sssgs_gaussians *g, const sssgs_camera 
                            opt->accumulate_grads, st);
   }
   // 2. compositing backward into the per-Gaussian accumulators
-  if (!fused_zero) launch_zero_f32(at<float>(ws, L.gacc), (size_t)(g->n) * L.GS, st);
+  DetSlots det;
+  memset(&det, 0, sizeof(det));
+  if (opt->deterministic && g->n > 0) {
+    // slot offsets: exclusive scan of the tile-rectangle areas; flags cleared
+    det.slots = at<float>(ws, L.slots);
+    det.flags = at<uint8_t>(ws, L.sflags);
+    det.rects = at<ushort4>(ws, L.rects);
+    det.toff = at<uint32_t>(ws, L.offsets);
+    det.cap = (size_t)cap;
+    launch_rect_area(det.rects, (uint32_t)g->n, at<uint32_t>(ws, L.tt), st);
+    launch_scan(at<uint32_t>(ws, L.tt), at<uint32_t>(ws, L.offsets), (uint32_t)g->n, at<uint32_t>(ws, L.partials),
+                at<uint32_t>(ws, L.status) + 3, st);
+    launch_zero_f32(at<float>(ws, L.sflags), (size_t)(cap + 3) / 4, st);
+  } else if (!fused_zero) {
+    launch_zero_f32(at<float>(ws, L.gacc), (size_t)(g->n) * L.GS, st);
+  }
   {
     Scope sc(kStCompositeBwd, st);
-    composite_bwd(L.C, L, ws, W, H, st);
+    composite_bwd(L.C, L, ws, W, H, det, st);
+    if (det.slots) launch_slot_reduce(L.C, det, (uint32_t)g->n, at<float>(ws, L.gacc), st);
   }
   // 3. projection backward
   ProjGradOut go;

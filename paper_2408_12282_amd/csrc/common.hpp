@@ -55,6 +55,24 @@ __device__ __forceinline__ float fast_exp(float x) { return __builtin_amdgcn_exp
 
 __device__ __forceinline__ float splat_alpha_raw(float opacity, float power) { return __fmul_rn(opacity, fast_exp(power)); }
 
+// Deterministic per-Gaussian gradient sums of the compositing backward: one
+// slot per (Gaussian, tile of its rectangle); the slots of Gaussian i are
+// toff[i] .. toff[i] + area(i) - 1 in row-major tile order.  slots == null:
+// the sums are added with atomics instead.
+struct DetSlots {
+  float *slots;          // [instances][grad_stride(C)]
+  uint8_t *flags;        // [instances]: 1 where a tile wrote the slot
+  const ushort4 *rects;  // [n] tile rectangles x0, y0, x1, y1
+  const uint32_t *toff;  // [n] first slot of each Gaussian
+  size_t cap;            // slots available (the instance capacity): after an
+                         // overflowed forward, slots beyond it are skipped
+};
+
+__device__ __forceinline__ size_t det_slot(const DetSlots &d, uint32_t i, int tx, int ty) {
+  const ushort4 r = d.rects[i];
+  return (size_t)d.toff[i] + (size_t)(ty - (int)r.y) * (size_t)(r.z - r.x) + (size_t)(tx - (int)r.x);
+}
+
 // Status word layout in the workspace.
 constexpr int kStatusFlags = 0, kStatusMLo = 1, kStatusMHi = 2;
 constexpr int kFlagOverflow = 1;

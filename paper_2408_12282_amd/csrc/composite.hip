@@ -158,7 +158,7 @@ __global__ __launch_bounds__(256, C > 26 ? 2 : 3) void composite_bwd_kernel(
     const uint2 *__restrict__ ranges, const uint32_t *__restrict__ sorted_g, const float *__restrict__ records,
     const short4 *__restrict__ boxes, int W, int H, int TX, const float *__restrict__ t_final,
     const uint32_t *__restrict__ n_contrib, const float *__restrict__ dG, const float *__restrict__ dT,
-    float *__restrict__ gacc) {
+    float *__restrict__ gacc, DetSlots det) {
   constexpr int RS = rec_stride(C);
   constexpr int R4 = RS / 4;              // float4 per record
   constexpr int GS = grad_stride(C);
@@ -399,15 +399,52 @@ __global__ __launch_bounds__(256, C > 26 ? 2 : 3) void composite_bwd_kernel(
     }
     if (ncnt > 0) stage(buf ^ 1, ncnt);
     __syncthreads();
-    for (int k = t; k < kBJ * C; k += 256) {
-      const int jj = k / C, c = k % C;
-      if (jj < cnt) {
-        const float s = (mat[jj * kMS + 0 * 64 + c] + mat[jj * kMS + 1 * 64 + c]) +
-                        (mat[jj * kMS + 2 * 64 + c] + mat[jj * kMS + 3 * 64 + c]);
-        if (s != 0.f) atomicAdd(gacc + (size_t)gidx[buf][jj] * GS + 6 + c, s);
+    if (det.slots) {
+      // deterministic: the tile's sums of each Gaussian go to that Gaussian's
+      // slot for this tile (no atomics); a fixed-order pass adds the slots
+      for (int k = t; k < kBJ * C; k += 256) {
+        const int jj = k / C, c = k % C;
+        if (jj < cnt) {
+          const float s = (mat[jj * kMS + 0 * 64 + c] + mat[jj * kMS + 1 * 64 + c]) +
+                          (mat[jj * kMS + 2 * 64 + c] + mat[jj * kMS + 3 * 64 + c]);
+          const size_t sl = det_slot(det, gidx[buf][jj], tx, ty);
+          if (sl < det.cap) det.slots[sl * GS + 6 + c] = s;
+        }
+      }
+    } else {
+      for (int k = t; k < kBJ * C; k += 256) {
+        const int jj = k / C, c = k % C;
+        if (jj < cnt) {
+          const float s = (mat[jj * kMS + 0 * 64 + c] + mat[jj * kMS + 1 * 64 + c]) +
+                          (mat[jj * kMS + 2 * 64 + c] + mat[jj * kMS + 3 * 64 + c]);
+          if (s != 0.f) atomicAdd(gacc + (size_t)gidx[buf][jj] * GS + 6 + c, s);
+        }
       }
     }
-    if (t < cnt) {
+    if (t < cnt && det.slots) {
+      float mo[6];
+#pragma unroll
+      for (int n = 0; n < 6; n++)
+        mo[n] = (mat[t * kMS + 0 * 64 + CP + n] + mat[t * kMS + 1 * 64 + CP + n]) +
+                (mat[t * kMS + 2 * 64 + CP + n] + mat[t * kMS + 3 * 64 + CP + n]);
+      const float *r = reinterpret_cast<const float *>(&recs[buf][t * R4]);
+      const float up = r[0] - (float)(tx * kTile), vp = r[1] - (float)(ty * kTile);
+      const float mx = up * mo[0] - mo[1], my = vp * mo[0] - mo[2];
+      const float mxx = up * up * mo[0] - 2.f * up * mo[1] + mo[3];
+      const float mxy = up * vp * mo[0] - up * mo[2] - vp * mo[1] + mo[4];
+      const float myy = vp * vp * mo[0] - 2.f * vp * mo[2] + mo[5];
+      const size_t sl = det_slot(det, gidx[buf][t], tx, ty);
+      if (sl < det.cap) {
+        float *ga = det.slots + sl * GS;
+        ga[0] = -(r[2] * mx + r[3] * my);
+        ga[1] = -(r[4] * my + r[3] * mx);
+        ga[2] = -0.5f * mxx;
+        ga[3] = -mxy;
+        ga[4] = -0.5f * myy;
+        ga[5] = mo[0] / r[5];
+        det.flags[sl] = 1;
+      }
+    } else if (t < cnt) {
       float mo[6];
 #pragma unroll
       for (int n = 0; n < 6; n++)
@@ -445,9 +482,64 @@ void launch_composite_fwd_t(const uint2 *ranges, const uint32_t *sorted_g, const
 template <int C>
 void launch_composite_bwd_t(const uint2 *ranges, const uint32_t *sorted_g, const float *records, const short4 *boxes,
                             int W, int H, int TX, int TY, const float *t_final, const uint32_t *n_contrib,
-                            const float *dG, const float *dT, float *gacc, hipStream_t st) {
+                            const float *dG, const float *dT, float *gacc, const DetSlots &det, hipStream_t st) {
   composite_bwd_kernel<C><<<TX * TY, 256, 0, st>>>(ranges, sorted_g, records, boxes, W, H, TX, t_final, n_contrib,
-                                                   dG, dT, gacc);
+                                                   dG, dT, gacc, det);
+}
+
+// ---------------------------------------------------------------- deterministic sums
+//
+// The slots of Gaussian i are toff[i] .. toff[i] + area(i) - 1, one per tile
+// of its rectangle in row-major order (toff: exclusive scan of the areas).
+__global__ __launch_bounds__(256) void rect_area_kernel(const ushort4 *__restrict__ rects, uint32_t n,
+                                                        uint32_t *__restrict__ area) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const ushort4 r = rects[i];
+  area[i] = (uint32_t)(r.z - r.x) * (uint32_t)(r.w - r.y);
+}
+
+// Per Gaussian, the sum of its flagged slots in row-major tile order (one
+// thread per float4 of the accumulator row); every row is written.
+template <int GS>
+__global__ __launch_bounds__(256) void slot_reduce_kernel(DetSlots det, uint32_t n, float *__restrict__ gacc) {
+  constexpr int Q = GS / 4;
+  const size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= (size_t)n * Q) return;
+  const uint32_t i = (uint32_t)(k / Q), q = (uint32_t)(k % Q);
+  const ushort4 r = det.rects[i];
+  const size_t base = det.toff[i];
+  size_t area = (size_t)(r.z - r.x) * (size_t)(r.w - r.y);
+  if (base >= det.cap) area = 0;
+  else if (area > det.cap - base) area = det.cap - base;
+  float4 a = make_float4(0.f, 0.f, 0.f, 0.f);
+  for (size_t s = 0; s < area; s++) {
+    if (det.flags[base + s]) {
+      const float4 v = ld4(det.slots + (base + s) * GS + 4 * q);
+      a.x += v.x;
+      a.y += v.y;
+      a.z += v.z;
+      a.w += v.w;
+    }
+  }
+  st4(gacc + (size_t)i * GS + 4 * q, a);
+}
+
+void launch_rect_area(const ushort4 *rects, uint32_t n, uint32_t *area, hipStream_t st) {
+  if (n) rect_area_kernel<<<(n + 255) / 256, 256, 0, st>>>(rects, n, area);
+}
+
+void launch_slot_reduce(int C, const DetSlots &det, uint32_t n, float *gacc, hipStream_t st) {
+  if (!n) return;
+  const int GS = grad_stride(C);
+  const size_t threads = (size_t)n * (GS / 4);
+  const unsigned blocks = (unsigned)((threads + 255) / 256);
+  switch (GS) {
+    case 16: slot_reduce_kernel<16><<<blocks, 256, 0, st>>>(det, n, gacc); break;
+    case 24: slot_reduce_kernel<24><<<blocks, 256, 0, st>>>(det, n, gacc); break;
+    case 32: slot_reduce_kernel<32><<<blocks, 256, 0, st>>>(det, n, gacc); break;
+    default: slot_reduce_kernel<48><<<blocks, 256, 0, st>>>(det, n, gacc); break;
+  }
 }
 
 #define SSSGS_COMP_INST(C)                                                                                      \
@@ -455,7 +547,7 @@ void launch_composite_bwd_t(const uint2 *ranges, const uint32_t *sorted_g, const
                                           int, int, int, float *, float *, uint32_t *, hipStream_t);          \
   template void launch_composite_bwd_t<C>(const uint2 *, const uint32_t *, const float *, const short4 *, int,  \
                                           int, int, int, const float *, const uint32_t *, const float *,      \
-                                          const float *, float *, hipStream_t);
+                                          const float *, float *, const DetSlots &, hipStream_t);
 SSSGS_COMP_INST(10)
 SSSGS_COMP_INST(18)
 SSSGS_COMP_INST(26)

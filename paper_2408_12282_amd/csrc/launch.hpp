@@ -52,14 +52,15 @@ void launch_composite_fwd_t(const uint2 *ranges, const uint32_t *sorted_g, const
 template <int C>
 void launch_composite_bwd_t(const uint2 *ranges, const uint32_t *sorted_g, const float *records, const short4 *boxes,
                             int W, int H, int TX, int TY, const float *t_final, const uint32_t *n_contrib,
-                            const float *dG, const float *dT, float *gacc, hipStream_t st);
+                            const float *dG, const float *dT, float *gacc, const DetSlots &det, hipStream_t st);
+void launch_rect_area(const ushort4 *rects, uint32_t n, uint32_t *area, hipStream_t st);
+void launch_slot_reduce(int C, const DetSlots &det, uint32_t n, float *gacc, hipStream_t st);
 
 template <int F, int NET, int WIDTH, int IN_PAD>
 void launch_shade_fwd_t(const ShadeArgs &a, const MultiLight &ml, hipStream_t st);
 template <int F, int NET, int WIDTH, int IN_PAD>
-void launch_shade_bwd_t(const ShadeArgs &a, int nblocks, hipStream_t st);
-int shade_bwd_waves(int net, int width, int in_pad);
-int shade_bwd_grid(int net, int width, int in_pad, int tiles, int max_blocks);
+void launch_shade_bwd_t(const ShadeArgs &a, hipStream_t st);
+size_t net_operand_elems(int width, int in_pad);
 // split form for the BF16 width-64 network: shading backward writing per-strip
 // records (one 64-thread workgroup per strip), then the weight-gradient kernel
 template <int F, int IN_PAD>
@@ -68,9 +69,12 @@ constexpr int kWgradMaxBlocks = 256;
 int mlp_wgrad_grid(int nstrips);
 void launch_mlp_wgrad(const void *wops, const void *tops, const float *params, const __bf16 *rec_x,
                       const __bf16 *rec_o, int nstrips, float *partials, hipStream_t st);
+int wgrad_gemm_splits(size_t P);
+void launch_wgrad_gemm(int net, int width, int in_pad, const void *gx, const void *gdy, size_t P, float *partials,
+                       hipStream_t st);
 
 // network weight preparation and gradient reduction (mlp_prep.hip)
-void launch_prep_weights(int net, int width, int in_pad, const float *params, void *wops, void *tops,
+void launch_prep_weights(int net, int width, int in_pad, const float *params, void *wops, void *tops, void *nops,
                          hipStream_t st);
 size_t prep_weight_bytes(int width, int in_pad);
 void launch_reduce_partials(const float *partials, int nparts, int nparams, float *scratch, float *out,

@@ -10,6 +10,12 @@
 //
 // Two arithmetic forms share the code: FP32 operands on v_mfma_f32_16x16x4_f32
 // and BF16 operands on v_mfma_f32_16x16x32_bf16, both with FP32 accumulation.
+// In the BF16 form the weights are single BF16 numbers and an activation
+// enters a forward product as two, hi = RNE(x) and lo = RNE(x - hi) (two
+// products per k-step, 16 significant bits of the activation): a single
+// rounding would turn differences of an FP32 ulp in the input into jumps of a
+// BF16 ulp, which the high octaves of the position encoding make frequent.
+// Weight gradients and upstream gradients use single BF16 numbers.
 #pragma once
 #include "common.hpp"
 
@@ -33,9 +39,19 @@ __device__ __forceinline__ bf16x8 pack_bf16x8(float v0, float v1, float v2, floa
   return __builtin_bit_cast(bf16x8, u);
 }
 
+// hi = RNE(v), lo = RNE(v - hi) of eight floats; v - hi is exact in FP32.
+__device__ __forceinline__ void pack_bf16x8_split(const float (&v)[8], bf16x8 &hi, bf16x8 &lo) {
+  hi = pack_bf16x8(v[0], v[1], v[2], v[3], v[4], v[5], v[6], v[7]);
+  float r[8];
+#pragma unroll
+  for (int j = 0; j < 8; j++) r[j] = v[j] - (float)hi[j];
+  lo = pack_bf16x8(r[0], r[1], r[2], r[3], r[4], r[5], r[6], r[7]);
+}
+
 struct MmaF32 {
   static constexpr int KS = 4;   // K per instruction
   static constexpr int KPL = 1;  // K elements held per lane
+  static constexpr int NSPLIT = 1;  // numbers per activation in a forward product
   using Op = float;
   using Elem = float;
   __device__ static __forceinline__ f32x4 mma(Op a, Op b, f32x4 c) {
@@ -48,6 +64,7 @@ struct MmaF32 {
 struct MmaBF16 {
   static constexpr int KS = 32;
   static constexpr int KPL = 8;
+  static constexpr int NSPLIT = 2;
   using Op = bf16x8;
   using Elem = __bf16;
   __device__ static __forceinline__ f32x4 mma(Op a, Op b, f32x4 c) {

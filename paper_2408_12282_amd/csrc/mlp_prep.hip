@@ -8,7 +8,9 @@
 namespace sssgs {
 
 // Forward operands: layer l, 16-row block mb, k-step ks, lane -> W[row][feat].
-template <class M, int WIDTH, int IN_PAD>
+// NATURAL: every layer's K in natural order (inputs read from LDS rows);
+// otherwise layers >= 1 in the permuted order of the accumulator layout.
+template <class M, int WIDTH, int IN_PAD, bool NATURAL>
 __global__ __launch_bounds__(256) void prep_fwd_kernel(const float *__restrict__ params, typename M::Op *wops) {
   using NS = NetShape<M, WIDTH, IN_PAD>;
   using PO = ParamOffsets<WIDTH, IN_PAD>;
@@ -30,11 +32,11 @@ __global__ __launch_bounds__(256) void prep_fwd_kernel(const float *__restrict__
   typename M::Op o;
   if constexpr (M::KPL == 8) {
     for (int j = 0; j < 8; j++) {
-      const int f = feat_index<M>(layer == 0, ks, g, j);
+      const int f = feat_index<M>(NATURAL || layer == 0, ks, g, j);
       o[j] = (__bf16)((row < rows && f < cols) ? W[row * cols + f] : 0.f);
     }
   } else {
-    const int f = feat_index<M>(layer == 0, ks, g, 0);
+    const int f = feat_index<M>(NATURAL || layer == 0, ks, g, 0);
     o = (row < rows && f < cols) ? W[row * cols + f] : 0.f;
   }
   wops[idx] = o;
@@ -76,23 +78,25 @@ __global__ __launch_bounds__(256) void prep_bwd_kernel(const float *__restrict__
 }
 
 template <class M, int WIDTH, int IN_PAD>
-static void prep_t(const float *params, void *wops, void *tops, hipStream_t st) {
+static void prep_t(const float *params, void *wops, void *tops, void *nops, hipStream_t st) {
   using NS = NetShape<M, WIDTH, IN_PAD>;
   const int nf = NS::total_ops(3), nb = NS::total_tops(3);
-  prep_fwd_kernel<M, WIDTH, IN_PAD><<<(nf + 255) / 256, 256, 0, st>>>(params, (typename M::Op *)wops);
-  if (tops) prep_bwd_kernel<M, WIDTH, IN_PAD><<<(nb + 255) / 256, 256, 0, st>>>(params, (typename M::Op *)tops);
+  using Op = typename M::Op;
+  if (wops) prep_fwd_kernel<M, WIDTH, IN_PAD, false><<<(nf + 255) / 256, 256, 0, st>>>(params, (Op *)wops);
+  if (nops) prep_fwd_kernel<M, WIDTH, IN_PAD, true><<<(nf + 255) / 256, 256, 0, st>>>(params, (Op *)nops);
+  if (tops) prep_bwd_kernel<M, WIDTH, IN_PAD><<<(nb + 255) / 256, 256, 0, st>>>(params, (Op *)tops);
 }
 
-void launch_prep_weights(int net, int width, int in_pad, const float *params, void *wops, void *tops,
+void launch_prep_weights(int net, int width, int in_pad, const float *params, void *wops, void *tops, void *nops,
                          hipStream_t st) {
   if (net == 1) {
-    if (width == 64 && in_pad == 64) prep_t<MmaF32, 64, 64>(params, wops, tops, st);
-    else if (width == 64 && in_pad == 96) prep_t<MmaF32, 64, 96>(params, wops, tops, st);
+    if (width == 64 && in_pad == 64) prep_t<MmaF32, 64, 64>(params, wops, tops, nops, st);
+    else if (width == 64 && in_pad == 96) prep_t<MmaF32, 64, 96>(params, wops, tops, nops, st);
   } else if (net == 2) {
-    if (width == 64 && in_pad == 64) prep_t<MmaBF16, 64, 64>(params, wops, tops, st);
-    else if (width == 64 && in_pad == 96) prep_t<MmaBF16, 64, 96>(params, wops, tops, st);
-    else if (width == 128 && in_pad == 64) prep_t<MmaBF16, 128, 64>(params, wops, tops, st);
-    else if (width == 128 && in_pad == 96) prep_t<MmaBF16, 128, 96>(params, wops, tops, st);
+    if (width == 64 && in_pad == 64) prep_t<MmaBF16, 64, 64>(params, wops, tops, nops, st);
+    else if (width == 64 && in_pad == 96) prep_t<MmaBF16, 64, 96>(params, wops, tops, nops, st);
+    else if (width == 128 && in_pad == 64) prep_t<MmaBF16, 128, 64>(params, wops, tops, nops, st);
+    else if (width == 128 && in_pad == 96) prep_t<MmaBF16, 128, 96>(params, wops, tops, nops, st);
   }
 }
 

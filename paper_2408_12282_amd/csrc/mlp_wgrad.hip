@@ -2,8 +2,10 @@
 // (Sec. 3.2, Eq. 6), BF16 operands, width 64, three hidden layers.
 //
 // Input: the strip records of the split shading backward, i.e. per 64-pixel
-// strip the BF16 network input rows as layer 0 reads them and the BF16
-// gradients of the six network outputs.  Each wave takes whole strips: it
+// strip the BF16 network input rows as layer 0 reads them (values and their
+// BF16 remainders) and the BF16 gradients of the six network outputs.  The
+// forward products take activations as hi + lo pairs (mlp.hpp); the weight
+// gradients take hi.  Each wave takes whole strips: it
 // recomputes the forward (for the activations and ReLU masks), runs the
 // backward through the hidden layers, and adds
 //   dW_l += dY_l^T X_l,   db_l += sum over pixels of dY_l
@@ -112,14 +114,17 @@ __device__ __forceinline__ void relu_mask_from_ops(const bf16x8 (&H)[MB / 2][4],
     }
 }
 
-// Layer-0 B operands of a strip from its record rows ([64][stride] BF16).
+// Layer-0 B operands of a strip from its record rows ([64][stride] BF16),
+// starting at element `first` of each row (0: the values, IN_PAD: the
+// remainders).
 template <int KS0>
-__device__ __forceinline__ void load_rows(const __bf16 *xr, int stride, bf16x8 (&X)[KS0][4], int g, int col) {
+__device__ __forceinline__ void load_rows(const __bf16 *xr, int stride, int first, bf16x8 (&X)[KS0][4], int g,
+                                          int col) {
 #pragma unroll
   for (int ks = 0; ks < KS0; ks++)
 #pragma unroll
     for (int nb = 0; nb < 4; nb++)
-      X[ks][nb] = *reinterpret_cast<const bf16x8 *>(xr + (16 * nb + col) * stride + ks * 32 + g * 8);
+      X[ks][nb] = *reinterpret_cast<const bf16x8 *>(xr + (16 * nb + col) * stride + first + ks * 32 + g * 8);
 }
 
 // LDS of a workgroup (input width 64): forward weight operands and biases
@@ -236,7 +241,7 @@ __global__ __launch_bounds__(kWgradWaves * 64, 1) void mlp_wgrad_kernel(const vo
 
 #pragma unroll 1
   for (int s = blockIdx.x * kWgradWaves + w; s < nstrips; s += gridDim.x * kWgradWaves) {
-    const __bf16 *xr = rec_x + (size_t)s * 64 * IN_PAD;
+    const __bf16 *xr = rec_x + (size_t)s * 64 * 2 * IN_PAD;
     const __bf16 *orow = rec_o + (size_t)s * 64 * 8;
     // Weight operands are re-read for every strip (LDS and L2 hits): an
     // opaque zero offset keeps the compiler from hoisting those loop-invariant
@@ -248,26 +253,19 @@ __global__ __launch_bounds__(kWgradWaves * 64, 1) void mlp_wgrad_kernel(const vo
     // forward: activations (H1, H2 to LDS)
     Op H3[KSH][4];
     {
-      Op X0[KS0][4];
-      load_rows<KS0>(xr, IN_PAD, X0, g, col);
+      Op X0[KS0][4], X0lo[KS0][4];
+      load_rows<KS0>(xr, 2 * IN_PAD, 0, X0, g, col);
+      load_rows<KS0>(xr, 2 * IN_PAD, IN_PAD, X0lo, g, col);
       f32x4 acc[MB][4];
-      Op H[KSH][4];
-#pragma unroll
-      for (int ks = 0; ks < KS0; ks++)
-#pragma unroll
-        for (int mb = 0; mb < MB; mb++) {
-          const Op a = wl[(mb * KS0 + ks) * 64 + lane];
-#pragma unroll
-          for (int nb = 0; nb < 4; nb++)
-            acc[mb][nb] = M::mma(a, X0[ks][nb], ks == 0 ? f32x4{0.f, 0.f, 0.f, 0.f} : acc[mb][nb]);
-        }
-      acc_to_ops<M, MB>(acc, bl, g, H);
+      Op H[KSH][4], Hlo[KSH][4];
+      act_mma<M, MB, KS0>(wl, X0, X0lo, acc, lane);
+      acc_to_ops<M, MB>(acc, bl, g, H, Hlo);
       store_ops(hs, H, lane);
-      layer_mma<M, MB, KSH>(wl + NS::L0, H, acc, lane);
-      acc_to_ops<M, MB>(acc, bl + 64, g, H);
+      act_mma<M, MB, KSH>(wl + NS::L0, H, Hlo, acc, lane);
+      acc_to_ops<M, MB>(acc, bl + 64, g, H, Hlo);
       store_ops(hs + KSH * 4 * 64, H, lane);
-      layer_mma<M, MB, KSH>(wl + NS::L0 + NS::LH, H, acc, lane);
-      acc_to_ops<M, MB>(acc, bl + 128, g, H3);
+      act_mma<M, MB, KSH>(wl + NS::L0 + NS::LH, H, Hlo, acc, lane);
+      acc_to_ops<M, MB>(acc, bl + 128, g, H3, Hlo);
     }
     // output layer: dY = output gradients, X = H3 (one 16-row block, rows 0..5)
     Op Bo[1][4];
@@ -302,7 +300,7 @@ __global__ __launch_bounds__(kWgradWaves * 64, 1) void mlp_wgrad_kernel(const vo
     {
       // the input rows again (cache-resident) rather than held across the strip
       Op X0[KS0][4];
-      load_rows<KS0>(xr, IN_PAD, X0, g, col);
+      load_rows<KS0>(xr, 2 * IN_PAD, 0, X0, g, col);
       layer_wgrad<MB, IB0>(Bd, X0, eye, dW0, db0);
     }
   }
@@ -368,6 +366,160 @@ void launch_mlp_wgrad(const void *wops, const void *tops, const float *params, c
                       const __bf16 *rec_o, int nstrips, float *partials, hipStream_t st) {
   mlp_wgrad_kernel<<<mlp_wgrad_grid(nstrips), kWgradWaves * 64, 0, st>>>(wops, tops, params, rec_x, rec_o, nstrips,
                                                                         partials);
+}
+
+
+// ---------------------------------------------------------------- generic form
+//
+// The weight and bias gradients of the other network forms (FP32; BF16 at
+// width 128 or input width 96) from the feature-major operands the generic
+// shading backward stores: dW_l = dY_l X_l^T and db_l = dY_l 1, contractions
+// over all P pixels.  Split K: workgroup (s, y) sums pixels [s S, (s + 1) S)
+// of one layer into row s of the partials (every element of the layer's
+// slice written), and the fixed-order reduction over s follows, so the result
+// does not depend on timing.  Operands are read straight from memory with
+// pixels along K: BF16 as 8 consecutive pixels per lane (16 B), FP32 as a
+// float4 of 4 pixels that serves 4 k-steps (the pixel order inside a sum is
+// free, so k-step t takes pixel 4 g + t of the 16).  The four waves tile the
+// layer's 16 x 16 blocks (WO x WI waves over output x input blocks; the bias
+// is one more input block whose B operand is a column of ones).
+constexpr int kGemmSplit = 4096;  // pixels per workgroup
+
+template <class M, int R16, int K16>
+struct GemmShape {
+  static constexpr int WO = R16 < 4 ? R16 : 4, WI = 4 / WO;
+  static constexpr int NOB = (R16 + WO - 1) / WO, NIB = (K16 + 1 + WI - 1) / WI;
+  static constexpr int KC = M::KPL == 8 ? 32 : 16;  // pixels per step
+};
+
+template <class M, int R16, int K16>
+__global__ __launch_bounds__(256) void wgrad_gemm_kernel(const typename M::Elem *__restrict__ dy0,
+                                                         const typename M::Elem *__restrict__ x0, size_t layer_dy,
+                                                         size_t layer_x, int rows_alloc, int rows, int cols,
+                                                         size_t P, float *__restrict__ partials, int nparams,
+                                                         int woff0, int param_step) {
+  using E = typename M::Elem;
+  using Op = typename M::Op;
+  using GS = GemmShape<M, R16, K16>;
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, g = lane >> 4, col = lane & 15;
+  const int wo = w % GS::WO, wi = w / GS::WO;
+  const E *dy = dy0 + (size_t)blockIdx.y * layer_dy;
+  const E *x = x0 + (size_t)blockIdx.y * layer_x;
+  const int woff = woff0 + blockIdx.y * param_step, boff = woff + rows * cols;
+  const size_t pa = (size_t)blockIdx.x * kGemmSplit, pb = pa + kGemmSplit < P ? pa + kGemmSplit : P;
+  f32x4 acc[GS::NOB][GS::NIB];
+#pragma unroll
+  for (int a = 0; a < GS::NOB; a++)
+#pragma unroll
+    for (int b = 0; b < GS::NIB; b++) acc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
+  for (size_t p = pa; p < pb; p += GS::KC) {
+    if constexpr (M::KPL == 8) {
+      Op A[GS::NOB], B[GS::NIB];
+#pragma unroll
+      for (int a = 0; a < GS::NOB; a++) {
+        const int r = 16 * (wo + GS::WO * a) + col;
+        A[a] = r < rows_alloc ? *reinterpret_cast<const bf16x8 *>(dy + (size_t)r * P + p + 8 * g) : Op{};
+      }
+#pragma unroll
+      for (int b = 0; b < GS::NIB; b++) {
+        const int ib = wi + GS::WI * b;
+        if (ib < K16) {
+          B[b] = *reinterpret_cast<const bf16x8 *>(x + (size_t)(16 * ib + col) * P + p + 8 * g);
+        } else {
+#pragma unroll
+          for (int j = 0; j < 8; j++) B[b][j] = (__bf16)(col == 0 ? 1.f : 0.f);
+        }
+      }
+#pragma unroll
+      for (int a = 0; a < GS::NOB; a++)
+#pragma unroll
+        for (int b = 0; b < GS::NIB; b++)
+          if (wo + GS::WO * a < R16 && wi + GS::WI * b <= K16) acc[a][b] = M::mma(A[a], B[b], acc[a][b]);
+    } else {
+      float4 A[GS::NOB], B[GS::NIB];
+#pragma unroll
+      for (int a = 0; a < GS::NOB; a++) {
+        const int r = 16 * (wo + GS::WO * a) + col;
+        A[a] = r < rows_alloc ? *reinterpret_cast<const float4 *>(dy + (size_t)r * P + p + 4 * g)
+                              : make_float4(0.f, 0.f, 0.f, 0.f);
+      }
+#pragma unroll
+      for (int b = 0; b < GS::NIB; b++) {
+        const int ib = wi + GS::WI * b;
+        const float one = col == 0 ? 1.f : 0.f;
+        B[b] = ib < K16 ? *reinterpret_cast<const float4 *>(x + (size_t)(16 * ib + col) * P + p + 4 * g)
+                        : make_float4(one, one, one, one);
+      }
+#pragma unroll
+      for (int a = 0; a < GS::NOB; a++)
+#pragma unroll
+        for (int b = 0; b < GS::NIB; b++)
+          if (wo + GS::WO * a < R16 && wi + GS::WI * b <= K16) {
+            acc[a][b] = M::mma(A[a].x, B[b].x, acc[a][b]);
+            acc[a][b] = M::mma(A[a].y, B[b].y, acc[a][b]);
+            acc[a][b] = M::mma(A[a].z, B[b].z, acc[a][b]);
+            acc[a][b] = M::mma(A[a].w, B[b].w, acc[a][b]);
+          }
+    }
+  }
+  // D layout: lane (col, g) holds block rows 4 g + j, block column col
+  float *part = partials + (size_t)blockIdx.x * nparams;
+#pragma unroll
+  for (int a = 0; a < GS::NOB; a++)
+#pragma unroll
+    for (int b = 0; b < GS::NIB; b++) {
+      const int ob = wo + GS::WO * a, ib = wi + GS::WI * b;
+      if (ob >= R16 || ib > K16) continue;
+#pragma unroll
+      for (int j = 0; j < 4; j++) {
+        const int o = 16 * ob + 4 * g + j;
+        if (o >= rows) continue;
+        if (ib < K16) {
+          const int i = 16 * ib + col;
+          if (i < cols) part[woff + o * cols + i] = acc[a][b][j];
+        } else if (col == 0) {
+          part[boff + o] = acc[a][b][j];
+        }
+      }
+    }
+}
+
+template <class M, int R16, int K16>
+static void gemm_layer(const void *dy, const void *x, size_t ldy, size_t lx, int nl, int rows_alloc, int rows,
+                       int cols, size_t P, float *partials, int nparams, int woff, int step, hipStream_t st) {
+  const dim3 grid((unsigned)((P + kGemmSplit - 1) / kGemmSplit), nl);
+  wgrad_gemm_kernel<M, R16, K16><<<grid, 256, 0, st>>>(reinterpret_cast<const typename M::Elem *>(dy),
+                                                       reinterpret_cast<const typename M::Elem *>(x), ldy, lx,
+                                                       rows_alloc, rows, cols, P, partials, nparams, woff, step);
+}
+
+template <class M, int WIDTH, int IN_PAD>
+static void wgrad_gemm_t(const void *gx, const void *gdy, size_t P, float *partials, hipStream_t st) {
+  using PO = ParamOffsets<WIDTH, IN_PAD>;
+  using E = typename M::Elem;
+  const E *X = reinterpret_cast<const E *>(gx), *Y = reinterpret_cast<const E *>(gdy);
+  const int np = PO::total();
+  const E *X1 = X + (size_t)IN_PAD * P, *X3 = X1 + 2 * (size_t)WIDTH * P;
+  const E *Y1 = Y + (size_t)WIDTH * P, *Y3 = Y1 + 2 * (size_t)WIDTH * P;
+  gemm_layer<M, WIDTH / 16, IN_PAD / 16>(Y, X, 0, 0, 1, WIDTH, WIDTH, IN_PAD, P, partials, np, PO::w(0), 0, st);
+  gemm_layer<M, WIDTH / 16, WIDTH / 16>(Y1, X1, (size_t)WIDTH * P, (size_t)WIDTH * P, 2, WIDTH, WIDTH, WIDTH, P,
+                                        partials, np, PO::w(1), PO::w(2) - PO::w(1), st);
+  gemm_layer<M, 1, WIDTH / 16>(Y3, X3, 0, 0, 1, 8, 6, WIDTH, P, partials, np, PO::w(3), 0, st);
+}
+
+int wgrad_gemm_splits(size_t P) { return (int)((P + kGemmSplit - 1) / kGemmSplit); }
+
+void launch_wgrad_gemm(int net, int width, int in_pad, const void *gx, const void *gdy, size_t P, float *partials,
+                       hipStream_t st) {
+  if (net == 1) {
+    if (width == 64 && in_pad == 64) wgrad_gemm_t<MmaF32, 64, 64>(gx, gdy, P, partials, st);
+    else if (width == 64 && in_pad == 96) wgrad_gemm_t<MmaF32, 64, 96>(gx, gdy, P, partials, st);
+  } else if (net == 2) {
+    if (width == 64 && in_pad == 64) wgrad_gemm_t<MmaBF16, 64, 64>(gx, gdy, P, partials, st);
+    else if (width == 64 && in_pad == 96) wgrad_gemm_t<MmaBF16, 64, 96>(gx, gdy, P, partials, st);
+    else if (width == 128 && in_pad == 64) wgrad_gemm_t<MmaBF16, 128, 64>(gx, gdy, P, partials, st);
+    else if (width == 128 && in_pad == 96) wgrad_gemm_t<MmaBF16, 128, 96>(gx, gdy, P, partials, st);
+  }
 }
 
 }  // namespace sssgs

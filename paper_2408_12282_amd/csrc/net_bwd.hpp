@@ -24,7 +24,8 @@ __device__ __forceinline__ void grad_to_ops(const f32x4 (&d)[MB][4], typename M:
     }
 }
 
-// One forward layer from B operands H (K = WIDTH) to accumulators.
+// One product from single B operands H (K = KSN k-steps) to accumulators:
+// the gradient products of the backward (dX^T = W^T dY^T).
 template <class M, int MB, int KSN>
 __device__ __forceinline__ void layer_mma(const typename M::Op *__restrict__ w, const typename M::Op (&H)[KSN][4],
                                           f32x4 (&acc)[MB][4], int lane) {
@@ -38,24 +39,6 @@ __device__ __forceinline__ void layer_mma(const typename M::Op *__restrict__ w, 
       for (int nb = 0; nb < 4; nb++)
         acc[mb][nb] = M::mma(a, H[ks][nb], ks == 0 ? f32x4{0.f, 0.f, 0.f, 0.f} : acc[mb][nb]);
     }
-}
-
-template <class M, int MB, int KS0>
-__device__ __forceinline__ void layer0_mma(const typename M::Op *__restrict__ w, const typename M::Elem *xs, int XS,
-                                           f32x4 (&acc)[MB][4], int lane) {
-  const int g = lane >> 4, col = lane & 15;
-#pragma unroll
-  for (int ks = 0; ks < KS0; ks++) {
-    typename M::Op B[4];
-#pragma unroll
-    for (int nb = 0; nb < 4; nb++) B[nb] = load_op_lds<M>(xs + (16 * nb + col) * XS + ks * M::KS + g * M::KPL);
-#pragma unroll
-    for (int mb = 0; mb < MB; mb++) {
-      const typename M::Op a = w[(mb * KS0 + ks) * 64 + lane];
-#pragma unroll
-      for (int nb = 0; nb < 4; nb++) acc[mb][nb] = M::mma(a, B[nb], ks == 0 ? f32x4{0.f, 0.f, 0.f, 0.f} : acc[mb][nb]);
-    }
-  }
 }
 
 // ReLU masks of one layer's outputs in D layout, one bit per (mb, nb, j).
@@ -95,6 +78,13 @@ struct Mask {
         const int b = mb * 16 + nb * 4;
         w[b >> 5] |= bits << (b & 31);
       }
+  }
+  // Materialise the words here: otherwise the compiler may sink the
+  // comparisons to the masks' use in the backward and keep the forward's
+  // accumulators alive until then.
+  __device__ __forceinline__ void pin() {
+#pragma unroll
+    for (int k = 0; k < (MB * 16 + 31) / 32; k++) asm volatile("" : "+v"(w[k]));
   }
   __device__ __forceinline__ void apply(f32x4 (&d)[MB][4]) const {
 #pragma unroll

@@ -19,7 +19,7 @@ __global__ __launch_bounds__(256) void shade_fwd_kernel(ShadeArgs A, MultiLight 
   using M = typename NetTraits<NET>::M;
   using E = typename M::Elem;
   constexpr int C = kChFeat + F;
-  constexpr int XS = IN_PAD + XPad<M>::value;  // LDS row stride (elements)
+  constexpr int XS = in_row_stride<M, IN_PAD>();  // LDS row stride (elements)
   __shared__ E xs[kIsNet<NET> ? 4 * 64 * XS : 1];
   __shared__ float outs[kIsNet<NET> ? 4 * 64 * 8 : 1];
   const int tile = blockIdx.x;
@@ -55,7 +55,7 @@ __global__ __launch_bounds__(256) void shade_fwd_kernel(ShadeArgs A, MultiLight 
     } else if constexpr (NET != 0) {
       // the network input row differs between lights only in w_i
       if (k == 0) build_net_input<F, IN_PAD, M>(gb, S, xrow);
-      else set_net_light<F, M>(S, xrow);
+      else set_net_light<F, IN_PAD, M>(S, xrow);
       __syncthreads();
       net_forward_wave<M, WIDTH, IN_PAD, false>(A.wops, A.params, xs + w * 64 * XS, XS, outs + w * 64 * 8, nullptr);
       __syncthreads();
@@ -63,7 +63,7 @@ __global__ __launch_bounds__(256) void shade_fwd_kernel(ShadeArgs A, MultiLight 
     }
 #pragma unroll
     for (int c = 0; c < 3; c++) {
-      const float v = S.bg ? 0.f : S.a * S.L[c];
+      const float v = (S.bg ? 0.f : S.a * S.L[c]) + T * A.bgc[c];
       acc[c] = MULTI ? __fmaf_rn(ML.weight[k][c], v, acc[c]) : v;
     }
   }

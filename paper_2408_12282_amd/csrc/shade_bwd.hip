@@ -1,138 +1,22 @@
 // shade_bwd.hip -- backward of the per-pixel deferred shading (Sec. 3.2,
 // Eq. 4, 6, 7): from dL/d(rgb) to dL/d(G-buffer), dL/d(T_final) and the
-// network parameter gradients.
+// operands of the network parameter gradients.
 //
-// Persistent grid; each wave shades 64-pixel strips (16 x 4).  The network
-// forward is recomputed (layer 3 input kept, layers 1-2 recomputed as
-// needed); input gradients use the transposed weights on the matrix cores
-// (dX^T = W^T dY^T, consuming the accumulator layout directly); weight
-// gradients dW = dY^T X are computed per workgroup over the strips of all its
-// waves (K = 64 x waves pixels, staged through LDS) and added to a
-// per-workgroup partial; the first strips store, later ones add with
-// no-return float atomics, so no wave stalls on a read-modify-write, and
-// every address is written by one wave only, so the sums are deterministic.
+// One wave per 64-pixel strip (16 x 4).  With the per-pixel network the
+// forward is recomputed on the matrix cores, Eq. 7's backward gives the
+// gradients of the six network outputs, and dX^T = W^T dY^T runs through the
+// transposed layers (consuming the accumulator layout directly) down to the
+// gradient of the network input, whose per-pixel backward gives dL/dG.  The
+// weight gradients dW = dY^T X, a contraction over all pixels, are left to
+// mlp_wgrad.hip: the BF16 width-64 network (the headline form, split kernel
+// below) leaves per strip its input rows and output gradients and the weight
+// kernel recomputes the rest; the other forms (generic kernel below) store
+// every layer's input X_l and pre-activation gradient dY_l, feature-major,
+// for a split-K matrix-core contraction.
 #include "launch.hpp"
 #include "net_bwd.hpp"
 
 namespace sssgs {
-
-// Staging of the weight-gradient operands.  For BF16 (8 pixels per lane and
-// k-step) both factors are stored feature-major [feat][px]; for FP32 (one
-// pixel per lane and k-step) pixel-major [px][feat].
-template <class M>
-struct Stage {
-  static constexpr bool FM = M::KPL == 8;  // feature-major
-  static constexpr int PXS = 64 + 8;       // feature-major row stride (elements)
-  __device__ static __forceinline__ int idx(int feat, int px, int fstride) {
-    return FM ? feat * PXS + px : px * fstride + feat;
-  }
-};
-
-// Workgroup weight gradient of one layer over the NW strips its waves have
-// staged (K = 64 NW pixels): dW[o][k] = sum_p dY[o][p] X[k][p] and the bias
-// gradient db[o] = sum_p dY[o][p] (the product with an all-ones column).
-// Wave w computes the 16-row blocks mbo = w, w + NW, ... and stores them
-// into (first call) or adds them to (later calls, with no-return float
-// atomics) the workgroup's partial at W offset woff (row-major [rows][cols])
-// and bias offset boff.  Every address of the partial is written by one wave
-// only, so the sums are deterministic.
-template <class M, int ROWS16, int KCOLS, int NW>
-__device__ __forceinline__ void dw_block(const typename M::Elem *st_all, int stage_elems, int fst,
-                                         float *__restrict__ part, int woff, int boff, int rows, int cols,
-                                         bool first, int w, int lane) {
-  using Op = typename M::Op;
-  using E = typename M::Elem;
-  using ST = Stage<M>;
-  constexpr int MBO = ROWS16 / 16, NBK = KCOLS / 16, KSW = 64 / M::KS;
-  const int g = lane >> 4, col = lane & 15;
-  Op ones;
-  if constexpr (M::KPL == 8) {
-#pragma unroll
-    for (int j = 0; j < 8; j++) ones[j] = (__bf16)(col == 0 ? 1.f : 0.f);
-  } else {
-    ones = col == 0 ? 1.f : 0.f;
-  }
-#pragma unroll 1
-  for (int mbo = w; mbo < MBO; mbo += NW) {
-    f32x4 acc[NBK + 1];
-#pragma unroll
-    for (int nbk = 0; nbk <= NBK; nbk++) acc[nbk] = f32x4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll 1
-    for (int v = 0; v < NW; v++) {
-      const E *dy = st_all + v * 2 * stage_elems;
-      const E *xk = dy + stage_elems;
-#pragma unroll
-      for (int ks = 0; ks < KSW; ks++) {
-        const int px0 = ks * M::KS + g * M::KPL;
-        Op a;
-        if constexpr (M::KPL == 8) a = *reinterpret_cast<const bf16x8 *>(dy + ST::idx(16 * mbo + col, px0, fst));
-        else a = dy[ST::idx(16 * mbo + col, px0, fst)];
-#pragma unroll
-        for (int nbk = 0; nbk < NBK; nbk++) {
-          Op b;
-          if constexpr (M::KPL == 8) b = *reinterpret_cast<const bf16x8 *>(xk + ST::idx(16 * nbk + col, px0, fst));
-          else b = xk[ST::idx(16 * nbk + col, px0, fst)];
-          acc[nbk] = M::mma(a, b, acc[nbk]);
-        }
-        acc[NBK] = M::mma(a, ones, acc[NBK]);
-      }
-    }
-    // D layout: lane (col, g) holds dW[16 mbo + 4 g + j][16 nbk + col]; the bias in column 0
-#pragma unroll
-    for (int nbk = 0; nbk < NBK; nbk++)
-#pragma unroll
-      for (int j = 0; j < 4; j++) {
-        const int o = 16 * mbo + 4 * g + j, k = 16 * nbk + col;
-        if (o < rows && k < cols) {
-          float *p = part + woff + o * cols + k;
-          if (first) *p = acc[nbk][j];
-          else atomicAdd(p, acc[nbk][j]);
-        }
-      }
-    if (col == 0)
-#pragma unroll
-      for (int j = 0; j < 4; j++) {
-        const int o = 16 * mbo + 4 * g + j;
-        if (o < rows) {
-          float *p = part + boff + o;
-          if (first) *p = acc[NBK][j];
-          else atomicAdd(p, acc[NBK][j]);
-        }
-      }
-  }
-}
-
-// Write D-layout values (feature f = 16 mb + 4 g + j, pixel 16 nb + col) into a stage.
-template <class M, int MB>
-__device__ __forceinline__ void stage_d(const f32x4 (&d)[MB][4], typename M::Elem *st, int fstride, int lane) {
-  using ST = Stage<M>;
-  const int g = lane >> 4, col = lane & 15;
-#pragma unroll
-  for (int mb = 0; mb < MB; mb++)
-#pragma unroll
-    for (int nb = 0; nb < 4; nb++)
-#pragma unroll
-      for (int j = 0; j < 4; j++) st[ST::idx(16 * mb + 4 * g + j, 16 * nb + col, fstride)] = M::cvt(d[mb][nb][j]);
-}
-
-// Write B-operand activations (permuted features) into a stage at their true feature index.
-template <class M, int KSN>
-__device__ __forceinline__ void stage_ops(const typename M::Op (&H)[KSN][4], typename M::Elem *st, int fstride,
-                                          int lane) {
-  using ST = Stage<M>;
-  const int g = lane >> 4, col = lane & 15;
-#pragma unroll
-  for (int ks = 0; ks < KSN; ks++)
-#pragma unroll
-    for (int nb = 0; nb < 4; nb++) {
-      if constexpr (M::KPL == 8) {
-#pragma unroll
-        for (int j = 0; j < 8; j++) st[ST::idx(feat_index<M>(false, ks, g, j), 16 * nb + col, fstride)] = H[ks][nb][j];
-      } else {
-        st[ST::idx(feat_index<M>(false, ks, g, 0), 16 * nb + col, fstride)] = H[ks][nb];
-      }
-    }
-}
 
 // -------------------------------------------------------------- per pixel
 
@@ -275,15 +159,6 @@ __device__ __forceinline__ float shade_pixel_bwd(const PixShade &S, const float 
 
 // -------------------------------------------------------------- kernel
 
-// Waves per workgroup: bounded by the LDS each wave needs (160 KB per CU).
-template <int NET, int WIDTH, int IN_PAD> struct BwdWaves {
-  static constexpr int value = !kIsNet<NET> ? 4 : ((NET == 2 && WIDTH == 64 && IN_PAD == 64) ? 4 : 2);
-};
-
-int shade_bwd_waves(int net, int width, int in_pad) {
-  return (net == 0 || net == 3) ? 4 : ((net == 2 && width == 64 && in_pad == 64) ? 4 : 2);
-}
-
 // Per-pixel inputs of the shading backward (reloaded in each per-pixel phase
 // instead of being kept live across the network phases).
 template <int C>
@@ -313,6 +188,8 @@ __device__ __forceinline__ void write_pixel_grads(const ShadeArgs &A, bool insid
     dT = -dA;
   }
   if (A.dalpha_ext) dT -= A.dalpha_ext[pix];
+  // rgb = ... + T_final background
+  for (int c = 0; c < 3; c++) dT += A.drgb[c * HW + pix] * A.bgc[c];
   A.dT[pix] = dT;
 #pragma unroll
   for (int k = 0; k < C; k++) {
@@ -322,235 +199,26 @@ __device__ __forceinline__ void write_pixel_grads(const ShadeArgs &A, bool insid
   }
 }
 
-template <int F, int NET, int WIDTH, int IN_PAD>
-__global__ __launch_bounds__((BwdWaves<NET, WIDTH, IN_PAD>::value * 64)) void shade_bwd_kernel(ShadeArgs A, int nstrips) {
-  using M = typename NetTraits<NET>::M;
-  using E = typename M::Elem;
-  using Op = typename M::Op;
-  using NS = NetShape<M, WIDTH, IN_PAD>;
-  using PO = ParamOffsets<WIDTH, IN_PAD>;
-  using ST = Stage<M>;
-  constexpr int NW = BwdWaves<NET, WIDTH, IN_PAD>::value;
+// Without a per-pixel network (light fall-off, or radiances composited from
+// the per-Gaussian network): one lane per pixel, one 256-lane workgroup per
+// tile.
+template <int F, int NET>
+__global__ __launch_bounds__(256) void shade_bwd_plain_kernel(ShadeArgs A) {
   constexpr int C = kChFeat + F;
-  constexpr int MB = NS::MB;
-  constexpr int XS = IN_PAD + XPad<M>::value;
-  constexpr int FMAX = WIDTH > IN_PAD ? WIDTH : IN_PAD;
-  constexpr int FST = FMAX + 4;  // pixel-major stage stride (FP32)
-  constexpr int STAGE_ELEMS = ST::FM ? FMAX * ST::PXS : 64 * FST;
-  constexpr int XS_ELEMS = 64 * XS;
-  // per wave: network input rows, two weight-gradient stages, outputs + their gradients
-  constexpr bool NETW = kIsNet<NET>;
-  __shared__ E xs_all[NETW ? NW * XS_ELEMS : 1];
-  __shared__ E st_all[NETW ? NW * 2 * STAGE_ELEMS : 1];
-  __shared__ float io_all[NETW ? NW * 64 * 16 : 1];
-  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int g = lane >> 4, col = lane & 15;
-  E *xs = xs_all + (NETW ? w * XS_ELEMS : 0);
-  E *sdy = st_all + (NETW ? w * 2 * STAGE_ELEMS : 0);
-  E *sxk = sdy + (NETW ? STAGE_ELEMS : 0);
-  float *io = io_all + (NETW ? w * 64 * 16 : 0);  // [px][0..7] outputs, [px][8..15] output gradients
-  float *dxin = reinterpret_cast<float *>(sdy);  // [64][IN_PAD + 1] after the last weight gradient
-  float *part = A.mlp_partials ? A.mlp_partials + (size_t)blockIdx.x * A.nparams : nullptr;
-  const size_t HW = (size_t)A.cam.W * A.cam.H;
-  bool first = true;
-  for (int s0 = blockIdx.x * NW; s0 < nstrips; s0 += gridDim.x * NW) {
-    const int strip = s0 + w;
-    const int tile = strip >> 2, sub = strip & 3;
-    const int tx = tile % A.cam.TX, ty = tile / A.cam.TX;
-    const int px = tx * kTile + (lane & 15), py = ty * kTile + 4 * sub + (lane >> 4);
-    const bool inside = strip < nstrips && px < A.cam.W && py < A.cam.H;
-    const size_t pix = inside ? (size_t)py * A.cam.W + px : 0;
-    const float uc = (float)px + 0.5f, vc = (float)py + 0.5f;
-    if constexpr (!NETW) {
-      float gb[C], T, gL[3], dgbar[C];
-      load_pixel<C>(A, inside, pix, HW, gb, T, gL);
-      PixShade S;
-      shade_geometry<C>(gb, T, uc, vc, A.cam, A.light, NET == 3, S);
-      if constexpr (NET == 3) combine_features(S, gb);
-      if (S.bg) gL[0] = gL[1] = gL[2] = 0.f;
-      const float dA = shade_pixel_bwd<C, F, NET == 3 ? 2 : 0>(S, gb, gL, A.light, nullptr, dgbar);
-      write_pixel_grads<C, F>(A, inside, pix, HW, S, gb, dgbar, dA);
-    } else {
-      // Weight operands are re-read for every strip (cache hits): an opaque
-      // zero offset keeps the compiler from hoisting these loop-invariant
-      // loads out of the persistent loop, which would pin them in registers.
-      int z;
-      asm volatile("v_mov_b32 %0, 0" : "=v"(z));
-      const Op *wops = reinterpret_cast<const Op *>(A.wops) + z;
-      const Op *tops = reinterpret_cast<const Op *>(A.tops) + z;
-      // ---- A: network input rows
-      {
-        float gb[C], T, gL[3];
-        load_pixel<C>(A, inside, pix, HW, gb, T, gL);
-        PixShade S;
-        shade_geometry<C>(gb, T, uc, vc, A.cam, A.light, true, S);
-        build_net_input<F, IN_PAD, M>(gb, S, xs + lane * XS);
-      }
-      __syncthreads();
-      // ---- B: network forward; keep the layer-3 input and the ReLU masks
-      Mask<MB> m1, m2, m3;
-      Op H3[NS::KSH][4];
-      {
-        f32x4 acc[MB][4];
-        Op H[NS::KSH][4];
-        __builtin_amdgcn_sched_barrier(0);
-        __builtin_amdgcn_sched_barrier(0);
-      layer0_mma<M, MB, NS::KS0>(wops, xs, XS, acc, lane);
-        m1.set_from(acc, A.params + PO::b(0), g);
-        acc_to_ops<M, MB>(acc, A.params + PO::b(0), g, H);
-        __builtin_amdgcn_sched_barrier(0);
-        __builtin_amdgcn_sched_barrier(0);
-      layer_mma<M, MB, NS::KSH>(wops + NS::L0, H, acc, lane);
-        m2.set_from(acc, A.params + PO::b(1), g);
-        acc_to_ops<M, MB>(acc, A.params + PO::b(1), g, H);
-        __builtin_amdgcn_sched_barrier(0);
-        __builtin_amdgcn_sched_barrier(0);
-      layer_mma<M, MB, NS::KSH>(wops + NS::L0 + NS::LH, H, acc, lane);
-        m3.set_from(acc, A.params + PO::b(2), g);
-        acc_to_ops<M, MB>(acc, A.params + PO::b(2), g, H3);
-      }
-      {
-        f32x4 oacc[1][4];
-        layer_mma<M, 1, NS::KSH>(wops + NS::L0 + 2 * NS::LH, H3, oacc, lane);
-        if (g < 2)
-#pragma unroll
-          for (int nb = 0; nb < 4; nb++)
-#pragma unroll
-            for (int j = 0; j < 4; j++) {
-              const int o = 4 * g + j;
-              io[(16 * nb + col) * 16 + o] = oacc[0][nb][j] + (o < 6 ? A.params[PO::b(3) + o] : 0.f);
-            }
-      }
-      __syncthreads();
-      // ---- C: per pixel, Eq. 7 and the gradient of the network outputs
-      {
-        float gb[C], T, gL[3];
-        load_pixel<C>(A, inside, pix, HW, gb, T, gL);
-        PixShade S;
-        shade_geometry<C>(gb, T, uc, vc, A.cam, A.light, true, S);
-        if (S.bg) gL[0] = gL[1] = gL[2] = 0.f;
-        float o[6];
-        for (int k = 0; k < 6; k++) o[k] = io[lane * 16 + k];
-        combine_net(S, gb[kChSss], o);
-        const float sss = gb[kChSss] * S.ia;
-        for (int c = 0; c < 3; c++) {
-          const float gLo = S.a * gL[c];
-          const float dLin = gLo * (1.f - sss) * (S.fs[c] + S.fd[c]) * S.cosI;
-          io[lane * 16 + 8 + c] = o[c] > 0.f ? dLin : 0.f;
-          io[lane * 16 + 11 + c] = gLo * sss * S.Lsss[c] * (1.f - S.Lsss[c]);
-        }
-        io[lane * 16 + 14] = 0.f;
-        io[lane * 16 + 15] = 0.f;
-      }
-      __syncthreads();
-      // ---- D: network backward
-      Op Bd[NS::KSH][4];
-      {
-        f32x4 dO[1][4];
-#pragma unroll
-        for (int nb = 0; nb < 4; nb++)
-#pragma unroll
-          for (int j = 0; j < 4; j++) dO[0][nb][j] = (g < 2) ? io[(16 * nb + col) * 16 + 8 + 4 * g + j] : 0.f;
-        stage_d<M, 1>(dO, sdy, FST, lane);
-        stage_ops<M, NS::KSH>(H3, sxk, FST, lane);
-        __syncthreads();
-        __builtin_amdgcn_sched_barrier(0);
-        __builtin_amdgcn_sched_barrier(0);
-      dw_block<M, 16, WIDTH, NW>(st_all, STAGE_ELEMS, FST, part, PO::w(3), PO::b(3), 6, WIDTH, first, w, lane);
-        Op Bo[NS::KT_O][4];
-#pragma unroll
-        for (int ks = 0; ks < NS::KT_O; ks++)
-#pragma unroll
-          for (int nb = 0; nb < 4; nb++) {
-            if constexpr (M::KPL == 8) {
-              bf16x8 v;
-#pragma unroll
-              for (int j = 0; j < 8; j++) v[j] = (__bf16)(j < 4 ? dO[0][nb][j] : 0.f);
-              Bo[ks][nb] = v;
-            } else {
-              Bo[ks][nb] = dO[0][nb][ks];
-            }
-          }
-        f32x4 dH[MB][4];
-        __builtin_amdgcn_sched_barrier(0);
-        __builtin_amdgcn_sched_barrier(0);
-      layer_mma<M, MB, NS::KT_O>(tops + NS::T0 + 2 * NS::TH, Bo, dH, lane);
-        m3.apply(dH);                       // upstream of layer 2's pre-activation
-        __syncthreads();
-        stage_d<M, MB>(dH, sdy, FST, lane);
-        grad_to_ops<M, MB>(dH, Bd);
-      }
-#pragma unroll 1
-      for (int l = 2; l >= 1; l--) {
-        // recompute this layer's input h_l from the input rows
-        {
-          f32x4 acc[MB][4];
-          Op H[NS::KSH][4];
-          __builtin_amdgcn_sched_barrier(0);
-        __builtin_amdgcn_sched_barrier(0);
-      layer0_mma<M, MB, NS::KS0>(wops, xs, XS, acc, lane);
-          acc_to_ops<M, MB>(acc, A.params + PO::b(0), g, H);
-          if (l == 2) {
-            __builtin_amdgcn_sched_barrier(0);
-        __builtin_amdgcn_sched_barrier(0);
-      layer_mma<M, MB, NS::KSH>(wops + NS::L0, H, acc, lane);
-            acc_to_ops<M, MB>(acc, A.params + PO::b(1), g, H);
-          }
-          stage_ops<M, NS::KSH>(H, sxk, FST, lane);
-        }
-        __syncthreads();
-        __builtin_amdgcn_sched_barrier(0);
-        __builtin_amdgcn_sched_barrier(0);
-      dw_block<M, WIDTH, WIDTH, NW>(st_all, STAGE_ELEMS, FST, part, PO::w(l), PO::b(l), WIDTH, WIDTH, first, w,
-                                    lane);
-        f32x4 dH[MB][4];
-        __builtin_amdgcn_sched_barrier(0);
-        __builtin_amdgcn_sched_barrier(0);
-      layer_mma<M, MB, NS::KT_H>(tops + NS::T0 + (l - 1) * NS::TH, Bd, dH, lane);
-        if (l == 2) m2.apply(dH);
-        else m1.apply(dH);
-        __syncthreads();
-        stage_d<M, MB>(dH, sdy, FST, lane);
-        grad_to_ops<M, MB>(dH, Bd);
-      }
-      // layer 0: weight gradient with the input rows, input gradient W0^T dpre0
-      for (int k = 0; k < IN_PAD; k++) sxk[ST::idx(k, lane, FST)] = xs[lane * XS + k];
-      __syncthreads();
-      __builtin_amdgcn_sched_barrier(0);
-      dw_block<M, WIDTH, IN_PAD, NW>(st_all, STAGE_ELEMS, FST, part, PO::w(0), PO::b(0), WIDTH, IN_PAD, first, w,
-                                     lane);
-      {
-        f32x4 dX[NS::MB0][4];
-        __builtin_amdgcn_sched_barrier(0);
-        __builtin_amdgcn_sched_barrier(0);
-      layer_mma<M, NS::MB0, NS::KT_H>(tops, Bd, dX, lane);
-        __syncthreads();
-#pragma unroll
-        for (int mb = 0; mb < NS::MB0; mb++)
-#pragma unroll
-          for (int nb = 0; nb < 4; nb++)
-#pragma unroll
-            for (int j = 0; j < 4; j++) dxin[(16 * nb + col) * (IN_PAD + 1) + 16 * mb + 4 * g + j] = dX[mb][nb][j];
-      }
-      __syncthreads();
-      // ---- E: per pixel backward of geometry, BRDF and Eq. 7
-      {
-        float gb[C], T, gL[3], dgbar[C];
-        load_pixel<C>(A, inside, pix, HW, gb, T, gL);
-        PixShade S;
-        shade_geometry<C>(gb, T, uc, vc, A.cam, A.light, true, S);
-        if (S.bg) gL[0] = gL[1] = gL[2] = 0.f;
-        float o[6];
-        for (int k = 0; k < 6; k++) o[k] = io[lane * 16 + k];
-        combine_net(S, gb[kChSss], o);
-        const float *din = dxin + lane * (IN_PAD + 1);
-        const float dA = shade_pixel_bwd<C, F, 1>(S, gb, gL, A.light, din, dgbar);
-        write_pixel_grads<C, F>(A, inside, pix, HW, S, gb, dgbar, dA);
-      }
-      first = false;
-      __syncthreads();
-    }
-  }
+  const int tile = blockIdx.x;
+  const int tx = tile % A.cam.TX, ty = tile / A.cam.TX;
+  const int px = tx * kTile + (threadIdx.x & 15), py = ty * kTile + (threadIdx.x >> 4);
+  const bool inside = px < A.cam.W && py < A.cam.H;
+  if (!inside) return;
+  const size_t HW = (size_t)A.cam.W * A.cam.H, pix = (size_t)py * A.cam.W + px;
+  float gb[C], T, gL[3], dgbar[C];
+  load_pixel<C>(A, true, pix, HW, gb, T, gL);
+  PixShade S;
+  shade_geometry<C>(gb, T, (float)px + 0.5f, (float)py + 0.5f, A.cam, A.light, NET == 3, S);
+  if constexpr (NET == 3) combine_features(S, gb);
+  if (S.bg) gL[0] = gL[1] = gL[2] = 0.f;
+  const float dA = shade_pixel_bwd<C, F, NET == 3 ? 2 : 0>(S, gb, gL, A.light, nullptr, dgbar);
+  write_pixel_grads<C, F>(A, true, pix, HW, S, gb, dgbar, dA);
 }
 
 // ---------------------------------------------------------------- split form
@@ -561,12 +229,13 @@ __global__ __launch_bounds__((BwdWaves<NET, WIDTH, IN_PAD>::value * 64)) void sh
 // and the network outputs with their gradients: about 20 KB, and no
 // workgroup-wide exchange, so each wave shades one strip on its own and two
 // waves fit per SIMD.  For the weight-gradient kernel it leaves a record per
-// strip: the BF16 network input rows as layer 0 reads them ([64][IN_PAD]) and
+// strip: the BF16 network input rows as layer 0 reads them ([64][2 IN_PAD],
+// the values rounded to BF16 followed by their BF16 remainders) and
 // the BF16 gradients of the six network outputs as the transposed output
 // layer reads them ([64][8], two zero pads).
 template <int IN_PAD>
 struct SplitLds {
-  static constexpr int XS = IN_PAD + XPad<MmaBF16>::value;  // bf16 input row stride
+  static constexpr int XS = in_row_stride<MmaBF16, IN_PAD>();  // bf16 input row stride (hi | lo)
   static constexpr int DS = IN_PAD + 1;                     // fp32 input-gradient row stride
   static constexpr int IO = 13;  // floats per pixel: 6 outputs, 6 output gradients, pad
   static constexpr int RB = (64 * XS * 2 > 64 * DS * 4) ? 64 * XS * 2 : 64 * DS * 4;
@@ -614,27 +283,27 @@ __global__ __launch_bounds__(64, 2) void shade_bwd_split_kernel(ShadeArgs A, __b
     shade_geometry<C>(gb, T, uc, vc, A.cam, A.light, true, S);
     build_net_input<F, IN_PAD, M>(gb, S, xs + lane * SL::XS);
     const uint4 *src = reinterpret_cast<const uint4 *>(xs + lane * SL::XS);
-    uint4 *dst = reinterpret_cast<uint4 *>(rec_x + rrow * IN_PAD);
+    uint4 *dst = reinterpret_cast<uint4 *>(rec_x + rrow * 2 * IN_PAD);
 #pragma unroll
-    for (int k = 0; k < IN_PAD / 8; k++) dst[k] = src[k];
+    for (int k = 0; k < IN_PAD / 4; k++) dst[k] = src[k];
   }
   __syncthreads();
   // ---- B: network forward: ReLU masks and outputs
   Mask<MB> m1, m2, m3;
   {
     f32x4 acc[MB][4];
-    Op H[NS::KSH][4];
+    Op H[NS::KSH][4], Hlo[NS::KSH][4];
     layer0_mma<M, MB, NS::KS0>(wops, xs, SL::XS, acc, lane);
-    acc_to_ops<M, MB>(acc, A.params + PO::b(0), g, H);
+    acc_to_ops<M, MB>(acc, A.params + PO::b(0), g, H, Hlo);
     m1.set_from_ops(H);
-    layer_mma<M, MB, NS::KSH>(wops + NS::L0, H, acc, lane);
-    acc_to_ops<M, MB>(acc, A.params + PO::b(1), g, H);
+    act_mma<M, MB, NS::KSH>(wops + NS::L0, H, Hlo, acc, lane);
+    acc_to_ops<M, MB>(acc, A.params + PO::b(1), g, H, Hlo);
     m2.set_from_ops(H);
-    layer_mma<M, MB, NS::KSH>(wops + NS::L0 + NS::LH, H, acc, lane);
-    acc_to_ops<M, MB>(acc, A.params + PO::b(2), g, H);
+    act_mma<M, MB, NS::KSH>(wops + NS::L0 + NS::LH, H, Hlo, acc, lane);
+    acc_to_ops<M, MB>(acc, A.params + PO::b(2), g, H, Hlo);
     m3.set_from_ops(H);
     f32x4 oacc[1][4];
-    layer_mma<M, 1, NS::KSH>(wops + NS::L0 + 2 * NS::LH, H, oacc, lane);
+    act_mma<M, 1, NS::KSH>(wops + NS::L0 + 2 * NS::LH, H, Hlo, oacc, lane);
     if (g < 2)
 #pragma unroll
       for (int nb = 0; nb < 4; nb++)
@@ -733,23 +402,278 @@ template void launch_shade_bwd_split_t<8, 64>(const ShadeArgs &, __bf16 *, __bf1
 template void launch_shade_bwd_split_t<16, 64>(const ShadeArgs &, __bf16 *, __bf16 *, hipStream_t);
 template void launch_shade_bwd_split_t<32, 96>(const ShadeArgs &, __bf16 *, __bf16 *, hipStream_t);
 
-// Workgroups of the persistent grid: every workgroup gets at least one strip.
-int shade_bwd_grid(int net, int width, int in_pad, int tiles, int max_blocks) {
-  const int nw = shade_bwd_waves(net, width, in_pad), nstrips = tiles * 4;
-  int grid = (nstrips + nw - 1) / nw;
-  if (grid > max_blocks) grid = max_blocks;
-  return grid < 1 ? 1 : grid;
+
+// ---------------------------------------------------------------- generic form
+//
+// The other network forms (FP32; BF16 at width 128 or input width 96).  One
+// wave per strip.  The layer inputs are staged in LDS rows [64 px][RS] in
+// natural feature order (BF16: values, then their remainders), so a layer
+// holds only its own accumulators in registers and every width fits.  Per
+// layer the kernel stores the weight-gradient operands feature-major over all
+// strip pixels (P = strips x 64): X_l[k][P], the layer input as the weight
+// gradient takes it (FP32, or the BF16 value), and dY_l[r][P], the gradient of
+// the layer's pre-activation as it enters the products (FP32, or BF16).
+template <class M, int WIDTH, int IN_PAD>
+struct NetLds {
+  using E = typename M::Elem;
+  static constexpr int KMAX = WIDTH > IN_PAD ? WIDTH : IN_PAD;
+  static constexpr int RS = M::NSPLIT * KMAX + XPad<M>::value;  // row stride (elements)
+  static constexpr int DS = IN_PAD + 1;                          // FP32 input-gradient row stride
+  static constexpr int IO = 13;                                  // outputs (6), their gradients (6), pad
+  static constexpr int RB_ROWS = 64 * RS * (int)sizeof(E), RB_DX = 64 * DS * 4;
+  static constexpr int RB = RB_ROWS > RB_DX ? RB_ROWS : RB_DX;
+  static constexpr int BYTES = RB + 64 * IO * 4;
+};
+
+// Bias-added, ReLU-ed accumulators (D layout: lane (col, g) holds features
+// 16 mb + 4 g + j of pixel 16 nb + col) into the LDS rows of the next layer's
+// input (K features; BF16: value at f, remainder at K + f).
+template <class M, int MB>
+__device__ __forceinline__ void acc_to_rows(const f32x4 (&acc)[MB][4], const float *bias, int K,
+                                            typename M::Elem *rows, int RS, int lane) {
+  const int g = lane >> 4, col = lane & 15;
+#pragma unroll
+  for (int mb = 0; mb < MB; mb++)
+#pragma unroll
+    for (int nb = 0; nb < 4; nb++) {
+      const int f = 16 * mb + 4 * g;
+      float v[4];
+#pragma unroll
+      for (int j = 0; j < 4; j++) v[j] = fmaxf(acc[mb][nb][j] + bias[f + j], 0.f);
+      typename M::Elem *r = rows + (16 * nb + col) * RS;
+      if constexpr (M::NSPLIT == 2) {
+        const bf16x2v h0 = __builtin_convertvector((f32x2v){v[0], v[1]}, bf16x2v);
+        const bf16x2v h1 = __builtin_convertvector((f32x2v){v[2], v[3]}, bf16x2v);
+        const bf16x2v l0 = __builtin_convertvector((f32x2v){v[0] - (float)h0[0], v[1] - (float)h0[1]}, bf16x2v);
+        const bf16x2v l1 = __builtin_convertvector((f32x2v){v[2] - (float)h1[0], v[3] - (float)h1[1]}, bf16x2v);
+        *reinterpret_cast<uint2 *>(r + f) =
+            make_uint2(__builtin_bit_cast(uint32_t, h0), __builtin_bit_cast(uint32_t, h1));
+        *reinterpret_cast<uint2 *>(r + K + f) =
+            make_uint2(__builtin_bit_cast(uint32_t, l0), __builtin_bit_cast(uint32_t, l1));
+      } else {
+        *reinterpret_cast<float4 *>(r + f) = make_float4(v[0], v[1], v[2], v[3]);
+      }
+    }
 }
 
+// The first K elements of the lane's own row (its pixel) into column P0 + lane
+// of a feature-major operand [K][P].
+template <class M>
+__device__ __forceinline__ void row_to_operand(const typename M::Elem *rows, int RS, int K,
+                                               typename M::Elem *__restrict__ dst, size_t P, size_t P0, int lane) {
+  const typename M::Elem *r = rows + lane * RS;
+  typename M::Elem *d = dst + P0 + lane;
+#pragma unroll 8
+  for (int k = 0; k < K; k++) d[(size_t)k * P] = r[k];
+}
+
+// D-layout gradients (features 16 mb + 4 g + j of pixel 16 nb + col) into
+// columns P0 .. P0 + 63 of a feature-major operand [R][P], rounded as the
+// gradient products round them.
+template <class M, int MB>
+__device__ __forceinline__ void d_to_operand(const f32x4 (&d)[MB][4], typename M::Elem *__restrict__ dst, size_t P,
+                                             size_t P0, int lane) {
+  const int g = lane >> 4, col = lane & 15;
+  // per-lane base; the row offsets (16 mb + j) P are wave-uniform
+  typename M::Elem *const base = dst + (size_t)(4 * g) * P + P0 + col;
+#pragma unroll
+  for (int mb = 0; mb < MB; mb++)
+#pragma unroll
+    for (int j = 0; j < 4; j++) {
+      typename M::Elem *const row = base + (size_t)(16 * mb + j) * P;
+#pragma unroll
+      for (int nb = 0; nb < 4; nb++) row[16 * nb] = M::cvt(d[mb][nb][j]);
+    }
+}
+
+template <int F, class M, int WIDTH, int IN_PAD>
+__global__ __launch_bounds__(64, WIDTH == 64 ? 2 : 1) void shade_bwd_net_kernel(ShadeArgs A) {
+  using E = typename M::Elem;
+  using Op = typename M::Op;
+  using NS = NetShape<M, WIDTH, IN_PAD>;
+  using PO = ParamOffsets<WIDTH, IN_PAD>;
+  using NL = NetLds<M, WIDTH, IN_PAD>;
+  constexpr int C = kChFeat + F;
+  constexpr int MB = NS::MB, RS = NL::RS;
+  __shared__ __attribute__((aligned(16))) char lds[NL::BYTES];
+  E *rows = reinterpret_cast<E *>(lds);
+  float *dxin = reinterpret_cast<float *>(lds);  // after the forward
+  float *io = reinterpret_cast<float *>(lds + NL::RB);
+  const int lane = threadIdx.x;
+  const int g = lane >> 4, col = lane & 15;
+  const int strip = blockIdx.x;
+  const int tile = strip >> 2, sub = strip & 3;
+  const int tx = tile % A.cam.TX, ty = tile / A.cam.TX;
+  const int px = tx * kTile + col, py = ty * kTile + 4 * sub + g;
+  const bool inside = px < A.cam.W && py < A.cam.H;
+  const size_t HW = (size_t)A.cam.W * A.cam.H;
+  const size_t pix = inside ? (size_t)py * A.cam.W + px : 0;
+  const float uc = (float)px + 0.5f, vc = (float)py + 0.5f;
+  const Op *__restrict__ nops = reinterpret_cast<const Op *>(A.nops);
+  const Op *__restrict__ tops = reinterpret_cast<const Op *>(A.tops);
+  const size_t P = A.gP, P0 = (size_t)strip * 64;
+  E *const gx = reinterpret_cast<E *>(A.gx);
+  E *const gdy = reinterpret_cast<E *>(A.gdy);
+  // operand rows: X_0 [IN_PAD], X_1..X_3 [WIDTH]; dY_0..dY_2 [WIDTH], dY_3 [8]
+  E *const X0 = gx, *const X1 = gx + (size_t)IN_PAD * P, *const X2 = X1 + (size_t)WIDTH * P,
+          *const X3 = X2 + (size_t)WIDTH * P;
+  E *const Y0 = gdy, *const Y1 = gdy + (size_t)WIDTH * P, *const Y2 = Y1 + (size_t)WIDTH * P,
+          *const Y3 = Y2 + (size_t)WIDTH * P;
+  // ---- A: network input row
+  {
+    float gb[C], T, gL[3];
+    load_pixel<C>(A, inside, pix, HW, gb, T, gL);
+    PixShade S;
+    shade_geometry<C>(gb, T, uc, vc, A.cam, A.light, true, S);
+    build_net_input<F, IN_PAD, M>(gb, S, rows + lane * RS);
+  }
+  __syncthreads();
+  row_to_operand<M>(rows, RS, IN_PAD, X0, P, P0, lane);
+  // ---- B: forward, layer inputs through the LDS rows; ReLU masks and outputs
+  Mask<MB> m1, m2, m3;
+  {
+    f32x4 acc[MB][4];
+    layer0_mma<M, MB, NS::KS0>(nops, rows, RS, acc, lane);
+    m1.set_from(acc, A.params + PO::b(0), g);
+    m1.pin();
+    __syncthreads();
+    acc_to_rows<M, MB>(acc, A.params + PO::b(0), WIDTH, rows, RS, lane);
+    __syncthreads();
+    row_to_operand<M>(rows, RS, WIDTH, X1, P, P0, lane);
+    __builtin_amdgcn_sched_barrier(0);
+    layer0_mma<M, MB, NS::KSH>(nops + NS::L0, rows, RS, acc, lane);
+    m2.set_from(acc, A.params + PO::b(1), g);
+    m2.pin();
+    __syncthreads();
+    acc_to_rows<M, MB>(acc, A.params + PO::b(1), WIDTH, rows, RS, lane);
+    __syncthreads();
+    row_to_operand<M>(rows, RS, WIDTH, X2, P, P0, lane);
+    __builtin_amdgcn_sched_barrier(0);
+    layer0_mma<M, MB, NS::KSH>(nops + NS::L0 + NS::LH, rows, RS, acc, lane);
+    m3.set_from(acc, A.params + PO::b(2), g);
+    m3.pin();
+    __syncthreads();
+    acc_to_rows<M, MB>(acc, A.params + PO::b(2), WIDTH, rows, RS, lane);
+    __syncthreads();
+    row_to_operand<M>(rows, RS, WIDTH, X3, P, P0, lane);
+    f32x4 oacc[1][4];
+    __builtin_amdgcn_sched_barrier(0);
+    layer0_mma<M, 1, NS::KSH>(nops + NS::L0 + 2 * NS::LH, rows, RS, oacc, lane);
+    if (g < 2)
+#pragma unroll
+      for (int nb = 0; nb < 4; nb++)
+#pragma unroll
+        for (int j = 0; j < 4; j++) {
+          const int o = 4 * g + j;
+          if (o < 6) io[(16 * nb + col) * NL::IO + o] = oacc[0][nb][j] + A.params[PO::b(3) + o];
+        }
+  }
+  __syncthreads();
+  // ---- C: Eq. 7 and the gradients of the network outputs
+  {
+    float gb[C], T, gL[3];
+    load_pixel<C>(A, inside, pix, HW, gb, T, gL);
+    PixShade S;
+    shade_geometry<C>(gb, T, uc, vc, A.cam, A.light, true, S);
+    if (S.bg) gL[0] = gL[1] = gL[2] = 0.f;
+    float o[6];
+    for (int k = 0; k < 6; k++) o[k] = io[lane * NL::IO + k];
+    combine_net(S, gb[kChSss], o);
+    const float sss = gb[kChSss] * S.ia;
+    float d[8];
+    for (int c = 0; c < 3; c++) {
+      const float gLo = S.a * gL[c];
+      const float dLin = gLo * (1.f - sss) * (S.fs[c] + S.fd[c]) * S.cosI;
+      d[c] = o[c] > 0.f ? dLin : 0.f;
+      d[3 + c] = gLo * sss * S.Lsss[c] * (1.f - S.Lsss[c]);
+    }
+    d[6] = d[7] = 0.f;
+#pragma unroll
+    for (int k = 0; k < 8; k++) {
+      if (k < 6) io[lane * NL::IO + 6 + k] = d[k];
+      Y3[(size_t)k * P + P0 + lane] = M::cvt(d[k]);
+    }
+  }
+  __syncthreads();
+  // ---- D: backward through the network to its inputs
+  {
+    Op Bo[NS::KT_O][4];
+#pragma unroll
+    for (int ks = 0; ks < NS::KT_O; ks++)
+#pragma unroll
+      for (int nb = 0; nb < 4; nb++) {
+        const float *r = io + (16 * nb + col) * NL::IO + 6;
+        if constexpr (M::KPL == 8) {
+          bf16x8 v;
+#pragma unroll
+          for (int j = 0; j < 8; j++) {
+            const int o = feat_index<M>(false, ks, g, j);
+            v[j] = (__bf16)(o < 6 ? r[o] : 0.f);
+          }
+          Bo[ks][nb] = v;
+        } else {
+          const int o = feat_index<M>(false, ks, g, 0);
+          Bo[ks][nb] = o < 6 ? r[o] : 0.f;
+        }
+      }
+    f32x4 dH[MB][4];
+    Op Bd[NS::KSH][4];
+    __builtin_amdgcn_sched_barrier(0);
+    layer_mma<M, MB, NS::KT_O>(tops + NS::T0 + 2 * NS::TH, Bo, dH, lane);
+    m3.apply(dH);
+    d_to_operand<M, MB>(dH, Y2, P, P0, lane);
+    grad_to_ops<M, MB>(dH, Bd);
+    __builtin_amdgcn_sched_barrier(0);
+    layer_mma<M, MB, NS::KT_H>(tops + NS::T0 + NS::TH, Bd, dH, lane);
+    m2.apply(dH);
+    d_to_operand<M, MB>(dH, Y1, P, P0, lane);
+    grad_to_ops<M, MB>(dH, Bd);
+    __builtin_amdgcn_sched_barrier(0);
+    layer_mma<M, MB, NS::KT_H>(tops + NS::T0, Bd, dH, lane);
+    m1.apply(dH);
+    d_to_operand<M, MB>(dH, Y0, P, P0, lane);
+    grad_to_ops<M, MB>(dH, Bd);
+    f32x4 dX[NS::MB0][4];
+    __builtin_amdgcn_sched_barrier(0);
+    layer_mma<M, NS::MB0, NS::KT_H>(tops, Bd, dX, lane);
+#pragma unroll
+    for (int mb = 0; mb < NS::MB0; mb++)
+#pragma unroll
+      for (int nb = 0; nb < 4; nb++)
+#pragma unroll
+        for (int j = 0; j < 4; j++) dxin[(16 * nb + col) * NL::DS + 16 * mb + 4 * g + j] = dX[mb][nb][j];
+  }
+  __syncthreads();
+  // ---- E: per pixel backward of geometry, BRDF and Eq. 7
+  {
+    float gb[C], T, gL[3], dgbar[C];
+    load_pixel<C>(A, inside, pix, HW, gb, T, gL);
+    PixShade S;
+    shade_geometry<C>(gb, T, uc, vc, A.cam, A.light, true, S);
+    if (S.bg) gL[0] = gL[1] = gL[2] = 0.f;
+    float o[6];
+    for (int k = 0; k < 6; k++) o[k] = io[lane * NL::IO + k];
+    combine_net(S, gb[kChSss], o);
+    const float dA = shade_pixel_bwd<C, F, 1>(S, gb, gL, A.light, dxin + lane * NL::DS, dgbar);
+    write_pixel_grads<C, F>(A, inside, pix, HW, S, gb, dgbar, dA);
+  }
+}
+
+// Elements of the generic form's weight-gradient operands per pixel.
+size_t net_operand_elems(int width, int in_pad) { return (size_t)in_pad + 6 * (size_t)width + 8; }
+
 template <int F, int NET, int WIDTH, int IN_PAD>
-void launch_shade_bwd_t(const ShadeArgs &a, int nblocks, hipStream_t st) {
-  constexpr int NW = BwdWaves<NET, WIDTH, IN_PAD>::value;
-  const int grid = shade_bwd_grid(NET, WIDTH, IN_PAD, a.cam.TX * a.cam.TY, nblocks);
-  shade_bwd_kernel<F, NET, WIDTH, IN_PAD><<<grid, NW * 64, 0, st>>>(a, a.cam.TX * a.cam.TY * 4);
+void launch_shade_bwd_t(const ShadeArgs &a, hipStream_t st) {
+  const int tiles = a.cam.TX * a.cam.TY;
+  if constexpr (NET == 1 || NET == 2) {
+    shade_bwd_net_kernel<F, typename NetTraits<NET>::M, WIDTH, IN_PAD><<<tiles * 4, 64, 0, st>>>(a);
+  } else {
+    shade_bwd_plain_kernel<F, NET><<<tiles, 256, 0, st>>>(a);
+  }
 }
 
 #define SSSGS_SHADE_BWD(F, NET, WIDTH, IN_PAD) \
-  template void launch_shade_bwd_t<F, NET, WIDTH, IN_PAD>(const ShadeArgs &, int, hipStream_t);
+  template void launch_shade_bwd_t<F, NET, WIDTH, IN_PAD>(const ShadeArgs &, hipStream_t);
 SSSGS_SHADE_INSTANCES(SSSGS_SHADE_BWD)
 
 }  // namespace sssgs

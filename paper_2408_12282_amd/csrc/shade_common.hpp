@@ -23,6 +23,13 @@ struct ShadeArgs {
   int nparams;
   float4 *zero_buf;      // or null: cleared by the split shading backward (the
   size_t zero_count4;    // compositing backward's accumulators, in float4)
+  // generic network backward: forward weights with natural K order in every
+  // layer, and the weight-gradient operands [rows][gP] it stores
+  const void *nops;
+  void *gx, *gdy;
+  size_t gP;
+  // colour behind the Gaussians: rgb = a L_out + T_final bgc
+  float bgc[3];
 };
 
 // Point lights of one shading pass (image-based lighting by a sum over light
@@ -44,6 +51,23 @@ template <> struct NetTraits<2> { using M = MmaBF16; };
 
 template <class M> struct XPad { static constexpr int value = 4; };
 template <> struct XPad<MmaBF16> { static constexpr int value = 8; };
+
+// LDS row of one pixel's network input: [hi IN_PAD | lo IN_PAD | pad] in the
+// BF16 form (see mlp.hpp), [value IN_PAD | pad] in the FP32 form.
+template <class M, int IN_PAD>
+constexpr int in_row_stride() { return M::NSPLIT * IN_PAD + XPad<M>::value; }
+
+// Entry p of a network input row.
+template <class M, int IN_PAD>
+__device__ __forceinline__ void put_in(typename M::Elem *row, int p, float v) {
+  if constexpr (M::NSPLIT == 2) {
+    const __bf16 hi = (__bf16)v;
+    row[p] = hi;
+    row[IN_PAD + p] = (__bf16)(v - (float)hi);
+  } else {
+    row[p] = M::cvt(v);
+  }
+}
 
 constexpr float kPi = 3.14159265358979323846f;
 
@@ -136,7 +160,7 @@ template <int F, int IN_PAD, class M>
 __device__ __forceinline__ void build_net_input(const float *gb, const PixShade &S, typename M::Elem *row) {
   int p = 0;
 #pragma unroll
-  for (int f = 0; f < F; f++) row[p++] = M::cvt(gb[kChFeat + f] * S.ia);
+  for (int f = 0; f < F; f++) put_in<M, IN_PAD>(row, p++, gb[kChFeat + f] * S.ia);
 #pragma unroll
   for (int oct = 0; oct < 6; oct++) {
     const float sc = (float)(1 << oct);
@@ -147,24 +171,24 @@ __device__ __forceinline__ void build_net_input(const float *gb, const PixShade 
       cv[ax] = cospif(sc * S.x[ax]);
     }
 #pragma unroll
-    for (int ax = 0; ax < 3; ax++) row[p++] = M::cvt(sv[ax]);
+    for (int ax = 0; ax < 3; ax++) put_in<M, IN_PAD>(row, p++, sv[ax]);
 #pragma unroll
-    for (int ax = 0; ax < 3; ax++) row[p++] = M::cvt(cv[ax]);
+    for (int ax = 0; ax < 3; ax++) put_in<M, IN_PAD>(row, p++, cv[ax]);
   }
 #pragma unroll
-  for (int k = 0; k < 3; k++) row[p++] = M::cvt(S.wo[k]);
+  for (int k = 0; k < 3; k++) put_in<M, IN_PAD>(row, p++, S.wo[k]);
 #pragma unroll
-  for (int k = 0; k < 3; k++) row[p++] = M::cvt(S.wi[k]);
+  for (int k = 0; k < 3; k++) put_in<M, IN_PAD>(row, p++, S.wi[k]);
 #pragma unroll
-  for (; p < IN_PAD; p++) row[p] = M::cvt(0.f);
+  for (; p < IN_PAD; p++) put_in<M, IN_PAD>(row, p, 0.f);
 }
 
 // Only the incident-direction entries of a network input row (after the
 // features, the position encoding and w_o).
-template <int F, class M>
+template <int F, int IN_PAD, class M>
 __device__ __forceinline__ void set_net_light(const PixShade &S, typename M::Elem *row) {
 #pragma unroll
-  for (int k = 0; k < 3; k++) row[F + kNumPE + 3 + k] = M::cvt(S.wi[k]);
+  for (int k = 0; k < 3; k++) put_in<M, IN_PAD>(row, F + kNumPE + 3 + k, S.wi[k]);
 }
 
 __device__ __forceinline__ void combine_net(PixShade &S, float sss_pre, const float *o) {
@@ -209,10 +233,12 @@ __device__ __forceinline__ typename M::Op load_op_lds(const typename M::Elem *p)
 }
 
 // Pack the bias-added, ReLU-ed accumulators of a layer into the next layer's
-// B operands (permuted K order, see feat_index).
+// B operands (permuted K order, see feat_index): H the activations (BF16: hi),
+// Hlo the BF16 remainders (unused in the FP32 form).
 template <class M, int MB>
 __device__ __forceinline__ void acc_to_ops(const f32x4 (&acc)[MB][4], const float *bias, int g,
-                                           typename M::Op (&H)[(MB * 16) / M::KS][4]) {
+                                           typename M::Op (&H)[(MB * 16) / M::KS][4],
+                                           typename M::Op (&Hlo)[(MB * 16) / M::KS][4]) {
   constexpr int KSN = (MB * 16) / M::KS;
 #pragma unroll
   for (int ks = 0; ks < KSN; ks++)
@@ -225,12 +251,60 @@ __device__ __forceinline__ void acc_to_ops(const f32x4 (&acc)[MB][4], const floa
           const int mb = 2 * ks + (j >> 2), jj = j & 3;
           v[j] = fmaxf(acc[mb][nb][jj] + bias[16 * mb + 4 * g + jj], 0.f);
         }
-        H[ks][nb] = pack_bf16x8(v[0], v[1], v[2], v[3], v[4], v[5], v[6], v[7]);
+        pack_bf16x8_split(v, H[ks][nb], Hlo[ks][nb]);
       } else {
         const int mb = ks >> 2, jj = ks & 3;
         H[ks][nb] = fmaxf(acc[mb][nb][jj] + bias[16 * mb + 4 * g + jj], 0.f);
       }
     }
+}
+
+// One forward product from activation operands (K = KSN k-steps): acc =
+// W H, and in the BF16 form + W Hlo.  The first k-step takes a literal zero
+// accumulator (an inline constant, no register clears).
+template <class M, int MB, int KSN>
+__device__ __forceinline__ void act_mma(const typename M::Op *__restrict__ w, const typename M::Op (&H)[KSN][4],
+                                        const typename M::Op (&Hlo)[KSN][4], f32x4 (&acc)[MB][4], int lane) {
+#pragma unroll
+  for (int ks = 0; ks < KSN; ks++)
+#pragma unroll
+    for (int mb = 0; mb < MB; mb++) {
+      const typename M::Op a = w[(mb * KSN + ks) * 64 + lane];
+#pragma unroll
+      for (int nb = 0; nb < 4; nb++)
+        acc[mb][nb] = M::mma(a, H[ks][nb], ks == 0 ? f32x4{0.f, 0.f, 0.f, 0.f} : acc[mb][nb]);
+      if constexpr (M::NSPLIT == 2)
+#pragma unroll
+        for (int nb = 0; nb < 4; nb++) acc[mb][nb] = M::mma(a, Hlo[ks][nb], acc[mb][nb]);
+    }
+}
+
+// Layer 0 from the LDS input rows (row stride XS; natural K order; in the
+// BF16 form the remainders follow at offset IN_PAD).
+template <class M, int MB, int KS0>
+__device__ __forceinline__ void layer0_mma(const typename M::Op *__restrict__ w, const typename M::Elem *xs, int XS,
+                                           f32x4 (&acc)[MB][4], int lane) {
+  constexpr int IN_PAD = KS0 * M::KS;
+  const int g = lane >> 4, col = lane & 15;
+#pragma unroll
+  for (int ks = 0; ks < KS0; ks++) {
+    typename M::Op B[4], Blo[4];
+#pragma unroll
+    for (int nb = 0; nb < 4; nb++) {
+      const typename M::Elem *r = xs + (16 * nb + col) * XS + ks * M::KS + g * M::KPL;
+      B[nb] = load_op_lds<M>(r);
+      if constexpr (M::NSPLIT == 2) Blo[nb] = load_op_lds<M>(r + IN_PAD);
+    }
+#pragma unroll
+    for (int mb = 0; mb < MB; mb++) {
+      const typename M::Op a = w[(mb * KS0 + ks) * 64 + lane];
+#pragma unroll
+      for (int nb = 0; nb < 4; nb++) acc[mb][nb] = M::mma(a, B[nb], ks == 0 ? f32x4{0.f, 0.f, 0.f, 0.f} : acc[mb][nb]);
+      if constexpr (M::NSPLIT == 2)
+#pragma unroll
+        for (int nb = 0; nb < 4; nb++) acc[mb][nb] = M::mma(a, Blo[nb], acc[mb][nb]);
+    }
+  }
 }
 
 // Forward of the whole network for the wave's 64 pixels.  xs: LDS rows of
@@ -246,46 +320,20 @@ __device__ __forceinline__ void net_forward_wave(const void *wops_v, const float
   const Op *__restrict__ wops = reinterpret_cast<const Op *>(wops_v);
   const int lane = threadIdx.x & 63, g = lane >> 4, col = lane & 15;
   f32x4 acc[MB][4];
-  Op H[KSH][4];
-  // layer 0: B operands from the LDS input rows
-  // first k-steps take a literal zero accumulator (inline constant)
-#pragma unroll
-  for (int ks = 0; ks < KS0; ks++) {
-    Op B[4];
-#pragma unroll
-    for (int nb = 0; nb < 4; nb++) B[nb] = load_op_lds<M>(xs + (16 * nb + col) * XS + ks * M::KS + g * M::KPL);
-#pragma unroll
-    for (int mb = 0; mb < MB; mb++) {
-      const Op a = wops[(mb * KS0 + ks) * 64 + lane];
-#pragma unroll
-      for (int nb = 0; nb < 4; nb++) acc[mb][nb] = M::mma(a, B[nb], ks == 0 ? f32x4{0.f, 0.f, 0.f, 0.f} : acc[mb][nb]);
-    }
-  }
-  acc_to_ops<M, MB>(acc, params + PO::b(0), g, H);
+  Op H[KSH][4], Hlo[KSH][4];
+  layer0_mma<M, MB, KS0>(wops, xs, XS, acc, lane);
+  acc_to_ops<M, MB>(acc, params + PO::b(0), g, H, Hlo);
   const Op *wl = wops + NS::L0;
   // hidden layers 1, 2
 #pragma unroll
   for (int l = 1; l < 3; l++) {
-#pragma unroll
-    for (int ks = 0; ks < KSH; ks++)
-#pragma unroll
-      for (int mb = 0; mb < MB; mb++) {
-        const Op a = wl[(mb * KSH + ks) * 64 + lane];
-#pragma unroll
-        for (int nb = 0; nb < 4; nb++)
-          acc[mb][nb] = M::mma(a, H[ks][nb], ks == 0 ? f32x4{0.f, 0.f, 0.f, 0.f} : acc[mb][nb]);
-      }
-    acc_to_ops<M, MB>(acc, params + PO::b(l), g, H);
+    act_mma<M, MB, KSH>(wl, H, Hlo, acc, lane);
+    acc_to_ops<M, MB>(acc, params + PO::b(l), g, H, Hlo);
     wl += NS::LH;
   }
   // output layer: 6 rows of one 16-row block
-  f32x4 oacc[4];
-#pragma unroll
-  for (int ks = 0; ks < KSH; ks++) {
-    const Op a = wl[ks * 64 + lane];
-#pragma unroll
-    for (int nb = 0; nb < 4; nb++) oacc[nb] = M::mma(a, H[ks][nb], ks == 0 ? f32x4{0.f, 0.f, 0.f, 0.f} : oacc[nb]);
-  }
+  f32x4 oacc[1][4];
+  act_mma<M, 1, KSH>(wl, H, Hlo, oacc, lane);
   if (g < 2) {
     const float *bo = params + PO::b(3);
 #pragma unroll
@@ -293,7 +341,7 @@ __device__ __forceinline__ void net_forward_wave(const void *wops_v, const float
 #pragma unroll
       for (int j = 0; j < 4; j++) {
         const int o = 4 * g + j;
-        outs[(16 * nb + col) * 8 + o] = oacc[nb][j] + (o < 6 ? bo[o] : 0.f);
+        outs[(16 * nb + col) * 8 + o] = oacc[0][nb][j] + (o < 6 ? bo[o] : 0.f);
       }
   }
 }

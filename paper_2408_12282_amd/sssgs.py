@@ -49,7 +49,15 @@ class Mlp(ct.Structure):
 
 
 class Options(ct.Structure):
-    _fields_ = [("precision", ct.c_int32), ("accumulate_grads", ct.c_int32), ("radiance_features", ct.c_int32)]
+    _fields_ = [("precision", ct.c_int32), ("accumulate_grads", ct.c_int32), ("radiance_features", ct.c_int32),
+                ("deterministic", ct.c_int32), ("background", ct.c_float * 3)]
+
+
+def make_options(precision: int, accumulate: bool = False, radiance_features: bool = False,
+                 deterministic: bool = False, background=None) -> Options:
+    bg = (0.0, 0.0, 0.0) if background is None else tuple(float(v) for v in background)
+    return Options(int(precision), int(accumulate), int(radiance_features), int(deterministic),
+                   (ct.c_float * 3)(*bg))
 
 
 class Layout(ct.Structure):
@@ -333,6 +341,9 @@ class View:
             raise SSSGSError(ERR_INVALID_ARG)
         self.workspace = torch.empty(self.ws_bytes, dtype=torch.uint8, device=device)
         self.layout = sssgs_workspace_layout(n, width, height, feat_dim, mlp_width, self.capacity)
+        # forward calls on this workspace so far: a backward must follow the
+        # forward whose state the workspace holds (SSSGSRender checks it)
+        self.generation = 0
 
     def region(self, offset: int, count: int, dtype=torch.int32) -> torch.Tensor:
         """A typed view of `count` elements of the workspace at byte `offset`."""
@@ -342,10 +353,11 @@ class View:
 
 def render_forward(view: View, params: dict, sh_degree: int, cam: Camera, light: Light, mlp_params=None,
                    mlp_width: int = 64, precision: int = PREC_BF16, want_count: bool = False,
-                   radiance_features: bool = False):
+                   radiance_features: bool = False, background=None):
     """One forward call.  Returns (rgb [3,H,W], gbuf [C,H,W], alpha [H,W], M or None).
     ``radiance_features``: Eq. 7 takes its radiances from feature planes 0-5
-    (the outputs of the per-Gaussian network)."""
+    (the outputs of the per-Gaussian network).  ``background``: colour behind
+    the Gaussians (default black)."""
     dev = params["means"].device
     H, W = view.height, view.width
     rgb = torch.empty((3, H, W), dtype=torch.float32, device=dev)
@@ -355,7 +367,8 @@ def render_forward(view: View, params: dict, sh_degree: int, cam: Camera, light:
     m = None
     if mlp_params is not None:
         m = Mlp(view.feat_dim + 42, mlp_width, 3, 6, _ptr(mlp_params))
-    opt = Options(precision, 0, int(radiance_features))
+    opt = make_options(precision, radiance_features=radiance_features, background=background)
+    view.generation += 1
     st, cnt = sssgs_render_forward(g, cam, light, m, opt, ct.c_void_p(view.workspace.data_ptr()), view.ws_bytes,
                                    view.capacity, _ptr(rgb), _ptr(gbuf), _ptr(alpha), want_count, _stream())
     _check(st)
@@ -373,7 +386,8 @@ def render_forward_lights(view: View, params: dict, sh_degree: int, cam: Camera,
     alpha = torch.empty((H, W), dtype=torch.float32, device=dev)
     g = gaussians_struct(params, view.feat_dim, sh_degree)
     m = Mlp(view.feat_dim + 42, mlp_width, 3, 6, _ptr(mlp_params)) if mlp_params is not None else None
-    opt = Options(precision, 0)
+    opt = make_options(precision)
+    view.generation += 1
     st, cnt = sssgs_render_forward_lights(g, cam, list(lights), weights, m, opt,
                                           ct.c_void_p(view.workspace.data_ptr()), view.ws_bytes, view.capacity,
                                           _ptr(rgb), _ptr(gbuf), _ptr(alpha), want_count, _stream())
@@ -384,7 +398,7 @@ def render_forward_lights(view: View, params: dict, sh_degree: int, cam: Camera,
 def render_backward(view: View, params: dict, sh_degree: int, cam: Camera, light: Light, gbuf, drgb, dgbuf=None,
                     dalpha=None, mlp_params=None, mlp_width: int = 64, precision: int = PREC_BF16,
                     grads: Optional[dict] = None, dmlp: Optional[torch.Tensor] = None, accumulate: bool = False,
-                    radiance_features: bool = False):
+                    radiance_features: bool = False, deterministic: bool = False, background=None):
     dev = params["means"].device
     if grads is None:
         grads = {k: torch.zeros_like(v) for k, v in params.items() if v is not None}
@@ -392,7 +406,7 @@ def render_backward(view: View, params: dict, sh_degree: int, cam: Camera, light
         dmlp = torch.zeros_like(mlp_params)
     g = gaussians_struct(params, view.feat_dim, sh_degree)
     m = Mlp(view.feat_dim + 42, mlp_width, 3, 6, _ptr(mlp_params)) if mlp_params is not None else None
-    opt = Options(precision, int(accumulate), int(radiance_features))
+    opt = make_options(precision, accumulate, radiance_features, deterministic, background)
     gs = grads_struct(grads)
     st = sssgs_render_backward(g, cam, light, m, opt, ct.c_void_p(view.workspace.data_ptr()), view.ws_bytes,
                                view.capacity, _ptr(gbuf), _ptr(drgb.contiguous()),
@@ -409,16 +423,21 @@ class SSSGSRender(torch.autograd.Function):
 
     Differentiable w.r.t. every Gaussian parameter tensor and the packed
     network parameters.  ``ctx_args`` = (view, sh_degree, Camera, Light,
-    mlp_width, precision).
+    mlp_width, precision, deterministic, background).  The forward reads the
+    instance count back (one wait on the stream) and raises SSSGSError
+    (ERR_CAPACITY) when the view's capacity is too small.  The backward uses
+    the state the forward left in the view's workspace: it raises if another
+    forward ran on the same view in between.
     """
 
     @staticmethod
     def forward(ctx, ctx_args, mlp_params, *tensors):
-        view, sh_degree, cam, light, mlp_width, precision = ctx_args
+        view, sh_degree, cam, light, mlp_width, precision, deterministic, background = ctx_args
         params = {k: (t if t is not None and t.numel() else None) for k, t in zip(PARAM_NAMES, tensors)}
-        rgb, gbuf, alpha, _ = render_forward(view, params, sh_degree, cam, light, mlp_params, mlp_width, precision)
+        rgb, gbuf, alpha, _ = render_forward(view, params, sh_degree, cam, light, mlp_params, mlp_width, precision,
+                                             want_count=True, background=background)
         ctx.ctx_args = ctx_args
-        ctx.params = params
+        ctx.generation = view.generation
         ctx.save_for_backward(gbuf, mlp_params if mlp_params is not None else torch.empty(0), *[
             t if t is not None else torch.empty(0) for t in tensors])
         ctx.has_mlp = mlp_params is not None
@@ -426,24 +445,30 @@ class SSSGSRender(torch.autograd.Function):
 
     @staticmethod
     def backward(ctx, drgb, dgbuf, dalpha):
-        view, sh_degree, cam, light, mlp_width, precision = ctx.ctx_args
+        view, sh_degree, cam, light, mlp_width, precision, deterministic, background = ctx.ctx_args
+        if view.generation != ctx.generation:
+            raise RuntimeError("SSSGSRender: another forward ran on this view before the backward; "
+                               "use one View per forward whose backward is pending")
         saved = ctx.saved_tensors
         gbuf = saved[0]
         mlp_params = saved[1] if ctx.has_mlp else None
-        params = ctx.params
+        params = {k: (t if t.numel() else None) for k, t in zip(PARAM_NAMES, saved[2:])}
         drgb = drgb if drgb is not None else torch.zeros((3, view.height, view.width), device=gbuf.device)
         grads, dmlp = render_backward(view, params, sh_degree, cam, light, gbuf, drgb.contiguous(),
                                       dgbuf.contiguous() if dgbuf is not None else None,
                                       dalpha.contiguous() if dalpha is not None else None, mlp_params, mlp_width,
-                                      precision)
+                                      precision, deterministic=deterministic, background=background)
         out = [grads.get(k) if params.get(k) is not None else None for k in PARAM_NAMES]
         return (None, dmlp, *out)
 
 
 def render(view: View, params: dict, sh_degree: int, cam: Camera, light: Light, mlp_params=None,
-           mlp_width: int = 64, precision: int = PREC_BF16):
+           mlp_width: int = 64, precision: int = PREC_BF16, deterministic: bool = False, background=None):
+    """Differentiable render (torch.autograd): returns (rgb, gbuffer, alpha)."""
     tensors: Sequence = [params.get(k) for k in PARAM_NAMES]
-    return SSSGSRender.apply((view, sh_degree, cam, light, mlp_width, precision), mlp_params, *tensors)
+    bg = None if background is None else tuple(float(v) for v in background)
+    return SSSGSRender.apply((view, sh_degree, cam, light, mlp_width, precision, bool(deterministic), bg),
+                             mlp_params, *tensors)
 
 
 # ----------------------------------------------------------------- per-Gaussian network

@@ -8,6 +8,25 @@ from paper_2408_12282_amd import scene
 
 TILE = 16
 
+# Parity tolerances shared by the GPU tests (relative L2 per output tensor or
+# per parameter group unless stated).
+GRAD_REL = 1e-3        # gradients, every parameter group, either network precision
+FWD_REL = 1e-5         # FP32 forward images
+BF16_FP64_REL = 2e-3   # BF16-network image against the FP64 network
+# BF16-network image against the oracle's emulation of the same arithmetic
+# (weights rounded once, activations as hi + lo pairs, FP32 accumulation):
+# a pre-activation differs from the emulation's by at most the granularity of
+# the pair (2^-17 of each term) plus the FP32 error of the network inputs
+# (~1e-6 of the terms), about 1e-5 of the sum of its terms' magnitudes; the
+# bound is three times that.
+BF16_EMU_REL = 3e-5
+# A pixel enters a gradient comparison only if every ReLU argument of its
+# network is farther from zero than this fraction of the sum of its terms'
+# magnitudes (the oracle's net_margin), the same 3x of the ~1e-5 bound above:
+# closer, FP32 and FP64 may take the ReLU decision differently, which moves
+# that unit's share of the gradient by O(1).
+NET_MARGIN = 3e-5
+
 
 def to_device(g, mlp=None, device="cuda"):
     import torch

@@ -7,7 +7,8 @@ import pytest
 from oracle import oracle as O
 from paper_2408_12282_amd import scene
 
-from helpers import assert_close_masked, gpu_render, rel_norm, small_workload, tile_lists_equal
+from helpers import (BF16_EMU_REL, BF16_FP64_REL, FWD_REL, assert_close_masked, gpu_render, rel_norm, small_workload,
+                     tile_lists_equal)
 
 pytestmark = pytest.mark.gpu
 
@@ -16,16 +17,8 @@ pytestmark = pytest.mark.gpu
 # |value| + sum|terms|: the record stores the projected mean in FP32 (relative
 # 6e-8, i.e. up to 5e-5 px at u ~ 800), which moves alpha at a Gaussian's
 # fringe by |A dx + B dy| x 5e-5 ~ 2.5e-5 relative, and FP32 sums of ~70 terms
-# add ~1e-6.
-FWD_REL = 1e-5
+# add ~1e-6.  The BF16 network bounds (emulation, FP64) are in helpers.py.
 ELEM_REL = 1e-4
-# BF16 network against the oracle's BF16 emulation: both round the same
-# tensors, but FP32 inputs (the Fourier features amplify the position's FP32
-# error up to 32 pi-fold) land on the other side of a bfloat16 rounding
-# boundary now and then; each flip is one bfloat16 ulp (2^-8).  Against the
-# FP64 network the bound is the stated 2e-3.
-BF16_EMU_REL = 1e-3
-BF16_FP64_REL = 2e-3
 
 
 def _projection_checks(g, out, ora):
@@ -193,6 +186,11 @@ def test_headline_300k_800(precision):
     e = rel_norm(out["rgb"], ora["rgb"])
     print(f"rgb rel err ({precision}): {e:.3e}")
     assert e < (FWD_REL if precision == "fp32" else BF16_EMU_REL)
+    if precision == "bf16":
+        ora64 = O.render(g, cam, light, mlp, bf16=False)
+        e64 = rel_norm(out["rgb"], ora64["rgb"])
+        print(f"rgb rel err vs FP64 network: {e64:.3e}")
+        assert e64 < BF16_FP64_REL
 
 
 @pytest.mark.parametrize("W,H", [(4096, 4096), (2500, 300), (500, 450)])

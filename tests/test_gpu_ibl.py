@@ -5,7 +5,7 @@ import pytest
 from oracle import oracle as O
 from paper_2408_12282_amd import scene
 
-from helpers import assert_close_masked, rel_norm, small_workload, to_device
+from helpers import BF16_EMU_REL, BF16_FP64_REL, assert_close_masked, rel_norm, small_workload, to_device
 
 pytestmark = pytest.mark.gpu
 
@@ -61,11 +61,11 @@ def test_environment_lighting_network_bf16():
     rgb, _, _ = _gpu_lights(g, cam, lights, weights, mlp, "bf16")
     e = rel_norm(rgb, ora["rgb"])
     print(f"  rgb rel err vs BF16 emulation {e:.2e}")
-    assert e < 1e-3
+    assert e < BF16_EMU_REL
     ora64 = O.render_lights(g, cam, lights, weights, mlp, bf16=False)
     e64 = rel_norm(rgb, ora64["rgb"])
     print(f"  rgb rel err vs FP64 network {e64:.2e}")
-    assert e64 < 2e-3
+    assert e64 < BF16_FP64_REL
 
 
 def test_single_light_with_unit_weights_is_the_single_light_forward():

@@ -8,7 +8,8 @@ import pytest
 from oracle import oracle as O
 from paper_2408_12282_amd import scene
 
-from helpers import assert_close_masked, gpu_render, rel_norm, tile_lists_equal, to_device
+from helpers import (BF16_EMU_REL, GRAD_REL, NET_MARGIN, assert_close_masked, gpu_render, rel_norm, tile_lists_equal,
+                     to_device)
 
 pytestmark = pytest.mark.gpu
 
@@ -122,7 +123,7 @@ def test_olat_training_step_8_views_500k():
                                B._stream()) == 0
         f = O.render(g, cam, light, mlp, bf16=True)
         rgb_np = rgb.cpu().numpy()
-        assert rel_norm(rgb_np, f["rgb"]) < 1e-3
+        assert rel_norm(rgb_np, f["rgb"]) < BF16_EMU_REL
         # the GPU's loss gradient is exactly sign(rgb - target) / (3HW)
         dl_np = dl.cpu().numpy()
         np.testing.assert_array_equal(dl_np, np.sign(rgb_np - target).astype(np.float32) * np.float32(scale))
@@ -136,7 +137,7 @@ def test_olat_training_step_8_views_500k():
         assert abs(loss.item() - ref_loss) < 2e-3 * ref_loss
         # backward of the renderer on the GPU's own loss gradient, zero where the
         # renderer's alpha, transmittance or ReLU decisions are marginal
-        keep = (f["pix_flag"] == 0) & (f["net_margin"] >= 5e-3)
+        keep = (f["pix_flag"] == 0) & (f["net_margin"] >= NET_MARGIN)
         up = (dl_np * keep[None]).astype(np.float32)
         B.render_backward(view, p, -1, bc, bl, gbuf, torch.from_numpy(up).cuda(), None, None, mp, mlp.width,
                           B.PREC_BF16, grads, dmlp, accumulate=(v > 0))
@@ -146,7 +147,7 @@ def test_olat_training_step_8_views_500k():
     errs = {k: rel_norm(grads[k].cpu().numpy(), ora_sum[k]) for k in grads if np.any(ora_sum[k])}
     errs["mlp"] = rel_norm(dmlp.cpu().numpy(), ora_sum["mlp"])
     print("accumulated grad rel errors:", {k: f"{v:.2e}" for k, v in errs.items()})
-    assert all(v < 1e-2 for v in errs.values()), errs
+    assert all(v < GRAD_REL for v in errs.values()), errs
 
 
 def test_large_scene_1m_sh_1600x1200_width128():
@@ -159,7 +160,8 @@ def test_large_scene_1m_sh_1600x1200_width128():
     print("[gpu] 1M 1600x1200 SH forward", flush=True)
     ora = O.render(g, cam, light, mlp, bf16=True, lists=True)
     drgb = scene.upstream_weights((3, H, W), 7)
-    keep = (ora["pix_flag"] == 0) & (ora["net_margin"] >= 5e-3)
+    keep = (ora["pix_flag"] == 0) & (ora["net_margin"] >= NET_MARGIN)
+    print(f"  pixels kept for the gradient comparison: {keep.mean():.3f}")
     drgb = (drgb * keep[None]).astype(np.float32)
     out = gpu_render(g, cam, light, mlp, "bf16", capacity=60_000_000, backward=(drgb, None, None))
     assert out["M"] == ora["num_instances"]
@@ -170,9 +172,9 @@ def test_large_scene_1m_sh_1600x1200_width128():
     assert rel_norm(out["gbuf"], ora["gbuf"]) < 1e-5
     e = rel_norm(out["rgb"], ora["rgb"])
     print(f"rgb rel err vs BF16 emulation: {e:.2e}")
-    assert e < 1e-3
+    assert e < BF16_EMU_REL
     print("[gpu] 1M backward vs oracle", flush=True)
     og = O.render(g, cam, light, mlp, bf16=True, drgb=drgb)["grads"]
     errs = {k: rel_norm(out["grads"][k], og[k]) for k in og if np.any(og[k]) and k != "albedo"}
     print("grad rel errors:", {k: f"{v:.2e}" for k, v in errs.items()})
-    assert all(v < 1e-2 for v in errs.values()), errs
+    assert all(v < GRAD_REL for v in errs.values()), errs

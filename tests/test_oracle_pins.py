@@ -258,6 +258,36 @@ def test_oracle_gradient_equals_autograd(case):
         np.testing.assert_allclose(og[k], ref, rtol=0, atol=1e-9 * max(1.0, np.abs(ref).max()), err_msg=k)
 
 
+@pytest.mark.parametrize("case", ["plain", "mlp"])
+def test_background_colour_against_brute_force_and_autograd(case):
+    """Composited over a constant background b: rgb = a L_out + T_final b, and
+    the gradient reaches the Gaussians through T_final."""
+    g, cam, mlp, shd = _brute_case(case)
+    light = scene.default_light()
+    bgc = np.array([0.2, 0.5, 0.9])
+    o = oracle.render(g, cam, light, mlp, background=bgc)
+    p = _tensor_params(g, mlp)
+    b = brute.render(p, cam, light, mlp, sh_degree=shd, background=bgc)
+    np.testing.assert_allclose(o["rgb"], b["rgb"].detach().numpy(), rtol=0, atol=1e-12)
+    o0 = oracle.render(g, cam, light, mlp)
+    np.testing.assert_allclose(o["rgb"] - o0["rgb"], bgc[:, None, None] * (1.0 - o0["alpha"])[None], atol=1e-12)
+    w = np.random.default_rng(3).normal(size=(3, cam.height, cam.width))
+    (b["rgb"] * torch.tensor(w)).sum().backward()
+    og = oracle.render(g, cam, light, mlp, drgb=w, background=bgc)["grads"]
+    for k, t in p.items():
+        if t.grad is not None:
+            ref = t.grad.numpy()
+            np.testing.assert_allclose(og[k], ref, rtol=0, atol=1e-9 * max(1.0, np.abs(ref).max()), err_msg=k)
+
+
+def test_background_of_an_empty_scene_is_the_background():
+    cam = scene.look_at_camera((0, 0, 3), 20, 12)
+    o = oracle.render(scene.make_gaussians(0, 0, False, seed=0), cam, scene.default_light(),
+                      background=(0.25, 0.5, 1.0))
+    for c, v in enumerate((0.25, 0.5, 1.0)):
+        assert np.all(o["rgb"][c] == v)
+
+
 # --------------------------------------------------------------------------- finite differences
 
 @pytest.mark.parametrize("use_mlp,sh", [(False, False), (True, False), (True, True)])
@@ -400,3 +430,61 @@ def test_one_pixel_image():
     o = oracle.render(g, cam, scene.default_light())
     assert o["num_instances"] == 1
     assert 0 < o["alpha"][0, 0] <= 0.99
+
+
+def _small_network_case():
+    w = scene.workload(3, n=20000)
+    cam = scene.look_at_camera(w.cameras[0].center, 128, 96)
+    return w.gaussians, cam, w.lights[0], w.mlp
+
+
+def test_bf16_emulation_is_stable_under_fp32_sized_input_changes():
+    """With activations entering the products as two bfloat16 numbers (hi + lo)
+    the emulated network is a smooth function of its inputs to ~2^-17, so a
+    GPU that computes the network inputs in FP32 can be held to the gradient
+    bound: perturbing the feature inputs by 2e-7 relative (an FP32-sized
+    change) moves no gradient group by more than 1e-4 on the pixels whose ReLU
+    arguments clear the 3e-5 relative margin."""
+    g, cam, light, mlp = _small_network_case()
+    rng = np.random.default_rng(4)
+    up = rng.normal(size=(3, cam.height, cam.width))
+    base = oracle.render(g, cam, light, mlp, bf16=True)
+    keep = (base["pix_flag"] == 0) & (base["net_margin"] >= 3e-5)
+    assert keep.mean() > 0.9
+    a = oracle.render(g, cam, light, mlp, bf16=True, drgb=up * keep)
+    feats = np.asarray(g.features, np.float64) * (1 + 2e-7 * rng.standard_normal(g.features.shape))
+    b = oracle.render(g, cam, light, mlp, bf16=True, drgb=up * keep, params64={"features": feats})
+    for k, v in a["grads"].items():
+        if np.any(v):
+            assert np.linalg.norm(b["grads"][k] - v) <= 1e-4 * np.linalg.norm(v), k
+
+
+def test_single_bf16_rounding_of_activations_would_be_unstable():
+    """Why the activations are split: rounding them once to bfloat16 turns
+    FP32-sized input changes into whole-ulp jumps.  A 64-64-64 ReLU chain with
+    bfloat16 weights, evaluated in float64 on random inputs with and without a
+    2e-7 relative change, moves its output by more than 1e-4 with one rounding
+    and by less than 1e-5 with the hi + lo pair."""
+    rng = np.random.default_rng(0)
+
+    def bf(x):
+        return torch.tensor(x, dtype=torch.float32).to(torch.bfloat16).to(torch.float64).numpy()
+
+    Ws = [bf(rng.normal(0, (2 / 64) ** 0.5, size=(64, 64))) for _ in range(3)]
+    x0 = rng.uniform(-1, 1, size=(64, 4096))
+    x1 = x0 * (1 + 2e-7 * rng.standard_normal(x0.shape))
+
+    def net(x, split):
+        for W in Ws:
+            h = bf(x)
+            if split:
+                h = h + bf(x - h)
+            x = np.maximum(W @ h, 0)
+        return x
+
+    def change(split):
+        y0, y1 = net(x0, split), net(x1, split)
+        return np.linalg.norm(y1 - y0) / np.linalg.norm(y0)
+
+    assert change(False) > 1e-4
+    assert change(True) < 1e-5
