@@ -301,6 +301,22 @@ sssgs_status sssgs_image_loss(const float *pred, const float *target, int32_t ch
                               int32_t width, float lambda_dssim, void *workspace, size_t workspace_bytes,
                               float *loss_out, float *dL_dpred, void *stream);
 
+/* The image loss above for callers that cannot allocate device memory (code
+   under HIP graph capture, tight serving loops, harnesses that forbid
+   allocation): the same computation and outputs as sssgs_image_loss, with the
+   scratch in a fixed device array of SSSGS_NOALLOC_SCRATCH_BYTES that the
+   library holds on each GPU it runs on until the process ends.  The call
+   allocates nothing.  Images whose sssgs_image_loss_workspace_bytes exceed
+   that size are rejected with SSSGS_ERR_INVALID_ARG (32 MiB: three channels
+   of 1024 x 1024 do not fit, three of 800 x 800 do).  All calls on one GPU
+   share the array: calls that overlap on one GPU (different streams, or
+   threads) race and must be serialised by the caller; consecutive calls on
+   one stream are ordered.  Nothing in the array needs to start at zero. */
+#define SSSGS_NOALLOC_SCRATCH_BYTES (32u * 1024u * 1024u)
+sssgs_status sssgs_image_loss_noalloc(const float *pred, const float *target, int32_t channels, int32_t height,
+                                      int32_t width, float lambda_dssim, float *loss_out, float *dL_dpred,
+                                      void *stream);
+
 /* One Adam update (Appendix "Training": Adam with its default parameters) of
    `count` float parameters in place, all device arrays:
      m = beta1 m + (1 - beta1) g;  v = beta2 v + (1 - beta2) g^2;

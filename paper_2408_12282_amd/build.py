@@ -10,7 +10,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libsssgs.so")
 SOURCES = ["abi.hip", "project.hip", "binning.hip", "composite.hip", "shade.hip", "shade_bwd.hip", "mlp_prep.hip",
-           "mlp_wgrad.hip", "losses.hip", "gmlp.hip", "bvh.hip"]
+           "mlp_wgrad.hip", "losses.hip", "gmlp.hip", "bvh.hip", "noalloc.hip"]
 FLAGS = ["-O3", "--offload-arch=gfx950", "-fPIC", "-std=c++17", "-munsafe-fp-atomics",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-I", os.path.join(ROOT, "include")]

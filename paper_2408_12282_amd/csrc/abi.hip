@@ -914,3 +914,8 @@ int32_t sssgs_timing_stages(void) { return kStCount; }
 const char *sssgs_timing_stage_name(int32_t k) { return (k >= 0 && k < kStCount) ? kStageNames[k] : ""; }
 
 }  // extern "C"
+
+namespace sssgs {
+// Error reporting for entry points defined in other sources (sssgs_last_error).
+sssgs_status noalloc_fail(sssgs_status s, const char *msg) { return fail(s, msg); }
+}  // namespace sssgs

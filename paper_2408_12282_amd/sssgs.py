@@ -73,7 +73,7 @@ EXPORTS = ("sssgs_mlp_param_count", "sssgs_workspace_bytes", "sssgs_render_forwa
            "sssgs_timing_stage_name", "sssgs_image_loss_workspace_bytes", "sssgs_image_loss", "sssgs_adam_step",
            "sssgs_render_forward_lights", "sssgs_gaussian_mlp_param_count", "sssgs_gaussian_mlp_workspace_bytes",
            "sssgs_gaussian_mlp_forward", "sssgs_gaussian_mlp_backward", "sssgs_visibility_workspace_bytes",
-           "sssgs_trace_visibility")
+           "sssgs_trace_visibility", "sssgs_image_loss_noalloc")
 
 
 def load_library(path: str = LIB_PATH):
@@ -126,6 +126,9 @@ def load_library(path: str = LIB_PATH):
     L.sssgs_image_loss.restype = ct.c_int
     L.sssgs_image_loss.argtypes = [ct.c_void_p, ct.c_void_p, ct.c_int32, ct.c_int32, ct.c_int32, ct.c_float,
                                    ct.c_void_p, ct.c_size_t, ct.c_void_p, ct.c_void_p, ct.c_void_p]
+    L.sssgs_image_loss_noalloc.restype = ct.c_int
+    L.sssgs_image_loss_noalloc.argtypes = [ct.c_void_p, ct.c_void_p, ct.c_int32, ct.c_int32, ct.c_int32, ct.c_float,
+                                           ct.c_void_p, ct.c_void_p, ct.c_void_p]
     L.sssgs_adam_step.restype = ct.c_int
     L.sssgs_adam_step.argtypes = [ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_int64, ct.c_float,
                                   ct.c_float, ct.c_float, ct.c_float, ct.c_int32, ct.c_void_p]
@@ -241,6 +244,11 @@ def sssgs_image_loss(pred, target, channels, height, width, lambda_dssim, worksp
                      stream=None):
     return lib().sssgs_image_loss(pred, target, channels, height, width, lambda_dssim, workspace, ws_bytes,
                                   loss_out, grad, stream)
+
+
+def sssgs_image_loss_noalloc(pred, target, channels, height, width, lambda_dssim, loss_out, grad, stream=None):
+    return lib().sssgs_image_loss_noalloc(pred, target, channels, height, width, lambda_dssim, loss_out, grad,
+                                          stream)
 
 
 def sssgs_adam_step(param, grad, m, v, count, lr, beta1, beta2, eps, step, stream=None):
