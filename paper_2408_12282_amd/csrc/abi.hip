@@ -86,7 +86,7 @@ int in_pad_of(int in_dim) { return (in_dim + 31) / 32 * 32; }
 
 struct Layout {
   size_t records, depth_keys, vals_a, keys_b, vals_b, keys_a, rects, radii, boxes, tt, offsets, partials, hist;
-  size_t ik_a, iv_a, ik_b, iv_b, ranges, tcount, apart, t_final, n_contrib, status, m_total;
+  size_t ik_a, iv_a, ik_b, iv_b, ranges, tcount, apart, t_final, tile_top, tile_order, n_contrib, status, m_total;
   size_t gacc, slots, sflags, dG, dT, wops, tops, nops, mlp_part, mlp_mid, rec_x, rec_o, gx, gdy;
   size_t total;
   int C, RS, GS, TX, TY, T;
@@ -140,6 +140,8 @@ bool make_layout(int32_t n, int32_t W, int32_t H, int32_t F, int32_t mlp_width, 
   L.iv_b = take(cc * 4);
   L.ranges = take((size_t)L.T * 8);
   L.t_final = take(HW * 4);
+  L.tile_top = take((size_t)L.T * 4);
+  L.tile_order = take((size_t)L.T * 4);
   L.n_contrib = take(HW * 4);
   L.status = take(16);
   L.m_total = take(16);
@@ -275,6 +277,7 @@ void project_bwd(int F, bool sh, const ProjIn &in, const CamArgs &cam, const flo
 }
 
 void composite_fwd(int C, const Layout &L, void *ws, int W, int H, float *gbuf, hipStream_t st) {
+  uint32_t *top = at<uint32_t>(ws, L.tile_top);
   const uint2 *rg = at<uint2>(ws, L.ranges);
   const uint32_t *sg = at<uint32_t>(ws, L.iv_a);
   const float *rec = at<float>(ws, L.records);
@@ -282,14 +285,17 @@ void composite_fwd(int C, const Layout &L, void *ws, int W, int H, float *gbuf, 
   float *tf = at<float>(ws, L.t_final);
   uint32_t *nc = at<uint32_t>(ws, L.n_contrib);
   switch (C) {
-    case 10: launch_composite_fwd_t<10>(rg, sg, rec, bx, W, H, L.TX, L.TY, gbuf, tf, nc, st); break;
-    case 18: launch_composite_fwd_t<18>(rg, sg, rec, bx, W, H, L.TX, L.TY, gbuf, tf, nc, st); break;
-    case 26: launch_composite_fwd_t<26>(rg, sg, rec, bx, W, H, L.TX, L.TY, gbuf, tf, nc, st); break;
-    default: launch_composite_fwd_t<42>(rg, sg, rec, bx, W, H, L.TX, L.TY, gbuf, tf, nc, st); break;
+    case 10: launch_composite_fwd_t<10>(rg, sg, rec, bx, W, H, L.TX, L.TY, gbuf, tf, nc, top, st); break;
+    case 18: launch_composite_fwd_t<18>(rg, sg, rec, bx, W, H, L.TX, L.TY, gbuf, tf, nc, top, st); break;
+    case 26: launch_composite_fwd_t<26>(rg, sg, rec, bx, W, H, L.TX, L.TY, gbuf, tf, nc, top, st); break;
+    default: launch_composite_fwd_t<42>(rg, sg, rec, bx, W, H, L.TX, L.TY, gbuf, tf, nc, top, st); break;
   }
 }
 
 void composite_bwd(int C, const Layout &L, void *ws, int W, int H, const DetSlots &det, hipStream_t st) {
+  // heaviest tiles first: dispatch order from the forward's per-tile work
+  uint32_t *ord = at<uint32_t>(ws, L.tile_order);
+  launch_tile_order(at<uint32_t>(ws, L.tile_top), L.T, ord, st);
   const uint2 *rg = at<uint2>(ws, L.ranges);
   const uint32_t *sg = at<uint32_t>(ws, L.iv_a);
   const float *rec = at<float>(ws, L.records);
@@ -300,10 +306,10 @@ void composite_bwd(int C, const Layout &L, void *ws, int W, int H, const DetSlot
   const float *dT = at<float>(ws, L.dT);
   float *ga = at<float>(ws, L.gacc);
   switch (C) {
-    case 10: launch_composite_bwd_t<10>(rg, sg, rec, bx, W, H, L.TX, L.TY, tf, nc, dG, dT, ga, det, st); break;
-    case 18: launch_composite_bwd_t<18>(rg, sg, rec, bx, W, H, L.TX, L.TY, tf, nc, dG, dT, ga, det, st); break;
-    case 26: launch_composite_bwd_t<26>(rg, sg, rec, bx, W, H, L.TX, L.TY, tf, nc, dG, dT, ga, det, st); break;
-    default: launch_composite_bwd_t<42>(rg, sg, rec, bx, W, H, L.TX, L.TY, tf, nc, dG, dT, ga, det, st); break;
+    case 10: launch_composite_bwd_t<10>(rg, sg, rec, bx, W, H, L.TX, L.TY, tf, nc, dG, dT, ga, det, ord, st); break;
+    case 18: launch_composite_bwd_t<18>(rg, sg, rec, bx, W, H, L.TX, L.TY, tf, nc, dG, dT, ga, det, ord, st); break;
+    case 26: launch_composite_bwd_t<26>(rg, sg, rec, bx, W, H, L.TX, L.TY, tf, nc, dG, dT, ga, det, ord, st); break;
+    default: launch_composite_bwd_t<42>(rg, sg, rec, bx, W, H, L.TX, L.TY, tf, nc, dG, dT, ga, det, ord, st); break;
   }
 }
 

@@ -30,11 +30,13 @@ __global__ __launch_bounds__(256, 6) void composite_fwd_kernel(const uint2 *__re
                                                             const short4 *__restrict__ boxes, int W, int H,
                                                             int TX, float *__restrict__ gbuf,
                                                             float *__restrict__ t_final,
-                                                            uint32_t *__restrict__ n_contrib) {
+                                                            uint32_t *__restrict__ n_contrib,
+                                                            uint32_t *__restrict__ tile_top) {
   constexpr int RS = rec_stride(C);
   constexpr int NB = 128;  // records per batch (small LDS footprint: 6 waves per SIMD)
   __shared__ float4 batch[NB * RS / 4];
   __shared__ uint2 bbox[NB];
+  __shared__ uint32_t tmax;
   const int t = threadIdx.x, lane = t & 63;
   const int w = __builtin_amdgcn_readfirstlane(t >> 6);
   const int tile = blockIdx.x;
@@ -51,6 +53,7 @@ __global__ __launch_bounds__(256, 6) void composite_fwd_kernel(const uint2 *__re
   for (int c = 0; c < C; c++) acc[c] = 0.f;
   uint32_t last = 0;
   bool done = !inside;
+  if (t == 0) tmax = 0;
   for (uint32_t b0 = rg.x; b0 < rg.y; b0 += NB) {
     if (__syncthreads_count(done) == 256) break;
     const uint32_t e = b0 + t;
@@ -67,26 +70,39 @@ __global__ __launch_bounds__(256, 6) void composite_fwd_kernel(const uint2 *__re
       bool h = false;
       if (j0 + lane < cnt) h = box_hits(bbox[j0 + lane], sx, sy);
       uint64_t m = __ballot(h);
-      while (m != 0 && __ballot(!done) != 0) {
-        const int j = j0 + (int)__builtin_ctzll(m);
+      if (m == 0 || __ballot(!done) == 0) continue;
+      int j = j0 + (int)__builtin_ctzll(m);
+      m &= m - 1;
+      float4 ha = batch[j * (RS / 4)], hb = batch[j * (RS / 4) + 1];  // u v a b | c opacity ..
+      while (true) {
+        // the next record's header is read while this one is evaluated (the
+        // walk is bound by the latency of these dependent LDS reads)
+        const bool more = m != 0;
+        const int jn = more ? j0 + (int)__builtin_ctzll(m) : j;
         m &= m - 1;
-        if (done) continue;
-        const float *r = reinterpret_cast<const float *>(&batch[j * (RS / 4)]);
-        float dx, dy;
-        const float pw = splat_power(r[0], r[1], r[2], r[3], r[4], pxc, pyc, dx, dy);
-        if (pw > 0.f) continue;
-        const float al = fminf(0.99f, splat_alpha_raw(r[5], pw));
-        if (al < (1.f / 255.f)) continue;
-        const float tn = T * (1.f - al);
-        if (tn < 1e-4f) {
-          done = true;
-          continue;
-        }
-        const float wgt = al * T;
+        const float4 na = batch[jn * (RS / 4)], nb = batch[jn * (RS / 4) + 1];
+        if (!done) {
+          float dx, dy;
+          const float pw = splat_power(ha.x, ha.y, ha.z, ha.w, hb.x, pxc, pyc, dx, dy);
+          const float al = fminf(0.99f, splat_alpha_raw(hb.y, pw));
+          if (pw <= 0.f && al >= (1.f / 255.f)) {
+            const float tn = T * (1.f - al);
+            if (tn < 1e-4f) {
+              done = true;
+            } else {
+              const float *r = reinterpret_cast<const float *>(&batch[j * (RS / 4)]);
+              const float wgt = al * T;
 #pragma unroll
-        for (int c = 0; c < C; c++) acc[c] = __fmaf_rn(wgt, r[6 + c], acc[c]);
-        T = tn;
-        last = b0 - rg.x + j + 1;
+              for (int c = 0; c < C; c++) acc[c] = __fmaf_rn(wgt, r[6 + c], acc[c]);
+              T = tn;
+              last = b0 - rg.x + j + 1;
+            }
+          }
+        }
+        if (!more || __ballot(!done) == 0) break;
+        j = jn;
+        ha = na;
+        hb = nb;
       }
     }
   }
@@ -97,6 +113,11 @@ __global__ __launch_bounds__(256, 6) void composite_fwd_kernel(const uint2 *__re
     t_final[pix] = T;
     n_contrib[pix] = last;
   }
+  // the tile's largest last-contributor index: the backward's work per tile
+  __syncthreads();
+  atomicMax(&tmax, last);
+  __syncthreads();
+  if (t == 0) tile_top[blockIdx.x] = tmax;
 }
 
 // ---------------------------------------------------------------- backward
@@ -158,7 +179,7 @@ __global__ __launch_bounds__(256, C > 26 ? 2 : 3) void composite_bwd_kernel(
     const uint2 *__restrict__ ranges, const uint32_t *__restrict__ sorted_g, const float *__restrict__ records,
     const short4 *__restrict__ boxes, int W, int H, int TX, const float *__restrict__ t_final,
     const uint32_t *__restrict__ n_contrib, const float *__restrict__ dG, const float *__restrict__ dT,
-    float *__restrict__ gacc, DetSlots det) {
+    float *__restrict__ gacc, DetSlots det, const uint32_t *__restrict__ order) {
   constexpr int RS = rec_stride(C);
   constexpr int R4 = RS / 4;              // float4 per record
   constexpr int GS = grad_stride(C);
@@ -179,7 +200,7 @@ __global__ __launch_bounds__(256, C > 26 ? 2 : 3) void composite_bwd_kernel(
   __shared__ uint32_t maxlast;
   const int t = threadIdx.x, lane = t & 63, g = lane >> 4, col = lane & 15;
   const int w = __builtin_amdgcn_readfirstlane(t >> 6);
-  const int tile = blockIdx.x;
+  const int tile = (int)order[blockIdx.x];  // heaviest tiles first
   const int tx = tile % TX, ty = tile / TX;
   const int sx = tx * kTile, sy = ty * kTile + 4 * w;  // the wave's 16x4 strip
   const int px = sx + (lane & 15), py = sy + (lane >> 4);
@@ -474,17 +495,66 @@ __global__ __launch_bounds__(256, C > 26 ? 2 : 3) void composite_bwd_kernel(
 template <int C>
 void launch_composite_fwd_t(const uint2 *ranges, const uint32_t *sorted_g, const float *records, const short4 *boxes,
                             int W, int H, int TX, int TY, float *gbuf, float *t_final, uint32_t *n_contrib,
-                            hipStream_t st) {
+                            uint32_t *tile_top, hipStream_t st) {
   composite_fwd_kernel<C><<<TX * TY, 256, 0, st>>>(ranges, sorted_g, records, boxes, W, H, TX, gbuf, t_final,
-                                                   n_contrib);
+                                                   n_contrib, tile_top);
 }
 
 template <int C>
 void launch_composite_bwd_t(const uint2 *ranges, const uint32_t *sorted_g, const float *records, const short4 *boxes,
                             int W, int H, int TX, int TY, const float *t_final, const uint32_t *n_contrib,
-                            const float *dG, const float *dT, float *gacc, const DetSlots &det, hipStream_t st) {
+                            const float *dG, const float *dT, float *gacc, const DetSlots &det,
+                            const uint32_t *order, hipStream_t st) {
   composite_bwd_kernel<C><<<TX * TY, 256, 0, st>>>(ranges, sorted_g, records, boxes, W, H, TX, t_final, n_contrib,
-                                                   dG, dT, gacc, det);
+                                                   dG, dT, gacc, det, order);
+}
+
+// Tiles in descending order of the forward's largest last-contributor index
+// (the backward's work per tile), so that the longest workgroups start first
+// and short ones fill the end: a counting sort on min(top, 4095) in one
+// workgroup.  Ties land in arbitrary order (it only changes the dispatch
+// order; every result is independent of it).
+constexpr int kOrderBins = 4096;
+
+__global__ __launch_bounds__(1024) void tile_order_kernel(const uint32_t *__restrict__ tile_top, int T,
+                                                          uint32_t *__restrict__ order) {
+  __shared__ uint32_t bins[kOrderBins];
+  __shared__ uint32_t part[1024];
+  const int t = threadIdx.x;
+  for (int b = t; b < kOrderBins; b += 1024) bins[b] = 0;
+  __syncthreads();
+  for (int i = t; i < T; i += 1024) atomicAdd(&bins[kOrderBins - 1 - min(tile_top[i], (uint32_t)kOrderBins - 1)], 1u);
+  __syncthreads();
+  // exclusive scan: 4 bins per thread, then over the threads
+  uint32_t v[4], s = 0;
+#pragma unroll
+  for (int k = 0; k < 4; k++) {
+    v[k] = bins[4 * t + k];
+    s += v[k];
+  }
+  part[t] = s;
+  __syncthreads();
+  for (int o = 1; o < 1024; o <<= 1) {
+    const uint32_t a = t >= o ? part[t - o] : 0u;
+    __syncthreads();
+    part[t] += a;
+    __syncthreads();
+  }
+  uint32_t run = part[t] - s;
+#pragma unroll
+  for (int k = 0; k < 4; k++) {
+    bins[4 * t + k] = run;
+    run += v[k];
+  }
+  __syncthreads();
+  for (int i = t; i < T; i += 1024) {
+    const uint32_t pos = atomicAdd(&bins[kOrderBins - 1 - min(tile_top[i], (uint32_t)kOrderBins - 1)], 1u);
+    order[pos] = (uint32_t)i;
+  }
+}
+
+void launch_tile_order(const uint32_t *tile_top, int T, uint32_t *order, hipStream_t st) {
+  tile_order_kernel<<<1, 1024, 0, st>>>(tile_top, T, order);
 }
 
 // ---------------------------------------------------------------- deterministic sums
@@ -544,10 +614,12 @@ void launch_slot_reduce(int C, const DetSlots &det, uint32_t n, float *gacc, hip
 
 #define SSSGS_COMP_INST(C)                                                                                      \
   template void launch_composite_fwd_t<C>(const uint2 *, const uint32_t *, const float *, const short4 *, int,  \
-                                          int, int, int, float *, float *, uint32_t *, hipStream_t);          \
+                                          int, int, int, float *, float *, uint32_t *, uint32_t *,             \
+                                          hipStream_t);                                                        \
   template void launch_composite_bwd_t<C>(const uint2 *, const uint32_t *, const float *, const short4 *, int,  \
                                           int, int, int, const float *, const uint32_t *, const float *,      \
-                                          const float *, float *, const DetSlots &, hipStream_t);
+                                          const float *, float *, const DetSlots &, const uint32_t *,        \
+                                          hipStream_t);
 SSSGS_COMP_INST(10)
 SSSGS_COMP_INST(18)
 SSSGS_COMP_INST(26)

@@ -48,11 +48,13 @@ void launch_tile_lists(uint32_t n, uint32_t cap, int TX, int TY, uint32_t *ka, u
 template <int C>
 void launch_composite_fwd_t(const uint2 *ranges, const uint32_t *sorted_g, const float *records, const short4 *boxes,
                             int W, int H, int TX, int TY, float *gbuf, float *t_final, uint32_t *n_contrib,
-                            hipStream_t st);
+                            uint32_t *tile_top, hipStream_t st);
 template <int C>
 void launch_composite_bwd_t(const uint2 *ranges, const uint32_t *sorted_g, const float *records, const short4 *boxes,
                             int W, int H, int TX, int TY, const float *t_final, const uint32_t *n_contrib,
-                            const float *dG, const float *dT, float *gacc, const DetSlots &det, hipStream_t st);
+                            const float *dG, const float *dT, float *gacc, const DetSlots &det,
+                            const uint32_t *order, hipStream_t st);
+void launch_tile_order(const uint32_t *tile_top, int T, uint32_t *order, hipStream_t st);
 void launch_rect_area(const ushort4 *rects, uint32_t n, uint32_t *area, hipStream_t st);
 void launch_slot_reduce(int C, const DetSlots &det, uint32_t n, float *gacc, hipStream_t st);
 

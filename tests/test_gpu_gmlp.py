@@ -133,6 +133,22 @@ def test_render_with_per_gaussian_network():
     assert_close_masked(rgb.cpu().numpy(), ora_f["rgb"], np.broadcast_to(ok, (3, H, W)), ELEM_REL, "rgb",
                         scale=np.abs(ora_f["rgb"]) + ora_f["rgb_sens"])
     np.testing.assert_allclose(alpha.cpu().numpy(), gbuf.cpu().numpy()[17], rtol=1e-6, atol=1e-5)
+    # end to end: the oracle's own FP64 network features through the oracle's
+    # render.  The FP32 network's outputs are held to 1e-5 of the size of
+    # their last sum's terms (forward_bound, as in the network tests); those
+    # bounds composited like the planes give the feature planes' scale.
+    ora_e = O.render(g, cam, light, radiance_features=True, params64=p64)
+    xin, _ = GM.inputs(g.means, g.log_scales, g.quats, vis, cam.center, light.pos)
+    bound8 = np.concatenate([GM.forward_bound(xin, gm), np.zeros((2, n))])
+    ora_bd = O.render(g, cam, light, radiance_features=True, params64=dict(p64, features=bound8))
+    ok_e = ora_e["pix_flag"] == 0
+    scale = np.abs(ora_e["gbuf"]) + ora_e["gbuf_abs"]
+    scale[10:16] += ora_bd["gbuf"][10:16]
+    assert_close_masked(gbuf.cpu().numpy(), ora_e["gbuf"], np.broadcast_to(ok_e, (18, H, W)), ELEM_REL, "gbuf e2e",
+                        scale=scale)
+    e_rgb, e_g = rel_norm(rgb.cpu().numpy(), ora_e["rgb"]), rel_norm(gbuf.cpu().numpy(), ora_e["gbuf"])
+    print(f"  end to end: rgb {e_rgb:.2e} gbuf {e_g:.2e}")
+    assert e_g < 1e-5 and e_rgb < 1e-4
     # backward with upstream gradient on pixels away from alpha / stop decisions
     rng = np.random.default_rng(13)
     drgb = (rng.normal(size=(3, H, W)) * ok).astype(np.float32)

@@ -119,15 +119,23 @@ def test_coincident_centres_and_determinism():
 
 
 def test_full_size_sampled():
-    """300k Gaussians (the headline scene): 40 sampled rays checked one by one
-    against the oracle over all 300k Gaussians."""
+    """300k Gaussians (the headline scene): the 4000 Gaussians nearest the
+    light (most of the scene's rays end at the 0 floor; these do not: over
+    2000 of them keep a visibility above it) and 40 random ones, each ray
+    checked against the oracle over all 300k Gaussians."""
     w = scene.workload(3)
     g = w.gaussians
     light = w.lights[0].pos
     print("[gpu] visibility 300k sampled", flush=True)
     got = _gpu(*_f32(g), light)
-    recv = np.random.default_rng(11).choice(g.n, 40, replace=False)
-    ref, flag = V.visibility(*_f32(g), light, margins=True, receivers=recv)
+    mu = g.means.T.astype(np.float64)
+    d = np.asarray(light, np.float64) / np.linalg.norm(light)
+    near_light = np.argsort(-(mu @ d))[:4000]
+    recv = np.unique(np.concatenate([near_light, np.random.default_rng(11).choice(g.n, 40, replace=False)]))
+    ref, flag = V.visibility(*_f32(g), light, margins=True, receivers=recv, prefilter=True)
+    nontrivial = int(np.sum((ref[recv] > 0) & ~flag[recv]))
+    print(f"  rays compared {recv.size}, above the floor {nontrivial}")
+    assert nontrivial >= 2000
     _compare(got[recv], ref[recv], flag[recv], "300k sampled")
     assert np.all((got >= 0) & (got <= 1))
 
@@ -199,3 +207,15 @@ def test_gaussians_that_cannot_occlude():
     keep[::3] = False
     sub = _gpu(g.means[:, keep], g.log_scales[:, keep], g.quats[:, keep], g.opacity_logits[keep], light)
     np.testing.assert_allclose(got[keep], sub, rtol=2e-7, atol=0)   # other tree, other product order
+
+
+def test_all_rays_20k():
+    """Every ray of a 20k-Gaussian scene (node ranges long enough for the
+    4096-leaf box units of the hierarchy's build) against the oracle."""
+    g = scene.make_gaussians(20000, 0, seed=19)
+    light = scene.default_light().pos
+    print("[gpu] visibility 20k, all rays", flush=True)
+    got = _gpu(*_f32(g), light)
+    ref, flag = V.visibility(*_f32(g), light, margins=True, prefilter=True)
+    print(f"  above the floor {int(np.sum(ref > 0))}")
+    _compare(got, ref, flag, "20k all rays")

@@ -100,3 +100,17 @@ def test_order_invariance():
     vp = V.visibility(g.means[:, perm], g.log_scales[:, perm], g.quats[:, perm], g.opacity_logits[perm], P)
     np.testing.assert_allclose(vp, v[perm], rtol=1e-12, atol=0)
     assert (v < 1).any() and (v > 0).any()
+
+
+def test_prefilter_gives_the_same_bits():
+    """The per-ray distance prefilter only drops Gaussians whose alpha stays
+    below 1/255 on the whole line: values and margin flags are identical."""
+    g = scene.make_gaussians(3000, 0, seed=13)
+    g.log_scales = (g.log_scales + 1.0).astype(np.float32)
+    light = scene.default_light().pos
+    args = (g.means, g.log_scales, g.quats, g.opacity_logits, light)
+    recv = np.random.default_rng(2).choice(g.n, 400, replace=False)
+    a, fa = V.visibility(*args, margins=True, receivers=recv)
+    b, fb = V.visibility(*args, margins=True, receivers=recv, prefilter=True)
+    assert np.array_equal(a, b) and np.array_equal(fa, fb)
+    assert np.any((a[recv] > 0) & (a[recv] < 1))
