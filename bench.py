@@ -22,10 +22,12 @@ sys.path.insert(0, ROOT)
 WORKLOAD = 3
 MPIX = 0.64
 HBM_PEAK_GBS = 8000.0
-FP32_VALU_TFLOPS = 78.6      # non-packed FP32 FMA: 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz
+# FP32 vector peak reachable here: packed FP32 is compiled out, so one FMA per
+# lane per clock: 256 CUs x 4 SIMDs x 16 lanes x 2 flop x 2.4 GHz (the 157.3
+# TFLOP/s figure counts packed FMA).
+FP32_VALU_TFLOPS = 78.6
 BF16_MFMA_TFLOPS = 2500.0
 FP32_MFMA_TFLOPS = 157.3      # dense FP32 matrix-core peak
-FP32_VALU_TFLOPS = 157.3      # FP32 vector peak: 256 CUs x 2.4 GHz x 128 lanes (packed) x 2 flop per FMA
 
 
 def parse():
@@ -36,6 +38,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-views", type=int, default=2, help="views in the CPU oracle sample")
     ap.add_argument("--precision", choices=["both", "bf16", "fp32"], default="both")
+    ap.add_argument("--no-other-workloads", action="store_true", help="skip the 100k, 8-view 500k and 1M lines")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="after the run, copy this many MiB device-to-device (a plain copy of known size, "
                          "to scale the HBM byte counters of a profiled run)")
@@ -84,15 +87,16 @@ def run_gpu(precision: str, steps: int, warmup: int):
     for _ in range(warmup):
         step()
     torch.cuda.synchronize()
-    # timed region: exactly `steps` steps, no per-stage events
-    t0 = torch.cuda.Event(enable_timing=True)
-    t1 = torch.cuda.Event(enable_timing=True)
-    t0.record()
-    for _ in range(steps):
+    # timed region: exactly `steps` steps, an event between consecutive steps
+    # (per-step median and percentiles), no per-stage events
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+    ev[0].record()
+    for i in range(steps):
         step()
-    t1.record()
+        ev[i + 1].record()
     torch.cuda.synchronize()
-    ms = t0.elapsed_time(t1) / steps
+    ms = ev[0].elapsed_time(ev[steps]) / steps
+    per_step = np.array([ev[i].elapsed_time(ev[i + 1]) for i in range(steps)])
     # per-stage kernel durations: HIP events recorded around every stage on the
     # stream its kernels run on, over separate steps
     B.sssgs_timing_read()
@@ -110,7 +114,8 @@ def run_gpu(precision: str, steps: int, warmup: int):
                                             cap)
     assert flags == 0 and m_dev == M, (flags, m_dev, M)
     per_tile_last, fwd_records, listed = tile_stats(view, cam)
-    return {"ms": ms, "stages": {k: (v[0] / max(v[1], 1), v[1]) for k, v in stages.items()}, "M": M,
+    return {"ms": ms, "per_step": per_step, "stages": {k: (v[0] / max(v[1], 1), v[1]) for k, v in stages.items()},
+            "M": M,
             "bwd_records": per_tile_last, "fwd_records": fwd_records, "listed": listed, "n": g.n,
             "C": 10 + g.feat_dim, "HW": cam.width * cam.height, "precision": precision, "training": extras,
             "ibl": ibl, "gnet": gnet, "vis": vis}
@@ -307,6 +312,7 @@ def roofline(r):
     """Algorithmic bytes (compositing, HBM-bound model) or flops (shading network,
     matrix-core model) per launch, divided by the kernels' measured durations."""
     C = r["C"]
+    in_dim, width = r.get("net") or (58, 64)
     RS = (6 + C + 3) // 4 * 4
     HW = r["HW"]
     # forward: records + index per processed instance, G-buffer + T + n_contrib written
@@ -317,7 +323,7 @@ def roofline(r):
     # backward = the forward recomputed + input gradients + weight gradients (3x).  With the BF16
     # width-64 network the backward is two kernels: shading backward (recompute + input
     # gradients, 2x) and the weight-gradient kernel (1x; it recomputes what it needs on top).
-    net_flop = 2 * (58 * 64 + 2 * 64 * 64 + 64 * 6)
+    net_flop = 2 * (in_dim * width + 2 * width * width + width * 6)
     split = r["stages"].get("mlp_wgrad", (0.0, 0))[0] > 0
     out = {}
     traffic = measured_traffic()
@@ -328,6 +334,8 @@ def roofline(r):
             out[name] = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                          "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": traffic.get(name), "kernel": name,
                          "bytes_per_launch": int(nbytes), "ms_per_launch": round(t, 4)}
+    if not r.get("has_net", True):
+        return out
     peak = BF16_MFMA_TFLOPS if r["precision"] == "bf16" else FP32_MFMA_TFLOPS
     flops = [("shade_fwd", HW * net_flop), ("shade_bwd", (2 if split else 3) * HW * net_flop)]
     if split:
@@ -339,6 +347,170 @@ def roofline(r):
             out[name] = {"bound": "mfma", "achieved": round(tf, 2), "peak": peak, "unit": "TFLOP/s",
                          "frac": round(tf / peak, 4), "traffic": traffic.get(name), "kernel": name,
                          "flop_per_launch": int(flop), "ms_per_launch": round(t, 4)}
+    return out
+
+
+def copy_ceiling(mib: int = 1024, reps: int = 10):
+    """Achievable HBM bandwidth: a device-to-device copy of `mib` MiB (read + write)."""
+    import torch
+    src = torch.ones(mib << 18, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    t0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    t1.record()
+    torch.cuda.synchronize()
+    ms = t0.elapsed_time(t1) / reps
+    gbs = 2 * (mib << 20) / (ms * 1e-3) / 1e9
+    del src, dst
+    return {"gbs": round(gbs, 1), "bytes_moved": 2 * (mib << 20), "ms": round(ms, 4),
+            "frac_of_peak": round(gbs / HBM_PEAK_GBS, 4)}
+
+
+def _time_steps(step, steps: int, warmup: int):
+    import torch
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+    ev[0].record()
+    for i in range(steps):
+        step()
+        ev[i + 1].record()
+    torch.cuda.synchronize()
+    per = np.array([ev[i].elapsed_time(ev[i + 1]) for i in range(steps)])
+    return ev[0].elapsed_time(ev[steps]) / steps, per
+
+
+def _stage_times(step, reps: int):
+    import torch
+    from paper_2408_12282_amd import sssgs as B
+    B.sssgs_timing_read()
+    B.sssgs_timing_enable(True)
+    for _ in range(reps):
+        step()
+    torch.cuda.synchronize()
+    B.sssgs_timing_enable(False)
+    return {k: (v[0] / max(v[1], 1), v[1]) for k, v in B.sssgs_timing_read().items()}
+
+
+def _stats(per):
+    return {"median_ms": round(float(np.median(per)), 4), "p10_ms": round(float(np.percentile(per, 10)), 4),
+            "p90_ms": round(float(np.percentile(per, 90)), 4)}
+
+
+def time_other_workloads(steps: int, warmup: int):
+    """The other synthetic workloads (outside the headline): the 100k G-buffer
+    fwd+bwd (FP32, no network, loss sum(w * G)), the 8-view 500k OLAT training
+    step (BF16 network, L1 loss, gradients accumulated over the views) and the
+    1M-Gaussian SH view at 1600x1200 with the width-128 BF16 network; each with
+    per-step statistics, stage times and the roofline of its kernels."""
+    import torch
+    from paper_2408_12282_amd import scene, sssgs as B
+    out = {}
+    dev = "cuda"
+
+    def setup(w, cam):
+        g = w.gaussians
+        p = {k: torch.from_numpy(np.ascontiguousarray(v)).to(dev) for k, v in g.arrays().items() if v is not None}
+        mp = torch.from_numpy(w.mlp.params).to(dev) if w.mlp is not None else None
+        mw = w.mlp.width if w.mlp is not None else 0
+        view = B.View(g.n, cam.width, cam.height, g.feat_dim, mw, 64 * g.n, device=dev)
+        return g, p, mp, mw, view
+
+    def summarize(name, desc, ms, per, stages, view, cam, g, prec, net, mpix, extra=None):
+        per_tile_last, fwd_records, listed = tile_stats(view, cam)
+        r = {"stages": stages, "C": 10 + g.feat_dim, "HW": cam.width * cam.height, "n": g.n, "precision": prec,
+             "fwd_records": fwd_records, "bwd_records": per_tile_last, "net": net, "has_net": net is not None}
+        rl = roofline(r)
+        d = {"workload": desc, "ms_per_step": round(ms, 4), "mpix_s": round(mpix / (ms * 1e-3), 2),
+             "step_stats": _stats(per), "stages_ms": {k: round(v[0], 4) for k, v in stages.items() if v[1] > 0},
+             "roofline": max(rl.values(), key=lambda v: v["ms_per_launch"]) if rl else None, "roofline_all": rl}
+        if extra:
+            d.update(extra)
+        out[name] = d
+
+    # 100k Gaussians, 800x800, G-buffer fwd + bwd, L = sum(w * G) + 0 * rgb
+    w = scene.workload(2)
+    cam, light = w.cameras[0], w.lights[0]
+    g, p, mp, mw, view = setup(w, cam)
+    bc, bl = B.make_camera(cam), B.make_light(light)
+    dg = torch.from_numpy(scene.upstream_weights((10 + g.feat_dim, cam.height, cam.width), 1)).to(dev)
+    zr = torch.zeros((3, cam.height, cam.width), device=dev)
+    grads = {k: torch.empty_like(v) for k, v in p.items()}
+
+    def step2():
+        rgb, gbuf, alpha, _ = B.render_forward(view, p, -1, bc, bl, None, 64, B.PREC_FP32)
+        B.render_backward(view, p, -1, bc, bl, gbuf, zr, dg, None, None, 64, B.PREC_FP32, grads)
+
+    ms, per = _time_steps(step2, steps, warmup)
+    summarize("gbuffer_100k_800sq", "100k Gaussians 800x800, 26-channel G-buffer fwd+bwd, FP32, loss sum(w*G)",
+              ms, per, _stage_times(step2, 5), view, cam, g, "fp32", None, MPIX)
+    del view, p, grads, dg
+    torch.cuda.empty_cache()
+
+    # 500k Gaussians, 8 (camera, light) views, BF16 network, L1 loss, accumulated gradients
+    w = scene.workload(4)
+    tw = scene.workload(4, seed=1)
+    g, p, mp, mw, view = setup(w, w.cameras[0])
+    tp = {k: torch.from_numpy(np.ascontiguousarray(v)).to(dev) for k, v in tw.gaussians.arrays().items()
+          if v is not None}
+    tmp = torch.from_numpy(tw.mlp.params).to(dev)
+    cams = [B.make_camera(c) for c in w.cameras]
+    lights = [B.make_light(l) for l in w.lights]
+    # targets: the independently seeded scene rendered by this renderer (outside the timed region)
+    targets = []
+    for v in range(8):
+        t, _, _, _ = B.render_forward(view, tp, -1, cams[v], lights[v], tmp, mw, B.PREC_BF16)
+        targets.append(t.clone())
+    H, W = w.cameras[0].height, w.cameras[0].width
+    scale = 1.0 / (3 * H * W)
+    grads = {k: torch.zeros_like(v) for k, v in p.items()}
+    dmlp = torch.zeros_like(mp)
+    dl = torch.empty((3, H, W), device=dev)
+    loss = torch.zeros(1, device=dev)
+
+    def step4():
+        for v in range(8):
+            rgb, gbuf, alpha, _ = B.render_forward(view, p, -1, cams[v], lights[v], mp, mw, B.PREC_BF16)
+            B.sssgs_l1_loss(B._ptr(rgb), B._ptr(targets[v]), rgb.numel(), scale, B._ptr(loss), B._ptr(dl),
+                            B._stream())
+            B.render_backward(view, p, -1, cams[v], lights[v], gbuf, dl, None, None, mp, mw, B.PREC_BF16, grads,
+                              dmlp, accumulate=(v > 0))
+
+    s4 = max(2, steps // 4)
+    ms, per = _time_steps(step4, s4, 1)
+    summarize("olat_8view_500k_800sq", "500k Gaussians, 8 cameras on a sphere of radius 3 each with its own point "
+              "light, 800x800, BF16 network, L1 loss, gradients accumulated; ms_per_step covers the 8 views",
+              ms, per, _stage_times(step4, 1), view, w.cameras[7], g, "bf16", (58, 64), 8 * MPIX,
+              {"ms_per_view": round(ms / 8, 4)})
+    del view, p, tp, grads, targets
+    torch.cuda.empty_cache()
+
+    # 1M Gaussians, SH colour, 32 features, 1600x1200, width-128 BF16 network
+    w = scene.workload(5)
+    cam, light = w.cameras[0], w.lights[0]
+    g, p, mp, mw, view = setup(w, cam)
+    bc, bl = B.make_camera(cam), B.make_light(light)
+    drgb = torch.from_numpy(scene.upstream_weights((3, cam.height, cam.width), 1)).to(dev)
+    grads = {k: torch.empty_like(v) for k, v in p.items()}
+    dmlp = torch.empty_like(mp)
+
+    def step5():
+        rgb, gbuf, alpha, _ = B.render_forward(view, p, 3, bc, bl, mp, mw, B.PREC_BF16)
+        B.render_backward(view, p, 3, bc, bl, gbuf, drgb, None, None, mp, mw, B.PREC_BF16, grads, dmlp)
+
+    s5 = max(3, steps // 2)
+    ms, per = _time_steps(step5, s5, 2)
+    summarize("sh_1m_1600x1200_w128", "1M Gaussians, degree-3 SH colour, 32 features (C = 42), 1600x1200, "
+              "BF16 network 74(96)->128x3->6, fwd+bwd", ms, per, _stage_times(step5, 3), view, cam, g, "bf16",
+              (74, 128), 1.92)
+    del view, p, grads
+    torch.cuda.empty_cache()
     return out
 
 
@@ -354,9 +526,17 @@ def cpu_baseline(views: int):
     for _ in range(views):
         oracle.render(g, cam, light, mlp, bf16=True, drgb=drgb, nthreads=threads)
     dt = (time.perf_counter() - t) / views
+    # one core: the centre 400x400 quarter of the view (a quarter of the pixels)
+    crop = (200, 200, 600, 600)
+    t = time.perf_counter()
+    oracle.render(g, cam, light, mlp, bf16=True, drgb=drgb, nthreads=1, crop=crop)
+    d1 = time.perf_counter() - t
+    mpix_crop = 0.16
     return {"value": round(MPIX / dt, 4), "unit": "Mpix/s", "cores": threads, "kind": "oracle",
             "sample": f"{views} full views (300k Gaussians, 800x800, fwd+bwd, FP64 with BF16 network emulation)",
-            "s_per_view": round(dt, 3)}
+            "s_per_view": round(dt, 3),
+            "one_core": {"value": round(mpix_crop / d1, 4), "unit": "Mpix/s", "cores": 1,
+                         "sample": "the centre 400x400 crop of the same view, fwd+bwd", "s": round(d1, 3)}}
 
 
 def main():
@@ -382,12 +562,14 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32 (network bf16)" if "bf16" in res else "f32",
+        "dtype": ("f32; network bf16 weights x bf16 hi+lo activations, fp32 accumulate; compositing-backward "
+                  "channel products bf16x3 split, fp32 accumulate") if "bf16" in res else "f32",
         "data": "synthetic",
         "config": {"workload": "300k-800sq-ggx-mlp-fwdbwd", "gaussians": head["n"], "width": 800, "height": 800,
                    "features": 16, "gbuffer_channels": head["C"], "mlp": "58(64)->64x3->6",
                    "mlp_precision": "bf16" if "bf16" in res else "fp32", "tile_instances": head["M"]},
         "roofline": dominant,
+        "step_stats": _stats(head["per_step"]),
         "stages_ms": {k: round(v[0], 4) for k, v in head["stages"].items() if v[1] > 0},
     }
     if "fp32" in res and "bf16" in res:
@@ -400,6 +582,12 @@ def main():
     line["image_based_lighting"] = head["ibl"]
     line["per_gaussian_network"] = head["gnet"]
     line["ray_traced_visibility"] = head["vis"]
+    cc = copy_ceiling()
+    line["hbm_copy_ceiling"] = cc
+    if dominant and dominant["unit"] == "GB/s":
+        dominant["frac_of_copy_ceiling"] = round(dominant["achieved"] / cc["gbs"], 4)
+    if not a.no_other_workloads:
+        line["other_workloads"] = time_other_workloads(a.steps, a.warmup)
     if a.calib_copy_mib > 0:
         import torch
         src = torch.ones(a.calib_copy_mib << 18, device="cuda")
