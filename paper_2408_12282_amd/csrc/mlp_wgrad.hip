@@ -381,14 +381,17 @@ void launch_mlp_wgrad(const void *wops, const void *tops, const float *params, c
 // pixels along K: BF16 as 8 consecutive pixels per lane (16 B), FP32 as a
 // float4 of 4 pixels that serves 4 k-steps (the pixel order inside a sum is
 // free, so k-step t takes pixel 4 g + t of the 16).  The four waves tile the
-// layer's 16 x 16 blocks (WO x WI waves over output x input blocks; the bias
-// is one more input block whose B operand is a column of ones).
-constexpr int kGemmSplit = 4096;  // pixels per workgroup
+// layer's 16 x 16 blocks (WO x WI waves over output x input blocks); the bias
+// sums are added on the vector ALUs from the dY operands the waves with
+// wi = 0 already hold.  1024 pixels per workgroup give a few hundred
+// workgroups per layer at 800x800 (one per CU would leave most of the chip
+// idle).
+constexpr int kGemmSplit = 1024;  // pixels per workgroup
 
 template <class M, int R16, int K16>
 struct GemmShape {
   static constexpr int WO = R16 < 4 ? R16 : 4, WI = 4 / WO;
-  static constexpr int NOB = (R16 + WO - 1) / WO, NIB = (K16 + 1 + WI - 1) / WI;
+  static constexpr int NOB = (R16 + WO - 1) / WO, NIB = (K16 + WI - 1) / WI;
   static constexpr int KC = M::KPL == 8 ? 32 : 16;  // pixels per step
 };
 
@@ -408,10 +411,13 @@ __global__ __launch_bounds__(256) void wgrad_gemm_kernel(const typename M::Elem 
   const int woff = woff0 + blockIdx.y * param_step, boff = woff + rows * cols;
   const size_t pa = (size_t)blockIdx.x * kGemmSplit, pb = pa + kGemmSplit < P ? pa + kGemmSplit : P;
   f32x4 acc[GS::NOB][GS::NIB];
+  float bsum[GS::NOB];
 #pragma unroll
-  for (int a = 0; a < GS::NOB; a++)
+  for (int a = 0; a < GS::NOB; a++) {
+    bsum[a] = 0.f;
 #pragma unroll
     for (int b = 0; b < GS::NIB; b++) acc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
+  }
   for (size_t p = pa; p < pb; p += GS::KC) {
     if constexpr (M::KPL == 8) {
       Op A[GS::NOB], B[GS::NIB];
@@ -419,22 +425,19 @@ __global__ __launch_bounds__(256) void wgrad_gemm_kernel(const typename M::Elem 
       for (int a = 0; a < GS::NOB; a++) {
         const int r = 16 * (wo + GS::WO * a) + col;
         A[a] = r < rows_alloc ? *reinterpret_cast<const bf16x8 *>(dy + (size_t)r * P + p + 8 * g) : Op{};
+#pragma unroll
+        for (int j = 0; j < 8; j++) bsum[a] += (float)A[a][j];
       }
 #pragma unroll
       for (int b = 0; b < GS::NIB; b++) {
         const int ib = wi + GS::WI * b;
-        if (ib < K16) {
-          B[b] = *reinterpret_cast<const bf16x8 *>(x + (size_t)(16 * ib + col) * P + p + 8 * g);
-        } else {
-#pragma unroll
-          for (int j = 0; j < 8; j++) B[b][j] = (__bf16)(col == 0 ? 1.f : 0.f);
-        }
+        if (ib < K16) B[b] = *reinterpret_cast<const bf16x8 *>(x + (size_t)(16 * ib + col) * P + p + 8 * g);
       }
 #pragma unroll
       for (int a = 0; a < GS::NOB; a++)
 #pragma unroll
         for (int b = 0; b < GS::NIB; b++)
-          if (wo + GS::WO * a < R16 && wi + GS::WI * b <= K16) acc[a][b] = M::mma(A[a], B[b], acc[a][b]);
+          if (wo + GS::WO * a < R16 && wi + GS::WI * b < K16) acc[a][b] = M::mma(A[a], B[b], acc[a][b]);
     } else {
       float4 A[GS::NOB], B[GS::NIB];
 #pragma unroll
@@ -442,19 +445,18 @@ __global__ __launch_bounds__(256) void wgrad_gemm_kernel(const typename M::Elem 
         const int r = 16 * (wo + GS::WO * a) + col;
         A[a] = r < rows_alloc ? *reinterpret_cast<const float4 *>(dy + (size_t)r * P + p + 4 * g)
                               : make_float4(0.f, 0.f, 0.f, 0.f);
+        bsum[a] += (A[a].x + A[a].y) + (A[a].z + A[a].w);
       }
 #pragma unroll
       for (int b = 0; b < GS::NIB; b++) {
         const int ib = wi + GS::WI * b;
-        const float one = col == 0 ? 1.f : 0.f;
-        B[b] = ib < K16 ? *reinterpret_cast<const float4 *>(x + (size_t)(16 * ib + col) * P + p + 4 * g)
-                        : make_float4(one, one, one, one);
+        if (ib < K16) B[b] = *reinterpret_cast<const float4 *>(x + (size_t)(16 * ib + col) * P + p + 4 * g);
       }
 #pragma unroll
       for (int a = 0; a < GS::NOB; a++)
 #pragma unroll
         for (int b = 0; b < GS::NIB; b++)
-          if (wo + GS::WO * a < R16 && wi + GS::WI * b <= K16) {
+          if (wo + GS::WO * a < R16 && wi + GS::WI * b < K16) {
             acc[a][b] = M::mma(A[a].x, B[b].x, acc[a][b]);
             acc[a][b] = M::mma(A[a].y, B[b].y, acc[a][b]);
             acc[a][b] = M::mma(A[a].z, B[b].z, acc[a][b]);
@@ -469,19 +471,25 @@ __global__ __launch_bounds__(256) void wgrad_gemm_kernel(const typename M::Elem 
 #pragma unroll
     for (int b = 0; b < GS::NIB; b++) {
       const int ob = wo + GS::WO * a, ib = wi + GS::WI * b;
-      if (ob >= R16 || ib > K16) continue;
+      if (ob >= R16 || ib >= K16) continue;
 #pragma unroll
       for (int j = 0; j < 4; j++) {
-        const int o = 16 * ob + 4 * g + j;
-        if (o >= rows) continue;
-        if (ib < K16) {
-          const int i = 16 * ib + col;
-          if (i < cols) part[woff + o * cols + i] = acc[a][b][j];
-        } else if (col == 0) {
-          part[boff + o] = acc[a][b][j];
-        }
+        const int o = 16 * ob + 4 * g + j, i = 16 * ib + col;
+        if (o < rows && i < cols) part[woff + o * cols + i] = acc[a][b][j];
       }
     }
+  // bias: lane (col, g) summed row 16 ob + col over its pixel group g; add
+  // the four groups (lanes col, col + 16, col + 32, col + 48) in a fixed order
+  if (wi == 0) {
+#pragma unroll
+    for (int a = 0; a < GS::NOB; a++) {
+      const float s1 = __shfl_xor(bsum[a], 16, 64);
+      const float s12 = bsum[a] + s1;
+      const float tot = s12 + __shfl_xor(s12, 32, 64);
+      const int ob = wo + GS::WO * a, o = 16 * ob + col;
+      if (g == 0 && ob < R16 && o < rows) part[boff + o] = tot;
+    }
+  }
 }
 
 template <class M, int R16, int K16>

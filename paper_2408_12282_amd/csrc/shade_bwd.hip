@@ -177,6 +177,23 @@ __device__ __forceinline__ void load_pixel(const ShadeArgs &A, bool inside, size
   }
 }
 
+// Only what Eq. 7's backward needs (geometry and material channels, T, the
+// upstream gradient): the feature planes are not read.
+template <int C>
+__device__ __forceinline__ void load_pixel_geo(const ShadeArgs &A, bool inside, size_t pix, size_t HW, float *gb,
+                                               float &T, float *gL) {
+  T = 1.f;
+  for (int c = 0; c < 3; c++) gL[c] = 0.f;
+#pragma unroll
+  for (int c = 0; c < C; c++) gb[c] = 0.f;
+  if (inside) {
+#pragma unroll
+    for (int c = 0; c < kChFeat; c++) gb[c] = A.gbuf[c * HW + pix];
+    T = A.t_final[pix];
+    for (int c = 0; c < 3; c++) gL[c] = A.drgb[c * HW + pix];
+  }
+}
+
 template <int C, int F>
 __device__ __forceinline__ void write_pixel_grads(const ShadeArgs &A, bool inside, size_t pix, size_t HW,
                                                   const PixShade &S, const float *gb, float *dgbar, float dA) {
@@ -317,7 +334,7 @@ __global__ __launch_bounds__(64, 2) void shade_bwd_split_kernel(ShadeArgs A, __b
   // ---- C: Eq. 7 and the gradients of the network outputs
   {
     float gb[C], T, gL[3];
-    load_pixel<C>(A, inside, pix, HW, gb, T, gL);
+    load_pixel_geo<C>(A, inside, pix, HW, gb, T, gL);
     PixShade S;
     shade_geometry<C>(gb, T, uc, vc, A.cam, A.light, true, S);
     if (S.bg) gL[0] = gL[1] = gL[2] = 0.f;
@@ -572,7 +589,7 @@ __global__ __launch_bounds__(64, WIDTH == 64 ? 2 : 1) void shade_bwd_net_kernel(
   // ---- C: Eq. 7 and the gradients of the network outputs
   {
     float gb[C], T, gL[3];
-    load_pixel<C>(A, inside, pix, HW, gb, T, gL);
+    load_pixel_geo<C>(A, inside, pix, HW, gb, T, gL);
     PixShade S;
     shade_geometry<C>(gb, T, uc, vc, A.cam, A.light, true, S);
     if (S.bg) gL[0] = gL[1] = gL[2] = 0.f;
