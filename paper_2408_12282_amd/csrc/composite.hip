@@ -142,24 +142,31 @@ typedef __attribute__((__vector_size__(4 * sizeof(float)))) float cf32x4;
 // The moment sums stay in FP32 (v_mfma_f32_16x16x4_f32): the geometry
 // gradients recombine them as u^2 sum g - 2 u sum g x + sum g x^2, which
 // cancels and would magnify a 2^-16 error.
-// The batch's records are staged in LDS (double-buffered; the next batch is
-// fetched into registers while the current one is walked), and each wave
-// skips the Gaussians whose alpha box misses its strip.
+// The batch is staged in LDS (double-buffered; the next batch is fetched
+// into registers while the current one is walked): the record headers, and
+// the channels already split into BF16 high and low parts in the lane order
+// of the products' A operand, so that each wave reads its operand with two
+// 16-byte loads per lane at consecutive addresses.  Each wave skips the
+// Gaussians whose alpha box misses its strip.
 typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 cbf16x8;
 
-// Eight floats as BF16 high parts (truncation) and low parts (RNE of the remainder).
+// Two floats as BF16 high parts (truncation) and low parts (RNE of the
+// remainder), each pair packed in one dword with the first float low.
+__device__ __forceinline__ void split_bf16x2(float x, float y, uint32_t &h, uint32_t &l) {
+  const uint32_t a = __float_as_uint(x), b = __float_as_uint(y);
+  h = __builtin_amdgcn_perm(b, a, 0x07060302u);  // upper halves: a in the low, b in the high half
+  const float ra = x - __uint_as_float(a & 0xffff0000u);
+  const float rb = y - __uint_as_float(b & 0xffff0000u);
+  typedef float f2 __attribute__((ext_vector_type(2)));
+  typedef __bf16 b2 __attribute__((ext_vector_type(2)));
+  l = __builtin_bit_cast(uint32_t, __builtin_convertvector((f2){ra, rb}, b2));
+}
+
+// Eight floats as BF16 high and low parts.
 __device__ __forceinline__ void split_bf16x8(const float (&v)[8], cbf16x8 &hi, cbf16x8 &lo) {
   uint32_t h[4], l[4];
 #pragma unroll
-  for (int k = 0; k < 4; k++) {
-    const uint32_t a = __float_as_uint(v[2 * k]), b = __float_as_uint(v[2 * k + 1]);
-    h[k] = __builtin_amdgcn_perm(b, a, 0x07060302u);  // upper halves: a in the low, b in the high half
-    const float ra = v[2 * k] - __uint_as_float(a & 0xffff0000u);
-    const float rb = v[2 * k + 1] - __uint_as_float(b & 0xffff0000u);
-    typedef float f2 __attribute__((ext_vector_type(2)));
-    typedef __bf16 b2 __attribute__((ext_vector_type(2)));
-    l[k] = __builtin_bit_cast(uint32_t, __builtin_convertvector((f2){ra, rb}, b2));
-  }
+  for (int k = 0; k < 4; k++) split_bf16x2(v[2 * k], v[2 * k + 1], h[k], l[k]);
   hi = __builtin_bit_cast(cbf16x8, make_uint4(h[0], h[1], h[2], h[3]));
   lo = __builtin_bit_cast(cbf16x8, make_uint4(l[0], l[1], l[2], l[3]));
 }
@@ -181,20 +188,20 @@ __global__ __launch_bounds__(256, C > 26 ? 2 : 3) void composite_bwd_kernel(
     const uint32_t *__restrict__ n_contrib, const float *__restrict__ dG, const float *__restrict__ dT,
     float *__restrict__ gacc, DetSlots det, const uint32_t *__restrict__ order) {
   constexpr int RS = rec_stride(C);
-  constexpr int R4 = RS / 4;              // float4 per record
   constexpr int GS = grad_stride(C);
   constexpr int CP = (C + 15) / 16 * 16;  // channels padded to 16-column blocks
   constexpr int NBC = CP / 16;
   constexpr int RW = CP + 16;             // columns of the per-wave partial sums: channels | moments
   constexpr int KC = (C + 31) / 32;       // 32-channel k-steps of the per-pair dot products
   static_assert(RW <= 64, "per-wave partial sums must fit the wave's 64 columns");
-  static_assert(kBJ * R4 <= 256, "one thread per record chunk");
+  static_assert(kBJ == 16 && KC <= 2 && C % 2 == 0, "batch fetch roles below");
   // [j][pixel]: weights (rows 0..kBJ-1) and dL/dpower (rows kBJ..2kBJ-1).  A
   // wave only touches its own 64 pixel columns, so once its reductions are
   // done it stores its partial sums [j][channels | moments] over its own
   // columns of the weight rows.
   __shared__ float mat[2 * kBJ * kMS];
-  __shared__ float4 recs[2][kBJ * R4];
+  __shared__ float4 hdr[2][2 * kBJ];         // u v a b | c opacity . . of each Gaussian
+  __shared__ cbf16x8 aop[2][KC][2][64];      // channel A operands: [k-step][high, low][lane]
   __shared__ uint32_t gidx[2][kBJ];
   __shared__ uint2 bbox[2][kBJ];
   __shared__ uint32_t maxlast;
@@ -275,25 +282,75 @@ __global__ __launch_bounds__(256, C > 26 ? 2 : 3) void composite_bwd_kernel(
   const float mb1 = col == 1 ? 1.f : col == 4 ? yb : 0.f;
   const float mb2 = col == 3 ? 1.f : 0.f;
   const int top = (int)maxlast;
-  // Batch fetch into registers: thread t < kBJ * R4 holds chunk t % R4 of
-  // record t / R4 and, for chunk 0, the Gaussian's index and box.
-  const int fj = t / R4, fq = t % R4;
-  float4 f_rec = make_float4(0.f, 0.f, 0.f, 0.f);
+  // Batch fetch into registers, one role per thread.  Threads 0..127 hold
+  // half h = t / 64 of the A operand of lane l = t % 64 in every k-step ks:
+  // channels 32 ks + 8 g + 4 h + i (i = 0..3) of Gaussian col, read straight
+  // from its record; threads 128..159 one 16-byte header chunk each;
+  // threads 160..175 the Gaussian's index and alpha box.
+  const int fl = t & 63, fh = (t >> 6) & 1;
+  const bool rA = t < 128, rH = t >= 128 && t < 160, rI = t >= 160 && t < 176;
+  const int f_j = rA ? (fl & 15) : rH ? (t - 128) >> 1 : t - 160;  // Gaussian of the batch
+  const int f_off = rA ? 6 + 8 * (fl >> 4) + 4 * fh : 4 * (t & 1);  // first float in its record
+  float f_v[4 * KC];
+#pragma unroll
+  for (int i = 0; i < 4 * KC; i++) f_v[i] = 0.f;
   uint32_t f_g = 0;
   uint2 f_box = make_uint2(0u, 0u);
   auto fetch = [&](int lo_, int cnt_) {
-    if (t < kBJ * R4 && fj < cnt_) {
-      f_g = sorted_g[rg.x + lo_ + fj];
-      f_rec = ld4(records + (size_t)f_g * RS + 4 * fq);
-      if (fq == 0) f_box = bxs[f_g];
+    if ((rA || rH || rI) && f_j < cnt_) {
+      const uint32_t gg = sorted_g[rg.x + lo_ + f_j];
+      const float *src = records + (size_t)gg * RS + f_off;
+      if (rA) {
+        // two 8-byte-aligned float2 per k-step; a pair is loaded whenever its
+        // first channel is below C (C even), so every channel used is loaded
+#pragma unroll
+        for (int ks = 0; ks < KC; ks++) {
+          const int c0 = f_off - 6 + 32 * ks;
+          if (c0 < C) {
+            const float2 v = *reinterpret_cast<const float2 *>(src + 32 * ks);
+            f_v[4 * ks] = v.x;
+            f_v[4 * ks + 1] = v.y;
+          }
+          if (c0 + 2 < C) {
+            const float2 v = *reinterpret_cast<const float2 *>(src + 32 * ks + 2);
+            f_v[4 * ks + 2] = v.x;
+            f_v[4 * ks + 3] = v.y;
+          }
+        }
+      } else if (rH) {
+        const float4 v = ld4(src);
+        f_v[0] = v.x;
+        f_v[1] = v.y;
+        f_v[2] = v.z;
+        f_v[3] = v.w;
+      } else {
+        f_g = gg;
+        f_box = bxs[gg];
+      }
     }
   };
   auto stage = [&](int buf, int cnt_) {
-    if (t < kBJ * R4 && fj < cnt_) {
-      recs[buf][t] = f_rec;
-      if (fq == 0) {
-        gidx[buf][fj] = f_g;
-        bbox[buf][fj] = f_box;
+    const bool ok = f_j < cnt_;
+    if (rA) {
+      // channels past C and Gaussians past the batch are zero
+#pragma unroll
+      for (int ks = 0; ks < KC; ks++) {
+        const int c0 = f_off - 6 + 32 * ks;
+        float v[4];
+#pragma unroll
+        for (int i = 0; i < 4; i++) v[i] = ok && c0 + i < C ? f_v[4 * ks + i] : 0.f;
+        uint2 hi, lo;
+        split_bf16x2(v[0], v[1], hi.x, lo.x);
+        split_bf16x2(v[2], v[3], hi.y, lo.y);
+        reinterpret_cast<uint2 *>(&aop[buf][ks][0][fl])[fh] = hi;
+        reinterpret_cast<uint2 *>(&aop[buf][ks][1][fl])[fh] = lo;
+      }
+    } else if (rH) {
+      if (ok) hdr[buf][t - 128] = make_float4(f_v[0], f_v[1], f_v[2], f_v[3]);
+    } else if (rI) {
+      if (ok) {
+        gidx[buf][f_j] = f_g;
+        bbox[buf][f_j] = f_box;
       }
     }
   };
@@ -318,17 +375,11 @@ __global__ __launch_bounds__(256, C > 26 ? 2 : 3) void composite_bwd_kernel(
     // (three-term BF16 split), into this wave's columns of rows kBJ.. (each
     // lane reads its own eg[j] there before the walk overwrites it with g)
     {
-      const float *rc = reinterpret_cast<const float *>(&recs[buf][col * R4]);
       cbf16x8 ah[KC], al[KC];
 #pragma unroll
       for (int ks = 0; ks < KC; ks++) {
-        float a[8];
-#pragma unroll
-        for (int i = 0; i < 8; i++) {
-          const int c = 32 * ks + 8 * g + i;
-          a[i] = (c < C && col < cnt) ? rc[6 + (c < C ? c : 0)] : 0.f;
-        }
-        split_bf16x8(a, ah[ks], al[ks]);
+        ah[ks] = aop[buf][ks][0][lane];
+        al[ks] = aop[buf][ks][1][lane];
       }
 #pragma unroll
       for (int nb = 0; nb < 4; nb++) {
@@ -346,7 +397,7 @@ __global__ __launch_bounds__(256, C > 26 ? 2 : 3) void composite_bwd_kernel(
     for (int jj = kBJ - 1; jj >= 0; jj--) {
       float wvj = 0.f, pvj = 0.f;
       if (((hm >> jj) & 1u) && __ballot((uint32_t)(lo + jj) < last) != 0 && (uint32_t)(lo + jj) < last) {
-        const float *r = reinterpret_cast<const float *>(&recs[buf][jj * R4]);
+        const float *r = reinterpret_cast<const float *>(&hdr[buf][2 * jj]);
         float dx, dy;
         const float pw = splat_power(r[0], r[1], r[2], r[3], r[4], pxc, pyc, dx, dy);
         if (pw <= 0.f) {
@@ -448,7 +499,7 @@ __global__ __launch_bounds__(256, C > 26 ? 2 : 3) void composite_bwd_kernel(
       for (int n = 0; n < 6; n++)
         mo[n] = (mat[t * kMS + 0 * 64 + CP + n] + mat[t * kMS + 1 * 64 + CP + n]) +
                 (mat[t * kMS + 2 * 64 + CP + n] + mat[t * kMS + 3 * 64 + CP + n]);
-      const float *r = reinterpret_cast<const float *>(&recs[buf][t * R4]);
+      const float *r = reinterpret_cast<const float *>(&hdr[buf][2 * t]);
       const float up = r[0] - (float)(tx * kTile), vp = r[1] - (float)(ty * kTile);
       const float mx = up * mo[0] - mo[1], my = vp * mo[0] - mo[2];
       const float mxx = up * up * mo[0] - 2.f * up * mo[1] + mo[3];
@@ -472,7 +523,7 @@ __global__ __launch_bounds__(256, C > 26 ? 2 : 3) void composite_bwd_kernel(
         mo[n] = (mat[t * kMS + 0 * 64 + CP + n] + mat[t * kMS + 1 * 64 + CP + n]) +
                 (mat[t * kMS + 2 * 64 + CP + n] + mat[t * kMS + 3 * 64 + CP + n]);
       if (mo[0] != 0.f || mo[1] != 0.f || mo[2] != 0.f) {
-        const float *r = reinterpret_cast<const float *>(&recs[buf][t * R4]);
+        const float *r = reinterpret_cast<const float *>(&hdr[buf][2 * t]);
         const float up = r[0] - (float)(tx * kTile), vp = r[1] - (float)(ty * kTile);
         // sums of g dx, g dy, g dx^2, g dx dy, g dy^2 with dx = u - x, dy = v - y
         const float mx = up * mo[0] - mo[1], my = vp * mo[0] - mo[2];
