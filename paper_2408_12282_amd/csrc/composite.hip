@@ -282,6 +282,10 @@ __global__ __launch_bounds__(256, C > 26 ? 2 : 3) void composite_bwd_kernel(
   const float mb1 = col == 1 ? 1.f : col == 4 ? yb : 0.f;
   const float mb2 = col == 3 ? 1.f : 0.f;
   const int top = (int)maxlast;
+  uint32_t wlast = last;  // the wave's largest last contributor
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) wlast = max(wlast, (uint32_t)__shfl_xor((int)wlast, o, 64));
+  wlast = __builtin_amdgcn_readfirstlane(wlast);
   // Batch fetch into registers, one role per thread.  Threads 0..127 hold
   // half h = t / 64 of the A operand of lane l = t % 64 in every k-step ks:
   // channels 32 ks + 8 g + 4 h + i (i = 0..3) of Gaussian col, read straight
@@ -392,33 +396,51 @@ __global__ __launch_bounds__(256, C > 26 ? 2 : 3) void composite_bwd_kernel(
       __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
       __builtin_amdgcn_wave_barrier();
     }
-    // ---- per pixel, last to first; each result goes straight to LDS
+    // ---- per pixel, last to first over the Gaussians whose box reaches this
+    // strip and whose index is below some pixel's last contributor; each
+    // result goes straight to LDS and the rows of the others are zero.  The
+    // next Gaussian's header and eg are read while the current one is
+    // evaluated, and a lane's tests are selects rather than branches, so that
+    // the walk is not a chain of LDS round trips.
+    uint32_t m = hm;
+    if ((uint32_t)hi > wlast) m &= wlast > (uint32_t)lo ? (1u << (wlast - (uint32_t)lo)) - 1u : 0u;
 #pragma unroll
-    for (int jj = kBJ - 1; jj >= 0; jj--) {
-      float wvj = 0.f, pvj = 0.f;
-      if (((hm >> jj) & 1u) && __ballot((uint32_t)(lo + jj) < last) != 0 && (uint32_t)(lo + jj) < last) {
-        const float *r = reinterpret_cast<const float *>(&hdr[buf][2 * jj]);
-        float dx, dy;
-        const float pw = splat_power(r[0], r[1], r[2], r[3], r[4], pxc, pyc, dx, dy);
-        if (pw <= 0.f) {
-          const float ex = fast_exp(pw);
-          const float araw = __fmul_rn(r[5], ex);
-          const float al = fminf(0.99f, araw);
-          if (al >= (1.f / 255.f)) {
-            const float inv = __builtin_amdgcn_rcpf(1.f - al);
-            const float Tb = Tcur * inv;
-            const float wgt = al * Tb;
-            const float eg = mat[(kBJ + jj) * kMS + t];
-            const float dal = Tb * eg - (S + dTT) * inv;
-            S = __fmaf_rn(wgt, eg, S);
-            Tcur = Tb;
-            wvj = wgt;
-            if (araw < 0.99f) pvj = dal * al;
-          }
-        }
+    for (int jj = 0; jj < kBJ; jj++)
+      if (!((m >> jj) & 1u)) {
+        mat[jj * kMS + t] = 0.f;
+        mat[(kBJ + jj) * kMS + t] = 0.f;
       }
-      mat[jj * kMS + t] = wvj;
-      mat[(kBJ + jj) * kMS + t] = pvj;
+    if (m != 0u) {
+      const int n = __builtin_popcount(m);
+      int jj = 31 - __builtin_clz(m);
+      float4 ha = hdr[buf][2 * jj];
+      float2 hb = *reinterpret_cast<const float2 *>(&hdr[buf][2 * jj + 1]);  // c, opacity
+      float eg = mat[(kBJ + jj) * kMS + t];
+      for (int k = 0; k < n; k++) {
+        m &= ~(1u << jj);
+        const int jn = m != 0u ? 31 - __builtin_clz(m) : jj;
+        const float4 na = hdr[buf][2 * jn];
+        const float2 nb = *reinterpret_cast<const float2 *>(&hdr[buf][2 * jn + 1]);
+        const float neg = mat[(kBJ + jn) * kMS + t];
+        float dx, dy;
+        const float pw = splat_power(ha.x, ha.y, ha.z, ha.w, hb.x, pxc, pyc, dx, dy);
+        const float araw = __fmul_rn(hb.y, fast_exp(fminf(pw, 0.f)));
+        const float al = fminf(0.99f, araw);
+        const bool on = (uint32_t)(lo + jj) < last && pw <= 0.f && al >= (1.f / 255.f);
+        const float inv = __builtin_amdgcn_rcpf(1.f - al);
+        const float Tb = Tcur * inv;
+        const float wgt = al * Tb;
+        const float dal = Tb * eg - (S + dTT) * inv;
+        const float Sn = __fmaf_rn(wgt, eg, S);
+        S = on ? Sn : S;
+        Tcur = on ? Tb : Tcur;
+        mat[jj * kMS + t] = on ? wgt : 0.f;
+        mat[(kBJ + jj) * kMS + t] = on && araw < 0.99f ? dal * al : 0.f;
+        jj = jn;
+        ha = na;
+        hb = nb;
+        eg = neg;
+      }
     }
     // the reductions read only this wave's own columns: a wave-level fence
     // suffices, and a wave whose strip had few hits goes on to the matrix
