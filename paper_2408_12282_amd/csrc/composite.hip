@@ -23,19 +23,33 @@ __device__ __forceinline__ bool box_hits(uint2 bx, int sx, int sy) {
   return !(xlo > sx + kTile - 1 || xhi < sx || ylo > sy + 3 || yhi < sy);
 }
 
+typedef __attribute__((__vector_size__(4 * sizeof(float)))) float cf32x4;
+
+// Forward: each wave walks the hits of its strip in depth order and keeps,
+// per pixel, only the transmittance recursion (alpha, T, the stopping test);
+// the blend weights w = alpha T of up to kFG hits wait as rows [hit][pixel]
+// in LDS, and the channel sums G[c][p] += sum_k channel_k,c w_k,p are one
+// FP32 product per four hits on the matrix cores (v_mfma_f32_16x16x4_f32,
+// channels x pixels, K = hits), accumulated in registers for the tile.
+constexpr int kFG = 8;        // hits per flush of the weight rows (two k-steps)
+constexpr int kFWS = 64 + 16;  // row stride of the weight rows (conflict-free column reads)
+
 template <int C>
-__global__ __launch_bounds__(256, 6) void composite_fwd_kernel(const uint2 *__restrict__ ranges,
-                                                            const uint32_t *__restrict__ sorted_g,
-                                                            const float *__restrict__ records,
-                                                            const short4 *__restrict__ boxes, int W, int H,
-                                                            int TX, float *__restrict__ gbuf,
-                                                            float *__restrict__ t_final,
-                                                            uint32_t *__restrict__ n_contrib,
-                                                            uint32_t *__restrict__ tile_top) {
+__global__ __launch_bounds__(256, C > 32 ? 4 : 6) void composite_fwd_kernel(const uint2 *__restrict__ ranges,
+                                                                          const uint32_t *__restrict__ sorted_g,
+                                                                          const float *__restrict__ records,
+                                                                          const short4 *__restrict__ boxes, int W,
+                                                                          int H, int TX, float *__restrict__ gbuf,
+                                                                          float *__restrict__ t_final,
+                                                                          uint32_t *__restrict__ n_contrib,
+                                                                          uint32_t *__restrict__ tile_top) {
   constexpr int RS = rec_stride(C);
-  constexpr int NB = 128;  // records per batch (small LDS footprint: 6 waves per SIMD)
+  constexpr int NB = 128;             // records per batch
+  constexpr int CB = (C + 15) / 16;   // 16-channel row blocks of the sums
+  static_assert(NB <= 256 && kFG == 8, "record index in 8 bits, two k-steps per flush");
   __shared__ float4 batch[NB * RS / 4];
   __shared__ uint2 bbox[NB];
+  __shared__ float wrow[4][kFG * kFWS];
   __shared__ uint32_t tmax;
   const int t = threadIdx.x, lane = t & 63;
   const int w = __builtin_amdgcn_readfirstlane(t >> 6);
@@ -47,12 +61,43 @@ __global__ __launch_bounds__(256, 6) void composite_fwd_kernel(const uint2 *__re
   const float pxc = (float)px + 0.5f, pyc = (float)py + 0.5f;
   const uint2 rg = ranges[tile];
   const uint2 *bxs = reinterpret_cast<const uint2 *>(boxes);
+  const float *bf = reinterpret_cast<const float *>(batch);
+  float *wr = wrow[w];
   float T = 1.f;
-  float acc[C];
+  // D layout of the sums: acc[cb][nb] lane l holds channel 16 cb + 4 (l / 16) + i
+  // (i = 0..3) of pixel (l % 16, row nb) of the strip
+  cf32x4 acc[CB][4];
 #pragma unroll
-  for (int c = 0; c < C; c++) acc[c] = 0.f;
+  for (int cb = 0; cb < CB; cb++)
+#pragma unroll
+    for (int nb = 0; nb < 4; nb++) acc[cb][nb] = cf32x4{0.f, 0.f, 0.f, 0.f};
   uint32_t last = 0;
   bool done = !inside;
+  int nk = 0;          // hits waiting in the weight rows (wave-uniform)
+  uint64_t krec = 0;   // their records in the batch, 8 bits each
+  auto flush = [&]() {
+    // the last k-step's unused rows are zero (their channels are any staged record's)
+    for (int s = nk; s < ((nk + 3) & ~3); s++) wr[s * kFWS + lane] = 0.f;
+    for (int ks = 0; 4 * ks < nk; ks++) {
+      const int s = 4 * ks + (lane >> 4);
+      const int js = (int)((krec >> (8 * s)) & 0xffu);
+      float a[CB];
+#pragma unroll
+      for (int cb = 0; cb < CB; cb++) {
+        const int c = 16 * cb + (lane & 15);
+        a[cb] = c < C ? bf[js * RS + 6 + (c < C ? c : 0)] : 0.f;
+      }
+      float b[4];
+#pragma unroll
+      for (int nb = 0; nb < 4; nb++) b[nb] = wr[s * kFWS + 16 * nb + (lane & 15)];
+#pragma unroll
+      for (int cb = 0; cb < CB; cb++)
+#pragma unroll
+        for (int nb = 0; nb < 4; nb++) acc[cb][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[cb], b[nb], acc[cb][nb], 0, 0, 0);
+    }
+    nk = 0;
+    krec = 0;
+  };
   if (t == 0) tmax = 0;
   for (uint32_t b0 = rg.x; b0 < rg.y; b0 += NB) {
     if (__syncthreads_count(done) == 256) break;
@@ -70,48 +115,61 @@ __global__ __launch_bounds__(256, 6) void composite_fwd_kernel(const uint2 *__re
       bool h = false;
       if (j0 + lane < cnt) h = box_hits(bbox[j0 + lane], sx, sy);
       uint64_t m = __ballot(h);
-      if (m == 0 || __ballot(!done) == 0) continue;
-      int j = j0 + (int)__builtin_ctzll(m);
-      m &= m - 1;
-      float4 ha = batch[j * (RS / 4)], hb = batch[j * (RS / 4) + 1];  // u v a b | c opacity ..
-      while (true) {
-        // the next record's header is read while this one is evaluated (the
-        // walk is bound by the latency of these dependent LDS reads)
-        const bool more = m != 0;
-        const int jn = more ? j0 + (int)__builtin_ctzll(m) : j;
-        m &= m - 1;
-        const float4 na = batch[jn * (RS / 4)], nb = batch[jn * (RS / 4) + 1];
-        if (!done) {
+      // groups of up to kFG hits in depth order: the alphas of a group are
+      // independent of each other, only the transmittance recursion is serial
+      while (m != 0 && __ballot(!done) != 0) {
+        int js[kFG];
+        int nv = 0;
+#pragma unroll
+        for (int s = 0; s < kFG; s++) {
+          js[s] = m != 0 ? j0 + (int)__builtin_ctzll(m) : -1;
+          nv += m != 0 ? 1 : 0;
+          m &= m - 1;
+        }
+        krec = 0;
+#pragma unroll
+        for (int s = 0; s < kFG; s++) {
+          const int j = js[s] >= 0 ? js[s] : js[0];
+          krec |= (uint64_t)j << (8 * s);
+          const float4 ha = batch[j * (RS / 4)], hb = batch[j * (RS / 4) + 1];  // u v a b | c opacity ..
           float dx, dy;
           const float pw = splat_power(ha.x, ha.y, ha.z, ha.w, hb.x, pxc, pyc, dx, dy);
-          const float al = fminf(0.99f, splat_alpha_raw(hb.y, pw));
-          if (pw <= 0.f && al >= (1.f / 255.f)) {
-            const float tn = T * (1.f - al);
-            if (tn < 1e-4f) {
-              done = true;
-            } else {
-              const float *r = reinterpret_cast<const float *>(&batch[j * (RS / 4)]);
-              const float wgt = al * T;
-#pragma unroll
-              for (int c = 0; c < C; c++) acc[c] = __fmaf_rn(wgt, r[6 + c], acc[c]);
-              T = tn;
-              last = b0 - rg.x + j + 1;
-            }
-          }
+          const float al = fminf(0.99f, __fmul_rn(hb.y, fast_exp(fminf(pw, 0.f))));
+          const bool ok = js[s] >= 0 && !done && pw <= 0.f && al >= (1.f / 255.f);
+          const float tn = T * (1.f - al);
+          const bool keep = ok && !(tn < 1e-4f);
+          done = done || (ok && tn < 1e-4f);
+          wr[s * kFWS + lane] = keep ? al * T : 0.f;
+          T = keep ? tn : T;
+          last = keep ? b0 - rg.x + j + 1 : last;
         }
-        if (!more || __ballot(!done) == 0) break;
-        j = jn;
-        ha = na;
-        hb = nb;
+        nk = nv;
+        flush();
       }
     }
   }
   if (inside) {
-    const size_t pix = (size_t)py * W + px, HW = (size_t)W * H;
-#pragma unroll
-    for (int c = 0; c < C; c++) gbuf[c * HW + pix] = acc[c];
+    const size_t pix = (size_t)py * W + px;
     t_final[pix] = T;
     n_contrib[pix] = last;
+  }
+  {
+    const size_t HW = (size_t)W * H;
+    const int qx = sx + (lane & 15);
+#pragma unroll
+    for (int nb = 0; nb < 4; nb++) {
+      const int qy = sy + nb;
+      if (qx < W && qy < H) {
+        const size_t pix = (size_t)qy * W + qx;
+#pragma unroll
+        for (int cb = 0; cb < CB; cb++)
+#pragma unroll
+          for (int i = 0; i < 4; i++) {
+            const int c = 16 * cb + 4 * (lane >> 4) + i;
+            if (c < C) gbuf[c * HW + pix] = acc[cb][nb][i];
+          }
+      }
+    }
   }
   // the tile's largest last-contributor index: the backward's work per tile
   __syncthreads();
@@ -121,8 +179,6 @@ __global__ __launch_bounds__(256, 6) void composite_fwd_kernel(const uint2 *__re
 }
 
 // ---------------------------------------------------------------- backward
-
-typedef __attribute__((__vector_size__(4 * sizeof(float)))) float cf32x4;
 
 // Backward of the compositing, one workgroup per tile.  Each pixel walks its
 // list from the last contributor down in batches of kBJ Gaussians, recovering
@@ -169,6 +225,29 @@ __device__ __forceinline__ void split_bf16x8(const float (&v)[8], cbf16x8 &hi, c
   for (int k = 0; k < 4; k++) split_bf16x2(v[2 * k], v[2 * k + 1], h[k], l[k]);
   hi = __builtin_bit_cast(cbf16x8, make_uint4(h[0], h[1], h[2], h[3]));
   lo = __builtin_bit_cast(cbf16x8, make_uint4(l[0], l[1], l[2], l[3]));
+}
+
+// Eight floats as three BF16 parts each, x = p1 + p2 + p3 exactly: p1 and p2
+// are the top 8 significant bits of x and of the remainder (truncation), p3
+// the last 8 (exact).
+__device__ __forceinline__ void split3_bf16x8(const float (&v)[8], cbf16x8 &p1, cbf16x8 &p2, cbf16x8 &p3) {
+  uint32_t a[4], b[4], c[4];
+#pragma unroll
+  for (int k = 0; k < 4; k++) {
+    const float x = v[2 * k], y = v[2 * k + 1];
+    a[k] = __builtin_amdgcn_perm(__float_as_uint(y), __float_as_uint(x), 0x07060302u);
+    const float rx = x - __uint_as_float(__float_as_uint(x) & 0xffff0000u);
+    const float ry = y - __uint_as_float(__float_as_uint(y) & 0xffff0000u);
+    b[k] = __builtin_amdgcn_perm(__float_as_uint(ry), __float_as_uint(rx), 0x07060302u);
+    const float sx = rx - __uint_as_float(__float_as_uint(rx) & 0xffff0000u);
+    const float sy = ry - __uint_as_float(__float_as_uint(ry) & 0xffff0000u);
+    typedef float f2 __attribute__((ext_vector_type(2)));
+    typedef __bf16 b2 __attribute__((ext_vector_type(2)));
+    c[k] = __builtin_bit_cast(uint32_t, __builtin_convertvector((f2){sx, sy}, b2));
+  }
+  p1 = __builtin_bit_cast(cbf16x8, make_uint4(a[0], a[1], a[2], a[3]));
+  p2 = __builtin_bit_cast(cbf16x8, make_uint4(b[0], b[1], b[2], b[3]));
+  p3 = __builtin_bit_cast(cbf16x8, make_uint4(c[0], c[1], c[2], c[3]));
 }
 
 __device__ __forceinline__ cf32x4 mma3(const cbf16x8 &ah, const cbf16x8 &al, const cbf16x8 &bh, const cbf16x8 &bl,
@@ -273,11 +352,13 @@ __global__ __launch_bounds__(256, C > 26 ? 2 : 3) void composite_bwd_kernel(
         for (int i = 0; i < 8; i++) ev[ks][nb][i] = 0.f;
       split_bf16x8(ev[ks][nb], eh[ks][nb], el[ks][nb]);
     }
-  // moment basis of pixel 64 w + 16 g + ks (FP32 B operand; K step ks takes
-  // one pixel from each lane group, so a lane's 16 pixels are contiguous):
-  // x = ks + 1/2 and y = 4 w + g + 1/2, so column col of the basis
-  // (1, x, y, x^2, xy, y^2) is mb0 + mb1 x + mb2 x^2 with per-lane constants
-  const float yb = (float)(4 * w + g) + 0.5f;
+  // moment basis of pixel 16 g + 8 kk + i of the wave (B operand of k-step
+  // kk, element i; a lane's 16 pixels are a row of the strip): offsets from
+  // the tile centre x = 8 kk + i - 15/2 and y = 4 w + g - 15/2, so column col
+  // of the basis (1, x, y, x^2, xy, y^2) is mb0 + mb1 x + mb2 x^2 with
+  // per-lane constants.  Every value is a multiple of 1/4 below 57 in
+  // magnitude with at most 8 significant bits: exact in BF16.
+  const float yb = (float)(4 * w + g) - 7.5f;
   const float mb0 = col == 0 ? 1.f : col == 2 ? yb : col == 5 ? yb * yb : 0.f;
   const float mb1 = col == 1 ? 1.f : col == 4 ? yb : 0.f;
   const float mb2 = col == 3 ? 1.f : 0.f;
@@ -300,9 +381,15 @@ __global__ __launch_bounds__(256, C > 26 ? 2 : 3) void composite_bwd_kernel(
   for (int i = 0; i < 4 * KC; i++) f_v[i] = 0.f;
   uint32_t f_g = 0;
   uint2 f_box = make_uint2(0u, 0u);
-  auto fetch = [&](int lo_, int cnt_) {
+  // The Gaussian index a fetch uses was read one batch earlier, so that the
+  // record loads do not wait on the index load.
+  uint32_t f_gn = 0;
+  auto load_index = [&](int lo_, int cnt_) {
+    if ((rA || rH || rI) && f_j < cnt_) f_gn = sorted_g[rg.x + lo_ + f_j];
+  };
+  auto fetch = [&](int cnt_) {
     if ((rA || rH || rI) && f_j < cnt_) {
-      const uint32_t gg = sorted_g[rg.x + lo_ + f_j];
+      const uint32_t gg = f_gn;
       const float *src = records + (size_t)gg * RS + f_off;
       if (rA) {
         // two 8-byte-aligned float2 per k-step; a pair is loaded whenever its
@@ -359,9 +446,11 @@ __global__ __launch_bounds__(256, C > 26 ? 2 : 3) void composite_bwd_kernel(
     }
   };
   if (top > 0) {
-    const int lo0 = top > kBJ ? top - kBJ : 0;
-    fetch(lo0, top - lo0);
+    const int lo0 = top > kBJ ? top - kBJ : 0, lo1 = lo0 > kBJ ? lo0 - kBJ : 0;
+    load_index(lo0, top - lo0);
+    fetch(top - lo0);
     stage(0, top - lo0);
+    if (lo0 > 0) load_index(lo1, lo0 - lo1);
   }
   __syncthreads();
   const float dTT = dTfin * Tfin;
@@ -370,7 +459,9 @@ __global__ __launch_bounds__(256, C > 26 ? 2 : 3) void composite_bwd_kernel(
   for (int hi = top; hi > 0; hi -= kBJ, buf ^= 1) {
     const int lo = hi > kBJ ? hi - kBJ : 0, cnt = hi - lo;
     const int nlo = lo > kBJ ? lo - kBJ : 0, ncnt = lo - nlo;
-    if (ncnt > 0) fetch(nlo, ncnt);  // next batch, in flight during this one
+    const int nnlo = nlo > kBJ ? nlo - kBJ : 0, nncnt = nlo - nnlo;
+    if (ncnt > 0) fetch(ncnt);  // next batch, in flight during this one
+    if (nncnt > 0) load_index(nnlo, nncnt);  // and the indices of the one after
     // Gaussians of the batch that can reach this wave's strip
     bool h = false;
     if (lane < cnt) h = box_hits(bbox[buf][lane], sx, sy);
@@ -449,7 +540,7 @@ __global__ __launch_bounds__(256, C > 26 ? 2 : 3) void composite_bwd_kernel(
     __builtin_amdgcn_wave_barrier();
     // ---- reductions over this wave's 64 pixels (two steps of 32):
     //   [j][c]  = sum_p w[j][p] dG[p][c]
-    //   [j][n]  = sum_p g[j][p] basis_n(p),  basis = (1, x, y, x^2, xy, y^2) from the tile corner
+    //   [j][n]  = sum_p g[j][p] basis_n(p),  basis = (1, x, y, x^2, xy, y^2) from the tile centre
     {
       cf32x4 acc[NBC + 1];
 #pragma unroll
@@ -476,15 +567,30 @@ __global__ __launch_bounds__(256, C > 26 ? 2 : 3) void composite_bwd_kernel(
 #pragma unroll
         for (int nc = 0; nc < NBC; nc++) acc[nc] = mma3(wh, wl, bh[kk][nc], bl[kk][nc], acc[nc]);
       }
-      // moments: even and odd k-steps in separate accumulators (shorter dependent chains)
-      cf32x4 am = cf32x4{0.f, 0.f, 0.f, 0.f};
+      // moments: g split exactly into three BF16 parts against the exact BF16
+      // basis, so every product is exact and only the FP32 accumulation
+      // rounds, as with FP32 operands, on v_mfma_f32_16x16x32_bf16 (a
+      // third of the matrix-core time); the parts in separate accumulators
+      cf32x4 am2 = cf32x4{0.f, 0.f, 0.f, 0.f}, am3 = cf32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-      for (int ks = 0; ks < 16; ks += 2) {
-        const float x0 = (float)ks + 0.5f, x1 = x0 + 1.f;
-        acc[NBC] = __builtin_amdgcn_mfma_f32_16x16x4f32(gv[ks], mb0 + x0 * (mb1 + x0 * mb2), acc[NBC], 0, 0, 0);
-        am = __builtin_amdgcn_mfma_f32_16x16x4f32(gv[ks + 1], mb0 + x1 * (mb1 + x1 * mb2), am, 0, 0, 0);
+      for (int kk = 0; kk < 2; kk++) {
+        float gk[8], bk[8];
+#pragma unroll
+        for (int i = 0; i < 8; i++) {
+          gk[i] = gv[8 * kk + i];
+          const float x = (float)(8 * kk + i) - 7.5f;
+          bk[i] = mb0 + x * (mb1 + x * mb2);
+        }
+        cbf16x8 g1, g2, g3;
+        split3_bf16x8(gk, g1, g2, g3);
+        typedef float f8 __attribute__((ext_vector_type(8)));
+        const cbf16x8 bb = __builtin_convertvector(
+            (f8){bk[0], bk[1], bk[2], bk[3], bk[4], bk[5], bk[6], bk[7]}, cbf16x8);
+        acc[NBC] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(g1, bb, acc[NBC], 0, 0, 0);
+        am2 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(g2, bb, am2, 0, 0, 0);
+        am3 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(g3, bb, am3, 0, 0, 0);
       }
-      acc[NBC] += am;
+      acc[NBC] += am2 + am3;
       // D layout: lane (col, g) holds rows j = 4 g + i of column 16 nc + col
 #pragma unroll
       for (int nc = 0; nc <= NBC; nc++)
@@ -515,19 +621,22 @@ __global__ __launch_bounds__(256, C > 26 ? 2 : 3) void composite_bwd_kernel(
         }
       }
     }
-    if (t < cnt && det.slots) {
+    // the moment gradients on the last kBJ threads (the first ones carry two
+    // rounds of channel sums)
+    const int jm = t - (256 - kBJ);
+    if (jm >= 0 && jm < cnt && det.slots) {
       float mo[6];
 #pragma unroll
       for (int n = 0; n < 6; n++)
-        mo[n] = (mat[t * kMS + 0 * 64 + CP + n] + mat[t * kMS + 1 * 64 + CP + n]) +
-                (mat[t * kMS + 2 * 64 + CP + n] + mat[t * kMS + 3 * 64 + CP + n]);
-      const float *r = reinterpret_cast<const float *>(&hdr[buf][2 * t]);
-      const float up = r[0] - (float)(tx * kTile), vp = r[1] - (float)(ty * kTile);
+        mo[n] = (mat[jm * kMS + 0 * 64 + CP + n] + mat[jm * kMS + 1 * 64 + CP + n]) +
+                (mat[jm * kMS + 2 * 64 + CP + n] + mat[jm * kMS + 3 * 64 + CP + n]);
+      const float *r = reinterpret_cast<const float *>(&hdr[buf][2 * jm]);
+      const float up = r[0] - (float)(tx * kTile + 8), vp = r[1] - (float)(ty * kTile + 8);
       const float mx = up * mo[0] - mo[1], my = vp * mo[0] - mo[2];
       const float mxx = up * up * mo[0] - 2.f * up * mo[1] + mo[3];
       const float mxy = up * vp * mo[0] - up * mo[2] - vp * mo[1] + mo[4];
       const float myy = vp * vp * mo[0] - 2.f * vp * mo[2] + mo[5];
-      const size_t sl = det_slot(det, gidx[buf][t], tx, ty);
+      const size_t sl = det_slot(det, gidx[buf][jm], tx, ty);
       if (sl < det.cap) {
         float *ga = det.slots + sl * GS;
         ga[0] = -(r[2] * mx + r[3] * my);
@@ -538,21 +647,21 @@ __global__ __launch_bounds__(256, C > 26 ? 2 : 3) void composite_bwd_kernel(
         ga[5] = mo[0] / r[5];
         det.flags[sl] = 1;
       }
-    } else if (t < cnt) {
+    } else if (jm >= 0 && jm < cnt) {
       float mo[6];
 #pragma unroll
       for (int n = 0; n < 6; n++)
-        mo[n] = (mat[t * kMS + 0 * 64 + CP + n] + mat[t * kMS + 1 * 64 + CP + n]) +
-                (mat[t * kMS + 2 * 64 + CP + n] + mat[t * kMS + 3 * 64 + CP + n]);
+        mo[n] = (mat[jm * kMS + 0 * 64 + CP + n] + mat[jm * kMS + 1 * 64 + CP + n]) +
+                (mat[jm * kMS + 2 * 64 + CP + n] + mat[jm * kMS + 3 * 64 + CP + n]);
       if (mo[0] != 0.f || mo[1] != 0.f || mo[2] != 0.f) {
-        const float *r = reinterpret_cast<const float *>(&hdr[buf][2 * t]);
-        const float up = r[0] - (float)(tx * kTile), vp = r[1] - (float)(ty * kTile);
+        const float *r = reinterpret_cast<const float *>(&hdr[buf][2 * jm]);
+        const float up = r[0] - (float)(tx * kTile + 8), vp = r[1] - (float)(ty * kTile + 8);
         // sums of g dx, g dy, g dx^2, g dx dy, g dy^2 with dx = u - x, dy = v - y
         const float mx = up * mo[0] - mo[1], my = vp * mo[0] - mo[2];
         const float mxx = up * up * mo[0] - 2.f * up * mo[1] + mo[3];
         const float mxy = up * vp * mo[0] - up * mo[2] - vp * mo[1] + mo[4];
         const float myy = vp * vp * mo[0] - 2.f * vp * mo[2] + mo[5];
-        float *ga = gacc + (size_t)gidx[buf][t] * GS;
+        float *ga = gacc + (size_t)gidx[buf][jm] * GS;
         atomicAdd(ga + 0, -(r[2] * mx + r[3] * my));
         atomicAdd(ga + 1, -(r[4] * my + r[3] * mx));
         atomicAdd(ga + 2, -0.5f * mxx);
