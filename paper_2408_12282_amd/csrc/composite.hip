@@ -195,9 +195,12 @@ __global__ __launch_bounds__(256, C > 32 ? 4 : 6) void composite_fwd_kernel(cons
 // x_hi = x truncated to BF16 and x_lo = x - x_hi rounded to BF16 (relative
 // error about 2^-16 per product, accumulated in FP32), on
 // v_mfma_f32_16x16x32_bf16: a sixth of the matrix-core time of FP32 operands.
-// The moment sums stay in FP32 (v_mfma_f32_16x16x4_f32): the geometry
-// gradients recombine them as u^2 sum g - 2 u sum g x + sum g x^2, which
-// cancels and would magnify a 2^-16 error.
+// The moment sums must stay FP32-accurate: the geometry gradients recombine
+// them as u^2 sum g - 2 u sum g x + sum g x^2, which cancels and would
+// magnify a 2^-16 error.  With x, y measured from the tile centre every basis
+// value has at most 8 significant bits, so g split exactly into three BF16
+// parts gives exact products on v_mfma_f32_16x16x32_bf16, where only the
+// FP32 accumulation rounds (as with FP32 operands, at a third of the time).
 // The batch is staged in LDS (double-buffered; the next batch is fetched
 // into registers while the current one is walked): the record headers, and
 // the channels already split into BF16 high and low parts in the lane order

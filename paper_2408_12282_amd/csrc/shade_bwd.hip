@@ -74,19 +74,16 @@ __device__ __forceinline__ float shade_pixel_bwd(const PixShade &S, const float 
 #pragma unroll
     for (int f = 0; f < F; f++) dgbar[kChFeat + f] += dnet_in[f];
     int p = F;
+    float sn[3][6], cs[3][6];
+#pragma unroll
+    for (int ax = 0; ax < 3; ax++) pe_octaves(S.x[ax], sn[ax], cs[ax]);
 #pragma unroll
     for (int oct = 0; oct < 6; oct++) {
       const float sc = (float)(1 << oct);
-      float cs[3], sn[3];
 #pragma unroll
-      for (int ax = 0; ax < 3; ax++) {
-        sn[ax] = sinpif(sc * S.x[ax]);
-        cs[ax] = cospif(sc * S.x[ax]);
-      }
+      for (int ax = 0; ax < 3; ax++) dx[ax] += dnet_in[p + ax] * (sc * kPi) * cs[ax][oct];
 #pragma unroll
-      for (int ax = 0; ax < 3; ax++) dx[ax] += dnet_in[p + ax] * (sc * kPi) * cs[ax];
-#pragma unroll
-      for (int ax = 0; ax < 3; ax++) dx[ax] -= dnet_in[p + 3 + ax] * (sc * kPi) * sn[ax];
+      for (int ax = 0; ax < 3; ax++) dx[ax] -= dnet_in[p + 3 + ax] * (sc * kPi) * sn[ax][oct];
       p += 6;
     }
     for (int k = 0; k < 3; k++) dwo[k] += dnet_in[p + k];

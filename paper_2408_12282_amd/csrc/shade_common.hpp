@@ -156,24 +156,39 @@ __device__ __forceinline__ void shade_geometry(const float *gb, float T, float u
 }
 
 // Network input [features | sin/cos(2^k pi x) | w_o | w_i | 0 ...] into an LDS row.
+// sin and cos of pi 2^k x for the position encoding's six octaves: octaves 0
+// and 3 from sinpi/cospi, the others by angle doubling (sin 2a = 2 sin a
+// cos a, cos 2a = (cos a - sin a)(cos a + sin a)).  A doubling at most
+// doubles the absolute error and adds one rounding, so every value is within
+// a few ulp of the direct evaluation, well below the error the FP32 position
+// itself carries into the top octave (its rounding times 32 pi).
+__device__ __forceinline__ void pe_octaves(float x, float (&s)[6], float (&c)[6]) {
+  s[0] = sinpif(x);
+  c[0] = cospif(x);
+  s[3] = sinpif(8.f * x);
+  c[3] = cospif(8.f * x);
+#pragma unroll
+  for (int k = 1; k < 6; k++) {
+    if (k == 3) continue;
+    s[k] = 2.f * s[k - 1] * c[k - 1];
+    c[k] = (c[k - 1] - s[k - 1]) * (c[k - 1] + s[k - 1]);
+  }
+}
+
 template <int F, int IN_PAD, class M>
 __device__ __forceinline__ void build_net_input(const float *gb, const PixShade &S, typename M::Elem *row) {
   int p = 0;
 #pragma unroll
   for (int f = 0; f < F; f++) put_in<M, IN_PAD>(row, p++, gb[kChFeat + f] * S.ia);
+  float sv[3][6], cv[3][6];
+#pragma unroll
+  for (int ax = 0; ax < 3; ax++) pe_octaves(S.x[ax], sv[ax], cv[ax]);
 #pragma unroll
   for (int oct = 0; oct < 6; oct++) {
-    const float sc = (float)(1 << oct);
-    float sv[3], cv[3];
 #pragma unroll
-    for (int ax = 0; ax < 3; ax++) {
-      sv[ax] = sinpif(sc * S.x[ax]);
-      cv[ax] = cospif(sc * S.x[ax]);
-    }
+    for (int ax = 0; ax < 3; ax++) put_in<M, IN_PAD>(row, p++, sv[ax][oct]);
 #pragma unroll
-    for (int ax = 0; ax < 3; ax++) put_in<M, IN_PAD>(row, p++, sv[ax]);
-#pragma unroll
-    for (int ax = 0; ax < 3; ax++) put_in<M, IN_PAD>(row, p++, cv[ax]);
+    for (int ax = 0; ax < 3; ax++) put_in<M, IN_PAD>(row, p++, cv[ax][oct]);
   }
 #pragma unroll
   for (int k = 0; k < 3; k++) put_in<M, IN_PAD>(row, p++, S.wo[k]);
