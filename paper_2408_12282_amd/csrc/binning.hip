@@ -68,22 +68,39 @@ __global__ __launch_bounds__(kScanThreads) void scan_partials_kernel(uint32_t *_
   if (threadIdx.x == 0 && total_out) total_out[0] = carry;
 }
 
+// Down sweep.  SUM: the block adds the partials of the blocks before it
+// itself (no separate scan of the partials); otherwise partials holds their
+// exclusive scan.
+template <bool SUM>
 __global__ __launch_bounds__(kScanThreads) void scan_down_kernel(const uint32_t *__restrict__ in,
                                                                  uint32_t *__restrict__ out, uint32_t n,
-                                                                 const uint32_t *__restrict__ partials) {
+                                                                 const uint32_t *__restrict__ partials,
+                                                                 uint32_t *__restrict__ total_out) {
   __shared__ uint32_t lds[4];
   const uint32_t base = blockIdx.x * kScanItems + threadIdx.x * 4;
   uint32_t v[4];
 #pragma unroll
   for (int k = 0; k < 4; k++) v[k] = base + k < n ? in[base + k] : 0u;
+  uint32_t before = 0;
+  if (SUM) {
+    uint32_t p = 0;
+    for (uint32_t i = threadIdx.x; i < blockIdx.x; i += kScanThreads) p += partials[i];
+    uint32_t tot;
+    block_exclusive_scan(p, lds, tot);
+    before = tot;
+  } else {
+    before = partials[blockIdx.x];
+  }
   const uint32_t s = v[0] + v[1] + v[2] + v[3];
   uint32_t total;
-  uint32_t ex = block_exclusive_scan(s, lds, total) + partials[blockIdx.x];
+  uint32_t ex = block_exclusive_scan(s, lds, total) + before;
 #pragma unroll
   for (int k = 0; k < 4; k++) {
     if (base + k < n) out[base + k] = ex;
     ex += v[k];
   }
+  // the grand total, from the last block (SUM form)
+  if (SUM && total_out && blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) total_out[0] = before + total;
 }
 
 // ------------------------------------------------------------------ radix pass
@@ -149,18 +166,35 @@ __global__ __launch_bounds__(kSortThreads) void radix_scatter_kernel(
   }
   run[t] = 0;
   if (LOCAL) {
-    // 16 independent loads in flight per step
-    uint32_t tot = 0, below = 0;
-    for (int b0 = 0; b0 < nblocks; b0 += 16) {
-      uint32_t c[16];
+    // Each wave sums a quarter of the blocks' counts, a lane four digits per
+    // 16-byte load (eight loads in flight), for all blocks and for the blocks
+    // before this one; the quarters are added through LDS.
+    const int q0 = (nblocks * w) >> 2, q1 = (nblocks * (w + 1)) >> 2;
+    const uint4 *h4 = reinterpret_cast<const uint4 *>(hist_scan) + lane;
+    uint4 tot4 = make_uint4(0u, 0u, 0u, 0u), bel4 = make_uint4(0u, 0u, 0u, 0u);
+    for (int b0 = q0; b0 < q1; b0 += 8) {
+      uint4 c[8];
 #pragma unroll
-      for (int k = 0; k < 16; k++) c[k] = b0 + k < nblocks ? hist_scan[(b0 + k) * kRadixBins + t] : 0u;
+      for (int k = 0; k < 8; k++) c[k] = b0 + k < q1 ? h4[(size_t)(b0 + k) * (kRadixBins / 4)] : make_uint4(0u, 0u, 0u, 0u);
 #pragma unroll
-      for (int k = 0; k < 16; k++) {
-        tot += c[k];
-        below += b0 + k < (int)blockIdx.x ? c[k] : 0u;
+      for (int k = 0; k < 8; k++) {
+        tot4.x += c[k].x;
+        tot4.y += c[k].y;
+        tot4.z += c[k].z;
+        tot4.w += c[k].w;
+        if (b0 + k < (int)blockIdx.x) {
+          bel4.x += c[k].x;
+          bel4.y += c[k].y;
+          bel4.z += c[k].z;
+          bel4.w += c[k].w;
+        }
       }
     }
+    reinterpret_cast<uint4 *>(wcnt[w])[lane] = tot4;
+    reinterpret_cast<uint4 *>(wbase[w])[lane] = bel4;
+    __syncthreads();
+    const uint32_t tot = (wcnt[0][t] + wcnt[1][t]) + (wcnt[2][t] + wcnt[3][t]);
+    const uint32_t below = (wbase[0][t] + wbase[1][t]) + (wbase[2][t] + wbase[3][t]);
     uint32_t total;
     gbase[t] = block_exclusive_scan(tot, lds4, total) + below;
   } else {
@@ -368,15 +402,19 @@ __global__ __launch_bounds__(256) void tile_scan_kernel(uint32_t *__restrict__ c
   for (int i = threadIdx.x; i < nparts; i += 256) msum += area_part[i];
   uint32_t mtot;
   block_exclusive_scan(msum, lds4, mtot);
-  uint32_t carry = 0;
-  for (int base = 0; base < T; base += 256) {
-    const int i = base + threadIdx.x;
-    const uint32_t v = i < T ? counts[i] : 0u;
-    uint32_t total;
-    const uint32_t ex = block_exclusive_scan(v, lds4, total);
-    if (i < T) counts[i] = carry + ex;
-    carry += total;
-  }
+  // one block scan: thread k sums, then rewrites, a contiguous chunk of counts
+  const int per = (T + 255) / 256, i0 = threadIdx.x * per;
+  uint32_t s = 0;
+  for (int k = 0; k < per; k++)
+    if (i0 + k < T) s += counts[i0 + k];
+  uint32_t total;
+  uint32_t ex = block_exclusive_scan(s, lds4, total);
+  for (int k = 0; k < per; k++)
+    if (i0 + k < T) {
+      const uint32_t v = counts[i0 + k];
+      counts[i0 + k] = ex;
+      ex += v;
+    }
   if (threadIdx.x == 0) {
     const uint32_t m = mtot;
     m_out[0] = m;
@@ -437,13 +475,21 @@ __global__ __launch_bounds__(256) void tile_write_kernel(const uint32_t *__restr
 
 static inline uint32_t cdiv(uint64_t a, uint64_t b) { return (uint32_t)((a + b - 1) / b); }
 
+constexpr uint32_t kScanSumBlocks = 4096;  // up to this many blocks a scan skips the partials pass
+
 // Exclusive scan of n (host-known bound) u32 values; total written to total_dev.
 void launch_scan(const uint32_t *in, uint32_t *out, uint32_t n, uint32_t *partials, uint32_t *total_dev,
                  hipStream_t st) {
   const uint32_t nb = n ? cdiv(n, kScanItems) : 1;
   scan_reduce_kernel<<<nb, kScanThreads, 0, st>>>(in, n, partials);
+  if (n && nb <= kScanSumBlocks) {
+    // few blocks: each down-sweep block sums the partials before it, the
+    // last one writes the total
+    scan_down_kernel<true><<<nb, kScanThreads, 0, st>>>(in, out, n, partials, total_dev);
+    return;
+  }
   scan_partials_kernel<<<1, kScanThreads, 0, st>>>(partials, nb, total_dev);
-  if (n) scan_down_kernel<<<nb, kScanThreads, 0, st>>>(in, out, n, partials);
+  if (n) scan_down_kernel<false><<<nb, kScanThreads, 0, st>>>(in, out, n, partials, nullptr);
 }
 
 uint32_t radix_blocks(uint64_t n) { return n ? cdiv(n, kSortItems) : 1; }
