@@ -31,7 +31,8 @@ typedef __attribute__((__vector_size__(4 * sizeof(float)))) float cf32x4;
 // in LDS, and the channel sums G[c][p] += sum_k channel_k,c w_k,p are one
 // FP32 product per four hits on the matrix cores (v_mfma_f32_16x16x4_f32,
 // channels x pixels, K = hits), accumulated in registers for the tile.
-constexpr int kFG = 8;        // hits per flush of the weight rows (two k-steps)
+constexpr int kFG = 4;        // hits per flush of the weight rows (one k-step; the small LDS
+                              // and register footprint lets seven workgroups share a CU)
 constexpr int kFWS = 64 + 16;  // row stride of the weight rows (conflict-free column reads)
 
 template <int C>
@@ -46,7 +47,7 @@ __global__ __launch_bounds__(256, C > 32 ? 4 : 6) void composite_fwd_kernel(cons
   constexpr int RS = rec_stride(C);
   constexpr int NB = 128;             // records per batch
   constexpr int CB = (C + 15) / 16;   // 16-channel row blocks of the sums
-  static_assert(NB <= 256 && kFG == 8, "record index in 8 bits, two k-steps per flush");
+  static_assert(NB <= 256 && kFG % 4 == 0 && kFG <= 8, "record index in 8 bits, one or two k-steps per flush");
   __shared__ float4 batch[NB * RS / 4];
   __shared__ uint2 bbox[NB];
   __shared__ float wrow[4][kFG * kFWS];
