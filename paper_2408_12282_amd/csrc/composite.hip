@@ -286,6 +286,7 @@ __global__ __launch_bounds__(256, C > 26 ? 2 : 3) void composite_bwd_kernel(
   __shared__ float4 hdr[2][2 * kBJ];         // u v a b | c opacity . . of each Gaussian
   __shared__ cbf16x8 aop[2][KC][2][64];      // channel A operands: [k-step][high, low][lane]
   __shared__ uint32_t gidx[2][kBJ];
+  __shared__ uint32_t gq[2][kBJ];            // Gaussian indices of the batch fetched next
   __shared__ uint2 bbox[2][kBJ];
   __shared__ uint32_t maxlast;
   const int t = threadIdx.x, lane = t & 63, g = lane >> 4, col = lane & 15;
@@ -385,15 +386,18 @@ __global__ __launch_bounds__(256, C > 26 ? 2 : 3) void composite_bwd_kernel(
   for (int i = 0; i < 4 * KC; i++) f_v[i] = 0.f;
   uint32_t f_g = 0;
   uint2 f_box = make_uint2(0u, 0u);
-  // The Gaussian index a fetch uses was read one batch earlier, so that the
-  // record loads do not wait on the index load.
-  uint32_t f_gn = 0;
-  auto load_index = [&](int lo_, int cnt_) {
-    if ((rA || rH || rI) && f_j < cnt_) f_gn = sorted_g[rg.x + lo_ + f_j];
+  // A fetch takes its Gaussian's index from LDS, where the index threads put
+  // it one batch earlier: no record load waits on an index load (a wait on a
+  // load would also take in this wave's gradient atomics of the batch before).
+  uint32_t f_gi2 = 0;  // index threads: their Gaussian's index two batches ahead
+  auto load_index2 = [&](int lo_, int cnt_) {
+    if (rI && f_j < cnt_) f_gi2 = sorted_g[rg.x + lo_ + f_j];
   };
-  auto fetch = [&](int cnt_) {
+  auto stage_index = [&](int slot, int cnt_) {
+    if (rI && f_j < cnt_) gq[slot][f_j] = f_gi2;
+  };
+  auto fetch = [&](int cnt_, uint32_t gg) {
     if ((rA || rH || rI) && f_j < cnt_) {
-      const uint32_t gg = f_gn;
       const float *src = records + (size_t)gg * RS + f_off;
       if (rA) {
         // two 8-byte-aligned float2 per k-step; a pair is loaded whenever its
@@ -451,21 +455,26 @@ __global__ __launch_bounds__(256, C > 26 ? 2 : 3) void composite_bwd_kernel(
   };
   if (top > 0) {
     const int lo0 = top > kBJ ? top - kBJ : 0, lo1 = lo0 > kBJ ? lo0 - kBJ : 0;
-    load_index(lo0, top - lo0);
-    fetch(top - lo0);
+    const uint32_t g0 = ((rA || rH || rI) && f_j < top - lo0) ? sorted_g[rg.x + lo0 + f_j] : 0u;
+    fetch(top - lo0, g0);
     stage(0, top - lo0);
-    if (lo0 > 0) load_index(lo1, lo0 - lo1);
+    if (lo0 > 0) {
+      load_index2(lo1, lo0 - lo1);
+      stage_index(1, lo0 - lo1);
+    }
   }
   __syncthreads();
-  const float dTT = dTfin * Tfin;
-  float Tcur = Tfin, S = 0.f;
+  // U: dL/dT_final T_final plus the sum of w eg over the Gaussians behind the
+  // current one (the part of dL/dalpha that the Gaussians behind contribute)
+  float Tcur = Tfin, U = dTfin * Tfin;
   int buf = 0;
   for (int hi = top; hi > 0; hi -= kBJ, buf ^= 1) {
     const int lo = hi > kBJ ? hi - kBJ : 0, cnt = hi - lo;
     const int nlo = lo > kBJ ? lo - kBJ : 0, ncnt = lo - nlo;
     const int nnlo = nlo > kBJ ? nlo - kBJ : 0, nncnt = nlo - nnlo;
-    if (ncnt > 0) fetch(ncnt);  // next batch, in flight during this one
-    if (nncnt > 0) load_index(nnlo, nncnt);  // and the indices of the one after
+    // next batch, in flight during this one, and the indices of the one after
+    if (ncnt > 0) fetch(ncnt, ((rA || rH || rI) && f_j < ncnt) ? gq[buf ^ 1][f_j] : 0u);
+    if (nncnt > 0) load_index2(nnlo, nncnt);
     // Gaussians of the batch that can reach this wave's strip
     bool h = false;
     if (lane < cnt) h = box_hits(bbox[buf][lane], sx, sy);
@@ -525,9 +534,9 @@ __global__ __launch_bounds__(256, C > 26 ? 2 : 3) void composite_bwd_kernel(
         const float inv = __builtin_amdgcn_rcpf(1.f - al);
         const float Tb = Tcur * inv;
         const float wgt = al * Tb;
-        const float dal = Tb * eg - (S + dTT) * inv;
-        const float Sn = __fmaf_rn(wgt, eg, S);
-        S = on ? Sn : S;
+        const float dal = Tb * eg - U * inv;
+        const float Un = __fmaf_rn(wgt, eg, U);
+        U = on ? Un : U;
         Tcur = on ? Tb : Tcur;
         mat[jj * kMS + t] = on ? wgt : 0.f;
         mat[(kBJ + jj) * kMS + t] = on && araw < 0.99f ? dal * al : 0.f;
@@ -602,6 +611,7 @@ __global__ __launch_bounds__(256, C > 26 ? 2 : 3) void composite_bwd_kernel(
         for (int i = 0; i < 4; i++) mat[(4 * g + i) * kMS + 64 * w + 16 * nc + col] = acc[nc][i];
     }
     if (ncnt > 0) stage(buf ^ 1, ncnt);
+    if (nncnt > 0) stage_index(buf, nncnt);
     __syncthreads();
     if (det.slots) {
       // deterministic: the tile's sums of each Gaussian go to that Gaussian's
