@@ -328,10 +328,12 @@ __global__ __launch_bounds__(64, 2) void shade_bwd_split_kernel(ShadeArgs A, __b
         }
   }
   __syncthreads();
-  // ---- C: Eq. 7 and the gradients of the network outputs
+  // ---- C: Eq. 7 and the gradients of the network outputs.  The pixel's
+  // G-buffer values stay in registers through D for E (the register budget of
+  // two waves per SIMD holds them).
+  float gb[C], T, gL[3];
+  load_pixel<C>(A, inside, pix, HW, gb, T, gL);
   {
-    float gb[C], T, gL[3];
-    load_pixel_geo<C>(A, inside, pix, HW, gb, T, gL);
     PixShade S;
     shade_geometry<C>(gb, T, uc, vc, A.cam, A.light, true, S);
     if (S.bg) gL[0] = gL[1] = gL[2] = 0.f;
@@ -392,8 +394,7 @@ __global__ __launch_bounds__(64, 2) void shade_bwd_split_kernel(ShadeArgs A, __b
   __syncthreads();
   // ---- E: per pixel backward of geometry, BRDF and Eq. 7
   {
-    float gb[C], T, gL[3], dgbar[C];
-    load_pixel<C>(A, inside, pix, HW, gb, T, gL);
+    float dgbar[C];
     PixShade S;
     shade_geometry<C>(gb, T, uc, vc, A.cam, A.light, true, S);
     if (S.bg) gL[0] = gL[1] = gL[2] = 0.f;
@@ -414,7 +415,6 @@ void launch_shade_bwd_split_t(const ShadeArgs &a, __bf16 *rec_x, __bf16 *rec_o, 
 template void launch_shade_bwd_split_t<0, 64>(const ShadeArgs &, __bf16 *, __bf16 *, hipStream_t);
 template void launch_shade_bwd_split_t<8, 64>(const ShadeArgs &, __bf16 *, __bf16 *, hipStream_t);
 template void launch_shade_bwd_split_t<16, 64>(const ShadeArgs &, __bf16 *, __bf16 *, hipStream_t);
-template void launch_shade_bwd_split_t<32, 96>(const ShadeArgs &, __bf16 *, __bf16 *, hipStream_t);
 
 
 // ---------------------------------------------------------------- generic form
