@@ -343,7 +343,6 @@ typedef struct {
   size_t radii;          /* int32 [n] */
   size_t tile_ranges;    /* uint32x2 [tiles]: [start, end) into sorted_gauss */
   size_t sorted_gauss;   /* uint32 [capacity] Gaussian index per instance, tile-major */
-  size_t sorted_tiles;   /* uint32 [capacity] tile id per instance */
   size_t t_final;        /* float [H][W] */
   size_t n_contrib;      /* uint32 [H][W] */
   size_t status;         /* int32[4]: flags, M low, M high, unused */

@@ -86,7 +86,7 @@ int in_pad_of(int in_dim) { return (in_dim + 31) / 32 * 32; }
 
 struct Layout {
   size_t records, depth_keys, vals_a, keys_b, vals_b, keys_a, rects, radii, boxes, tt, offsets, partials, hist;
-  size_t ik_a, iv_a, ik_b, iv_b, ranges, tcount, apart, t_final, tile_top, tile_order, n_contrib, status, m_total;
+  size_t ik_a, iv_a, ik_b, iv_b, ranges, tcount, tpcnt, dtot, apart, t_final, tile_top, tile_order, n_contrib, status, m_total;
   size_t gacc, slots, sflags, dG, dT, wops, tops, nops, mlp_part, mlp_mid, rec_x, rec_o, gx, gdy;
   size_t total;
   int C, RS, GS, TX, TY, T;
@@ -133,6 +133,8 @@ bool make_layout(int32_t n, int32_t W, int32_t H, int32_t F, int32_t mlp_width, 
   L.partials = take(np * 4);
   L.hist = take((size_t)nbmax * kRadixBins * 4);
   L.tcount = take((size_t)L.T * 4);
+  L.tpcnt = take(tile_piece_words(L.TX, L.TY, (uint32_t)cc) * 4);
+  L.dtot = take(kRadixBins * 4);  // digit totals of a radix pass
   L.apart = take((size_t)area_parts((uint32_t)nn) * 4);
   L.ik_a = take(cc * 4);
   L.iv_a = take(cc * 4);
@@ -361,7 +363,6 @@ sssgs_status sssgs_workspace_layout(int32_t n, int32_t width, int32_t height, in
   out->boxes = L.boxes;
   out->tile_ranges = L.ranges;
   out->sorted_gauss = L.iv_a;
-  out->sorted_tiles = L.ik_a;
   out->t_final = L.t_final;
   out->n_contrib = L.n_contrib;
   out->status = L.status;
@@ -416,7 +417,7 @@ sssgs_status forward_impl(const sssgs_gaussians *g, const sssgs_camera *cam, con
     for (int pass = 0; pass < 4; pass++) {
       uint32_t *ko = (pass & 1) ? ka : kb;
       uint32_t *vo = (pass & 1) ? va : vb;
-      launch_radix_pass(kin, vin, ko, vo, n, nullptr, pass * kRadixBits, hist, part, st, false);
+      launch_radix_pass(kin, vin, ko, vo, n, nullptr, pass * kRadixBits, hist, at<uint32_t>(ws, L.dtot), st);
       kin = ko;
       vin = vo;
     }
@@ -433,10 +434,11 @@ sssgs_status forward_impl(const sssgs_gaussians *g, const sssgs_camera *cam, con
     launch_superbin_expand(va, rects, n, ucap, L.TX, L.TY, tt, offs, ik_a, iv_a, part, mtot + 1,
                            at<uint32_t>(ws, L.apart), st);
   }
-  // 4-5. tile-major lists (Gaussian index, tile id), ranges, instance count and status
+  // 4-5. tile-major Gaussian-index lists, tile ranges, instance count and status
   {
     Scope sc(kStSortTiles, st);
-    launch_tile_lists(n, ucap, L.TX, L.TY, ik_a, iv_a, ik_b, iv_b, at<uint32_t>(ws, L.tcount), hist, part,
+    launch_tile_lists(n, ucap, L.TX, L.TY, ik_a, iv_a, ik_b, iv_b, at<uint32_t>(ws, L.tcount),
+                      at<uint32_t>(ws, L.tpcnt), hist, at<uint32_t>(ws, L.dtot),
                       mtot + 1, at<uint32_t>(ws, L.apart), mtot, status, ranges, st);
   }
   // 6. compositing into the G-buffer (Eq. 3)
@@ -770,6 +772,7 @@ VisLayout vis_layout(int32_t n) {
   size_t np = scan_partials_needed(nn);
   const size_t np2 = scan_partials_needed((uint64_t)nb * kRadixBins);
   if (np2 > np) np = np2;
+  if (np < (size_t)kRadixBins) np = kRadixBins;  // also the digit totals of the radix passes
   L.hist = take((size_t)nb * kRadixBins * 4);
   L.part = take(np * 4);
   L.left = take(nn * 4);

@@ -8,8 +8,10 @@
 // later (tile) passes are stable, so the result is the same total order
 // (tile, depth, index) as sorting all M 64-bit keys, at a fraction of the
 // traffic.  Every pass is a stable 8-bit counting pass: per-block digit
-// histograms, one exclusive scan over all of them (digit-major), and a
-// scatter in which each block ranks its keys stably with wave ballots.
+// counts, a scan down each digit's column of block counts (one workgroup per
+// digit, active blocks only) giving the digit totals and each block's count
+// before it, and a scatter in which each block ranks its keys stably with
+// wave ballots.
 #include "common.hpp"
 
 namespace sssgs {
@@ -111,40 +113,66 @@ __device__ __forceinline__ uint32_t load_count(uint32_t n_host, const uint32_t *
   return m < n_host ? m : n_host;
 }
 
-// Per-block digit histograms: digit-major hist[digit][block] for the scan
-// across blocks, or block-major hist[block][digit] (LOCAL) when the scatter
-// derives its own offsets.
-template <bool LOCAL>
+// Per-block digit counts, block-major: hist[block][digit].  Blocks past the
+// item count write nothing (the column scan reads only the active blocks).
 __global__ __launch_bounds__(kSortThreads) void radix_hist_kernel(const uint32_t *__restrict__ keys, uint32_t n_host,
                                                                   const uint32_t *__restrict__ n_dev, int shift,
-                                                                  uint32_t *__restrict__ hist, int nblocks) {
+                                                                  uint32_t *__restrict__ hist) {
   __shared__ uint32_t h[kRadixBins];
   const int t = threadIdx.x;
-  h[t] = 0;
-  __syncthreads();
   const uint32_t n = load_count(n_host, n_dev);
   const uint32_t base = blockIdx.x * kSortItems;
+  if (base >= n) return;  // uniform per block
+  h[t] = 0;
+  __syncthreads();
 #pragma unroll
   for (int r = 0; r < kSortRounds; r++) {
     const uint32_t idx = base + r * kSortThreads + t;
     if (idx < n) atomicAdd(&h[(keys[idx] >> shift) & (kRadixBins - 1)], 1u);
   }
   __syncthreads();
-  if (LOCAL) hist[blockIdx.x * kRadixBins + t] = h[t];
-  else hist[t * nblocks + blockIdx.x] = h[t];
+  hist[blockIdx.x * kRadixBins + t] = h[t];
+}
+
+// One workgroup per digit d: hist[b][d] becomes the count of digit d in the
+// blocks before b (exclusive scan down the column, over the active blocks
+// only), and tot[d] the digit's total.  A thread takes four consecutive
+// blocks per step.
+__global__ __launch_bounds__(kSortThreads) void radix_colscan_kernel(uint32_t *__restrict__ hist, uint32_t n_host,
+                                                                     const uint32_t *__restrict__ n_dev,
+                                                                     uint32_t *__restrict__ tot) {
+  __shared__ uint32_t lds4[4];
+  const int d = blockIdx.x, t = threadIdx.x;
+  const uint32_t n = load_count(n_host, n_dev);
+  const uint32_t na = (n + kSortItems - 1) / kSortItems;
+  uint32_t carry = 0;
+  for (uint32_t b0 = 0; b0 < na; b0 += 4 * kSortThreads) {
+    const uint32_t b = b0 + 4 * t;
+    uint32_t v[4];
+#pragma unroll
+    for (int k = 0; k < 4; k++) v[k] = b + k < na ? hist[(size_t)(b + k) * kRadixBins + d] : 0u;
+    uint32_t total;
+    uint32_t ex = carry + block_exclusive_scan((v[0] + v[1]) + (v[2] + v[3]), lds4, total);
+#pragma unroll
+    for (int k = 0; k < 4; k++) {
+      if (b + k < na) hist[(size_t)(b + k) * kRadixBins + d] = ex;
+      ex += v[k];
+    }
+    carry += total;
+  }
+  if (t == 0) tot[d] = carry;
 }
 
 // Stable scatter of one 8-bit digit.  The block ranks its keys with wave
 // ballots into block-local digit runs in LDS, then streams the runs out, so
 // that consecutive lanes write consecutive global addresses.  The global
-// start of each of the block's runs comes from the scanned digit-major
-// histogram, or (LOCAL, few blocks) from the block-major counts directly:
-// all blocks' counts of the thread's digit, and those of earlier blocks.
-template <bool LOCAL>
+// start of the block's run of digit d is the start of digit d (exclusive scan
+// of the digit totals) plus the column-scanned count of digit d in earlier
+// blocks.
 __global__ __launch_bounds__(kSortThreads) void radix_scatter_kernel(
     const uint32_t *__restrict__ keys_in, const uint32_t *__restrict__ vals_in, uint32_t *__restrict__ keys_out,
     uint32_t *__restrict__ vals_out, uint32_t n_host, const uint32_t *__restrict__ n_dev, int shift,
-    const uint32_t *__restrict__ hist_scan, int nblocks) {
+    const uint32_t *__restrict__ hist_col, const uint32_t *__restrict__ tot) {
   __shared__ uint32_t run[kRadixBins];   // running block-local position per digit
   __shared__ uint32_t loff[kRadixBins];  // block-local start of each digit's run
   __shared__ uint32_t gbase[kRadixBins]; // global start of this block's run of each digit
@@ -164,42 +192,11 @@ __global__ __launch_bounds__(kSortThreads) void radix_scatter_kernel(
     key[r] = idx < n ? keys_in[idx] : 0u;
     val[r] = idx < n ? vals_in[idx] : 0u;
   }
-  run[t] = 0;
-  if (LOCAL) {
-    // Each wave sums a quarter of the blocks' counts, a lane four digits per
-    // 16-byte load (eight loads in flight), for all blocks and for the blocks
-    // before this one; the quarters are added through LDS.
-    const int q0 = (nblocks * w) >> 2, q1 = (nblocks * (w + 1)) >> 2;
-    const uint4 *h4 = reinterpret_cast<const uint4 *>(hist_scan) + lane;
-    uint4 tot4 = make_uint4(0u, 0u, 0u, 0u), bel4 = make_uint4(0u, 0u, 0u, 0u);
-    for (int b0 = q0; b0 < q1; b0 += 8) {
-      uint4 c[8];
-#pragma unroll
-      for (int k = 0; k < 8; k++) c[k] = b0 + k < q1 ? h4[(size_t)(b0 + k) * (kRadixBins / 4)] : make_uint4(0u, 0u, 0u, 0u);
-#pragma unroll
-      for (int k = 0; k < 8; k++) {
-        tot4.x += c[k].x;
-        tot4.y += c[k].y;
-        tot4.z += c[k].z;
-        tot4.w += c[k].w;
-        if (b0 + k < (int)blockIdx.x) {
-          bel4.x += c[k].x;
-          bel4.y += c[k].y;
-          bel4.z += c[k].z;
-          bel4.w += c[k].w;
-        }
-      }
-    }
-    reinterpret_cast<uint4 *>(wcnt[w])[lane] = tot4;
-    reinterpret_cast<uint4 *>(wbase[w])[lane] = bel4;
-    __syncthreads();
-    const uint32_t tot = (wcnt[0][t] + wcnt[1][t]) + (wcnt[2][t] + wcnt[3][t]);
-    const uint32_t below = (wbase[0][t] + wbase[1][t]) + (wbase[2][t] + wbase[3][t]);
+  {
     uint32_t total;
-    gbase[t] = block_exclusive_scan(tot, lds4, total) + below;
-  } else {
-    gbase[t] = hist_scan[t * nblocks + blockIdx.x];
+    gbase[t] = block_exclusive_scan(tot[t], lds4, total) + hist_col[blockIdx.x * kRadixBins + t];
   }
+  run[t] = 0;
 #pragma unroll
   for (int k = 0; k < 4; k++) wcnt[k][t] = 0;
   __syncthreads();
@@ -337,71 +334,198 @@ __global__ void zero_u32_kernel(uint32_t *__restrict__ p) { *p = 0u; }
 // ------------------------------------------------------------------ tile lists
 //
 // Tile lists from super-bin lists.  The depth-sorted Gaussians are expanded
-// into (super-bin, Gaussian) instances -- a super-bin is a square of 2^log2s
-// tiles, sized so that there are at most 256 -- and one stable 8-bit radix
-// pass makes them super-bin-major, depth order kept within each super-bin.
-// Each tile then filters its super-bin's list by its own rectangle test,
-// which keeps the depth order: the tile's list is written as one contiguous,
-// coalesced run.  One workgroup per tile counts its instances, one block scans
-// the counts into tile offsets, and one workgroup per tile writes its run.
-// The result is the order (tile, depth, index) of a stable sort of all
-// (tile, depth) keys.
+// into (super-bin, Gaussian) instances -- a super-bin is a square of
+// S = 2^log2s tiles on a side, sized so that there are at most 256 -- and one
+// stable 8-bit radix pass makes them super-bin-major, depth order kept within
+// each super-bin.  Each super-bin's list is cut into pieces of kPieceItems
+// consecutive items, and one wave takes a piece: it reads each item once and,
+// for every tile of the super-bin, one wave ballot per 64 items says which of
+// them cover the tile, in list order.  Four kernels: the count kernel writes
+// per (piece, tile) counts; one workgroup per super-bin turns them, per tile,
+// into the count before each piece (and the tile's total); one block scans
+// the totals into the tiles' list offsets in row-major tile order; the write
+// kernel writes every tile's items at its offset plus the piece's prefix plus
+// the item's ballot rank.  Pieces spread the work of the heaviest super-bins
+// over the whole chip.  The result is the order (tile, depth, index) of a
+// stable sort of all (tile, depth) keys.
 
-// [start, end) of super-bin sb in the radix pass output (digit-major scanned
-// histogram; digits >= the number of super-bins are empty).
-__device__ __forceinline__ uint2 superbin_range(const uint32_t *__restrict__ hist_scan, int nblocks, int sb,
-                                                uint32_t ms) {
-  const uint32_t a = hist_scan[(size_t)sb * nblocks];
-  const uint32_t b = sb + 1 < kRadixBins ? hist_scan[(size_t)(sb + 1) * nblocks] : ms;
-  return make_uint2(a, b);
-}
-
-// Does the clipped rectangle packed in a super-bin key cover the tile at
-// super-bin-local coordinates (lx, ly)?
-__device__ __forceinline__ bool key_covers(uint32_t key, int log2s, uint32_t lx, uint32_t ly) {
-  const uint32_t m = (1u << log2s) - 1u;
-  const uint32_t x0 = (key >> 8) & m, x1 = (key >> (8 + log2s)) & m;
-  const uint32_t y0 = (key >> (8 + 2 * log2s)) & m, y1 = (key >> (8 + 3 * log2s)) & m;
-  return lx >= x0 && lx <= x1 && ly >= y0 && ly <= y1;
-}
-
-constexpr int kTileItems = 4;  // list items per thread and step
+constexpr int kPieceItems = 256;  // items per piece: four 64-item chunks, loaded together
+constexpr int kPieceWaves = 4;    // waves per workgroup of the piece kernels
+constexpr int kPieceGrid = 2048;  // at most this many workgroups; each wave loops over pieces
 static_assert(8 + 4 * kMaxSuperbinLog2 <= 32, "super-bin key layout");
 
-__global__ __launch_bounds__(256) void tile_count_kernel(const uint32_t *__restrict__ sb_keys,
-                                                         const uint32_t *__restrict__ hist_scan, int nblocks,
-                                                         const uint32_t *__restrict__ ms_dev, uint32_t cap, int TX,
-                                                         int SX, int log2s, uint32_t *__restrict__ counts) {
-  __shared__ uint32_t lds4[4];
-  const int t = blockIdx.x;
-  const uint32_t tx = t % TX, ty = t / TX;
-  const uint32_t lx = tx & ((1u << log2s) - 1u), ly = ty & ((1u << log2s) - 1u);
-  const uint32_t ms = min(ms_dev[0], cap);
-  const uint2 rg = superbin_range(hist_scan, nblocks, (int)(ty >> log2s) * SX + (int)(tx >> log2s), ms);
-  uint32_t c = 0;
-  for (uint32_t i0 = rg.x + threadIdx.x * kTileItems; i0 < rg.y; i0 += 256u * kTileItems) {
-#pragma unroll
-    for (int j = 0; j < kTileItems; j++)
-      if (i0 + j < rg.y && key_covers(sb_keys[i0 + j], log2s, lx, ly)) c++;
-  }
+// Pieces of the super-bin lists: pf[sb] = first piece of super-bin sb,
+// pf[256] = the number of pieces; beg / end = the super-bin's list.
+struct PieceTable {
+  uint32_t pf[kRadixBins + 1];
+  uint32_t beg[kRadixBins], end[kRadixBins];
+};
+
+// Built by a 256-thread workgroup (thread = super-bin) from the super-bin
+// totals of the radix pass.
+__device__ void build_piece_table(PieceTable &pt, const uint32_t *__restrict__ sb_tot, uint32_t *lds4) {
+  const int t = threadIdx.x;
+  const uint32_t c = sb_tot[t];
   uint32_t total;
-  block_exclusive_scan(c, lds4, total);
-  if (threadIdx.x == 0) counts[t] = total;
+  const uint32_t b = block_exclusive_scan(c, lds4, total);
+  pt.pf[t] = block_exclusive_scan((c + kPieceItems - 1) / kPieceItems, lds4, total);
+  pt.beg[t] = b;
+  pt.end[t] = b + c;
+  if (t == 0) pt.pf[kRadixBins] = total;
+  __syncthreads();
 }
 
-// One block: tile offsets (exclusive scan of the counts), the instance count
-// (the sum of the per-block tiles-touched totals: exact also when the
-// super-bin instances overflowed the capacity and the counts are incomplete)
-// and the status word.
+// Super-bin of piece p (< the number of pieces): the last sb with pf[sb] <= p.
+__device__ __forceinline__ int piece_superbin(const PieceTable &pt, uint32_t p) {
+  int lo = 0;
+#pragma unroll
+  for (int step = kRadixBins / 2; step > 0; step >>= 1)
+    if (pt.pf[lo + step] <= p) lo += step;
+  return lo;
+}
+
+// Tile rectangle of a super-bin key, in super-bin-local coordinates: x0, the
+// width minus one, y0, the height minus one (log2s bits each after the 8-bit
+// super-bin id).  A lane without an item gets a row offset no tile matches.
+struct LocalRect {
+  uint32_t x0, wx, y0, wy;
+};
+
+__device__ __forceinline__ LocalRect key_rect(uint32_t key, int log2s, bool valid) {
+  const uint32_t m = (1u << log2s) - 1u;
+  LocalRect r;
+  r.x0 = (key >> 8) & m;
+  r.wx = ((key >> (8 + log2s)) & m) - r.x0;
+  r.y0 = valid ? (key >> (8 + 2 * log2s)) & m : 0xFFFFu;
+  r.wy = ((key >> (8 + 3 * log2s)) & m) - ((key >> (8 + 2 * log2s)) & m);
+  return r;
+}
+
+// The tiles of a super-bin are taken in blocks of up to 64 (lane j of a wave
+// stands for local tile 64 tb + j, row-major in the super-bin): one block for
+// S <= 8, S^2 / 64 blocks above.  Rows of block tb: [row0, row0 + nrows).
+struct TileBlock {
+  int row0, nrows;
+};
+
+__device__ __forceinline__ TileBlock tile_block(int log2s, int tb) {
+  const int S = 1 << log2s, per = S * S < 64 ? S : 64 / S;
+  return TileBlock{tb * per, per};
+}
+
+__device__ __forceinline__ int tile_blocks(int log2s) { return log2s <= 3 ? 1 : (1 << (2 * log2s)) / 64; }
+
+// Global tile id of local tile (lx, ly) of super-bin sb, or -1 outside the grid.
+__device__ __forceinline__ int tile_of(int sb, int SX, int log2s, int lx, int ly, int TX, int TY) {
+  const int tx = ((sb % SX) << log2s) + lx, ty = ((sb / SX) << log2s) + ly;
+  return tx < TX && ty < TY ? ty * TX + tx : -1;
+}
+
+// Items [i0, i1) (0 < i1 - i0 <= kPieceItems, wave-uniform) of a piece: the
+// number covering each tile of block tb (lane j: tile j of the block).
+__device__ uint32_t piece_tile_counts(const uint32_t *__restrict__ keys, uint32_t i0, uint32_t i1, int log2s,
+                                      TileBlock blk, int lane) {
+  const int S = 1 << log2s;
+  const uint32_t last = i1 - 1u;
+  uint32_t k[kPieceItems / 64];
+#pragma unroll
+  for (int q = 0; q < kPieceItems / 64; q++) k[q] = keys[min(i0 + 64u * q + lane, last)];
+  uint32_t cnt = 0;
+#pragma unroll
+  for (int q = 0; q < kPieceItems / 64; q++) {
+    const uint32_t c0 = i0 + 64u * q;
+    if (c0 >= i1) break;
+    const LocalRect r = key_rect(k[q], log2s, c0 + lane < i1);
+    for (int ry = 0; ry < blk.nrows; ry++) {
+      const bool rowhit = (uint32_t)(blk.row0 + ry) - r.y0 <= r.wy;
+      if (__ballot(rowhit) == 0ull) continue;
+      for (int lx = 0; lx < S; lx++) {
+        const uint64_t b = __ballot(rowhit && (uint32_t)lx - r.x0 <= r.wx);
+        if (lane == ry * S + lx) cnt += (uint32_t)__popcll(b);
+      }
+    }
+  }
+  return cnt;
+}
+
+// Piece p's list items, wave-uniform: [i0, i1) of super-bin sb.
+struct Piece {
+  int sb;
+  uint32_t i0, i1;
+};
+
+__device__ __forceinline__ Piece piece_of(const PieceTable &pt, uint32_t p) {
+  const int sb = piece_superbin(pt, p);
+  const uint32_t i0 = pt.beg[sb] + (p - pt.pf[sb]) * kPieceItems;
+  const uint32_t i1 = min(i0 + kPieceItems, pt.end[sb]);
+  return Piece{__builtin_amdgcn_readfirstlane(sb), (uint32_t)__builtin_amdgcn_readfirstlane(i0),
+               (uint32_t)__builtin_amdgcn_readfirstlane(i1)};
+}
+
+// pcnt[p * S^2 + j] = items of piece p covering local tile j of its super-bin.
+__global__ __launch_bounds__(kPieceWaves * 64) void tile_count_kernel(const uint32_t *__restrict__ sb_keys,
+                                                                      const uint32_t *__restrict__ sb_tot, int log2s,
+                                                                      uint32_t *__restrict__ pcnt) {
+  __shared__ PieceTable pt;
+  __shared__ uint32_t lds4[4];
+  build_piece_table(pt, sb_tot, lds4);
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int S2 = 1 << (2 * log2s);
+  const uint32_t np = pt.pf[kRadixBins];
+  const uint32_t p0 = __builtin_amdgcn_readfirstlane(blockIdx.x * kPieceWaves + w);
+  for (uint32_t p = p0; p < np; p += gridDim.x * kPieceWaves) {
+    const Piece pc = piece_of(pt, p);
+    for (int tb = 0; tb < tile_blocks(log2s); tb++) {
+      const uint32_t c = piece_tile_counts(sb_keys, pc.i0, pc.i1, log2s, tile_block(log2s, tb), lane);
+      const int j = 64 * tb + lane;
+      if (j < S2) pcnt[(size_t)p * S2 + j] = c;
+    }
+  }
+}
+
+// One workgroup per super-bin, one wave per tile at a time: pcnt becomes, per
+// tile, the count of the super-bin's earlier pieces (exclusive scan over the
+// pieces); counts[tile] = the tile's total.
+__global__ __launch_bounds__(256) void tile_piece_scan_kernel(const uint32_t *__restrict__ sb_tot, int TX, int TY,
+                                                              int SX, int log2s,
+                                                              uint32_t *__restrict__ pcnt,
+                                                              uint32_t *__restrict__ counts) {
+  __shared__ PieceTable pt;
+  __shared__ uint32_t lds4[4];
+  build_piece_table(pt, sb_tot, lds4);
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int sb = blockIdx.x, S = 1 << log2s, S2 = S * S;
+  const uint32_t P0 = pt.pf[sb], npc = pt.pf[sb + 1] - P0;
+  for (int j = w; j < S2; j += 4) {
+    uint32_t carry = 0;
+    for (uint32_t k0 = 0; k0 < npc; k0 += 64) {
+      const uint32_t k = k0 + lane;
+      uint32_t *q = pcnt + (size_t)(P0 + k) * S2 + j;
+      const uint32_t v = k < npc ? *q : 0u;
+      const uint32_t inc = wave_inclusive_scan(v, lane);
+      if (k < npc) *q = carry + inc - v;
+      carry += __shfl(inc, 63, 64);
+    }
+    const int t = tile_of(sb, SX, log2s, j & (S - 1), j >> log2s, TX, TY);
+    if (lane == 0 && t >= 0) counts[t] = carry;
+  }
+}
+
+// One block: tile offsets (exclusive scan of the counts, in place), the tile
+// ranges, the instance count (the sum of the per-block tiles-touched totals:
+// exact also when the super-bin instances overflowed the capacity and the
+// counts are incomplete) and the status word.  On overflow every range is
+// empty.
 __global__ __launch_bounds__(256) void tile_scan_kernel(uint32_t *__restrict__ counts, int T,
                                                         const uint32_t *__restrict__ area_part, int nparts,
                                                         uint32_t cap, uint32_t *__restrict__ m_out,
-                                                        int32_t *__restrict__ status) {
+                                                        int32_t *__restrict__ status, uint2 *__restrict__ ranges) {
   __shared__ uint32_t lds4[4];
   uint32_t msum = 0;
   for (int i = threadIdx.x; i < nparts; i += 256) msum += area_part[i];
   uint32_t mtot;
   block_exclusive_scan(msum, lds4, mtot);
+  const bool over = mtot > cap;
   // one block scan: thread k sums, then rewrites, a contiguous chunk of counts
   const int per = (T + 255) / 256, i0 = threadIdx.x * per;
   uint32_t s = 0;
@@ -413,61 +537,71 @@ __global__ __launch_bounds__(256) void tile_scan_kernel(uint32_t *__restrict__ c
     if (i0 + k < T) {
       const uint32_t v = counts[i0 + k];
       counts[i0 + k] = ex;
+      ranges[i0 + k] = over ? make_uint2(0u, 0u) : make_uint2(ex, ex + v);
       ex += v;
     }
   if (threadIdx.x == 0) {
-    const uint32_t m = mtot;
-    m_out[0] = m;
-    status[kStatusMLo] = (int32_t)m;
+    m_out[0] = mtot;
+    status[kStatusMLo] = (int32_t)mtot;
     status[kStatusMHi] = 0;
-    status[kStatusFlags] = m > cap ? kFlagOverflow : 0;
+    status[kStatusFlags] = over ? kFlagOverflow : 0;
   }
 }
 
-__global__ __launch_bounds__(256) void tile_write_kernel(const uint32_t *__restrict__ sb_keys,
-                                                         const uint32_t *__restrict__ sb_list,
-                                                         const uint32_t *__restrict__ hist_scan, int nblocks,
-                                                         const uint32_t *__restrict__ ms_dev, int TX, int T, int SX,
-                                                         int log2s, const uint32_t *__restrict__ tile_off,
-                                                         const uint32_t *__restrict__ m_dev, uint32_t cap,
-                                                         uint32_t *__restrict__ out_tiles,
-                                                         uint32_t *__restrict__ out_gauss, uint2 *__restrict__ ranges) {
+__global__ __launch_bounds__(kPieceWaves * 64) void tile_write_kernel(
+    const uint32_t *__restrict__ sb_keys, const uint32_t *__restrict__ sb_list, const uint32_t *__restrict__ sb_tot,
+    int TX, int TY, int SX, int log2s,
+    const uint32_t *__restrict__ pcnt, const uint32_t *__restrict__ tile_off, const uint32_t *__restrict__ m_dev,
+    uint32_t cap, uint32_t *__restrict__ out_gauss) {
+  __shared__ PieceTable pt;
   __shared__ uint32_t lds4[4];
-  const int t = blockIdx.x;
-  const uint32_t m = m_dev[0];
-  if (m > cap) {  // overflow: empty tiles, nothing written
-    if (threadIdx.x == 0) ranges[t] = make_uint2(0u, 0u);
-    return;
-  }
-  const uint32_t tx = t % TX, ty = t / TX;
-  const uint32_t lx = tx & ((1u << log2s) - 1u), ly = ty & ((1u << log2s) - 1u);
-  const uint2 rg =
-      superbin_range(hist_scan, nblocks, (int)(ty >> log2s) * SX + (int)(tx >> log2s), min(ms_dev[0], cap));
-  const uint32_t start = tile_off[t];
-  uint32_t run = start;
-  for (uint32_t c0 = rg.x; c0 < rg.y; c0 += 256u * kTileItems) {
-    // thread k takes the contiguous items c0 + kTileItems k + j, so the
-    // block-wide prefix of per-thread hit counts keeps the list order
-    const uint32_t i0 = c0 + threadIdx.x * kTileItems;
-    bool hit[kTileItems];
-    uint32_t c = 0;
+  if (m_dev[0] > cap) return;  // overflow: nothing written, the ranges are empty (uniform per launch)
+  build_piece_table(pt, sb_tot, lds4);
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int S = 1 << log2s, S2 = S * S;
+  const uint32_t np = pt.pf[kRadixBins];
+  const uint32_t p0 = __builtin_amdgcn_readfirstlane(blockIdx.x * kPieceWaves + w);
+  for (uint32_t p = p0; p < np; p += gridDim.x * kPieceWaves) {
+    const Piece pc = piece_of(pt, p);
+    const uint32_t last = pc.i1 - 1u;
+    uint32_t kv[kPieceItems / 64], vv[kPieceItems / 64];
 #pragma unroll
-    for (int j = 0; j < kTileItems; j++) {
-      hit[j] = i0 + j < rg.y && key_covers(sb_keys[i0 + j], log2s, lx, ly);
-      c += hit[j];
+    for (int q = 0; q < kPieceItems / 64; q++) {
+      const uint32_t i = min(pc.i0 + 64u * q + lane, last);
+      kv[q] = sb_keys[i];
+      vv[q] = sb_list[i];
     }
-    uint32_t total;
-    uint32_t pos = run + block_exclusive_scan(c, lds4, total);
+    for (int tb = 0; tb < tile_blocks(log2s); tb++) {
+      const TileBlock blk = tile_block(log2s, tb);
+      // lane j: next output position of tile j of the block
+      const int j = 64 * tb + lane;
+      const int tj = j < S2 ? tile_of(pc.sb, SX, log2s, j & (S - 1), j >> log2s, TX, TY) : -1;
+      uint32_t run = tj >= 0 ? tile_off[tj] + pcnt[(size_t)p * S2 + j] : 0u;
 #pragma unroll
-    for (int j = 0; j < kTileItems; j++)
-      if (hit[j]) {
-        out_tiles[pos] = (uint32_t)t;
-        out_gauss[pos] = sb_list[i0 + j];
-        pos++;
+      for (int q = 0; q < kPieceItems / 64; q++) {
+        const uint32_t c0 = pc.i0 + 64u * q;
+        if (c0 >= pc.i1) break;
+        const LocalRect r = key_rect(kv[q], log2s, c0 + lane < pc.i1);
+        for (int ry = 0; ry < blk.nrows; ry++) {
+          const bool rowhit = (uint32_t)(blk.row0 + ry) - r.y0 <= r.wy;
+          if (__ballot(rowhit) == 0ull) continue;
+          for (int lx = 0; lx < S; lx++) {
+            const bool hit = rowhit && (uint32_t)lx - r.x0 <= r.wx;
+            const uint64_t b = __ballot(hit);
+            if (b == 0ull) continue;
+            const int jj = ry * S + lx;  // lane of the tile in this block
+            const uint32_t base = __builtin_amdgcn_readlane(run, jj);
+            if (hit) {
+              const uint32_t rank =
+                  __builtin_amdgcn_mbcnt_hi((uint32_t)(b >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)b, 0u));
+              out_gauss[base + rank] = vv[q];
+            }
+            if (lane == jj) run += (uint32_t)__popcll(b);
+          }
+        }
       }
-    run += total;
+    }
   }
-  if (threadIdx.x == 0) ranges[t] = make_uint2(start, run);
 }
 
 
@@ -495,23 +629,15 @@ void launch_scan(const uint32_t *in, uint32_t *out, uint32_t n, uint32_t *partia
 uint32_t radix_blocks(uint64_t n) { return n ? cdiv(n, kSortItems) : 1; }
 uint32_t scan_partials_needed(uint64_t n) { return n ? cdiv(n, kScanItems) : 1; }
 
-// One stable 8-bit pass (keys/vals in -> out) over min(n_host, *n_dev) items.
+// One stable 8-bit pass (keys/vals in -> out) over min(n_host, *n_dev) items;
+// tot receives the 256 digit totals.
 void launch_radix_pass(const uint32_t *kin, const uint32_t *vin, uint32_t *kout, uint32_t *vout, uint32_t n_host,
-                       const uint32_t *n_dev, int shift, uint32_t *hist, uint32_t *partials, hipStream_t st,
-                       bool digit_major) {
+                       const uint32_t *n_dev, int shift, uint32_t *hist, uint32_t *tot, hipStream_t st) {
   const uint32_t nb = radix_blocks(n_host);
-  if (!digit_major && nb <= kRadixLocalBlocks) {
-    // two launches: each scatter block sums the (few) block histograms itself
-    radix_hist_kernel<true><<<nb, kSortThreads, 0, st>>>(kin, n_host, n_dev, shift, hist, (int)nb);
-    radix_scatter_kernel<true><<<nb, kSortThreads, 0, st>>>(kin, vin, kout, vout, n_host, n_dev, shift, hist, (int)nb);
-    return;
-  }
-  radix_hist_kernel<false><<<nb, kSortThreads, 0, st>>>(kin, n_host, n_dev, shift, hist, (int)nb);
-  launch_scan(hist, hist, nb * kRadixBins, partials, nullptr, st);
-  radix_scatter_kernel<false><<<nb, kSortThreads, 0, st>>>(kin, vin, kout, vout, n_host, n_dev, shift, hist, (int)nb);
+  radix_hist_kernel<<<nb, kSortThreads, 0, st>>>(kin, n_host, n_dev, shift, hist);
+  radix_colscan_kernel<<<kRadixBins, kSortThreads, 0, st>>>(hist, n_host, n_dev, tot);
+  radix_scatter_kernel<<<nb, kSortThreads, 0, st>>>(kin, vin, kout, vout, n_host, n_dev, shift, hist, tot);
 }
-
-
 
 int superbin_log2(int TX, int TY) {
   int l = 0;
@@ -535,19 +661,27 @@ void launch_superbin_expand(const uint32_t *sorted_g, const ushort4 *rects, uint
   if (n) emit_kernel<<<cdiv(n, 256), 256, 0, st>>>(sorted_g, rects, offs, n, cap, SX, log2s, ka, va);
 }
 
+static uint32_t piece_bound(uint32_t cap) { return cap / kPieceItems + kRadixBins; }
+
+size_t tile_piece_words(int TX, int TY, uint32_t cap) {
+  return (size_t)piece_bound(cap) << (2 * superbin_log2(TX, TY));
+}
+
 void launch_tile_lists(uint32_t n, uint32_t cap, int TX, int TY, uint32_t *ka, uint32_t *va, uint32_t *kb,
-                       uint32_t *vb, uint32_t *counts, uint32_t *hist, uint32_t *partials, const uint32_t *ms_dev,
-                       const uint32_t *area_part, uint32_t *m_out, int32_t *status, uint2 *ranges, hipStream_t st) {
+                       uint32_t *vb, uint32_t *counts, uint32_t *pcnt, uint32_t *hist, uint32_t *tot,
+                       const uint32_t *ms_dev, const uint32_t *area_part, uint32_t *m_out, int32_t *status,
+                       uint2 *ranges, hipStream_t st) {
   const int log2s = superbin_log2(TX, TY);
-  const int SX = (int)cdiv(TX, 1u << log2s);
+  const int SX = (int)cdiv(TX, 1u << log2s), SY = (int)cdiv(TY, 1u << log2s);
   const int T = TX * TY;
-  // one stable 8-bit pass: super-bin-major, depth order within each super-bin
-  launch_radix_pass(ka, va, kb, vb, cap, ms_dev, 0, hist, partials, st, true);  // ranges read the scanned histogram
-  const int nb = (int)radix_blocks(cap);
-  tile_count_kernel<<<T, 256, 0, st>>>(kb, hist, nb, ms_dev, cap, TX, SX, log2s, counts);
-  tile_scan_kernel<<<1, 256, 0, st>>>(counts, T, area_part, (int)area_parts(n), cap, m_out, status);
-  tile_write_kernel<<<T, 256, 0, st>>>(kb, vb, hist, nb, ms_dev, TX, T, SX, log2s, counts, m_out, cap, ka, va,
-                                       ranges);
+  // one stable 8-bit pass: super-bin-major, depth order within each super-bin;
+  // tot = the super-bin list lengths
+  launch_radix_pass(ka, va, kb, vb, cap, ms_dev, 0, hist, tot, st);
+  const uint32_t gp = cdiv(piece_bound(cap), kPieceWaves), grid = gp < (uint32_t)kPieceGrid ? gp : (uint32_t)kPieceGrid;
+  tile_count_kernel<<<grid, kPieceWaves * 64, 0, st>>>(kb, tot, log2s, pcnt);
+  tile_piece_scan_kernel<<<SX * SY, 256, 0, st>>>(tot, TX, TY, SX, log2s, pcnt, counts);
+  tile_scan_kernel<<<1, 256, 0, st>>>(counts, T, area_part, (int)area_parts(n), cap, m_out, status, ranges);
+  tile_write_kernel<<<grid, kPieceWaves * 64, 0, st>>>(kb, vb, tot, TX, TY, SX, log2s, pcnt, counts, m_out, cap, va);
 }
 
 

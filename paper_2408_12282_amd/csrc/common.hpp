@@ -15,7 +15,6 @@ constexpr int kRadixBins = 1 << kRadixBits;
 constexpr int kSortThreads = 256;
 constexpr int kSortRounds = 8;                     // keys per thread per radix block
 constexpr int kSortItems = kSortThreads * kSortRounds;
-constexpr int kRadixLocalBlocks = 512;           // up to this many blocks a pass skips the separate scan
 constexpr int kMaxSuperbinLog2 = 6;              // super-bins of up to 64 x 64 tiles
 constexpr int kScanThreads = 256;
 constexpr int kScanItems = kScanThreads * 4;

@@ -26,24 +26,25 @@ void launch_scan(const uint32_t *in, uint32_t *out, uint32_t n, uint32_t *partia
                  hipStream_t st);
 uint32_t radix_blocks(uint64_t n);
 uint32_t scan_partials_needed(uint64_t n);
-// One stable 8-bit pass.  digit_major: leave the scanned digit-major histogram
-// in hist (starts of every digit's output run); otherwise small inputs take a
-// two-launch form that does not.
+// One stable 8-bit pass over min(n_host, *n_dev) items (n_dev may be null):
+// block-major digit counts in hist (radix_blocks(n_host) x 256), the 256
+// digit totals in tot.
 void launch_radix_pass(const uint32_t *kin, const uint32_t *vin, uint32_t *kout, uint32_t *vout, uint32_t n_host,
-                       const uint32_t *n_dev, int shift, uint32_t *hist, uint32_t *partials, hipStream_t st,
-                       bool digit_major);
+                       const uint32_t *n_dev, int shift, uint32_t *hist, uint32_t *tot, hipStream_t st);
 // Tile lists (Sec. 3.1 binning): super-bin expansion of the depth-sorted
 // Gaussians, then the stable super-bin pass and the per-tile filtering into
-// tile-major (Gaussian index, tile id) lists with their ranges and the status word.
+// tile-major Gaussian-index lists with their ranges and the status word.
 int superbin_log2(int TX, int TY);
 bool superbin_supported(int TX, int TY);
 uint32_t area_parts(uint32_t n);
+size_t tile_piece_words(int TX, int TY, uint32_t cap);  // per-piece tile counts of the tile-list kernels
 void launch_superbin_expand(const uint32_t *sorted_g, const ushort4 *rects, uint32_t n, uint32_t cap, int TX, int TY,
                             uint32_t *tt, uint32_t *offs, uint32_t *ka, uint32_t *va, uint32_t *partials,
                             uint32_t *ms_dev, uint32_t *area_part, hipStream_t st);
 void launch_tile_lists(uint32_t n, uint32_t cap, int TX, int TY, uint32_t *ka, uint32_t *va, uint32_t *kb,
-                       uint32_t *vb, uint32_t *counts, uint32_t *hist, uint32_t *partials, const uint32_t *ms_dev,
-                       const uint32_t *area_part, uint32_t *m_out, int32_t *status, uint2 *ranges, hipStream_t st);
+                       uint32_t *vb, uint32_t *counts, uint32_t *pcnt, uint32_t *hist, uint32_t *tot,
+                       const uint32_t *ms_dev, const uint32_t *area_part, uint32_t *m_out, int32_t *status,
+                       uint2 *ranges, hipStream_t st);
 
 template <int C>
 void launch_composite_fwd_t(const uint2 *ranges, const uint32_t *sorted_g, const float *records, const short4 *boxes,

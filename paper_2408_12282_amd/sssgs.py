@@ -63,7 +63,7 @@ def make_options(precision: int, accumulate: bool = False, radiance_features: bo
 class Layout(ct.Structure):
     _fields_ = [("records", ct.c_size_t), ("rec_stride", ct.c_int32), ("depth_keys", ct.c_size_t),
                 ("rects", ct.c_size_t), ("radii", ct.c_size_t), ("tile_ranges", ct.c_size_t),
-                ("sorted_gauss", ct.c_size_t), ("sorted_tiles", ct.c_size_t), ("t_final", ct.c_size_t),
+                ("sorted_gauss", ct.c_size_t), ("t_final", ct.c_size_t),
                 ("n_contrib", ct.c_size_t), ("status", ct.c_size_t), ("boxes", ct.c_size_t)]
 
 
