@@ -27,6 +27,26 @@ __device__ __forceinline__ uint32_t wave_inclusive_scan(uint32_t v, int lane) {
   return v;
 }
 
+// Exclusive scan over a block of NW waves; lds holds NW words.  Returns the
+// block total in `total`.
+template <int NW>
+__device__ __forceinline__ uint32_t block_exclusive_scan_w(uint32_t v, uint32_t *lds, uint32_t &total) {
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const uint32_t inc = wave_inclusive_scan(v, lane);
+  if (lane == 63) lds[w] = inc;
+  __syncthreads();
+  uint32_t off = 0, tot = 0;
+#pragma unroll
+  for (int k = 0; k < NW; k++) {
+    const uint32_t c = lds[k];
+    off += k < w ? c : 0u;
+    tot += c;
+  }
+  total = tot;
+  __syncthreads();
+  return off + inc - v;
+}
+
 // Exclusive scan over a 256-thread block; returns the block total in `total`.
 __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t *lds4, uint32_t &total) {
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
@@ -216,11 +236,11 @@ __global__ __launch_bounds__(kSortThreads) void radix_scatter_kernel(
   for (int r = 0; r < kSortRounds; r++) {
     const bool active = r * kSortThreads + t < (int)cnt;
     const uint32_t d = (key[r] >> shift) & (kRadixBins - 1);
-    uint64_t match = __ballot(active);
+    uint64_t match = __builtin_amdgcn_ballot_w64(active);
 #pragma unroll
     for (int b = 0; b < kRadixBits; b++) {
       const bool bit = (d >> b) & 1u;
-      const uint64_t bl = __ballot(bit);
+      const uint64_t bl = __builtin_amdgcn_ballot_w64(bit);
       match &= bit ? bl : ~bl;
     }
     const uint32_t rank = __popcll(match & lt);
@@ -438,13 +458,54 @@ __device__ uint32_t piece_tile_counts(const uint32_t *__restrict__ keys, uint32_
     const LocalRect r = key_rect(k[q], log2s, c0 + lane < i1);
     for (int ry = 0; ry < blk.nrows; ry++) {
       const bool rowhit = (uint32_t)(blk.row0 + ry) - r.y0 <= r.wy;
-      if (__ballot(rowhit) == 0ull) continue;
+      if (__builtin_amdgcn_ballot_w64(rowhit) == 0ull) continue;
       for (int lx = 0; lx < S; lx++) {
-        const uint64_t b = __ballot(rowhit && (uint32_t)lx - r.x0 <= r.wx);
+        const uint64_t b = __builtin_amdgcn_ballot_w64(rowhit && (uint32_t)lx - r.x0 <= r.wx);
         if (lane == ry * S + lx) cnt += (uint32_t)__popcll(b);
       }
     }
   }
+  return cnt;
+}
+
+// The same for super-bins of S = 2^L <= 8 tiles on a side (lane j = tile j):
+// per 64-item chunk one ballot per column and per row, and per tile the
+// intersection of the two lane masks, counted in scalar registers.
+template <int L>
+__device__ __forceinline__ uint32_t piece_tile_counts_t(const uint32_t *__restrict__ keys, uint32_t i0, uint32_t i1,
+                                                        int lane) {
+  constexpr int S = 1 << L, S2 = S * S;
+  constexpr uint32_t m = S - 1;
+  const uint32_t last = i1 - 1u;
+  uint32_t k[kPieceItems / 64];
+#pragma unroll
+  for (int q = 0; q < kPieceItems / 64; q++) k[q] = keys[min(i0 + 64u * q + lane, last)];
+  uint32_t sc[S2];
+#pragma unroll
+  for (int j = 0; j < S2; j++) sc[j] = 0;
+#pragma unroll
+  for (int q = 0; q < kPieceItems / 64; q++) {
+    const uint32_t c0 = i0 + 64u * q;
+    if (c0 < i1) {
+      const uint32_t key = k[q];
+      const bool valid = c0 + lane < i1;
+      const uint32_t x0 = (key >> 8) & m, x1 = (key >> (8 + L)) & m;
+      const uint32_t y0 = (key >> (8 + 2 * L)) & m, y1 = (key >> (8 + 3 * L)) & m;
+      uint64_t col[S];
+#pragma unroll
+      for (int c = 0; c < S; c++) col[c] = __builtin_amdgcn_ballot_w64(x0 <= (uint32_t)c && (uint32_t)c <= x1);
+#pragma unroll
+      for (int r = 0; r < S; r++) {
+        const uint64_t row = __builtin_amdgcn_ballot_w64(valid && y0 <= (uint32_t)r && (uint32_t)r <= y1);
+        if (row == 0ull) continue;
+#pragma unroll
+        for (int c = 0; c < S; c++) sc[r * S + c] += (uint32_t)__popcll(col[c] & row);
+      }
+    }
+  }
+  uint32_t cnt = 0;
+#pragma unroll
+  for (int j = 0; j < S2; j++) cnt = lane == j ? sc[j] : cnt;
   return cnt;
 }
 
@@ -463,6 +524,9 @@ __device__ __forceinline__ Piece piece_of(const PieceTable &pt, uint32_t p) {
 }
 
 // pcnt[p * S^2 + j] = items of piece p covering local tile j of its super-bin.
+// L >= 0: super-bins of 2^L tiles on a side (L <= 3); L < 0: any size
+// (log2s), tiles in blocks of 64.
+template <int L>
 __global__ __launch_bounds__(kPieceWaves * 64) void tile_count_kernel(const uint32_t *__restrict__ sb_keys,
                                                                       const uint32_t *__restrict__ sb_tot, int log2s,
                                                                       uint32_t *__restrict__ pcnt) {
@@ -475,20 +539,25 @@ __global__ __launch_bounds__(kPieceWaves * 64) void tile_count_kernel(const uint
   const uint32_t p0 = __builtin_amdgcn_readfirstlane(blockIdx.x * kPieceWaves + w);
   for (uint32_t p = p0; p < np; p += gridDim.x * kPieceWaves) {
     const Piece pc = piece_of(pt, p);
-    for (int tb = 0; tb < tile_blocks(log2s); tb++) {
-      const uint32_t c = piece_tile_counts(sb_keys, pc.i0, pc.i1, log2s, tile_block(log2s, tb), lane);
-      const int j = 64 * tb + lane;
-      if (j < S2) pcnt[(size_t)p * S2 + j] = c;
+    if constexpr (L >= 0) {
+      const uint32_t c = piece_tile_counts_t<L>(sb_keys, pc.i0, pc.i1, lane);
+      if (lane < (1 << (2 * L))) pcnt[(size_t)p * (1 << (2 * L)) + lane] = c;
+    } else {
+      for (int tb = 0; tb < tile_blocks(log2s); tb++) {
+        const uint32_t c = piece_tile_counts(sb_keys, pc.i0, pc.i1, log2s, tile_block(log2s, tb), lane);
+        const int j = 64 * tb + lane;
+        if (j < S2) pcnt[(size_t)p * S2 + j] = c;
+      }
     }
   }
 }
 
-// One workgroup per super-bin, one wave per tile at a time: pcnt becomes, per
-// tile, the count of the super-bin's earlier pieces (exclusive scan over the
-// pieces); counts[tile] = the tile's total.
+// One workgroup per super-bin; a wave takes eight tiles at a time (their
+// loads in flight together): pcnt becomes, per tile, the count of the
+// super-bin's earlier pieces (exclusive scan over the pieces); counts[tile] =
+// the tile's total.
 __global__ __launch_bounds__(256) void tile_piece_scan_kernel(const uint32_t *__restrict__ sb_tot, int TX, int TY,
-                                                              int SX, int log2s,
-                                                              uint32_t *__restrict__ pcnt,
+                                                              int SX, int log2s, uint32_t *__restrict__ pcnt,
                                                               uint32_t *__restrict__ counts) {
   __shared__ PieceTable pt;
   __shared__ uint32_t lds4[4];
@@ -496,51 +565,92 @@ __global__ __launch_bounds__(256) void tile_piece_scan_kernel(const uint32_t *__
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int sb = blockIdx.x, S = 1 << log2s, S2 = S * S;
   const uint32_t P0 = pt.pf[sb], npc = pt.pf[sb + 1] - P0;
-  for (int j = w; j < S2; j += 4) {
-    uint32_t carry = 0;
+  constexpr int G = 8;
+  for (int j0 = G * w; j0 < S2; j0 += G * 4) {
+    uint32_t carry[G];
+#pragma unroll
+    for (int g = 0; g < G; g++) carry[g] = 0;
     for (uint32_t k0 = 0; k0 < npc; k0 += 64) {
-      const uint32_t k = k0 + lane;
-      uint32_t *q = pcnt + (size_t)(P0 + k) * S2 + j;
-      const uint32_t v = k < npc ? *q : 0u;
-      const uint32_t inc = wave_inclusive_scan(v, lane);
-      if (k < npc) *q = carry + inc - v;
-      carry += __shfl(inc, 63, 64);
+      const uint32_t k = k0 + lane, kc = min(k, npc - 1u);
+      uint32_t v[G];
+#pragma unroll
+      for (int g = 0; g < G; g++) v[g] = j0 + g < S2 ? pcnt[(size_t)(P0 + kc) * S2 + j0 + g] : 0u;
+#pragma unroll
+      for (int g = 0; g < G; g++) {
+        const uint32_t x = k < npc ? v[g] : 0u;
+        const uint32_t inc = wave_inclusive_scan(x, lane);
+        if (k < npc && j0 + g < S2) pcnt[(size_t)(P0 + k) * S2 + j0 + g] = carry[g] + inc - x;
+        carry[g] += __shfl(inc, 63, 64);
+      }
     }
-    const int t = tile_of(sb, SX, log2s, j & (S - 1), j >> log2s, TX, TY);
-    if (lane == 0 && t >= 0) counts[t] = carry;
+#pragma unroll
+    for (int g = 0; g < G; g++) {
+      const int j = j0 + g;
+      if (j < S2) {
+        const int t = tile_of(sb, SX, log2s, j & (S - 1), j >> log2s, TX, TY);
+        if (lane == 0 && t >= 0) counts[t] = carry[g];
+      }
+    }
   }
 }
 
-// One block: tile offsets (exclusive scan of the counts, in place), the tile
-// ranges, the instance count (the sum of the per-block tiles-touched totals:
-// exact also when the super-bin instances overflowed the capacity and the
-// counts are incomplete) and the status word.  On overflow every range is
-// empty.
-__global__ __launch_bounds__(256) void tile_scan_kernel(uint32_t *__restrict__ counts, int T,
-                                                        const uint32_t *__restrict__ area_part, int nparts,
-                                                        uint32_t cap, uint32_t *__restrict__ m_out,
-                                                        int32_t *__restrict__ status, uint2 *__restrict__ ranges) {
-  __shared__ uint32_t lds4[4];
+// One block of 1024 threads: tile offsets (exclusive scan of the counts, in
+// place, 4096 tiles per step staged through LDS so that global accesses are
+// coalesced), the tile ranges, the instance count (the sum of the per-block
+// tiles-touched totals: exact also when the super-bin instances overflowed
+// the capacity and the counts are incomplete) and the status word.  On
+// overflow every range is empty.
+constexpr int kTileScanThreads = 1024;
+
+__global__ __launch_bounds__(kTileScanThreads) void tile_scan_kernel(uint32_t *__restrict__ counts, int T,
+                                                                     const uint32_t *__restrict__ area_part,
+                                                                     int nparts, uint32_t cap,
+                                                                     uint32_t *__restrict__ m_out,
+                                                                     int32_t *__restrict__ status,
+                                                                     uint2 *__restrict__ ranges) {
+  constexpr int NT = kTileScanThreads, NW = NT / 64;
+  __shared__ uint32_t buf[4 * NT];
+  __shared__ uint32_t lds[NW];
+  const int t = threadIdx.x;
   uint32_t msum = 0;
-  for (int i = threadIdx.x; i < nparts; i += 256) msum += area_part[i];
+  for (int i = t; i < nparts; i += NT) msum += area_part[i];
   uint32_t mtot;
-  block_exclusive_scan(msum, lds4, mtot);
+  block_exclusive_scan_w<NW>(msum, lds, mtot);
   const bool over = mtot > cap;
-  // one block scan: thread k sums, then rewrites, a contiguous chunk of counts
-  const int per = (T + 255) / 256, i0 = threadIdx.x * per;
-  uint32_t s = 0;
-  for (int k = 0; k < per; k++)
-    if (i0 + k < T) s += counts[i0 + k];
-  uint32_t total;
-  uint32_t ex = block_exclusive_scan(s, lds4, total);
-  for (int k = 0; k < per; k++)
-    if (i0 + k < T) {
-      const uint32_t v = counts[i0 + k];
-      counts[i0 + k] = ex;
-      ranges[i0 + k] = over ? make_uint2(0u, 0u) : make_uint2(ex, ex + v);
-      ex += v;
+  uint32_t carry = 0;
+  for (int c0 = 0; c0 < T; c0 += 4 * NT) {
+    uint32_t orig[4];
+#pragma unroll
+    for (int k = 0; k < 4; k++) {
+      const int i = c0 + k * NT + t;
+      orig[k] = i < T ? counts[i] : 0u;
+      buf[k * NT + t] = orig[k];
     }
-  if (threadIdx.x == 0) {
+    __syncthreads();
+    uint32_t v[4];
+#pragma unroll
+    for (int k = 0; k < 4; k++) v[k] = buf[4 * t + k];
+    uint32_t total;
+    uint32_t ex = block_exclusive_scan_w<NW>((v[0] + v[1]) + (v[2] + v[3]), lds, total);
+#pragma unroll
+    for (int k = 0; k < 4; k++) {
+      buf[4 * t + k] = ex;
+      ex += v[k];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < 4; k++) {
+      const int i = c0 + k * NT + t;
+      if (i < T) {
+        const uint32_t o = carry + buf[k * NT + t];
+        counts[i] = o;
+        ranges[i] = over ? make_uint2(0u, 0u) : make_uint2(o, o + orig[k]);
+      }
+    }
+    carry += total;
+    __syncthreads();
+  }
+  if (t == 0) {
     m_out[0] = mtot;
     status[kStatusMLo] = (int32_t)mtot;
     status[kStatusMHi] = 0;
@@ -548,11 +658,70 @@ __global__ __launch_bounds__(256) void tile_scan_kernel(uint32_t *__restrict__ c
   }
 }
 
+// Writes piece p's items of super-bin-local tile j at the tile's offset plus
+// the piece's prefix plus the item's ballot rank, for super-bins of
+// S = 2^L <= 8 tiles on a side: the tiles' output positions are kept in
+// scalar registers.
+// Marks a loaded value as complete here.  Loads and stores share one
+// completion counter; without this the compiler may sink a load into a
+// branch and then, where branches merge, wait for every outstanding
+// operation (the stores included) before each store.  An empty asm that
+// takes the register as input and output makes it wait for the loads once,
+// before the stores start.
+__device__ __forceinline__ void settle(uint32_t &x) { asm volatile("" : "+v"(x)); }
+
+template <int L>
+__device__ __forceinline__ void write_piece_t(const uint32_t *__restrict__ keys, const uint32_t *__restrict__ vals,
+                                              uint32_t i0, uint32_t i1, uint32_t run, int lane,
+                                              uint32_t *__restrict__ out_gauss) {
+  constexpr int S = 1 << L, S2 = S * S;
+  constexpr uint32_t m = S - 1;
+  const uint32_t last = i1 - 1u;
+  uint32_t k[kPieceItems / 64], v[kPieceItems / 64];
+#pragma unroll
+  for (int q = 0; q < kPieceItems / 64; q++) {
+    const uint32_t i = min(i0 + 64u * q + lane, last);
+    k[q] = keys[i];
+    v[q] = vals[i];
+  }
+#pragma unroll
+  for (int q = 0; q < kPieceItems / 64; q++) {
+    settle(k[q]);
+    settle(v[q]);
+  }
+  uint32_t base[S2];
+#pragma unroll
+  for (int j = 0; j < S2; j++) base[j] = __builtin_amdgcn_readlane(run, j);
+#pragma unroll
+  for (int q = 0; q < kPieceItems / 64; q++) {
+    const uint32_t c0 = i0 + 64u * q;
+    if (c0 < i1) {
+      const uint32_t key = k[q];
+      const bool valid = c0 + lane < i1;
+      const uint32_t x0 = (key >> 8) & m, x1 = (key >> (8 + L)) & m;
+      const uint32_t y0 = (key >> (8 + 2 * L)) & m, y1 = (key >> (8 + 3 * L)) & m;
+#pragma unroll
+      for (int r = 0; r < S; r++) {
+        const bool rh = valid && y0 <= (uint32_t)r && (uint32_t)r <= y1;
+#pragma unroll
+        for (int c = 0; c < S; c++) {
+          const bool hit = rh && x0 <= (uint32_t)c && (uint32_t)c <= x1;
+          const uint64_t b = __builtin_amdgcn_ballot_w64(hit);
+          const uint32_t pos =
+              base[r * S + c] + __builtin_amdgcn_mbcnt_hi((uint32_t)(b >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)b, 0u));
+          if (hit) out_gauss[pos] = v[q];
+          base[r * S + c] += (uint32_t)__popcll(b);
+        }
+      }
+    }
+  }
+}
+
+template <int L>
 __global__ __launch_bounds__(kPieceWaves * 64) void tile_write_kernel(
     const uint32_t *__restrict__ sb_keys, const uint32_t *__restrict__ sb_list, const uint32_t *__restrict__ sb_tot,
-    int TX, int TY, int SX, int log2s,
-    const uint32_t *__restrict__ pcnt, const uint32_t *__restrict__ tile_off, const uint32_t *__restrict__ m_dev,
-    uint32_t cap, uint32_t *__restrict__ out_gauss) {
+    int TX, int TY, int SX, int log2s, const uint32_t *__restrict__ pcnt, const uint32_t *__restrict__ tile_off,
+    const uint32_t *__restrict__ m_dev, uint32_t cap, uint32_t *__restrict__ out_gauss) {
   __shared__ PieceTable pt;
   __shared__ uint32_t lds4[4];
   if (m_dev[0] > cap) return;  // overflow: nothing written, the ranges are empty (uniform per launch)
@@ -563,6 +732,13 @@ __global__ __launch_bounds__(kPieceWaves * 64) void tile_write_kernel(
   const uint32_t p0 = __builtin_amdgcn_readfirstlane(blockIdx.x * kPieceWaves + w);
   for (uint32_t p = p0; p < np; p += gridDim.x * kPieceWaves) {
     const Piece pc = piece_of(pt, p);
+    if constexpr (L >= 0) {
+      // lane j: first output position of tile j for this piece
+      const int tj = lane < S2 ? tile_of(pc.sb, SX, L, lane & (S - 1), lane >> L, TX, TY) : -1;
+      const uint32_t run = tj >= 0 ? tile_off[tj] + pcnt[(size_t)p * S2 + lane] : 0u;
+      write_piece_t<L>(sb_keys, sb_list, pc.i0, pc.i1, run, lane, out_gauss);
+      continue;
+    }
     const uint32_t last = pc.i1 - 1u;
     uint32_t kv[kPieceItems / 64], vv[kPieceItems / 64];
 #pragma unroll
@@ -570,6 +746,11 @@ __global__ __launch_bounds__(kPieceWaves * 64) void tile_write_kernel(
       const uint32_t i = min(pc.i0 + 64u * q + lane, last);
       kv[q] = sb_keys[i];
       vv[q] = sb_list[i];
+    }
+#pragma unroll
+    for (int q = 0; q < kPieceItems / 64; q++) {
+      settle(kv[q]);
+      settle(vv[q]);
     }
     for (int tb = 0; tb < tile_blocks(log2s); tb++) {
       const TileBlock blk = tile_block(log2s, tb);
@@ -584,10 +765,10 @@ __global__ __launch_bounds__(kPieceWaves * 64) void tile_write_kernel(
         const LocalRect r = key_rect(kv[q], log2s, c0 + lane < pc.i1);
         for (int ry = 0; ry < blk.nrows; ry++) {
           const bool rowhit = (uint32_t)(blk.row0 + ry) - r.y0 <= r.wy;
-          if (__ballot(rowhit) == 0ull) continue;
+          if (__builtin_amdgcn_ballot_w64(rowhit) == 0ull) continue;
           for (int lx = 0; lx < S; lx++) {
             const bool hit = rowhit && (uint32_t)lx - r.x0 <= r.wx;
-            const uint64_t b = __ballot(hit);
+            const uint64_t b = __builtin_amdgcn_ballot_w64(hit);
             if (b == 0ull) continue;
             const int jj = ry * S + lx;  // lane of the tile in this block
             const uint32_t base = __builtin_amdgcn_readlane(run, jj);
@@ -678,10 +859,27 @@ void launch_tile_lists(uint32_t n, uint32_t cap, int TX, int TY, uint32_t *ka, u
   // tot = the super-bin list lengths
   launch_radix_pass(ka, va, kb, vb, cap, ms_dev, 0, hist, tot, st);
   const uint32_t gp = cdiv(piece_bound(cap), kPieceWaves), grid = gp < (uint32_t)kPieceGrid ? gp : (uint32_t)kPieceGrid;
-  tile_count_kernel<<<grid, kPieceWaves * 64, 0, st>>>(kb, tot, log2s, pcnt);
+  const dim3 gb(grid), bb(kPieceWaves * 64);
+  switch (log2s) {
+    case 0: tile_count_kernel<0><<<gb, bb, 0, st>>>(kb, tot, log2s, pcnt); break;
+    case 1: tile_count_kernel<1><<<gb, bb, 0, st>>>(kb, tot, log2s, pcnt); break;
+    case 2: tile_count_kernel<2><<<gb, bb, 0, st>>>(kb, tot, log2s, pcnt); break;
+    case 3: tile_count_kernel<3><<<gb, bb, 0, st>>>(kb, tot, log2s, pcnt); break;
+    default: tile_count_kernel<-1><<<gb, bb, 0, st>>>(kb, tot, log2s, pcnt); break;
+  }
   tile_piece_scan_kernel<<<SX * SY, 256, 0, st>>>(tot, TX, TY, SX, log2s, pcnt, counts);
-  tile_scan_kernel<<<1, 256, 0, st>>>(counts, T, area_part, (int)area_parts(n), cap, m_out, status, ranges);
-  tile_write_kernel<<<grid, kPieceWaves * 64, 0, st>>>(kb, vb, tot, TX, TY, SX, log2s, pcnt, counts, m_out, cap, va);
+  tile_scan_kernel<<<1, kTileScanThreads, 0, st>>>(counts, T, area_part, (int)area_parts(n), cap, m_out, status,
+                                                 ranges);
+#define SSSGS_TILE_WRITE(LL) \
+  tile_write_kernel<LL><<<gb, bb, 0, st>>>(kb, vb, tot, TX, TY, SX, log2s, pcnt, counts, m_out, cap, va)
+  switch (log2s) {
+    case 0: SSSGS_TILE_WRITE(0); break;
+    case 1: SSSGS_TILE_WRITE(1); break;
+    case 2: SSSGS_TILE_WRITE(2); break;
+    case 3: SSSGS_TILE_WRITE(3); break;
+    default: SSSGS_TILE_WRITE(-1); break;
+  }
+#undef SSSGS_TILE_WRITE
 }
 
 
