@@ -417,7 +417,7 @@ sssgs_status forward_impl(const sssgs_gaussians *g, const sssgs_camera *cam, con
     for (int pass = 0; pass < 4; pass++) {
       uint32_t *ko = (pass & 1) ? ka : kb;
       uint32_t *vo = (pass & 1) ? va : vb;
-      launch_radix_pass(kin, vin, ko, vo, n, nullptr, pass * kRadixBits, hist, at<uint32_t>(ws, L.dtot), st);
+      launch_radix_pass(kin, vin, ko, vo, n, nullptr, pass * kRadixBits, hist, at<uint32_t>(ws, L.dtot), false, st);
       kin = ko;
       vin = vo;
     }

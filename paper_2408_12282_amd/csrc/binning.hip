@@ -187,8 +187,12 @@ __global__ __launch_bounds__(kSortThreads) void radix_colscan_kernel(uint32_t *_
 // ballots into block-local digit runs in LDS, then streams the runs out, so
 // that consecutive lanes write consecutive global addresses.  The global
 // start of the block's run of digit d is the start of digit d (exclusive scan
-// of the digit totals) plus the column-scanned count of digit d in earlier
-// blocks.
+// of the digit totals) plus the count of digit d in earlier blocks: read from
+// the column-scanned counts, or (LOCAL: few blocks, a host-known item count,
+// no column scan) summed by the block itself from all blocks' counts -- each
+// wave a quarter of the blocks, a lane four digits per 16-byte load with
+// eight in flight, the quarters added through LDS.
+template <bool LOCAL>
 __global__ __launch_bounds__(kSortThreads) void radix_scatter_kernel(
     const uint32_t *__restrict__ keys_in, const uint32_t *__restrict__ vals_in, uint32_t *__restrict__ keys_out,
     uint32_t *__restrict__ vals_out, uint32_t n_host, const uint32_t *__restrict__ n_dev, int shift,
@@ -212,7 +216,37 @@ __global__ __launch_bounds__(kSortThreads) void radix_scatter_kernel(
     key[r] = idx < n ? keys_in[idx] : 0u;
     val[r] = idx < n ? vals_in[idx] : 0u;
   }
-  {
+  if (LOCAL) {
+    const int nblocks = (int)((n + kSortItems - 1) / kSortItems);
+    const int q0 = (nblocks * w) >> 2, q1 = (nblocks * (w + 1)) >> 2;
+    const uint4 *h4 = reinterpret_cast<const uint4 *>(hist_col) + lane;
+    uint4 tot4 = make_uint4(0u, 0u, 0u, 0u), bel4 = make_uint4(0u, 0u, 0u, 0u);
+    for (int b0 = q0; b0 < q1; b0 += 8) {
+      uint4 c[8];
+#pragma unroll
+      for (int k = 0; k < 8; k++) c[k] = b0 + k < q1 ? h4[(size_t)(b0 + k) * (kRadixBins / 4)] : make_uint4(0u, 0u, 0u, 0u);
+#pragma unroll
+      for (int k = 0; k < 8; k++) {
+        tot4.x += c[k].x;
+        tot4.y += c[k].y;
+        tot4.z += c[k].z;
+        tot4.w += c[k].w;
+        if (b0 + k < (int)blockIdx.x) {
+          bel4.x += c[k].x;
+          bel4.y += c[k].y;
+          bel4.z += c[k].z;
+          bel4.w += c[k].w;
+        }
+      }
+    }
+    reinterpret_cast<uint4 *>(wcnt[w])[lane] = tot4;
+    reinterpret_cast<uint4 *>(wbase[w])[lane] = bel4;
+    __syncthreads();
+    const uint32_t dt = (wcnt[0][t] + wcnt[1][t]) + (wcnt[2][t] + wcnt[3][t]);
+    const uint32_t below = (wbase[0][t] + wbase[1][t]) + (wbase[2][t] + wbase[3][t]);
+    uint32_t total;
+    gbase[t] = block_exclusive_scan(dt, lds4, total) + below;
+  } else {
     uint32_t total;
     gbase[t] = block_exclusive_scan(tot[t], lds4, total) + hist_col[blockIdx.x * kRadixBins + t];
   }
@@ -791,6 +825,7 @@ __global__ __launch_bounds__(kPieceWaves * 64) void tile_write_kernel(
 static inline uint32_t cdiv(uint64_t a, uint64_t b) { return (uint32_t)((a + b - 1) / b); }
 
 constexpr uint32_t kScanSumBlocks = 4096;  // up to this many blocks a scan skips the partials pass
+constexpr uint32_t kRadixLocalBlocks = 512;  // up to this many blocks a pass without totals skips the column scan
 
 // Exclusive scan of n (host-known bound) u32 values; total written to total_dev.
 void launch_scan(const uint32_t *in, uint32_t *out, uint32_t n, uint32_t *partials, uint32_t *total_dev,
@@ -813,11 +848,17 @@ uint32_t scan_partials_needed(uint64_t n) { return n ? cdiv(n, kScanItems) : 1; 
 // One stable 8-bit pass (keys/vals in -> out) over min(n_host, *n_dev) items;
 // tot receives the 256 digit totals.
 void launch_radix_pass(const uint32_t *kin, const uint32_t *vin, uint32_t *kout, uint32_t *vout, uint32_t n_host,
-                       const uint32_t *n_dev, int shift, uint32_t *hist, uint32_t *tot, hipStream_t st) {
+                       const uint32_t *n_dev, int shift, uint32_t *hist, uint32_t *tot, bool want_tot,
+                       hipStream_t st) {
   const uint32_t nb = radix_blocks(n_host);
   radix_hist_kernel<<<nb, kSortThreads, 0, st>>>(kin, n_host, n_dev, shift, hist);
+  if (!want_tot && !n_dev && nb <= kRadixLocalBlocks) {
+    // few blocks: each scatter block sums the block counts itself
+    radix_scatter_kernel<true><<<nb, kSortThreads, 0, st>>>(kin, vin, kout, vout, n_host, n_dev, shift, hist, tot);
+    return;
+  }
   radix_colscan_kernel<<<kRadixBins, kSortThreads, 0, st>>>(hist, n_host, n_dev, tot);
-  radix_scatter_kernel<<<nb, kSortThreads, 0, st>>>(kin, vin, kout, vout, n_host, n_dev, shift, hist, tot);
+  radix_scatter_kernel<false><<<nb, kSortThreads, 0, st>>>(kin, vin, kout, vout, n_host, n_dev, shift, hist, tot);
 }
 
 int superbin_log2(int TX, int TY) {
@@ -857,7 +898,7 @@ void launch_tile_lists(uint32_t n, uint32_t cap, int TX, int TY, uint32_t *ka, u
   const int T = TX * TY;
   // one stable 8-bit pass: super-bin-major, depth order within each super-bin;
   // tot = the super-bin list lengths
-  launch_radix_pass(ka, va, kb, vb, cap, ms_dev, 0, hist, tot, st);
+  launch_radix_pass(ka, va, kb, vb, cap, ms_dev, 0, hist, tot, true, st);
   const uint32_t gp = cdiv(piece_bound(cap), kPieceWaves), grid = gp < (uint32_t)kPieceGrid ? gp : (uint32_t)kPieceGrid;
   const dim3 gb(grid), bb(kPieceWaves * 64);
   switch (log2s) {

@@ -467,7 +467,7 @@ void launch_visibility(const VisArgs &a0, uint32_t *keys_a, uint32_t *vals_a, ui
   for (int pass = 0; pass < 4; pass++) {
     uint32_t *ko = (pass & 1) ? keys_a : keys_b;
     uint32_t *vo = (pass & 1) ? vals_a : vals_b;
-    launch_radix_pass(kin, vin, ko, vo, (uint32_t)n, nullptr, pass * kRadixBits, hist, partials, st);  // partials: >= 256 words
+    launch_radix_pass(kin, vin, ko, vo, (uint32_t)n, nullptr, pass * kRadixBits, hist, partials, false, st);  // partials: >= 256 words
     kin = ko;
     vin = vo;
   }

@@ -27,10 +27,11 @@ void launch_scan(const uint32_t *in, uint32_t *out, uint32_t n, uint32_t *partia
 uint32_t radix_blocks(uint64_t n);
 uint32_t scan_partials_needed(uint64_t n);
 // One stable 8-bit pass over min(n_host, *n_dev) items (n_dev may be null):
-// block-major digit counts in hist (radix_blocks(n_host) x 256), the 256
-// digit totals in tot.
+// block-major digit counts in hist (radix_blocks(n_host) x 256); with
+// want_tot the 256 digit totals in tot (tot is scratch of 256 words either way).
 void launch_radix_pass(const uint32_t *kin, const uint32_t *vin, uint32_t *kout, uint32_t *vout, uint32_t n_host,
-                       const uint32_t *n_dev, int shift, uint32_t *hist, uint32_t *tot, hipStream_t st);
+                       const uint32_t *n_dev, int shift, uint32_t *hist, uint32_t *tot, bool want_tot,
+                       hipStream_t st);
 // Tile lists (Sec. 3.1 binning): super-bin expansion of the depth-sorted
 // Gaussians, then the stable super-bin pass and the per-tile filtering into
 // tile-major Gaussian-index lists with their ranges and the status word.
