@@ -12,6 +12,12 @@
 
 namespace sssgs {
 
+// LDS writes of this wave visible to its own later reads (all lanes).
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
 // MULTI = false: one light of weight 1 written (not added) -- the plain
 // forward, compiled without the light loop.
 template <int F, int NET, int WIDTH, int IN_PAD, bool MULTI>
@@ -56,9 +62,11 @@ __global__ __launch_bounds__(256) void shade_fwd_kernel(ShadeArgs A, MultiLight 
       // the network input row differs between lights only in w_i
       if (k == 0) build_net_input<F, IN_PAD, M>(gb, S, xrow);
       else set_net_light<F, IN_PAD, M>(S, xrow);
-      __syncthreads();
+      // each wave reads and writes only its own rows: a wave-level fence
+      // suffices, and the four waves run the network independently
+      wave_sync();
       net_forward_wave<M, WIDTH, IN_PAD, false>(A.wops, A.params, xs + w * 64 * XS, XS, outs + w * 64 * 8, nullptr);
-      __syncthreads();
+      wave_sync();
       combine_net(S, gb[kChSss], outs + (w * 64 + lane) * 8);
     }
 #pragma unroll

@@ -251,10 +251,14 @@ template <int IN_PAD>
 struct SplitLds {
   static constexpr int XS = in_row_stride<MmaBF16, IN_PAD>();  // bf16 input row stride (hi | lo)
   static constexpr int DS = IN_PAD + 1;                     // fp32 input-gradient row stride
-  static constexpr int IO = 13;  // floats per pixel: 6 outputs, 6 output gradients, pad
+  // floats per pixel: 6 outputs, 6 output gradients.  No odd padding (its
+  // few accesses conflict): 20480 bytes in all, so that eight one-wave
+  // workgroups share a CU's 160 KB.
+  static constexpr int IO = 12;
   static constexpr int RB = (64 * XS * 2 > 64 * DS * 4) ? 64 * XS * 2 : 64 * DS * 4;
   static constexpr int BYTES = RB + 64 * IO * 4;
 };
+static_assert(SplitLds<64>::BYTES <= 160 * 1024 / 8, "eight split-backward workgroups per CU");
 
 template <int F, int IN_PAD>
 __global__ __launch_bounds__(64, 2) void shade_bwd_split_kernel(ShadeArgs A, __bf16 *__restrict__ rec_x,
