@@ -181,6 +181,12 @@ __device__ inline short4 alpha_box(const Geo &G, double opac) {
                      clamp16(floor(G.v + ey - 0.5)));
 }
 
+// Rq[3 r + k] for a run-time column k, by selects: an index into the array
+// would send the whole array to scratch memory.
+__device__ __forceinline__ double rq_col(const double *Rq, int r, int k) {
+  return k == 0 ? Rq[3 * r] : (k == 1 ? Rq[3 * r + 1] : Rq[3 * r + 2]);
+}
+
 // Index of the smallest log-scale (first on ties) and the sign that turns
 // that rotation axis toward the camera.
 __device__ inline void normal_axis(const ProjIn &in, const CamArgs &cam, int i, const double *Rq, int &kmin,
@@ -194,7 +200,7 @@ __device__ inline void normal_axis(const ProjIn &in, const CamArgs &cam, int i, 
   const double tc0 = cam.Cw[0] - (double)in.means[i];
   const double tc1 = cam.Cw[1] - (double)in.means[n + i];
   const double tc2 = cam.Cw[2] - (double)in.means[2 * n + i];
-  const double d = Rq[kmin] * tc0 + Rq[3 + kmin] * tc1 + Rq[6 + kmin] * tc2;
+  const double d = rq_col(Rq, 0, kmin) * tc0 + rq_col(Rq, 1, kmin) * tc1 + rq_col(Rq, 2, kmin) * tc2;
   sign = d < 0.0 ? -1.0 : 1.0;
 }
 
@@ -244,7 +250,7 @@ __global__ __launch_bounds__(256) void project_fwd_kernel(ProjIn in, CamArgs cam
   int kmin;
   double sgn;
   normal_axis(in, cam, i, G.Rq, kmin, sgn);
-  for (int r = 0; r < 3; r++) rec[6 + kChNrm + r] = (float)(sgn * G.Rq[3 * r + kmin]);
+  for (int r = 0; r < 3; r++) rec[6 + kChNrm + r] = (float)(sgn * rq_col(G.Rq, r, kmin));
   rec[6 + kChRough] = in.roughness[i];
   rec[6 + kChMetal] = in.metallic[i];
   rec[6 + kChSss] = in.sss[i];
@@ -363,7 +369,10 @@ __global__ __launch_bounds__(256) void project_bwd_kernel(ProjIn in, CamArgs cam
     int kmin;
     double sgn;
     normal_axis(in, cam, i, G.Rq, kmin, sgn);
-    for (int r = 0; r < 3; r++) dRq[3 * r + kmin] += sgn * (double)dch[kChNrm + r];
+    for (int r = 0; r < 3; r++)
+#pragma unroll
+      for (int k = 0; k < 3; k++)
+        if (k == kmin) dRq[3 * r + k] += sgn * (double)dch[kChNrm + r];
     // Rq(qn) -> dqn
     const double w = G.qn[0], qx = G.qn[1], qy = G.qn[2], qz = G.qn[3];
     double dqn[4];
