@@ -11,10 +11,9 @@ namespace sssgs {
 // NATURAL: every layer's K in natural order (inputs read from LDS rows);
 // otherwise layers >= 1 in the permuted order of the accumulator layout.
 template <class M, int WIDTH, int IN_PAD, bool NATURAL>
-__global__ __launch_bounds__(256) void prep_fwd_kernel(const float *__restrict__ params, typename M::Op *wops) {
+__device__ __forceinline__ void prep_fwd_op(const float *__restrict__ params, typename M::Op *wops, int idx) {
   using NS = NetShape<M, WIDTH, IN_PAD>;
   using PO = ParamOffsets<WIDTH, IN_PAD>;
-  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= NS::total_ops(3)) return;
   int layer, local;
   if (idx < NS::L0) {
@@ -46,10 +45,9 @@ __global__ __launch_bounds__(256) void prep_fwd_kernel(const float *__restrict__
 // (16-row blocks mb), K = the layer's output features in the permuted order
 // of the accumulator layout.
 template <class M, int WIDTH, int IN_PAD>
-__global__ __launch_bounds__(256) void prep_bwd_kernel(const float *__restrict__ params, typename M::Op *tops) {
+__device__ __forceinline__ void prep_bwd_op(const float *__restrict__ params, typename M::Op *tops, int idx) {
   using NS = NetShape<M, WIDTH, IN_PAD>;
   using PO = ParamOffsets<WIDTH, IN_PAD>;
-  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= NS::total_tops(3)) return;
   int layer, local;
   if (idx < NS::T0) {
@@ -77,14 +75,25 @@ __global__ __launch_bounds__(256) void prep_bwd_kernel(const float *__restrict__
   tops[idx] = o;
 }
 
+// All requested operand sets in one launch: blocks [0, bw) write wops,
+// [bw, bw + bn) nops, the rest tops (bw, bn = 0 for a set not requested).
+template <class M, int WIDTH, int IN_PAD>
+__global__ __launch_bounds__(256) void prep_kernel(const float *__restrict__ params, typename M::Op *wops,
+                                                   typename M::Op *nops, typename M::Op *tops, int bw, int bn) {
+  const int b = blockIdx.x;
+  if (b < bw) prep_fwd_op<M, WIDTH, IN_PAD, false>(params, wops, b * 256 + threadIdx.x);
+  else if (b < bw + bn) prep_fwd_op<M, WIDTH, IN_PAD, true>(params, nops, (b - bw) * 256 + threadIdx.x);
+  else prep_bwd_op<M, WIDTH, IN_PAD>(params, tops, (b - bw - bn) * 256 + threadIdx.x);
+}
+
 template <class M, int WIDTH, int IN_PAD>
 static void prep_t(const float *params, void *wops, void *tops, void *nops, hipStream_t st) {
   using NS = NetShape<M, WIDTH, IN_PAD>;
-  const int nf = NS::total_ops(3), nb = NS::total_tops(3);
   using Op = typename M::Op;
-  if (wops) prep_fwd_kernel<M, WIDTH, IN_PAD, false><<<(nf + 255) / 256, 256, 0, st>>>(params, (Op *)wops);
-  if (nops) prep_fwd_kernel<M, WIDTH, IN_PAD, true><<<(nf + 255) / 256, 256, 0, st>>>(params, (Op *)nops);
-  if (tops) prep_bwd_kernel<M, WIDTH, IN_PAD><<<(nb + 255) / 256, 256, 0, st>>>(params, (Op *)tops);
+  const int cf = (NS::total_ops(3) + 255) / 256, cb = (NS::total_tops(3) + 255) / 256;
+  const int bw = wops ? cf : 0, bn = nops ? cf : 0, bt = tops ? cb : 0;
+  if (bw + bn + bt == 0) return;
+  prep_kernel<M, WIDTH, IN_PAD><<<bw + bn + bt, 256, 0, st>>>(params, (Op *)wops, (Op *)nops, (Op *)tops, bw, bn);
 }
 
 void launch_prep_weights(int net, int width, int in_pad, const float *params, void *wops, void *tops, void *nops,
