@@ -825,7 +825,7 @@ __global__ __launch_bounds__(kPieceWaves * 64) void tile_write_kernel(
 static inline uint32_t cdiv(uint64_t a, uint64_t b) { return (uint32_t)((a + b - 1) / b); }
 
 constexpr uint32_t kScanSumBlocks = 4096;  // up to this many blocks a scan skips the partials pass
-constexpr uint32_t kRadixLocalBlocks = 512;  // up to this many blocks a pass without totals skips the column scan
+constexpr uint32_t kRadixLocalBlocks = 256;  // up to this many blocks a pass without totals skips the column scan
 
 // Exclusive scan of n (host-known bound) u32 values; total written to total_dev.
 void launch_scan(const uint32_t *in, uint32_t *out, uint32_t n, uint32_t *partials, uint32_t *total_dev,

@@ -204,15 +204,14 @@ __device__ inline void normal_axis(const ProjIn &in, const CamArgs &cam, int i, 
   sign = d < 0.0 ? -1.0 : 1.0;
 }
 
+// One Gaussian: keys, values, rectangle, radius and culling box to memory,
+// its record to the workgroup's LDS slot `sr` (zeros when it is culled).
 template <int F, bool SH>
-__global__ __launch_bounds__(256) void project_fwd_kernel(ProjIn in, CamArgs cam, float *__restrict__ records,
-                                                          uint32_t *__restrict__ keys, uint32_t *__restrict__ vals,
-                                                          ushort4 *__restrict__ rects, int32_t *__restrict__ radii,
-                                                          short4 *__restrict__ boxes) {
+__device__ __forceinline__ void project_record(const ProjIn &in, const CamArgs &cam, int i, uint32_t *__restrict__ keys,
+                                               uint32_t *__restrict__ vals, ushort4 *__restrict__ rects,
+                                               int32_t *__restrict__ radii, short4 *__restrict__ boxes, float4 *sr) {
   constexpr int C = kChFeat + F;
   constexpr int RS = rec_stride(C);
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= in.n) return;
   const int n = in.n;
   Geo G;
   project_geometry(in, cam, i, G);
@@ -224,7 +223,11 @@ __global__ __launch_bounds__(256) void project_fwd_kernel(ProjIn in, CamArgs cam
                      : make_ushort4(0, 0, 0, 0);
   const double opac = 1.0 / (1.0 + exp(-(double)in.opacity_logits[i]));
   boxes[i] = alpha_box(G, opac);
-  if (!G.valid) return;
+  if (!G.valid) {
+#pragma unroll
+    for (int k = 0; k < RS / 4; k++) sr[k] = make_float4(0.f, 0.f, 0.f, 0.f);
+    return;
+  }
   float rec[RS];
   rec[0] = (float)G.u;
   rec[1] = (float)G.v;
@@ -259,9 +262,26 @@ __global__ __launch_bounds__(256) void project_fwd_kernel(ProjIn in, CamArgs cam
   for (int f = 0; f < F; f++) rec[6 + kChFeat + f] = in.features[f * n + i];
 #pragma unroll
   for (int k = 6 + C; k < RS; k++) rec[k] = 0.f;
-  float *dst = records + (size_t)i * RS;
 #pragma unroll
-  for (int k = 0; k < RS; k += 4) st4(dst + k, make_float4(rec[k], rec[k + 1], rec[k + 2], rec[k + 3]));
+  for (int k = 0; k < RS; k += 4) sr[k / 4] = make_float4(rec[k], rec[k + 1], rec[k + 2], rec[k + 3]);
+}
+
+template <int F, bool SH>
+__global__ __launch_bounds__(256) void project_fwd_kernel(ProjIn in, CamArgs cam, float *__restrict__ records,
+                                                          uint32_t *__restrict__ keys, uint32_t *__restrict__ vals,
+                                                          ushort4 *__restrict__ rects, int32_t *__restrict__ radii,
+                                                          short4 *__restrict__ boxes) {
+  // the workgroup's records are staged in LDS and written out coalesced
+  // (consecutive threads, consecutive 16-byte chunks): a thread writing its
+  // own 128-byte record with 16-byte stores spread every store over 64 lines
+  constexpr int RS = rec_stride(kChFeat + F);
+  __shared__ float4 srec[256 * (RS / 4)];
+  const int i0 = blockIdx.x * blockDim.x, i = i0 + threadIdx.x;
+  const int nv = min(256, in.n - i0);
+  if (i < in.n) project_record<F, SH>(in, cam, i, keys, vals, rects, radii, boxes, srec + threadIdx.x * (RS / 4));
+  __syncthreads();
+  float4 *dst = reinterpret_cast<float4 *>(records + (size_t)i0 * RS);
+  for (int k = threadIdx.x; k < nv * (RS / 4); k += 256) dst[k] = srec[k];
 }
 
 __device__ __forceinline__ void put(float *p, int idx, double v, int acc) {
