@@ -300,12 +300,18 @@ __global__ __launch_bounds__(64, 2) void shade_bwd_split_kernel(ShadeArgs A, __b
     PixShade S;
     shade_geometry<C>(gb, T, uc, vc, A.cam, A.light, true, S);
     build_net_input<F, IN_PAD, M>(gb, S, xs + lane * SL::XS);
-    const uint4 *src = reinterpret_cast<const uint4 *>(xs + lane * SL::XS);
-    uint4 *dst = reinterpret_cast<uint4 *>(rec_x + rrow * 2 * IN_PAD);
-#pragma unroll
-    for (int k = 0; k < IN_PAD / 4; k++) dst[k] = src[k];
   }
   __syncthreads();
+  {
+    // the strip's rows to its record, coalesced: consecutive lanes write
+    // consecutive 16-byte chunks of the 64 rows
+    static_assert(SL::XS % 8 == 0, "row stride in 16-byte chunks");
+    constexpr int CH = 2 * IN_PAD / 8;  // chunks per row
+    const uint4 *src = reinterpret_cast<const uint4 *>(xs);
+    uint4 *dst = reinterpret_cast<uint4 *>(rec_x + (size_t)strip * 64 * 2 * IN_PAD);
+#pragma unroll
+    for (int q = lane; q < 64 * CH; q += 64) dst[q] = src[(q / CH) * (SL::XS / 8) + q % CH];
+  }
   // ---- B: network forward: ReLU masks and outputs
   Mask<MB> m1, m2, m3;
   {
