@@ -34,6 +34,18 @@ struct LightArgs {
   float pos[3], intensity[3];
 };
 
+// Work item of block b in a grid of G blocks such that the blocks one XCD
+// runs take consecutive items.  The hardware deals workgroups to the eight
+// XCDs round-robin (block b to XCD b mod 8), and each XCD has its own L2:
+// with consecutive tiles on one XCD, the two tiles that share a 128-byte
+// line of a planar per-pixel array are fetched into one L2, not two.  A
+// bijection on [0, G): XCD x runs G/8 blocks (one more for x < G mod 8).
+constexpr int kXcds = 8;
+__device__ __forceinline__ int xcd_item(int b, int G) {
+  const int per = G / kXcds, rem = G % kXcds, x = b % kXcds, k = b / kXcds;
+  return x < rem ? x * (per + 1) + k : rem * (per + 1) + (x - rem) * per + k;
+}
+
 __device__ __forceinline__ float4 ld4(const float *p) { return *reinterpret_cast<const float4 *>(p); }
 __device__ __forceinline__ void st4(float *p, float4 v) { *reinterpret_cast<float4 *>(p) = v; }
 

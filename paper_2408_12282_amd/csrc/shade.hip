@@ -28,7 +28,7 @@ __global__ __launch_bounds__(256) void shade_fwd_kernel(ShadeArgs A, MultiLight 
   constexpr int XS = in_row_stride<M, IN_PAD>();  // LDS row stride (elements)
   __shared__ E xs[kIsNet<NET> ? 4 * 64 * XS : 1];
   __shared__ float outs[kIsNet<NET> ? 4 * 64 * 8 : 1];
-  const int tile = blockIdx.x;
+  const int tile = xcd_item(blockIdx.x, gridDim.x);
   const int tx = tile % A.cam.TX, ty = tile / A.cam.TX;
   const int px = tx * kTile + (threadIdx.x & 15), py = ty * kTile + (threadIdx.x >> 4);
   const bool inside = px < A.cam.W && py < A.cam.H;

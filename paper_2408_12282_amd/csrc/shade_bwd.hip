@@ -219,7 +219,7 @@ __device__ __forceinline__ void write_pixel_grads(const ShadeArgs &A, bool insid
 template <int F, int NET>
 __global__ __launch_bounds__(256) void shade_bwd_plain_kernel(ShadeArgs A) {
   constexpr int C = kChFeat + F;
-  const int tile = blockIdx.x;
+  const int tile = xcd_item(blockIdx.x, gridDim.x);
   const int tx = tile % A.cam.TX, ty = tile / A.cam.TX;
   const int px = tx * kTile + (threadIdx.x & 15), py = ty * kTile + (threadIdx.x >> 4);
   const bool inside = px < A.cam.W && py < A.cam.H;
@@ -276,7 +276,7 @@ __global__ __launch_bounds__(64, 2) void shade_bwd_split_kernel(ShadeArgs A, __b
   float *io = reinterpret_cast<float *>(lds + SL::RB);
   const int lane = threadIdx.x;
   const int g = lane >> 4, col = lane & 15;
-  const int strip = blockIdx.x;
+  const int strip = xcd_item(blockIdx.x, gridDim.x);
   const int tile = strip >> 2, sub = strip & 3;
   const int tx = tile % A.cam.TX, ty = tile / A.cam.TX;
   const int px = tx * kTile + col, py = ty * kTile + 4 * sub + g;
@@ -525,7 +525,7 @@ __global__ __launch_bounds__(64, WIDTH == 64 ? 2 : 1) void shade_bwd_net_kernel(
   float *io = reinterpret_cast<float *>(lds + NL::RB);
   const int lane = threadIdx.x;
   const int g = lane >> 4, col = lane & 15;
-  const int strip = blockIdx.x;
+  const int strip = xcd_item(blockIdx.x, gridDim.x);
   const int tile = strip >> 2, sub = strip & 3;
   const int tx = tile % A.cam.TX, ty = tile / A.cam.TX;
   const int px = tx * kTile + col, py = ty * kTile + 4 * sub + g;
