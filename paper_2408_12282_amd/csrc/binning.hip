@@ -315,21 +315,33 @@ __device__ __forceinline__ ushort4 super_rect(ushort4 r, int log2s) {
   return make_ushort4(r.x >> log2s, r.y >> log2s, ((r.z - 1) >> log2s) + 1, ((r.w - 1) >> log2s) + 1);
 }
 
-// Super-bins touched by the Gaussian at each depth-sorted position; the
-// block's number of tiles touched goes to area_part[block].
-__global__ __launch_bounds__(256) void gather_tiles_kernel(const uint32_t *__restrict__ sorted_g,
-                                                           const ushort4 *__restrict__ rects, uint32_t n, int log2s,
-                                                           uint32_t *__restrict__ tt, uint32_t *__restrict__ area_part) {
+// Super-bins touched by the Gaussian at each depth-sorted position, kScanItems
+// positions per block (four per thread, coalesced): the block's sum of them
+// goes to partials[block] -- the block sums of the exclusive scan that
+// follows, which then needs no reduction pass of its own -- and its number of
+// tiles touched to area_part[block].
+__global__ __launch_bounds__(kScanThreads) void gather_tiles_kernel(const uint32_t *__restrict__ sorted_g,
+                                                                    const ushort4 *__restrict__ rects, uint32_t n,
+                                                                    int log2s, uint32_t *__restrict__ tt,
+                                                                    uint32_t *__restrict__ partials,
+                                                                    uint32_t *__restrict__ area_part) {
   __shared__ uint32_t lds4[4];
-  const uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
-  uint32_t area = 0;
-  if (p < n) {
-    const ushort4 r = rects[sorted_g[p]];
-    const ushort4 q = super_rect(r, log2s);
-    tt[p] = (uint32_t)(q.z - q.x) * (uint32_t)(q.w - q.y);
-    area = (uint32_t)(r.z - r.x) * (uint32_t)(r.w - r.y);
+  uint32_t sum = 0, area = 0;
+#pragma unroll
+  for (int k = 0; k < kScanItems / kScanThreads; k++) {
+    const uint32_t p = blockIdx.x * kScanItems + k * kScanThreads + threadIdx.x;
+    if (p < n) {
+      const ushort4 r = rects[sorted_g[p]];
+      const ushort4 q = super_rect(r, log2s);
+      const uint32_t c = (uint32_t)(q.z - q.x) * (uint32_t)(q.w - q.y);
+      tt[p] = c;
+      sum += c;
+      area += (uint32_t)(r.z - r.x) * (uint32_t)(r.w - r.y);
+    }
   }
   uint32_t total;
+  block_exclusive_scan(sum, lds4, total);
+  if (threadIdx.x == 0) partials[blockIdx.x] = total;
   block_exclusive_scan(area, lds4, total);
   if (threadIdx.x == 0) area_part[blockIdx.x] = total;
 }
@@ -827,11 +839,13 @@ static inline uint32_t cdiv(uint64_t a, uint64_t b) { return (uint32_t)((a + b -
 constexpr uint32_t kScanSumBlocks = 4096;  // up to this many blocks a scan skips the partials pass
 constexpr uint32_t kRadixLocalBlocks = 256;  // up to this many blocks a pass without totals skips the column scan
 
-// Exclusive scan of n (host-known bound) u32 values; total written to total_dev.
+// Exclusive scan of n (host-known bound) u32 values; total written to
+// total_dev.  have_partials: partials already holds the block sums (blocks of
+// kScanItems values).
 void launch_scan(const uint32_t *in, uint32_t *out, uint32_t n, uint32_t *partials, uint32_t *total_dev,
-                 hipStream_t st) {
+                 hipStream_t st, bool have_partials) {
   const uint32_t nb = n ? cdiv(n, kScanItems) : 1;
-  scan_reduce_kernel<<<nb, kScanThreads, 0, st>>>(in, n, partials);
+  if (!have_partials) scan_reduce_kernel<<<nb, kScanThreads, 0, st>>>(in, n, partials);
   if (n && nb <= kScanSumBlocks) {
     // few blocks: each down-sweep block sums the partials before it, the
     // last one writes the total
@@ -870,16 +884,17 @@ int superbin_log2(int TX, int TY) {
 // The super-bin key packs 8 bits of super-bin and four log2s-bit coordinates.
 bool superbin_supported(int TX, int TY) { return superbin_log2(TX, TY) <= kMaxSuperbinLog2; }
 
-uint32_t area_parts(uint32_t n) { return n ? cdiv(n, 256) : 1; }
+uint32_t area_parts(uint32_t n) { return n ? cdiv(n, kScanItems) : 1; }
 
 void launch_superbin_expand(const uint32_t *sorted_g, const ushort4 *rects, uint32_t n, uint32_t cap, int TX, int TY,
                             uint32_t *tt, uint32_t *offs, uint32_t *ka, uint32_t *va, uint32_t *partials,
                             uint32_t *ms_dev, uint32_t *area_part, hipStream_t st) {
   const int log2s = superbin_log2(TX, TY);
   const int SX = (int)cdiv(TX, 1u << log2s);
-  if (n) gather_tiles_kernel<<<cdiv(n, 256), 256, 0, st>>>(sorted_g, rects, n, log2s, tt, area_part);
+  if (n) gather_tiles_kernel<<<cdiv(n, kScanItems), kScanThreads, 0, st>>>(sorted_g, rects, n, log2s, tt, partials,
+                                                                          area_part);
   else zero_u32_kernel<<<1, 1, 0, st>>>(area_part);
-  launch_scan(tt, offs, n, partials, ms_dev, st);
+  launch_scan(tt, offs, n, partials, ms_dev, st, n > 0);
   if (n) emit_kernel<<<cdiv(n, 256), 256, 0, st>>>(sorted_g, rects, offs, n, cap, SX, log2s, ka, va);
 }
 

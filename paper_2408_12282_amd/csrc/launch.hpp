@@ -23,7 +23,7 @@ void launch_project_bwd_t(const ProjIn &in, const CamArgs &cam, const float *gac
                           hipStream_t st);
 
 void launch_scan(const uint32_t *in, uint32_t *out, uint32_t n, uint32_t *partials, uint32_t *total_dev,
-                 hipStream_t st);
+                 hipStream_t st, bool have_partials = false);
 uint32_t radix_blocks(uint64_t n);
 uint32_t scan_partials_needed(uint64_t n);
 // One stable 8-bit pass over min(n_host, *n_dev) items (n_dev may be null):
