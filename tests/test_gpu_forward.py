@@ -193,11 +193,12 @@ def test_headline_300k_800(precision):
         assert e64 < BF16_FP64_REL
 
 
-@pytest.mark.parametrize("W,H", [(4096, 4096), (2500, 300), (500, 450)])
+@pytest.mark.parametrize("W,H", [(4112, 4112), (4096, 4096), (1600, 1200), (2500, 300), (500, 450)])
 def test_tile_lists_large_grids(W, H):
-    """Tile lists on large tile grids (256 x 256 tiles: super-bins of 16 x 16
-    tiles; a wide 157 x 19 grid: super-bins of 4 x 4; 32 x 29 tiles: 2 x 2),
-    checked for every tile against the order
+    """Tile lists on large tile grids (257 x 257 tiles: super-bins of 32 x 32
+    tiles, 16 blocks of 64 tiles each; 256 x 256 tiles: super-bins of 16 x 16;
+    100 x 75 tiles: 8 x 8, the largest compile-time size; a wide 157 x 19
+    grid: 4 x 4; 32 x 29 tiles: 2 x 2), checked for every tile against the order
     (float32 depth key, index) over the Gaussians whose tile rectangle holds
     the tile, built on the CPU from the GPU's own rectangles and depth keys
     (those two are checked against the oracle by the tests above)."""
