@@ -275,25 +275,27 @@ __global__ __launch_bounds__(kWgradWaves * 64, 1) void mlp_wgrad_kernel(const vo
       if (g < 2) v = *reinterpret_cast<const uint2 *>(orow + (16 * nb + col) * 8 + 4 * g);
       Bo[0][nb] = __builtin_bit_cast(bf16x8, make_uint4(v.x, v.y, 0u, 0u));
     }
-    layer_wgrad<1, MB>(Bo, H3, eye, dW3, db3);
     f32x4 dH[MB][4];
     Op Bd[KSH][4];
+    // each layer's backward product first: its weight loads (L2) are then in
+    // flight while the independent weight-gradient products run
     layer_mma<M, MB, NS::KT_O>(tops + NS::T0 + 2 * NS::TH, Bo, dH, lane);
+    layer_wgrad<1, MB>(Bo, H3, eye, dW3, db3);
     relu_mask_from_ops<MB>(H3, dH);
     grad_to_ops<M, MB>(dH, Bd);
     {
       Op X[KSH][4];
       load_ops(hs + KSH * 4 * 64, X, lane);  // H2
-      layer_wgrad<MB, MB>(Bd, X, eye, dW2, db2);
       layer_mma<M, MB, NS::KT_H>(tops + NS::T0 + NS::TH, Bd, dH, lane);
+      layer_wgrad<MB, MB>(Bd, X, eye, dW2, db2);
       relu_mask_from_ops<MB>(X, dH);
     }
     grad_to_ops<M, MB>(dH, Bd);
     {
       Op X[KSH][4];
       load_ops(hs, X, lane);  // H1
-      layer1_wgrad_lds(Bd, X, eye, d1, db1, lane);
       layer_mma<M, MB, NS::KT_H>(tops + NS::T0, Bd, dH, lane);
+      layer1_wgrad_lds(Bd, X, eye, d1, db1, lane);
       relu_mask_from_ops<MB>(X, dH);
     }
     grad_to_ops<M, MB>(dH, Bd);
