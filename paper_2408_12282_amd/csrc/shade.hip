@@ -65,7 +65,13 @@ __global__ __launch_bounds__(256) void shade_fwd_kernel(ShadeArgs A, MultiLight 
       // each wave reads and writes only its own rows: a wave-level fence
       // suffices, and the four waves run the network independently
       wave_sync();
-      net_forward_wave<M, WIDTH, IN_PAD, false>(A.wops, A.params, xs + w * 64 * XS, XS, outs + w * 64 * 8, nullptr);
+      // Over several lights an opaque zero offset keeps the compiler from
+      // hoisting the loop-invariant weight and bias loads out of the light
+      // loop, which would hold every layer's operands in registers at once.
+      int z = 0;
+      if constexpr (MULTI) asm volatile("v_mov_b32 %0, 0" : "=v"(z));
+      net_forward_wave<M, WIDTH, IN_PAD, false>(reinterpret_cast<const char *>(A.wops) + z, A.params + z,
+                                                xs + w * 64 * XS, XS, outs + w * 64 * 8, nullptr);
       wave_sync();
       combine_net(S, gb[kChSss], outs + (w * 64 + lane) * 8);
     }
