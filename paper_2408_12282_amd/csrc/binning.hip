@@ -197,7 +197,7 @@ __global__ __launch_bounds__(kSortThreads) void radix_scatter_kernel(
     const uint32_t *__restrict__ keys_in, const uint32_t *__restrict__ vals_in, uint32_t *__restrict__ keys_out,
     uint32_t *__restrict__ vals_out, uint32_t n_host, const uint32_t *__restrict__ n_dev, int shift,
     const uint32_t *__restrict__ hist_col, const uint32_t *__restrict__ tot) {
-  __shared__ uint32_t run[kRadixBins];   // running block-local position per digit
+  __shared__ uint32_t rc[kSortRounds * 4][kRadixBins];  // digit counts per (round, wave), then their prefix
   __shared__ uint32_t loff[kRadixBins];  // block-local start of each digit's run
   __shared__ uint32_t gbase[kRadixBins]; // global start of this block's run of each digit
   __shared__ uint32_t wcnt[4][kRadixBins];
@@ -216,6 +216,8 @@ __global__ __launch_bounds__(kSortThreads) void radix_scatter_kernel(
     key[r] = idx < n ? keys_in[idx] : 0u;
     val[r] = idx < n ? vals_in[idx] : 0u;
   }
+#pragma unroll
+  for (int k = 0; k < kSortRounds * 4; k++) rc[k][t] = 0u;
   if (LOCAL) {
     const int nblocks = (int)((n + kSortItems - 1) / kSortItems);
     const int q0 = (nblocks * w) >> 2, q1 = (nblocks * (w + 1)) >> 2;
@@ -250,22 +252,12 @@ __global__ __launch_bounds__(kSortThreads) void radix_scatter_kernel(
     uint32_t total;
     gbase[t] = block_exclusive_scan(tot[t], lds4, total) + hist_col[blockIdx.x * kRadixBins + t];
   }
-  run[t] = 0;
-#pragma unroll
-  for (int k = 0; k < 4; k++) wcnt[k][t] = 0;
-  __syncthreads();
-#pragma unroll
-  for (int r = 0; r < kSortRounds; r++)
-    if (r * kSortThreads + t < (int)cnt) atomicAdd(&run[(key[r] >> shift) & (kRadixBins - 1)], 1u);
-  __syncthreads();
-  {
-    uint32_t total;
-    const uint32_t ex = block_exclusive_scan(run[t], lds4, total);
-    loff[t] = ex;
-    run[t] = ex;
-  }
-  __syncthreads();
+  // Rank every key among the block's keys of its digit that come before it
+  // (item order r, w, lane): its rank among the equal digits of its wave and
+  // round from the ballots, and the counts of the earlier (round, wave) rows,
+  // summed per digit once for all rows -- three barriers for the whole block.
   const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  uint32_t rank[kSortRounds];
 #pragma unroll
   for (int r = 0; r < kSortRounds; r++) {
     const bool active = r * kSortThreads + t < (int)cnt;
@@ -277,23 +269,27 @@ __global__ __launch_bounds__(kSortThreads) void radix_scatter_kernel(
       const uint64_t bl = __builtin_amdgcn_ballot_w64(bit);
       match &= bit ? bl : ~bl;
     }
-    const uint32_t rank = __popcll(match & lt);
-    if (active && rank == 0) wcnt[w][d] = __popcll(match);
-    __syncthreads();
-    {
-      uint32_t s = run[t];
+    rank[r] = __popcll(match & lt);
+    if (active && rank[r] == 0) rc[r * 4 + w][d] = __popcll(match);
+  }
+  __syncthreads();
+  {
+    uint32_t s = 0;
 #pragma unroll
-      for (int k = 0; k < 4; k++) {
-        const uint32_t c = wcnt[k][t];
-        wbase[k][t] = s;
-        s += c;
-        wcnt[k][t] = 0;
-      }
-      run[t] = s;
+    for (int k = 0; k < kSortRounds * 4; k++) {
+      const uint32_t c = rc[k][t];
+      rc[k][t] = s;
+      s += c;
     }
-    __syncthreads();
-    if (active) {
-      const uint32_t pos = wbase[w][d] + rank;
+    uint32_t total;
+    loff[t] = block_exclusive_scan(s, lds4, total);
+  }
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < kSortRounds; r++) {
+    if (r * kSortThreads + t < (int)cnt) {
+      const uint32_t d = (key[r] >> shift) & (kRadixBins - 1);
+      const uint32_t pos = loff[d] + rc[r * 4 + w][d] + rank[r];
       sk[pos] = key[r];
       sv[pos] = val[r];
     }
