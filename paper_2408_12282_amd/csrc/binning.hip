@@ -183,44 +183,53 @@ __global__ __launch_bounds__(kSortThreads) void radix_colscan_kernel(uint32_t *_
   if (t == 0) tot[d] = carry;
 }
 
-// Stable scatter of one 8-bit digit.  The block ranks its keys with wave
-// ballots into block-local digit runs in LDS, then streams the runs out, so
-// that consecutive lanes write consecutive global addresses.  The global
-// start of the block's run of digit d is the start of digit d (exclusive scan
-// of the digit totals) plus the count of digit d in earlier blocks: read from
-// the column-scanned counts, or (LOCAL: few blocks, a host-known item count,
-// no column scan) summed by the block itself from all blocks' counts -- each
-// wave a quarter of the blocks, a lane four digits per 16-byte load with
-// eight in flight, the quarters added through LDS.
+// Stable scatter of one 8-bit digit, kSortItems keys per block of
+// kScatterWaves waves.  The block ranks its keys with wave ballots into
+// block-local digit runs in LDS, then streams the runs out, so that
+// consecutive lanes write consecutive global addresses.  The global start of
+// the block's run of digit d is the start of digit d (exclusive scan of the
+// digit totals) plus the count of digit d in earlier blocks: read from the
+// column-scanned counts, or (LOCAL: few blocks, a host-known item count, no
+// column scan) summed by the block itself from all blocks' counts -- each
+// wave an eighth of the blocks, a lane four digits per 16-byte load with
+// eight in flight, the eighths added through LDS.
+constexpr int kScatterWaves = 8;
+constexpr int kScatterThreads = 64 * kScatterWaves;
+constexpr int kScatterRounds = kSortItems / kScatterThreads;
+static_assert(kScatterRounds * kScatterThreads == kSortItems, "scatter block covers one count block");
 template <bool LOCAL>
-__global__ __launch_bounds__(kSortThreads) void radix_scatter_kernel(
+__global__ __launch_bounds__(kScatterThreads) void radix_scatter_kernel(
     const uint32_t *__restrict__ keys_in, const uint32_t *__restrict__ vals_in, uint32_t *__restrict__ keys_out,
     uint32_t *__restrict__ vals_out, uint32_t n_host, const uint32_t *__restrict__ n_dev, int shift,
     const uint32_t *__restrict__ hist_col, const uint32_t *__restrict__ tot) {
-  __shared__ uint32_t rc[kSortRounds * 4][kRadixBins];  // digit counts per (round, wave), then their prefix
-  __shared__ uint32_t loff[kRadixBins];  // block-local start of each digit's run
-  __shared__ uint32_t gbase[kRadixBins]; // global start of this block's run of each digit
-  __shared__ uint32_t wcnt[4][kRadixBins];
-  __shared__ uint32_t wbase[4][kRadixBins];
+  constexpr int NR = kScatterRounds * kScatterWaves;  // (round, wave) rows in item order
+  __shared__ uint32_t rc[NR][kRadixBins];  // digit counts per (round, wave), then their prefix per digit
+  __shared__ uint32_t loff[kRadixBins];    // block-local start of each digit's run
+  __shared__ uint32_t gbase[kRadixBins];   // global start of this block's run of each digit
+  __shared__ uint32_t wcnt[kScatterWaves][kRadixBins];
+  __shared__ uint32_t wbase[kScatterWaves][kRadixBins];
   __shared__ uint32_t sk[kSortItems], sv[kSortItems];
-  __shared__ uint32_t lds4[4];
+  __shared__ uint32_t ldsw[kScatterWaves];
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const bool dig = t < kRadixBins;  // the threads that own a digit
   const uint32_t n = load_count(n_host, n_dev);
   const uint32_t base = blockIdx.x * kSortItems;
   if (base >= n) return;  // uniform per block
   const uint32_t cnt = min((uint32_t)kSortItems, n - base);
-  uint32_t key[kSortRounds], val[kSortRounds];
+  uint32_t key[kScatterRounds], val[kScatterRounds];
 #pragma unroll
-  for (int r = 0; r < kSortRounds; r++) {
-    const uint32_t idx = base + r * kSortThreads + t;
+  for (int r = 0; r < kScatterRounds; r++) {
+    const uint32_t idx = base + r * kScatterThreads + t;
     key[r] = idx < n ? keys_in[idx] : 0u;
     val[r] = idx < n ? vals_in[idx] : 0u;
   }
+  uint32_t *rcf = &rc[0][0];
 #pragma unroll
-  for (int k = 0; k < kSortRounds * 4; k++) rc[k][t] = 0u;
+  for (int k = 0; k < NR * kRadixBins / kScatterThreads; k++) rcf[k * kScatterThreads + t] = 0u;
+  uint32_t dt = 0, below = 0;
   if (LOCAL) {
     const int nblocks = (int)((n + kSortItems - 1) / kSortItems);
-    const int q0 = (nblocks * w) >> 2, q1 = (nblocks * (w + 1)) >> 2;
+    const int q0 = (nblocks * w) / kScatterWaves, q1 = (nblocks * (w + 1)) / kScatterWaves;
     const uint4 *h4 = reinterpret_cast<const uint4 *>(hist_col) + lane;
     uint4 tot4 = make_uint4(0u, 0u, 0u, 0u), bel4 = make_uint4(0u, 0u, 0u, 0u);
     for (int b0 = q0; b0 < q1; b0 += 8) {
@@ -244,23 +253,31 @@ __global__ __launch_bounds__(kSortThreads) void radix_scatter_kernel(
     reinterpret_cast<uint4 *>(wcnt[w])[lane] = tot4;
     reinterpret_cast<uint4 *>(wbase[w])[lane] = bel4;
     __syncthreads();
-    const uint32_t dt = (wcnt[0][t] + wcnt[1][t]) + (wcnt[2][t] + wcnt[3][t]);
-    const uint32_t below = (wbase[0][t] + wbase[1][t]) + (wbase[2][t] + wbase[3][t]);
+    if (dig) {
+#pragma unroll
+      for (int k = 0; k < kScatterWaves; k++) {
+        dt += wcnt[k][t];
+        below += wbase[k][t];
+      }
+    }
+  } else if (dig) {
+    dt = tot[t];
+    below = hist_col[blockIdx.x * kRadixBins + t];
+  }
+  {
     uint32_t total;
-    gbase[t] = block_exclusive_scan(dt, lds4, total) + below;
-  } else {
-    uint32_t total;
-    gbase[t] = block_exclusive_scan(tot[t], lds4, total) + hist_col[blockIdx.x * kRadixBins + t];
+    const uint32_t ex = block_exclusive_scan_w<kScatterWaves>(dt, ldsw, total);
+    if (dig) gbase[t] = ex + below;
   }
   // Rank every key among the block's keys of its digit that come before it
   // (item order r, w, lane): its rank among the equal digits of its wave and
   // round from the ballots, and the counts of the earlier (round, wave) rows,
   // summed per digit once for all rows -- three barriers for the whole block.
   const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-  uint32_t rank[kSortRounds];
+  uint32_t rank[kScatterRounds];
 #pragma unroll
-  for (int r = 0; r < kSortRounds; r++) {
-    const bool active = r * kSortThreads + t < (int)cnt;
+  for (int r = 0; r < kScatterRounds; r++) {
+    const bool active = r * kScatterThreads + t < (int)cnt;
     const uint32_t d = (key[r] >> shift) & (kRadixBins - 1);
     uint64_t match = __builtin_amdgcn_ballot_w64(active);
 #pragma unroll
@@ -270,32 +287,35 @@ __global__ __launch_bounds__(kSortThreads) void radix_scatter_kernel(
       match &= bit ? bl : ~bl;
     }
     rank[r] = __popcll(match & lt);
-    if (active && rank[r] == 0) rc[r * 4 + w][d] = __popcll(match);
+    if (active && rank[r] == 0) rc[r * kScatterWaves + w][d] = __popcll(match);
   }
   __syncthreads();
   {
     uint32_t s = 0;
+    if (dig) {
 #pragma unroll
-    for (int k = 0; k < kSortRounds * 4; k++) {
-      const uint32_t c = rc[k][t];
-      rc[k][t] = s;
-      s += c;
+      for (int k = 0; k < NR; k++) {
+        const uint32_t c = rc[k][t];
+        rc[k][t] = s;
+        s += c;
+      }
     }
     uint32_t total;
-    loff[t] = block_exclusive_scan(s, lds4, total);
+    const uint32_t ex = block_exclusive_scan_w<kScatterWaves>(s, ldsw, total);
+    if (dig) loff[t] = ex;
   }
   __syncthreads();
 #pragma unroll
-  for (int r = 0; r < kSortRounds; r++) {
-    if (r * kSortThreads + t < (int)cnt) {
+  for (int r = 0; r < kScatterRounds; r++) {
+    if (r * kScatterThreads + t < (int)cnt) {
       const uint32_t d = (key[r] >> shift) & (kRadixBins - 1);
-      const uint32_t pos = loff[d] + rc[r * 4 + w][d] + rank[r];
+      const uint32_t pos = loff[d] + rc[r * kScatterWaves + w][d] + rank[r];
       sk[pos] = key[r];
       sv[pos] = val[r];
     }
   }
   __syncthreads();
-  for (uint32_t i = t; i < cnt; i += kSortThreads) {
+  for (uint32_t i = t; i < cnt; i += kScatterThreads) {
     const uint32_t k = sk[i], d = (k >> shift) & (kRadixBins - 1);
     const uint32_t pos = gbase[d] + (i - loff[d]);
     keys_out[pos] = k;
@@ -864,11 +884,11 @@ void launch_radix_pass(const uint32_t *kin, const uint32_t *vin, uint32_t *kout,
   radix_hist_kernel<<<nb, kSortThreads, 0, st>>>(kin, n_host, n_dev, shift, hist);
   if (!want_tot && !n_dev && nb <= kRadixLocalBlocks) {
     // few blocks: each scatter block sums the block counts itself
-    radix_scatter_kernel<true><<<nb, kSortThreads, 0, st>>>(kin, vin, kout, vout, n_host, n_dev, shift, hist, tot);
+    radix_scatter_kernel<true><<<nb, kScatterThreads, 0, st>>>(kin, vin, kout, vout, n_host, n_dev, shift, hist, tot);
     return;
   }
   radix_colscan_kernel<<<kRadixBins, kSortThreads, 0, st>>>(hist, n_host, n_dev, tot);
-  radix_scatter_kernel<false><<<nb, kSortThreads, 0, st>>>(kin, vin, kout, vout, n_host, n_dev, shift, hist, tot);
+  radix_scatter_kernel<false><<<nb, kScatterThreads, 0, st>>>(kin, vin, kout, vout, n_host, n_dev, shift, hist, tot);
 }
 
 int superbin_log2(int TX, int TY) {
