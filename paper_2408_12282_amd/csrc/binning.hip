@@ -135,23 +135,28 @@ __device__ __forceinline__ uint32_t load_count(uint32_t n_host, const uint32_t *
 
 // Per-block digit counts, block-major: hist[block][digit].  Blocks past the
 // item count write nothing (the column scan reads only the active blocks).
-__global__ __launch_bounds__(kSortThreads) void radix_hist_kernel(const uint32_t *__restrict__ keys, uint32_t n_host,
+// Sixteen waves per block, each adding into one of four LDS copies of the
+// counts (fewer waves queued on one address when a digit dominates).
+constexpr int kHistThreads = 1024;
+constexpr int kHistRounds = kSortItems / kHistThreads;
+__global__ __launch_bounds__(kHistThreads) void radix_hist_kernel(const uint32_t *__restrict__ keys, uint32_t n_host,
                                                                   const uint32_t *__restrict__ n_dev, int shift,
                                                                   uint32_t *__restrict__ hist) {
-  __shared__ uint32_t h[kRadixBins];
+  __shared__ uint32_t h[4][kRadixBins];
   const int t = threadIdx.x;
   const uint32_t n = load_count(n_host, n_dev);
   const uint32_t base = blockIdx.x * kSortItems;
   if (base >= n) return;  // uniform per block
-  h[t] = 0;
+  (&h[0][0])[t] = 0;
   __syncthreads();
+  uint32_t *hc = h[(t >> 6) & 3];
 #pragma unroll
-  for (int r = 0; r < kSortRounds; r++) {
-    const uint32_t idx = base + r * kSortThreads + t;
-    if (idx < n) atomicAdd(&h[(keys[idx] >> shift) & (kRadixBins - 1)], 1u);
+  for (int r = 0; r < kHistRounds; r++) {
+    const uint32_t idx = base + r * kHistThreads + t;
+    if (idx < n) atomicAdd(&hc[(keys[idx] >> shift) & (kRadixBins - 1)], 1u);
   }
   __syncthreads();
-  hist[blockIdx.x * kRadixBins + t] = h[t];
+  if (t < kRadixBins) hist[blockIdx.x * kRadixBins + t] = (h[0][t] + h[1][t]) + (h[2][t] + h[3][t]);
 }
 
 // One workgroup per digit d: hist[b][d] becomes the count of digit d in the
@@ -881,7 +886,7 @@ void launch_radix_pass(const uint32_t *kin, const uint32_t *vin, uint32_t *kout,
                        const uint32_t *n_dev, int shift, uint32_t *hist, uint32_t *tot, bool want_tot,
                        hipStream_t st) {
   const uint32_t nb = radix_blocks(n_host);
-  radix_hist_kernel<<<nb, kSortThreads, 0, st>>>(kin, n_host, n_dev, shift, hist);
+  radix_hist_kernel<<<nb, kHistThreads, 0, st>>>(kin, n_host, n_dev, shift, hist);
   if (!want_tot && !n_dev && nb <= kRadixLocalBlocks) {
     // few blocks: each scatter block sums the block counts itself
     radix_scatter_kernel<true><<<nb, kScatterThreads, 0, st>>>(kin, vin, kout, vout, n_host, n_dev, shift, hist, tot);
