@@ -139,6 +139,8 @@ __device__ __forceinline__ uint32_t load_count(uint32_t n_host, const uint32_t *
 // counts (fewer waves queued on one address when a digit dominates).
 constexpr int kHistThreads = 1024;
 constexpr int kHistRounds = kSortItems / kHistThreads;
+static_assert(kHistRounds * kHistThreads == kSortItems && kHistThreads == 4 * kRadixBins,
+              "count block covers one scatter block; one thread per count entry");
 __global__ __launch_bounds__(kHistThreads) void radix_hist_kernel(const uint32_t *__restrict__ keys, uint32_t n_host,
                                                                   const uint32_t *__restrict__ n_dev, int shift,
                                                                   uint32_t *__restrict__ hist) {
