@@ -48,6 +48,13 @@ __global__ __launch_bounds__(256) void shade_fwd_kernel(ShadeArgs A, MultiLight 
   float acc[3] = {0.f, 0.f, 0.f};
   const int K = MULTI ? ML.K : 1;
   for (int k = 0; k < K; k++) {
+    if constexpr (MULTI && kIsNet<NET>) {
+      // opaque per light: keeps the light-independent terms derived from the
+      // G-buffer inside the loop instead of live across it and the network
+#pragma unroll
+      for (int c = 0; c < C; c++) asm volatile("" : "+v"(gb[c]));
+      asm volatile("" : "+v"(T));
+    }
     LightArgs L;
 #pragma unroll
     for (int c = 0; c < 3; c++) {
