@@ -222,3 +222,35 @@ def test_tile_lists_large_grids(W, H):
     for t in range(T):
         got = out["sorted_gauss"][gr[t, 0]:gr[t, 1]]
         assert np.array_equal(got, np.asarray(lists[t], got.dtype)), f"tile {t}"
+
+
+@pytest.mark.parametrize("n", [256 * 2048, 256 * 2048 + 1])
+def test_depth_sort_block_count_boundary(n):
+    """The depth passes sum the per-block digit counts inside the scatter up
+    to 256 blocks of 2048 keys and take a column-scan launch beyond that.  At
+    256 blocks exactly, and at one key more (a last block of one key), the
+    tile lists must still follow (tile, float32 depth key, index), built on the
+    CPU from the GPU's own rectangles and depth keys."""
+    g = scene.make_gaussians(n, 0, False, seed=11)
+    g.log_scales = (g.log_scales - 1.0).astype(np.float32)  # small footprints: few tiles each
+    W = H = 512
+    cam = scene.look_at_camera((0, 0, 3), W, H)
+    print(f"[gpu] depth sort at the block-count boundary, n={n}", flush=True)
+    out = gpu_render(g, cam, scene.default_light())
+    rects = out["rects"].astype(np.int64)
+    keys = out["depth_keys"]
+    x0, y0, x1, y1 = rects[:, 0], rects[:, 1], rects[:, 2], rects[:, 3]
+    cnt = np.maximum(x1 - x0, 0) * np.maximum(y1 - y0, 0)
+    idx = np.repeat(np.arange(n), cnt)
+    off = np.arange(idx.size) - np.repeat(np.cumsum(cnt) - cnt, cnt)
+    w = np.maximum(x1 - x0, 1)[idx]
+    TX = W // 16
+    tile = (y0[idx] + off // w) * TX + (x0[idx] + off % w)
+    exp = idx[np.lexsort((idx, keys[idx], tile))]
+    assert out["M"] == exp.size and exp.size > n
+    T = TX * (H // 16)
+    counts = np.bincount(tile, minlength=T)
+    gr = out["tile_ranges"].astype(np.int64)
+    assert np.array_equal(gr[:, 1] - gr[:, 0], counts)
+    got = np.concatenate([out["sorted_gauss"][gr[t, 0]:gr[t, 1]] for t in range(T)])
+    assert np.array_equal(got.astype(np.int64), exp)
