@@ -117,39 +117,52 @@ size_t prep_weight_bytes(int width, int in_pad) {
   return 4 * (elems_fwd > elems_bwd ? elems_fwd : elems_bwd);
 }
 
-// Two-level deterministic sum of per-wave partials: level 1 sums kSplit
-// contiguous groups of partials (grid y = group), level 2 sums the groups in order.
-constexpr int kSplit = 64;
+// Deterministic sum of per-block partials in one pass: a 1024-thread block
+// takes 64 parameters; each of its 16 waves sums a contiguous sixteenth of
+// the partials for them (a wave reads 256 contiguous bytes of a partial row,
+// eight rows in flight), and the sixteen sums are added in a fixed pairwise
+// order.
+constexpr int kRedParams = 64, kRedGroups = 16;
 
-__global__ __launch_bounds__(256) void reduce_partials_l1_kernel(const float *__restrict__ partials, int nparts,
-                                                                 int nparams, float *__restrict__ mid) {
-  const int p = blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= nparams) return;
-  const int per = (nparts + kSplit - 1) / kSplit;
-  const int b0 = blockIdx.y * per, b1 = min(nparts, b0 + per);
+__global__ __launch_bounds__(kRedParams * kRedGroups) void reduce_partials_kernel(const float *__restrict__ partials,
+                                                                                   int nparts, int nparams,
+                                                                                   float *__restrict__ out,
+                                                                                   int accumulate) {
+  __shared__ float q[kRedGroups][kRedParams];
+  const int t = threadIdx.x % kRedParams, h = threadIdx.x / kRedParams;
+  const int p = blockIdx.x * kRedParams + t;
+  const int per = (nparts + kRedGroups - 1) / kRedGroups;
+  const int b0 = h * per, b1 = min(nparts, b0 + per);
   float s = 0.f;
-  for (int b = b0; b < b1; b++) s += partials[(size_t)b * nparams + p];
-  mid[(size_t)blockIdx.y * nparams + p] = s;
+  if (p < nparams) {
+    int b = b0;
+    for (; b + 8 <= b1; b += 8) {
+      float v[8];
+#pragma unroll
+      for (int k = 0; k < 8; k++) v[k] = partials[(size_t)(b + k) * nparams + p];
+#pragma unroll
+      for (int k = 0; k < 8; k++) s += v[k];
+    }
+    for (; b < b1; b++) s += partials[(size_t)b * nparams + p];
+  }
+  q[h][t] = s;
+  __syncthreads();
+  for (int w = kRedGroups / 2; w >= 1; w >>= 1) {
+    if (h < w) q[h][t] += q[h + w][t];
+    __syncthreads();
+  }
+  if (h == 0 && p < nparams) out[p] = accumulate ? out[p] + q[0][t] : q[0][t];
 }
 
-__global__ __launch_bounds__(256) void reduce_partials_l2_kernel(const float *__restrict__ mid, int nparams,
-                                                                 float *__restrict__ out, int accumulate) {
-  const int p = blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= nparams) return;
-  float s = 0.f;
-  for (int k = 0; k < kSplit; k++) s += mid[(size_t)k * nparams + p];
-  out[p] = accumulate ? out[p] + s : s;
-}
-
-// `scratch` holds kSplit * nparams floats.
+// `scratch` is not used by the one-pass sum (kept for the workspace layout).
 void launch_reduce_partials(const float *partials, int nparts, int nparams, float *scratch, float *out,
                             int accumulate, hipStream_t st) {
-  const dim3 g1((nparams + 255) / 256, kSplit);
-  reduce_partials_l1_kernel<<<g1, 256, 0, st>>>(partials, nparts, nparams, scratch);
-  reduce_partials_l2_kernel<<<(nparams + 255) / 256, 256, 0, st>>>(scratch, nparams, out, accumulate);
+  (void)scratch;
+  reduce_partials_kernel<<<(nparams + kRedParams - 1) / kRedParams, kRedParams * kRedGroups, 0, st>>>(
+      partials, nparts, nparams, out, accumulate);
 }
 
-int reduce_scratch_floats(int nparams) { return kSplit * nparams; }
+int reduce_scratch_floats(int) { return 0; }  // the one-pass sum needs no scratch
 
 __global__ __launch_bounds__(256) void l1_kernel(const float *__restrict__ pred, const float *__restrict__ target,
                                                  int64_t count, float scale, float *__restrict__ loss_out,
